@@ -1,0 +1,249 @@
+/*
+ * pipnn.h -- C ABI of the MI355X (gfx950) PiPNN leaf hot path.
+ *
+ * PiPNN ("PiPNN: Ultra-Scalable Graph-Based Nearest Neighbor Indexing",
+ * arXiv 2602.21247) builds a graph index in four steps (Alg. 4):
+ *   1. Partition: randomized ball carving with fanout into overlapping
+ *      leaves of at most C_max points (Sec. 4.1, Alg. 5);
+ *   2. Pick: per leaf, an all-pairs distance matrix computed as a dense
+ *      GEMM and each row's k nearest co-members, bi-directed (Sec. 4.2);
+ *   3. Prune_And_Add_Edges: those edges stream into HashPrune, a bounded
+ *      per-point reservoir with one slot per LSH bucket (Sec. 3, Alg. 3);
+ *   4. PruneNode: a final RobustPrune of every reservoir (Sec. 4.3, Alg. 2).
+ * Queries use BeamSearch (Alg. 1).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Status: every call returns pipnn_status; 0 is success, negative values
+ *    are errors. pipnn_last_error() returns a thread-local message for the
+ *    last failing call on the calling thread. No C++ exception crosses this
+ *    interface and no call aborts the process.
+ *  - Streams: device work is enqueued on the caller's hipStream_t (0 = the
+ *    null stream) and is asynchronous unless the call is marked "sync".
+ *    Device faults surface as PIPNN_EDEVICE at the next synchronising call.
+ *  - Pointers: arguments named d_* are device pointers; h_* are host
+ *    pointers. All of them are owned by the caller and must stay valid until
+ *    the enqueued work has finished. X (and H) must outlive the index.
+ *  - Memory: the index allocates its own device scratch (sketches, norms,
+ *    low-precision copies, partition levels, candidate bins) with hipMalloc
+ *    and frees it in pipnn_destroy. pipnn_workspace_bytes reports an upper
+ *    bound of that scratch so that a caller can admit work by free memory.
+ *  - Ids are uint32 point indices 0..n-1; 0xFFFFFFFF marks an empty slot.
+ *  - Distances are squared L2 (metric 0) or the negated inner product
+ *    (metric 1), so that smaller is always nearer (Preliminaries).
+ *  - Ties are broken by (distance, id) everywhere.
+ *
+ * Thread safety: calls on different indices may run concurrently; calls on
+ * one index must be serialised by the caller.
+ */
+#ifndef PIPNN_H
+#define PIPNN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t *pipnn_stream_t; /* the same type as hipStream_t */
+typedef struct pipnn_index pipnn_index;
+typedef int32_t pipnn_status;
+
+#define PIPNN_OK 0
+#define PIPNN_EINVAL (-1)    /* an argument is out of range */
+#define PIPNN_ENOMEM (-2)    /* a device allocation failed */
+#define PIPNN_EOVERFLOW (-3) /* an output capacity is too small; the need is written back */
+#define PIPNN_EDEVICE (-4)   /* a HIP runtime error, or an id >= n found on the device */
+#define PIPNN_ESTATE (-5)    /* the call is not valid in the index's current state */
+
+#define PIPNN_METRIC_L2 0 /* squared Euclidean distance */
+#define PIPNN_METRIC_IP 1 /* negative inner product (MIPS) */
+
+#define PIPNN_DTYPE_F32 0
+#define PIPNN_DTYPE_F16 1
+#define PIPNN_DTYPE_BF16 2
+
+#define PIPNN_PREC_FP32 0    /* leaf GEMM on FP32 MFMA */
+#define PIPNN_PREC_BF16 1    /* BF16 MFMA, FP32 accumulation */
+#define PIPNN_PREC_FP8 2     /* OCP e4m3 MFMA with per-point scales, FP32 accumulation */
+#define PIPNN_PREC_FP16 3    /* FP16 MFMA, FP32 accumulation */
+
+#define PIPNN_EMPTY_ID 0xFFFFFFFFu
+
+/* Hyper-parameter bundle BP of Alg. 4.
+ *  metric       PIPNN_METRIC_*.
+ *  c_max        C_max, the largest leaf (Sec. 4.1; "typically 1024-2048").
+ *  c_min        C_min: buckets below it are merged (Sec. 4.1, Merge).
+ *  leader_div   P_samp = 1/leader_div: a subproblem P gets
+ *               l = min(leader_cap, max(2, ceil(|P|/leader_div)), |P|) leaders.
+ *  leader_cap   the hard cap on leaders per subproblem (typically 1000).
+ *  fanout[4]    fanout(depth) for depth 0,1,2 and >= 3 (Alg. 5); each
+ *               point joins its min(fanout, l) nearest leaders' buckets.
+ *               fanout[3] must be 1 so that the instance count stays bounded.
+ *  k            leaf pick: each point's k nearest co-members (Sec. 4.2).
+ *  hash_bits    m, hyperplanes per hash, 1..16 (Sec. 3; 12 by default).
+ *  l_max        HashPrune reservoir slots per point (Alg. 3), 1..256.
+ *  R            final degree bound of RobustPrune (Alg. 2), 1..256.
+ *  alpha        RobustPrune's alpha (Alg. 2), >= 1, applied to the
+ *               distances above (squared L2 or negated inner product).
+ *  gemm_prec    PIPNN_PREC_*: arithmetic of the leaf distance GEMM.
+ *  rescore_mult 0, or r >= 2: select the r*k nearest by the GEMM distance
+ *               and keep the k nearest by an FP32 direct-difference rescore.
+ *  seed         root key of the leader sampling (Alg. 5, SampleLeaders).
+ */
+typedef struct {
+  int32_t metric;
+  int32_t c_max, c_min, leader_div, leader_cap;
+  int32_t fanout[4];
+  int32_t k, hash_bits, l_max, R;
+  float alpha;
+  int32_t gemm_prec;
+  int32_t rescore_mult;
+  int32_t reserved;
+  uint64_t seed;
+} pipnn_params;
+
+/* Library version string. Never fails. */
+const char *pipnn_version(void);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char *pipnn_last_error(void);
+
+/* Fills *p with the defaults: L2, C_max 1024, C_min 64, leader_div 200,
+ * leader_cap 1000, fanout {2,1,1,1}, k 16, m 12, l_max 64, R 32, alpha 1.2,
+ * FP32 GEMM, no rescore, seed 0. */
+void pipnn_default_params(pipnn_params *p);
+
+/* Upper bound, in bytes, of the device scratch an index over n points of
+ * dimension d holds at its peak (partition levels, candidate bins for
+ * up to max_batch_records records, sketches, norms, low-precision copies).
+ * Returns 0 if the parameters are invalid. */
+size_t pipnn_workspace_bytes(const pipnn_params *p, int64_t n, int32_t d,
+                             int64_t max_batch_records);
+
+/* Create an index over d_X (n x d, row-major, x_dtype) with hyperplanes
+ * d_H (hash_bits x d, float32, row-major; Sec. 3, "random hyperplanes
+ * through the origin"). Computes the per-point sketches Sketch(v)_b = H_b . v
+ * (Sec. 3, Implementation) and squared norms on the stream. d_X and d_H are
+ * referenced, not copied, and must outlive the index.
+ * EINVAL if n < 2, d < 1, hash_bits not in 1..16, k < 1, l_max not in
+ * 1..256, R not in 1..256, alpha < 1, c_max < 2, c_min > c_max, leader_div
+ * < 1, leader_cap < 2, a fanout < 1, fanout[3] != 1, an unknown dtype or
+ * precision, or n >= 2^32 - 1. ENOMEM if scratch cannot be allocated. */
+pipnn_status pipnn_create(const pipnn_params *p, const void *d_X, int64_t n, int32_t d,
+                          int32_t x_dtype, const float *d_H, pipnn_stream_t stream,
+                          pipnn_index **out);
+
+/* Release the index and its device scratch (synchronises its stream). */
+void pipnn_destroy(pipnn_index *idx);
+
+/* (sync) Randomized ball carving (Alg. 5) of all n points into leaves of at
+ * most C_max points. Leaves are returned as CSR: d_leaf_offsets[0..L]
+ * (int64, offsets[0] = 0) and d_leaf_members (uint32, ascending ids within a
+ * leaf). The leaf order is unspecified; leaf contents are deterministic for
+ * a seed. Reads bucket sizes back to the host once per recursion level.
+ * EOVERFLOW if L > cap_leaves or the member count > cap_members; the needed
+ * sizes are written to *h_n_leaves and *h_n_members either way. */
+pipnn_status pipnn_partition(pipnn_index *idx, int64_t *d_leaf_offsets, int64_t cap_leaves,
+                             uint32_t *d_leaf_members, int64_t cap_members, int64_t *h_n_leaves,
+                             int64_t *h_n_members, pipnn_stream_t stream);
+
+/* Pick + Prune_And_Add_Edges for every leaf (Alg. 4, the parallel loop over
+ * leaves; Sec. 4.2): per leaf, the distance matrix on MFMA, each member's
+ * k nearest co-members by (GEMM distance, id) (or the rescore_mult*k
+ * nearest, rescored), the FP32 direct-difference distance of each winner,
+ * and both directed records of each picked edge inserted into HashPrune.
+ * d_leaf_offsets/d_leaf_members is any CSR of leaves with ascending member
+ * ids (RBC output or explicit leaves); leaves of size 1 contribute nothing.
+ * d_reservoirs holds n x l_max uint64 slots (see pipnn_reservoir_init);
+ * repeated calls accumulate, and by the history-independence theorem of
+ * Sec. 3 the result does not depend on leaf order or call splitting.
+ * Reads d_leaf_offsets back to the host once. EINVAL on a leaf larger than
+ * 65535 points or an unsorted leaf (found on the device: EDEVICE). */
+pipnn_status pipnn_build_leaves(pipnn_index *idx, const int64_t *d_leaf_offsets,
+                                const uint32_t *d_leaf_members, int64_t n_leaves,
+                                uint64_t *d_reservoirs, pipnn_stream_t stream);
+
+/* HashPrune insertion (Alg. 3) of a batch of candidate records
+ * (p = d_dst[i], c = d_cand[i], ||p,c|| = d_dist[i]) into the reservoirs.
+ * The hash h_p(c) comes from the index's sketches (bit b set iff
+ * Sketch(c)_b >= Sketch(p)_b). The stored distance is bf16 (round to nearest
+ * even, -0 as +0) and every comparison uses the key (bf16 distance, id).
+ * Records with dst == cand are ignored; inserting a record twice changes
+ * nothing. Ids >= n are reported as EDEVICE by this call (it synchronises
+ * to read the device-side check). */
+pipnn_status pipnn_hashprune_insert(pipnn_index *idx, const uint32_t *d_dst,
+                                    const uint32_t *d_cand, const float *d_dist,
+                                    int64_t n_records, uint64_t *d_reservoirs,
+                                    pipnn_stream_t stream);
+
+/* Reservoir slot layout (Sec. 3, Implementation: 4-byte id, 2-byte hash,
+ * bf16 distance): bits 0..31 id, 32..47 hash, 48..63 bf16 distance.
+ * Sets n x l_max slots to the empty slot (id 0xFFFFFFFF, hash 0, +inf). */
+pipnn_status pipnn_reservoir_init(uint64_t *d_reservoirs, int64_t n, int32_t l_max,
+                                  pipnn_stream_t stream);
+
+/* Writes the canonical form of the reservoirs: per point, valid slots
+ * sorted by (bf16 distance, id) and empty slots last. Reservoirs written by
+ * this library are already canonical; d_out may equal d_res. */
+pipnn_status pipnn_reservoir_canonical(const pipnn_index *idx, const uint64_t *d_res,
+                                       uint64_t *d_out, pipnn_stream_t stream);
+
+/* Final prune (Alg. 4, PruneNode; Sec. 4.3): RobustPrune (Alg. 2) in its
+ * lazy form (Supplement, "Optimizing RobustPrune") on every reservoir. The
+ * candidates of x are its reservoir ids; d(x,c) and d(y,c) are FP32
+ * direct-difference distances; candidates are taken in (distance, id)
+ * order and c is admitted unless an admitted y has alpha*d(y,c) < d(x,c)
+ * (evaluated as the sign of one fused multiply-add). Writes d_graph (n x R,
+ * admission order, 0xFFFFFFFF padding) and d_degree (n). */
+pipnn_status pipnn_robustprune(pipnn_index *idx, const uint64_t *d_reservoirs, uint32_t *d_graph,
+                               uint32_t *d_degree, pipnn_stream_t stream);
+
+/* (sync) The search start point: the point nearest the mean of X by
+ * (squared L2, id), the mean and distances in FP64. Written to *h_out. */
+pipnn_status pipnn_start_node(pipnn_index *idx, uint32_t *h_out, pipnn_stream_t stream);
+
+/* BeamSearch (Alg. 1) for nq queries d_Q (nq x d, q_dtype) over d_graph
+ * (n x R from pipnn_robustprune) from start point `start`, beam width L.
+ * Writes the first k beam entries per query: d_out_ids (nq x k) and
+ * d_out_dist (nq x k, FP32; may be NULL); d_out_cmps (nq, may be NULL)
+ * receives the number of distance evaluations, the start included.
+ * EINVAL if k < 1, k > L, L > 1024, start >= n. */
+pipnn_status pipnn_search(pipnn_index *idx, const uint32_t *d_graph, const void *d_Q, int64_t nq,
+                          int32_t q_dtype, int32_t k, int32_t L, uint32_t start,
+                          uint32_t *d_out_ids, float *d_out_dist, uint32_t *d_out_cmps,
+                          pipnn_stream_t stream);
+
+/* ---- inspection calls, used to check the path against the oracle ---- */
+
+/* Copies the index's float32 sketches (n x hash_bits) to d_out. */
+pipnn_status pipnn_get_sketches(const pipnn_index *idx, float *d_out, pipnn_stream_t stream);
+
+/* The leaf distance kernel on one explicit block: rows d_row_ids (n_rows
+ * point ids) against columns d_col_ids (n_cols point ids), each row's
+ * k nearest columns by (GEMM distance, column index), excluding the column
+ * at the row's own position when exclude_diag is 1 (then n_rows must equal
+ * n_cols and the two lists must be equal). Writes column indices
+ * d_out_col (n_rows x k) in that order, the FP32 direct-difference
+ * distances d_out_dist (n_rows x k, may be NULL) and, when d_out_matrix is
+ * not NULL, the GEMM distances of every pair (n_rows x n_cols). The same
+ * code as pipnn_build_leaves runs, with the index's gemm_prec and
+ * rescore_mult. EINVAL if k < 1, k > 32, n_cols > 65535. */
+pipnn_status pipnn_knn_block(pipnn_index *idx, const uint32_t *d_row_ids, int64_t n_rows,
+                             const uint32_t *d_col_ids, int64_t n_cols, int32_t k,
+                             int32_t exclude_diag, uint32_t *d_out_col, float *d_out_dist,
+                             float *d_out_matrix, pipnn_stream_t stream);
+
+/* The pick step alone: like pipnn_build_leaves but, instead of inserting
+ * into HashPrune, writes each leaf row's picks as point ids d_out_cand and
+ * FP32 direct-difference distances d_out_dist, both (offsets[L] x k) in CSR
+ * member order, unused slots 0xFFFFFFFF / +inf. */
+pipnn_status pipnn_leaf_pick(pipnn_index *idx, const int64_t *d_leaf_offsets,
+                             const uint32_t *d_leaf_members, int64_t n_leaves, uint32_t *d_out_cand,
+                             float *d_out_dist, pipnn_stream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PIPNN_H */

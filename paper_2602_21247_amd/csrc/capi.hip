@@ -1,0 +1,877 @@
+// C ABI of the PiPNN gfx950 library and its host-side orchestration.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <deque>
+#include <new>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "common.hpp"
+#include "internal.hpp"
+
+using namespace pipnn;
+
+namespace {
+
+thread_local std::string g_err;
+
+pipnn_status fail(pipnn_status st, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+#define HIPCHK(expr)                                                                          \
+  do {                                                                                        \
+    hipError_t e_ = (expr);                                                                   \
+    if (e_ != hipSuccess)                                                                     \
+      return fail(e_ == hipErrorOutOfMemory ? PIPNN_ENOMEM : PIPNN_EDEVICE, "%s failed: %s", \
+                  #expr, hipGetErrorString(e_));                                              \
+  } while (0)
+
+#define GUARD_BEGIN try {
+#define GUARD_END                                                    \
+  }                                                                  \
+  catch (const std::bad_alloc &) {                                   \
+    return fail(PIPNN_ENOMEM, "host allocation failed");             \
+  }                                                                  \
+  catch (...) {                                                      \
+    return fail(PIPNN_EDEVICE, "unexpected internal exception");    \
+  }
+
+// splitmix64 (Steele, Lea and Flood, 2014): golden-ratio increment of the
+// state, then the published xor-shift-multiply finaliser.
+uint64_t sm64_next(uint64_t &state) {
+  uint64_t z = (state += 0x9E3779B97F4A7C15ull);
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// Key of the subproblem formed by bucket t of a subproblem with key `key`.
+uint64_t sub_key(uint64_t key, int64_t t) {
+  uint64_t s = key ^ ((uint64_t)(t + 1) * 0x9E3779B97F4A7C15ull);
+  return sm64_next(s);
+}
+
+// Positions (within the subproblem's ascending id list) of its `ell`
+// leaders: the first ell entries of a partial Fisher-Yates shuffle driven by
+// splitmix64 from `key`, drawing j = t + floor(r * (np - t) / 2^64) (Alg. 5,
+// SampleLeaders). Only swapped positions are stored.
+std::vector<int64_t> leader_positions(uint64_t key, int64_t np, int64_t ell) {
+  std::unordered_map<int64_t, int64_t> sw;
+  sw.reserve((size_t)ell * 2);
+  auto at = [&](int64_t i) {
+    auto it = sw.find(i);
+    return it == sw.end() ? i : it->second;
+  };
+  std::vector<int64_t> pos((size_t)ell);
+  uint64_t st = key;
+  for (int64_t t = 0; t < ell; ++t) {
+    const uint64_t r = sm64_next(st);
+    const int64_t j =
+        t + (int64_t)(((unsigned __int128)r * (unsigned __int128)(uint64_t)(np - t)) >> 64);
+    const int64_t vt = at(t), vj = at(j);
+    sw[t] = vj;
+    sw[j] = vt;
+    pos[(size_t)t] = vj;
+  }
+  return pos;
+}
+
+bool valid_params(const pipnn_params *p, std::string &why) {
+  char b[160];
+  auto bad = [&](const char *m) {
+    why = m;
+    return false;
+  };
+  if (!p) return bad("params is NULL");
+  if (p->metric != PIPNN_METRIC_L2 && p->metric != PIPNN_METRIC_IP) return bad("unknown metric");
+  if (p->c_max < 2 || p->c_max > 16384) return bad("c_max must be in 2..16384");
+  if (p->c_min < 0 || p->c_min > p->c_max) return bad("c_min must be in 0..c_max");
+  if (p->leader_div < 1) return bad("leader_div must be >= 1");
+  if (p->leader_cap < 2 || p->leader_cap > 4096) return bad("leader_cap must be in 2..4096");
+  for (int i = 0; i < 4; ++i)
+    if (p->fanout[i] < 1 || p->fanout[i] > 4) return bad("fanout values must be in 1..4");
+  if (p->fanout[3] != 1) return bad("fanout[3] must be 1");
+  if (p->k < 1 || p->k > 32) return bad("k must be in 1..32");
+  if (p->hash_bits < 1 || p->hash_bits > 16) return bad("hash_bits must be in 1..16");
+  if (p->l_max < 1 || p->l_max > 256) return bad("l_max must be in 1..256");
+  if (p->R < 1 || p->R > 256) return bad("R must be in 1..256");
+  if (!(p->alpha >= 1.0f)) return bad("alpha must be >= 1");
+  if (p->gemm_prec != PIPNN_PREC_FP32) {
+    snprintf(b, sizeof(b), "gemm_prec %d is not available in this build", p->gemm_prec);
+    why = b;
+    return false;
+  }
+  if (p->rescore_mult != 0 && (p->rescore_mult < 2 || p->rescore_mult * p->k > 32))
+    return bad("rescore_mult must be 0, or >= 2 with rescore_mult * k <= 32");
+  return true;
+}
+
+template <class T>
+hipError_t upload(DevBuf &b, const std::vector<T> &v, hipStream_t s) {
+  hipError_t e = b.ensure(std::max<size_t>(1, v.size()) * sizeof(T));
+  if (e != hipSuccess || v.empty()) return e;
+  return hipMemcpyAsync(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s);
+}
+
+constexpr int kKnnRows = 128;  // rows per knn work item (32 per wave x 4 waves)
+constexpr int kGroupTile = 1024;
+
+}  // namespace
+
+namespace pipnn {
+
+hipError_t DevBuf::ensure(size_t bytes) {
+  if (bytes <= cap && p) return hipSuccess;
+  release();
+  const size_t want = std::max<size_t>(bytes, 256);
+  hipError_t e = hipMalloc(&p, want);
+  if (e != hipSuccess) {
+    p = nullptr;
+    cap = 0;
+    return e;
+  }
+  cap = want;
+  return hipSuccess;
+}
+
+void DevBuf::release() {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+  cap = 0;
+}
+
+const float *Index::xf() const {
+  return x_dtype == PIPNN_DTYPE_F32 ? reinterpret_cast<const float *>(X) : xf32.as<float>();
+}
+
+}  // namespace pipnn
+
+extern "C" {
+
+const char *pipnn_version(void) { return "pipnn-gfx950 0.1.0"; }
+
+const char *pipnn_last_error(void) { return g_err.c_str(); }
+
+void pipnn_default_params(pipnn_params *p) {
+  if (!p) return;
+  memset(p, 0, sizeof(*p));
+  p->metric = PIPNN_METRIC_L2;
+  p->c_max = 1024;
+  p->c_min = 64;
+  p->leader_div = 200;
+  p->leader_cap = 1000;
+  p->fanout[0] = 2;
+  p->fanout[1] = p->fanout[2] = p->fanout[3] = 1;
+  p->k = 16;
+  p->hash_bits = 12;
+  p->l_max = 64;
+  p->R = 32;
+  p->alpha = 1.2f;
+  p->gemm_prec = PIPNN_PREC_FP32;
+  p->rescore_mult = 0;
+  p->seed = 0;
+}
+
+size_t pipnn_workspace_bytes(const pipnn_params *p, int64_t n, int32_t d,
+                             int64_t max_batch_records) {
+  std::string why;
+  if (!valid_params(p, why) || n < 2 || d < 1) return 0;
+  const int64_t inst = n * p->fanout[0] * p->fanout[1] * p->fanout[2];
+  const int64_t picks = inst * p->k;
+  const int64_t rec = std::max<int64_t>(2 * picks, max_batch_records);
+  size_t b = 0;
+  b += (size_t)n * (size_t)(p->hash_bits + 1) * 4;          // sketches + norms
+  b += (size_t)inst * 4 * 6;                                  // partition levels
+  b += (size_t)inst * p->fanout[0] * 4 * 2;                   // assignments
+  b += (size_t)picks * 8;                                     // picks (id + dist)
+  b += (size_t)rec * 8;                                       // binned slots
+  b += (size_t)(n + 1) * 8 + (size_t)n * 4;                   // bin offsets + counts
+  return b;
+}
+
+pipnn_status pipnn_create(const pipnn_params *p, const void *d_X, int64_t n, int32_t d,
+                          int32_t x_dtype, const float *d_H, pipnn_stream_t stream,
+                          pipnn_index **out) {
+  GUARD_BEGIN
+  std::string why;
+  if (!out) return fail(PIPNN_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!valid_params(p, why)) return fail(PIPNN_EINVAL, "invalid params: %s", why.c_str());
+  if (!d_X || !d_H) return fail(PIPNN_EINVAL, "X or H is NULL");
+  if (n < 2 || n >= (int64_t)0xFFFFFFFFll) return fail(PIPNN_EINVAL, "n must be in 2..2^32-2");
+  if (d < 1 || d > 1024) return fail(PIPNN_EINVAL, "d must be in 1..1024");
+  if (x_dtype != PIPNN_DTYPE_F32 && x_dtype != PIPNN_DTYPE_F16 && x_dtype != PIPNN_DTYPE_BF16)
+    return fail(PIPNN_EINVAL, "unknown x_dtype %d", x_dtype);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  Index *I = new Index();
+  I->p = *p;
+  I->X = d_X;
+  I->n = n;
+  I->d = d;
+  I->x_dtype = x_dtype;
+  I->H = d_H;
+  I->m = p->hash_bits;
+  I->stream = s;
+  auto cleanup = [&](pipnn_status st) {
+    pipnn_destroy(reinterpret_cast<pipnn_index *>(I));
+    return st;
+  };
+  hipError_t e;
+  if ((e = I->sketches.ensure((size_t)n * I->m * 4)) != hipSuccess ||
+      (e = I->norms.ensure((size_t)n * 4)) != hipSuccess ||
+      (e = I->flag.ensure(64)) != hipSuccess)
+    return cleanup(fail(PIPNN_ENOMEM, "device allocation failed: %s", hipGetErrorString(e)));
+  if (x_dtype != PIPNN_DTYPE_F32) {
+    if ((e = I->xf32.ensure((size_t)n * d * 4)) != hipSuccess)
+      return cleanup(fail(PIPNN_ENOMEM, "device allocation failed: %s", hipGetErrorString(e)));
+    if ((e = launch_to_f32(d_X, x_dtype, I->xf32.as<float>(), n * (int64_t)d, s)) != hipSuccess)
+      return cleanup(fail(PIPNN_EDEVICE, "conversion launch failed: %s", hipGetErrorString(e)));
+  }
+  if ((e = launch_norms_sketches(*I, s)) != hipSuccess)
+    return cleanup(fail(PIPNN_EDEVICE, "sketch launch failed: %s", hipGetErrorString(e)));
+  if ((e = hipMemsetAsync(I->flag.p, 0, 64, s)) != hipSuccess)
+    return cleanup(fail(PIPNN_EDEVICE, "memset failed: %s", hipGetErrorString(e)));
+  *out = reinterpret_cast<pipnn_index *>(I);
+  return PIPNN_OK;
+  GUARD_END
+}
+
+void pipnn_destroy(pipnn_index *idx) {
+  if (!idx) return;
+  Index *I = reinterpret_cast<Index *>(idx);
+  (void)hipDeviceSynchronize();
+  for (DevBuf *b : {&I->xf32, &I->xlow, &I->xscale, &I->sketches, &I->norms, &I->flag, &I->s_jobs,
+                    &I->s_items, &I->s_picks_c, &I->s_picks_d, &I->s_cnt, &I->s_off, &I->s_bins,
+                    &I->s_tmp0, &I->s_tmp1, &I->p_asg, &I->p_leaders, &I->p_cm, &I->p_bstart,
+                    &I->p_groups, &I->p_gout, &I->p_gsize, &I->p_copy})
+    b->release();
+  for (DevBuf &b : I->levels) b.release();
+  delete I;
+}
+
+// ---------------------------------------------------------------------
+// Randomized ball carving (Alg. 5), level by level.
+pipnn_status pipnn_partition(pipnn_index *idx, int64_t *d_leaf_offsets, int64_t cap_leaves,
+                             uint32_t *d_leaf_members, int64_t cap_members, int64_t *h_n_leaves,
+                             int64_t *h_n_members, pipnn_stream_t stream) {
+  GUARD_BEGIN
+  if (!idx || !h_n_leaves || !h_n_members) return fail(PIPNN_EINVAL, "NULL argument");
+  Index &I = *reinterpret_cast<Index *>(idx);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const pipnn_params &P = I.p;
+  const int64_t n = I.n;
+
+  struct Sub {
+    int64_t row_off, cnt;
+    uint64_t key;
+    int depth;
+  };
+  struct Leaf {
+    const uint32_t *src;
+    int64_t len;        // -1: size read from a merge-size array
+    int32_t *size_dev;  // merge output sizes (device) when len < 0
+    int size_idx;
+  };
+  std::vector<Leaf> leaves;
+  // every level allocates its own buffers; they are kept until the end
+  std::deque<DevBuf> keep;  // stable addresses as it grows
+  auto fresh = [&](size_t bytes, DevBuf *&out) -> hipError_t {
+    keep.emplace_back();
+    out = &keep.back();
+    return out->ensure(bytes);
+  };
+
+  DevBuf *A0;
+  HIPCHK(fresh((size_t)n * 4, A0));
+  HIPCHK(launch_iota(A0->as<uint32_t>(), n, s));
+  std::vector<Sub> subs;
+  if (n <= P.c_max) {
+    leaves.push_back({A0->as<uint32_t>(), n, nullptr, 0});
+  } else {
+    subs.push_back({0, n, P.seed, 0});
+  }
+  DevBuf *A = A0;
+  std::vector<int32_t> gsize_host;
+  std::vector<std::pair<int32_t *, int>> gsize_arrays;  // (device array, count)
+
+  while (!subs.empty()) {
+    // --- leaders and assignment jobs
+    std::vector<KnnJob> jobs;
+    std::vector<KnnItem> items;
+    std::vector<int64_t> lead_idx;
+    std::vector<int32_t> ells, fs;
+    int64_t inst = 0;
+    int fmax = 1;
+    for (size_t si = 0; si < subs.size(); ++si) {
+      const Sub &sb = subs[si];
+      int64_t ell = (sb.cnt + P.leader_div - 1) / P.leader_div;
+      ell = std::max<int64_t>(ell, 2);
+      ell = std::min<int64_t>(ell, P.leader_cap);
+      ell = std::min<int64_t>(ell, sb.cnt);
+      int f = P.fanout[std::min(sb.depth, 3)];
+      f = (int)std::min<int64_t>(f, ell);
+      f = std::max(f, 1);
+      fmax = std::max(fmax, f);
+      const int64_t lead_off = (int64_t)lead_idx.size();
+      for (int64_t pos : leader_positions(sb.key, sb.cnt, ell)) lead_idx.push_back(sb.row_off + pos);
+      KnnJob J;
+      J.row_off = sb.row_off;
+      J.col_off = lead_off;
+      J.out_off = sb.row_off;
+      J.n_rows = (int32_t)sb.cnt;
+      J.n_cols = (int32_t)ell;
+      J.k_sel = f;
+      J.flags = 0;
+      const int32_t jid = (int32_t)jobs.size();
+      jobs.push_back(J);
+      for (int64_t rb = 0; rb * kKnnRows < sb.cnt; ++rb) items.push_back({jid, (int32_t)rb});
+      ells.push_back((int32_t)ell);
+      fs.push_back(f);
+      inst += sb.cnt;
+    }
+    HIPCHK(upload(I.s_tmp1, lead_idx, s));
+    HIPCHK(I.p_leaders.ensure(lead_idx.size() * 4));
+    HIPCHK(launch_gather_u32(A->as<uint32_t>(), I.s_tmp1.as<int64_t>(), I.p_leaders.as<uint32_t>(),
+                             (int64_t)lead_idx.size(), s));
+    HIPCHK(upload(I.s_jobs, jobs, s));
+    HIPCHK(upload(I.s_items, items, s));
+    HIPCHK(I.p_asg.ensure((size_t)inst * fmax * 4));
+    KnnLaunch L{};
+    L.idx = &I;
+    L.row_base = A->as<uint32_t>();
+    L.col_base = I.p_leaders.as<uint32_t>();
+    L.jobs = I.s_jobs.as<KnnJob>();
+    L.items = I.s_items.as<KnnItem>();
+    L.n_items = (int32_t)items.size();
+    L.ksel = fmax;
+    L.k_out = fmax;
+    L.out_ids = 0;
+    L.recompute = 0;
+    L.rescore_k = 0;
+    L.out_col = I.p_asg.as<uint32_t>();
+    L.out_dist = nullptr;
+    L.out_matrix = nullptr;
+    HIPCHK(launch_knn(L, s));
+
+    // --- stable group-by into buckets
+    std::vector<GroupSub> gsubs;
+    std::vector<GroupTile> tiles;
+    std::vector<int64_t> bucket_cm;
+    int64_t cm_len = 0, nbuck = 0;
+    for (size_t si = 0; si < subs.size(); ++si) {
+      GroupSub g;
+      g.elem_off = subs[si].row_off * fmax;
+      g.n_elems = subs[si].cnt * fmax;
+      g.n_buckets = ells[si];
+      g.n_tiles = (int32_t)((g.n_elems + kGroupTile - 1) / kGroupTile);
+      g.cm_off = cm_len;
+      g.bucket_off = nbuck;
+      for (int t = 0; t < g.n_buckets; ++t) bucket_cm.push_back(g.cm_off + (int64_t)t * g.n_tiles);
+      for (int t = 0; t < g.n_tiles; ++t) tiles.push_back({(int32_t)si, t});
+      cm_len += (int64_t)g.n_buckets * g.n_tiles;
+      nbuck += g.n_buckets;
+      gsubs.push_back(g);
+    }
+    bucket_cm.push_back(cm_len);  // end of the last bucket = total
+    HIPCHK(upload(I.s_tmp0, gsubs, s));
+    HIPCHK(upload(I.p_groups, tiles, s));
+    HIPCHK(upload(I.p_bstart, bucket_cm, s));
+    HIPCHK(I.p_cm.ensure((size_t)(cm_len + 1) * 8));
+    HIPCHK(I.s_off.ensure((size_t)scan_tmp_elems(cm_len) * 8));
+    DevBuf *G;
+    HIPCHK(fresh((size_t)inst * fmax * 4, G));
+    int32_t fm = fmax;
+    HIPCHK(launch_groupby(I.p_asg.as<uint32_t>(), A->as<uint32_t>(), &fm, I.s_tmp0.as<GroupSub>(),
+                          I.p_groups.as<GroupTile>(), (int32_t)tiles.size(), kGroupTile,
+                          I.p_cm.as<int64_t>(), cm_len, I.s_off.as<int64_t>(),
+                          G->as<uint32_t>(), I.p_bstart.as<int64_t>(), nbuck + 1, s));
+    std::vector<int64_t> bstart((size_t)nbuck + 1);
+    HIPCHK(hipMemcpyAsync(bstart.data(), I.p_bstart.p, bstart.size() * 8, hipMemcpyDeviceToHost,
+                          s));
+    HIPCHK(hipStreamSynchronize(s));
+
+    // --- plan: merge small buckets, emit leaves, recurse
+    std::vector<Sub> next;
+    std::vector<const uint32_t *> seg_ptr;
+    std::vector<int32_t> seg_len, grp_first;
+    std::vector<int64_t> grp_off;
+    int64_t gout_total = 0;
+    int32_t max_sum = 0;
+    std::vector<std::pair<const uint32_t *, int64_t>> recurse_src;
+    int64_t next_off = 0;
+    uint32_t *Gp = G->as<uint32_t>();
+    for (size_t si = 0; si < subs.size(); ++si) {
+      const Sub &sb = subs[si];
+      const int64_t b0 = gsubs[si].bucket_off;
+      int64_t gsum = 0;
+      int gcnt = 0;
+      auto close_group = [&]() {
+        if (gcnt == 0) return;
+        grp_off.push_back(gout_total);
+        gout_total += gsum;
+        max_sum = std::max<int32_t>(max_sum, (int32_t)gsum);
+        gsum = 0;
+        gcnt = 0;
+      };
+      for (int t = 0; t < ells[si]; ++t) {
+        const int64_t st = bstart[(size_t)(b0 + t)];
+        const int64_t sz = bstart[(size_t)(b0 + t + 1)] - st;
+        if (sz == 0 || sz >= P.c_min) continue;
+        if (gcnt > 0 && gsum + sz > P.c_max) close_group();
+        if (gcnt == 0) grp_first.push_back((int32_t)seg_ptr.size());
+        seg_ptr.push_back(Gp + st);
+        seg_len.push_back((int32_t)sz);
+        gsum += sz;
+        ++gcnt;
+      }
+      close_group();
+      for (int t = 0; t < ells[si]; ++t) {
+        const int64_t st = bstart[(size_t)(b0 + t)];
+        const int64_t sz = bstart[(size_t)(b0 + t + 1)] - st;
+        if (sz == 0 || sz < P.c_min) continue;
+        if (sz <= P.c_max) {
+          leaves.push_back({Gp + st, sz, nullptr, 0});
+        } else if (sz == sb.cnt) {
+          const int64_t q = (sz + P.c_max - 1) / P.c_max;
+          const int64_t base = sz / q, extra = sz % q;
+          int64_t pos = 0;
+          for (int64_t c = 0; c < q; ++c) {
+            const int64_t len = base + (c < extra ? 1 : 0);
+            leaves.push_back({Gp + st + pos, len, nullptr, 0});
+            pos += len;
+          }
+        } else {
+          next.push_back({next_off, sz, sub_key(sb.key, t), sb.depth + 1});
+          recurse_src.push_back({Gp + st, sz});
+          next_off += sz;
+        }
+      }
+    }
+    const int n_groups = (int)grp_off.size();
+    if (n_groups > 0) {
+      grp_first.push_back((int32_t)seg_ptr.size());
+      DevBuf *gout, *gptr, *glen, *gfirst, *goff, *gsz;
+      HIPCHK(fresh((size_t)gout_total * 4, gout));
+      HIPCHK(fresh(seg_ptr.size() * sizeof(void *), gptr));
+      HIPCHK(fresh(seg_len.size() * 4, glen));
+      HIPCHK(fresh(grp_first.size() * 4, gfirst));
+      HIPCHK(fresh(grp_off.size() * 8, goff));
+      HIPCHK(fresh((size_t)n_groups * 4, gsz));
+      HIPCHK(hipMemcpyAsync(gptr->p, seg_ptr.data(), seg_ptr.size() * sizeof(void *),
+                            hipMemcpyHostToDevice, s));
+      HIPCHK(hipMemcpyAsync(glen->p, seg_len.data(), seg_len.size() * 4, hipMemcpyHostToDevice, s));
+      HIPCHK(hipMemcpyAsync(gfirst->p, grp_first.data(), grp_first.size() * 4,
+                            hipMemcpyHostToDevice, s));
+      HIPCHK(hipMemcpyAsync(goff->p, grp_off.data(), grp_off.size() * 8, hipMemcpyHostToDevice, s));
+      HIPCHK(launch_merge_dedup(gptr->as<const uint32_t *>(), glen->as<int32_t>(),
+                                gfirst->as<int32_t>(), n_groups, max_sum, gout->as<uint32_t>(),
+                                goff->as<int64_t>(), gsz->as<int32_t>(), s));
+      for (int g = 0; g < n_groups; ++g)
+        leaves.push_back({gout->as<uint32_t>() + grp_off[(size_t)g], -1, gsz->as<int32_t>(), g});
+      gsize_arrays.push_back({gsz->as<int32_t>(), n_groups});
+      // host-side copies of the segment tables must live until the copies finish
+      HIPCHK(hipStreamSynchronize(s));
+    }
+    // --- next level: recursing buckets, contiguous
+    if (!next.empty()) {
+      DevBuf *An, *sp, *so, *sl;
+      HIPCHK(fresh((size_t)next_off * 4, An));
+      std::vector<const uint32_t *> src;
+      std::vector<int64_t> doff;
+      std::vector<int32_t> lens;
+      int64_t o = 0;
+      for (auto &rs : recurse_src) {
+        src.push_back(rs.first);
+        doff.push_back(o);
+        lens.push_back((int32_t)rs.second);
+        o += rs.second;
+      }
+      HIPCHK(fresh(src.size() * sizeof(void *), sp));
+      HIPCHK(fresh(doff.size() * 8, so));
+      HIPCHK(fresh(lens.size() * 4, sl));
+      HIPCHK(hipMemcpyAsync(sp->p, src.data(), src.size() * sizeof(void *), hipMemcpyHostToDevice,
+                            s));
+      HIPCHK(hipMemcpyAsync(so->p, doff.data(), doff.size() * 8, hipMemcpyHostToDevice, s));
+      HIPCHK(hipMemcpyAsync(sl->p, lens.data(), lens.size() * 4, hipMemcpyHostToDevice, s));
+      HIPCHK(launch_copy_segments(sp->as<const uint32_t *>(), so->as<int64_t>(), sl->as<int32_t>(),
+                                  (int32_t)src.size(), An->as<uint32_t>(), s));
+      HIPCHK(hipStreamSynchronize(s));
+      A = An;
+    }
+    subs.swap(next);
+  }
+
+  // --- sizes of merged leaves, then the final CSR
+  std::unordered_map<const int32_t *, std::vector<int32_t>> gsz_host;
+  for (auto &ga : gsize_arrays) {
+    std::vector<int32_t> v((size_t)ga.second);
+    HIPCHK(hipMemcpyAsync(v.data(), ga.first, v.size() * 4, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    gsz_host[ga.first] = std::move(v);
+  }
+  std::vector<int64_t> offs(leaves.size() + 1, 0);
+  std::vector<const uint32_t *> srcs;
+  std::vector<int32_t> lens;
+  for (size_t i = 0; i < leaves.size(); ++i) {
+    int64_t len = leaves[i].len;
+    if (len < 0) len = gsz_host[leaves[i].size_dev][(size_t)leaves[i].size_idx];
+    offs[i + 1] = offs[i] + len;
+    srcs.push_back(leaves[i].src);
+    lens.push_back((int32_t)len);
+  }
+  *h_n_leaves = (int64_t)leaves.size();
+  *h_n_members = offs.back();
+  if ((int64_t)leaves.size() > cap_leaves || offs.back() > cap_members)
+    return fail(PIPNN_EOVERFLOW, "partition needs %lld leaves and %lld members",
+                (long long)leaves.size(), (long long)offs.back());
+  if (!d_leaf_offsets || !d_leaf_members) return fail(PIPNN_EINVAL, "NULL output");
+  {
+    DevBuf *sp, *so, *sl;
+    HIPCHK(fresh(srcs.size() * sizeof(void *), sp));
+    HIPCHK(fresh(offs.size() * 8, so));
+    HIPCHK(fresh(lens.size() * 4, sl));
+    HIPCHK(hipMemcpyAsync(sp->p, srcs.data(), srcs.size() * sizeof(void *), hipMemcpyHostToDevice,
+                          s));
+    HIPCHK(hipMemcpyAsync(so->p, offs.data(), offs.size() * 8, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(sl->p, lens.data(), lens.size() * 4, hipMemcpyHostToDevice, s));
+    HIPCHK(launch_copy_segments(sp->as<const uint32_t *>(), so->as<int64_t>(), sl->as<int32_t>(),
+                                (int32_t)srcs.size(), d_leaf_members, s));
+    HIPCHK(hipMemcpyAsync(d_leaf_offsets, offs.data(), offs.size() * 8, hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+  }
+  for (DevBuf &b : keep) b.release();
+  return PIPNN_OK;
+  GUARD_END
+}
+
+// ---------------------------------------------------------------------
+namespace {
+
+struct LeafPlan {
+  std::vector<int64_t> offs;  // host copy of the CSR offsets
+};
+
+pipnn_status read_offsets(const int64_t *d_off, int64_t n_leaves, hipStream_t s,
+                          std::vector<int64_t> &offs) {
+  offs.resize((size_t)n_leaves + 1);
+  HIPCHK(hipMemcpyAsync(offs.data(), d_off, offs.size() * 8, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  for (int64_t i = 0; i < n_leaves; ++i) {
+    const int64_t sz = offs[(size_t)i + 1] - offs[(size_t)i];
+    if (sz < 0) return fail(PIPNN_EINVAL, "leaf offsets are not monotone at leaf %lld", (long long)i);
+    if (sz > 65535) return fail(PIPNN_EINVAL, "leaf %lld has %lld > 65535 points", (long long)i,
+                                (long long)sz);
+  }
+  if (offs[0] < 0) return fail(PIPNN_EINVAL, "negative leaf offset");
+  return PIPNN_OK;
+}
+
+// Run the pick on leaves [l0, l1) into picks indexed from offs[l0].
+pipnn_status run_pick(Index &I, const std::vector<int64_t> &offs, int64_t l0, int64_t l1,
+                      const uint32_t *d_members, uint32_t *pick_c, float *pick_d, hipStream_t s) {
+  const pipnn_params &P = I.p;
+  const int ksel = P.rescore_mult ? P.rescore_mult * P.k : P.k;
+  std::vector<KnnJob> jobs;
+  std::vector<KnnItem> items;
+  int32_t max_cols = 0;
+  const int64_t base = offs[(size_t)l0];
+  for (int64_t l = l0; l < l1; ++l) {
+    const int64_t sz = offs[(size_t)l + 1] - offs[(size_t)l];
+    if (sz < 2) continue;
+    KnnJob J;
+    J.row_off = offs[(size_t)l];
+    J.col_off = offs[(size_t)l];
+    J.out_off = offs[(size_t)l] - base;
+    J.n_rows = (int32_t)sz;
+    J.n_cols = (int32_t)sz;
+    J.k_sel = ksel;
+    J.flags = 1;
+    const int32_t jid = (int32_t)jobs.size();
+    jobs.push_back(J);
+    for (int64_t rb = 0; rb * kKnnRows < sz; ++rb) items.push_back({jid, (int32_t)rb});
+    max_cols = std::max<int32_t>(max_cols, (int32_t)sz);
+  }
+  const int64_t rows = offs[(size_t)l1] - base;
+  HIPCHK(launch_fill_u32(pick_c, kEmptyId, rows * P.k, s));
+  HIPCHK(launch_fill_u32(reinterpret_cast<uint32_t *>(pick_d), 0x7F800000u, rows * P.k, s));
+  if (items.empty()) return PIPNN_OK;
+  HIPCHK(upload(I.s_jobs, jobs, s));
+  HIPCHK(upload(I.s_items, items, s));
+  KnnLaunch L{};
+  L.idx = &I;
+  L.row_base = d_members;
+  L.col_base = d_members;
+  L.jobs = I.s_jobs.as<KnnJob>();
+  L.items = I.s_items.as<KnnItem>();
+  L.n_items = (int32_t)items.size();
+  L.max_cols = max_cols;
+  L.ksel = ksel;
+  L.k_out = P.k;
+  L.out_ids = 1;
+  L.recompute = 1;
+  L.rescore_k = P.rescore_mult ? P.k : 0;
+  L.out_col = pick_c;
+  L.out_dist = pick_d;
+  L.out_matrix = nullptr;
+  HIPCHK(launch_knn(L, s));
+  return PIPNN_OK;
+}
+
+// Bin records by destination and merge them into the reservoirs.
+pipnn_status bin_and_merge(Index &I, bool from_picks, const uint32_t *a, const uint32_t *b,
+                           const float *dist, int64_t count, int32_t k, uint64_t *res,
+                           hipStream_t s) {
+  const int64_t n = I.n;
+  HIPCHK(I.s_cnt.ensure((size_t)n * 4));
+  HIPCHK(I.s_off.ensure((size_t)(n + 1) * 8));
+  HIPCHK(I.s_tmp0.ensure((size_t)scan_tmp_elems(n) * 8));
+  HIPCHK(hipMemsetAsync(I.s_cnt.p, 0, (size_t)n * 4, s));
+  HIPCHK(hipMemsetAsync(I.flag.p, 0, 4, s));
+  if (from_picks)
+    HIPCHK(launch_bin_count(a, b, count, k, I.s_cnt.as<uint32_t>(), n, I.flag.as<int32_t>(), s));
+  else
+    HIPCHK(launch_rec_count(a, b, count, I.s_cnt.as<uint32_t>(), n, I.flag.as<int32_t>(), s));
+  int32_t flag = 0;
+  HIPCHK(hipMemcpyAsync(&flag, I.flag.p, 4, hipMemcpyDeviceToHost, s));
+  HIPCHK(launch_scan_u32(I.s_cnt.as<uint32_t>(), I.s_off.as<int64_t>(), n, I.s_tmp0.as<int64_t>(),
+                         s));
+  int64_t total = 0;
+  HIPCHK(hipMemcpyAsync(&total, I.s_off.as<int64_t>() + n, 8, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (flag) return fail(PIPNN_EDEVICE, "a record names a point id >= n");
+  HIPCHK(I.s_bins.ensure((size_t)std::max<int64_t>(total, 1) * 8));
+  HIPCHK(hipMemsetAsync(I.s_cnt.p, 0, (size_t)n * 4, s));
+  if (from_picks)
+    HIPCHK(launch_bin_scatter(a, b, dist, count, k, I.sketches.as<float>(), I.m,
+                              I.s_off.as<int64_t>(), I.s_cnt.as<uint32_t>(),
+                              I.s_bins.as<uint64_t>(), n, s));
+  else
+    HIPCHK(launch_rec_scatter(a, b, dist, count, I.sketches.as<float>(), I.m,
+                              I.s_off.as<int64_t>(), I.s_cnt.as<uint32_t>(),
+                              I.s_bins.as<uint64_t>(), n, s));
+  HIPCHK(launch_hashprune_merge(res, n, I.p.l_max, I.s_bins.as<uint64_t>(), I.s_off.as<int64_t>(),
+                                s));
+  return PIPNN_OK;
+}
+
+}  // namespace
+
+pipnn_status pipnn_build_leaves(pipnn_index *idx, const int64_t *d_leaf_offsets,
+                                const uint32_t *d_leaf_members, int64_t n_leaves,
+                                uint64_t *d_reservoirs, pipnn_stream_t stream) {
+  GUARD_BEGIN
+  if (!idx || !d_leaf_offsets || !d_reservoirs || n_leaves < 0)
+    return fail(PIPNN_EINVAL, "invalid argument");
+  if (n_leaves == 0) return PIPNN_OK;
+  if (!d_leaf_members) return fail(PIPNN_EINVAL, "members is NULL");
+  Index &I = *reinterpret_cast<Index *>(idx);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  std::vector<int64_t> offs;
+  pipnn_status st = read_offsets(d_leaf_offsets, n_leaves, s, offs);
+  if (st != PIPNN_OK) return st;
+  const int k = I.p.k;
+  // batches of leaves bounded in picks, so scratch stays bounded
+  const int64_t max_rows = std::max<int64_t>((int64_t)1 << 25, 65536);
+  int64_t l0 = 0;
+  while (l0 < n_leaves) {
+    int64_t l1 = l0 + 1;
+    while (l1 < n_leaves && offs[(size_t)l1 + 1] - offs[(size_t)l0] <= max_rows) ++l1;
+    const int64_t rows = offs[(size_t)l1] - offs[(size_t)l0];
+    HIPCHK(I.s_picks_c.ensure((size_t)std::max<int64_t>(rows, 1) * k * 4));
+    HIPCHK(I.s_picks_d.ensure((size_t)std::max<int64_t>(rows, 1) * k * 4));
+    st = run_pick(I, offs, l0, l1, d_leaf_members, I.s_picks_c.as<uint32_t>(),
+                  I.s_picks_d.as<float>(), s);
+    if (st != PIPNN_OK) return st;
+    st = bin_and_merge(I, true, d_leaf_members + offs[(size_t)l0], I.s_picks_c.as<uint32_t>(),
+                       I.s_picks_d.as<float>(), rows, k, d_reservoirs, s);
+    if (st != PIPNN_OK) return st;
+    l0 = l1;
+  }
+  return PIPNN_OK;
+  GUARD_END
+}
+
+pipnn_status pipnn_leaf_pick(pipnn_index *idx, const int64_t *d_leaf_offsets,
+                             const uint32_t *d_leaf_members, int64_t n_leaves, uint32_t *d_out_cand,
+                             float *d_out_dist, pipnn_stream_t stream) {
+  GUARD_BEGIN
+  if (!idx || !d_leaf_offsets || !d_out_cand || !d_out_dist || n_leaves < 0)
+    return fail(PIPNN_EINVAL, "invalid argument");
+  if (n_leaves == 0) return PIPNN_OK;
+  Index &I = *reinterpret_cast<Index *>(idx);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  std::vector<int64_t> offs;
+  pipnn_status st = read_offsets(d_leaf_offsets, n_leaves, s, offs);
+  if (st != PIPNN_OK) return st;
+  if (offs[0] != 0) return fail(PIPNN_EINVAL, "offsets[0] must be 0");
+  return run_pick(I, offs, 0, n_leaves, d_leaf_members, d_out_cand, d_out_dist, s);
+  GUARD_END
+}
+
+pipnn_status pipnn_knn_block(pipnn_index *idx, const uint32_t *d_row_ids, int64_t n_rows,
+                             const uint32_t *d_col_ids, int64_t n_cols, int32_t k,
+                             int32_t exclude_diag, uint32_t *d_out_col, float *d_out_dist,
+                             float *d_out_matrix, pipnn_stream_t stream) {
+  GUARD_BEGIN
+  if (!idx || !d_row_ids || !d_col_ids || !d_out_col) return fail(PIPNN_EINVAL, "NULL argument");
+  Index &I = *reinterpret_cast<Index *>(idx);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const int ksel = I.p.rescore_mult ? I.p.rescore_mult * k : k;
+  if (k < 1 || ksel > 32) return fail(PIPNN_EINVAL, "k out of range");
+  if (n_rows < 1 || n_cols < 1 || n_cols > 65535 || n_rows > 0x7FFFFFFF)
+    return fail(PIPNN_EINVAL, "bad block size");
+  if (exclude_diag && n_rows != n_cols) return fail(PIPNN_EINVAL, "exclude_diag needs a square block");
+  std::vector<KnnJob> jobs(1);
+  jobs[0].row_off = 0;
+  jobs[0].col_off = 0;
+  jobs[0].out_off = 0;
+  jobs[0].n_rows = (int32_t)n_rows;
+  jobs[0].n_cols = (int32_t)n_cols;
+  jobs[0].k_sel = ksel;
+  jobs[0].flags = exclude_diag ? 1 : 0;
+  std::vector<KnnItem> items;
+  for (int64_t rb = 0; rb * kKnnRows < n_rows; ++rb) items.push_back({0, (int32_t)rb});
+  HIPCHK(upload(I.s_jobs, jobs, s));
+  HIPCHK(upload(I.s_items, items, s));
+  KnnLaunch L{};
+  L.idx = &I;
+  L.row_base = d_row_ids;
+  L.col_base = d_col_ids;
+  L.jobs = I.s_jobs.as<KnnJob>();
+  L.items = I.s_items.as<KnnItem>();
+  L.n_items = (int32_t)items.size();
+  L.max_cols = (int32_t)n_cols;
+  L.ksel = ksel;
+  L.k_out = k;
+  L.out_ids = 0;
+  L.recompute = 1;
+  L.rescore_k = I.p.rescore_mult ? k : 0;
+  L.out_col = d_out_col;
+  L.out_dist = d_out_dist;
+  L.out_matrix = d_out_matrix;
+  L.matrix_ld = n_cols;
+  HIPCHK(launch_knn(L, s));
+  HIPCHK(hipStreamSynchronize(s));
+  return PIPNN_OK;
+  GUARD_END
+}
+
+pipnn_status pipnn_hashprune_insert(pipnn_index *idx, const uint32_t *d_dst,
+                                    const uint32_t *d_cand, const float *d_dist,
+                                    int64_t n_records, uint64_t *d_reservoirs,
+                                    pipnn_stream_t stream) {
+  GUARD_BEGIN
+  if (!idx || !d_reservoirs || n_records < 0) return fail(PIPNN_EINVAL, "invalid argument");
+  if (n_records == 0) return PIPNN_OK;
+  if (!d_dst || !d_cand || !d_dist) return fail(PIPNN_EINVAL, "NULL record array");
+  Index &I = *reinterpret_cast<Index *>(idx);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  return bin_and_merge(I, false, d_dst, d_cand, d_dist, n_records, 1, d_reservoirs, s);
+  GUARD_END
+}
+
+pipnn_status pipnn_reservoir_init(uint64_t *d_reservoirs, int64_t n, int32_t l_max,
+                                  pipnn_stream_t stream) {
+  GUARD_BEGIN
+  if (!d_reservoirs || n < 0 || l_max < 1) return fail(PIPNN_EINVAL, "invalid argument");
+  HIPCHK(launch_fill_u64(d_reservoirs, empty_slot(), n * (int64_t)l_max,
+                         reinterpret_cast<hipStream_t>(stream)));
+  return PIPNN_OK;
+  GUARD_END
+}
+
+pipnn_status pipnn_reservoir_canonical(const pipnn_index *idx, const uint64_t *d_res,
+                                       uint64_t *d_out, pipnn_stream_t stream) {
+  GUARD_BEGIN
+  if (!idx || !d_res || !d_out) return fail(PIPNN_EINVAL, "NULL argument");
+  const Index &I = *reinterpret_cast<const Index *>(idx);
+  HIPCHK(launch_reservoir_canonical(d_res, d_out, I.n, I.p.l_max,
+                                    reinterpret_cast<hipStream_t>(stream)));
+  return PIPNN_OK;
+  GUARD_END
+}
+
+pipnn_status pipnn_robustprune(pipnn_index *idx, const uint64_t *d_reservoirs, uint32_t *d_graph,
+                               uint32_t *d_degree, pipnn_stream_t stream) {
+  GUARD_BEGIN
+  if (!idx || !d_reservoirs || !d_graph || !d_degree) return fail(PIPNN_EINVAL, "NULL argument");
+  Index &I = *reinterpret_cast<Index *>(idx);
+  HIPCHK(launch_robustprune(I, d_reservoirs, d_graph, d_degree,
+                            reinterpret_cast<hipStream_t>(stream)));
+  return PIPNN_OK;
+  GUARD_END
+}
+
+pipnn_status pipnn_start_node(pipnn_index *idx, uint32_t *h_out, pipnn_stream_t stream) {
+  GUARD_BEGIN
+  if (!idx || !h_out) return fail(PIPNN_EINVAL, "NULL argument");
+  Index &I = *reinterpret_cast<Index *>(idx);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const int64_t nb = (I.n + 255) / 256;
+  HIPCHK(I.s_tmp1.ensure((size_t)(I.d + 2 * nb + 1) * 8 + 8));
+  uint32_t *dout = reinterpret_cast<uint32_t *>(I.s_tmp1.as<double>() + I.d + 2 * nb + 1);
+  HIPCHK(launch_start_node(I, I.s_tmp1.as<double>(), dout, s));
+  HIPCHK(hipMemcpyAsync(h_out, dout, 4, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  return PIPNN_OK;
+  GUARD_END
+}
+
+pipnn_status pipnn_search(pipnn_index *idx, const uint32_t *d_graph, const void *d_Q, int64_t nq,
+                          int32_t q_dtype, int32_t k, int32_t L, uint32_t start,
+                          uint32_t *d_out_ids, float *d_out_dist, uint32_t *d_out_cmps,
+                          pipnn_stream_t stream) {
+  GUARD_BEGIN
+  if (!idx || !d_graph || !d_out_ids || (!d_Q && nq > 0) || nq < 0)
+    return fail(PIPNN_EINVAL, "invalid argument");
+  Index &I = *reinterpret_cast<Index *>(idx);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  if (k < 1 || k > L || L > 1024) return fail(PIPNN_EINVAL, "need 1 <= k <= L <= 1024");
+  if ((int64_t)start >= I.n) return fail(PIPNN_EINVAL, "start >= n");
+  if (q_dtype != PIPNN_DTYPE_F32 && q_dtype != PIPNN_DTYPE_F16 && q_dtype != PIPNN_DTYPE_BF16)
+    return fail(PIPNN_EINVAL, "unknown q_dtype");
+  if (nq == 0) return PIPNN_OK;
+  const float *Q = reinterpret_cast<const float *>(d_Q);
+  if (q_dtype != PIPNN_DTYPE_F32) {
+    HIPCHK(I.s_tmp0.ensure((size_t)nq * I.d * 4));
+    HIPCHK(launch_to_f32(d_Q, q_dtype, I.s_tmp0.as<float>(), nq * (int64_t)I.d, s));
+    Q = I.s_tmp0.as<float>();
+  }
+  const int64_t words = (I.n + 31) / 32;
+  const int64_t budget_words = (int64_t)1 << 26;  // 256 MiB of seen bitmaps
+  const int64_t batch = std::max<int64_t>(1, std::min<int64_t>(nq, budget_words / words));
+  HIPCHK(I.s_tmp1.ensure((size_t)batch * words * 4));
+  for (int64_t q0 = 0; q0 < nq; q0 += batch) {
+    const int64_t nb = std::min(batch, nq - q0);
+    HIPCHK(hipMemsetAsync(I.s_tmp1.p, 0, (size_t)nb * words * 4, s));
+    HIPCHK(launch_search(I, d_graph, Q + q0 * I.d, nb, k, L, start, d_out_ids + q0 * k,
+                         d_out_dist ? d_out_dist + q0 * k : nullptr,
+                         d_out_cmps ? d_out_cmps + q0 : nullptr, I.s_tmp1.as<uint32_t>(), words,
+                         s));
+  }
+  return PIPNN_OK;
+  GUARD_END
+}
+
+pipnn_status pipnn_get_sketches(const pipnn_index *idx, float *d_out, pipnn_stream_t stream) {
+  GUARD_BEGIN
+  if (!idx || !d_out) return fail(PIPNN_EINVAL, "NULL argument");
+  const Index &I = *reinterpret_cast<const Index *>(idx);
+  HIPCHK(hipMemcpyAsync(d_out, I.sketches.p, (size_t)I.n * I.m * 4, hipMemcpyDeviceToDevice,
+                        reinterpret_cast<hipStream_t>(stream)));
+  return PIPNN_OK;
+  GUARD_END
+}
+
+}  // extern "C"

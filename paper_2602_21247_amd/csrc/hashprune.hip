@@ -1,0 +1,288 @@
+// HashPrune on gfx950 (Sec. 3, Alg. 3).
+//
+// Candidate records are first binned by destination point (a counting sort:
+// per-point counts, an exclusive scan, then a scatter). Each binned record
+// is already a reservoir slot: candidate id, the residualized hash h_p(c)
+// (bit b set iff Sketch(c)_b >= Sketch(p)_b) and the bf16 distance.
+//
+// One wave then merges a point's reservoir with its bin. By the
+// history-independence lemma the result is the l_max smallest keys among
+// the per-bucket minimum keys of (reservoir U bin), where a key is
+// (bf16 distance, id). The merge computes exactly that: a bitonic sort of
+// (hash, key) in LDS, the first entry of every hash run (its bucket's
+// minimum), a second sort by key, and the first l_max. Large bins are taken
+// in chunks; since dropped bucket minima can never re-enter (every kept key
+// is smaller and sits in a different bucket), merging chunk by chunk gives
+// the same reservoir as one merge. Atomics decide only record positions
+// inside a bin, never reservoir contents, so the result is deterministic.
+#include "common.hpp"
+#include "internal.hpp"
+
+namespace pipnn {
+
+__device__ __forceinline__ uint32_t hash_of(const float *__restrict__ S, int m, uint32_t p,
+                                            uint32_t c) {
+  const float *sp = S + (int64_t)p * m;
+  const float *sc = S + (int64_t)c * m;
+  uint32_t h = 0;
+  for (int b = 0; b < m; ++b) h |= (sc[b] >= sp[b] ? 1u : 0u) << b;
+  return h;
+}
+
+// picks: n_rows x k candidate ids (0xFFFFFFFF unused); row g belongs to
+// point row_ids[g]. Each pick (i -> j) yields the records (i, j) and (j, i).
+__global__ void bin_count_kernel(const uint32_t *row_ids, const uint32_t *picks, int64_t n_rows,
+                                 int k, uint32_t *cnt, int64_t n, int32_t *flag) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n_rows * k) return;
+  const uint32_t j = picks[t];
+  if (j == kEmptyId) return;
+  const uint32_t i = row_ids[t / k];
+  if (i >= n || j >= n) {
+    atomicOr(flag, 1);
+    return;
+  }
+  if (i == j) return;
+  atomicAdd(&cnt[i], 1u);
+  atomicAdd(&cnt[j], 1u);
+}
+
+__global__ void bin_scatter_kernel(const uint32_t *row_ids, const uint32_t *picks,
+                                   const float *dist, int64_t n_rows, int k, const float *S, int m,
+                                   const int64_t *off, uint32_t *cursor, uint64_t *bins, int64_t n) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n_rows * k) return;
+  const uint32_t j = picks[t];
+  if (j == kEmptyId) return;
+  const uint32_t i = row_ids[t / k];
+  if (i >= n || j >= n || i == j) return;
+  const uint32_t bf = bf16_rne(dist[t]);
+  const uint32_t hij = hash_of(S, m, i, j);
+  const uint32_t hji = hash_of(S, m, j, i);
+  const int64_t pi = off[i] + atomicAdd(&cursor[i], 1u);
+  bins[pi] = slot_pack(j, hij, bf);
+  const int64_t pj = off[j] + atomicAdd(&cursor[j], 1u);
+  bins[pj] = slot_pack(i, hji, bf);
+}
+
+hipError_t launch_bin_count(const uint32_t *row_ids, const uint32_t *picks, int64_t n_rows,
+                            int32_t k, uint32_t *cnt, int64_t n, int32_t *flag, hipStream_t s) {
+  const int64_t tot = n_rows * k;
+  if (tot == 0) return hipSuccess;
+  hipLaunchKernelGGL(bin_count_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s,
+                     row_ids, picks, n_rows, k, cnt, n, flag);
+  return hipGetLastError();
+}
+
+hipError_t launch_bin_scatter(const uint32_t *row_ids, const uint32_t *picks, const float *dist,
+                              int64_t n_rows, int32_t k, const float *sketch, int32_t m,
+                              const int64_t *off, uint32_t *cursor, uint64_t *bins, int64_t n,
+                              hipStream_t s) {
+  const int64_t tot = n_rows * k;
+  if (tot == 0) return hipSuccess;
+  hipLaunchKernelGGL(bin_scatter_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s,
+                     row_ids, picks, dist, n_rows, k, sketch, m, off, cursor, bins, n);
+  return hipGetLastError();
+}
+
+// Explicit records (p = dst, c = cand, dist) for pipnn_hashprune_insert.
+__global__ void rec_count_kernel(const uint32_t *dst, const uint32_t *cand, int64_t cnt_rec,
+                                 uint32_t *cnt, int64_t n, int32_t *flag) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= cnt_rec) return;
+  const uint32_t p = dst[t], c = cand[t];
+  if (p >= n || c >= n) {
+    atomicOr(flag, 1);
+    return;
+  }
+  if (p == c) return;
+  atomicAdd(&cnt[p], 1u);
+}
+
+__global__ void rec_scatter_kernel(const uint32_t *dst, const uint32_t *cand, const float *dist,
+                                   int64_t cnt_rec, const float *S, int m, const int64_t *off,
+                                   uint32_t *cursor, uint64_t *bins, int64_t n) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= cnt_rec) return;
+  const uint32_t p = dst[t], c = cand[t];
+  if (p >= n || c >= n || p == c) return;
+  const int64_t pos = off[p] + atomicAdd(&cursor[p], 1u);
+  bins[pos] = slot_pack(c, hash_of(S, m, p, c), bf16_rne(dist[t]));
+}
+
+hipError_t launch_rec_count(const uint32_t *dst, const uint32_t *cand, int64_t cnt_rec,
+                            uint32_t *cnt, int64_t n, int32_t *flag, hipStream_t s) {
+  if (cnt_rec == 0) return hipSuccess;
+  hipLaunchKernelGGL(rec_count_kernel, dim3((unsigned)((cnt_rec + 255) / 256)), dim3(256), 0, s,
+                     dst, cand, cnt_rec, cnt, n, flag);
+  return hipGetLastError();
+}
+
+hipError_t launch_rec_scatter(const uint32_t *dst, const uint32_t *cand, const float *dist,
+                              int64_t cnt_rec, const float *sketch, int32_t m, const int64_t *off,
+                              uint32_t *cursor, uint64_t *bins, int64_t n, hipStream_t s) {
+  if (cnt_rec == 0) return hipSuccess;
+  hipLaunchKernelGGL(rec_scatter_kernel, dim3((unsigned)((cnt_rec + 255) / 256)), dim3(256), 0, s,
+                     dst, cand, dist, cnt_rec, sketch, m, off, cursor, bins, n);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------
+constexpr int kMergeArr = 512;          // LDS entries per wave and array
+constexpr int kMergeWaves = 4;
+constexpr uint64_t kNone = ~0ull;
+
+// key1 = (hash, rank16(bf16), id): groups buckets, minimum first.
+// key2 = (rank16(bf16), id, hash): the reservoir order.
+__device__ __forceinline__ uint64_t key1_of_slot(uint64_t s) {
+  return ((uint64_t)slot_hash(s) << 48) | ((uint64_t)bf16_rank(slot_bf(s)) << 32) | slot_id(s);
+}
+__device__ __forceinline__ uint64_t key2_of_key1(uint64_t k1) {
+  const uint64_t hash = k1 >> 48, rank = (k1 >> 32) & 0xFFFFu, id = k1 & 0xFFFFFFFFu;
+  return (rank << 48) | (id << 16) | hash;
+}
+__device__ __forceinline__ uint64_t key1_of_key2(uint64_t k2) {
+  const uint64_t rank = k2 >> 48, id = (k2 >> 16) & 0xFFFFFFFFu, hash = k2 & 0xFFFFu;
+  return (hash << 48) | (rank << 32) | id;
+}
+__device__ __forceinline__ uint64_t slot_of_key2(uint64_t k2) {
+  const uint32_t rank = (uint32_t)(k2 >> 48), id = (uint32_t)((k2 >> 16) & 0xFFFFFFFFu),
+                 hash = (uint32_t)(k2 & 0xFFFFu);
+  return slot_pack(id, hash, rank_to_bf16(rank));
+}
+
+__device__ void wave_bitonic_sort(uint64_t *A, int P) {
+  const int lane = lane_id();
+  for (int k = 2; k <= P; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int t = lane; t < P / 2; t += 64) {
+        const int i = (t / j) * 2 * j + (t % j);
+        const int l = i + j;
+        const bool asc = (i & k) == 0;
+        const uint64_t x = A[i], y = A[l];
+        if ((x > y) == asc) {
+          A[i] = y;
+          A[l] = x;
+        }
+      }
+      wave_sync();
+    }
+  }
+}
+
+__device__ __forceinline__ int pow2_at_least(int v) {
+  int P = 2;
+  while (P < v) P <<= 1;
+  return P;
+}
+
+__global__ void __launch_bounds__(64 * kMergeWaves) hashprune_merge_kernel(
+    uint64_t *__restrict__ res, int64_t n, int l_max, const uint64_t *__restrict__ bins,
+    const int64_t *__restrict__ off) {
+  __shared__ uint64_t sA[kMergeWaves][kMergeArr];
+  __shared__ uint64_t sB[kMergeWaves][kMergeArr];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t p = (int64_t)blockIdx.x * kMergeWaves + wave;
+  if (p >= n) return;
+  const int64_t b0 = off[p], b1 = off[p + 1];
+  if (b1 == b0) return;
+  uint64_t *A = sA[wave];
+  uint64_t *B = sB[wave];
+  uint64_t *r = res + p * l_max;
+  const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+
+  // current reservoir -> B as key2, compacted
+  int nres = 0;
+  for (int base = 0; base < l_max; base += 64) {
+    const int i = base + lane;
+    const uint64_t s = i < l_max ? r[i] : empty_slot();
+    const bool ok = slot_id(s) != kEmptyId;
+    const uint64_t mask = __ballot(ok);
+    if (ok) B[nres + __popcll(mask & below)] = key2_of_key1(key1_of_slot(s));
+    nres += __popcll(mask);
+  }
+  wave_sync();
+
+  const int chunk_cap = kMergeArr - l_max;
+  for (int64_t c0 = b0; c0 < b1; c0 += chunk_cap) {
+    const int nc = (int)min((int64_t)chunk_cap, b1 - c0);
+    const int tot = nres + nc;
+    const int P = pow2_at_least(tot);
+    for (int i = lane; i < P; i += 64) {
+      uint64_t k1 = kNone;
+      if (i < nres) {
+        k1 = key1_of_key2(B[i]);
+      } else if (i < tot) {
+        k1 = key1_of_slot(bins[c0 + (i - nres)]);
+      }
+      A[i] = k1;
+    }
+    wave_sync();
+    wave_bitonic_sort(A, P);
+    // first entry of each hash run = the bucket's minimum key
+    int nk = 0;
+    for (int base = 0; base < P; base += 64) {
+      const int i = base + lane;
+      bool keep = false;
+      uint64_t k1 = kNone;
+      if (i < P) {
+        k1 = A[i];
+        keep = k1 != kNone && (i == 0 || (A[i - 1] >> 48) != (k1 >> 48));
+      }
+      const uint64_t mask = __ballot(keep);
+      if (keep) B[nk + __popcll(mask & below)] = key2_of_key1(k1);
+      nk += __popcll(mask);
+    }
+    wave_sync();
+    const int P2 = pow2_at_least(nk);
+    for (int i = nk + lane; i < P2; i += 64) B[i] = kNone;
+    wave_sync();
+    wave_bitonic_sort(B, P2);
+    nres = nk < l_max ? nk : l_max;
+  }
+  for (int i = lane; i < l_max; i += 64) r[i] = i < nres ? slot_of_key2(B[i]) : empty_slot();
+}
+
+hipError_t launch_hashprune_merge(uint64_t *res, int64_t n, int32_t l_max, const uint64_t *bins,
+                                  const int64_t *off, hipStream_t s) {
+  if (l_max > 256) return hipErrorInvalidValue;
+  const int64_t blocks = (n + kMergeWaves - 1) / kMergeWaves;
+  hipLaunchKernelGGL(hashprune_merge_kernel, dim3((unsigned)blocks), dim3(64 * kMergeWaves), 0, s,
+                     res, n, l_max, bins, off);
+  return hipGetLastError();
+}
+
+// Canonical layout: per point, valid slots by (bf16 distance, id), empties last.
+__global__ void __launch_bounds__(64 * kMergeWaves) canonical_kernel(const uint64_t *in,
+                                                                     uint64_t *out, int64_t n,
+                                                                     int l_max) {
+  __shared__ uint64_t sA[kMergeWaves][256];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t p = (int64_t)blockIdx.x * kMergeWaves + wave;
+  if (p >= n) return;
+  uint64_t *A = sA[wave];
+  const int P = pow2_at_least(l_max);
+  for (int i = lane; i < P; i += 64) {
+    uint64_t k2 = kNone;
+    if (i < l_max) {
+      const uint64_t s = in[p * l_max + i];
+      if (slot_id(s) != kEmptyId) k2 = key2_of_key1(key1_of_slot(s));
+    }
+    A[i] = k2;
+  }
+  wave_sync();
+  wave_bitonic_sort(A, P);
+  for (int i = lane; i < l_max; i += 64)
+    out[p * l_max + i] = A[i] != kNone ? slot_of_key2(A[i]) : empty_slot();
+}
+
+hipError_t launch_reservoir_canonical(const uint64_t *in, uint64_t *out, int64_t n, int32_t l_max,
+                                      hipStream_t s) {
+  if (l_max > 256) return hipErrorInvalidValue;
+  const int64_t blocks = (n + kMergeWaves - 1) / kMergeWaves;
+  hipLaunchKernelGGL(canonical_kernel, dim3((unsigned)blocks), dim3(64 * kMergeWaves), 0, s, in, out,
+                     n, l_max);
+  return hipGetLastError();
+}
+
+}  // namespace pipnn

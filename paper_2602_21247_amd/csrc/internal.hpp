@@ -1,0 +1,147 @@
+// Host-side structures of the PiPNN gfx950 library and the launchers each
+// kernel file provides.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/pipnn.h"
+
+namespace pipnn {
+
+// A device buffer owned by the index; grows on demand, never shrinks.
+struct DevBuf {
+  void *p = nullptr;
+  size_t cap = 0;
+  hipError_t ensure(size_t bytes);
+  void release();
+  template <class T> T *as() const { return reinterpret_cast<T *>(p); }
+};
+
+struct Index {
+  pipnn_params p;
+  const void *X = nullptr;  // n x d, caller-owned
+  int64_t n = 0;
+  int32_t d = 0;
+  int32_t x_dtype = PIPNN_DTYPE_F32;
+  const float *H = nullptr;  // m x d, caller-owned
+  int32_t m = 0;
+  hipStream_t stream = nullptr;
+
+  DevBuf xf32;      // float32 copy of X when X is not float32
+  DevBuf xlow;      // low-precision copy for the leaf GEMM (bf16 / fp16 / fp8)
+  DevBuf xscale;    // per-point fp8 scale (value = code * scale)
+  DevBuf sketches;  // n x m float32
+  DevBuf norms;     // n float32, squared norms (of the GEMM operand)
+  DevBuf flag;      // int32 device error flag
+
+  // scratch reused across calls
+  DevBuf s_jobs, s_items, s_picks_c, s_picks_d, s_cnt, s_off, s_bins, s_tmp0, s_tmp1;
+  std::vector<DevBuf> levels;   // partition level member arrays
+  DevBuf p_asg, p_leaders, p_cm, p_bstart, p_groups, p_gout, p_gsize, p_copy;
+
+  const float *xf() const;
+};
+
+// ---- knn (fused distance GEMM + per-row selection) --------------------
+struct KnnJob {
+  int64_t row_off;   // into row_base
+  int64_t col_off;   // into col_base
+  int64_t out_off;   // first output row
+  int32_t n_rows, n_cols;
+  int32_t k_sel;     // number of GEMM-nearest kept (<= KSEL)
+  int32_t flags;     // bit 0: exclude the column at the row's own position
+};
+struct KnnItem {
+  int32_t job, rb;
+};
+
+struct KnnLaunch {
+  const Index *idx;
+  const uint32_t *row_base, *col_base;
+  const KnnJob *jobs;
+  const KnnItem *items;
+  int32_t n_items;
+  int32_t max_cols;      // largest n_cols over the jobs
+  int32_t ksel;          // selection size used to pick the template
+  int32_t k_out;         // outputs per row
+  int32_t out_ids;       // 1: write col_base ids, 0: write column indices
+  int32_t recompute;     // 1: FP32 direct-difference distance of the winners
+  int32_t rescore_k;     // > 0: keep this many of the k_sel by the direct distance
+  uint32_t *out_col;
+  float *out_dist;
+  float *out_matrix;
+  int64_t matrix_ld;
+};
+hipError_t launch_knn(const KnnLaunch &L, hipStream_t s);
+
+// ---- misc kernels ----------------------------------------------------
+hipError_t launch_norms_sketches(const Index &I, hipStream_t s);
+hipError_t launch_to_f32(const void *src, int dtype, float *dst, int64_t count, hipStream_t s);
+hipError_t launch_iota(uint32_t *dst, int64_t n, hipStream_t s);
+hipError_t launch_fill_u32(uint32_t *dst, uint32_t v, int64_t n, hipStream_t s);
+hipError_t launch_fill_u64(uint64_t *dst, uint64_t v, int64_t n, hipStream_t s);
+// exclusive scan of n uint32 into n+1 int64 (out[n] = total); tmp holds
+// scan_tmp_elems(n) int64
+int64_t scan_tmp_elems(int64_t n);
+hipError_t launch_scan_u32(const uint32_t *in, int64_t *out, int64_t n, int64_t *tmp, hipStream_t s);
+hipError_t launch_scan_i64_inplace(int64_t *data, int64_t n, int64_t *tmp, hipStream_t s);
+hipError_t launch_gather_u32(const uint32_t *src, const int64_t *idx, uint32_t *dst, int64_t n,
+                             hipStream_t s);
+
+// ---- partition group-by ------------------------------------------------
+struct GroupSub {
+  int64_t elem_off;   // first element (instance x fanout slot) of the subproblem
+  int64_t n_elems;
+  int64_t cm_off;     // first counter of its (bucket x tile) matrix
+  int32_t n_buckets;  // leaders
+  int32_t n_tiles;
+  int64_t bucket_off; // first global bucket index
+};
+struct GroupTile {
+  int32_t sub, tile;
+};
+hipError_t launch_groupby(const uint32_t *asg_col, const uint32_t *src_ids, int32_t *fan,
+                          const GroupSub *subs, const GroupTile *tiles, int32_t n_tiles,
+                          int32_t tile_elems, int64_t *cm, int64_t cm_len, int64_t *tmp,
+                          uint32_t *out, int64_t *bucket_start, int64_t n_buckets_total,
+                          hipStream_t s);
+struct MergeGroup {
+  int64_t src_off[1];
+};
+hipError_t launch_merge_dedup(const uint32_t *const *seg_ptr, const int32_t *seg_len,
+                              const int32_t *grp_first_seg, int32_t n_groups, int32_t max_sum,
+                              uint32_t *out, const int64_t *out_off, int32_t *out_size,
+                              hipStream_t s);
+hipError_t launch_copy_segments(const uint32_t *const *src, const int64_t *dst_off,
+                                const int32_t *len, int32_t n_segs, uint32_t *dst, hipStream_t s);
+
+// ---- HashPrune -------------------------------------------------------
+hipError_t launch_bin_count(const uint32_t *row_ids, const uint32_t *picks, int64_t n_rows,
+                            int32_t k, uint32_t *cnt, int64_t n, int32_t *flag, hipStream_t s);
+hipError_t launch_bin_scatter(const uint32_t *row_ids, const uint32_t *picks, const float *dist,
+                              int64_t n_rows, int32_t k, const float *sketch, int32_t m,
+                              const int64_t *off, uint32_t *cursor, uint64_t *bins, int64_t n,
+                              hipStream_t s);
+hipError_t launch_rec_count(const uint32_t *dst, const uint32_t *cand, int64_t cnt_rec,
+                            uint32_t *cnt, int64_t n, int32_t *flag, hipStream_t s);
+hipError_t launch_rec_scatter(const uint32_t *dst, const uint32_t *cand, const float *dist,
+                              int64_t cnt_rec, const float *sketch, int32_t m, const int64_t *off,
+                              uint32_t *cursor, uint64_t *bins, int64_t n, hipStream_t s);
+hipError_t launch_hashprune_merge(uint64_t *res, int64_t n, int32_t l_max, const uint64_t *bins,
+                                  const int64_t *off, hipStream_t s);
+hipError_t launch_reservoir_canonical(const uint64_t *in, uint64_t *out, int64_t n, int32_t l_max,
+                                      hipStream_t s);
+
+// ---- RobustPrune / search ---------------------------------------------
+hipError_t launch_robustprune(const Index &I, const uint64_t *res, uint32_t *graph, uint32_t *degree,
+                              hipStream_t s);
+hipError_t launch_start_node(const Index &I, double *tmp, uint32_t *out, hipStream_t s);
+hipError_t launch_search(const Index &I, const uint32_t *graph, const float *Q, int64_t nq,
+                         int32_t k, int32_t L, uint32_t start, uint32_t *out_ids, float *out_dist,
+                         uint32_t *out_cmps, uint32_t *visited_bits, int64_t words_per_query,
+                         hipStream_t s);
+
+}  // namespace pipnn

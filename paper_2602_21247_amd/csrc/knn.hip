@@ -1,0 +1,424 @@
+// Fused leaf distance GEMM + per-row k-nearest selection for gfx950.
+//
+// One kernel serves every dense "rows x columns -> k nearest columns per
+// row" step of PiPNN:
+//   - the leaf pick (Sec. 4.2): rows = columns = the members of a leaf, the
+//     own column excluded, k nearest by (distance, column);
+//   - the ball-carving assignment (Alg. 5): rows = the points of a
+//     subproblem, columns = its leaders, f nearest leaders per point.
+// The distance of a pair is the GEMM form ||x||^2 + ||y||^2 - 2 x.y
+// (squared L2) or -x.y (negated inner product), with x.y on MFMA.
+//
+// Work decomposition: a work item is (job, block of 32*NW rows). A
+// workgroup of NW waves owns one item; wave w owns 32 rows and keeps their
+// A operand (the row vectors) in registers for the whole item. Column
+// tiles of 64 points are staged in LDS (row stride d+4 floats, so the
+// 16-byte fragment reads are bank-conflict free) and shared by the NW
+// waves; the next tile is prefetched into registers while the current one
+// is multiplied.
+//
+// Selection: each row keeps its KSEL best (distance, column) pairs in LDS
+// and a threshold tau (the worst kept pair once KSEL are kept). After each
+// 32x32 MFMA block, every lane tests its 16 accumulator entries against the
+// tau of their rows and appends the survivors to the row's LDS buffer; one
+// owner lane per row then drains the buffer into the kept set. The filter
+// uses <= so that equal distances with a smaller column are not lost; the
+// drain applies the exact (distance, column) order.
+//
+// Epilogue: the kept pairs are sorted by (GEMM distance, column); when
+// asked, each winner's FP32 distance is recomputed by direct difference,
+// sum_i (x_i - y_i)^2 (or -sum x_i y_i), over four fixed quarter-slices of
+// the dimensions reduced in a fixed order, so a pair always gets the same
+// value whichever row it is found from. With rescoring, the k_sel GEMM
+// winners are re-ranked by (direct distance, column) and the first k kept.
+#include "common.hpp"
+#include "internal.hpp"
+
+namespace pipnn {
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+struct KnnArgs {
+  const float *X;
+  const float *norms;
+  const uint32_t *row_base;
+  const uint32_t *col_base;
+  const KnnJob *jobs;
+  const KnnItem *items;
+  uint32_t *out_col;
+  float *out_dist;
+  float *out_matrix;
+  int64_t matrix_ld;
+  int32_t n_items;
+  int32_t d;
+  int32_t metric;
+  int32_t k_out;
+  int32_t out_ids;
+  int32_t recompute;
+  int32_t rescore_k;
+};
+
+// Row (0..31) of accumulator entry v held by a lane in the upper (h=1) or
+// lower (h=0) half of the wave, for v_mfma_f32_32x32x2_f32.
+__device__ __forceinline__ int acc_row(int v, int h) { return (v & 3) + 8 * (v >> 2) + 4 * h; }
+
+template <int DP, int KSEL, int NW>
+__global__ void __launch_bounds__(NW * 64) knn_f32_kernel(KnnArgs a) {
+  constexpr int BM = 32 * NW;     // rows per workgroup
+  constexpr int BN = 64;          // columns per tile
+  constexpr int LDB = DP + 4;     // LDS stride of a staged column vector (floats)
+  constexpr int HALF = DP / 2;    // k-range owned by each half of the wave
+  constexpr int CAP = BN;         // per-row buffer: a tile appends at most BN
+  constexpr int BUFD = CAP + 1;
+  constexpr int BUFC = CAP + 2;
+  constexpr int KS1 = KSEL + 1;
+  constexpr int NTH = NW * 64;
+  constexpr int F4_PER_TILE = BN * DP / 4;
+  constexpr int NPRE = (F4_PER_TILE + NTH - 1) / NTH;
+
+  __shared__ __attribute__((aligned(16))) float sB[BN * LDB];
+  __shared__ float sBufD[BM * BUFD];
+  __shared__ uint16_t sBufC[BM * BUFC];
+  __shared__ float sTopD[BM * KS1];
+  __shared__ uint32_t sTopC[BM * KS1];
+  __shared__ float sTau[BM];
+  __shared__ int sBufN[BM];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int h = lane >> 5, l32 = lane & 31;
+  const int item = xcd_item(blockIdx.x, gridDim.x);
+  if (item >= a.n_items) return;
+  const KnnItem it = a.items[item];
+  const KnnJob J = a.jobs[it.job];
+  const int rbase = it.rb * BM;
+  const int wrow = rbase + wave * 32;
+  const uint32_t *rows = a.row_base + J.row_off;
+  const uint32_t *cols = a.col_base + J.col_off;
+  const int d = a.d;
+  const bool l2 = a.metric == PIPNN_METRIC_L2;
+  const bool excl = (J.flags & 1) != 0;
+  const bool full_d = (d == DP);
+  const int n_rows = J.n_rows, n_cols = J.n_cols;
+
+  for (int r = tid; r < BM; r += NTH) {
+    sTau[r] = INFINITY;
+    sBufN[r] = 0;
+  }
+
+  // A operand: lane holds row l32 of this wave, dims [h*HALF, h*HALF+HALF).
+  float av[HALF];
+  {
+    const int r = wrow + l32;
+    if (r < n_rows) {
+      const float *src = a.X + (int64_t)rows[r] * d + h * HALF;
+      if (full_d) {
+#pragma unroll
+        for (int kk = 0; kk < HALF; kk += 4) {
+          float4 q = *reinterpret_cast<const float4 *>(src + kk);
+          av[kk] = q.x; av[kk + 1] = q.y; av[kk + 2] = q.z; av[kk + 3] = q.w;
+        }
+      } else {
+#pragma unroll
+        for (int kk = 0; kk < HALF; ++kk) av[kk] = (h * HALF + kk < d) ? src[kk] : 0.f;
+      }
+    } else {
+#pragma unroll
+      for (int kk = 0; kk < HALF; ++kk) av[kk] = 0.f;
+    }
+  }
+  // squared norms of the 16 rows this lane's accumulator entries belong to
+  float nr[16];
+  bool rvalid[16];
+#pragma unroll
+  for (int v = 0; v < 16; ++v) {
+    const int rr = wrow + acc_row(v, h);
+    rvalid[v] = rr < n_rows;
+    nr[v] = (rvalid[v] && l2) ? a.norms[rows[rr]] : 0.f;
+  }
+
+  // owner-lane state (lanes 0..31 own row wrow + lane)
+  const int orow = wave * 32 + l32;  // LDS row index
+  int tn = 0, maxpos = 0;
+  float maxd = INFINITY;
+  uint32_t maxc = 0xFFFFFFFFu;
+
+  // column tile staging: thread t loads float4s t, t+NTH, ... of the tile
+  float4 pre[NPRE];
+  auto load_tile = [&](int c0) {
+#pragma unroll
+    for (int i = 0; i < NPRE; ++i) {
+      const int q = tid + i * NTH;
+      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (q < F4_PER_TILE) {
+        const int c = q / (DP / 4), kq = (q % (DP / 4)) * 4;
+        const int cc = c0 + c;
+        if (cc < n_cols) {
+          const float *src = a.X + (int64_t)cols[cc] * d + kq;
+          if (full_d) {
+            v = *reinterpret_cast<const float4 *>(src);
+          } else {
+            v.x = kq < d ? src[0] : 0.f;
+            v.y = kq + 1 < d ? src[1] : 0.f;
+            v.z = kq + 2 < d ? src[2] : 0.f;
+            v.w = kq + 3 < d ? src[3] : 0.f;
+          }
+        }
+      }
+      pre[i] = v;
+    }
+  };
+  auto store_tile = [&]() {
+#pragma unroll
+    for (int i = 0; i < NPRE; ++i) {
+      const int q = tid + i * NTH;
+      if (q < F4_PER_TILE) {
+        const int c = q / (DP / 4), kq = (q % (DP / 4)) * 4;
+        *reinterpret_cast<float4 *>(&sB[c * LDB + kq]) = pre[i];
+      }
+    }
+  };
+
+  auto drain = [&]() {
+    // lanes 0..31: move the buffered survivors of row `orow` into its kept set
+    if (l32 == lane && wrow + l32 < n_rows) {
+      const int nb = sBufN[orow];
+      for (int e = 0; e < nb; ++e) {
+        const float dv = sBufD[orow * BUFD + e];
+        const uint32_t cv = sBufC[orow * BUFC + e];
+        if (tn < KSEL) {
+          sTopD[orow * KS1 + tn] = dv;
+          sTopC[orow * KS1 + tn] = cv;
+          ++tn;
+          if (tn == KSEL) {
+            maxpos = 0; maxd = sTopD[orow * KS1]; maxc = sTopC[orow * KS1];
+            for (int i = 1; i < KSEL; ++i) {
+              const float di = sTopD[orow * KS1 + i];
+              const uint32_t ci = sTopC[orow * KS1 + i];
+              if (di > maxd || (di == maxd && ci > maxc)) { maxd = di; maxc = ci; maxpos = i; }
+            }
+          }
+        } else if (dv < maxd || (dv == maxd && cv < maxc)) {
+          sTopD[orow * KS1 + maxpos] = dv;
+          sTopC[orow * KS1 + maxpos] = cv;
+          maxpos = 0; maxd = sTopD[orow * KS1]; maxc = sTopC[orow * KS1];
+          for (int i = 1; i < KSEL; ++i) {
+            const float di = sTopD[orow * KS1 + i];
+            const uint32_t ci = sTopC[orow * KS1 + i];
+            if (di > maxd || (di == maxd && ci > maxc)) { maxd = di; maxc = ci; maxpos = i; }
+          }
+        }
+      }
+      sBufN[orow] = 0;
+      sTau[orow] = (tn == KSEL) ? maxd : INFINITY;
+    }
+  };
+
+  load_tile(0);
+  store_tile();
+  __syncthreads();
+
+  for (int c0 = 0; c0 < n_cols; c0 += BN) {
+    const bool has_next = c0 + BN < n_cols;
+    if (has_next) load_tile(c0 + BN);
+
+    f32x16 acc0, acc1;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) { acc0[v] = 0.f; acc1[v] = 0.f; }
+    const float *b0p = &sB[l32 * LDB + h * HALF];
+    const float *b1p = &sB[(32 + l32) * LDB + h * HALF];
+#pragma unroll
+    for (int kk = 0; kk < HALF; kk += 4) {
+      const float4 b0 = *reinterpret_cast<const float4 *>(b0p + kk);
+      const float4 b1 = *reinterpret_cast<const float4 *>(b1p + kk);
+      acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(av[kk], b0.x, acc0, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(av[kk], b1.x, acc1, 0, 0, 0);
+      acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(av[kk + 1], b0.y, acc0, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(av[kk + 1], b1.y, acc1, 0, 0, 0);
+      acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(av[kk + 2], b0.z, acc0, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(av[kk + 2], b1.z, acc1, 0, 0, 0);
+      acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(av[kk + 3], b0.w, acc0, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(av[kk + 3], b1.w, acc1, 0, 0, 0);
+    }
+
+    // filter: the two column blocks of this tile
+    const int cA = c0 + l32, cB = c0 + 32 + l32;
+    const bool vA = cA < n_cols, vB = cB < n_cols;
+    const float ncA = (vA && l2) ? a.norms[cols[cA]] : 0.f;
+    const float ncB = (vB && l2) ? a.norms[cols[cB]] : 0.f;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      if (!rvalid[v]) continue;
+      const int rr = wrow + acc_row(v, h);
+      const int rl = rr - rbase;
+      const float tau = sTau[rl];
+      const float dA = l2 ? nr[v] + fmaf(-2.f, acc0[v], ncA) : -acc0[v];
+      const float dB = l2 ? nr[v] + fmaf(-2.f, acc1[v], ncB) : -acc1[v];
+      if (a.out_matrix) {
+        float *mrow = a.out_matrix + (J.out_off + rr) * a.matrix_ld;
+        if (vA) mrow[cA] = dA;
+        if (vB) mrow[cB] = dB;
+      }
+      if (vA && !(excl && rr == cA) && dA <= tau) {
+        const int pos = atomicAdd(&sBufN[rl], 1);
+        sBufD[rl * BUFD + pos] = dA;
+        sBufC[rl * BUFC + pos] = (uint16_t)cA;
+      }
+      if (vB && !(excl && rr == cB) && dB <= tau) {
+        const int pos = atomicAdd(&sBufN[rl], 1);
+        sBufD[rl * BUFD + pos] = dB;
+        sBufC[rl * BUFC + pos] = (uint16_t)cB;
+      }
+    }
+    wave_sync();
+    drain();
+    wave_sync();
+    __syncthreads();  // every wave is done with sB
+    if (has_next) {
+      store_tile();
+      __syncthreads();
+    }
+  }
+
+  // ---- epilogue: this wave's 32 rows ----
+  // sort each kept set by (GEMM distance, column)
+  if (l32 == lane && wrow + l32 < n_rows) {
+    for (int i = 1; i < tn; ++i) {
+      const float di = sTopD[orow * KS1 + i];
+      const uint32_t ci = sTopC[orow * KS1 + i];
+      int j = i - 1;
+      while (j >= 0) {
+        const float dj = sTopD[orow * KS1 + j];
+        const uint32_t cj = sTopC[orow * KS1 + j];
+        if (dj > di || (dj == di && cj > ci)) {
+          sTopD[orow * KS1 + j + 1] = dj;
+          sTopC[orow * KS1 + j + 1] = cj;
+          --j;
+        } else {
+          break;
+        }
+      }
+      sTopD[orow * KS1 + j + 1] = di;
+      sTopC[orow * KS1 + j + 1] = ci;
+    }
+  }
+  wave_sync();
+
+  const int ksel_job = J.k_sel < KSEL ? J.k_sel : KSEL;
+  if (a.recompute) {
+    // FP32 direct-difference distance of each winner into sBufD[row][i]
+    constexpr int QS = (DP + 3) / 4;  // dims per quarter slice
+    for (int r = 0; r < 32; ++r) {
+      const int rr = wrow + r;
+      if (rr >= n_rows) break;
+      const int tnr = __shfl(tn, r, 64);
+      const int cnt = tnr < ksel_job ? tnr : ksel_job;
+      const int lrow = wave * 32 + r;
+      const float *xr = a.X + (int64_t)rows[rr] * d;
+      for (int base = 0; base < cnt; base += 16) {
+        const int wi = base + (lane >> 2), q = lane & 3;
+        float s = 0.f;
+        if (wi < cnt) {
+          const uint32_t c = sTopC[lrow * KS1 + wi];
+          const float *xc = a.X + (int64_t)cols[c] * d;
+          const int k0 = q * QS;
+          const int k1 = (k0 + QS < d) ? k0 + QS : d;
+          if (l2) {
+            for (int kx = k0; kx < k1; ++kx) {
+              const float t = xr[kx] - xc[kx];
+              s = fmaf(t, t, s);
+            }
+          } else {
+            for (int kx = k0; kx < k1; ++kx) s = fmaf(xr[kx], xc[kx], s);
+          }
+        }
+        s += __shfl_xor(s, 1, 64);
+        s += __shfl_xor(s, 2, 64);
+        if (wi < cnt && q == 0) sBufD[lrow * BUFD + wi] = l2 ? s : -s;
+      }
+    }
+  }
+  wave_sync();
+
+  if (l32 == lane && wrow + l32 < n_rows) {
+    const int rr = wrow + l32;
+    int cnt = tn < ksel_job ? tn : ksel_job;
+    float *dd = a.recompute ? &sBufD[orow * BUFD] : &sTopD[orow * KS1];
+    if (a.rescore_k > 0) {
+      // re-rank the GEMM winners by (direct distance, column)
+      for (int i = 1; i < cnt; ++i) {
+        const float di = dd[i];
+        const uint32_t ci = sTopC[orow * KS1 + i];
+        int j = i - 1;
+        while (j >= 0 && (dd[j] > di || (dd[j] == di && sTopC[orow * KS1 + j] > ci))) {
+          dd[j + 1] = dd[j];
+          sTopC[orow * KS1 + j + 1] = sTopC[orow * KS1 + j];
+          --j;
+        }
+        dd[j + 1] = di;
+        sTopC[orow * KS1 + j + 1] = ci;
+      }
+      if (cnt > a.rescore_k) cnt = a.rescore_k;
+    }
+    const int64_t o = (J.out_off + rr) * (int64_t)a.k_out;
+    for (int i = 0; i < a.k_out; ++i) {
+      if (i < cnt) {
+        const uint32_t c = sTopC[orow * KS1 + i];
+        a.out_col[o + i] = a.out_ids ? cols[c] : c;
+        if (a.out_dist) a.out_dist[o + i] = dd[i];
+      } else {
+        a.out_col[o + i] = kEmptyId;
+        if (a.out_dist) a.out_dist[o + i] = INFINITY;
+      }
+    }
+  }
+}
+
+template <int DP, int KSEL>
+static hipError_t launch_dp_ksel(const KnnArgs &args, int n_items, hipStream_t s) {
+  constexpr int NW = 4;
+  hipLaunchKernelGGL((knn_f32_kernel<DP, KSEL, NW>), dim3(xcd_grid(n_items)), dim3(NW * 64), 0, s,
+                     args);
+  return hipGetLastError();
+}
+
+template <int DP>
+static hipError_t launch_dp(const KnnArgs &args, int ksel, int n_items, hipStream_t s) {
+  if (ksel <= 4) return launch_dp_ksel<DP, 4>(args, n_items, s);
+  if (ksel <= 16) return launch_dp_ksel<DP, 16>(args, n_items, s);
+  return launch_dp_ksel<DP, 32>(args, n_items, s);
+}
+
+int knn_rows_per_item() { return 32 * 4; }
+
+hipError_t launch_knn(const KnnLaunch &L, hipStream_t s) {
+  const Index &I = *L.idx;
+  if (L.n_items == 0) return hipSuccess;
+  KnnArgs a;
+  a.X = I.xf();
+  a.norms = I.norms.as<float>();
+  a.row_base = L.row_base;
+  a.col_base = L.col_base;
+  a.jobs = L.jobs;
+  a.items = L.items;
+  a.out_col = L.out_col;
+  a.out_dist = L.out_dist;
+  a.out_matrix = L.out_matrix;
+  a.matrix_ld = L.matrix_ld;
+  a.n_items = L.n_items;
+  a.d = I.d;
+  a.metric = I.p.metric;
+  a.k_out = L.k_out;
+  a.out_ids = L.out_ids;
+  a.recompute = L.recompute;
+  a.rescore_k = L.rescore_k;
+  const int d = I.d;
+  if (d <= 32) return launch_dp<32>(a, L.ksel, L.n_items, s);
+  if (d <= 64) return launch_dp<64>(a, L.ksel, L.n_items, s);
+  if (d <= 96) return launch_dp<96>(a, L.ksel, L.n_items, s);
+  if (d <= 128) return launch_dp<128>(a, L.ksel, L.n_items, s);
+  if (d <= 192) return launch_dp<192>(a, L.ksel, L.n_items, s);
+  if (d <= 256) return launch_dp<256>(a, L.ksel, L.n_items, s);
+  return hipErrorInvalidValue;
+}
+
+}  // namespace pipnn

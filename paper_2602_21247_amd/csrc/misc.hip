@@ -1,0 +1,490 @@
+// Supporting kernels: norms and sketches, conversions, fills, prefix sums,
+// and the stable group-by, merge and copy steps of randomized ball carving.
+#include "common.hpp"
+#include "internal.hpp"
+
+namespace pipnn {
+
+// ---------------------------------------------------------------------
+// Squared norms (for the GEMM distance form) and sketches
+// Sketch(v)_b = H_b . v (Sec. 3, Implementation). One wave per point; lane l
+// accumulates dims l, l+64, ... in order, then a fixed butterfly reduction.
+__global__ void __launch_bounds__(256) norms_sketches_kernel(const float *__restrict__ X, int64_t n,
+                                                             int d, const float *__restrict__ H,
+                                                             int m, float *__restrict__ norms,
+                                                             float *__restrict__ S) {
+  const int lane = threadIdx.x & 63;
+  const int64_t p = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (p >= n) return;
+  const float *x = X + p * d;
+  float nn = 0.f;
+  float s[16];
+#pragma unroll
+  for (int b = 0; b < 16; ++b) s[b] = 0.f;
+  for (int i = lane; i < d; i += 64) {
+    const float v = x[i];
+    nn = fmaf(v, v, nn);
+#pragma unroll
+    for (int b = 0; b < 16; ++b)
+      if (b < m) s[b] = fmaf(H[(int64_t)b * d + i], v, s[b]);
+  }
+  nn = wave_sum(nn);
+#pragma unroll
+  for (int b = 0; b < 16; ++b)
+    if (b < m) s[b] = wave_sum(s[b]);
+  if (lane == 0) {
+    norms[p] = nn;
+#pragma unroll
+    for (int b = 0; b < 16; ++b)
+      if (b < m) S[p * m + b] = s[b];
+  }
+}
+
+hipError_t launch_norms_sketches(const Index &I, hipStream_t s) {
+  const int64_t blocks = (I.n + 3) / 4;
+  hipLaunchKernelGGL(norms_sketches_kernel, dim3((unsigned)blocks), dim3(256), 0, s, I.xf(), I.n,
+                     I.d, I.H, I.m, I.norms.as<float>(), I.sketches.as<float>());
+  return hipGetLastError();
+}
+
+__global__ void to_f32_kernel(const void *src, int dtype, float *dst, int64_t count) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  if (dtype == PIPNN_DTYPE_F16) {
+    dst[i] = (float)reinterpret_cast<const _Float16 *>(src)[i];
+  } else if (dtype == PIPNN_DTYPE_BF16) {
+    const uint16_t b = reinterpret_cast<const uint16_t *>(src)[i];
+    dst[i] = __uint_as_float((uint32_t)b << 16);
+  } else {
+    dst[i] = reinterpret_cast<const float *>(src)[i];
+  }
+}
+
+hipError_t launch_to_f32(const void *src, int dtype, float *dst, int64_t count, hipStream_t s) {
+  if (count == 0) return hipSuccess;
+  hipLaunchKernelGGL(to_f32_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, src,
+                     dtype, dst, count);
+  return hipGetLastError();
+}
+
+__global__ void iota_kernel(uint32_t *dst, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = (uint32_t)i;
+}
+hipError_t launch_iota(uint32_t *dst, int64_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(iota_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, dst, n);
+  return hipGetLastError();
+}
+
+__global__ void fill_u32_kernel(uint32_t *dst, uint32_t v, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = v;
+}
+hipError_t launch_fill_u32(uint32_t *dst, uint32_t v, int64_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, dst, v,
+                     n);
+  return hipGetLastError();
+}
+__global__ void fill_u64_kernel(uint64_t *dst, uint64_t v, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = v;
+}
+hipError_t launch_fill_u64(uint64_t *dst, uint64_t v, int64_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_u64_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, dst, v,
+                     n);
+  return hipGetLastError();
+}
+
+__global__ void gather_u32_kernel(const uint32_t *src, const int64_t *idx, uint32_t *dst,
+                                  int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = src[idx[i]];
+}
+hipError_t launch_gather_u32(const uint32_t *src, const int64_t *idx, uint32_t *dst, int64_t n,
+                             hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(gather_u32_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, src,
+                     idx, dst, n);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------
+// Exclusive prefix sum. Tiles of 4096 values (256 threads x 16); tile sums
+// are scanned by one workgroup (up to 4096 tiles), then added back.
+constexpr int kScanThreads = 256;
+constexpr int kScanPer = 16;
+constexpr int kScanTile = kScanThreads * kScanPer;
+
+template <class T>
+__device__ int64_t block_excl_scan(int64_t v, int64_t *sh, int64_t *total) {
+  // v: this thread's value; returns the exclusive prefix across the block
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int64_t x = v;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    int64_t t = __shfl_up(x, off, 64);
+    if (lane >= off) x += t;
+  }
+  if (lane == 63) sh[wave] = x;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int64_t acc = 0;
+    for (int w = 0; w < kScanThreads / 64; ++w) {
+      int64_t t = sh[w];
+      sh[w] = acc;
+      acc += t;
+    }
+    *total = acc;
+  }
+  __syncthreads();
+  return x - v + sh[wave];
+}
+
+template <class T>
+__global__ void __launch_bounds__(kScanThreads) scan_tiles_kernel(const T *in, int64_t *out,
+                                                                  int64_t n, int64_t *tile_sums) {
+  __shared__ int64_t sh[kScanThreads / 64];
+  __shared__ int64_t tot;
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanPer;
+  int64_t v[kScanPer];
+  int64_t s = 0;
+#pragma unroll
+  for (int i = 0; i < kScanPer; ++i) {
+    v[i] = (base + i < n) ? (int64_t)in[base + i] : 0;
+    s += v[i];
+  }
+  int64_t pre = block_excl_scan<T>(s, sh, &tot);
+#pragma unroll
+  for (int i = 0; i < kScanPer; ++i) {
+    if (base + i < n) out[base + i] = pre;
+    pre += v[i];
+  }
+  if (threadIdx.x == 0) tile_sums[blockIdx.x] = tot;
+}
+
+__global__ void __launch_bounds__(kScanThreads) scan_sums_kernel(int64_t *sums, int64_t nt,
+                                                                 int64_t *total_out) {
+  __shared__ int64_t sh[kScanThreads / 64];
+  __shared__ int64_t tot;
+  const int64_t base = (int64_t)threadIdx.x * kScanPer;
+  int64_t v[kScanPer];
+  int64_t s = 0;
+#pragma unroll
+  for (int i = 0; i < kScanPer; ++i) {
+    v[i] = (base + i < nt) ? sums[base + i] : 0;
+    s += v[i];
+  }
+  int64_t pre = block_excl_scan<int64_t>(s, sh, &tot);
+#pragma unroll
+  for (int i = 0; i < kScanPer; ++i) {
+    if (base + i < nt) sums[base + i] = pre;
+    pre += v[i];
+  }
+  if (threadIdx.x == 0) *total_out = tot;
+}
+
+__global__ void scan_add_kernel(int64_t *out, int64_t n, const int64_t *tile_pre) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] += tile_pre[i / kScanTile];
+}
+
+int64_t scan_tmp_elems(int64_t n) { return (n + kScanTile - 1) / kScanTile + 1; }
+
+template <class T>
+static hipError_t scan_impl(const T *in, int64_t *out, int64_t n, int64_t *tmp, hipStream_t s) {
+  const int64_t nt = (n + kScanTile - 1) / kScanTile;
+  if (nt > kScanTile) return hipErrorInvalidValue;
+  if (n == 0) {
+    return hipMemsetAsync(out, 0, sizeof(int64_t), s);
+  }
+  hipLaunchKernelGGL((scan_tiles_kernel<T>), dim3((unsigned)nt), dim3(kScanThreads), 0, s, in, out,
+                     n, tmp);
+  hipLaunchKernelGGL(scan_sums_kernel, dim3(1), dim3(kScanThreads), 0, s, tmp, nt, out + n);
+  hipLaunchKernelGGL(scan_add_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, out, n,
+                     tmp);
+  return hipGetLastError();
+}
+
+hipError_t launch_scan_u32(const uint32_t *in, int64_t *out, int64_t n, int64_t *tmp,
+                           hipStream_t s) {
+  return scan_impl<uint32_t>(in, out, n, tmp, s);
+}
+hipError_t launch_scan_i64_inplace(int64_t *data, int64_t n, int64_t *tmp, hipStream_t s) {
+  // out[i] may alias in[i]: each tile reads its values before writing them
+  return scan_impl<int64_t>(data, data, n, tmp, s);
+}
+
+// ---------------------------------------------------------------------
+// Stable group-by of ball-carving assignments into buckets.
+//
+// Elements of subproblem s are (instance r, fanout slot j) for r over its
+// points in ascending id order; asg_col[e] is the leader index t of element
+// e (or 0xFFFFFFFF for an unused slot). The counts of every (bucket t,
+// tile) pair are laid out subproblem by subproblem, bucket-major, so that
+// one exclusive scan gives each (bucket, tile) its output position, and a
+// stable scatter then leaves every bucket in ascending id order.
+constexpr int kGroupTile = 1024;  // elements per tile (one wave)
+constexpr int kMaxLeaders = 4096;
+
+__global__ void __launch_bounds__(64) group_hist_kernel(const uint32_t *asg, const GroupSub *subs,
+                                                        const GroupTile *tiles, int64_t *cm) {
+  __shared__ int hist[kMaxLeaders];
+  const GroupTile tl = tiles[blockIdx.x];
+  const GroupSub sb = subs[tl.sub];
+  const int lane = threadIdx.x;
+  for (int t = lane; t < sb.n_buckets; t += 64) hist[t] = 0;
+  wave_sync();
+  const int64_t e0 = sb.elem_off + (int64_t)tl.tile * kGroupTile;
+  const int64_t e1 = min(e0 + kGroupTile, sb.elem_off + sb.n_elems);
+  for (int64_t e = e0 + lane; e < e1; e += 64) {
+    const uint32_t t = asg[e];
+    if (t != kEmptyId) atomicAdd(&hist[t], 1);
+  }
+  wave_sync();
+  for (int t = lane; t < sb.n_buckets; t += 64)
+    cm[sb.cm_off + (int64_t)t * sb.n_tiles + tl.tile] = hist[t];
+}
+
+__global__ void __launch_bounds__(64) group_scatter_kernel(const uint32_t *asg,
+                                                           const uint32_t *src_ids, int32_t fmax,
+                                                           const GroupSub *subs,
+                                                           const GroupTile *tiles,
+                                                           const int64_t *cm, uint32_t *out) {
+  __shared__ int64_t pos[kMaxLeaders];
+  const GroupTile tl = tiles[blockIdx.x];
+  const GroupSub sb = subs[tl.sub];
+  const int lane = threadIdx.x;
+  for (int t = lane; t < sb.n_buckets; t += 64)
+    pos[t] = cm[sb.cm_off + (int64_t)t * sb.n_tiles + tl.tile];
+  wave_sync();
+  const int64_t e0 = sb.elem_off + (int64_t)tl.tile * kGroupTile;
+  const int64_t e1 = min(e0 + kGroupTile, sb.elem_off + sb.n_elems);
+  const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  for (int64_t c = e0; c < e1; c += 64) {
+    const int64_t e = c + lane;
+    const bool valid = e < e1;
+    const uint32_t t = valid ? asg[e] : kEmptyId;
+    uint64_t todo = __ballot(valid && t != kEmptyId);
+    int64_t mypos = -1;
+    while (todo) {
+      const int leader = __ffsll((long long)todo) - 1;
+      const uint32_t bt = __shfl(t, leader, 64);
+      const uint64_t same = __ballot(t == bt) & todo;
+      if (t == bt && ((todo >> lane) & 1ull)) mypos = pos[bt] + __popcll(same & below);
+      wave_sync();
+      if (lane == leader) pos[bt] += __popcll(same);
+      wave_sync();
+      todo &= ~same;
+    }
+    if (mypos >= 0) out[mypos] = src_ids[e / fmax];
+  }
+}
+
+__global__ void bucket_start_kernel(const int64_t *cm, const int64_t *bucket_cm_idx,
+                                    int64_t n_buckets, int64_t *bucket_start) {
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b < n_buckets) bucket_start[b] = cm[bucket_cm_idx[b]];
+}
+
+hipError_t launch_groupby(const uint32_t *asg_col, const uint32_t *src_ids, int32_t *fan,
+                          const GroupSub *subs, const GroupTile *tiles, int32_t n_tiles,
+                          int32_t tile_elems, int64_t *cm, int64_t cm_len, int64_t *tmp,
+                          uint32_t *out, int64_t *bucket_start, int64_t n_buckets_total,
+                          hipStream_t s) {
+  (void)tile_elems;
+  const int32_t fmax = *fan;
+  if (n_tiles == 0) return hipSuccess;
+  hipLaunchKernelGGL(group_hist_kernel, dim3(n_tiles), dim3(64), 0, s, asg_col, subs, tiles, cm);
+  hipError_t e = launch_scan_i64_inplace(cm, cm_len, tmp, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(group_scatter_kernel, dim3(n_tiles), dim3(64), 0, s, asg_col, src_ids, fmax,
+                     subs, tiles, cm, out);
+  // bucket_start holds, on entry, the cm index of every bucket's first tile
+  hipLaunchKernelGGL(bucket_start_kernel, dim3((unsigned)((n_buckets_total + 255) / 256)),
+                     dim3(256), 0, s, cm, bucket_start, n_buckets_total, bucket_start);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------
+// Merge of small buckets: each group's buckets are concatenated, sorted and
+// deduplicated (a point may sit in two small buckets of one subproblem).
+constexpr int kMergeMax = 16384;
+
+__global__ void __launch_bounds__(1024) merge_dedup_kernel(const uint32_t *const *seg_ptr,
+                                                           const int32_t *seg_len,
+                                                           const int32_t *grp_first_seg,
+                                                           uint32_t *out, const int64_t *out_off,
+                                                           int32_t *out_size) {
+  __shared__ uint32_t buf[kMergeMax];
+  const int g = blockIdx.x;
+  const int s0 = grp_first_seg[g], s1 = grp_first_seg[g + 1];
+  int total = 0;
+  for (int sg = s0; sg < s1; ++sg) {
+    const int len = seg_len[sg];
+    const uint32_t *src = seg_ptr[sg];
+    for (int i = threadIdx.x; i < len; i += blockDim.x) buf[total + i] = src[i];
+    total += len;
+  }
+  int P = 1;
+  while (P < total) P <<= 1;
+  for (int i = total + threadIdx.x; i < P; i += blockDim.x) buf[i] = kEmptyId;
+  __syncthreads();
+  for (int k = 2; k <= P; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int t = threadIdx.x; t < P / 2; t += blockDim.x) {
+        const int i = (t / j) * 2 * j + (t % j);
+        const int l = i + j;
+        const bool asc = (i & k) == 0;
+        const uint32_t x = buf[i], y = buf[l];
+        if ((x > y) == asc) { buf[i] = y; buf[l] = x; }
+      }
+      __syncthreads();
+    }
+  }
+  // keep the first of every run; ranks via a block scan of keep flags
+  __shared__ int wsum[16];
+  int base = 0;
+  for (int c = 0; c < total; c += blockDim.x) {
+    const int i = c + threadIdx.x;
+    const int keep = (i < total && (i == 0 || buf[i] != buf[i - 1])) ? 1 : 0;
+    const int incl = wave_incl_scan(keep);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 63) wsum[wave] = incl;
+    __syncthreads();
+    int wpre = 0, tot = 0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+      if (w < wave) wpre += wsum[w];
+      tot += wsum[w];
+    }
+    if (keep) out[out_off[g] + base + wpre + incl - 1] = buf[i];
+    base += tot;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out_size[g] = base;
+}
+
+hipError_t launch_merge_dedup(const uint32_t *const *seg_ptr, const int32_t *seg_len,
+                              const int32_t *grp_first_seg, int32_t n_groups, int32_t max_sum,
+                              uint32_t *out, const int64_t *out_off, int32_t *out_size,
+                              hipStream_t s) {
+  if (n_groups == 0) return hipSuccess;
+  if (max_sum > kMergeMax) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(merge_dedup_kernel, dim3(n_groups), dim3(1024), 0, s, seg_ptr, seg_len,
+                     grp_first_seg, out, out_off, out_size);
+  return hipGetLastError();
+}
+
+__global__ void copy_segments_kernel(const uint32_t *const *src, const int64_t *dst_off,
+                                     const int32_t *len, uint32_t *dst) {
+  const int g = blockIdx.x;
+  const uint32_t *s = src[g];
+  uint32_t *o = dst + dst_off[g];
+  const int L = len[g];
+  for (int i = threadIdx.x; i < L; i += blockDim.x) o[i] = s[i];
+}
+
+hipError_t launch_copy_segments(const uint32_t *const *src, const int64_t *dst_off,
+                                const int32_t *len, int32_t n_segs, uint32_t *dst, hipStream_t s) {
+  if (n_segs == 0) return hipSuccess;
+  hipLaunchKernelGGL(copy_segments_kernel, dim3(n_segs), dim3(256), 0, s, src, dst_off, len, dst);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------
+// Start point: nearest to the mean of X by (squared L2 in FP64, id).
+__global__ void colsum_kernel(const float *X, int64_t n, int d, double *sum) {
+  const int64_t p0 = (int64_t)blockIdx.x * 1024;
+  const int64_t p1 = min(p0 + 1024, n);
+  for (int j = threadIdx.x; j < d; j += blockDim.x) {
+    double s = 0.0;
+    for (int64_t p = p0; p < p1; ++p) s += (double)X[p * d + j];
+    atomicAdd(&sum[j], s);
+  }
+}
+
+__global__ void __launch_bounds__(256) center_dist_kernel(const float *X, int64_t n, int d,
+                                                          const double *sum, double *bd,
+                                                          uint32_t *bi) {
+  __shared__ double sd[256];
+  __shared__ uint32_t si[256];
+  const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  double best = INFINITY;
+  uint32_t bid = kEmptyId;
+  if (p < n) {
+    double s = 0.0;
+    for (int j = 0; j < d; ++j) {
+      const double t = (double)X[p * d + j] - sum[j] / (double)n;
+      s += t * t;
+    }
+    best = s;
+    bid = (uint32_t)p;
+  }
+  sd[threadIdx.x] = best;
+  si[threadIdx.x] = bid;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      const double o = sd[threadIdx.x + w];
+      const uint32_t oi = si[threadIdx.x + w];
+      if (o < sd[threadIdx.x] || (o == sd[threadIdx.x] && oi < si[threadIdx.x])) {
+        sd[threadIdx.x] = o;
+        si[threadIdx.x] = oi;
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    bd[blockIdx.x] = sd[0];
+    bi[blockIdx.x] = si[0];
+  }
+}
+
+__global__ void __launch_bounds__(256) argmin_kernel(const double *bd, const uint32_t *bi,
+                                                     int64_t nb, uint32_t *out) {
+  __shared__ double sd[256];
+  __shared__ uint32_t si[256];
+  double best = INFINITY;
+  uint32_t bid = kEmptyId;
+  for (int64_t i = threadIdx.x; i < nb; i += 256) {
+    if (bd[i] < best || (bd[i] == best && bi[i] < bid)) {
+      best = bd[i];
+      bid = bi[i];
+    }
+  }
+  sd[threadIdx.x] = best;
+  si[threadIdx.x] = bid;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      const double o = sd[threadIdx.x + w];
+      const uint32_t oi = si[threadIdx.x + w];
+      if (o < sd[threadIdx.x] || (o == sd[threadIdx.x] && oi < si[threadIdx.x])) {
+        sd[threadIdx.x] = o;
+        si[threadIdx.x] = oi;
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = si[0];
+}
+
+// tmp: d + 2 * ceil(n/256) doubles
+hipError_t launch_start_node(const Index &I, double *tmp, uint32_t *out, hipStream_t s) {
+  const int64_t nb = (I.n + 255) / 256;
+  double *sum = tmp;
+  double *bd = tmp + I.d;
+  uint32_t *bi = reinterpret_cast<uint32_t *>(bd + nb);
+  hipError_t e = hipMemsetAsync(sum, 0, sizeof(double) * I.d, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(colsum_kernel, dim3((unsigned)((I.n + 1023) / 1024)), dim3(256), 0, s, I.xf(),
+                     I.n, I.d, sum);
+  hipLaunchKernelGGL(center_dist_kernel, dim3((unsigned)nb), dim3(256), 0, s, I.xf(), I.n, I.d, sum,
+                     bd, bi);
+  hipLaunchKernelGGL(argmin_kernel, dim3(1), dim3(256), 0, s, bd, bi, nb, out);
+  return hipGetLastError();
+}
+
+}  // namespace pipnn

@@ -1,0 +1,84 @@
+"""The C-ABI library loads and exports every symbol the header declares.
+
+These run without a GPU: only host-side calls (version, defaults, workspace
+sizing, argument validation) are made.
+"""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+import paper_2602_21247_amd as pp
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "pipnn.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(pipnn_[a-z_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(pp.LIB_PATH):
+        from paper_2602_21247_amd import build
+        build.build()
+    return pp.lib()
+
+
+def test_every_declared_symbol_is_exported(L):
+    names = _declared()
+    assert len(names) >= 15
+    for name in names:
+        assert hasattr(L, name), name
+    assert set(names) == set(pp.EXPORTS)
+
+
+def test_version_and_defaults(L):
+    assert pp.version().startswith("pipnn-gfx950")
+    p = pp.default_params()
+    assert (p.c_max, p.c_min, p.k, p.hash_bits, p.l_max, p.R) == (1024, 64, 16, 12, 64, 32)
+    assert list(p.fanout) == [2, 1, 1, 1]
+    assert abs(p.alpha - 1.2) < 1e-6
+
+
+def test_workspace_bytes(L):
+    p = pp.default_params(c_max=2048)
+    b1 = pp.workspace_bytes(p, 1_000_000, 128)
+    b2 = pp.workspace_bytes(p, 2_000_000, 128)
+    assert b1 > 0 and b2 > b1
+    bad = pp.default_params(l_max=0)
+    assert pp.workspace_bytes(bad, 100, 8) == 0
+
+
+@pytest.mark.parametrize("field,value", [("c_max", 1), ("k", 0), ("hash_bits", 17), ("l_max", 300),
+                                         ("R", 0), ("alpha", 0.5), ("c_min", 5000),
+                                         ("gemm_prec", 9)])
+def test_create_rejects_bad_params(L, field, value):
+    p = pp.default_params(**{field: value})
+    h = C.c_void_p()
+    st = L.pipnn_create(C.byref(p), C.c_void_p(16), 100, 8, 0, C.c_void_p(16), None, C.byref(h))
+    assert st == -1
+    assert len(L.pipnn_last_error()) > 0
+    assert not h.value
+
+
+def test_create_rejects_bad_shapes(L):
+    p = pp.default_params()
+    h = C.c_void_p()
+    assert L.pipnn_create(C.byref(p), C.c_void_p(16), 1, 8, 0, C.c_void_p(16), None,
+                          C.byref(h)) == -1
+    assert L.pipnn_create(C.byref(p), C.c_void_p(16), 100, 0, 0, C.c_void_p(16), None,
+                          C.byref(h)) == -1
+    assert L.pipnn_create(C.byref(p), None, 100, 8, 0, C.c_void_p(16), None, C.byref(h)) == -1
+    assert L.pipnn_create(C.byref(p), C.c_void_p(16), 100, 8, 7, C.c_void_p(16), None,
+                          C.byref(h)) == -1
+
+
+def test_null_arguments_fail_cleanly(L):
+    assert L.pipnn_robustprune(None, None, None, None, None) == -1
+    assert L.pipnn_search(None, None, None, 0, 0, 10, 10, 0, None, None, None, None) == -1
+    assert L.pipnn_reservoir_init(None, 10, 4, None) == -1
+    L.pipnn_destroy(None)
