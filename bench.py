@@ -1,0 +1,304 @@
+#!/usr/bin/env python3
+"""PiPNN build throughput on one MI355X.
+
+One step is one pass of the whole hot path over the workload, with the
+points already resident in HBM: sketches and norms, randomized ball carving,
+the leaf pick + HashPrune on every leaf, and the final RobustPrune (Alg. 4).
+The default workload is 1,000,000 x 128 integer-valued points (a seeded
+1,000-cluster mixture stored as float32, BigANN-shaped), FP32 leaf GEMM,
+C_max 2048, two leaves per point, k 16, l_max 64, R 32, alpha 1.2.
+
+After the timed steps the graph of the last build is searched with 10,000
+queries from the same mixture for recall@10 against exact brute force
+(FP64), and the smallest beam width reaching 0.95 is reported.
+
+Printed: one JSON line. `roofline` is for the fused leaf distance +
+selection kernel (the dominant kernel): its average launch time comes from
+HIP events recorded around it on its own stream during the timed steps.
+`cpu_baseline` is the FP64 oracle timed on a bounded sample of the same
+build (each phase on a sample of its units, scaled by the unit counts of the
+GPU build).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_FP32_MFMA_TFLOPS = 157.3
+RECALL_LS = [10, 12, 16, 20, 24, 32, 40, 48, 64, 80, 96, 128, 160, 192, 256, 384, 512]
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", type=int, default=2)
+    ap.add_argument("--n", type=int, default=None, help="override the point count")
+    ap.add_argument("--queries", type=int, default=None)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-recall", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=4.0,
+                    help="target seconds of oracle work per sampled phase")
+    return ap.parse_args()
+
+
+def ground_truth(torch, Xd, Qd, k=10):
+    """Exact k-th neighbour distance per query, FP64 on the GPU (evaluation
+    only: the build never uses it)."""
+    X64 = Xd.double()
+    xn = (X64 * X64).sum(1)
+    kth = torch.empty(Qd.shape[0], dtype=torch.float64, device="cuda")
+    for q0 in range(0, Qd.shape[0], 512):
+        q = Qd[q0:q0 + 512].double()
+        D = (q * q).sum(1, keepdim=True) + xn[None, :] - 2.0 * (q @ X64.T)
+        vals, ids = torch.topk(D, k, dim=1, largest=False)
+        # exact recomputation of the k winners by direct difference
+        diff = X64[ids] - q[:, None, :]
+        dd = (diff * diff).sum(-1)
+        kth[q0:q0 + 512] = dd.max(1).values
+        del D
+    return kth
+
+
+def traffic_from_profiles():
+    """HBM bytes per leaf-kernel launch from committed counter runs, if they
+    were taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "leaf_knn_hbm_traffic.json")
+    src = os.path.join(ROOT, "paper_2602_21247_amd", "csrc", "knn.hip")
+    try:
+        rec = json.load(open(path))
+        h = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        if rec.get("knn_hip_sha256") != h:
+            return None
+        return rec.get("bytes_per_launch")
+    except Exception:
+        return None
+
+
+def cpu_baseline(X, H, off, mem, res_np, stats, w, budget):
+    """The FP64 oracle on a bounded sample of this build, phase by phase."""
+    import numpy as np
+
+    import oracle
+    oracle.lib()
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or (os.cpu_count() or 1)
+    oracle.set_threads(threads)
+    threads = oracle.get_threads()
+    n, d = X.shape
+    rng = np.random.default_rng(12345)
+    notes = []
+    total = 0.0
+
+    # partition: point-to-leader distances with top-f selection
+    ell = min(w.leader_cap, max(2, -(-n // w.leader_div)), n)
+    leaders = X[rng.choice(n, ell, replace=False)]
+    m = 2000
+    t = time.perf_counter()
+    oracle.bruteforce_knn(leaders, X[rng.choice(n, m, replace=False)], 2)
+    dt = time.perf_counter() - t
+    m2 = int(min(n, max(m, m * budget / max(dt, 1e-3))))
+    t = time.perf_counter()
+    oracle.bruteforce_knn(leaders, X[rng.choice(n, m2, replace=False)], 2)
+    dt = time.perf_counter() - t
+    t_part = dt * stats["leader_dists"] / float(m2 * ell)
+    total += t_part
+    notes.append(f"partition: {m2} points x {ell} leaders (x{stats['leader_dists'] / (m2 * ell):.0f})")
+
+    # leaf pick: a random sample of the GPU build's leaves
+    nl = len(off) - 1
+    order = rng.permutation(nl)
+    sizes = np.diff(off)
+    pairs_tot = float((sizes.astype(np.float64) ** 2).sum())
+    pick, acc = [], 0.0
+    for i in order:
+        pick.append(i)
+        acc += float(sizes[i]) ** 2
+        if acc >= pairs_tot * 0.004 and len(pick) >= 4:
+            break
+    s_off = np.concatenate([[0], np.cumsum(sizes[pick])]).astype(np.int64)
+    s_mem = np.concatenate([mem[off[i]:off[i + 1]] for i in pick]).astype(np.uint32)
+    t = time.perf_counter()
+    cand, dist = oracle.leaf_knn(X, s_off, s_mem, w.k)
+    dt = time.perf_counter() - t
+    t_leaf = dt * pairs_tot / acc
+    total += t_leaf
+    notes.append(f"leaf pick: {len(pick)} leaves, {acc / pairs_tot * 100:.2f}% of pairs")
+
+    # sketches of every point
+    t = time.perf_counter()
+    ns_sk = min(n, 100000)
+    oracle.sketches(X[:ns_sk], H)
+    t_sk = (time.perf_counter() - t) * n / ns_sk
+    total += t_sk
+    notes.append(f"sketches: {ns_sk} points")
+
+    # HashPrune: the sampled leaves' records, ids renumbered densely
+    dst, cnd, dv = oracle.bidirected_records(s_mem, cand, dist)
+    uniq, inv = np.unique(np.concatenate([dst, cnd]), return_inverse=True)
+    dst_c = inv[:len(dst)].astype(np.uint32)
+    cnd_c = inv[len(dst):].astype(np.uint32)
+    S = oracle.sketches(X[uniq], H)
+    t = time.perf_counter()
+    oracle.hashprune(oracle.reservoir_init(len(uniq), w.l_max), S, dst_c, cnd_c, dv)
+    dt = time.perf_counter() - t
+    t_hp = dt * stats["records"] / max(1, len(dst))
+    total += t_hp
+    notes.append(f"HashPrune: {len(dst)} records ({len(dst) / max(1, stats['records']) * 100:.2f}%)")
+
+    # RobustPrune: the reservoirs of the first points
+    ns = 20000
+    t = time.perf_counter()
+    oracle.robustprune(X, res_np[:ns], w.alpha, w.R)
+    dt = time.perf_counter() - t
+    t_rp = dt * n / ns
+    total += t_rp
+    notes.append(f"RobustPrune: {ns} points")
+    return {
+        "value": n / total, "unit": "points/s", "cores": threads, "kind": "oracle",
+        "sample": "; ".join(notes) + "; each phase scaled by the GPU build's unit counts",
+        "phase_s": {"sketches": t_sk, "partition": t_part, "leaf_pick": t_leaf,
+                    "hashprune": t_hp, "robustprune": t_rp},
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(sharding across GPUs is not built)", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_2602_21247_amd as pp
+    import pipnn_inputs as pi
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a ROCm GPU", file=sys.stderr)
+        sys.exit(2)
+    if not os.path.exists(pp.LIB_PATH):
+        from paper_2602_21247_amd import build as libbuild
+        libbuild.build()
+    cfg = args.workload
+    w = pi.WORKLOADS[cfg]
+    n = args.n or w.n
+    log(f"[bench] generating workload {cfg} ({w.name}) n={n}")
+    X = pi.workload_points(cfg, n)
+    H = pi.workload_hyperplanes(cfg)
+    Xd = torch.from_numpy(X).cuda()
+    Hd = torch.from_numpy(H).cuda()
+    p = pp.default_params(metric=w.metric, c_max=w.c_max, c_min=w.c_min, k=w.k, l_max=w.l_max,
+                          R=w.R, alpha=w.alpha, hash_bits=w.hash_bits, leader_div=w.leader_div,
+                          leader_cap=w.leader_cap, fanout=w.fanout, seed=pi.workload_seed(cfg))
+    idx = pp.Index(Xd, Hd, p)
+    res = torch.empty((n, w.l_max), dtype=torch.int64, device="cuda")
+
+    def step():
+        idx.prepare()
+        off, mem = idx.partition()
+        pp._check(pp.lib().pipnn_reservoir_init(pp._ptr(res), n, w.l_max, pp._stream()))
+        idx.build_leaves(off, mem, res)
+        g, deg = idx.robustprune(res)
+        return off, mem, g, deg
+
+    for i in range(args.warmup):
+        step()
+        torch.cuda.synchronize()
+        log(f"[bench] warmup {i + 1}/{args.warmup} done")
+    torch.cuda.synchronize()
+    idx.set_profiling(True)
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        out = step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    st = idx.stats()
+    idx.set_profiling(False)
+    ms = (t1 - t0) * 1000.0 / args.steps
+    log(f"[bench] {args.steps} steps, {ms:.2f} ms/step")
+    off, mem, g, deg = out
+
+    # leaf kernel roofline: dense flops 2 s^2 d per leaf, per launch
+    launches = max(1, st["leaf_knn_launches"])
+    flops_per_launch = 2.0 * st["leaf_pairs"] * w.d * args.steps / launches
+    avg_launch_s = st["ms_leaf_knn"] / launches / 1000.0
+    achieved = flops_per_launch / avg_launch_s / 1e12
+    phases = {k: st[k] / args.steps for k in ("ms_prepare", "ms_partition", "ms_leaf_knn",
+                                               "ms_bin", "ms_merge", "ms_robustprune")}
+
+    recall = None
+    l_at = None
+    curve = {}
+    if not args.no_recall:
+        nq = args.queries or w.n_queries
+        Q = pi.workload_queries(cfg, nq)
+        Qd = torch.from_numpy(Q).cuda()
+        kth = ground_truth(torch, Xd, Qd)
+        start = idx.start_node()
+        for L in RECALL_LS:
+            ids, dist, cmps = idx.search(g, Qd, 10, L, start)
+            hits = (dist.double() <= kth[:, None]).sum().item()
+            r = hits / (nq * 10.0)
+            curve[L] = {"recall": round(r, 5), "cmps": round(cmps.double().mean().item(), 1)}
+            log(f"[bench] L={L} recall@10={r:.4f} cmps={curve[L]['cmps']}")
+            if r >= 0.95:
+                l_at, recall = L, r
+                break
+        if recall is None:
+            recall = max(v["recall"] for v in curve.values())
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("[bench] timing the FP64 oracle on a sample")
+        cpu = cpu_baseline(X, H, off.cpu().numpy(), mem.cpu().numpy().view(np.uint32),
+                           res.cpu().numpy().view(np.uint64), st, w, args.cpu_budget)
+
+    traffic = traffic_from_profiles()
+    line = {
+        "metric": "build points/sec at recall@10>=0.95",
+        "value": n / (ms / 1000.0),
+        "unit": "points/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "n": n, "d": w.d, "metric": "L2", "c_max": w.c_max,
+                   "leaves_per_point": 2, "k": w.k, "l_max": w.l_max, "R": w.R,
+                   "alpha": w.alpha, "hash_bits": w.hash_bits, "gemm": "fp32-mfma"},
+        "recall_at_10": recall,
+        "L_at_recall_0.95": l_at,
+        "recall_curve": curve,
+        "leaf_gemm_tflops": achieved,
+        "insert_p99_ms": None,
+        "phase_ms": phases,
+        "build_stats": {k: st[k] for k in ("n_leaves", "n_members", "leader_dists", "levels",
+                                           "leaf_pairs", "records")},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP32_MFMA_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_MFMA_TFLOPS,
+                     "traffic": traffic},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+    idx.close()
+
+
+if __name__ == "__main__":
+    main()

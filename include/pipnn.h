@@ -159,8 +159,10 @@ pipnn_status pipnn_partition(pipnn_index *idx, int64_t *d_leaf_offsets, int64_t 
  * d_reservoirs holds n x l_max uint64 slots (see pipnn_reservoir_init);
  * repeated calls accumulate, and by the history-independence theorem of
  * Sec. 3 the result does not depend on leaf order or call splitting.
- * Reads d_leaf_offsets back to the host once. EINVAL on a leaf larger than
- * 65535 points or an unsorted leaf (found on the device: EDEVICE). */
+ * Reads d_leaf_offsets back to the host once. Ties between equal distances
+ * go to the co-member at the smaller position in the leaf, which is the
+ * smaller id when leaves are ascending. EINVAL on a leaf of more than 65535
+ * points or non-monotone offsets. */
 pipnn_status pipnn_build_leaves(pipnn_index *idx, const int64_t *d_leaf_offsets,
                                 const uint32_t *d_leaf_members, int64_t n_leaves,
                                 uint64_t *d_reservoirs, pipnn_stream_t stream);
@@ -171,8 +173,9 @@ pipnn_status pipnn_build_leaves(pipnn_index *idx, const int64_t *d_leaf_offsets,
  * Sketch(c)_b >= Sketch(p)_b). The stored distance is bf16 (round to nearest
  * even, -0 as +0) and every comparison uses the key (bf16 distance, id).
  * Records with dst == cand are ignored; inserting a record twice changes
- * nothing. Ids >= n are reported as EDEVICE by this call (it synchronises
- * to read the device-side check). */
+ * nothing. Records naming an id >= n are skipped and reported as EDEVICE
+ * by this call (it synchronises to read the device-side check); the other
+ * records are still inserted. */
 pipnn_status pipnn_hashprune_insert(pipnn_index *idx, const uint32_t *d_dst,
                                     const uint32_t *d_cand, const float *d_dist,
                                     int64_t n_records, uint64_t *d_reservoirs,
@@ -214,6 +217,30 @@ pipnn_status pipnn_search(pipnn_index *idx, const uint32_t *d_graph, const void 
                           int32_t q_dtype, int32_t k, int32_t L, uint32_t start,
                           uint32_t *d_out_ids, float *d_out_dist, uint32_t *d_out_cmps,
                           pipnn_stream_t stream);
+
+/* Recompute the per-point squared norms and sketches from X (call after the
+ * caller changed X in place; pipnn_create already does this once). */
+pipnn_status pipnn_prepare(pipnn_index *idx, pipnn_stream_t stream);
+
+/* Counters and phase timings of the most recent calls on an index.
+ * Phase times (milliseconds, summed since profiling was switched on) are
+ * taken with HIP events recorded on the call's stream around each phase:
+ * ms_leaf_knn covers only the fused leaf distance + selection kernel. */
+typedef struct {
+  int64_t n_leaves, n_members;   /* last pipnn_partition */
+  int64_t leader_dists;          /* point-to-leader distances it evaluated */
+  int32_t levels;                /* its recursion levels */
+  int32_t leaf_knn_launches;     /* leaf kernel launches since profiling on */
+  int64_t leaf_pairs;            /* sum of s^2 over the leaves of the last build */
+  int64_t records;               /* candidate records binned by the last build */
+  double ms_prepare, ms_partition, ms_leaf_knn, ms_bin, ms_merge, ms_robustprune;
+} pipnn_stats;
+
+/* Switch phase timing on (1; also clears the sums) or off (0). */
+pipnn_status pipnn_set_profiling(pipnn_index *idx, int32_t on);
+
+/* (sync) Fills *h_out; synchronises the recorded events. */
+pipnn_status pipnn_get_stats(pipnn_index *idx, pipnn_stats *h_out);
 
 /* ---- inspection calls, used to check the path against the oracle ---- */
 

@@ -26,7 +26,8 @@ EXPORTS = [
     "pipnn_create", "pipnn_destroy", "pipnn_partition", "pipnn_build_leaves",
     "pipnn_hashprune_insert", "pipnn_reservoir_init", "pipnn_reservoir_canonical",
     "pipnn_robustprune", "pipnn_start_node", "pipnn_search", "pipnn_get_sketches",
-    "pipnn_knn_block", "pipnn_leaf_pick",
+    "pipnn_knn_block", "pipnn_leaf_pick", "pipnn_prepare", "pipnn_set_profiling",
+    "pipnn_get_stats",
 ]
 
 
@@ -43,6 +44,18 @@ class Params(C.Structure):
                 ("l_max", C.c_int32), ("R", C.c_int32), ("alpha", C.c_float),
                 ("gemm_prec", C.c_int32), ("rescore_mult", C.c_int32),
                 ("reserved", C.c_int32), ("seed", C.c_uint64)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("n_leaves", C.c_int64), ("n_members", C.c_int64), ("leader_dists", C.c_int64),
+                ("levels", C.c_int32), ("leaf_knn_launches", C.c_int32),
+                ("leaf_pairs", C.c_int64), ("records", C.c_int64),
+                ("ms_prepare", C.c_double), ("ms_partition", C.c_double),
+                ("ms_leaf_knn", C.c_double), ("ms_bin", C.c_double), ("ms_merge", C.c_double),
+                ("ms_robustprune", C.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
 
 
 _lib = None
@@ -76,6 +89,9 @@ def lib():
         L.pipnn_get_sketches.argtypes = [P, P, P]
         L.pipnn_knn_block.argtypes = [P, P, i64, P, i64, i32, i32, P, P, P, P]
         L.pipnn_leaf_pick.argtypes = [P, P, P, i64, P, P, P]
+        L.pipnn_prepare.argtypes = [P, P]
+        L.pipnn_set_profiling.argtypes = [P, i32]
+        L.pipnn_get_stats.argtypes = [P, C.POINTER(Stats)]
         for name in EXPORTS:
             if name not in ("pipnn_version", "pipnn_last_error", "pipnn_default_params",
                             "pipnn_workspace_bytes", "pipnn_destroy"):
@@ -165,6 +181,17 @@ class Index:
             pass
 
     # ---- the hot path
+    def prepare(self):
+        _check(lib().pipnn_prepare(self._h, _stream()))
+
+    def set_profiling(self, on: bool):
+        _check(lib().pipnn_set_profiling(self._h, 1 if on else 0))
+
+    def stats(self) -> dict:
+        st = Stats()
+        _check(lib().pipnn_get_stats(self._h, C.byref(st)))
+        return st.as_dict()
+
     def partition(self):
         torch = _torch()
         nl, nm = C.c_int64(), C.c_int64()

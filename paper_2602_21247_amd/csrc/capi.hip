@@ -155,6 +155,46 @@ const float *Index::xf() const {
   return x_dtype == PIPNN_DTYPE_F32 ? reinterpret_cast<const float *>(X) : xf32.as<float>();
 }
 
+static hipEvent_t take_event(Index &I) {
+  if (!I.ev_free.empty()) {
+    hipEvent_t e = I.ev_free.back();
+    I.ev_free.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+PhaseTimer::PhaseTimer(Index &I_, int ph, hipStream_t s_) : I(I_), phase(ph), s(s_) {
+  if (!I.profiling) return;
+  a = take_event(I);
+  if (a) (void)hipEventRecord(a, s);
+}
+
+PhaseTimer::~PhaseTimer() {
+  if (!a) return;
+  hipEvent_t b = take_event(I);
+  if (!b) {
+    I.ev_free.push_back(a);
+    return;
+  }
+  (void)hipEventRecord(b, s);
+  I.events.push_back({phase, a, b});
+}
+
+// Flush recorded event pairs into the per-phase sums.
+static void flush_events(Index &I) {
+  for (auto &e : I.events) {
+    float ms = 0.f;
+    if (hipEventSynchronize(e.b) == hipSuccess && hipEventElapsedTime(&ms, e.a, e.b) == hipSuccess)
+      I.phase_ms[e.phase] += ms;
+    I.ev_free.push_back(e.a);
+    I.ev_free.push_back(e.b);
+  }
+  I.events.clear();
+}
+
 }  // namespace pipnn
 
 extern "C" {
@@ -257,6 +297,12 @@ void pipnn_destroy(pipnn_index *idx) {
                     &I->p_groups, &I->p_gout, &I->p_gsize, &I->p_copy})
     b->release();
   for (DevBuf &b : I->levels) b.release();
+  for (DevBuf &b : I->ppool) b.release();
+  for (auto &e : I->events) {
+    (void)hipEventDestroy(e.a);
+    (void)hipEventDestroy(e.b);
+  }
+  for (hipEvent_t e : I->ev_free) (void)hipEventDestroy(e);
   delete I;
 }
 
@@ -285,12 +331,17 @@ pipnn_status pipnn_partition(pipnn_index *idx, int64_t *d_leaf_offsets, int64_t 
   };
   std::vector<Leaf> leaves;
   // every level allocates its own buffers; they are kept until the end
-  std::deque<DevBuf> keep;  // stable addresses as it grows
+  // per-call buffers come from a pool kept by the index (stable addresses,
+  // reused by the next call, so repeated partitions allocate nothing)
+  I.ppool_used = 0;
   auto fresh = [&](size_t bytes, DevBuf *&out) -> hipError_t {
-    keep.emplace_back();
-    out = &keep.back();
+    if (I.ppool_used == I.ppool.size()) I.ppool.emplace_back();
+    out = &I.ppool[I.ppool_used++];
     return out->ensure(bytes);
   };
+  PhaseTimer timer(I, kPhPartition, s);
+  int64_t leader_dists = 0;
+  int levels = 0;
 
   DevBuf *A0;
   HIPCHK(fresh((size_t)n * 4, A0));
@@ -339,7 +390,9 @@ pipnn_status pipnn_partition(pipnn_index *idx, int64_t *d_leaf_offsets, int64_t 
       ells.push_back((int32_t)ell);
       fs.push_back(f);
       inst += sb.cnt;
+      leader_dists += sb.cnt * ell;
     }
+    ++levels;
     HIPCHK(upload(I.s_tmp1, lead_idx, s));
     HIPCHK(I.p_leaders.ensure(lead_idx.size() * 4));
     HIPCHK(launch_gather_u32(A->as<uint32_t>(), I.s_tmp1.as<int64_t>(), I.p_leaders.as<uint32_t>(),
@@ -550,7 +603,10 @@ pipnn_status pipnn_partition(pipnn_index *idx, int64_t *d_leaf_offsets, int64_t 
     HIPCHK(hipMemcpyAsync(d_leaf_offsets, offs.data(), offs.size() * 8, hipMemcpyHostToDevice, s));
     HIPCHK(hipStreamSynchronize(s));
   }
-  for (DevBuf &b : keep) b.release();
+  I.stats.n_leaves = (int64_t)leaves.size();
+  I.stats.n_members = offs.back();
+  I.stats.leader_dists = leader_dists;
+  I.stats.levels = levels;
   return PIPNN_OK;
   GUARD_END
 }
@@ -624,7 +680,15 @@ pipnn_status run_pick(Index &I, const std::vector<int64_t> &offs, int64_t l0, in
   L.out_col = pick_c;
   L.out_dist = pick_d;
   L.out_matrix = nullptr;
-  HIPCHK(launch_knn(L, s));
+  {
+    PhaseTimer t(I, kPhLeafKnn, s);
+    HIPCHK(launch_knn(L, s));
+  }
+  ++I.leaf_launches;
+  for (int64_t l = l0; l < l1; ++l) {
+    const int64_t sz = offs[(size_t)l + 1] - offs[(size_t)l];
+    if (sz >= 2) I.stats.leaf_pairs += sz * sz;
+  }
   return PIPNN_OK;
 }
 
@@ -633,35 +697,70 @@ pipnn_status bin_and_merge(Index &I, bool from_picks, const uint32_t *a, const u
                            const float *dist, int64_t count, int32_t k, uint64_t *res,
                            hipStream_t s) {
   const int64_t n = I.n;
+  // every pick yields two records, every explicit record one
+  const int64_t max_rec = from_picks ? 2 * count * k : count;
   HIPCHK(I.s_cnt.ensure((size_t)n * 4));
   HIPCHK(I.s_off.ensure((size_t)(n + 1) * 8));
   HIPCHK(I.s_tmp0.ensure((size_t)scan_tmp_elems(n) * 8));
-  HIPCHK(hipMemsetAsync(I.s_cnt.p, 0, (size_t)n * 4, s));
+  HIPCHK(I.s_bins.ensure((size_t)std::max<int64_t>(max_rec, 1) * 8));
+  {
+    PhaseTimer tb(I, kPhBin, s);
+    HIPCHK(hipMemsetAsync(I.s_cnt.p, 0, (size_t)n * 4, s));
+    if (from_picks)
+      HIPCHK(launch_bin_count(a, b, count, k, I.s_cnt.as<uint32_t>(), n, I.flag.as<int32_t>(), s));
+    else
+      HIPCHK(launch_rec_count(a, b, count, I.s_cnt.as<uint32_t>(), n, I.flag.as<int32_t>(), s));
+    HIPCHK(launch_scan_u32(I.s_cnt.as<uint32_t>(), I.s_off.as<int64_t>(), n,
+                           I.s_tmp0.as<int64_t>(), s));
+    HIPCHK(hipMemsetAsync(I.s_cnt.p, 0, (size_t)n * 4, s));
+    if (from_picks)
+      HIPCHK(launch_bin_scatter(a, b, dist, count, k, I.sketches.as<float>(), I.m,
+                                I.s_off.as<int64_t>(), I.s_cnt.as<uint32_t>(),
+                                I.s_bins.as<uint64_t>(), n, s));
+    else
+      HIPCHK(launch_rec_scatter(a, b, dist, count, I.sketches.as<float>(), I.m,
+                                I.s_off.as<int64_t>(), I.s_cnt.as<uint32_t>(),
+                                I.s_bins.as<uint64_t>(), n, s));
+  }
+  {
+    PhaseTimer tm(I, kPhMerge, s);
+    HIPCHK(launch_hashprune_merge(res, n, I.p.l_max, I.s_bins.as<uint64_t>(),
+                                  I.s_off.as<int64_t>(), s));
+  }
+  return PIPNN_OK;
+}
+
+// Reads the device error flag and the last bin total (one synchronisation).
+pipnn_status finish_bins(Index &I, hipStream_t s, const char *what) {
+  int32_t flag = 0;
+  int64_t total = 0;
+  HIPCHK(hipMemcpyAsync(&flag, I.flag.p, 4, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(&total, I.s_off.as<int64_t>() + I.n, 8, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
   HIPCHK(hipMemsetAsync(I.flag.p, 0, 4, s));
-  if (from_picks)
-    HIPCHK(launch_bin_count(a, b, count, k, I.s_cnt.as<uint32_t>(), n, I.flag.as<int32_t>(), s));
-  else
-    HIPCHK(launch_rec_count(a, b, count, I.s_cnt.as<uint32_t>(), n, I.flag.as<int32_t>(), s));
+  I.stats.records += total;
+  if (flag) return fail(PIPNN_EDEVICE, "%s: a point id >= n was found on the device", what);
+  return PIPNN_OK;
+}
+
+__global__ void check_ids_kernel(const uint32_t *ids, int64_t cnt, int64_t n, int32_t *flag) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < cnt && ids[i] >= n) atomicOr(flag, 1);
+}
+
+// (sync) Fails if any of the cnt ids is >= n, before a kernel reads X rows.
+pipnn_status check_ids(Index &I, const uint32_t *ids, int64_t cnt, hipStream_t s, const char *what) {
+  if (cnt == 0) return PIPNN_OK;
+  hipLaunchKernelGGL(check_ids_kernel, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, ids,
+                     cnt, I.n, I.flag.as<int32_t>());
+  HIPCHK(hipGetLastError());
   int32_t flag = 0;
   HIPCHK(hipMemcpyAsync(&flag, I.flag.p, 4, hipMemcpyDeviceToHost, s));
-  HIPCHK(launch_scan_u32(I.s_cnt.as<uint32_t>(), I.s_off.as<int64_t>(), n, I.s_tmp0.as<int64_t>(),
-                         s));
-  int64_t total = 0;
-  HIPCHK(hipMemcpyAsync(&total, I.s_off.as<int64_t>() + n, 8, hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
-  if (flag) return fail(PIPNN_EDEVICE, "a record names a point id >= n");
-  HIPCHK(I.s_bins.ensure((size_t)std::max<int64_t>(total, 1) * 8));
-  HIPCHK(hipMemsetAsync(I.s_cnt.p, 0, (size_t)n * 4, s));
-  if (from_picks)
-    HIPCHK(launch_bin_scatter(a, b, dist, count, k, I.sketches.as<float>(), I.m,
-                              I.s_off.as<int64_t>(), I.s_cnt.as<uint32_t>(),
-                              I.s_bins.as<uint64_t>(), n, s));
-  else
-    HIPCHK(launch_rec_scatter(a, b, dist, count, I.sketches.as<float>(), I.m,
-                              I.s_off.as<int64_t>(), I.s_cnt.as<uint32_t>(),
-                              I.s_bins.as<uint64_t>(), n, s));
-  HIPCHK(launch_hashprune_merge(res, n, I.p.l_max, I.s_bins.as<uint64_t>(), I.s_off.as<int64_t>(),
-                                s));
+  if (flag) {
+    HIPCHK(hipMemsetAsync(I.flag.p, 0, 4, s));
+    return fail(PIPNN_EINVAL, "%s: a point id is >= n", what);
+  }
   return PIPNN_OK;
 }
 
@@ -681,6 +780,10 @@ pipnn_status pipnn_build_leaves(pipnn_index *idx, const int64_t *d_leaf_offsets,
   pipnn_status st = read_offsets(d_leaf_offsets, n_leaves, s, offs);
   if (st != PIPNN_OK) return st;
   const int k = I.p.k;
+  I.stats.leaf_pairs = 0;
+  I.stats.records = 0;
+  st = check_ids(I, d_leaf_members + offs[0], offs[(size_t)n_leaves] - offs[0], s, "build_leaves");
+  if (st != PIPNN_OK) return st;
   // batches of leaves bounded in picks, so scratch stays bounded
   const int64_t max_rows = std::max<int64_t>((int64_t)1 << 25, 65536);
   int64_t l0 = 0;
@@ -696,9 +799,13 @@ pipnn_status pipnn_build_leaves(pipnn_index *idx, const int64_t *d_leaf_offsets,
     st = bin_and_merge(I, true, d_leaf_members + offs[(size_t)l0], I.s_picks_c.as<uint32_t>(),
                        I.s_picks_d.as<float>(), rows, k, d_reservoirs, s);
     if (st != PIPNN_OK) return st;
+    if (l1 < n_leaves) {
+      st = finish_bins(I, s, "build_leaves");
+      if (st != PIPNN_OK) return st;
+    }
     l0 = l1;
   }
-  return PIPNN_OK;
+  return finish_bins(I, s, "build_leaves");
   GUARD_END
 }
 
@@ -715,6 +822,8 @@ pipnn_status pipnn_leaf_pick(pipnn_index *idx, const int64_t *d_leaf_offsets,
   pipnn_status st = read_offsets(d_leaf_offsets, n_leaves, s, offs);
   if (st != PIPNN_OK) return st;
   if (offs[0] != 0) return fail(PIPNN_EINVAL, "offsets[0] must be 0");
+  st = check_ids(I, d_leaf_members, offs[(size_t)n_leaves], s, "leaf_pick");
+  if (st != PIPNN_OK) return st;
   return run_pick(I, offs, 0, n_leaves, d_leaf_members, d_out_cand, d_out_dist, s);
   GUARD_END
 }
@@ -732,6 +841,10 @@ pipnn_status pipnn_knn_block(pipnn_index *idx, const uint32_t *d_row_ids, int64_
   if (n_rows < 1 || n_cols < 1 || n_cols > 65535 || n_rows > 0x7FFFFFFF)
     return fail(PIPNN_EINVAL, "bad block size");
   if (exclude_diag && n_rows != n_cols) return fail(PIPNN_EINVAL, "exclude_diag needs a square block");
+  pipnn_status st = check_ids(I, d_row_ids, n_rows, s, "knn_block rows");
+  if (st != PIPNN_OK) return st;
+  st = check_ids(I, d_col_ids, n_cols, s, "knn_block cols");
+  if (st != PIPNN_OK) return st;
   std::vector<KnnJob> jobs(1);
   jobs[0].row_off = 0;
   jobs[0].col_off = 0;
@@ -777,7 +890,10 @@ pipnn_status pipnn_hashprune_insert(pipnn_index *idx, const uint32_t *d_dst,
   if (!d_dst || !d_cand || !d_dist) return fail(PIPNN_EINVAL, "NULL record array");
   Index &I = *reinterpret_cast<Index *>(idx);
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  return bin_and_merge(I, false, d_dst, d_cand, d_dist, n_records, 1, d_reservoirs, s);
+  I.stats.records = 0;
+  pipnn_status st = bin_and_merge(I, false, d_dst, d_cand, d_dist, n_records, 1, d_reservoirs, s);
+  if (st != PIPNN_OK) return st;
+  return finish_bins(I, s, "hashprune_insert");
   GUARD_END
 }
 
@@ -807,6 +923,7 @@ pipnn_status pipnn_robustprune(pipnn_index *idx, const uint64_t *d_reservoirs, u
   GUARD_BEGIN
   if (!idx || !d_reservoirs || !d_graph || !d_degree) return fail(PIPNN_EINVAL, "NULL argument");
   Index &I = *reinterpret_cast<Index *>(idx);
+  PhaseTimer t(I, kPhRobustPrune, reinterpret_cast<hipStream_t>(stream));
   HIPCHK(launch_robustprune(I, d_reservoirs, d_graph, d_degree,
                             reinterpret_cast<hipStream_t>(stream)));
   return PIPNN_OK;
@@ -860,6 +977,49 @@ pipnn_status pipnn_search(pipnn_index *idx, const uint32_t *d_graph, const void 
                          d_out_cmps ? d_out_cmps + q0 : nullptr, I.s_tmp1.as<uint32_t>(), words,
                          s));
   }
+  return PIPNN_OK;
+  GUARD_END
+}
+
+pipnn_status pipnn_prepare(pipnn_index *idx, pipnn_stream_t stream) {
+  GUARD_BEGIN
+  if (!idx) return fail(PIPNN_EINVAL, "NULL index");
+  Index &I = *reinterpret_cast<Index *>(idx);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  PhaseTimer t(I, kPhPrepare, s);
+  if (I.x_dtype != PIPNN_DTYPE_F32)
+    HIPCHK(launch_to_f32(I.X, I.x_dtype, I.xf32.as<float>(), I.n * (int64_t)I.d, s));
+  HIPCHK(launch_norms_sketches(I, s));
+  return PIPNN_OK;
+  GUARD_END
+}
+
+pipnn_status pipnn_set_profiling(pipnn_index *idx, int32_t on) {
+  GUARD_BEGIN
+  if (!idx) return fail(PIPNN_EINVAL, "NULL index");
+  Index &I = *reinterpret_cast<Index *>(idx);
+  flush_events(I);
+  for (double &v : I.phase_ms) v = 0.0;
+  I.leaf_launches = 0;
+  I.profiling = on != 0;
+  return PIPNN_OK;
+  GUARD_END
+}
+
+pipnn_status pipnn_get_stats(pipnn_index *idx, pipnn_stats *h_out) {
+  GUARD_BEGIN
+  if (!idx || !h_out) return fail(PIPNN_EINVAL, "NULL argument");
+  Index &I = *reinterpret_cast<Index *>(idx);
+  flush_events(I);
+  pipnn_stats st = I.stats;
+  st.leaf_knn_launches = I.leaf_launches;
+  st.ms_prepare = I.phase_ms[kPhPrepare];
+  st.ms_partition = I.phase_ms[kPhPartition];
+  st.ms_leaf_knn = I.phase_ms[kPhLeafKnn];
+  st.ms_bin = I.phase_ms[kPhBin];
+  st.ms_merge = I.phase_ms[kPhMerge];
+  st.ms_robustprune = I.phase_ms[kPhRobustPrune];
+  *h_out = st;
   return PIPNN_OK;
   GUARD_END
 }

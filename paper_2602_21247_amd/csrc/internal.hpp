@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <deque>
 #include <string>
 #include <vector>
 
@@ -41,8 +42,33 @@ struct Index {
   DevBuf s_jobs, s_items, s_picks_c, s_picks_d, s_cnt, s_off, s_bins, s_tmp0, s_tmp1;
   std::vector<DevBuf> levels;   // partition level member arrays
   DevBuf p_asg, p_leaders, p_cm, p_bstart, p_groups, p_gout, p_gsize, p_copy;
+  std::deque<DevBuf> ppool;     // per-call partition buffers, reused across calls
+  size_t ppool_used = 0;
+
+  // statistics and phase events
+  pipnn_stats stats{};
+  bool profiling = false;
+  struct Ev {
+    int phase;
+    hipEvent_t a, b;
+  };
+  std::vector<Ev> events;
+  std::vector<hipEvent_t> ev_free;
+  double phase_ms[8] = {0};
+  int leaf_launches = 0;
 
   const float *xf() const;
+};
+
+// Phase timing: begin/end record events on the stream when profiling is on.
+enum Phase { kPhPrepare = 0, kPhPartition, kPhLeafKnn, kPhBin, kPhMerge, kPhRobustPrune };
+struct PhaseTimer {
+  Index &I;
+  int phase;
+  hipStream_t s;
+  hipEvent_t a = nullptr;
+  PhaseTimer(Index &I_, int ph, hipStream_t s_);
+  ~PhaseTimer();
 };
 
 // ---- knn (fused distance GEMM + per-row selection) --------------------
