@@ -127,6 +127,49 @@ hipError_t upload(DevBuf &b, const std::vector<T> &v, hipStream_t s) {
 constexpr int kKnnRows = 128;  // rows per knn work item (32 per wave x 4 waves)
 constexpr int kGroupTile = 1024;
 
+// Work items of a knn launch in launch order: block b runs on XCD b % 8 and
+// takes item b. Jobs are taken largest first (by rows x columns); a job of
+// at most 16 row blocks goes whole to the least-loaded XCD (its columns stay
+// in that XCD's L2), the row blocks of a larger job are dealt one by one to
+// the least-loaded XCD. Shorter XCD lists are padded with idle items.
+std::vector<KnnItem> plan_items(const std::vector<KnnJob> &jobs) {
+  constexpr int X = kNumXcd;
+  std::vector<int> order(jobs.size());
+  for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+  auto work = [&](int j) { return (double)jobs[(size_t)j].n_rows * jobs[(size_t)j].n_cols; };
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return work(a) > work(b); });
+  std::vector<std::vector<KnnItem>> per(X);
+  double load[X] = {0};
+  auto least = [&]() {
+    int b = 0;
+    for (int x = 1; x < X; ++x)
+      if (load[x] < load[b]) b = x;
+    return b;
+  };
+  for (int j : order) {
+    const KnnJob &J = jobs[(size_t)j];
+    const int nrb = (J.n_rows + kKnnRows - 1) / kKnnRows;
+    const double w_item = (double)kKnnRows * J.n_cols;
+    if (nrb <= 16) {
+      const int x = least();
+      for (int rb = 0; rb < nrb; ++rb) per[x].push_back({j, rb});
+      load[x] += w_item * nrb;
+    } else {
+      for (int rb = 0; rb < nrb; ++rb) {
+        const int x = least();
+        per[x].push_back({j, rb});
+        load[x] += w_item;
+      }
+    }
+  }
+  size_t mx = 0;
+  for (auto &v : per) mx = std::max(mx, v.size());
+  std::vector<KnnItem> items(mx * X, KnnItem{-1, 0});
+  for (int x = 0; x < X; ++x)
+    for (size_t i = 0; i < per[x].size(); ++i) items[i * X + x] = per[x][i];
+  return items;
+}
+
 }  // namespace
 
 namespace pipnn {
@@ -291,7 +334,8 @@ void pipnn_destroy(pipnn_index *idx) {
   if (!idx) return;
   Index *I = reinterpret_cast<Index *>(idx);
   (void)hipDeviceSynchronize();
-  for (DevBuf *b : {&I->xf32, &I->xlow, &I->xscale, &I->sketches, &I->norms, &I->flag, &I->s_jobs,
+  for (DevBuf *b : {&I->rp_order, &I->o_first, &I->o_flag, &I->o_pos, &I->o_pos2, &I->o_tmp,
+                    &I->xf32, &I->xlow, &I->xscale, &I->sketches, &I->norms, &I->flag, &I->s_jobs,
                     &I->s_items, &I->s_picks_c, &I->s_picks_d, &I->s_cnt, &I->s_off, &I->s_bins,
                     &I->s_tmp0, &I->s_tmp1, &I->p_asg, &I->p_leaders, &I->p_cm, &I->p_bstart,
                     &I->p_groups, &I->p_gout, &I->p_gsize, &I->p_copy})
@@ -384,9 +428,7 @@ pipnn_status pipnn_partition(pipnn_index *idx, int64_t *d_leaf_offsets, int64_t 
       J.n_cols = (int32_t)ell;
       J.k_sel = f;
       J.flags = 0;
-      const int32_t jid = (int32_t)jobs.size();
       jobs.push_back(J);
-      for (int64_t rb = 0; rb * kKnnRows < sb.cnt; ++rb) items.push_back({jid, (int32_t)rb});
       ells.push_back((int32_t)ell);
       fs.push_back(f);
       inst += sb.cnt;
@@ -397,6 +439,7 @@ pipnn_status pipnn_partition(pipnn_index *idx, int64_t *d_leaf_offsets, int64_t 
     HIPCHK(I.p_leaders.ensure(lead_idx.size() * 4));
     HIPCHK(launch_gather_u32(A->as<uint32_t>(), I.s_tmp1.as<int64_t>(), I.p_leaders.as<uint32_t>(),
                              (int64_t)lead_idx.size(), s));
+    items = plan_items(jobs);
     HIPCHK(upload(I.s_jobs, jobs, s));
     HIPCHK(upload(I.s_items, items, s));
     HIPCHK(I.p_asg.ensure((size_t)inst * fmax * 4));
@@ -653,15 +696,14 @@ pipnn_status run_pick(Index &I, const std::vector<int64_t> &offs, int64_t l0, in
     J.n_cols = (int32_t)sz;
     J.k_sel = ksel;
     J.flags = 1;
-    const int32_t jid = (int32_t)jobs.size();
     jobs.push_back(J);
-    for (int64_t rb = 0; rb * kKnnRows < sz; ++rb) items.push_back({jid, (int32_t)rb});
     max_cols = std::max<int32_t>(max_cols, (int32_t)sz);
   }
   const int64_t rows = offs[(size_t)l1] - base;
   HIPCHK(launch_fill_u32(pick_c, kEmptyId, rows * P.k, s));
   HIPCHK(launch_fill_u32(reinterpret_cast<uint32_t *>(pick_d), 0x7F800000u, rows * P.k, s));
-  if (items.empty()) return PIPNN_OK;
+  if (jobs.empty()) return PIPNN_OK;
+  items = plan_items(jobs);
   HIPCHK(upload(I.s_jobs, jobs, s));
   HIPCHK(upload(I.s_items, items, s));
   KnnLaunch L{};
@@ -805,6 +847,22 @@ pipnn_status pipnn_build_leaves(pipnn_index *idx, const int64_t *d_leaf_offsets,
     }
     l0 = l1;
   }
+  {
+    // processing order of the final prune: points in leaf order
+    const int64_t cnt = offs[(size_t)n_leaves] - offs[0];
+    const int64_t mx = std::max<int64_t>(cnt, I.n);
+    HIPCHK(I.o_first.ensure((size_t)I.n * 4));
+    HIPCHK(I.o_flag.ensure((size_t)mx * 4));
+    HIPCHK(I.o_pos.ensure((size_t)(mx + 1) * 8));
+    HIPCHK(I.o_pos2.ensure((size_t)(I.n + 1) * 8));
+    HIPCHK(I.o_tmp.ensure((size_t)scan_tmp_elems(mx) * 8));
+    HIPCHK(I.rp_order.ensure((size_t)I.n * 4));
+    HIPCHK(launch_leaf_order(d_leaf_members + offs[0], cnt, I.n, I.o_first.as<uint32_t>(),
+                             I.o_flag.as<uint32_t>(), I.o_pos.as<int64_t>(),
+                             I.o_pos2.as<int64_t>(), I.o_tmp.as<int64_t>(),
+                             I.rp_order.as<uint32_t>(), s));
+    I.rp_order_valid = true;
+  }
   return finish_bins(I, s, "build_leaves");
   GUARD_END
 }
@@ -853,8 +911,7 @@ pipnn_status pipnn_knn_block(pipnn_index *idx, const uint32_t *d_row_ids, int64_
   jobs[0].n_cols = (int32_t)n_cols;
   jobs[0].k_sel = ksel;
   jobs[0].flags = exclude_diag ? 1 : 0;
-  std::vector<KnnItem> items;
-  for (int64_t rb = 0; rb * kKnnRows < n_rows; ++rb) items.push_back({0, (int32_t)rb});
+  std::vector<KnnItem> items = plan_items(jobs);
   HIPCHK(upload(I.s_jobs, jobs, s));
   HIPCHK(upload(I.s_items, items, s));
   KnnLaunch L{};

@@ -45,7 +45,7 @@ __device__ __forceinline__ float row_dist(const float *__restrict__ X, int d, bo
   return l2 ? s : -s;
 }
 
-__device__ void wave_sort_u64(uint64_t *A, int P) {
+__device__ __forceinline__ void wave_sort_u64(uint64_t *A, int P) {
   const int lane = lane_id();
   for (int k = 2; k <= P; k <<= 1) {
     for (int j = k >> 1; j > 0; j >>= 1) {
@@ -140,12 +140,224 @@ __global__ void __launch_bounds__(64 * kRpWaves) robustprune_kernel(
   if (lane == 0) degree[x] = (uint32_t)ne;
 }
 
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ int acc_row32(int v, int h) { return (v & 3) + 8 * (v >> 2) + 4 * h; }
+
+// RobustPrune with the candidate Gram on MFMA (up to 64 candidates,
+// d <= DP <= 128). One wave per point x:
+//  1. d(x,c) for every reservoir candidate by FP32 direct difference, and a
+//     sort of the candidates by (d(x,c), id);
+//  2. the rows of the sorted candidates are loaded once into MFMA operand
+//     fragments (lane l: candidate l%32 of a 32-block, dims of its half);
+//     G = C C^T on v_mfma_f32_32x32x2_f32, only the blocks with y < z;
+//  3. d(y,z) = |y|^2 + |z|^2 - 2 G[y][z] (or -G for inner product), and bit y
+//     of z's 64-bit mask is set when alpha*d(y,z) < d(x,z) (sign of a fused
+//     multiply-add) for y before z in the sorted order;
+//  4. the lazy scan: z is admitted iff its mask has no admitted bit, until R
+//     are admitted. This admits exactly the candidates of Alg. 2.
+template <int DP>
+__global__ void __launch_bounds__(64 * kRpWaves) robustprune_mfma_kernel(
+    const float *__restrict__ X, const float *__restrict__ norms, int64_t n, int d, int metric,
+    const uint64_t *__restrict__ res, int l_max, float alpha, int R,
+    const uint32_t *__restrict__ order, uint32_t *__restrict__ graph,
+    uint32_t *__restrict__ degree) {
+  constexpr int HALF = DP / 2;
+  __shared__ uint64_t sK[kRpWaves][64];
+  __shared__ float sD[kRpWaves][64];
+  __shared__ float sN[kRpWaves][64];
+  __shared__ uint32_t sI[kRpWaves][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int h = lane >> 5, l32 = lane & 31;
+  const int64_t item = (int64_t)xcd_item(blockIdx.x, gridDim.x) * kRpWaves + wave;
+  if (item >= n) return;
+  const uint32_t x = __builtin_amdgcn_readfirstlane(order ? order[item] : (uint32_t)item);
+  const bool l2 = metric == PIPNN_METRIC_L2;
+  const bool full_d = d == DP;
+  uint64_t *K = sK[wave];
+
+  // 1. candidates, their distance to x, sorted by (distance, id)
+  {
+    uint64_t key = kNoKey;
+    if (lane < l_max) {
+      const uint32_t c = slot_id(res[(int64_t)x * l_max + lane]);
+      if (c != kEmptyId && c != x && c < n) {
+        const float dxc = row_dist(X, d, l2, x, c);
+        key = ((uint64_t)f32_rank(dxc) << 32) | c;
+      }
+    }
+    K[lane] = key;
+  }
+  wave_sync();
+  wave_sort_u64(K, 64);
+  const uint64_t myk = K[lane];
+  const int nv = __popcll(__ballot(myk != kNoKey));
+  const uint32_t myid = (uint32_t)myk;
+  sI[wave][lane] = myid;
+  sD[wave][lane] = myk != kNoKey ? rank_to_f32((uint32_t)(myk >> 32)) : 0.f;
+  sN[wave][lane] = (myk != kNoKey && l2) ? norms[myid] : 0.f;
+  wave_sync();
+
+  // 2. operand fragments of the sorted candidates: F0 rows 0..31, F1 rows 32..63
+  float f0[HALF], f1[HALF];
+  {
+    const int kb = h * HALF;
+    const uint32_t c0 = sI[wave][l32], c1 = sI[wave][32 + l32];
+    const bool v0 = l32 < nv, v1 = 32 + l32 < nv;
+    const float *r0 = X + (int64_t)(v0 ? c0 : 0) * d + kb;
+    const float *r1 = X + (int64_t)(v1 ? c1 : 0) * d + kb;
+    if (full_d) {
+#pragma unroll
+      for (int kk = 0; kk < HALF; kk += 4) {
+        float4 q0 = v0 ? *reinterpret_cast<const float4 *>(r0 + kk) : make_float4(0, 0, 0, 0);
+        float4 q1 = v1 ? *reinterpret_cast<const float4 *>(r1 + kk) : make_float4(0, 0, 0, 0);
+        f0[kk] = q0.x; f0[kk + 1] = q0.y; f0[kk + 2] = q0.z; f0[kk + 3] = q0.w;
+        f1[kk] = q1.x; f1[kk + 1] = q1.y; f1[kk + 2] = q1.z; f1[kk + 3] = q1.w;
+      }
+    } else {
+#pragma unroll
+      for (int kk = 0; kk < HALF; ++kk) {
+        const bool in = kb + kk < d;
+        f0[kk] = (v0 && in) ? r0[kk] : 0.f;
+        f1[kk] = (v1 && in) ? r1[kk] : 0.f;
+      }
+    }
+  }
+  f32x16 g00, g01, g11;
+#pragma unroll
+  for (int v = 0; v < 16; ++v) { g00[v] = 0.f; g01[v] = 0.f; g11[v] = 0.f; }
+#pragma unroll
+  for (int kk = 0; kk < HALF; ++kk)
+    g00 = __builtin_amdgcn_mfma_f32_32x32x2f32(f0[kk], f0[kk], g00, 0, 0, 0);
+  if (nv > 32) {
+#pragma unroll
+    for (int kk = 0; kk < HALF; ++kk) {
+      g01 = __builtin_amdgcn_mfma_f32_32x32x2f32(f0[kk], f1[kk], g01, 0, 0, 0);
+      g11 = __builtin_amdgcn_mfma_f32_32x32x2f32(f1[kk], f1[kk], g11, 0, 0, 0);
+    }
+  }
+
+  // 3. prune masks. Column of this lane: z = l32 (block 00), 32 + l32 (01, 11).
+  uint32_t b00 = 0, b01 = 0, b11 = 0;
+  {
+    const int zA = l32, zB = 32 + l32;
+    const float dxA = sD[wave][zA], dxB = sD[wave][zB];
+    const float nA = sN[wave][zA], nB = sN[wave][zB];
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int y = acc_row32(v, h);
+      const float ny = sN[wave][y], ny1 = sN[wave][32 + y];
+      const float d00 = l2 ? ny + fmaf(-2.f, g00[v], nA) : -g00[v];
+      if (y < zA && zA < nv && fmaf(alpha, d00, -dxA) < 0.f) b00 |= 1u << y;
+      if (nv > 32) {
+        const float d01 = l2 ? ny + fmaf(-2.f, g01[v], nB) : -g01[v];
+        const float d11 = l2 ? ny1 + fmaf(-2.f, g11[v], nB) : -g11[v];
+        if (zB < nv && fmaf(alpha, d01, -dxB) < 0.f) b01 |= 1u << y;
+        if (32 + y < zB && zB < nv && fmaf(alpha, d11, -dxB) < 0.f) b11 |= 1u << y;
+      }
+    }
+    b00 |= __shfl_xor(b00, 32, 64);
+    b01 |= __shfl_xor(b01, 32, 64);
+    b11 |= __shfl_xor(b11, 32, 64);
+  }
+  // lane j holds the mask of candidate j: lanes < 32 from block 00, the
+  // others from blocks 01 (rows 0..31) and 11 (rows 32..63)
+  const uint32_t mlo = h == 0 ? b00 : b01;
+  const uint32_t mhi = h == 0 ? 0u : b11;
+
+  // 4. lazy admission scan (wave-uniform)
+  uint64_t adm = 0;
+  int ne = 0;
+  for (int z = 0; z < nv && ne < R; ++z) {
+    // readlane returns int: widen through uint32_t so bit 31 does not sign-extend
+    const uint64_t mz = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)mhi, z) << 32) |
+                        (uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)mlo, z);
+    if ((mz & adm) == 0) {
+      adm |= 1ull << z;
+      ++ne;
+    }
+  }
+  // admitted candidates in sorted order = admission order
+  const bool mine = (adm >> lane) & 1ull;
+  const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  const int pos = __popcll(adm & below);
+  uint32_t *grow = graph + (int64_t)x * R;
+  if (mine) grow[pos] = myid;
+  for (int i = ne + lane; i < R; i += 64) grow[i] = kEmptyId;
+  if (lane == 0) degree[x] = (uint32_t)ne;
+}
+
 hipError_t launch_robustprune(const Index &I, const uint64_t *res, uint32_t *graph, uint32_t *degree,
                               hipStream_t s) {
   if (I.p.l_max > 256 || I.p.R > 256) return hipErrorInvalidValue;
+  const uint32_t *order = I.rp_order_valid ? I.rp_order.as<uint32_t>() : nullptr;
+  if (I.p.l_max <= 64 && I.d <= 128) {
+    const int64_t blocks = xcd_grid((I.n + kRpWaves - 1) / kRpWaves);
+    auto args = [&](auto kern) {
+      hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(64 * kRpWaves), 0, s, I.xf(),
+                         I.norms.as<float>(), I.n, I.d, I.p.metric, res, I.p.l_max, I.p.alpha,
+                         I.p.R, order, graph, degree);
+    };
+    if (I.d <= 32) args(robustprune_mfma_kernel<32>);
+    else if (I.d <= 64) args(robustprune_mfma_kernel<64>);
+    else if (I.d <= 96) args(robustprune_mfma_kernel<96>);
+    else args(robustprune_mfma_kernel<128>);
+    return hipGetLastError();
+  }
   const int64_t blocks = (I.n + kRpWaves - 1) / kRpWaves;
   hipLaunchKernelGGL(robustprune_kernel, dim3((unsigned)blocks), dim3(64 * kRpWaves), 0, s, I.xf(),
                      I.n, I.d, I.p.metric, res, I.p.l_max, I.p.alpha, I.p.R, graph, degree);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------
+// Processing order for RobustPrune: points in the order of their first
+// appearance in the leaf CSR (so that a point's candidates, which come from
+// its own leaves, are read while those leaves are hot in L2), then every
+// point that no leaf holds, ascending.
+__global__ void first_pos_kernel(const uint32_t *mem, int64_t cnt, int64_t n, uint32_t *first) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < cnt && mem[p] < n) atomicMin(&first[mem[p]], (uint32_t)p);
+}
+__global__ void first_flag_kernel(const uint32_t *mem, int64_t cnt, int64_t n,
+                                  const uint32_t *first, uint32_t *flag) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < cnt) flag[p] = (mem[p] < n && first[mem[p]] == (uint32_t)p) ? 1u : 0u;
+}
+__global__ void order_seen_kernel(const uint32_t *mem, int64_t cnt, const uint32_t *flag,
+                                  const int64_t *pos, uint32_t *order) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < cnt && flag[p]) order[pos[p]] = mem[p];
+}
+__global__ void unseen_flag_kernel(const uint32_t *first, int64_t n, uint32_t *flag) {
+  const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (x < n) flag[x] = first[x] == 0xFFFFFFFFu ? 1u : 0u;
+}
+__global__ void order_unseen_kernel(const uint32_t *flag, const int64_t *pos, int64_t n,
+                                    const int64_t *n_seen, uint32_t *order) {
+  const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (x < n && flag[x]) order[*n_seen + pos[x]] = (uint32_t)x;
+}
+
+// first/flag: n and max(n, cnt) uint32; pos: max(n, cnt)+1 int64; tmp: scan scratch
+hipError_t launch_leaf_order(const uint32_t *mem, int64_t cnt, int64_t n, uint32_t *first,
+                             uint32_t *flag, int64_t *pos, int64_t *pos2, int64_t *tmp,
+                             uint32_t *order, hipStream_t s) {
+  const unsigned gc = (unsigned)((cnt + 255) / 256), gn = (unsigned)((n + 255) / 256);
+  hipError_t e = launch_fill_u32(first, 0xFFFFFFFFu, n, s);
+  if (e != hipSuccess) return e;
+  if (cnt > 0) {
+    hipLaunchKernelGGL(first_pos_kernel, dim3(gc), dim3(256), 0, s, mem, cnt, n, first);
+    hipLaunchKernelGGL(first_flag_kernel, dim3(gc), dim3(256), 0, s, mem, cnt, n, first, flag);
+    if ((e = launch_scan_u32(flag, pos, cnt, tmp, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(order_seen_kernel, dim3(gc), dim3(256), 0, s, mem, cnt, flag, pos, order);
+  } else {
+    if ((e = hipMemsetAsync(pos, 0, 8, s)) != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(unseen_flag_kernel, dim3(gn), dim3(256), 0, s, first, n, flag);
+  if ((e = launch_scan_u32(flag, pos2, n, tmp, s)) != hipSuccess) return e;
+  hipLaunchKernelGGL(order_unseen_kernel, dim3(gn), dim3(256), 0, s, flag, pos2, n, pos + cnt,
+                     order);
   return hipGetLastError();
 }
 

@@ -42,6 +42,9 @@ struct Index {
   DevBuf s_jobs, s_items, s_picks_c, s_picks_d, s_cnt, s_off, s_bins, s_tmp0, s_tmp1;
   std::vector<DevBuf> levels;   // partition level member arrays
   DevBuf p_asg, p_leaders, p_cm, p_bstart, p_groups, p_gout, p_gsize, p_copy;
+  DevBuf rp_order;              // RobustPrune processing order (from the last leaves)
+  DevBuf o_first, o_flag, o_pos, o_pos2, o_tmp;
+  bool rp_order_valid = false;
   std::deque<DevBuf> ppool;     // per-call partition buffers, reused across calls
   size_t ppool_used = 0;
 
@@ -164,6 +167,9 @@ hipError_t launch_reservoir_canonical(const uint64_t *in, uint64_t *out, int64_t
 // ---- RobustPrune / search ---------------------------------------------
 hipError_t launch_robustprune(const Index &I, const uint64_t *res, uint32_t *graph, uint32_t *degree,
                               hipStream_t s);
+hipError_t launch_leaf_order(const uint32_t *mem, int64_t cnt, int64_t n, uint32_t *first,
+                             uint32_t *flag, int64_t *pos, int64_t *pos2, int64_t *tmp,
+                             uint32_t *order, hipStream_t s);
 hipError_t launch_start_node(const Index &I, double *tmp, uint32_t *out, hipStream_t s);
 hipError_t launch_search(const Index &I, const uint32_t *graph, const float *Q, int64_t nq,
                          int32_t k, int32_t L, uint32_t start, uint32_t *out_ids, float *out_dist,

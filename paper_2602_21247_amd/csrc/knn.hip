@@ -15,7 +15,11 @@
 // tiles of 64 points are staged in LDS (row stride d+4 floats, so the
 // 16-byte fragment reads are bank-conflict free) and shared by the NW
 // waves; the next tile is prefetched into registers while the current one
-// is multiplied.
+// is multiplied. The host lists the work items in launch order (block b
+// runs on XCD b % 8): whole small jobs go to one XCD so that their column
+// vectors stay in that XCD's L2, and jobs are dealt to XCDs largest first
+// by work so that the eight XCDs finish together. Two workgroups fit on a
+// CU, so one's selection and epilogue overlap the other's MFMA work.
 //
 // Selection: each row keeps its KSEL best (distance, column) pairs in LDS
 // and a threshold tau (the worst kept pair once KSEL are kept). After each
@@ -27,9 +31,9 @@
 //
 // Epilogue: the kept pairs are sorted by (GEMM distance, column); when
 // asked, each winner's FP32 distance is recomputed by direct difference,
-// sum_i (x_i - y_i)^2 (or -sum x_i y_i), over four fixed quarter-slices of
-// the dimensions reduced in a fixed order, so a pair always gets the same
-// value whichever row it is found from. With rescoring, the k_sel GEMM
+// sum_i (x_i - y_i)^2 (or -sum x_i y_i): each half of the dimensions is
+// summed in index order and the halves are added, so a pair always gets the
+// same value whichever row it is found from. With rescoring, the k_sel GEMM
 // winners are re-ranked by (direct distance, column) and the first k kept.
 #include "common.hpp"
 #include "internal.hpp"
@@ -63,12 +67,12 @@ struct KnnArgs {
 __device__ __forceinline__ int acc_row(int v, int h) { return (v & 3) + 8 * (v >> 2) + 4 * h; }
 
 template <int DP, int KSEL, int NW>
-__global__ void __launch_bounds__(NW * 64) knn_f32_kernel(KnnArgs a) {
+__global__ void __launch_bounds__(NW * 64, 2) knn_f32_kernel(KnnArgs a) {
   constexpr int BM = 32 * NW;     // rows per workgroup
   constexpr int BN = 64;          // columns per tile
   constexpr int LDB = DP + 4;     // LDS stride of a staged column vector (floats)
   constexpr int HALF = DP / 2;    // k-range owned by each half of the wave
-  constexpr int CAP = BN;         // per-row buffer: a tile appends at most BN
+  constexpr int CAP = 32;         // per-row buffer: a 32-column block appends at most 32
   constexpr int BUFD = CAP + 1;
   constexpr int BUFC = CAP + 2;
   constexpr int KS1 = KSEL + 1;
@@ -83,11 +87,12 @@ __global__ void __launch_bounds__(NW * 64) knn_f32_kernel(KnnArgs a) {
   __shared__ uint32_t sTopC[BM * KS1];
   __shared__ float sTau[BM];
   __shared__ int sBufN[BM];
+  __shared__ float sNr[BM];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int h = lane >> 5, l32 = lane & 31;
-  const int item = xcd_item(blockIdx.x, gridDim.x);
-  if (item >= a.n_items) return;
+  const int item = blockIdx.x;
+  if (item >= a.n_items || a.items[item].job < 0) return;
   const KnnItem it = a.items[item];
   const KnnJob J = a.jobs[it.job];
   const int rbase = it.rb * BM;
@@ -103,6 +108,7 @@ __global__ void __launch_bounds__(NW * 64) knn_f32_kernel(KnnArgs a) {
   for (int r = tid; r < BM; r += NTH) {
     sTau[r] = INFINITY;
     sBufN[r] = 0;
+    sNr[r] = (l2 && rbase + r < n_rows) ? a.norms[rows[rbase + r]] : 0.f;
   }
 
   // A operand: lane holds row l32 of this wave, dims [h*HALF, h*HALF+HALF).
@@ -125,15 +131,6 @@ __global__ void __launch_bounds__(NW * 64) knn_f32_kernel(KnnArgs a) {
 #pragma unroll
       for (int kk = 0; kk < HALF; ++kk) av[kk] = 0.f;
     }
-  }
-  // squared norms of the 16 rows this lane's accumulator entries belong to
-  float nr[16];
-  bool rvalid[16];
-#pragma unroll
-  for (int v = 0; v < 16; ++v) {
-    const int rr = wrow + acc_row(v, h);
-    rvalid[v] = rr < n_rows;
-    nr[v] = (rvalid[v] && l2) ? a.norms[rows[rr]] : 0.f;
   }
 
   // owner-lane state (lanes 0..31 own row wrow + lane)
@@ -240,38 +237,30 @@ __global__ void __launch_bounds__(NW * 64) knn_f32_kernel(KnnArgs a) {
       acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(av[kk + 3], b1.w, acc1, 0, 0, 0);
     }
 
-    // filter: the two column blocks of this tile
-    const int cA = c0 + l32, cB = c0 + 32 + l32;
-    const bool vA = cA < n_cols, vB = cB < n_cols;
-    const float ncA = (vA && l2) ? a.norms[cols[cA]] : 0.f;
-    const float ncB = (vB && l2) ? a.norms[cols[cB]] : 0.f;
+    // filter + drain, one 32-column block at a time (each appends <= 32 per row)
 #pragma unroll
-    for (int v = 0; v < 16; ++v) {
-      if (!rvalid[v]) continue;
-      const int rr = wrow + acc_row(v, h);
-      const int rl = rr - rbase;
-      const float tau = sTau[rl];
-      const float dA = l2 ? nr[v] + fmaf(-2.f, acc0[v], ncA) : -acc0[v];
-      const float dB = l2 ? nr[v] + fmaf(-2.f, acc1[v], ncB) : -acc1[v];
-      if (a.out_matrix) {
-        float *mrow = a.out_matrix + (J.out_off + rr) * a.matrix_ld;
-        if (vA) mrow[cA] = dA;
-        if (vB) mrow[cB] = dB;
+    for (int blk = 0; blk < 2; ++blk) {
+      const f32x16 &acc = blk == 0 ? acc0 : acc1;
+      const int cc = c0 + 32 * blk + l32;
+      const bool vc = cc < n_cols;
+      const float nc = (vc && l2) ? a.norms[cols[cc]] : 0.f;
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int rl = wave * 32 + acc_row(v, h);
+        const int rr = rbase + rl;
+        if (rr >= n_rows) continue;
+        const float dv = l2 ? sNr[rl] + fmaf(-2.f, acc[v], nc) : -acc[v];
+        if (a.out_matrix && vc) a.out_matrix[(J.out_off + rr) * a.matrix_ld + cc] = dv;
+        if (vc && !(excl && rr == cc) && dv <= sTau[rl]) {
+          const int pos = atomicAdd(&sBufN[rl], 1);
+          sBufD[rl * BUFD + pos] = dv;
+          sBufC[rl * BUFC + pos] = (uint16_t)cc;
+        }
       }
-      if (vA && !(excl && rr == cA) && dA <= tau) {
-        const int pos = atomicAdd(&sBufN[rl], 1);
-        sBufD[rl * BUFD + pos] = dA;
-        sBufC[rl * BUFC + pos] = (uint16_t)cA;
-      }
-      if (vB && !(excl && rr == cB) && dB <= tau) {
-        const int pos = atomicAdd(&sBufN[rl], 1);
-        sBufD[rl * BUFD + pos] = dB;
-        sBufC[rl * BUFC + pos] = (uint16_t)cB;
-      }
+      wave_sync();
+      drain();
+      wave_sync();
     }
-    wave_sync();
-    drain();
-    wave_sync();
     __syncthreads();  // every wave is done with sB
     if (has_next) {
       store_tile();
@@ -305,36 +294,52 @@ __global__ void __launch_bounds__(NW * 64) knn_f32_kernel(KnnArgs a) {
 
   const int ksel_job = J.k_sel < KSEL ? J.k_sel : KSEL;
   if (a.recompute) {
-    // FP32 direct-difference distance of each winner into sBufD[row][i]
-    constexpr int QS = (DP + 3) / 4;  // dims per quarter slice
-    for (int r = 0; r < 32; ++r) {
-      const int rr = wrow + r;
-      if (rr >= n_rows) break;
-      const int tnr = __shfl(tn, r, 64);
-      const int cnt = tnr < ksel_job ? tnr : ksel_job;
-      const int lrow = wave * 32 + r;
-      const float *xr = a.X + (int64_t)rows[rr] * d;
-      for (int base = 0; base < cnt; base += 16) {
-        const int wi = base + (lane >> 2), q = lane & 3;
-        float s = 0.f;
-        if (wi < cnt) {
-          const uint32_t c = sTopC[lrow * KS1 + wi];
-          const float *xc = a.X + (int64_t)cols[c] * d;
-          const int k0 = q * QS;
-          const int k1 = (k0 + QS < d) ? k0 + QS : d;
-          if (l2) {
-            for (int kx = k0; kx < k1; ++kx) {
-              const float t = xr[kx] - xc[kx];
-              s = fmaf(t, t, s);
+    // FP32 direct-difference distance of each winner of row l32, into
+    // sBufD[row][i]. Lane (l32, h) holds its row's dims [h*HALF, h*HALF+HALF)
+    // in av[]; it sums (x_r - x_c)^2 over that half in index order, and the
+    // two halves are added, so a pair gets the same value from either row.
+    const int rr = wrow + l32;
+    const int tnr = __shfl(tn, l32, 64);
+    const int cnt = rr < n_rows ? (tnr < ksel_job ? tnr : ksel_job) : 0;
+    const int lrow = wave * 32 + l32;
+    const int kbase = h * HALF;
+    for (int i = 0; i < KSEL; ++i) {
+      if (!__any(i < cnt)) break;
+      float s = 0.f;
+      if (i < cnt) {
+        const uint32_t c = sTopC[lrow * KS1 + i];
+        const float *xc = a.X + (int64_t)cols[c] * d + kbase;
+        if (full_d) {
+#pragma unroll
+          for (int kk = 0; kk < HALF; kk += 4) {
+            const float4 q = *reinterpret_cast<const float4 *>(xc + kk);
+            if (l2) {
+              float t = av[kk] - q.x; s = fmaf(t, t, s);
+              t = av[kk + 1] - q.y; s = fmaf(t, t, s);
+              t = av[kk + 2] - q.z; s = fmaf(t, t, s);
+              t = av[kk + 3] - q.w; s = fmaf(t, t, s);
+            } else {
+              s = fmaf(av[kk], q.x, s); s = fmaf(av[kk + 1], q.y, s);
+              s = fmaf(av[kk + 2], q.z, s); s = fmaf(av[kk + 3], q.w, s);
             }
-          } else {
-            for (int kx = k0; kx < k1; ++kx) s = fmaf(xr[kx], xc[kx], s);
+          }
+        } else {
+#pragma unroll
+          for (int kk = 0; kk < HALF; ++kk) {
+            const float v = (kbase + kk < d) ? xc[kk] : 0.f;
+            if (l2) {
+              const float t = av[kk] - v;
+              s = fmaf(t, t, s);
+            } else {
+              s = fmaf(av[kk], v, s);
+            }
           }
         }
-        s += __shfl_xor(s, 1, 64);
-        s += __shfl_xor(s, 2, 64);
-        if (wi < cnt && q == 0) sBufD[lrow * BUFD + wi] = l2 ? s : -s;
       }
+      const float other = __shfl_xor(s, 32, 64);
+      const float lo = h == 0 ? s : other, hi = h == 0 ? other : s;
+      const float tot = lo + hi;
+      if (i < cnt && h == 0) sBufD[lrow * BUFD + i] = l2 ? tot : -tot;
     }
   }
   wave_sync();
@@ -376,8 +381,7 @@ __global__ void __launch_bounds__(NW * 64) knn_f32_kernel(KnnArgs a) {
 template <int DP, int KSEL>
 static hipError_t launch_dp_ksel(const KnnArgs &args, int n_items, hipStream_t s) {
   constexpr int NW = 4;
-  hipLaunchKernelGGL((knn_f32_kernel<DP, KSEL, NW>), dim3(xcd_grid(n_items)), dim3(NW * 64), 0, s,
-                     args);
+  hipLaunchKernelGGL((knn_f32_kernel<DP, KSEL, NW>), dim3(n_items), dim3(NW * 64), 0, s, args);
   return hipGetLastError();
 }
 
