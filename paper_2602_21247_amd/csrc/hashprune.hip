@@ -29,37 +29,82 @@ __device__ __forceinline__ uint32_t hash_of(const float *__restrict__ S, int m, 
   return h;
 }
 
-// picks: n_rows x k candidate ids (0xFFFFFFFF unused); row g belongs to
-// point row_ids[g]. Each pick (i -> j) yields the records (i, j) and (j, i).
-__global__ void bin_count_kernel(const uint32_t *row_ids, const uint32_t *picks, int64_t n_rows,
-                                 int k, uint32_t *cnt, int64_t n, int32_t *flag) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= n_rows * k) return;
-  const uint32_t j = picks[t];
-  if (j == kEmptyId) return;
-  const uint32_t i = row_ids[t / k];
-  if (i >= n || j >= n) {
-    atomicOr(flag, 1);
-    return;
+// Both hashes of a pair from one read of each sketch: bit b of h_p(c) is
+// Sketch(c)_b >= Sketch(p)_b and bit b of h_c(p) is Sketch(p)_b >= Sketch(c)_b.
+__device__ __forceinline__ void hash_pair(const float *__restrict__ S, int m, uint32_t p,
+                                          uint32_t c, uint32_t &hpc, uint32_t &hcp) {
+  const float *sp = S + (int64_t)p * m;
+  const float *sc = S + (int64_t)c * m;
+  uint32_t a = 0, b = 0;
+  for (int i = 0; i < m; ++i) {
+    const float x = sp[i], y = sc[i];
+    a |= (y >= x ? 1u : 0u) << i;
+    b |= (x >= y ? 1u : 0u) << i;
   }
-  if (i == j) return;
-  atomicAdd(&cnt[i], 1u);
-  atomicAdd(&cnt[j], 1u);
+  hpc = a;
+  hcp = b;
 }
 
-__global__ void bin_scatter_kernel(const uint32_t *row_ids, const uint32_t *picks,
-                                   const float *dist, int64_t n_rows, int k, const float *S, int m,
-                                   const int64_t *off, uint32_t *cursor, uint64_t *bins, int64_t n) {
+// picks: n_rows x k candidate ids (0xFFFFFFFF unused); row g belongs to
+// point row_ids[g]. Each pick (i -> j) yields the records (i, j) and (j, i).
+// One thread per pick, so the k picks of a row are k consecutive lanes; when
+// k is a power of two that group is aligned inside a wave and the row's
+// forward records are counted and placed with one atomic (AGG).
+template <bool AGG>
+__global__ void __launch_bounds__(256) bin_count_kernel(const uint32_t *row_ids,
+                                                        const uint32_t *picks, int64_t n_rows,
+                                                        int k, uint32_t *cnt, int64_t n,
+                                                        int32_t *flag) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= n_rows * k) return;
-  const uint32_t j = picks[t];
-  if (j == kEmptyId) return;
-  const uint32_t i = row_ids[t / k];
-  if (i >= n || j >= n || i == j) return;
-  const uint32_t bf = bf16_rne(dist[t]);
-  const uint32_t hij = hash_of(S, m, i, j);
-  const uint32_t hji = hash_of(S, m, j, i);
-  const int64_t pi = off[i] + atomicAdd(&cursor[i], 1u);
+  const bool in = t < n_rows * k;
+  const uint32_t j = in ? picks[t] : kEmptyId;
+  const uint32_t i = in ? row_ids[t / k] : kEmptyId;
+  if (in && j != kEmptyId && (i >= n || j >= n)) atomicOr(flag, 1);
+  const bool ok = in && j != kEmptyId && i < n && j < n && i != j;
+  if (AGG) {
+    const int lane = threadIdx.x & 63;
+    const int g0 = lane & ~(k - 1);
+    const uint64_t m = __ballot(ok);
+    const uint64_t gm = (k == 64) ? m : ((m >> g0) & ((1ull << k) - 1));
+    if (lane == g0 && gm) atomicAdd(&cnt[i], (uint32_t)__popcll(gm));
+  } else if (ok) {
+    atomicAdd(&cnt[i], 1u);
+  }
+  if (ok) atomicAdd(&cnt[j], 1u);
+}
+
+template <bool AGG>
+__global__ void __launch_bounds__(256) bin_scatter_kernel(const uint32_t *row_ids,
+                                                          const uint32_t *picks, const float *dist,
+                                                          int64_t n_rows, int k, const float *S,
+                                                          int m, const int64_t *off,
+                                                          uint32_t *cursor, uint64_t *bins,
+                                                          int64_t n) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool in = t < n_rows * k;
+  const uint32_t j = in ? picks[t] : kEmptyId;
+  const uint32_t i = in ? row_ids[t / k] : kEmptyId;
+  const bool ok = in && j != kEmptyId && i < n && j < n && i != j;
+  uint32_t hij = 0, hji = 0, bf = 0;
+  if (ok) {
+    bf = bf16_rne(dist[t]);
+    hash_pair(S, m, i, j, hij, hji);
+  }
+  int64_t pi = 0;
+  if (AGG) {
+    const int lane = threadIdx.x & 63;
+    const int g0 = lane & ~(k - 1);
+    const uint64_t msk = __ballot(ok);
+    const uint64_t gm = (k == 64) ? msk : ((msk >> g0) & ((1ull << k) - 1));
+    uint32_t base = 0;
+    if (lane == g0 && gm) base = atomicAdd(&cursor[i], (uint32_t)__popcll(gm));
+    base = __shfl(base, g0, 64);
+    const uint64_t below = (lane == g0) ? 0ull : ((~0ull >> (64 - (lane - g0))));
+    pi = off[i] + base + __popcll(gm & below);
+  } else if (ok) {
+    pi = off[i] + atomicAdd(&cursor[i], 1u);
+  }
+  if (!ok) return;
   bins[pi] = slot_pack(j, hij, bf);
   const int64_t pj = off[j] + atomicAdd(&cursor[j], 1u);
   bins[pj] = slot_pack(i, hji, bf);
@@ -69,8 +114,13 @@ hipError_t launch_bin_count(const uint32_t *row_ids, const uint32_t *picks, int6
                             int32_t k, uint32_t *cnt, int64_t n, int32_t *flag, hipStream_t s) {
   const int64_t tot = n_rows * k;
   if (tot == 0) return hipSuccess;
-  hipLaunchKernelGGL(bin_count_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s,
-                     row_ids, picks, n_rows, k, cnt, n, flag);
+  const bool agg = k <= 64 && (k & (k - 1)) == 0;
+  if (agg)
+    hipLaunchKernelGGL(bin_count_kernel<true>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0,
+                       s, row_ids, picks, n_rows, k, cnt, n, flag);
+  else
+    hipLaunchKernelGGL(bin_count_kernel<false>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0,
+                       s, row_ids, picks, n_rows, k, cnt, n, flag);
   return hipGetLastError();
 }
 
@@ -80,8 +130,13 @@ hipError_t launch_bin_scatter(const uint32_t *row_ids, const uint32_t *picks, co
                               hipStream_t s) {
   const int64_t tot = n_rows * k;
   if (tot == 0) return hipSuccess;
-  hipLaunchKernelGGL(bin_scatter_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s,
-                     row_ids, picks, dist, n_rows, k, sketch, m, off, cursor, bins, n);
+  const bool agg = k <= 64 && (k & (k - 1)) == 0;
+  if (agg)
+    hipLaunchKernelGGL(bin_scatter_kernel<true>, dim3((unsigned)((tot + 255) / 256)), dim3(256),
+                       0, s, row_ids, picks, dist, n_rows, k, sketch, m, off, cursor, bins, n);
+  else
+    hipLaunchKernelGGL(bin_scatter_kernel<false>, dim3((unsigned)((tot + 255) / 256)), dim3(256),
+                       0, s, row_ids, picks, dist, n_rows, k, sketch, m, off, cursor, bins, n);
   return hipGetLastError();
 }
 

@@ -7,42 +7,56 @@ namespace pipnn {
 
 // ---------------------------------------------------------------------
 // Squared norms (for the GEMM distance form) and sketches
-// Sketch(v)_b = H_b . v (Sec. 3, Implementation). One wave per point; lane l
-// accumulates dims l, l+64, ... in order, then a fixed butterfly reduction.
+// Sketch(v)_b = H_b . v (Sec. 3, Implementation). One thread per point
+// reads its row with 16-byte loads and accumulates every output in
+// dimension order; the hyperplanes are broadcast from LDS.
 __global__ void __launch_bounds__(256) norms_sketches_kernel(const float *__restrict__ X, int64_t n,
                                                              int d, const float *__restrict__ H,
                                                              int m, float *__restrict__ norms,
                                                              float *__restrict__ S) {
-  const int lane = threadIdx.x & 63;
-  const int64_t p = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  extern __shared__ float sH[];  // m x d
+  for (int i = threadIdx.x; i < m * d; i += blockDim.x) sH[i] = H[i];
+  __syncthreads();
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= n) return;
   const float *x = X + p * d;
   float nn = 0.f;
   float s[16];
 #pragma unroll
   for (int b = 0; b < 16; ++b) s[b] = 0.f;
-  for (int i = lane; i < d; i += 64) {
-    const float v = x[i];
-    nn = fmaf(v, v, nn);
+  if ((d & 3) == 0) {
+    for (int i = 0; i < d; i += 4) {
+      const float4 v = *reinterpret_cast<const float4 *>(x + i);
+      nn = fmaf(v.x, v.x, nn); nn = fmaf(v.y, v.y, nn);
+      nn = fmaf(v.z, v.z, nn); nn = fmaf(v.w, v.w, nn);
 #pragma unroll
-    for (int b = 0; b < 16; ++b)
-      if (b < m) s[b] = fmaf(H[(int64_t)b * d + i], v, s[b]);
+      for (int b = 0; b < 16; ++b) {
+        if (b < m) {
+          const float *h = sH + b * d + i;
+          s[b] = fmaf(h[0], v.x, s[b]); s[b] = fmaf(h[1], v.y, s[b]);
+          s[b] = fmaf(h[2], v.z, s[b]); s[b] = fmaf(h[3], v.w, s[b]);
+        }
+      }
+    }
+  } else {
+    for (int i = 0; i < d; ++i) {
+      const float v = x[i];
+      nn = fmaf(v, v, nn);
+#pragma unroll
+      for (int b = 0; b < 16; ++b)
+        if (b < m) s[b] = fmaf(sH[b * d + i], v, s[b]);
+    }
   }
-  nn = wave_sum(nn);
+  norms[p] = nn;
 #pragma unroll
   for (int b = 0; b < 16; ++b)
-    if (b < m) s[b] = wave_sum(s[b]);
-  if (lane == 0) {
-    norms[p] = nn;
-#pragma unroll
-    for (int b = 0; b < 16; ++b)
-      if (b < m) S[p * m + b] = s[b];
-  }
+    if (b < m) S[p * m + b] = s[b];
 }
 
 hipError_t launch_norms_sketches(const Index &I, hipStream_t s) {
-  const int64_t blocks = (I.n + 3) / 4;
-  hipLaunchKernelGGL(norms_sketches_kernel, dim3((unsigned)blocks), dim3(256), 0, s, I.xf(), I.n,
+  const int64_t blocks = (I.n + 255) / 256;
+  const size_t lds = (size_t)I.m * I.d * sizeof(float);
+  hipLaunchKernelGGL(norms_sketches_kernel, dim3((unsigned)blocks), dim3(256), lds, s, I.xf(), I.n,
                      I.d, I.H, I.m, I.norms.as<float>(), I.sketches.as<float>());
   return hipGetLastError();
 }
