@@ -50,7 +50,7 @@ __device__ __forceinline__ void wave_sort_u64(uint64_t *A, int P) {
   for (int k = 2; k <= P; k <<= 1) {
     for (int j = k >> 1; j > 0; j >>= 1) {
       for (int t = lane; t < P / 2; t += 64) {
-        const int i = (t / j) * 2 * j + (t % j);
+        const int i = 2 * t - (t & (j - 1));  // t = q*j + r -> q*2j + r (j is a power of two)
         const int l = i + j;
         const bool asc = (i & k) == 0;
         const uint64_t x = A[i], y = A[l];

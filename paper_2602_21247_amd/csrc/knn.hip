@@ -14,8 +14,7 @@
 // A operand (the row vectors) in registers for the whole item. Column
 // tiles of 64 points are staged in LDS (row stride d+4 floats, so the
 // 16-byte fragment reads are bank-conflict free) and shared by the NW
-// waves; the next tile is prefetched into registers while the current one
-// is multiplied. The host lists the work items in launch order (block b
+// waves. The host lists the work items in launch order (block b
 // runs on XCD b % 8): whole small jobs go to one XCD so that their column
 // vectors stay in that XCD's L2, and jobs are dealt to XCDs largest first
 // by work so that the eight XCDs finish together. Two workgroups fit on a
@@ -66,7 +65,7 @@ struct KnnArgs {
 // lower (h=0) half of the wave, for v_mfma_f32_32x32x2_f32.
 __device__ __forceinline__ int acc_row(int v, int h) { return (v & 3) + 8 * (v >> 2) + 4 * h; }
 
-template <int DP, int KSEL, int NW>
+template <int DP, int KSEL, int NW, bool L2>
 __global__ void __launch_bounds__(NW * 64, 2) knn_f32_kernel(KnnArgs a) {
   constexpr int BM = 32 * NW;     // rows per workgroup
   constexpr int BN = 64;          // columns per tile
@@ -87,6 +86,7 @@ __global__ void __launch_bounds__(NW * 64, 2) knn_f32_kernel(KnnArgs a) {
   __shared__ uint32_t sTopC[BM * KS1];
   __shared__ float sTau[BM];
   __shared__ int sBufN[BM];
+  __shared__ float sColN[BN];
   __shared__ float sNr[BM];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -100,16 +100,21 @@ __global__ void __launch_bounds__(NW * 64, 2) knn_f32_kernel(KnnArgs a) {
   const uint32_t *rows = a.row_base + J.row_off;
   const uint32_t *cols = a.col_base + J.col_off;
   const int d = a.d;
-  const bool l2 = a.metric == PIPNN_METRIC_L2;
+  constexpr bool l2 = L2;
   const bool excl = (J.flags & 1) != 0;
   const bool full_d = (d == DP);
   const int n_rows = J.n_rows, n_cols = J.n_cols;
 
+  // per-row squared norm and selection threshold (-inf past the last row)
   for (int r = tid; r < BM; r += NTH) {
-    sTau[r] = INFINITY;
+    const bool ok = rbase + r < n_rows;
+    sTau[r] = ok ? INFINITY : -INFINITY;
     sBufN[r] = 0;
-    sNr[r] = (l2 && rbase + r < n_rows) ? a.norms[rows[rbase + r]] : 0.f;
+    sNr[r] = (ok && l2) ? a.norms[rows[rbase + r]] : 0.f;
   }
+  uint32_t rowmask = 0;
+#pragma unroll
+  for (int v = 0; v < 16; ++v) rowmask |= (wrow + acc_row(v, h) < n_rows ? 1u : 0u) << v;
 
   // A operand: lane holds row l32 of this wave, dims [h*HALF, h*HALF+HALF).
   float av[HALF];
@@ -141,7 +146,9 @@ __global__ void __launch_bounds__(NW * 64, 2) knn_f32_kernel(KnnArgs a) {
 
   // column tile staging: thread t loads float4s t, t+NTH, ... of the tile
   float4 pre[NPRE];
+  float pre_n = 0.f;
   auto load_tile = [&](int c0) {
+    if (tid < BN) pre_n = (l2 && c0 + tid < n_cols) ? a.norms[cols[c0 + tid]] : 0.f;
 #pragma unroll
     for (int i = 0; i < NPRE; ++i) {
       const int q = tid + i * NTH;
@@ -165,6 +172,7 @@ __global__ void __launch_bounds__(NW * 64, 2) knn_f32_kernel(KnnArgs a) {
     }
   };
   auto store_tile = [&]() {
+    if (tid < BN) sColN[tid] = pre_n;
 #pragma unroll
     for (int i = 0; i < NPRE; ++i) {
       const int q = tid + i * NTH;
@@ -175,85 +183,123 @@ __global__ void __launch_bounds__(NW * 64, 2) knn_f32_kernel(KnnArgs a) {
     }
   };
 
+  // The owner lane of a row loads its kept set into registers once, folds
+  // in every buffered survivor there (replace the current worst, rescan for
+  // the new worst), and writes the set back once.
   auto drain = [&]() {
-    // lanes 0..31: move the buffered survivors of row `orow` into its kept set
     if (l32 == lane && wrow + l32 < n_rows) {
       const int nb = sBufN[orow];
-      for (int e = 0; e < nb; ++e) {
-        const float dv = sBufD[orow * BUFD + e];
-        const uint32_t cv = sBufC[orow * BUFC + e];
-        if (tn < KSEL) {
-          sTopD[orow * KS1 + tn] = dv;
-          sTopC[orow * KS1 + tn] = cv;
-          ++tn;
-          if (tn == KSEL) {
-            maxpos = 0; maxd = sTopD[orow * KS1]; maxc = sTopC[orow * KS1];
-            for (int i = 1; i < KSEL; ++i) {
-              const float di = sTopD[orow * KS1 + i];
-              const uint32_t ci = sTopC[orow * KS1 + i];
-              if (di > maxd || (di == maxd && ci > maxc)) { maxd = di; maxc = ci; maxpos = i; }
+      if (nb > 0) {
+        float kd[KSEL];
+        uint32_t kc[KSEL];
+#pragma unroll
+        for (int i = 0; i < KSEL; ++i) {
+          kd[i] = sTopD[orow * KS1 + i];
+          kc[i] = sTopC[orow * KS1 + i];
+        }
+        float nd = sBufD[orow * BUFD];
+        uint32_t ncv = sBufC[orow * BUFC];
+        for (int e = 0; e < nb; ++e) {
+          const float dv = nd;
+          const uint32_t cv = ncv;
+          if (e + 1 < nb) {
+            nd = sBufD[orow * BUFD + e + 1];
+            ncv = sBufC[orow * BUFC + e + 1];
+          }
+          int slot = -1;
+          if (tn < KSEL) {
+            slot = tn++;
+          } else if (dv < maxd || (dv == maxd && cv < maxc)) {
+            slot = maxpos;
+          }
+          if (slot >= 0) {
+#pragma unroll
+            for (int i = 0; i < KSEL; ++i) {
+              if (i == slot) {
+                kd[i] = dv;
+                kc[i] = cv;
+              }
+            }
+            if (tn == KSEL) {
+              maxpos = 0;
+              maxd = kd[0];
+              maxc = kc[0];
+#pragma unroll
+              for (int i = 1; i < KSEL; ++i) {
+                const bool gt = kd[i] > maxd || (kd[i] == maxd && kc[i] > maxc);
+                maxd = gt ? kd[i] : maxd;
+                maxc = gt ? kc[i] : maxc;
+                maxpos = gt ? i : maxpos;
+              }
             }
           }
-        } else if (dv < maxd || (dv == maxd && cv < maxc)) {
-          sTopD[orow * KS1 + maxpos] = dv;
-          sTopC[orow * KS1 + maxpos] = cv;
-          maxpos = 0; maxd = sTopD[orow * KS1]; maxc = sTopC[orow * KS1];
-          for (int i = 1; i < KSEL; ++i) {
-            const float di = sTopD[orow * KS1 + i];
-            const uint32_t ci = sTopC[orow * KS1 + i];
-            if (di > maxd || (di == maxd && ci > maxc)) { maxd = di; maxc = ci; maxpos = i; }
-          }
         }
+#pragma unroll
+        for (int i = 0; i < KSEL; ++i) {
+          sTopD[orow * KS1 + i] = kd[i];
+          sTopC[orow * KS1 + i] = kc[i];
+        }
+        sBufN[orow] = 0;
+        sTau[orow] = (tn == KSEL) ? maxd : INFINITY;
       }
-      sBufN[orow] = 0;
-      sTau[orow] = (tn == KSEL) ? maxd : INFINITY;
     }
   };
 
-  load_tile(0);
-  store_tile();
-  __syncthreads();
-
   for (int c0 = 0; c0 < n_cols; c0 += BN) {
-    const bool has_next = c0 + BN < n_cols;
-    if (has_next) load_tile(c0 + BN);
+    // stage the column tile (the other workgroup on the CU covers the latency)
+    load_tile(c0);
+    store_tile();
+    __syncthreads();
 
-    f32x16 acc0, acc1;
-#pragma unroll
-    for (int v = 0; v < 16; ++v) { acc0[v] = 0.f; acc1[v] = 0.f; }
-    const float *b0p = &sB[l32 * LDB + h * HALF];
-    const float *b1p = &sB[(32 + l32) * LDB + h * HALF];
-#pragma unroll
-    for (int kk = 0; kk < HALF; kk += 4) {
-      const float4 b0 = *reinterpret_cast<const float4 *>(b0p + kk);
-      const float4 b1 = *reinterpret_cast<const float4 *>(b1p + kk);
-      acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(av[kk], b0.x, acc0, 0, 0, 0);
-      acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(av[kk], b1.x, acc1, 0, 0, 0);
-      acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(av[kk + 1], b0.y, acc0, 0, 0, 0);
-      acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(av[kk + 1], b1.y, acc1, 0, 0, 0);
-      acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(av[kk + 2], b0.z, acc0, 0, 0, 0);
-      acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(av[kk + 2], b1.z, acc1, 0, 0, 0);
-      acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(av[kk + 3], b0.w, acc0, 0, 0, 0);
-      acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(av[kk + 3], b1.w, acc1, 0, 0, 0);
-    }
-
-    // filter + drain, one 32-column block at a time (each appends <= 32 per row)
 #pragma unroll
     for (int blk = 0; blk < 2; ++blk) {
-      const f32x16 &acc = blk == 0 ? acc0 : acc1;
+      // MFMA: this wave's 32 rows against columns c0 + 32*blk + [0, 32)
+      f32x16 acc;
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[v] = 0.f;
+      const float *bp = &sB[(32 * blk + l32) * LDB + h * HALF];
+#pragma unroll
+      for (int kk = 0; kk < HALF; kk += 4) {
+        const float4 b = *reinterpret_cast<const float4 *>(bp + kk);
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av[kk], b.x, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av[kk + 1], b.y, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av[kk + 2], b.z, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av[kk + 3], b.w, acc, 0, 0, 0);
+      }
       const int cc = c0 + 32 * blk + l32;
       const bool vc = cc < n_cols;
-      const float nc = (vc && l2) ? a.norms[cols[cc]] : 0.f;
+      const float nc = sColN[32 * blk + l32];
+      float nr[16], tau[16];
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
-        const int rl = wave * 32 + acc_row(v, h);
-        const int rr = rbase + rl;
-        if (rr >= n_rows) continue;
-        const float dv = l2 ? sNr[rl] + fmaf(-2.f, acc[v], nc) : -acc[v];
-        if (a.out_matrix && vc) a.out_matrix[(J.out_off + rr) * a.matrix_ld + cc] = dv;
-        if (vc && !(excl && rr == cc) && dv <= sTau[rl]) {
+        nr[v] = sNr[wave * 32 + acc_row(v, h)];
+        tau[v] = sTau[wave * 32 + acc_row(v, h)];
+      }
+      float dv[16];
+#pragma unroll
+      for (int v = 0; v < 16; ++v) dv[v] = l2 ? nr[v] + fmaf(-2.f, acc[v], nc) : -acc[v];
+      if (a.out_matrix && vc) {
+        // test-only: the GEMM distance of every pair
+#pragma unroll
+        for (int v = 0; v < 16; ++v)
+          if ((rowmask >> v) & 1u)
+            a.out_matrix[(J.out_off + wrow + acc_row(v, h)) * a.matrix_ld + cc] = dv[v];
+      }
+      // branch-free pass test; a block without any survivor costs one ballot
+      uint32_t pass = 0;
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int rr = wrow + acc_row(v, h);
+        const bool ok = vc && dv[v] <= tau[v] && !(excl && rr == cc);
+        pass |= (ok ? 1u : 0u) << v;
+      }
+      if (__ballot(pass != 0) == 0ull) continue;
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        if ((pass >> v) & 1u) {
+          const int rl = wave * 32 + acc_row(v, h);
           const int pos = atomicAdd(&sBufN[rl], 1);
-          sBufD[rl * BUFD + pos] = dv;
+          sBufD[rl * BUFD + pos] = dv[v];
           sBufC[rl * BUFC + pos] = (uint16_t)cc;
         }
       }
@@ -262,10 +308,6 @@ __global__ void __launch_bounds__(NW * 64, 2) knn_f32_kernel(KnnArgs a) {
       wave_sync();
     }
     __syncthreads();  // every wave is done with sB
-    if (has_next) {
-      store_tile();
-      __syncthreads();
-    }
   }
 
   // ---- epilogue: this wave's 32 rows ----
@@ -381,7 +423,12 @@ __global__ void __launch_bounds__(NW * 64, 2) knn_f32_kernel(KnnArgs a) {
 template <int DP, int KSEL>
 static hipError_t launch_dp_ksel(const KnnArgs &args, int n_items, hipStream_t s) {
   constexpr int NW = 4;
-  hipLaunchKernelGGL((knn_f32_kernel<DP, KSEL, NW>), dim3(n_items), dim3(NW * 64), 0, s, args);
+  if (args.metric == PIPNN_METRIC_L2)
+    hipLaunchKernelGGL((knn_f32_kernel<DP, KSEL, NW, true>), dim3(n_items), dim3(NW * 64), 0, s,
+                       args);
+  else
+    hipLaunchKernelGGL((knn_f32_kernel<DP, KSEL, NW, false>), dim3(n_items), dim3(NW * 64), 0, s,
+                       args);
   return hipGetLastError();
 }
 

@@ -349,7 +349,7 @@ __global__ void __launch_bounds__(1024) merge_dedup_kernel(const uint32_t *const
   for (int k = 2; k <= P; k <<= 1) {
     for (int j = k >> 1; j > 0; j >>= 1) {
       for (int t = threadIdx.x; t < P / 2; t += blockDim.x) {
-        const int i = (t / j) * 2 * j + (t % j);
+        const int i = 2 * t - (t & (j - 1));  // t = q*j + r -> q*2j + r (j is a power of two)
         const int l = i + j;
         const bool asc = (i & k) == 0;
         const uint32_t x = buf[i], y = buf[l];
