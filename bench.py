@@ -52,6 +52,9 @@ def parse():
     ap.add_argument("--no-recall", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=4.0,
                     help="target seconds of oracle work per sampled phase")
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="after the timed steps, copy this many MiB once (a plain copy of known "
+                         "size, used to scale hardware byte counters)")
     return ap.parse_args()
 
 
@@ -230,6 +233,13 @@ def main():
     ms = (t1 - t0) * 1000.0 / args.steps
     log(f"[bench] {args.steps} steps, {ms:.2f} ms/step")
     off, mem, g, deg = out
+    if args.calibrate_copy_mib > 0:
+        # a fill (writes N MiB) and a sum (reads N MiB) of known size
+        src = torch.ones(args.calibrate_copy_mib * 262144, dtype=torch.float32, device="cuda")
+        total = src.sum()
+        torch.cuda.synchronize()
+        log(f"[bench] calibration: {args.calibrate_copy_mib} MiB filled and summed ({total.item():.0f})")
+        del src
 
     # leaf kernel roofline: dense flops 2 s^2 d per leaf, per launch
     launches = max(1, st["leaf_knn_launches"])
