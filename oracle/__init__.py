@@ -95,6 +95,20 @@ def lib():
         L.orc_start_node.restype = C.c_uint32
         L.orc_start_node.argtypes = [P, i64, i32, P]
         L.orc_set_threads.argtypes = [i32]
+        L.orc_bf16_rne.restype = C.c_uint16
+        L.orc_bf16_rne.argtypes = [C.c_float]
+        L.orc_fp16_rne.restype = C.c_uint16
+        L.orc_fp16_rne.argtypes = [C.c_float]
+        L.orc_e4m3_rne_sat.restype = C.c_uint8
+        L.orc_e4m3_rne_sat.argtypes = [C.c_float]
+        L.orc_bf16_value.restype = C.c_double
+        L.orc_bf16_value.argtypes = [C.c_uint16]
+        L.orc_fp16_value.restype = C.c_double
+        L.orc_fp16_value.argtypes = [C.c_uint16]
+        L.orc_e4m3_value.restype = C.c_double
+        L.orc_e4m3_value.argtypes = [C.c_uint8]
+        L.orc_quantize.argtypes = [P, i64, i32, i32, P, P, P]
+        L.orc_leaf_knn_lowp.argtypes = [P, P, i32, i32, P, P, i64, i32, i32, P, P]
         L.orc_get_threads.restype = i32
         _lib = L
     return _lib
@@ -215,6 +229,52 @@ def leaf_knn(X, offsets, members, k: int, metric: int = 0):
     dd = np.zeros((tot, k), dtype=np.float64)
     lib().orc_leaf_knn(_p(X), X.shape[1], metric, _p(offsets), _p(members), len(offsets) - 1,
                        k, _p(cand), _p(dd))
+    return cand, dd
+
+
+PREC_FP32, PREC_BF16, PREC_FP8, PREC_FP16 = 0, 1, 2, 3
+
+
+def encode(x: float, prec: int) -> int:
+    """One binary32 value encoded as a bf16 / fp16 / OCP e4m3 code (no scaling)."""
+    f = {PREC_BF16: lib().orc_bf16_rne, PREC_FP16: lib().orc_fp16_rne,
+         PREC_FP8: lib().orc_e4m3_rne_sat}[prec]
+    return int(f(float(np.float32(x))))
+
+
+def decode(code: int, prec: int) -> float:
+    f = {PREC_BF16: lib().orc_bf16_value, PREC_FP16: lib().orc_fp16_value,
+         PREC_FP8: lib().orc_e4m3_value}[prec]
+    return float(f(int(code)))
+
+
+def quantize(X, prec: int):
+    """GEMM operand of the rows of X: (codes, inv_scale, xq) with codes
+    uint16 (bf16/fp16), uint8 (fp8) or float32 (fp32), inv_scale float32 per
+    row and xq the decoded operand in float64."""
+    X = _f32(X)
+    n, d = X.shape
+    dt = {PREC_FP32: np.float32, PREC_BF16: np.uint16, PREC_FP16: np.uint16,
+          PREC_FP8: np.uint8}[prec]
+    codes = np.zeros((n, d), dtype=dt)
+    inv = np.zeros(n, dtype=np.float32)
+    xq = np.zeros((n, d), dtype=np.float64)
+    lib().orc_quantize(_p(X), n, d, prec, _p(codes), _p(inv), _p(xq))
+    return codes, inv, xq
+
+
+def leaf_knn_lowp(X, xq, offsets, members, k: int, mult: int, metric: int = 0):
+    """Leaf pick on the decoded operand xq with FP64 rescoring of the
+    mult*k nearest (mult 0: no re-ranking); returns (cand, dist) like leaf_knn."""
+    X = _f32(X)
+    xq = np.ascontiguousarray(xq, dtype=np.float64)
+    offsets = np.ascontiguousarray(offsets, dtype=np.int64)
+    members = np.ascontiguousarray(members, dtype=np.uint32)
+    tot = int(offsets[-1])
+    cand = np.zeros((tot, k), dtype=np.uint32)
+    dd = np.zeros((tot, k), dtype=np.float64)
+    lib().orc_leaf_knn_lowp(_p(X), _p(xq), X.shape[1], metric, _p(offsets), _p(members),
+                            len(offsets) - 1, k, mult, _p(cand), _p(dd))
     return cand, dd
 
 

@@ -20,6 +20,10 @@
  *   - RobustPrune, standard (Alg. 2) and lazy (Supplement "Optimizing
  *     RobustPrune");
  *   - BeamSearch (Alg. 1) and brute-force k-NN (Definition of k-NN search).
+ * Beside the paper's method it holds the encoders of the reduced-precision
+ * leaf-GEMM operands (bf16, fp16, OCP e4m3 with a per-point scale), written
+ * from the published format definitions, and the leaf pick over such an
+ * operand with FP64 rescoring of the nearest candidates.
  *
  * Readings of passages the paper leaves open (tie-breaks, the leader count,
  * the merge rule, the random stream) are fixed in the comments below.
@@ -532,6 +536,244 @@ int orc_partition(const float *X, int64_t n, int d, const orc_params *prm, int64
   *n_members_out = lb.n_mem;
   if (leader_dists_out) *leader_dists_out = lb.leader_dists;
   return (lb.n_leaves > cap_leaves || lb.n_mem > cap_members) ? -1 : 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* Low-precision GEMM operands (precision forms of the leaf GEMM).
+ * The paper computes leaf distances in full precision; a reduced-precision
+ * leaf GEMM is this library's extension. Its operand encodings follow the
+ * published format definitions:
+ *   bf16: the upper 16 bits of IEEE binary32 after round-to-nearest-even;
+ *   fp16: IEEE 754 binary16 (5 exponent bits, bias 15, 10 fraction bits,
+ *         subnormals), round-to-nearest-even, overflow to infinity;
+ *   fp8:  OCP 8-bit floating point, E4M3 ("e4m3fn": bias 7, 3 fraction
+ *         bits, subnormals, no infinities, S.1111.111 = NaN, largest finite
+ *         448), round-to-nearest-even, saturating at +-448. Each point is
+ *         scaled by s = 448 / max_i |x_i| (computed in binary32; s = 1 for a
+ *         zero vector) before encoding, and decodes as code * (max / 448).  */
+#define ORC_PREC_FP32 0
+#define ORC_PREC_BF16 1
+#define ORC_PREC_FP8 2
+#define ORC_PREC_FP16 3
+
+static uint32_t f32_bits(float f) {
+  uint32_t u;
+  memcpy(&u, &f, 4);
+  return u;
+}
+
+uint16_t orc_bf16_rne(float f) {
+  uint32_t u = f32_bits(f);
+  if ((u & 0x7F800000u) == 0x7F800000u && (u & 0x007FFFFFu)) return (uint16_t)((u >> 16) | 0x40u);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+double orc_bf16_value(uint16_t b) {
+  uint32_t u = (uint32_t)b << 16;
+  float f;
+  memcpy(&f, &u, 4);
+  return (double)f;
+}
+
+/* Round a non-negative finite double that is a binary32 value to an
+ * integer, ties to even. */
+static double rne_int(double v) {
+  double fl = floor(v), fr = v - fl;
+  if (fr > 0.5) return fl + 1.0;
+  if (fr < 0.5) return fl;
+  return fmod(fl, 2.0) == 0.0 ? fl : fl + 1.0;
+}
+
+uint16_t orc_fp16_rne(float f) {
+  uint32_t u = f32_bits(f);
+  uint16_t sign = (uint16_t)((u >> 16) & 0x8000u);
+  double a = fabs((double)f);
+  if (isnan(a)) return (uint16_t)(sign | 0x7E00u);
+  /* the largest finite binary16 is 65504; halfway to the next step (65536)
+   * is 65520, which rounds (to even) up to infinity */
+  if (a >= 65520.0) return (uint16_t)(sign | 0x7C00u);
+  if (a < ldexp(1.0, -14)) {
+    /* subnormal: value = m * 2^-24, m in 0..1024 (1024 is the smallest normal) */
+    double m = rne_int(a * ldexp(1.0, 24));
+    return (uint16_t)(sign | (uint16_t)m);
+  }
+  int e;
+  double fr = frexp(a, &e); /* a = fr * 2^e, fr in [0.5, 1) */
+  int E = e - 1;            /* a = (2 fr) * 2^E, 2 fr in [1, 2) */
+  double m = rne_int((2.0 * fr - 1.0) * 1024.0);
+  if (m == 1024.0) {
+    m = 0.0;
+    E += 1;
+  }
+  return (uint16_t)(sign | (uint16_t)((E + 15) << 10) | (uint16_t)m);
+}
+
+double orc_fp16_value(uint16_t h) {
+  int s = (h >> 15) & 1, e = (h >> 10) & 31, m = h & 1023;
+  double v;
+  if (e == 31) v = m ? NAN : INFINITY;
+  else if (e == 0) v = ldexp((double)m, -24);
+  else v = ldexp(1.0 + m / 1024.0, e - 15);
+  return s ? -v : v;
+}
+
+uint8_t orc_e4m3_rne_sat(float f) {
+  uint8_t sign = (f32_bits(f) >> 24) & 0x80u;
+  double a = fabs((double)f);
+  if (isnan(a)) return (uint8_t)(sign | 0x7Fu);
+  if (a >= 448.0) return (uint8_t)(sign | 0x7Eu); /* saturate to the largest finite */
+  if (a < ldexp(1.0, -6)) {
+    /* subnormal: value = m * 2^-9, m in 0..8 (8 is the smallest normal, code 0x08) */
+    double m = rne_int(a * 512.0);
+    return (uint8_t)(sign | (uint8_t)m);
+  }
+  int e;
+  double fr = frexp(a, &e);
+  int E = e - 1;
+  double m = rne_int((2.0 * fr - 1.0) * 8.0);
+  if (m == 8.0) {
+    m = 0.0;
+    E += 1;
+  }
+  /* 448 <= value would need E = 8, m = 7 (the NaN pattern); unreachable
+   * here because a < 448 and the largest finite value is 448 (E 8, m 6) */
+  return (uint8_t)(sign | (uint8_t)((E + 7) << 3) | (uint8_t)m);
+}
+
+double orc_e4m3_value(uint8_t c) {
+  int s = (c >> 7) & 1, e = (c >> 3) & 15, m = c & 7;
+  double v;
+  if (e == 15 && m == 7) v = NAN;
+  else if (e == 0) v = ldexp((double)m, -9);
+  else v = ldexp(1.0 + m / 8.0, e - 7);
+  return s ? -v : v;
+}
+
+/* Quantize the rows of X (n x d) to a GEMM operand. codes: n x d uint16
+ * (bf16, fp16) or uint8 (fp8); inv_scale: n floats (fp8: max_i |x_i| / 448
+ * in binary32, or 1 for a zero row; other precisions: 1); xq: the decoded
+ * operand in FP64 (n x d), code value times inv_scale. prec FP32 copies X. */
+void orc_quantize(const float *X, int64_t n, int d, int prec, void *codes, float *inv_scale,
+                  double *xq) {
+  for (int64_t p = 0; p < n; p++) {
+    const float *x = X + p * d;
+    float inv = 1.0f, s = 1.0f;
+    if (prec == ORC_PREC_FP8) {
+      float mx = 0.0f;
+      for (int i = 0; i < d; i++) {
+        float a = fabsf(x[i]);
+        if (a > mx) mx = a;
+      }
+      if (mx > 0.0f) {
+        s = 448.0f / mx;
+        inv = mx / 448.0f;
+      }
+    }
+    if (inv_scale) inv_scale[p] = inv;
+    for (int i = 0; i < d; i++) {
+      double v;
+      if (prec == ORC_PREC_BF16) {
+        uint16_t c = orc_bf16_rne(x[i]);
+        if (codes) ((uint16_t *)codes)[p * d + i] = c;
+        v = orc_bf16_value(c);
+      } else if (prec == ORC_PREC_FP16) {
+        uint16_t c = orc_fp16_rne(x[i]);
+        if (codes) ((uint16_t *)codes)[p * d + i] = c;
+        v = orc_fp16_value(c);
+      } else if (prec == ORC_PREC_FP8) {
+        float t = x[i] * s; /* binary32 product, as the encoder sees it */
+        uint8_t c = orc_e4m3_rne_sat(t);
+        if (codes) ((uint8_t *)codes)[p * d + i] = c;
+        v = orc_e4m3_value(c) * (double)inv;
+      } else {
+        if (codes) ((float *)codes)[p * d + i] = x[i];
+        v = (double)x[i];
+      }
+      if (xq) xq[p * d + i] = v;
+    }
+  }
+}
+
+static double dist64(const double *a, const double *b, int d, int metric) {
+  double s = 0.0;
+  if (metric == 0) {
+    for (int i = 0; i < d; i++) {
+      double t = a[i] - b[i];
+      s += t * t;
+    }
+    return s;
+  }
+  for (int i = 0; i < d; i++) s += a[i] * b[i];
+  return -s;
+}
+
+/* Leaf pick with a reduced-precision GEMM distance and rescoring, in the
+ * independent (FP64) mode. For every member i of a leaf: the k1 = mult * k
+ * nearest co-members j != i by (distance between the decoded operands xq_i,
+ * xq_j, id_j) -- the value a low-precision GEMM approximates -- then those
+ * k1 re-ranked by (distance between the original vectors, id) and the first
+ * k kept. mult = 0 keeps the k nearest by the operand distance without
+ * re-ranking. Emitted distances are always those of the original vectors.
+ * Output layout as orc_leaf_knn. */
+void orc_leaf_knn_lowp(const float *X, const double *xq, int d, int metric,
+                       const int64_t *offsets, const uint32_t *members, int64_t n_leaves, int k,
+                       int mult, uint32_t *out_cand, double *out_dist) {
+  int k1 = mult > 0 ? mult * k : k;
+#pragma omp parallel
+  {
+    double *bd = (double *)malloc(sizeof(double) * (size_t)k1);
+    uint32_t *bi = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)k1);
+    double *rd = (double *)malloc(sizeof(double) * (size_t)k1);
+#pragma omp for schedule(dynamic, 1)
+    for (int64_t L = 0; L < n_leaves; L++) {
+      int64_t o = offsets[L], s = offsets[L + 1] - offsets[L];
+      for (int64_t i = 0; i < s; i++) {
+        uint32_t pi = members[o + i];
+        int cnt = 0;
+        for (int64_t j = 0; j < s; j++) {
+          if (j == i) continue;
+          uint32_t pj = members[o + j];
+          double dv = dist64(xq + (int64_t)pi * d, xq + (int64_t)pj * d, d, metric);
+          if (cnt == k1 && !(dv < bd[k1 - 1] || (dv == bd[k1 - 1] && pj < bi[k1 - 1]))) continue;
+          int pos = cnt < k1 ? cnt : k1 - 1;
+          while (pos > 0 && (dv < bd[pos - 1] || (dv == bd[pos - 1] && pj < bi[pos - 1]))) {
+            bd[pos] = bd[pos - 1];
+            bi[pos] = bi[pos - 1];
+            pos--;
+          }
+          bd[pos] = dv;
+          bi[pos] = pj;
+          if (cnt < k1) cnt++;
+        }
+        /* distances of the original vectors; re-rank when rescoring */
+        for (int r = 0; r < cnt; r++)
+          rd[r] = orc_dist(X + (int64_t)pi * d, X + (int64_t)bi[r] * d, d, metric);
+        if (mult > 0) {
+          for (int a = 1; a < cnt; a++) {
+            double dv = rd[a];
+            uint32_t iv = bi[a];
+            int b = a;
+            while (b > 0 && (rd[b - 1] > dv || (rd[b - 1] == dv && bi[b - 1] > iv))) {
+              rd[b] = rd[b - 1];
+              bi[b] = bi[b - 1];
+              b--;
+            }
+            rd[b] = dv;
+            bi[b] = iv;
+          }
+          if (cnt > k) cnt = k;
+        }
+        for (int r = 0; r < k; r++) {
+          out_cand[(o + i) * k + r] = r < cnt ? bi[r] : ORC_EMPTY_ID;
+          out_dist[(o + i) * k + r] = r < cnt ? rd[r] : INFINITY;
+        }
+      }
+    }
+    free(bd);
+    free(bi);
+    free(rd);
+  }
 }
 
 /* ------------------------------------------------------------------ */
