@@ -12,6 +12,11 @@ After the timed steps the graph of the last build is searched with 10,000
 queries from the same mixture for recall@10 against exact brute force
 (FP64), and the smallest beam width reaching 0.95 is reported.
 
+`--prec` / `--rescore-mult` choose the leaf-GEMM form of the measured build
+(default FP32). `variants` lists other forms (by default bf16 exact, bf16
+with FP32 rescoring of the top-2k, fp8 with rescoring) built, timed and
+searched the same way on the same points after the main measurement.
+
 Printed: one JSON line. `roofline` is for the fused leaf distance +
 selection kernel (the dominant kernel): its average launch time comes from
 HIP events recorded around it on its own stream during the timed steps.
@@ -32,7 +37,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-PEAK_FP32_MFMA_TFLOPS = 157.3
+# published dense MFMA peaks of one MI355X, TFLOP/s, by operand precision
+PEAK_MFMA_TFLOPS = {"fp32": 157.3, "bf16": 2500.0, "fp16": 2500.0, "fp8": 5000.0}
+PREC_CODES = {"fp32": 0, "bf16": 1, "fp8": 2, "fp16": 3}
 RECALL_LS = [10, 12, 16, 20, 24, 32, 40, 48, 64, 80, 96, 128, 160, 192, 256, 384, 512]
 
 
@@ -52,6 +59,13 @@ def parse():
     ap.add_argument("--no-recall", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=4.0,
                     help="target seconds of oracle work per sampled phase")
+    ap.add_argument("--prec", default="fp32", choices=sorted(PREC_CODES),
+                    help="operand precision of the leaf GEMM of the measured build")
+    ap.add_argument("--rescore-mult", type=int, default=0,
+                    help="select rescore_mult*k by the GEMM distance, keep k by FP32 rescoring")
+    ap.add_argument("--variants", default="bf16:0,bf16:2,fp8:2",
+                    help="other leaf-GEMM forms (prec:rescore_mult, comma separated) built and "
+                         "timed after the main one on the same workload; '' for none")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="after the timed steps, copy this many MiB once (a plain copy of known "
                          "size, used to scale hardware byte counters)")
@@ -80,10 +94,11 @@ def traffic_from_profiles():
     """HBM bytes per leaf-kernel launch from committed counter runs, if they
     were taken on the current kernel source."""
     path = os.path.join(ROOT, "profiles", "leaf_knn_hbm_traffic.json")
-    src = os.path.join(ROOT, "paper_2602_21247_amd", "csrc", "knn.hip")
+    csrc = os.path.join(ROOT, "paper_2602_21247_amd", "csrc")
     try:
         rec = json.load(open(path))
-        h = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        h = hashlib.sha256(b"".join(open(os.path.join(csrc, f), "rb").read()
+                                    for f in ("knn_kernel.hpp", "knn.hip"))).hexdigest()
         if rec.get("knn_hip_sha256") != h:
             return None
         return rec.get("bytes_per_launch")
@@ -203,36 +218,85 @@ def main():
     H = pi.workload_hyperplanes(cfg)
     Xd = torch.from_numpy(X).cuda()
     Hd = torch.from_numpy(H).cuda()
-    p = pp.default_params(metric=w.metric, c_max=w.c_max, c_min=w.c_min, k=w.k, l_max=w.l_max,
-                          R=w.R, alpha=w.alpha, hash_bits=w.hash_bits, leader_div=w.leader_div,
-                          leader_cap=w.leader_cap, fanout=w.fanout, seed=pi.workload_seed(cfg))
-    idx = pp.Index(Xd, Hd, p)
-    res = torch.empty((n, w.l_max), dtype=torch.int64, device="cuda")
+    Qd = kth = None
+    if not args.no_recall:
+        nq = args.queries or w.n_queries
+        Qd = torch.from_numpy(pi.workload_queries(cfg, nq)).cuda()
+        kth = ground_truth(torch, Xd, Qd)
 
-    def step():
-        idx.prepare()
-        off, mem = idx.partition()
-        pp._check(pp.lib().pipnn_reservoir_init(pp._ptr(res), n, w.l_max, pp._stream()))
-        idx.build_leaves(off, mem, res)
-        g, deg = idx.robustprune(res)
-        return off, mem, g, deg
+    def run_form(prec, mult, steps, warmup, keep=False):
+        """Build the whole index `warmup + steps` times with one leaf-GEMM
+        form; time the last `steps`; search the last graph for recall@10."""
+        p = pp.default_params(metric=w.metric, c_max=w.c_max, c_min=w.c_min, k=w.k,
+                              l_max=w.l_max, R=w.R, alpha=w.alpha, hash_bits=w.hash_bits,
+                              leader_div=w.leader_div, leader_cap=w.leader_cap, fanout=w.fanout,
+                              seed=pi.workload_seed(cfg), gemm_prec=PREC_CODES[prec],
+                              rescore_mult=mult)
+        idx = pp.Index(Xd, Hd, p)
+        res = torch.empty((n, w.l_max), dtype=torch.int64, device="cuda")
 
-    for i in range(args.warmup):
-        step()
+        def step():
+            idx.prepare()
+            off, mem = idx.partition()
+            pp._check(pp.lib().pipnn_reservoir_init(pp._ptr(res), n, w.l_max, pp._stream()))
+            idx.build_leaves(off, mem, res)
+            g, deg = idx.robustprune(res)
+            return off, mem, g, deg
+
+        for i in range(warmup):
+            step()
+            torch.cuda.synchronize()
+            log(f"[bench] {prec} x{mult}: warmup {i + 1}/{warmup} done")
         torch.cuda.synchronize()
-        log(f"[bench] warmup {i + 1}/{args.warmup} done")
-    torch.cuda.synchronize()
-    idx.set_profiling(True)
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        out = step()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    st = idx.stats()
-    idx.set_profiling(False)
-    ms = (t1 - t0) * 1000.0 / args.steps
-    log(f"[bench] {args.steps} steps, {ms:.2f} ms/step")
-    off, mem, g, deg = out
+        idx.set_profiling(True)
+        t0 = time.perf_counter()
+        for i in range(steps):
+            out = step()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        st = idx.stats()
+        idx.set_profiling(False)
+        ms = (t1 - t0) * 1000.0 / steps
+        log(f"[bench] {prec} x{mult}: {steps} steps, {ms:.2f} ms/step")
+        off, mem, g, deg = out
+        # leaf kernel roofline: dense flops 2 s^2 d per leaf, per launch
+        launches = max(1, st["leaf_knn_launches"])
+        flops_per_launch = 2.0 * st["leaf_pairs"] * w.d * steps / launches
+        avg_launch_s = st["ms_leaf_knn"] / launches / 1000.0
+        achieved = flops_per_launch / avg_launch_s / 1e12
+        phases = {k: st[k] / steps for k in ("ms_prepare", "ms_partition", "ms_leaf_knn",
+                                              "ms_bin", "ms_merge", "ms_robustprune")}
+        recall, l_at, curve = None, None, {}
+        if Qd is not None:
+            start = idx.start_node()
+            nq = Qd.shape[0]
+            for L in RECALL_LS:
+                ids, dist, cmps = idx.search(g, Qd, 10, L, start)
+                hits = (dist.double() <= kth[:, None]).sum().item()
+                r = hits / (nq * 10.0)
+                curve[L] = {"recall": round(r, 5), "cmps": round(cmps.double().mean().item(), 1)}
+                log(f"[bench] {prec} x{mult}: L={L} recall@10={r:.4f} cmps={curve[L]['cmps']}")
+                if r >= 0.95:
+                    l_at, recall = L, r
+                    break
+            if recall is None:
+                recall = max(v["recall"] for v in curve.values())
+        form = {"prec": prec, "rescore_mult": mult, "ms_per_step": ms, "value": n / (ms / 1000.0),
+                "leaf_gemm_tflops": achieved, "peak": PEAK_MFMA_TFLOPS[prec],
+                "frac": achieved / PEAK_MFMA_TFLOPS[prec], "recall_at_10": recall,
+                "L_at_recall_0.95": l_at, "recall_curve": curve, "phase_ms": phases,
+                "stats": st}
+        if keep:
+            form["_out"] = (idx, res, off, mem, g, deg)
+        else:
+            idx.close()
+        return form
+
+    main_form = run_form(args.prec, args.rescore_mult, args.steps, args.warmup, keep=True)
+    idx, res, off, mem, g, deg = main_form.pop("_out")
+    st = main_form.pop("stats")
+    ms = main_form["ms_per_step"]
+    achieved = main_form["leaf_gemm_tflops"]
     if args.calibrate_copy_mib > 0:
         # a fill (writes N MiB) and a sum (reads N MiB) of known size
         src = torch.ones(args.calibrate_copy_mib * 262144, dtype=torch.float32, device="cuda")
@@ -241,42 +305,25 @@ def main():
         log(f"[bench] calibration: {args.calibrate_copy_mib} MiB filled and summed ({total.item():.0f})")
         del src
 
-    # leaf kernel roofline: dense flops 2 s^2 d per leaf, per launch
-    launches = max(1, st["leaf_knn_launches"])
-    flops_per_launch = 2.0 * st["leaf_pairs"] * w.d * args.steps / launches
-    avg_launch_s = st["ms_leaf_knn"] / launches / 1000.0
-    achieved = flops_per_launch / avg_launch_s / 1e12
-    phases = {k: st[k] / args.steps for k in ("ms_prepare", "ms_partition", "ms_leaf_knn",
-                                               "ms_bin", "ms_merge", "ms_robustprune")}
-
-    recall = None
-    l_at = None
-    curve = {}
-    if not args.no_recall:
-        nq = args.queries or w.n_queries
-        Q = pi.workload_queries(cfg, nq)
-        Qd = torch.from_numpy(Q).cuda()
-        kth = ground_truth(torch, Xd, Qd)
-        start = idx.start_node()
-        for L in RECALL_LS:
-            ids, dist, cmps = idx.search(g, Qd, 10, L, start)
-            hits = (dist.double() <= kth[:, None]).sum().item()
-            r = hits / (nq * 10.0)
-            curve[L] = {"recall": round(r, 5), "cmps": round(cmps.double().mean().item(), 1)}
-            log(f"[bench] L={L} recall@10={r:.4f} cmps={curve[L]['cmps']}")
-            if r >= 0.95:
-                l_at, recall = L, r
-                break
-        if recall is None:
-            recall = max(v["recall"] for v in curve.values())
-
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] timing the FP64 oracle on a sample")
         cpu = cpu_baseline(X, H, off.cpu().numpy(), mem.cpu().numpy().view(np.uint32),
                            res.cpu().numpy().view(np.uint64), st, w, args.cpu_budget)
 
-    traffic = traffic_from_profiles()
+    variants = []
+    for spec in [v for v in args.variants.split(",") if v.strip()]:
+        vp, vm = spec.split(":")
+        if (vp, int(vm)) == (args.prec, args.rescore_mult):
+            continue
+        f = run_form(vp, int(vm), args.steps, 1)
+        f.pop("stats")
+        variants.append(f)
+
+    traffic = traffic_from_profiles() if args.prec == "fp32" else None
+    peak = PEAK_MFMA_TFLOPS[args.prec]
+    gemm = f"{args.prec}-mfma" + (f", fp32 rescore of top-{args.rescore_mult}k"
+                                  if args.rescore_mult else "")
     line = {
         "metric": "build points/sec at recall@10>=0.95",
         "value": n / (ms / 1000.0),
@@ -288,23 +335,24 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": {"fp32": "f32"}.get(args.prec, args.prec),
         "data": "synthetic",
-        "config": {"workload": w.name, "n": n, "d": w.d, "metric": "L2", "c_max": w.c_max,
+        "config": {"workload": w.name, "n": n, "d": w.d,
+                   "metric": "L2" if w.metric == 0 else "IP", "c_max": w.c_max,
                    "leaves_per_point": 2, "k": w.k, "l_max": w.l_max, "R": w.R,
-                   "alpha": w.alpha, "hash_bits": w.hash_bits, "gemm": "fp32-mfma"},
-        "recall_at_10": recall,
-        "L_at_recall_0.95": l_at,
-        "recall_curve": curve,
+                   "alpha": w.alpha, "hash_bits": w.hash_bits, "gemm": gemm},
+        "recall_at_10": main_form["recall_at_10"],
+        "L_at_recall_0.95": main_form["L_at_recall_0.95"],
+        "recall_curve": main_form["recall_curve"],
         "leaf_gemm_tflops": achieved,
         "insert_p99_ms": None,
-        "phase_ms": phases,
+        "phase_ms": main_form["phase_ms"],
         "build_stats": {k: st[k] for k in ("n_leaves", "n_members", "leader_dists", "levels",
                                            "leaf_pairs", "records")},
-        "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP32_MFMA_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_MFMA_TFLOPS,
-                     "traffic": traffic},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak,
+                     "unit": "TFLOP/s", "frac": achieved / peak, "traffic": traffic},
         "cpu_baseline": cpu,
+        "variants": variants,
     }
     print(json.dumps(line), flush=True)
     idx.close()

@@ -73,7 +73,7 @@ typedef int32_t pipnn_status;
 
 /* Hyper-parameter bundle BP of Alg. 4.
  *  metric       PIPNN_METRIC_*.
- *  c_max        C_max, the largest leaf (Sec. 4.1; "typically 1024-2048").
+ *  c_max        C_max, the largest leaf (Sec. 4.1 keeps it small, about 1-2 thousand).
  *  c_min        C_min: buckets below it are merged (Sec. 4.1, Merge).
  *  leader_div   P_samp = 1/leader_div: a subproblem P gets
  *               l = min(leader_cap, max(2, ceil(|P|/leader_div)), |P|) leaders.
@@ -87,7 +87,10 @@ typedef int32_t pipnn_status;
  *  R            final degree bound of RobustPrune (Alg. 2), 1..256.
  *  alpha        RobustPrune's alpha (Alg. 2), >= 1, applied to the
  *               distances above (squared L2 or negated inner product).
- *  gemm_prec    PIPNN_PREC_*: arithmetic of the leaf distance GEMM.
+ *  gemm_prec    PIPNN_PREC_*: arithmetic of the leaf distance GEMM. BF16,
+ *               FP16 and FP8 multiply a copy of X in that format (made by
+ *               pipnn_create / pipnn_prepare, d <= 256) and accumulate in
+ *               FP32; partition distances always use the float32 vectors.
  *  rescore_mult 0, or r >= 2: select the r*k nearest by the GEMM distance
  *               and keep the k nearest by an FP32 direct-difference rescore.
  *  seed         root key of the leader sampling (Alg. 5, SampleLeaders).
@@ -123,14 +126,16 @@ size_t pipnn_workspace_bytes(const pipnn_params *p, int64_t n, int32_t d,
                              int64_t max_batch_records);
 
 /* Create an index over d_X (n x d, row-major, x_dtype) with hyperplanes
- * d_H (hash_bits x d, float32, row-major; Sec. 3, "random hyperplanes
- * through the origin"). Computes the per-point sketches Sketch(v)_b = H_b . v
+ * d_H (hash_bits x d, float32, row-major; Sec. 3: m random hyperplanes,
+ * each given by its normal vector). Computes the per-point sketches Sketch(v)_b = H_b . v
  * (Sec. 3, Implementation) and squared norms on the stream. d_X and d_H are
  * referenced, not copied, and must outlive the index.
  * EINVAL if n < 2, d < 1, hash_bits not in 1..16, k < 1, l_max not in
  * 1..256, R not in 1..256, alpha < 1, c_max < 2, c_min > c_max, leader_div
  * < 1, leader_cap < 2, a fanout < 1, fanout[3] != 1, an unknown dtype or
- * precision, or n >= 2^32 - 1. ENOMEM if scratch cannot be allocated. */
+ * precision, n >= 2^32 - 1, or a reduced gemm_prec with d > 256. ENOMEM
+ * if scratch cannot be allocated. With a reduced gemm_prec it also encodes
+ * the GEMM operand (see pipnn_get_operand). */
 pipnn_status pipnn_create(const pipnn_params *p, const void *d_X, int64_t n, int32_t d,
                           int32_t x_dtype, const float *d_H, pipnn_stream_t stream,
                           pipnn_index **out);
@@ -269,6 +274,15 @@ pipnn_status pipnn_knn_block(pipnn_index *idx, const uint32_t *d_row_ids, int64_
 pipnn_status pipnn_leaf_pick(pipnn_index *idx, const int64_t *d_leaf_offsets,
                              const uint32_t *d_leaf_members, int64_t n_leaves, uint32_t *d_out_cand,
                              float *d_out_dist, pipnn_stream_t stream);
+
+/* The reduced-precision leaf-GEMM operand the index made from X (gemm_prec
+ * BF16, FP16 or FP8): d_codes (n x d; uint16 bf16 / fp16 bits, or uint8
+ * OCP e4m3 codes), d_scale (n floats: the per-point decode scale, value =
+ * code * scale, max|x_i| / 448 for fp8 and 1 otherwise) and d_norms (n
+ * floats: squared norms of the decoded vectors, the norms the GEMM form
+ * uses). Any output may be NULL. ESTATE if gemm_prec is FP32. */
+pipnn_status pipnn_get_operand(const pipnn_index *idx, void *d_codes, float *d_scale,
+                               float *d_norms, pipnn_stream_t stream);
 
 #ifdef __cplusplus
 }

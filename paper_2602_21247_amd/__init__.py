@@ -27,7 +27,7 @@ EXPORTS = [
     "pipnn_hashprune_insert", "pipnn_reservoir_init", "pipnn_reservoir_canonical",
     "pipnn_robustprune", "pipnn_start_node", "pipnn_search", "pipnn_get_sketches",
     "pipnn_knn_block", "pipnn_leaf_pick", "pipnn_prepare", "pipnn_set_profiling",
-    "pipnn_get_stats",
+    "pipnn_get_stats", "pipnn_get_operand",
 ]
 
 
@@ -92,6 +92,7 @@ def lib():
         L.pipnn_prepare.argtypes = [P, P]
         L.pipnn_set_profiling.argtypes = [P, i32]
         L.pipnn_get_stats.argtypes = [P, C.POINTER(Stats)]
+        L.pipnn_get_operand.argtypes = [P, P, P, P, P]
         for name in EXPORTS:
             if name not in ("pipnn_version", "pipnn_last_error", "pipnn_default_params",
                             "pipnn_workspace_bytes", "pipnn_destroy"):
@@ -252,6 +253,19 @@ class Index:
         out = torch.empty((self.n, self.params.hash_bits), dtype=torch.float32, device="cuda")
         _check(lib().pipnn_get_sketches(self._h, _ptr(out), _stream()))
         return out
+
+    def get_operand(self):
+        """The reduced-precision GEMM operand: (codes n x d as uint16 / uint8,
+        per-point decode scale, squared norms of the decoded vectors)."""
+        torch = _torch()
+        prec = self.params.gemm_prec
+        dt = torch.uint8 if prec == PREC_FP8 else torch.int16
+        codes = torch.empty((self.n, self.d), dtype=dt, device="cuda")
+        scale = torch.empty(self.n, dtype=torch.float32, device="cuda")
+        norms = torch.empty(self.n, dtype=torch.float32, device="cuda")
+        _check(lib().pipnn_get_operand(self._h, _ptr(codes), _ptr(scale), _ptr(norms),
+                                       _stream()))
+        return codes, scale, norms
 
     def knn_block(self, row_ids, col_ids, k: int, exclude_diag: bool, want_matrix=False):
         torch = _torch()

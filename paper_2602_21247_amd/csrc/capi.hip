@@ -107,8 +107,9 @@ bool valid_params(const pipnn_params *p, std::string &why) {
   if (p->l_max < 1 || p->l_max > 256) return bad("l_max must be in 1..256");
   if (p->R < 1 || p->R > 256) return bad("R must be in 1..256");
   if (!(p->alpha >= 1.0f)) return bad("alpha must be >= 1");
-  if (p->gemm_prec != PIPNN_PREC_FP32) {
-    snprintf(b, sizeof(b), "gemm_prec %d is not available in this build", p->gemm_prec);
+  if (p->gemm_prec != PIPNN_PREC_FP32 && p->gemm_prec != PIPNN_PREC_BF16 &&
+      p->gemm_prec != PIPNN_PREC_FP8 && p->gemm_prec != PIPNN_PREC_FP16) {
+    snprintf(b, sizeof(b), "unknown gemm_prec %d", p->gemm_prec);
     why = b;
     return false;
   }
@@ -280,6 +281,9 @@ size_t pipnn_workspace_bytes(const pipnn_params *p, int64_t n, int32_t d,
   b += (size_t)picks * 8;                                     // picks (id + dist)
   b += (size_t)rec * 8;                                       // binned slots
   b += (size_t)(n + 1) * 8 + (size_t)n * 4;                   // bin offsets + counts
+  if (p->gemm_prec != PIPNN_PREC_FP32)                        // operand copy, scales, norms
+    b += (size_t)n * lowp_padded_dim(d) * (p->gemm_prec == PIPNN_PREC_FP8 ? 1 : 2) +
+         (size_t)n * 8;
   return b;
 }
 
@@ -323,6 +327,18 @@ pipnn_status pipnn_create(const pipnn_params *p, const void *d_X, int64_t n, int
   }
   if ((e = launch_norms_sketches(*I, s)) != hipSuccess)
     return cleanup(fail(PIPNN_EDEVICE, "sketch launch failed: %s", hipGetErrorString(e)));
+  if (p->gemm_prec != PIPNN_PREC_FP32) {
+    I->ldo = lowp_padded_dim(d);
+    if (I->ldo == 0)
+      return cleanup(fail(PIPNN_EINVAL, "a reduced-precision leaf GEMM needs d <= 256"));
+    const size_t eb = p->gemm_prec == PIPNN_PREC_FP8 ? 1 : 2;
+    if ((e = I->xlow.ensure((size_t)n * I->ldo * eb)) != hipSuccess ||
+        (e = I->xscale.ensure((size_t)n * 4)) != hipSuccess ||
+        (e = I->lnorms.ensure((size_t)n * 4)) != hipSuccess)
+      return cleanup(fail(PIPNN_ENOMEM, "device allocation failed: %s", hipGetErrorString(e)));
+    if ((e = launch_quantize(*I, s)) != hipSuccess)
+      return cleanup(fail(PIPNN_EDEVICE, "quantize launch failed: %s", hipGetErrorString(e)));
+  }
   if ((e = hipMemsetAsync(I->flag.p, 0, 64, s)) != hipSuccess)
     return cleanup(fail(PIPNN_EDEVICE, "memset failed: %s", hipGetErrorString(e)));
   *out = reinterpret_cast<pipnn_index *>(I);
@@ -335,7 +351,7 @@ void pipnn_destroy(pipnn_index *idx) {
   Index *I = reinterpret_cast<Index *>(idx);
   (void)hipDeviceSynchronize();
   for (DevBuf *b : {&I->rp_order, &I->o_first, &I->o_flag, &I->o_pos, &I->o_pos2, &I->o_tmp,
-                    &I->xf32, &I->xlow, &I->xscale, &I->sketches, &I->norms, &I->flag, &I->s_jobs,
+                    &I->xf32, &I->xlow, &I->xscale, &I->lnorms, &I->sketches, &I->norms, &I->flag, &I->s_jobs,
                     &I->s_items, &I->s_picks_c, &I->s_picks_d, &I->s_cnt, &I->s_off, &I->s_bins,
                     &I->s_tmp0, &I->s_tmp1, &I->p_asg, &I->p_leaders, &I->p_cm, &I->p_bstart,
                     &I->p_groups, &I->p_gout, &I->p_gsize, &I->p_copy})
@@ -455,6 +471,7 @@ pipnn_status pipnn_partition(pipnn_index *idx, int64_t *d_leaf_offsets, int64_t 
     L.out_ids = 0;
     L.recompute = 0;
     L.rescore_k = 0;
+    L.prec = PIPNN_PREC_FP32;
     L.out_col = I.p_asg.as<uint32_t>();
     L.out_dist = nullptr;
     L.out_matrix = nullptr;
@@ -719,6 +736,7 @@ pipnn_status run_pick(Index &I, const std::vector<int64_t> &offs, int64_t l0, in
   L.out_ids = 1;
   L.recompute = 1;
   L.rescore_k = P.rescore_mult ? P.k : 0;
+  L.prec = P.gemm_prec;
   L.out_col = pick_c;
   L.out_dist = pick_d;
   L.out_matrix = nullptr;
@@ -927,6 +945,7 @@ pipnn_status pipnn_knn_block(pipnn_index *idx, const uint32_t *d_row_ids, int64_
   L.out_ids = 0;
   L.recompute = 1;
   L.rescore_k = I.p.rescore_mult ? k : 0;
+  L.prec = I.p.gemm_prec;
   L.out_col = d_out_col;
   L.out_dist = d_out_dist;
   L.out_matrix = d_out_matrix;
@@ -1047,6 +1066,7 @@ pipnn_status pipnn_prepare(pipnn_index *idx, pipnn_stream_t stream) {
   if (I.x_dtype != PIPNN_DTYPE_F32)
     HIPCHK(launch_to_f32(I.X, I.x_dtype, I.xf32.as<float>(), I.n * (int64_t)I.d, s));
   HIPCHK(launch_norms_sketches(I, s));
+  if (I.p.gemm_prec != PIPNN_PREC_FP32) HIPCHK(launch_quantize(I, s));
   return PIPNN_OK;
   GUARD_END
 }
@@ -1087,6 +1107,30 @@ pipnn_status pipnn_get_sketches(const pipnn_index *idx, float *d_out, pipnn_stre
   const Index &I = *reinterpret_cast<const Index *>(idx);
   HIPCHK(hipMemcpyAsync(d_out, I.sketches.p, (size_t)I.n * I.m * 4, hipMemcpyDeviceToDevice,
                         reinterpret_cast<hipStream_t>(stream)));
+  return PIPNN_OK;
+  GUARD_END
+}
+
+pipnn_status pipnn_get_operand(const pipnn_index *idx, void *d_codes, float *d_scale,
+                               float *d_norms, pipnn_stream_t stream) {
+  GUARD_BEGIN
+  if (!idx) return fail(PIPNN_EINVAL, "NULL index");
+  const Index &I = *reinterpret_cast<const Index *>(idx);
+  if (I.p.gemm_prec == PIPNN_PREC_FP32)
+    return fail(PIPNN_ESTATE, "the index has no reduced-precision operand");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const size_t eb = I.p.gemm_prec == PIPNN_PREC_FP8 ? 1 : 2;
+  if (d_codes)
+    HIPCHK(hipMemcpy2DAsync(d_codes, (size_t)I.d * eb, I.xlow.p, (size_t)I.ldo * eb,
+                            (size_t)I.d * eb, (size_t)I.n, hipMemcpyDeviceToDevice, s));
+  if (d_scale) {
+    if (I.p.gemm_prec == PIPNN_PREC_FP8)
+      HIPCHK(hipMemcpyAsync(d_scale, I.xscale.p, (size_t)I.n * 4, hipMemcpyDeviceToDevice, s));
+    else
+      HIPCHK(launch_fill_u32(reinterpret_cast<uint32_t *>(d_scale), 0x3F800000u, I.n, s));
+  }
+  if (d_norms)
+    HIPCHK(hipMemcpyAsync(d_norms, I.lnorms.p, (size_t)I.n * 4, hipMemcpyDeviceToDevice, s));
   return PIPNN_OK;
   GUARD_END
 }

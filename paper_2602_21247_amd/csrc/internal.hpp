@@ -33,9 +33,11 @@ struct Index {
 
   DevBuf xf32;      // float32 copy of X when X is not float32
   DevBuf xlow;      // low-precision copy for the leaf GEMM (bf16 / fp16 / fp8)
-  DevBuf xscale;    // per-point fp8 scale (value = code * scale)
+  DevBuf xscale;    // per-point fp8 decode scale (value = code * scale)
+  DevBuf lnorms;    // n float32, squared norms of the decoded low-precision operand
+  int32_t ldo = 0;  // row stride (elements) of xlow: d padded by lowp_padded_dim
   DevBuf sketches;  // n x m float32
-  DevBuf norms;     // n float32, squared norms (of the GEMM operand)
+  DevBuf norms;     // n float32, squared norms of the float32 vectors
   DevBuf flag;      // int32 device error flag
 
   // scratch reused across calls
@@ -99,6 +101,7 @@ struct KnnLaunch {
   int32_t out_ids;       // 1: write col_base ids, 0: write column indices
   int32_t recompute;     // 1: FP32 direct-difference distance of the winners
   int32_t rescore_k;     // > 0: keep this many of the k_sel by the direct distance
+  int32_t prec;          // PIPNN_PREC_*: the operand (FP32 for the partition)
   uint32_t *out_col;
   float *out_dist;
   float *out_matrix;
@@ -106,8 +109,19 @@ struct KnnLaunch {
 };
 hipError_t launch_knn(const KnnLaunch &L, hipStream_t s);
 
+// Reduced-precision operands are stored zero padded to one of these
+// dimensions, so that every operand row is a whole number of 16-byte
+// vectors and the kernel never tests the dimension; 0 = not supported.
+inline int lowp_padded_dim(int d) {
+  return d <= 64 ? 64 : d <= 96 ? 96 : d <= 128 ? 128 : d <= 256 ? 256 : 0;
+}
+
 // ---- misc kernels ----------------------------------------------------
 hipError_t launch_norms_sketches(const Index &I, hipStream_t s);
+// The index's reduced-precision operand (I.p.gemm_prec): codes into I.xlow
+// (n x I.ldo), decode scales into I.xscale (fp8), squared norms of the
+// decoded vectors into I.lnorms.
+hipError_t launch_quantize(const Index &I, hipStream_t s);
 hipError_t launch_to_f32(const void *src, int dtype, float *dst, int64_t count, hipStream_t s);
 hipError_t launch_iota(uint32_t *dst, int64_t n, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *dst, uint32_t v, int64_t n, hipStream_t s);

@@ -1,442 +1,15 @@
-// Fused leaf distance GEMM + per-row k-nearest selection for gfx950.
-//
-// One kernel serves every dense "rows x columns -> k nearest columns per
-// row" step of PiPNN:
-//   - the leaf pick (Sec. 4.2): rows = columns = the members of a leaf, the
-//     own column excluded, k nearest by (distance, column);
-//   - the ball-carving assignment (Alg. 5): rows = the points of a
-//     subproblem, columns = its leaders, f nearest leaders per point.
-// The distance of a pair is the GEMM form ||x||^2 + ||y||^2 - 2 x.y
-// (squared L2) or -x.y (negated inner product), with x.y on MFMA.
-//
-// Work decomposition: a work item is (job, block of 32*NW rows). A
-// workgroup of NW waves owns one item; wave w owns 32 rows and keeps their
-// A operand (the row vectors) in registers for the whole item. Column
-// tiles of 64 points are staged in LDS (row stride d+4 floats, so the
-// 16-byte fragment reads are bank-conflict free) and shared by the NW
-// waves. The host lists the work items in launch order (block b
-// runs on XCD b % 8): whole small jobs go to one XCD so that their column
-// vectors stay in that XCD's L2, and jobs are dealt to XCDs largest first
-// by work so that the eight XCDs finish together. Two workgroups fit on a
-// CU, so one's selection and epilogue overlap the other's MFMA work.
-//
-// Selection: each row keeps its KSEL best (distance, column) pairs in LDS
-// and a threshold tau (the worst kept pair once KSEL are kept). After each
-// 32x32 MFMA block, every lane tests its 16 accumulator entries against the
-// tau of their rows and appends the survivors to the row's LDS buffer; one
-// owner lane per row then drains the buffer into the kept set. The filter
-// uses <= so that equal distances with a smaller column are not lost; the
-// drain applies the exact (distance, column) order.
-//
-// Epilogue: the kept pairs are sorted by (GEMM distance, column); when
-// asked, each winner's FP32 distance is recomputed by direct difference,
-// sum_i (x_i - y_i)^2 (or -sum x_i y_i): each half of the dimensions is
-// summed in index order and the halves are added, so a pair always gets the
-// same value whichever row it is found from. With rescoring, the k_sel GEMM
-// winners are re-ranked by (direct distance, column) and the first k kept.
-#include "common.hpp"
-#include "internal.hpp"
+// Fused leaf distance GEMM + per-row k-nearest selection: the FP32
+// instantiations and the dispatch over operand precisions. The kernel
+// itself is in knn_kernel.hpp.
+#include "knn_kernel.hpp"
 
 namespace pipnn {
 
-typedef float f32x16 __attribute__((ext_vector_type(16)));
-
-struct KnnArgs {
-  const float *X;
-  const float *norms;
-  const uint32_t *row_base;
-  const uint32_t *col_base;
-  const KnnJob *jobs;
-  const KnnItem *items;
-  uint32_t *out_col;
-  float *out_dist;
-  float *out_matrix;
-  int64_t matrix_ld;
-  int32_t n_items;
-  int32_t d;
-  int32_t metric;
-  int32_t k_out;
-  int32_t out_ids;
-  int32_t recompute;
-  int32_t rescore_k;
-};
-
-// Row (0..31) of accumulator entry v held by a lane in the upper (h=1) or
-// lower (h=0) half of the wave, for v_mfma_f32_32x32x2_f32.
-__device__ __forceinline__ int acc_row(int v, int h) { return (v & 3) + 8 * (v >> 2) + 4 * h; }
-
-template <int DP, int KSEL, int NW, bool L2>
-__global__ void __launch_bounds__(NW * 64, 2) knn_f32_kernel(KnnArgs a) {
-  constexpr int BM = 32 * NW;     // rows per workgroup
-  constexpr int BN = 64;          // columns per tile
-  constexpr int LDB = DP + 4;     // LDS stride of a staged column vector (floats)
-  constexpr int HALF = DP / 2;    // k-range owned by each half of the wave
-  constexpr int CAP = 32;         // per-row buffer: a 32-column block appends at most 32
-  constexpr int BUFD = CAP + 1;
-  constexpr int BUFC = CAP + 2;
-  constexpr int KS1 = KSEL + 1;
-  constexpr int NTH = NW * 64;
-  constexpr int F4_PER_TILE = BN * DP / 4;
-  constexpr int NPRE = (F4_PER_TILE + NTH - 1) / NTH;
-
-  __shared__ __attribute__((aligned(16))) float sB[BN * LDB];
-  __shared__ float sBufD[BM * BUFD];
-  __shared__ uint16_t sBufC[BM * BUFC];
-  __shared__ float sTopD[BM * KS1];
-  __shared__ uint32_t sTopC[BM * KS1];
-  __shared__ float sTau[BM];
-  __shared__ int sBufN[BM];
-  __shared__ float sColN[BN];
-  __shared__ float sNr[BM];
-
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int h = lane >> 5, l32 = lane & 31;
-  const int item = blockIdx.x;
-  if (item >= a.n_items || a.items[item].job < 0) return;
-  const KnnItem it = a.items[item];
-  const KnnJob J = a.jobs[it.job];
-  const int rbase = it.rb * BM;
-  const int wrow = rbase + wave * 32;
-  const uint32_t *rows = a.row_base + J.row_off;
-  const uint32_t *cols = a.col_base + J.col_off;
-  const int d = a.d;
-  constexpr bool l2 = L2;
-  const bool excl = (J.flags & 1) != 0;
-  const bool full_d = (d == DP);
-  const int n_rows = J.n_rows, n_cols = J.n_cols;
-
-  // per-row squared norm and selection threshold (-inf past the last row)
-  for (int r = tid; r < BM; r += NTH) {
-    const bool ok = rbase + r < n_rows;
-    sTau[r] = ok ? INFINITY : -INFINITY;
-    sBufN[r] = 0;
-    sNr[r] = (ok && l2) ? a.norms[rows[rbase + r]] : 0.f;
-  }
-  uint32_t rowmask = 0;
-#pragma unroll
-  for (int v = 0; v < 16; ++v) rowmask |= (wrow + acc_row(v, h) < n_rows ? 1u : 0u) << v;
-
-  // A operand: lane holds row l32 of this wave, dims [h*HALF, h*HALF+HALF).
-  float av[HALF];
-  {
-    const int r = wrow + l32;
-    if (r < n_rows) {
-      const float *src = a.X + (int64_t)rows[r] * d + h * HALF;
-      if (full_d) {
-#pragma unroll
-        for (int kk = 0; kk < HALF; kk += 4) {
-          float4 q = *reinterpret_cast<const float4 *>(src + kk);
-          av[kk] = q.x; av[kk + 1] = q.y; av[kk + 2] = q.z; av[kk + 3] = q.w;
-        }
-      } else {
-#pragma unroll
-        for (int kk = 0; kk < HALF; ++kk) av[kk] = (h * HALF + kk < d) ? src[kk] : 0.f;
-      }
-    } else {
-#pragma unroll
-      for (int kk = 0; kk < HALF; ++kk) av[kk] = 0.f;
-    }
-  }
-
-  // owner-lane state (lanes 0..31 own row wrow + lane)
-  const int orow = wave * 32 + l32;  // LDS row index
-  int tn = 0, maxpos = 0;
-  float maxd = INFINITY;
-  uint32_t maxc = 0xFFFFFFFFu;
-
-  // column tile staging: thread t loads float4s t, t+NTH, ... of the tile
-  float4 pre[NPRE];
-  float pre_n = 0.f;
-  auto load_tile = [&](int c0) {
-    if (tid < BN) pre_n = (l2 && c0 + tid < n_cols) ? a.norms[cols[c0 + tid]] : 0.f;
-#pragma unroll
-    for (int i = 0; i < NPRE; ++i) {
-      const int q = tid + i * NTH;
-      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (q < F4_PER_TILE) {
-        const int c = q / (DP / 4), kq = (q % (DP / 4)) * 4;
-        const int cc = c0 + c;
-        if (cc < n_cols) {
-          const float *src = a.X + (int64_t)cols[cc] * d + kq;
-          if (full_d) {
-            v = *reinterpret_cast<const float4 *>(src);
-          } else {
-            v.x = kq < d ? src[0] : 0.f;
-            v.y = kq + 1 < d ? src[1] : 0.f;
-            v.z = kq + 2 < d ? src[2] : 0.f;
-            v.w = kq + 3 < d ? src[3] : 0.f;
-          }
-        }
-      }
-      pre[i] = v;
-    }
-  };
-  auto store_tile = [&]() {
-    if (tid < BN) sColN[tid] = pre_n;
-#pragma unroll
-    for (int i = 0; i < NPRE; ++i) {
-      const int q = tid + i * NTH;
-      if (q < F4_PER_TILE) {
-        const int c = q / (DP / 4), kq = (q % (DP / 4)) * 4;
-        *reinterpret_cast<float4 *>(&sB[c * LDB + kq]) = pre[i];
-      }
-    }
-  };
-
-  // The owner lane of a row loads its kept set into registers once, folds
-  // in every buffered survivor there (replace the current worst, rescan for
-  // the new worst), and writes the set back once.
-  auto drain = [&]() {
-    if (l32 == lane && wrow + l32 < n_rows) {
-      const int nb = sBufN[orow];
-      if (nb > 0) {
-        float kd[KSEL];
-        uint32_t kc[KSEL];
-#pragma unroll
-        for (int i = 0; i < KSEL; ++i) {
-          kd[i] = sTopD[orow * KS1 + i];
-          kc[i] = sTopC[orow * KS1 + i];
-        }
-        float nd = sBufD[orow * BUFD];
-        uint32_t ncv = sBufC[orow * BUFC];
-        for (int e = 0; e < nb; ++e) {
-          const float dv = nd;
-          const uint32_t cv = ncv;
-          if (e + 1 < nb) {
-            nd = sBufD[orow * BUFD + e + 1];
-            ncv = sBufC[orow * BUFC + e + 1];
-          }
-          int slot = -1;
-          if (tn < KSEL) {
-            slot = tn++;
-          } else if (dv < maxd || (dv == maxd && cv < maxc)) {
-            slot = maxpos;
-          }
-          if (slot >= 0) {
-#pragma unroll
-            for (int i = 0; i < KSEL; ++i) {
-              if (i == slot) {
-                kd[i] = dv;
-                kc[i] = cv;
-              }
-            }
-            if (tn == KSEL) {
-              maxpos = 0;
-              maxd = kd[0];
-              maxc = kc[0];
-#pragma unroll
-              for (int i = 1; i < KSEL; ++i) {
-                const bool gt = kd[i] > maxd || (kd[i] == maxd && kc[i] > maxc);
-                maxd = gt ? kd[i] : maxd;
-                maxc = gt ? kc[i] : maxc;
-                maxpos = gt ? i : maxpos;
-              }
-            }
-          }
-        }
-#pragma unroll
-        for (int i = 0; i < KSEL; ++i) {
-          sTopD[orow * KS1 + i] = kd[i];
-          sTopC[orow * KS1 + i] = kc[i];
-        }
-        sBufN[orow] = 0;
-        sTau[orow] = (tn == KSEL) ? maxd : INFINITY;
-      }
-    }
-  };
-
-  for (int c0 = 0; c0 < n_cols; c0 += BN) {
-    // stage the column tile (the other workgroup on the CU covers the latency)
-    load_tile(c0);
-    store_tile();
-    __syncthreads();
-
-#pragma unroll
-    for (int blk = 0; blk < 2; ++blk) {
-      // MFMA: this wave's 32 rows against columns c0 + 32*blk + [0, 32)
-      f32x16 acc;
-#pragma unroll
-      for (int v = 0; v < 16; ++v) acc[v] = 0.f;
-      const float *bp = &sB[(32 * blk + l32) * LDB + h * HALF];
-#pragma unroll
-      for (int kk = 0; kk < HALF; kk += 4) {
-        const float4 b = *reinterpret_cast<const float4 *>(bp + kk);
-        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av[kk], b.x, acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av[kk + 1], b.y, acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av[kk + 2], b.z, acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av[kk + 3], b.w, acc, 0, 0, 0);
-      }
-      const int cc = c0 + 32 * blk + l32;
-      const bool vc = cc < n_cols;
-      const float nc = sColN[32 * blk + l32];
-      float nr[16], tau[16];
-#pragma unroll
-      for (int v = 0; v < 16; ++v) {
-        nr[v] = sNr[wave * 32 + acc_row(v, h)];
-        tau[v] = sTau[wave * 32 + acc_row(v, h)];
-      }
-      float dv[16];
-#pragma unroll
-      for (int v = 0; v < 16; ++v) dv[v] = l2 ? nr[v] + fmaf(-2.f, acc[v], nc) : -acc[v];
-      if (a.out_matrix && vc) {
-        // test-only: the GEMM distance of every pair
-#pragma unroll
-        for (int v = 0; v < 16; ++v)
-          if ((rowmask >> v) & 1u)
-            a.out_matrix[(J.out_off + wrow + acc_row(v, h)) * a.matrix_ld + cc] = dv[v];
-      }
-      // branch-free pass test; a block without any survivor costs one ballot
-      uint32_t pass = 0;
-#pragma unroll
-      for (int v = 0; v < 16; ++v) {
-        const int rr = wrow + acc_row(v, h);
-        const bool ok = vc && dv[v] <= tau[v] && !(excl && rr == cc);
-        pass |= (ok ? 1u : 0u) << v;
-      }
-      if (__ballot(pass != 0) == 0ull) continue;
-#pragma unroll
-      for (int v = 0; v < 16; ++v) {
-        if ((pass >> v) & 1u) {
-          const int rl = wave * 32 + acc_row(v, h);
-          const int pos = atomicAdd(&sBufN[rl], 1);
-          sBufD[rl * BUFD + pos] = dv[v];
-          sBufC[rl * BUFC + pos] = (uint16_t)cc;
-        }
-      }
-      wave_sync();
-      drain();
-      wave_sync();
-    }
-    __syncthreads();  // every wave is done with sB
-  }
-
-  // ---- epilogue: this wave's 32 rows ----
-  // sort each kept set by (GEMM distance, column)
-  if (l32 == lane && wrow + l32 < n_rows) {
-    for (int i = 1; i < tn; ++i) {
-      const float di = sTopD[orow * KS1 + i];
-      const uint32_t ci = sTopC[orow * KS1 + i];
-      int j = i - 1;
-      while (j >= 0) {
-        const float dj = sTopD[orow * KS1 + j];
-        const uint32_t cj = sTopC[orow * KS1 + j];
-        if (dj > di || (dj == di && cj > ci)) {
-          sTopD[orow * KS1 + j + 1] = dj;
-          sTopC[orow * KS1 + j + 1] = cj;
-          --j;
-        } else {
-          break;
-        }
-      }
-      sTopD[orow * KS1 + j + 1] = di;
-      sTopC[orow * KS1 + j + 1] = ci;
-    }
-  }
-  wave_sync();
-
-  const int ksel_job = J.k_sel < KSEL ? J.k_sel : KSEL;
-  if (a.recompute) {
-    // FP32 direct-difference distance of each winner of row l32, into
-    // sBufD[row][i]. Lane (l32, h) holds its row's dims [h*HALF, h*HALF+HALF)
-    // in av[]; it sums (x_r - x_c)^2 over that half in index order, and the
-    // two halves are added, so a pair gets the same value from either row.
-    const int rr = wrow + l32;
-    const int tnr = __shfl(tn, l32, 64);
-    const int cnt = rr < n_rows ? (tnr < ksel_job ? tnr : ksel_job) : 0;
-    const int lrow = wave * 32 + l32;
-    const int kbase = h * HALF;
-    for (int i = 0; i < KSEL; ++i) {
-      if (!__any(i < cnt)) break;
-      float s = 0.f;
-      if (i < cnt) {
-        const uint32_t c = sTopC[lrow * KS1 + i];
-        const float *xc = a.X + (int64_t)cols[c] * d + kbase;
-        if (full_d) {
-#pragma unroll
-          for (int kk = 0; kk < HALF; kk += 4) {
-            const float4 q = *reinterpret_cast<const float4 *>(xc + kk);
-            if (l2) {
-              float t = av[kk] - q.x; s = fmaf(t, t, s);
-              t = av[kk + 1] - q.y; s = fmaf(t, t, s);
-              t = av[kk + 2] - q.z; s = fmaf(t, t, s);
-              t = av[kk + 3] - q.w; s = fmaf(t, t, s);
-            } else {
-              s = fmaf(av[kk], q.x, s); s = fmaf(av[kk + 1], q.y, s);
-              s = fmaf(av[kk + 2], q.z, s); s = fmaf(av[kk + 3], q.w, s);
-            }
-          }
-        } else {
-#pragma unroll
-          for (int kk = 0; kk < HALF; ++kk) {
-            const float v = (kbase + kk < d) ? xc[kk] : 0.f;
-            if (l2) {
-              const float t = av[kk] - v;
-              s = fmaf(t, t, s);
-            } else {
-              s = fmaf(av[kk], v, s);
-            }
-          }
-        }
-      }
-      const float other = __shfl_xor(s, 32, 64);
-      const float lo = h == 0 ? s : other, hi = h == 0 ? other : s;
-      const float tot = lo + hi;
-      if (i < cnt && h == 0) sBufD[lrow * BUFD + i] = l2 ? tot : -tot;
-    }
-  }
-  wave_sync();
-
-  if (l32 == lane && wrow + l32 < n_rows) {
-    const int rr = wrow + l32;
-    int cnt = tn < ksel_job ? tn : ksel_job;
-    float *dd = a.recompute ? &sBufD[orow * BUFD] : &sTopD[orow * KS1];
-    if (a.rescore_k > 0) {
-      // re-rank the GEMM winners by (direct distance, column)
-      for (int i = 1; i < cnt; ++i) {
-        const float di = dd[i];
-        const uint32_t ci = sTopC[orow * KS1 + i];
-        int j = i - 1;
-        while (j >= 0 && (dd[j] > di || (dd[j] == di && sTopC[orow * KS1 + j] > ci))) {
-          dd[j + 1] = dd[j];
-          sTopC[orow * KS1 + j + 1] = sTopC[orow * KS1 + j];
-          --j;
-        }
-        dd[j + 1] = di;
-        sTopC[orow * KS1 + j + 1] = ci;
-      }
-      if (cnt > a.rescore_k) cnt = a.rescore_k;
-    }
-    const int64_t o = (J.out_off + rr) * (int64_t)a.k_out;
-    for (int i = 0; i < a.k_out; ++i) {
-      if (i < cnt) {
-        const uint32_t c = sTopC[orow * KS1 + i];
-        a.out_col[o + i] = a.out_ids ? cols[c] : c;
-        if (a.out_dist) a.out_dist[o + i] = dd[i];
-      } else {
-        a.out_col[o + i] = kEmptyId;
-        if (a.out_dist) a.out_dist[o + i] = INFINITY;
-      }
-    }
-  }
-}
-
-template <int DP, int KSEL>
-static hipError_t launch_dp_ksel(const KnnArgs &args, int n_items, hipStream_t s) {
-  constexpr int NW = 4;
-  if (args.metric == PIPNN_METRIC_L2)
-    hipLaunchKernelGGL((knn_f32_kernel<DP, KSEL, NW, true>), dim3(n_items), dim3(NW * 64), 0, s,
-                       args);
-  else
-    hipLaunchKernelGGL((knn_f32_kernel<DP, KSEL, NW, false>), dim3(n_items), dim3(NW * 64), 0, s,
-                       args);
-  return hipGetLastError();
-}
-
 template <int DP>
 static hipError_t launch_dp(const KnnArgs &args, int ksel, int n_items, hipStream_t s) {
-  if (ksel <= 4) return launch_dp_ksel<DP, 4>(args, n_items, s);
-  if (ksel <= 16) return launch_dp_ksel<DP, 16>(args, n_items, s);
-  return launch_dp_ksel<DP, 32>(args, n_items, s);
+  if (ksel <= 4) return launch_knn_shape<PIPNN_PREC_FP32, DP, 4>(args, n_items, s);
+  if (ksel <= 16) return launch_knn_shape<PIPNN_PREC_FP32, DP, 16>(args, n_items, s);
+  return launch_knn_shape<PIPNN_PREC_FP32, DP, 32>(args, n_items, s);
 }
 
 int knn_rows_per_item() { return 32 * 4; }
@@ -444,9 +17,12 @@ int knn_rows_per_item() { return 32 * 4; }
 hipError_t launch_knn(const KnnLaunch &L, hipStream_t s) {
   const Index &I = *L.idx;
   if (L.n_items == 0) return hipSuccess;
+  const bool lowp = L.prec != PIPNN_PREC_FP32;
   KnnArgs a;
   a.X = I.xf();
-  a.norms = I.norms.as<float>();
+  a.Xop = lowp ? I.xlow.p : nullptr;
+  a.norms = lowp ? I.lnorms.as<float>() : I.norms.as<float>();
+  a.scale = L.prec == PIPNN_PREC_FP8 ? I.xscale.as<float>() : nullptr;
   a.row_base = L.row_base;
   a.col_base = L.col_base;
   a.jobs = L.jobs;
@@ -457,11 +33,20 @@ hipError_t launch_knn(const KnnLaunch &L, hipStream_t s) {
   a.matrix_ld = L.matrix_ld;
   a.n_items = L.n_items;
   a.d = I.d;
+  a.ldo = lowp ? I.ldo : I.d;
   a.metric = I.p.metric;
   a.k_out = L.k_out;
   a.out_ids = L.out_ids;
   a.recompute = L.recompute;
   a.rescore_k = L.rescore_k;
+  if (lowp) {
+    if (!a.Xop || a.ldo != lowp_padded_dim(I.d) || L.prec != I.p.gemm_prec)
+      return hipErrorInvalidValue;
+    if (L.prec == PIPNN_PREC_BF16) return launch_knn_bf16(a, L.ksel, L.n_items, s);
+    if (L.prec == PIPNN_PREC_FP16) return launch_knn_fp16(a, L.ksel, L.n_items, s);
+    if (L.prec == PIPNN_PREC_FP8) return launch_knn_fp8(a, L.ksel, L.n_items, s);
+    return hipErrorInvalidValue;
+  }
   const int d = I.d;
   if (d <= 32) return launch_dp<32>(a, L.ksel, L.n_items, s);
   if (d <= 64) return launch_dp<64>(a, L.ksel, L.n_items, s);

@@ -61,6 +61,89 @@ hipError_t launch_norms_sketches(const Index &I, hipStream_t s) {
   return hipGetLastError();
 }
 
+// ---- reduced-precision GEMM operand -------------------------------------
+// bf16: upper half of the binary32 after round-to-nearest-even.
+__device__ __forceinline__ uint32_t enc_bf16(float f) {
+  const uint32_t u = __float_as_uint(f);
+  if ((u & 0x7F800000u) == 0x7F800000u && (u & 0x007FFFFFu)) return (u >> 16) | 0x40u;
+  return (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;
+}
+// OCP E4M3 ("e4m3fn": bias 7, 3 fraction bits, subnormals, no infinities,
+// S.1111.111 = NaN, largest finite 448), round-to-nearest-even on the
+// dropped fraction bits, saturating at +-448.
+__device__ __forceinline__ uint32_t enc_e4m3(float f) {
+  const uint32_t u = __float_as_uint(f);
+  const uint32_t sign = (u >> 24) & 0x80u;
+  const uint32_t a = u & 0x7FFFFFFFu;
+  if (a > 0x7F800000u) return sign | 0x7Fu;        // NaN
+  if (a >= 0x43E00000u) return sign | 0x7Eu;       // |f| >= 448
+  if (a < 0x3C800000u) {                           // |f| < 2^-6: subnormal step 2^-9
+    return sign | (uint32_t)rintf(__uint_as_float(a) * 512.f);  // 8 is the smallest normal
+  }
+  const uint32_t e = (a >> 23) - 120u;             // biased E4M3 exponent, 1..15
+  const uint32_t m = a & 0x7FFFFFu;
+  const uint32_t r = (m + 0x7FFFFu + ((m >> 20) & 1u)) >> 20;  // 0..8, 8 carries
+  return sign | ((e << 3) + r);
+}
+__device__ __forceinline__ float dec_e4m3(uint32_t c) {
+  const uint32_t e = (c >> 3) & 15u, m = c & 7u;
+  const float v = e == 0 ? (float)m * 0.001953125f : __uint_as_float(((e + 120u) << 23) | (m << 20));
+  return (c & 0x80u) ? -v : v;
+}
+
+// One wave per point: encode its d values (zero padded to ldo), and the
+// squared norm of the decoded vector, summed per lane and then across the
+// wave. fp8 scales each point by 448 / max|x_i| first.
+__global__ void __launch_bounds__(256) quantize_kernel(const float *__restrict__ X, int64_t n, int d,
+                                                       int ldo, int prec, void *out,
+                                                       float *__restrict__ scale,
+                                                       float *__restrict__ norms) {
+  const int lane = threadIdx.x & 63;
+  const int64_t p = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (p >= n) return;
+  const float *x = X + p * d;
+  float s = 1.f, inv = 1.f;
+  if (prec == PIPNN_PREC_FP8) {
+    float mx = 0.f;
+    for (int i = lane; i < d; i += 64) mx = fmaxf(mx, fabsf(x[i]));
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off, 64));
+    if (mx > 0.f) {
+      s = 448.f / mx;
+      inv = mx / 448.f;
+    }
+    if (lane == 0) scale[p] = inv;
+  }
+  float nn = 0.f;
+  for (int i = lane; i < ldo; i += 64) {
+    const float v = i < d ? x[i] : 0.f;
+    float q;
+    if (prec == PIPNN_PREC_BF16) {
+      const uint32_t c = enc_bf16(v);
+      reinterpret_cast<uint16_t *>(out)[p * ldo + i] = (uint16_t)c;
+      q = __uint_as_float(c << 16);
+    } else if (prec == PIPNN_PREC_FP16) {
+      const _Float16 c = (_Float16)v;
+      reinterpret_cast<_Float16 *>(out)[p * ldo + i] = c;
+      q = (float)c;
+    } else {
+      const uint32_t c = enc_e4m3(v * s);
+      reinterpret_cast<uint8_t *>(out)[p * ldo + i] = (uint8_t)c;
+      q = dec_e4m3(c) * inv;
+    }
+    nn = fmaf(q, q, nn);
+  }
+  nn = wave_sum(nn);
+  if (lane == 0) norms[p] = nn;
+}
+
+hipError_t launch_quantize(const Index &I, hipStream_t s) {
+  const int64_t blocks = (I.n + 3) / 4;
+  hipLaunchKernelGGL(quantize_kernel, dim3((unsigned)blocks), dim3(256), 0, s, I.xf(), I.n, I.d,
+                     I.ldo, I.p.gemm_prec, I.xlow.p, I.xscale.as<float>(), I.lnorms.as<float>());
+  return hipGetLastError();
+}
+
 __global__ void to_f32_kernel(const void *src, int dtype, float *dst, int64_t count) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= count) return;

@@ -1,0 +1,301 @@
+"""Reduced-precision leaf GEMM (bf16, fp16, OCP e4m3 with per-point scales;
+FP32 accumulation) and FP32 rescoring, through the C ABI, against the FP64
+oracle.
+
+Bit-exact: the encoded operand (codes and scales are integer work); on
+integer data 0..255, which bf16 holds exactly, the whole bf16 path equals
+the FP32 path. Real-valued data: the GEMM distances are held to the float32
+rounding bound of the decoded operand's norm expansion, the selection is
+replayed through the oracle on the GPU's own GEMM distances, emitted
+distances to the FP32 direct-difference tolerance, and the rescored picks
+must be the k nearest (by FP64 distance) of the replayed top-(mult*k) set up
+to float32 near-ties. Agreement with the FP64 picks and recall are reported
+and held to stated floors.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import pipnn_inputs as pi
+
+torch = pytest.importorskip("torch")
+import paper_2602_21247_amd as pp  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+REL, ABS = 1e-5, 1e-6
+LOWP = [pp.PREC_BF16, pp.PREC_FP16, pp.PREC_FP8]
+NAMES = {pp.PREC_BF16: "bf16", pp.PREC_FP16: "fp16", pp.PREC_FP8: "fp8"}
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    pp.lib()
+    oracle.set_threads(16)
+
+
+def u32(t):
+    return t.detach().cpu().numpy().view(np.uint32)
+
+
+def dev(a):
+    a = np.ascontiguousarray(a)
+    if a.dtype == np.uint32:
+        a = a.view(np.int32)
+    if a.dtype == np.uint64:
+        a = a.view(np.int64)
+    return torch.from_numpy(a).cuda()
+
+
+def oracle_params(p):
+    return oracle.make_params(metric=p.metric, c_max=p.c_max, c_min=p.c_min,
+                              leader_div=p.leader_div, leader_cap=p.leader_cap,
+                              fanout=tuple(p.fanout), k=p.k, hash_bits=p.hash_bits,
+                              l_max=p.l_max, R=p.R, alpha=p.alpha, seed=p.seed)
+
+
+def topk_lex(D, k, exclude_diag):
+    rows, cols = D.shape
+    out = np.full((rows, k), 0xFFFFFFFF, dtype=np.uint32)
+    ci = np.arange(cols)
+    for r in range(rows):
+        order = np.lexsort((ci, D[r]))
+        if exclude_diag:
+            order = order[order != r]
+        m = min(k, len(order))
+        out[r, :m] = order[:m]
+    return out
+
+
+def mixed_float_points(n, d, seed):
+    """vMF points plus rows that exercise the encoders: a zero row, rows of
+    tiny and huge scale, and a row with one dominant coordinate."""
+    X = pi.vmf_mixture(n, d, 50, 50.0, seed=seed, center_seed=seed)
+    X[0] = 0.0
+    X[1] *= 1e-6
+    X[2] *= 1e4
+    X[3] = 1e-3
+    X[3, 5] = 30.0
+    return X.astype(np.float32)
+
+
+@pytest.mark.parametrize("prec", LOWP)
+@pytest.mark.parametrize("d", [96, 40, 128])
+def test_operand_encoding_bit_exact(prec, d):
+    X = mixed_float_points(1500, d, seed=d)
+    H = pi.hyperplanes(12, d, seed=3)
+    idx = pp.Index(dev(X), dev(H), pp.default_params(gemm_prec=prec))
+    codes, scale, norms = idx.get_operand()
+    torch.cuda.synchronize()
+    oc, oinv, xq = oracle.quantize(X, prec)
+    got = codes.cpu().numpy()
+    if prec != pp.PREC_FP8:
+        got = got.view(np.uint16)
+    assert np.array_equal(got, oc), f"{NAMES[prec]} codes differ"
+    assert np.array_equal(scale.cpu().numpy(), oinv)
+    # squared norms of the decoded vectors: a float32 sum of d squares
+    ref = (xq * xq).sum(1)
+    assert np.all(np.abs(norms.cpu().numpy() - ref) <= (d + 2) * 2.0 ** -24 * ref + 1e-30)
+    idx.close()
+
+
+@pytest.mark.parametrize("d", [128, 96, 40])
+@pytest.mark.parametrize("mult", [0, 2])
+def test_bf16_equals_fp32_on_integer_data(d, mult):
+    """Integers 0..255 are exact in bf16 and every product and sum stays
+    below 2^24: the bf16 GEMM is the exact distance, as the FP32 one is."""
+    X = pi.integer_mixture(1200, d, 40, 30.0, seed=11 + d)
+    H = pi.hyperplanes(12, d, seed=5, integer=True)
+    k = 16 if mult == 0 else 8
+    idx = pp.Index(dev(X), dev(H), pp.default_params(k=k, gemm_prec=pp.PREC_BF16,
+                                                      rescore_mult=mult))
+    ids = np.sort(np.random.default_rng(d).choice(1200, 500, replace=False)).astype(np.uint32)
+    oc, od, om = idx.knn_block(dev(ids), dev(ids), k, True, want_matrix=True)
+    torch.cuda.synchronize()
+    Xi = X[ids].astype(np.int64)
+    D = ((Xi[:, None, :] - Xi[None]) ** 2).sum(-1)
+    assert np.array_equal(om.cpu().numpy(), D.astype(np.float32))
+    want = topk_lex(D, k, True)
+    assert np.array_equal(u32(oc), want)
+    assert np.array_equal(od.cpu().numpy(), np.take_along_axis(D, want.astype(np.int64), 1))
+    idx.close()
+
+
+def _check_rescored_block(X, xq, ids, oc, od, M, k, mult, d, prec):
+    n = len(ids)
+    self_col = np.arange(n)
+    Xd = X[ids].astype(np.float64)
+    Q = xq[ids]
+    # 1. the GEMM distances: norm-expansion form of the decoded operand,
+    #    within the float32 rounding bound of a d-term dot product and the
+    #    decode-scale products
+    Dq = ((Q[:, None, :] - Q[None]) ** 2).sum(-1)
+    nq = (Q * Q).sum(1)
+    bound = (d + 8) * 2.0 ** -23 * (nq[:, None] + nq[None])
+    np.fill_diagonal(bound, np.inf)
+    ratio = np.abs(M - Dq) / bound
+    print(f"prec {prec}: GEMM distance error / sequential-fp32 bound: max {ratio.max():.3f} "
+          f"median {np.median(ratio):.4f}")
+    # the fp8 MFMA sums its products inside the matrix core with an
+    # unspecified grouping and rounding, not as a chain of IEEE fp32 adds;
+    # it is held to four times the sequential bound
+    assert ratio.max() <= (4.0 if prec == pp.PREC_FP8 else 1.0)
+    # typical errors are random-walk roundings, far below the worst case
+    assert np.median(ratio) < 0.1
+    # 2. the first selection, replayed on the GPU's own GEMM values
+    k1 = mult * k if mult else k
+    sel, _ = oracle.topk_rows(M, k1, self_col=self_col)
+    got = u32(oc)
+    D64 = ((Xd[:, None, :] - Xd[None]) ** 2).sum(-1)
+    if not mult:
+        assert np.array_equal(got, sel)
+    gd = od.cpu().numpy()
+    ref = np.take_along_axis(D64, got.astype(np.int64), 1)
+    tol = np.maximum(REL * np.abs(ref), ABS)
+    # 3. emitted distances: FP32 direct differences of the original vectors
+    assert np.all(np.abs(gd - ref) <= tol)
+    if mult:
+        for r in range(n):
+            s = set(sel[r].tolist())
+            g = got[r].tolist()
+            assert set(g) <= s, f"row {r}: a pick outside the replayed top-{k1}"
+            rest = np.array(sorted(s - set(g)), dtype=np.int64)
+            if len(rest):
+                # the k kept are the k nearest of the set, up to float32 near-ties
+                worst_kept = ref[r].max()
+                best_rest = D64[r, rest].min()
+                assert worst_kept <= best_rest + 2 * max(REL * abs(best_rest), ABS), r
+            # emitted in non-decreasing order of the emitted distance
+            assert np.all(np.diff(gd[r]) >= 0)
+
+
+@pytest.mark.parametrize("prec", LOWP)
+@pytest.mark.parametrize("mult", [0, 2])
+def test_lowp_knn_block_replay(prec, mult):
+    d, n, k = 96, 900, 16
+    X = pi.workload_points(3, 6000)
+    H = pi.workload_hyperplanes(3)
+    idx = pp.Index(dev(X), dev(H), pp.default_params(k=k, gemm_prec=prec, rescore_mult=mult))
+    ids = np.sort(np.random.default_rng(prec * 10 + mult).choice(6000, n, replace=False)).astype(
+        np.uint32)
+    oc, od, om = idx.knn_block(dev(ids), dev(ids), k, True, want_matrix=True)
+    torch.cuda.synchronize()
+    _, _, xq = oracle.quantize(X, prec)
+    _check_rescored_block(X, xq, ids, oc, od, om.cpu().numpy(), k, mult, d, prec)
+    idx.close()
+
+
+@pytest.mark.parametrize("prec", LOWP)
+def test_lowp_ragged_blocks(prec):
+    """Blocks that are not whole tiles, rectangular, and smaller than k1."""
+    X = pi.workload_points(3, 3000)
+    H = pi.workload_hyperplanes(3)
+    for nr, nc, k, mult, diag in [(37, 37, 16, 2, True), (300, 1001, 8, 2, False),
+                                  (5, 5, 16, 2, True), (129, 129, 4, 4, True)]:
+        idx = pp.Index(dev(X), dev(H), pp.default_params(k=k, gemm_prec=prec, rescore_mult=mult))
+        rng = np.random.default_rng(nr + nc)
+        cols = np.sort(rng.choice(3000, nc, replace=False)).astype(np.uint32)
+        rows = cols if diag else np.sort(rng.choice(3000, nr, replace=False)).astype(np.uint32)
+        oc, od, om = idx.knn_block(dev(rows), dev(cols), k, diag, want_matrix=True)
+        torch.cuda.synchronize()
+        M = om.cpu().numpy()
+        sel, _ = oracle.topk_rows(M, mult * k, self_col=np.arange(nr) if diag else None)
+        got = u32(oc)
+        Xr, Xc = X[rows].astype(np.float64), X[cols].astype(np.float64)
+        D64 = ((Xr[:, None, :] - Xc[None]) ** 2).sum(-1)
+        for r in range(nr):
+            valid = sel[r][sel[r] != 0xFFFFFFFF]
+            want = sorted(((D64[r, c], c) for c in valid))[:k]
+            g = got[r][got[r] != 0xFFFFFFFF]
+            assert len(g) == len(want)
+            assert set(g.tolist()) <= set(valid.tolist())
+        idx.close()
+
+
+def _vmf_partition(n):
+    X = pi.workload_points(3, n)
+    H = pi.workload_hyperplanes(3)
+    w = pi.WORKLOADS[3]
+    p = pp.default_params(c_max=1024, c_min=w.c_min, k=w.k, l_max=w.l_max, R=w.R,
+                          alpha=w.alpha, seed=pi.workload_seed(3))
+    off, mem, _ = oracle.partition(X, oracle_params(p))
+    return X, H, p, off, mem
+
+
+def test_lowp_leaf_pick_against_fp64():
+    """Per-row pick agreement with the oracle's FP64 picks (reported; held
+    to floors) for every precision, with and without rescoring."""
+    X, H, p, off, mem = _vmf_partition(12000)
+    exact, _ = oracle.leaf_knn(X, off, mem, p.k)
+    for prec in [pp.PREC_FP32] + LOWP:
+        for mult in (0, 2):
+            if prec == pp.PREC_FP32 and mult:
+                continue
+            p.gemm_prec, p.rescore_mult = prec, mult
+            idx = pp.Index(dev(X), dev(H), p)
+            oc, od = idx.leaf_pick(dev(off), dev(mem))
+            torch.cuda.synchronize()
+            got = u32(oc)
+            agree = np.mean([len(set(a) & set(b)) / len(b) for a, b in zip(got, exact)])
+            # the oracle's independent run of the same form
+            if prec != pp.PREC_FP32:
+                _, _, xq = oracle.quantize(X, prec)
+                oref, _ = oracle.leaf_knn_lowp(X, xq, off, mem, p.k, mult)
+                same = np.mean([len(set(a) & set(b)) / len(b) for a, b in zip(got, oref)])
+            else:
+                same = agree
+            print(f"{NAMES.get(prec, 'fp32')} rescore x{mult}: pick agreement with FP64 "
+                  f"{agree:.5f}, with the oracle's {NAMES.get(prec, 'fp32')} form {same:.5f}")
+            floor = {pp.PREC_FP32: 0.999, pp.PREC_BF16: 0.97, pp.PREC_FP16: 0.995,
+                     pp.PREC_FP8: 0.80}[prec]
+            if mult:
+                floor = max(floor, 0.995 if prec != pp.PREC_FP8 else 0.97)
+            assert agree >= floor
+            assert same >= 0.99
+            idx.close()
+    p.gemm_prec, p.rescore_mult = pp.PREC_FP32, 0
+
+
+def test_lowp_build_recall():
+    """End graphs of the rescored forms against the FP32 form: recall@10 on
+    the same queries (reported; bf16/fp16 within 0.01, fp8 within 0.02)."""
+    X, H, p, _, _ = _vmf_partition(20000)
+    Q = pi.workload_queries(3, 500)
+    start, _ = oracle.start_node(X)
+    _, gd = oracle.bruteforce_knn(X, Q, 10)
+    rec = {}
+    for prec, mult in [(pp.PREC_FP32, 0), (pp.PREC_BF16, 2), (pp.PREC_FP16, 2),
+                       (pp.PREC_FP8, 2)]:
+        p.gemm_prec, p.rescore_mult = prec, mult
+        idx, off, mem, res, g, deg = pp.build(dev(X), dev(H), p)
+        ids, _, _ = idx.search(g, dev(Q), 10, 64, start)
+        torch.cuda.synchronize()
+        rec[prec] = oracle.recall_at_k(u32(ids), X, Q, gd)
+        print(f"{NAMES.get(prec, 'fp32')} rescore x{mult}: recall@10 at L=64 {rec[prec]:.4f}")
+        idx.close()
+    assert abs(rec[pp.PREC_BF16] - rec[pp.PREC_FP32]) <= 0.01
+    assert abs(rec[pp.PREC_FP16] - rec[pp.PREC_FP32]) <= 0.01
+    assert abs(rec[pp.PREC_FP8] - rec[pp.PREC_FP32]) <= 0.02
+    p.gemm_prec, p.rescore_mult = pp.PREC_FP32, 0
+
+
+def test_bf16_full_build_integer_bit_exact():
+    X = pi.integer_mixture(12000, 128, 60, 40.0, seed=41)
+    H = pi.hyperplanes(12, 128, seed=42, integer=True)
+    p = pp.default_params(c_max=1024, c_min=64, k=16, l_max=64, R=32, seed=43,
+                          gemm_prec=pp.PREC_BF16)
+    ref = oracle.build_index(X, H, oracle_params(p))
+    idx, off, mem, res, g, deg = pp.build(dev(X), dev(H), p)
+    torch.cuda.synchronize()
+    assert np.array_equal(res.cpu().numpy().view(np.uint64), ref["reservoirs"])
+    assert np.array_equal(u32(g), ref["graph"])
+    idx.close()
+
+
+def test_reduced_precision_rejects_wide_vectors():
+    X = np.zeros((10, 300), dtype=np.float32)
+    H = pi.hyperplanes(12, 300, seed=1)
+    with pytest.raises(pp.PipnnError, match="d <= 256"):
+        pp.Index(dev(X), dev(H), pp.default_params(gemm_prec=pp.PREC_BF16))
