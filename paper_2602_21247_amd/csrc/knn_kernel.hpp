@@ -112,6 +112,20 @@ __device__ __forceinline__ f32x16 mfma16(uint4 a, uint4 b, f32x16 acc) {
   }
 }
 
+// Selection key of a (distance, column) pair: the order-preserving rank of
+// the float32 distance above the column, so that unsigned 64-bit order is
+// the (distance, column) order. All ones marks an empty slot.
+__device__ __forceinline__ uint64_t sel_key(float d, uint32_t c) {
+  return ((uint64_t)f32_rank(d) << 32) | c;
+}
+__device__ __forceinline__ float key_dist(uint64_t k) {
+  const uint32_t r = (uint32_t)(k >> 32);
+  return __uint_as_float((r & 0x80000000u) ? (r & 0x7FFFFFFFu) : ~r);
+}
+constexpr uint64_t kEmptyKey = ~0ull;
+__device__ __forceinline__ uint64_t kmin(uint64_t a, uint64_t b) { return a < b ? a : b; }
+__device__ __forceinline__ uint64_t kmax(uint64_t a, uint64_t b) { return a < b ? b : a; }
+
 template <int PREC, int DP, int KSEL, int NW, bool L2>
 __global__ void __launch_bounds__(NW * 64, 2) knn_kernel(KnnArgs a) {
   constexpr bool LP = PREC != PIPNN_PREC_FP32;  // reduced-precision operand
@@ -127,7 +141,8 @@ __global__ void __launch_bounds__(NW * 64, 2) knn_kernel(KnnArgs a) {
   constexpr int CAP = 32;         // per-row buffer: a 32-column block appends at most 32
   constexpr int BUFD = CAP + 1;
   constexpr int BUFC = CAP + 2;
-  constexpr int KS1 = KSEL + 1;
+  constexpr int KH = KSEL / 2;     // kept-list entries held by each lane of a row's pair
+  constexpr int KST = KSEL + 1;   // LDS stride of a row's kept list (64-bit keys)
   constexpr int NTH = NW * 64;
   constexpr int CH_PER_TILE = BN * CPC;
   constexpr int NPRE = (CH_PER_TILE + NTH - 1) / NTH;
@@ -136,8 +151,7 @@ __global__ void __launch_bounds__(NW * 64, 2) knn_kernel(KnnArgs a) {
   __shared__ __attribute__((aligned(16))) uint32_t sBw[BN * LDW];
   __shared__ float sBufD[BM * BUFD];
   __shared__ uint16_t sBufC[BM * BUFC];
-  __shared__ float sTopD[BM * KS1];
-  __shared__ uint32_t sTopC[BM * KS1];
+  __shared__ uint64_t sKeep[BM * KST];
   __shared__ float sTau[BM];
   __shared__ int sBufN[BM];
   __shared__ float sColN[BN];
@@ -165,6 +179,7 @@ __global__ void __launch_bounds__(NW * 64, 2) knn_kernel(KnnArgs a) {
   const int64_t op_ld = (int64_t)a.ldo * EB;  // bytes per operand row
 
   // per-row squared norm and selection threshold (-inf past the last row)
+  for (int i = tid; i < BM * KST; i += NTH) sKeep[i] = kEmptyKey;
   for (int r = tid; r < BM; r += NTH) {
     const bool ok = rbase + r < n_rows;
     sTau[r] = ok ? INFINITY : -INFINITY;
@@ -208,11 +223,8 @@ __global__ void __launch_bounds__(NW * 64, 2) knn_kernel(KnnArgs a) {
     }
   }
 
-  // owner-lane state (lanes 0..31 own row wrow + lane)
+  // lanes l32 and l32 + 32 own row wrow + l32 together
   const int orow = wave * 32 + l32;  // LDS row index
-  int tn = 0, maxpos = 0;
-  float maxd = INFINITY;
-  uint32_t maxc = 0xFFFFFFFFu;
 
   // column tile staging: thread t loads 16-byte chunks t, t+NTH, ... of the tile
   uint4 pre[NPRE];
@@ -264,64 +276,41 @@ __global__ void __launch_bounds__(NW * 64, 2) knn_kernel(KnnArgs a) {
     }
   };
 
-  // The owner lane of a row loads its kept set into registers once, folds
-  // in every buffered survivor there (replace the current worst, rescan for
-  // the new worst), and writes the set back once.
+  // Drain: the row's kept list is sorted in descending key order and split
+  // between its two lanes (lane h holds positions [h*KH, h*KH+KH)). A key x
+  // enters by b[i] = max(a[i+1], min(a[i], x)): the largest entry drops out
+  // when x is smaller, and nothing changes otherwise. Every entry is
+  // independent of the others, so the update has no select chain and no
+  // rescan; the lane holding the upper half needs only the first entry of
+  // the lower half.
   auto drain = [&]() {
-    if (l32 == lane && wrow + l32 < n_rows) {
-      const int nb = sBufN[orow];
-      if (nb > 0) {
-        float kd[KSEL];
-        uint32_t kc[KSEL];
+    const int nb = (wrow + l32 < n_rows) ? sBufN[orow] : 0;
+    if (nb > 0) {
+      uint64_t ks[KH];
 #pragma unroll
-        for (int i = 0; i < KSEL; ++i) {
-          kd[i] = sTopD[orow * KS1 + i];
-          kc[i] = sTopC[orow * KS1 + i];
+      for (int i = 0; i < KH; ++i) ks[i] = sKeep[orow * KST + h * KH + i];
+      float nd = sBufD[orow * BUFD];
+      uint32_t ncv = sBufC[orow * BUFC];
+      for (int e = 0; e < nb; ++e) {
+        const uint64_t x = sel_key(nd, ncv);
+        if (e + 1 < nb) {
+          nd = sBufD[orow * BUFD + e + 1];
+          ncv = sBufC[orow * BUFC + e + 1];
         }
-        float nd = sBufD[orow * BUFD];
-        uint32_t ncv = sBufC[orow * BUFC];
-        for (int e = 0; e < nb; ++e) {
-          const float dv = nd;
-          const uint32_t cv = ncv;
-          if (e + 1 < nb) {
-            nd = sBufD[orow * BUFD + e + 1];
-            ncv = sBufC[orow * BUFC + e + 1];
-          }
-          int slot = -1;
-          if (tn < KSEL) {
-            slot = tn++;
-          } else if (dv < maxd || (dv == maxd && cv < maxc)) {
-            slot = maxpos;
-          }
-          if (slot >= 0) {
+        const uint32_t lo = (uint32_t)ks[0], hi = (uint32_t)(ks[0] >> 32);
+        const uint32_t olo = __shfl_xor(lo, 32, 64), ohi = __shfl_xor(hi, 32, 64);
+        const uint64_t below = h == 0 ? (((uint64_t)ohi << 32) | olo) : 0ull;
 #pragma unroll
-            for (int i = 0; i < KSEL; ++i) {
-              if (i == slot) {
-                kd[i] = dv;
-                kc[i] = cv;
-              }
-            }
-            if (tn == KSEL) {
-              maxpos = 0;
-              maxd = kd[0];
-              maxc = kc[0];
-#pragma unroll
-              for (int i = 1; i < KSEL; ++i) {
-                const bool gt = kd[i] > maxd || (kd[i] == maxd && kc[i] > maxc);
-                maxd = gt ? kd[i] : maxd;
-                maxc = gt ? kc[i] : maxc;
-                maxpos = gt ? i : maxpos;
-              }
-            }
-          }
+        for (int i = 0; i < KH; ++i) {
+          const uint64_t nxt = (i + 1 < KH) ? ks[i + 1] : below;
+          ks[i] = kmax(nxt, kmin(ks[i], x));
         }
+      }
 #pragma unroll
-        for (int i = 0; i < KSEL; ++i) {
-          sTopD[orow * KS1 + i] = kd[i];
-          sTopC[orow * KS1 + i] = kc[i];
-        }
+      for (int i = 0; i < KH; ++i) sKeep[orow * KST + h * KH + i] = ks[i];
+      if (h == 0) {
         sBufN[orow] = 0;
-        sTau[orow] = (tn == KSEL) ? maxd : INFINITY;
+        sTau[orow] = ks[0] == kEmptyKey ? INFINITY : key_dist(ks[0]);
       }
     }
   };
@@ -388,13 +377,19 @@ __global__ void __launch_bounds__(NW * 64, 2) knn_kernel(KnnArgs a) {
         pass |= (ok ? 1u : 0u) << v;
       }
       if (__ballot(pass != 0) == 0ull) continue;
+      // append: a row's survivors go to its buffer (empty after every
+      // drain) at their rank among the row's survivors, from one ballot
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
+        const uint64_t m = __ballot((pass >> v) & 1u);
+        if (m == 0ull) continue;
         if ((pass >> v) & 1u) {
+          const uint32_t hm = h ? (uint32_t)(m >> 32) : (uint32_t)m;
+          const int pos = __popc(hm & ((1u << l32) - 1u));
           const int rl = wave * 32 + acc_row(v, h);
-          const int pos = atomicAdd(&sBufN[rl], 1);
           sBufD[rl * BUFD + pos] = dv[v];
           sBufC[rl * BUFC + pos] = (uint16_t)cc;
+          if (pos == __popc(hm) - 1) sBufN[rl] = pos + 1;
         }
       }
       wave_sync();
@@ -405,26 +400,22 @@ __global__ void __launch_bounds__(NW * 64, 2) knn_kernel(KnnArgs a) {
   }
 
   // ---- epilogue: this wave's 32 rows ----
-  // sort each kept set by (GEMM distance, column)
-  if (l32 == lane && wrow + l32 < n_rows) {
-    for (int i = 1; i < tn; ++i) {
-      const float di = sTopD[orow * KS1 + i];
-      const uint32_t ci = sTopC[orow * KS1 + i];
-      int j = i - 1;
-      while (j >= 0) {
-        const float dj = sTopD[orow * KS1 + j];
-        const uint32_t cj = sTopC[orow * KS1 + j];
-        if (dj > di || (dj == di && cj > ci)) {
-          sTopD[orow * KS1 + j + 1] = dj;
-          sTopC[orow * KS1 + j + 1] = cj;
-          --j;
-        } else {
-          break;
-        }
-      }
-      sTopD[orow * KS1 + j + 1] = di;
-      sTopC[orow * KS1 + j + 1] = ci;
+  // unpack each kept list into ascending (GEMM distance, column) order in
+  // the row's buffer; empty slots sort last
+  int tn = 0;
+  if (wrow + l32 < n_rows) {
+    int empty = 0;
+#pragma unroll
+    for (int i = 0; i < KH; ++i) {
+      const uint64_t k = sKeep[orow * KST + h * KH + i];
+      const int q = KSEL - 1 - (h * KH + i);
+      empty += k == kEmptyKey ? 1 : 0;
+      sBufD[orow * BUFD + q] = k == kEmptyKey ? INFINITY : key_dist(k);
+      sBufC[orow * BUFC + q] = (uint16_t)k;
     }
+    tn = KSEL - empty - __shfl_xor(empty, 32, 64);
+  } else {
+    (void)__shfl_xor(0, 32, 64);
   }
   wave_sync();
 
@@ -435,8 +426,7 @@ __global__ void __launch_bounds__(NW * 64, 2) knn_kernel(KnnArgs a) {
     // in registers; it sums (x_r - x_c)^2 over that half in index order, and the
     // two halves are added, so a pair gets the same value from either row.
     const int rr = wrow + l32;
-    const int tnr = __shfl(tn, l32, 64);
-    const int cnt = rr < n_rows ? (tnr < ksel_job ? tnr : ksel_job) : 0;
+    const int cnt = rr < n_rows ? (tn < ksel_job ? tn : ksel_job) : 0;
     const int lrow = wave * 32 + l32;
     const int kbase = h * HALF;
     // the row's FP32 half: av[] already holds it on the FP32 path
@@ -467,8 +457,8 @@ __global__ void __launch_bounds__(NW * 64, 2) knn_kernel(KnnArgs a) {
       if (!__any(i < cnt)) break;
       float s = 0.f;
       if (i < cnt) {
-        const uint32_t c = sTopC[lrow * KS1 + i];
-        const float *xc = a.X + (int64_t)cols[c] * d + kbase;
+        const uint32_t c = sBufC[lrow * BUFC + i];
+        const float *xc = a.X + (int64_t)cols[c < (uint32_t)n_cols ? c : 0] * d + kbase;
         if (full_d) {
 #pragma unroll
           for (int kk = 0; kk < HALF; kk += 4) {
@@ -507,27 +497,28 @@ __global__ void __launch_bounds__(NW * 64, 2) knn_kernel(KnnArgs a) {
   if (l32 == lane && wrow + l32 < n_rows) {
     const int rr = wrow + l32;
     int cnt = tn < ksel_job ? tn : ksel_job;
-    float *dd = a.recompute ? &sBufD[orow * BUFD] : &sTopD[orow * KS1];
+    float *dd = &sBufD[orow * BUFD];
+    uint16_t *cc = &sBufC[orow * BUFC];
     if (a.rescore_k > 0) {
       // re-rank the GEMM winners by (direct distance, column)
       for (int i = 1; i < cnt; ++i) {
         const float di = dd[i];
-        const uint32_t ci = sTopC[orow * KS1 + i];
+        const uint16_t ci = cc[i];
         int j = i - 1;
-        while (j >= 0 && (dd[j] > di || (dd[j] == di && sTopC[orow * KS1 + j] > ci))) {
+        while (j >= 0 && (dd[j] > di || (dd[j] == di && cc[j] > ci))) {
           dd[j + 1] = dd[j];
-          sTopC[orow * KS1 + j + 1] = sTopC[orow * KS1 + j];
+          cc[j + 1] = cc[j];
           --j;
         }
         dd[j + 1] = di;
-        sTopC[orow * KS1 + j + 1] = ci;
+        cc[j + 1] = ci;
       }
       if (cnt > a.rescore_k) cnt = a.rescore_k;
     }
     const int64_t o = (J.out_off + rr) * (int64_t)a.k_out;
     for (int i = 0; i < a.k_out; ++i) {
-      if (i < cnt) {
-        const uint32_t c = sTopC[orow * KS1 + i];
+      const uint32_t c = i < cnt ? cc[i] : 0xFFFFu;
+      if (c < (uint32_t)n_cols) {
         a.out_col[o + i] = a.out_ids ? cols[c] : c;
         if (a.out_dist) a.out_dist[o + i] = dd[i];
       } else {
