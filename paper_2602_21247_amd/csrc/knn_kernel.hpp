@@ -123,6 +123,16 @@ __device__ __forceinline__ float key_dist(uint64_t k) {
   return __uint_as_float((r & 0x80000000u) ? (r & 0x7FFFFFFFu) : ~r);
 }
 constexpr uint64_t kEmptyKey = ~0ull;
+
+// The value lane l ^ 32 holds (the same lane of the other half-wave), by a
+// VALU swap of the two halves (v_permlane32_swap) instead of an LDS route.
+__device__ __forceinline__ uint32_t other_half_u32(uint32_t x) {
+  const auto r = __builtin_amdgcn_permlane32_swap(x, x, false, false);
+  return (__lane_id() < 32) ? r[1] : r[0];
+}
+__device__ __forceinline__ float other_half(float x) {
+  return __uint_as_float(other_half_u32(__float_as_uint(x)));
+}
 __device__ __forceinline__ uint64_t kmin(uint64_t a, uint64_t b) { return a < b ? a : b; }
 __device__ __forceinline__ uint64_t kmax(uint64_t a, uint64_t b) { return a < b ? b : a; }
 
@@ -298,7 +308,7 @@ __global__ void __launch_bounds__(NW * 64, 2) knn_kernel(KnnArgs a) {
           ncv = sBufC[orow * BUFC + e + 1];
         }
         const uint32_t lo = (uint32_t)ks[0], hi = (uint32_t)(ks[0] >> 32);
-        const uint32_t olo = __shfl_xor(lo, 32, 64), ohi = __shfl_xor(hi, 32, 64);
+        const uint32_t olo = other_half_u32(lo), ohi = other_half_u32(hi);
         const uint64_t below = h == 0 ? (((uint64_t)ohi << 32) | olo) : 0ull;
 #pragma unroll
         for (int i = 0; i < KH; ++i) {
@@ -413,9 +423,7 @@ __global__ void __launch_bounds__(NW * 64, 2) knn_kernel(KnnArgs a) {
       sBufD[orow * BUFD + q] = k == kEmptyKey ? INFINITY : key_dist(k);
       sBufC[orow * BUFC + q] = (uint16_t)k;
     }
-    tn = KSEL - empty - __shfl_xor(empty, 32, 64);
-  } else {
-    (void)__shfl_xor(0, 32, 64);
+    tn = KSEL - empty - (int)other_half_u32((uint32_t)empty);
   }
   wave_sync();
 
@@ -453,43 +461,54 @@ __global__ void __launch_bounds__(NW * 64, 2) knn_kernel(KnnArgs a) {
       if constexpr (LP) return xr[kk];
       else return av[kk];
     };
-    for (int i = 0; i < KSEL; ++i) {
-      if (!__any(i < cnt)) break;
+    // sum over this lane's half of the dimensions for column c
+    auto half_dist = [&](uint32_t c) -> float {
+      const float *xc = a.X + (int64_t)cols[c] * d + kbase;
       float s = 0.f;
-      if (i < cnt) {
-        const uint32_t c = sBufC[lrow * BUFC + i];
-        const float *xc = a.X + (int64_t)cols[c < (uint32_t)n_cols ? c : 0] * d + kbase;
-        if (full_d) {
+      if (full_d) {
 #pragma unroll
-          for (int kk = 0; kk < HALF; kk += 4) {
-            const float4 q = *reinterpret_cast<const float4 *>(xc + kk);
-            if (l2) {
-              float t = rv(kk) - q.x; s = fmaf(t, t, s);
-              t = rv(kk + 1) - q.y; s = fmaf(t, t, s);
-              t = rv(kk + 2) - q.z; s = fmaf(t, t, s);
-              t = rv(kk + 3) - q.w; s = fmaf(t, t, s);
-            } else {
-              s = fmaf(rv(kk), q.x, s); s = fmaf(rv(kk + 1), q.y, s);
-              s = fmaf(rv(kk + 2), q.z, s); s = fmaf(rv(kk + 3), q.w, s);
-            }
+        for (int kk = 0; kk < HALF; kk += 4) {
+          const float4 q = *reinterpret_cast<const float4 *>(xc + kk);
+          if (l2) {
+            float t = rv(kk) - q.x; s = fmaf(t, t, s);
+            t = rv(kk + 1) - q.y; s = fmaf(t, t, s);
+            t = rv(kk + 2) - q.z; s = fmaf(t, t, s);
+            t = rv(kk + 3) - q.w; s = fmaf(t, t, s);
+          } else {
+            s = fmaf(rv(kk), q.x, s); s = fmaf(rv(kk + 1), q.y, s);
+            s = fmaf(rv(kk + 2), q.z, s); s = fmaf(rv(kk + 3), q.w, s);
           }
-        } else {
+        }
+      } else {
 #pragma unroll
-          for (int kk = 0; kk < HALF; ++kk) {
-            const float v = (kbase + kk < d) ? xc[kk] : 0.f;
-            if (l2) {
-              const float t = rv(kk) - v;
-              s = fmaf(t, t, s);
-            } else {
-              s = fmaf(rv(kk), v, s);
-            }
+        for (int kk = 0; kk < HALF; ++kk) {
+          const float v = (kbase + kk < d) ? xc[kk] : 0.f;
+          if (l2) {
+            const float t = rv(kk) - v;
+            s = fmaf(t, t, s);
+          } else {
+            s = fmaf(rv(kk), v, s);
           }
         }
       }
-      const float other = __shfl_xor(s, 32, 64);
-      const float lo = h == 0 ? s : other, hi = h == 0 ? other : s;
-      const float tot = lo + hi;
-      if (i < cnt && h == 0) sBufD[lrow * BUFD + i] = l2 ? tot : -tot;
+      return s;
+    };
+    // two winners per pass, so that both columns' loads are in flight
+    // together; a slot past the row's count reads column 0 and is dropped
+    for (int i = 0; i < KSEL; i += 2) {
+      if (!__any(i < cnt)) break;
+      const uint32_t c0 = i < cnt ? sBufC[lrow * BUFC + i] : 0u;
+      const uint32_t c1 = i + 1 < cnt ? sBufC[lrow * BUFC + i + 1] : 0u;
+      const float s0 = half_dist(c0 < (uint32_t)n_cols ? c0 : 0u);
+      const float s1 = half_dist(c1 < (uint32_t)n_cols ? c1 : 0u);
+      const float o0 = other_half(s0), o1 = other_half(s1);
+      // the lower half's sum first, then the upper half's
+      const float t0 = h == 0 ? s0 + o0 : o0 + s0;
+      const float t1 = h == 0 ? s1 + o1 : o1 + s1;
+      if (h == 0) {
+        if (i < cnt) sBufD[lrow * BUFD + i] = l2 ? t0 : -t0;
+        if (i + 1 < cnt) sBufD[lrow * BUFD + i + 1] = l2 ? t1 : -t1;
+      }
     }
   }
   wave_sync();
