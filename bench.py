@@ -59,8 +59,9 @@ def parse():
     ap.add_argument("--no-recall", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=4.0,
                     help="target seconds of oracle work per sampled phase")
-    ap.add_argument("--prec", default="fp32", choices=sorted(PREC_CODES),
-                    help="operand precision of the leaf GEMM of the measured build")
+    ap.add_argument("--prec", default=None, choices=sorted(PREC_CODES),
+                    help="operand precision of the leaf GEMM of the measured build (default: "
+                         "fp32, or fp16 for the 768-d workload)")
     ap.add_argument("--rescore-mult", type=int, default=0,
                     help="select rescore_mult*k by the GEMM distance, keep k by FP32 rescoring")
     ap.add_argument("--variants", default="bf16:0,bf16:2,fp8:2",
@@ -72,20 +73,25 @@ def parse():
     return ap.parse_args()
 
 
-def ground_truth(torch, Xd, Qd, k=10):
-    """Exact k-th neighbour distance per query, FP64 on the GPU (evaluation
-    only: the build never uses it)."""
+def ground_truth(torch, Xd, Qd, metric=0, k=10):
+    """Exact k-th neighbour distance per query (squared L2, or negated inner
+    product), FP64 on the GPU (evaluation only: the build never uses it)."""
     X64 = Xd.double()
     xn = (X64 * X64).sum(1)
     kth = torch.empty(Qd.shape[0], dtype=torch.float64, device="cuda")
     for q0 in range(0, Qd.shape[0], 512):
         q = Qd[q0:q0 + 512].double()
-        D = (q * q).sum(1, keepdim=True) + xn[None, :] - 2.0 * (q @ X64.T)
-        vals, ids = torch.topk(D, k, dim=1, largest=False)
-        # exact recomputation of the k winners by direct difference
-        diff = X64[ids] - q[:, None, :]
-        dd = (diff * diff).sum(-1)
-        kth[q0:q0 + 512] = dd.max(1).values
+        if metric == 1:
+            D = -(q @ X64.T)
+            vals, ids = torch.topk(D, k, dim=1, largest=False)
+            kth[q0:q0 + 512] = vals.max(1).values
+        else:
+            D = (q * q).sum(1, keepdim=True) + xn[None, :] - 2.0 * (q @ X64.T)
+            vals, ids = torch.topk(D, k, dim=1, largest=False)
+            # exact recomputation of the k winners by direct difference
+            diff = X64[ids] - q[:, None, :]
+            dd = (diff * diff).sum(-1)
+            kth[q0:q0 + 512] = dd.max(1).values
         del D
     return kth
 
@@ -120,20 +126,24 @@ def cpu_baseline(X, H, off, mem, res_np, stats, w, budget):
     notes = []
     total = 0.0
 
-    # partition: point-to-leader distances with top-f selection
-    ell = min(w.leader_cap, max(2, -(-n // w.leader_div)), n)
-    leaders = X[rng.choice(n, ell, replace=False)]
-    m = 2000
-    t = time.perf_counter()
-    oracle.bruteforce_knn(leaders, X[rng.choice(n, m, replace=False)], 2)
-    dt = time.perf_counter() - t
-    m2 = int(min(n, max(m, m * budget / max(dt, 1e-3))))
-    t = time.perf_counter()
-    oracle.bruteforce_knn(leaders, X[rng.choice(n, m2, replace=False)], 2)
-    dt = time.perf_counter() - t
-    t_part = dt * stats["leader_dists"] / float(m2 * ell)
-    total += t_part
-    notes.append(f"partition: {m2} points x {ell} leaders (x{stats['leader_dists'] / (m2 * ell):.0f})")
+    # partition: point-to-leader distances with top-f selection (none when
+    # the leaves are given)
+    t_part = 0.0
+    if stats["leader_dists"] > 0:
+        ell = min(w.leader_cap, max(2, -(-n // w.leader_div)), n)
+        leaders = X[rng.choice(n, ell, replace=False)]
+        m = 2000
+        t = time.perf_counter()
+        oracle.bruteforce_knn(leaders, X[rng.choice(n, m, replace=False)], 2, metric=w.metric)
+        dt = time.perf_counter() - t
+        m2 = int(min(n, max(m, m * budget / max(dt, 1e-3))))
+        t = time.perf_counter()
+        oracle.bruteforce_knn(leaders, X[rng.choice(n, m2, replace=False)], 2, metric=w.metric)
+        dt = time.perf_counter() - t
+        t_part = dt * stats["leader_dists"] / float(m2 * ell)
+        total += t_part
+        notes.append(f"partition: {m2} points x {ell} leaders "
+                     f"(x{stats['leader_dists'] / (m2 * ell):.0f})")
 
     # leaf pick: a random sample of the GPU build's leaves
     nl = len(off) - 1
@@ -149,7 +159,7 @@ def cpu_baseline(X, H, off, mem, res_np, stats, w, budget):
     s_off = np.concatenate([[0], np.cumsum(sizes[pick])]).astype(np.int64)
     s_mem = np.concatenate([mem[off[i]:off[i + 1]] for i in pick]).astype(np.uint32)
     t = time.perf_counter()
-    cand, dist = oracle.leaf_knn(X, s_off, s_mem, w.k)
+    cand, dist = oracle.leaf_knn(X, s_off, s_mem, w.k, metric=w.metric)
     dt = time.perf_counter() - t
     t_leaf = dt * pairs_tot / acc
     total += t_leaf
@@ -179,7 +189,7 @@ def cpu_baseline(X, H, off, mem, res_np, stats, w, budget):
     # RobustPrune: the reservoirs of the first points
     ns = 20000
     t = time.perf_counter()
-    oracle.robustprune(X, res_np[:ns], w.alpha, w.R)
+    oracle.robustprune(X, res_np[:ns], w.alpha, w.R, metric=w.metric)
     dt = time.perf_counter() - t
     t_rp = dt * n / ns
     total += t_rp
@@ -212,6 +222,8 @@ def main():
         libbuild.build()
     cfg = args.workload
     w = pi.WORKLOADS[cfg]
+    if args.prec is None:
+        args.prec = "fp16" if w.d > 256 else "fp32"
     n = args.n or w.n
     log(f"[bench] generating workload {cfg} ({w.name}) n={n}")
     X = pi.workload_points(cfg, n)
@@ -222,11 +234,20 @@ def main():
     if not args.no_recall:
         nq = args.queries or w.n_queries
         Qd = torch.from_numpy(pi.workload_queries(cfg, nq)).cuda()
-        kth = ground_truth(torch, Xd, Qd)
+        kth = ground_truth(torch, Xd, Qd, w.metric)
+
+    leaves = None
+    if cfg == 4:
+        lo, lm = pi.workload_leaves(cfg, n)
+        leaves = (torch.from_numpy(lo).cuda(), torch.from_numpy(lm.view(np.int32)).cuda())
+        log(f"[bench] explicit leaves: {len(lo) - 1}, sizes {np.diff(lo).min()}..{np.diff(lo).max()}")
 
     def run_form(prec, mult, steps, warmup, keep=False):
         """Build the whole index `warmup + steps` times with one leaf-GEMM
-        form; time the last `steps`; search the last graph for recall@10."""
+        form; time the last `steps`; search the last graph for recall@10.
+        With given leaves, the leaf kernel is autotuned on them, one eager
+        build is profiled for the phase times, and the timed builds are
+        replays of one captured HIP graph of the whole step."""
         p = pp.default_params(metric=w.metric, c_max=w.c_max, c_min=w.c_min, k=w.k,
                               l_max=w.l_max, R=w.R, alpha=w.alpha, hash_bits=w.hash_bits,
                               leader_div=w.leader_div, leader_cap=w.leader_cap, fanout=w.fanout,
@@ -234,31 +255,68 @@ def main():
                               rescore_mult=mult)
         idx = pp.Index(Xd, Hd, p)
         res = torch.empty((n, w.l_max), dtype=torch.int64, device="cuda")
+        tune = None
 
-        def step():
-            idx.prepare()
-            off, mem = idx.partition()
-            pp._check(pp.lib().pipnn_reservoir_init(pp._ptr(res), n, w.l_max, pp._stream()))
-            idx.build_leaves(off, mem, res)
-            g, deg = idx.robustprune(res)
-            return off, mem, g, deg
+        if leaves is None:
+            def step():
+                idx.prepare()
+                off, mem = idx.partition()
+                pp.reservoir_init(n, w.l_max, out=res)
+                idx.build_leaves(off, mem, res)
+                g, deg = idx.robustprune(res)
+                return off, mem, g, deg
 
-        for i in range(warmup):
-            step()
+            for i in range(warmup):
+                step()
+                torch.cuda.synchronize()
+                log(f"[bench] {prec} x{mult}: warmup {i + 1}/{warmup} done")
             torch.cuda.synchronize()
-            log(f"[bench] {prec} x{mult}: warmup {i + 1}/{warmup} done")
-        torch.cuda.synchronize()
-        idx.set_profiling(True)
-        t0 = time.perf_counter()
-        for i in range(steps):
-            out = step()
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        st = idx.stats()
-        idx.set_profiling(False)
+            idx.set_profiling(True)
+            t0 = time.perf_counter()
+            for i in range(steps):
+                out = step()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            st = idx.stats()
+            idx.set_profiling(False)
+            off, mem, g, deg = out
+        else:
+            off, mem = leaves
+            tune = idx.autotune(off, mem)
+            log(f"[bench] {prec} x{mult}: autotune {tune}")
+            g = torch.empty((n, w.R), dtype=torch.int32, device="cuda")
+            deg = torch.empty(n, dtype=torch.int32, device="cuda")
+
+            def step():
+                idx.prepare()
+                pp.reservoir_init(n, w.l_max, out=res)
+                idx.build_leaves(off, mem, res)
+                idx.robustprune(res, g, deg)
+
+            step()  # eager warm-up
+            torch.cuda.synchronize()
+            idx.set_profiling(True)
+            step()  # eager, profiled: phase times and the leaf-kernel launch time
+            torch.cuda.synchronize()
+            st = idx.stats()
+            st = {k: (v * steps if k.startswith("ms_") or k == "leaf_knn_launches" else v)
+                  for k, v in st.items()}
+            idx.set_profiling(False)
+            idx.plan_leaves(off, mem)
+            graph = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(graph):
+                step()
+            for i in range(warmup):
+                graph.replay()
+                torch.cuda.synchronize()
+                log(f"[bench] {prec} x{mult}: warmup replay {i + 1}/{warmup} done")
+            t0 = time.perf_counter()
+            for i in range(steps):
+                graph.replay()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
         ms = (t1 - t0) * 1000.0 / steps
         log(f"[bench] {prec} x{mult}: {steps} steps, {ms:.2f} ms/step")
-        off, mem, g, deg = out
         # leaf kernel roofline: dense flops 2 s^2 d per leaf, per launch
         launches = max(1, st["leaf_knn_launches"])
         flops_per_launch = 2.0 * st["leaf_pairs"] * w.d * steps / launches
@@ -285,7 +343,7 @@ def main():
                 "leaf_gemm_tflops": achieved, "peak": PEAK_MFMA_TFLOPS[prec],
                 "frac": achieved / PEAK_MFMA_TFLOPS[prec], "recall_at_10": recall,
                 "L_at_recall_0.95": l_at, "recall_curve": curve, "phase_ms": phases,
-                "stats": st}
+                "stats": st, "autotune": tune}
         if keep:
             form["_out"] = (idx, res, off, mem, g, deg)
         else:

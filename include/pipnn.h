@@ -89,8 +89,9 @@ typedef int32_t pipnn_status;
  *               distances above (squared L2 or negated inner product).
  *  gemm_prec    PIPNN_PREC_*: arithmetic of the leaf distance GEMM. BF16,
  *               FP16 and FP8 multiply a copy of X in that format (made by
- *               pipnn_create / pipnn_prepare, d <= 256) and accumulate in
- *               FP32; partition distances always use the float32 vectors.
+ *               pipnn_create / pipnn_prepare, d <= 768) and accumulate in
+ *               FP32; FP32 needs d <= 256. Partition distances use the
+ *               float32 vectors for d <= 256, the reduced operand above.
  *  rescore_mult 0, or r >= 2: select the r*k nearest by the GEMM distance
  *               and keep the k nearest by an FP32 direct-difference rescore.
  *  seed         root key of the leader sampling (Alg. 5, SampleLeaders).
@@ -133,7 +134,7 @@ size_t pipnn_workspace_bytes(const pipnn_params *p, int64_t n, int32_t d,
  * EINVAL if n < 2, d < 1, hash_bits not in 1..16, k < 1, l_max not in
  * 1..256, R not in 1..256, alpha < 1, c_max < 2, c_min > c_max, leader_div
  * < 1, leader_cap < 2, a fanout < 1, fanout[3] != 1, an unknown dtype or
- * precision, n >= 2^32 - 1, or a reduced gemm_prec with d > 256. ENOMEM
+ * precision, n >= 2^32 - 1, d > 256 with gemm_prec FP32, or d > 768. ENOMEM
  * if scratch cannot be allocated. With a reduced gemm_prec it also encodes
  * the GEMM operand (see pipnn_get_operand). */
 pipnn_status pipnn_create(const pipnn_params *p, const void *d_X, int64_t n, int32_t d,
@@ -154,20 +155,62 @@ pipnn_status pipnn_partition(pipnn_index *idx, int64_t *d_leaf_offsets, int64_t 
                              uint32_t *d_leaf_members, int64_t cap_members, int64_t *h_n_leaves,
                              int64_t *h_n_members, pipnn_stream_t stream);
 
+/* (sync) Plan the leaves of a later pipnn_build_leaves call: reads the
+ * offsets, checks the member ids, builds the leaf kernel's work lists on the
+ * device and reserves every scratch buffer of the build. pipnn_build_leaves
+ * with the same d_leaf_offsets, d_leaf_members and n_leaves pointers and
+ * count (and the same leaf configuration) then does no host work, reads
+ * nothing back and allocates nothing, so it may be captured in a HIP graph
+ * and replayed; the caller must not change the offsets or members between
+ * plan and replay (ids are checked here, not again). The plan is replaced
+ * by the next call. ESTATE under stream capture. */
+pipnn_status pipnn_plan_leaves(pipnn_index *idx, const int64_t *d_leaf_offsets,
+                               const uint32_t *d_leaf_members, int64_t n_leaves,
+                               pipnn_stream_t stream);
+
+/* Leaf-kernel configuration of the index: rows_per_item 128 (four waves of
+ * 32 rows) or 64 (two waves; built for operands of 65..128 dimensions), and
+ * persistent 0 (one workgroup per work item, dealt to the XCDs by the host)
+ * or 1 (resident workgroups take the items of their XCD from a device
+ * counter, which balances uneven leaves at run time). Results do not depend
+ * on it. EINVAL for other values or a shape that is not built. */
+pipnn_status pipnn_set_leaf_config(pipnn_index *idx, int32_t rows_per_item, int32_t persistent);
+
+typedef struct {
+  int32_t rows_per_item, persistent;
+  float ms; /* best of the timed runs of the leaf pick on the sample */
+} pipnn_tune_result;
+
+/* (sync) Autotuner of the leaf kernel: times the leaf pick (distance GEMM +
+ * selection, no HashPrune) on the given leaves (the first 2^25 rows' worth)
+ * for every configuration pipnn_set_leaf_config accepts on this index, sets
+ * the fastest, and reports each configuration's time in h_results (up to
+ * cap_results; *h_n_results receives the count). */
+pipnn_status pipnn_autotune(pipnn_index *idx, const int64_t *d_leaf_offsets,
+                            const uint32_t *d_leaf_members, int64_t n_leaves,
+                            pipnn_tune_result *h_results, int32_t cap_results,
+                            int32_t *h_n_results, pipnn_stream_t stream);
+
 /* Pick + Prune_And_Add_Edges for every leaf (Alg. 4, the parallel loop over
  * leaves; Sec. 4.2): per leaf, the distance matrix on MFMA, each member's
  * k nearest co-members by (GEMM distance, id) (or the rescore_mult*k
- * nearest, rescored), the FP32 direct-difference distance of each winner,
- * and both directed records of each picked edge inserted into HashPrune.
+ * nearest, rescored), the FP32 direct-difference distance of each winner
+ * (for the inner product on an operand equal to the data -- FP32, or fp16 /
+ * bf16 data with the same gemm_prec -- the GEMM's own FP32 sum, which has no
+ * norm-expansion cancellation to repair), and both directed records of each
+ * picked edge inserted into HashPrune.
  * d_leaf_offsets/d_leaf_members is any CSR of leaves with ascending member
  * ids (RBC output or explicit leaves); leaves of size 1 contribute nothing.
  * d_reservoirs holds n x l_max uint64 slots (see pipnn_reservoir_init);
  * repeated calls accumulate, and by the history-independence theorem of
  * Sec. 3 the result does not depend on leaf order or call splitting.
- * Reads d_leaf_offsets back to the host once. Ties between equal distances
- * go to the co-member at the smaller position in the leaf, which is the
- * smaller id when leaves are ascending. EINVAL on a leaf of more than 65535
- * points or non-monotone offsets. */
+ * Reads d_leaf_offsets back to the host once, unless the same leaves were
+ * planned (pipnn_plan_leaves): then it only launches device work and may
+ * run under stream capture (it must, if the stream is capturing: ESTATE
+ * otherwise). Ties between equal distances go to the co-member at the
+ * smaller position in the leaf, which is the smaller id when leaves are
+ * ascending. EINVAL on a leaf of more than 65535 points or non-monotone
+ * offsets. */
 pipnn_status pipnn_build_leaves(pipnn_index *idx, const int64_t *d_leaf_offsets,
                                 const uint32_t *d_leaf_members, int64_t n_leaves,
                                 uint64_t *d_reservoirs, pipnn_stream_t stream);

@@ -27,7 +27,8 @@ EXPORTS = [
     "pipnn_hashprune_insert", "pipnn_reservoir_init", "pipnn_reservoir_canonical",
     "pipnn_robustprune", "pipnn_start_node", "pipnn_search", "pipnn_get_sketches",
     "pipnn_knn_block", "pipnn_leaf_pick", "pipnn_prepare", "pipnn_set_profiling",
-    "pipnn_get_stats", "pipnn_get_operand",
+    "pipnn_get_stats", "pipnn_get_operand", "pipnn_plan_leaves", "pipnn_set_leaf_config",
+    "pipnn_autotune",
 ]
 
 
@@ -93,6 +94,9 @@ def lib():
         L.pipnn_set_profiling.argtypes = [P, i32]
         L.pipnn_get_stats.argtypes = [P, C.POINTER(Stats)]
         L.pipnn_get_operand.argtypes = [P, P, P, P, P]
+        L.pipnn_plan_leaves.argtypes = [P, P, P, i64, P]
+        L.pipnn_set_leaf_config.argtypes = [P, i32, i32]
+        L.pipnn_autotune.argtypes = [P, P, P, i64, C.POINTER(TuneResult), i32, C.POINTER(i32), P]
         for name in EXPORTS:
             if name not in ("pipnn_version", "pipnn_last_error", "pipnn_default_params",
                             "pipnn_workspace_bytes", "pipnn_destroy"):
@@ -148,11 +152,15 @@ def _dtype_code(t):
     return {torch.float32: DTYPE_F32, torch.float16: DTYPE_F16, torch.bfloat16: DTYPE_BF16}[t.dtype]
 
 
-def reservoir_init(n: int, l_max: int):
+def reservoir_init(n: int, l_max: int, out=None):
     torch = _torch()
-    res = torch.empty((n, l_max), dtype=torch.int64, device="cuda")
+    res = out if out is not None else torch.empty((n, l_max), dtype=torch.int64, device="cuda")
     _check(lib().pipnn_reservoir_init(_ptr(res), n, l_max, _stream()))
     return res
+
+
+class TuneResult(C.Structure):
+    _fields_ = [("rows_per_item", C.c_int32), ("persistent", C.c_int32), ("ms", C.c_float)]
 
 
 class Index:
@@ -193,6 +201,24 @@ class Index:
         _check(lib().pipnn_get_stats(self._h, C.byref(st)))
         return st.as_dict()
 
+    def plan_leaves(self, offsets, members):
+        """Plan these leaves so that build_leaves on them can be captured."""
+        _check(lib().pipnn_plan_leaves(self._h, _ptr(offsets), _ptr(members),
+                                       offsets.numel() - 1, _stream()))
+
+    def set_leaf_config(self, rows_per_item: int = 128, persistent: bool = False):
+        _check(lib().pipnn_set_leaf_config(self._h, rows_per_item, 1 if persistent else 0))
+
+    def autotune(self, offsets, members):
+        """Time every leaf-kernel configuration on these leaves and keep the
+        fastest; returns [(rows_per_item, persistent, ms), ...]."""
+        out = (TuneResult * 8)()
+        cnt = C.c_int32()
+        _check(lib().pipnn_autotune(self._h, _ptr(offsets), _ptr(members), offsets.numel() - 1,
+                                    out, 8, C.byref(cnt), _stream()))
+        return [(out[i].rows_per_item, bool(out[i].persistent), out[i].ms)
+                for i in range(cnt.value)]
+
     def partition(self):
         torch = _torch()
         nl, nm = C.c_int64(), C.c_int64()
@@ -225,10 +251,12 @@ class Index:
         _check(lib().pipnn_reservoir_canonical(self._h, _ptr(res), _ptr(out), _stream()))
         return out
 
-    def robustprune(self, reservoirs):
+    def robustprune(self, reservoirs, graph=None, degree=None):
         torch = _torch()
-        g = torch.empty((self.n, self.params.R), dtype=torch.int32, device="cuda")
-        deg = torch.empty(self.n, dtype=torch.int32, device="cuda")
+        g = graph if graph is not None else torch.empty((self.n, self.params.R),
+                                                        dtype=torch.int32, device="cuda")
+        deg = degree if degree is not None else torch.empty(self.n, dtype=torch.int32,
+                                                            device="cuda")
         _check(lib().pipnn_robustprune(self._h, _ptr(reservoirs), _ptr(g), _ptr(deg), _stream()))
         return g, deg
 

@@ -37,6 +37,17 @@ pipnn_status fail(pipnn_status st, const char *fmt, ...) {
                   #expr, hipGetErrorString(e_));                                              \
   } while (0)
 
+}  // namespace
+
+namespace pipnn {
+bool stream_capturing(hipStream_t s) {
+  hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+  return hipStreamIsCapturing(s, &st) == hipSuccess && st == hipStreamCaptureStatusActive;
+}
+}  // namespace pipnn
+
+namespace {
+
 #define GUARD_BEGIN try {
 #define GUARD_END                                                    \
   }                                                                  \
@@ -125,7 +136,6 @@ hipError_t upload(DevBuf &b, const std::vector<T> &v, hipStream_t s) {
   return hipMemcpyAsync(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s);
 }
 
-constexpr int kKnnRows = 128;  // rows per knn work item (32 per wave x 4 waves)
 constexpr int kGroupTile = 1024;
 
 // Work items of a knn launch in launch order: block b runs on XCD b % 8 and
@@ -133,7 +143,8 @@ constexpr int kGroupTile = 1024;
 // at most 16 row blocks goes whole to the least-loaded XCD (its columns stay
 // in that XCD's L2), the row blocks of a larger job are dealt one by one to
 // the least-loaded XCD. Shorter XCD lists are padded with idle items.
-std::vector<KnnItem> plan_items(const std::vector<KnnJob> &jobs) {
+std::vector<KnnItem> plan_items(const std::vector<KnnJob> &jobs, int rows_per_item = 128) {
+  const int kKnnRows = rows_per_item;
   constexpr int X = kNumXcd;
   std::vector<int> order(jobs.size());
   for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
@@ -211,7 +222,7 @@ static hipEvent_t take_event(Index &I) {
 }
 
 PhaseTimer::PhaseTimer(Index &I_, int ph, hipStream_t s_) : I(I_), phase(ph), s(s_) {
-  if (!I.profiling) return;
+  if (!I.profiling || stream_capturing(s)) return;
   a = take_event(I);
   if (a) (void)hipEventRecord(a, s);
 }
@@ -315,7 +326,18 @@ pipnn_status pipnn_create(const pipnn_params *p, const void *d_X, int64_t n, int
     return st;
   };
   hipError_t e;
-  if ((e = I->sketches.ensure((size_t)n * I->m * 4)) != hipSuccess ||
+  {
+    int dev = 0, ncu = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+        ncu >= kNumXcd)
+      I->n_cu = ncu;
+  }
+  if (p->gemm_prec == PIPNN_PREC_FP32 && knn_operand_dim(d, PIPNN_PREC_FP32) == 0)
+    return cleanup(fail(PIPNN_EINVAL, "a float32 leaf GEMM needs d <= 256 (use a reduced "
+                                      "gemm_prec for wider vectors)"));
+  if ((e = I->s_counter.ensure(64)) != hipSuccess ||
+      (e = I->sketches.ensure((size_t)n * I->m * 4)) != hipSuccess ||
       (e = I->norms.ensure((size_t)n * 4)) != hipSuccess ||
       (e = I->flag.ensure(64)) != hipSuccess)
     return cleanup(fail(PIPNN_ENOMEM, "device allocation failed: %s", hipGetErrorString(e)));
@@ -330,7 +352,7 @@ pipnn_status pipnn_create(const pipnn_params *p, const void *d_X, int64_t n, int
   if (p->gemm_prec != PIPNN_PREC_FP32) {
     I->ldo = lowp_padded_dim(d);
     if (I->ldo == 0)
-      return cleanup(fail(PIPNN_EINVAL, "a reduced-precision leaf GEMM needs d <= 256"));
+      return cleanup(fail(PIPNN_EINVAL, "a reduced-precision leaf GEMM needs d <= 768"));
     const size_t eb = p->gemm_prec == PIPNN_PREC_FP8 ? 1 : 2;
     if ((e = I->xlow.ensure((size_t)n * I->ldo * eb)) != hipSuccess ||
         (e = I->xscale.ensure((size_t)n * 4)) != hipSuccess ||
@@ -351,12 +373,16 @@ void pipnn_destroy(pipnn_index *idx) {
   Index *I = reinterpret_cast<Index *>(idx);
   (void)hipDeviceSynchronize();
   for (DevBuf *b : {&I->rp_order, &I->o_first, &I->o_flag, &I->o_pos, &I->o_pos2, &I->o_tmp,
-                    &I->xf32, &I->xlow, &I->xscale, &I->lnorms, &I->sketches, &I->norms, &I->flag, &I->s_jobs,
+                    &I->xf32, &I->xlow, &I->xscale, &I->lnorms, &I->s_counter, &I->sketches, &I->norms, &I->flag, &I->s_jobs,
                     &I->s_items, &I->s_picks_c, &I->s_picks_d, &I->s_cnt, &I->s_off, &I->s_bins,
                     &I->s_tmp0, &I->s_tmp1, &I->p_asg, &I->p_leaders, &I->p_cm, &I->p_bstart,
                     &I->p_groups, &I->p_gout, &I->p_gsize, &I->p_copy})
     b->release();
   for (DevBuf &b : I->levels) b.release();
+  for (auto &b : I->plan.batches) {
+    b.jobs.release();
+    b.items.release();
+  }
   for (DevBuf &b : I->ppool) b.release();
   for (auto &e : I->events) {
     (void)hipEventDestroy(e.a);
@@ -377,6 +403,13 @@ pipnn_status pipnn_partition(pipnn_index *idx, int64_t *d_leaf_offsets, int64_t 
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   const pipnn_params &P = I.p;
   const int64_t n = I.n;
+  // point-to-leader distances in float32 where the float32 kernel is built
+  // (d <= 256), else on the index's reduced-precision operand
+  const int32_t part_prec =
+      knn_operand_dim(I.d, PIPNN_PREC_FP32) ? PIPNN_PREC_FP32 : P.gemm_prec;
+  if (knn_operand_dim(I.d, part_prec) == 0)
+    return fail(PIPNN_EINVAL, "partition of d = %d needs a reduced gemm_prec (float32 partition "
+                              "distances are built for d <= 256)", I.d);
 
   struct Sub {
     int64_t row_off, cnt;
@@ -455,7 +488,7 @@ pipnn_status pipnn_partition(pipnn_index *idx, int64_t *d_leaf_offsets, int64_t 
     HIPCHK(I.p_leaders.ensure(lead_idx.size() * 4));
     HIPCHK(launch_gather_u32(A->as<uint32_t>(), I.s_tmp1.as<int64_t>(), I.p_leaders.as<uint32_t>(),
                              (int64_t)lead_idx.size(), s));
-    items = plan_items(jobs);
+    items = plan_items(jobs, 128);
     HIPCHK(upload(I.s_jobs, jobs, s));
     HIPCHK(upload(I.s_items, items, s));
     HIPCHK(I.p_asg.ensure((size_t)inst * fmax * 4));
@@ -471,7 +504,9 @@ pipnn_status pipnn_partition(pipnn_index *idx, int64_t *d_leaf_offsets, int64_t 
     L.out_ids = 0;
     L.recompute = 0;
     L.rescore_k = 0;
-    L.prec = PIPNN_PREC_FP32;
+    L.prec = part_prec;
+    L.nw = 4;
+    L.persistent = 0;
     L.out_col = I.p_asg.as<uint32_t>();
     L.out_dist = nullptr;
     L.out_matrix = nullptr;
@@ -693,14 +728,26 @@ pipnn_status read_offsets(const int64_t *d_off, int64_t n_leaves, hipStream_t s,
   return PIPNN_OK;
 }
 
-// Run the pick on leaves [l0, l1) into picks indexed from offs[l0].
-pipnn_status run_pick(Index &I, const std::vector<int64_t> &offs, int64_t l0, int64_t l1,
-                      const uint32_t *d_members, uint32_t *pick_c, float *pick_d, hipStream_t s) {
+// True when the leaf GEMM's distance already is a direct FP32 evaluation:
+// the inner product (no norm expansion, hence no cancellation) on an
+// operand that holds the data exactly. The winners are then not recomputed.
+static bool gemm_is_direct(const Index &I) {
+  if (I.p.metric != PIPNN_METRIC_IP) return false;
+  return I.p.gemm_prec == PIPNN_PREC_FP32 ||
+         (I.p.gemm_prec == PIPNN_PREC_FP16 && I.x_dtype == PIPNN_DTYPE_F16) ||
+         (I.p.gemm_prec == PIPNN_PREC_BF16 && I.x_dtype == PIPNN_DTYPE_BF16);
+}
+
+// Work list of the pick on leaves [l0, l1) (rows indexed from offs[l0]),
+// uploaded into jobs_buf / items_buf.
+pipnn_status plan_pick(Index &I, const std::vector<int64_t> &offs, int64_t l0, int64_t l1,
+                       DevBuf &jobs_buf, DevBuf &items_buf, int32_t &n_items, int32_t &max_cols,
+                       int64_t &pairs, hipStream_t s) {
   const pipnn_params &P = I.p;
   const int ksel = P.rescore_mult ? P.rescore_mult * P.k : P.k;
   std::vector<KnnJob> jobs;
-  std::vector<KnnItem> items;
-  int32_t max_cols = 0;
+  max_cols = 0;
+  pairs = 0;
   const int64_t base = offs[(size_t)l0];
   for (int64_t l = l0; l < l1; ++l) {
     const int64_t sz = offs[(size_t)l + 1] - offs[(size_t)l];
@@ -715,28 +762,43 @@ pipnn_status run_pick(Index &I, const std::vector<int64_t> &offs, int64_t l0, in
     J.flags = 1;
     jobs.push_back(J);
     max_cols = std::max<int32_t>(max_cols, (int32_t)sz);
+    pairs += sz * sz;
   }
-  const int64_t rows = offs[(size_t)l1] - base;
+  n_items = 0;
+  if (jobs.empty()) return PIPNN_OK;
+  std::vector<KnnItem> items = plan_items(jobs, 32 * I.leaf_nw);
+  HIPCHK(upload(jobs_buf, jobs, s));
+  HIPCHK(upload(items_buf, items, s));
+  n_items = (int32_t)items.size();
+  return PIPNN_OK;
+}
+
+// The pick on a planned work list: clears the picks of `rows` rows, then
+// one leaf-kernel launch.
+pipnn_status launch_pick(Index &I, const KnnJob *d_jobs, const KnnItem *d_items, int32_t n_items,
+                         int32_t max_cols, int64_t rows, const uint32_t *d_members,
+                         uint32_t *pick_c, float *pick_d, hipStream_t s) {
+  const pipnn_params &P = I.p;
+  const int ksel = P.rescore_mult ? P.rescore_mult * P.k : P.k;
   HIPCHK(launch_fill_u32(pick_c, kEmptyId, rows * P.k, s));
   HIPCHK(launch_fill_u32(reinterpret_cast<uint32_t *>(pick_d), 0x7F800000u, rows * P.k, s));
-  if (jobs.empty()) return PIPNN_OK;
-  items = plan_items(jobs);
-  HIPCHK(upload(I.s_jobs, jobs, s));
-  HIPCHK(upload(I.s_items, items, s));
+  if (n_items == 0) return PIPNN_OK;
   KnnLaunch L{};
   L.idx = &I;
   L.row_base = d_members;
   L.col_base = d_members;
-  L.jobs = I.s_jobs.as<KnnJob>();
-  L.items = I.s_items.as<KnnItem>();
-  L.n_items = (int32_t)items.size();
+  L.jobs = d_jobs;
+  L.items = d_items;
+  L.n_items = n_items;
   L.max_cols = max_cols;
   L.ksel = ksel;
   L.k_out = P.k;
   L.out_ids = 1;
-  L.recompute = 1;
+  L.recompute = gemm_is_direct(I) ? 0 : 1;
   L.rescore_k = P.rescore_mult ? P.k : 0;
   L.prec = P.gemm_prec;
+  L.nw = I.leaf_nw;
+  L.persistent = I.leaf_persistent;
   L.out_col = pick_c;
   L.out_dist = pick_d;
   L.out_matrix = nullptr;
@@ -745,11 +807,21 @@ pipnn_status run_pick(Index &I, const std::vector<int64_t> &offs, int64_t l0, in
     HIPCHK(launch_knn(L, s));
   }
   ++I.leaf_launches;
-  for (int64_t l = l0; l < l1; ++l) {
-    const int64_t sz = offs[(size_t)l + 1] - offs[(size_t)l];
-    if (sz >= 2) I.stats.leaf_pairs += sz * sz;
-  }
   return PIPNN_OK;
+}
+
+// Run the pick on leaves [l0, l1) into picks indexed from offs[l0].
+pipnn_status run_pick(Index &I, const std::vector<int64_t> &offs, int64_t l0, int64_t l1,
+                      const uint32_t *d_members, uint32_t *pick_c, float *pick_d, hipStream_t s) {
+  int32_t n_items = 0, max_cols = 0;
+  int64_t pairs = 0;
+  pipnn_status st = plan_pick(I, offs, l0, l1, I.s_jobs, I.s_items, n_items, max_cols, pairs, s);
+  if (st != PIPNN_OK) return st;
+  const int64_t rows = offs[(size_t)l1] - offs[(size_t)l0];
+  st = launch_pick(I, I.s_jobs.as<KnnJob>(), I.s_items.as<KnnItem>(), n_items, max_cols, rows,
+                   d_members, pick_c, pick_d, s);
+  I.stats.leaf_pairs += pairs;
+  return st;
 }
 
 // Bin records by destination and merge them into the reservoirs.
@@ -765,14 +837,14 @@ pipnn_status bin_and_merge(Index &I, bool from_picks, const uint32_t *a, const u
   HIPCHK(I.s_bins.ensure((size_t)std::max<int64_t>(max_rec, 1) * 8));
   {
     PhaseTimer tb(I, kPhBin, s);
-    HIPCHK(hipMemsetAsync(I.s_cnt.p, 0, (size_t)n * 4, s));
+    HIPCHK(launch_fill_u32(I.s_cnt.as<uint32_t>(), 0u, n, s));
     if (from_picks)
       HIPCHK(launch_bin_count(a, b, count, k, I.s_cnt.as<uint32_t>(), n, I.flag.as<int32_t>(), s));
     else
       HIPCHK(launch_rec_count(a, b, count, I.s_cnt.as<uint32_t>(), n, I.flag.as<int32_t>(), s));
     HIPCHK(launch_scan_u32(I.s_cnt.as<uint32_t>(), I.s_off.as<int64_t>(), n,
                            I.s_tmp0.as<int64_t>(), s));
-    HIPCHK(hipMemsetAsync(I.s_cnt.p, 0, (size_t)n * 4, s));
+    HIPCHK(launch_fill_u32(I.s_cnt.as<uint32_t>(), 0u, n, s));
     if (from_picks)
       HIPCHK(launch_bin_scatter(a, b, dist, count, k, I.sketches.as<float>(), I.m,
                                 I.s_off.as<int64_t>(), I.s_cnt.as<uint32_t>(),
@@ -826,6 +898,102 @@ pipnn_status check_ids(Index &I, const uint32_t *ids, int64_t cnt, hipStream_t s
 
 }  // namespace
 
+// Batches of leaves bounded in picks, so that scratch stays bounded.
+static std::vector<std::pair<int64_t, int64_t>> leaf_batches(const std::vector<int64_t> &offs,
+                                                             int64_t n_leaves) {
+  const int64_t max_rows = (int64_t)1 << 25;
+  std::vector<std::pair<int64_t, int64_t>> out;
+  int64_t l0 = 0;
+  while (l0 < n_leaves) {
+    int64_t l1 = l0 + 1;
+    while (l1 < n_leaves && offs[(size_t)l1 + 1] - offs[(size_t)l0] <= max_rows) ++l1;
+    out.push_back({l0, l1});
+    l0 = l1;
+  }
+  return out;
+}
+
+// Device scratch of a build over these batches, allocated up front so that
+// a planned build allocates nothing.
+static pipnn_status reserve_build(Index &I, const std::vector<int64_t> &offs,
+                                  const std::vector<std::pair<int64_t, int64_t>> &batches,
+                                  int64_t n_leaves) {
+  const int k = I.p.k;
+  int64_t max_rows = 1;
+  for (auto &b : batches)
+    max_rows = std::max<int64_t>(max_rows, offs[(size_t)b.second] - offs[(size_t)b.first]);
+  const int64_t n = I.n;
+  HIPCHK(I.s_picks_c.ensure((size_t)max_rows * k * 4));
+  HIPCHK(I.s_picks_d.ensure((size_t)max_rows * k * 4));
+  HIPCHK(I.s_cnt.ensure((size_t)n * 4));
+  HIPCHK(I.s_off.ensure((size_t)(n + 1) * 8));
+  HIPCHK(I.s_tmp0.ensure((size_t)scan_tmp_elems(n) * 8));
+  HIPCHK(I.s_bins.ensure((size_t)2 * max_rows * k * 8));
+  const int64_t cnt = offs[(size_t)n_leaves] - offs[0];
+  const int64_t mx = std::max<int64_t>(cnt, n);
+  HIPCHK(I.o_first.ensure((size_t)n * 4));
+  HIPCHK(I.o_flag.ensure((size_t)mx * 4));
+  HIPCHK(I.o_pos.ensure((size_t)(mx + 1) * 8));
+  HIPCHK(I.o_pos2.ensure((size_t)(n + 1) * 8));
+  HIPCHK(I.o_tmp.ensure((size_t)scan_tmp_elems(mx) * 8));
+  HIPCHK(I.rp_order.ensure((size_t)n * 4));
+  return PIPNN_OK;
+}
+
+// RobustPrune processing order: points in leaf order.
+static pipnn_status leaf_order(Index &I, const uint32_t *d_members, int64_t cnt, hipStream_t s) {
+  HIPCHK(launch_leaf_order(d_members, cnt, I.n, I.o_first.as<uint32_t>(),
+                           I.o_flag.as<uint32_t>(), I.o_pos.as<int64_t>(),
+                           I.o_pos2.as<int64_t>(), I.o_tmp.as<int64_t>(),
+                           I.rp_order.as<uint32_t>(), s));
+  I.rp_order_valid = true;
+  return PIPNN_OK;
+}
+
+static bool plan_matches(const Index &I, const int64_t *d_off, const uint32_t *d_mem,
+                         int64_t n_leaves) {
+  return I.plan.n_leaves == n_leaves && I.plan.d_off == d_off && I.plan.d_mem == d_mem &&
+         I.plan.nw == I.leaf_nw;
+}
+
+pipnn_status pipnn_plan_leaves(pipnn_index *idx, const int64_t *d_leaf_offsets,
+                               const uint32_t *d_leaf_members, int64_t n_leaves,
+                               pipnn_stream_t stream) {
+  GUARD_BEGIN
+  if (!idx || !d_leaf_offsets || !d_leaf_members || n_leaves < 1)
+    return fail(PIPNN_EINVAL, "invalid argument");
+  Index &I = *reinterpret_cast<Index *>(idx);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  if (stream_capturing(s)) return fail(PIPNN_ESTATE, "plan_leaves cannot run under capture");
+  Index::LeafPlan &P = I.plan;
+  P.n_leaves = -1;
+  pipnn_status st = read_offsets(d_leaf_offsets, n_leaves, s, P.offs);
+  if (st != PIPNN_OK) return st;
+  st = check_ids(I, d_leaf_members + P.offs[0], P.offs[(size_t)n_leaves] - P.offs[0], s,
+                 "plan_leaves");
+  if (st != PIPNN_OK) return st;
+  auto batches = leaf_batches(P.offs, n_leaves);
+  st = reserve_build(I, P.offs, batches, n_leaves);
+  if (st != PIPNN_OK) return st;
+  while (P.batches.size() < batches.size()) P.batches.emplace_back();
+  for (size_t i = 0; i < batches.size(); ++i) {
+    Index::PlanBatch &B = P.batches[i];
+    B.l0 = batches[i].first;
+    B.l1 = batches[i].second;
+    B.rows = P.offs[(size_t)B.l1] - P.offs[(size_t)B.l0];
+    st = plan_pick(I, P.offs, B.l0, B.l1, B.jobs, B.items, B.n_items, B.max_cols, B.pairs, s);
+    if (st != PIPNN_OK) return st;
+  }
+  HIPCHK(hipStreamSynchronize(s));  // the host work lists may be released now
+  P.batches.resize(batches.size());
+  P.d_off = d_leaf_offsets;
+  P.d_mem = d_leaf_members;
+  P.n_leaves = n_leaves;
+  P.nw = I.leaf_nw;
+  return PIPNN_OK;
+  GUARD_END
+}
+
 pipnn_status pipnn_build_leaves(pipnn_index *idx, const int64_t *d_leaf_offsets,
                                 const uint32_t *d_leaf_members, int64_t n_leaves,
                                 uint64_t *d_reservoirs, pipnn_stream_t stream) {
@@ -836,52 +1004,151 @@ pipnn_status pipnn_build_leaves(pipnn_index *idx, const int64_t *d_leaf_offsets,
   if (!d_leaf_members) return fail(PIPNN_EINVAL, "members is NULL");
   Index &I = *reinterpret_cast<Index *>(idx);
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  std::vector<int64_t> offs;
-  pipnn_status st = read_offsets(d_leaf_offsets, n_leaves, s, offs);
-  if (st != PIPNN_OK) return st;
   const int k = I.p.k;
+  const bool capturing = stream_capturing(s);
+  const bool planned = plan_matches(I, d_leaf_offsets, d_leaf_members, n_leaves);
+  if (capturing && !planned)
+    return fail(PIPNN_ESTATE, "build_leaves under stream capture needs pipnn_plan_leaves on the "
+                              "same offsets, members and leaf count first");
+  pipnn_status st;
+  if (planned) {
+    // the planned path: device work only
+    const Index::LeafPlan &P = I.plan;
+    if (!capturing) {
+      I.stats.leaf_pairs = 0;
+      I.stats.records = 0;
+    }
+    for (size_t i = 0; i < P.batches.size(); ++i) {
+      const Index::PlanBatch &B = P.batches[i];
+      st = launch_pick(I, B.jobs.as<KnnJob>(), B.items.as<KnnItem>(), B.n_items, B.max_cols,
+                       B.rows, d_leaf_members, I.s_picks_c.as<uint32_t>(),
+                       I.s_picks_d.as<float>(), s);
+      if (st != PIPNN_OK) return st;
+      if (!capturing) I.stats.leaf_pairs += B.pairs;
+      st = bin_and_merge(I, true, d_leaf_members + P.offs[(size_t)B.l0],
+                         I.s_picks_c.as<uint32_t>(), I.s_picks_d.as<float>(), B.rows, k,
+                         d_reservoirs, s);
+      if (st != PIPNN_OK) return st;
+      if (!capturing && i + 1 < P.batches.size()) {
+        st = finish_bins(I, s, "build_leaves");
+        if (st != PIPNN_OK) return st;
+      }
+    }
+    st = leaf_order(I, d_leaf_members + P.offs[0], P.offs[(size_t)n_leaves] - P.offs[0], s);
+    if (st != PIPNN_OK) return st;
+    return capturing ? PIPNN_OK : finish_bins(I, s, "build_leaves");
+  }
+  std::vector<int64_t> offs;
+  st = read_offsets(d_leaf_offsets, n_leaves, s, offs);
+  if (st != PIPNN_OK) return st;
   I.stats.leaf_pairs = 0;
   I.stats.records = 0;
   st = check_ids(I, d_leaf_members + offs[0], offs[(size_t)n_leaves] - offs[0], s, "build_leaves");
   if (st != PIPNN_OK) return st;
-  // batches of leaves bounded in picks, so scratch stays bounded
-  const int64_t max_rows = std::max<int64_t>((int64_t)1 << 25, 65536);
-  int64_t l0 = 0;
-  while (l0 < n_leaves) {
-    int64_t l1 = l0 + 1;
-    while (l1 < n_leaves && offs[(size_t)l1 + 1] - offs[(size_t)l0] <= max_rows) ++l1;
+  auto batches = leaf_batches(offs, n_leaves);
+  st = reserve_build(I, offs, batches, n_leaves);
+  if (st != PIPNN_OK) return st;
+  for (size_t i = 0; i < batches.size(); ++i) {
+    const int64_t l0 = batches[i].first, l1 = batches[i].second;
     const int64_t rows = offs[(size_t)l1] - offs[(size_t)l0];
-    HIPCHK(I.s_picks_c.ensure((size_t)std::max<int64_t>(rows, 1) * k * 4));
-    HIPCHK(I.s_picks_d.ensure((size_t)std::max<int64_t>(rows, 1) * k * 4));
     st = run_pick(I, offs, l0, l1, d_leaf_members, I.s_picks_c.as<uint32_t>(),
                   I.s_picks_d.as<float>(), s);
     if (st != PIPNN_OK) return st;
     st = bin_and_merge(I, true, d_leaf_members + offs[(size_t)l0], I.s_picks_c.as<uint32_t>(),
                        I.s_picks_d.as<float>(), rows, k, d_reservoirs, s);
     if (st != PIPNN_OK) return st;
-    if (l1 < n_leaves) {
+    if (i + 1 < batches.size()) {
       st = finish_bins(I, s, "build_leaves");
       if (st != PIPNN_OK) return st;
     }
-    l0 = l1;
   }
-  {
-    // processing order of the final prune: points in leaf order
-    const int64_t cnt = offs[(size_t)n_leaves] - offs[0];
-    const int64_t mx = std::max<int64_t>(cnt, I.n);
-    HIPCHK(I.o_first.ensure((size_t)I.n * 4));
-    HIPCHK(I.o_flag.ensure((size_t)mx * 4));
-    HIPCHK(I.o_pos.ensure((size_t)(mx + 1) * 8));
-    HIPCHK(I.o_pos2.ensure((size_t)(I.n + 1) * 8));
-    HIPCHK(I.o_tmp.ensure((size_t)scan_tmp_elems(mx) * 8));
-    HIPCHK(I.rp_order.ensure((size_t)I.n * 4));
-    HIPCHK(launch_leaf_order(d_leaf_members + offs[0], cnt, I.n, I.o_first.as<uint32_t>(),
-                             I.o_flag.as<uint32_t>(), I.o_pos.as<int64_t>(),
-                             I.o_pos2.as<int64_t>(), I.o_tmp.as<int64_t>(),
-                             I.rp_order.as<uint32_t>(), s));
-    I.rp_order_valid = true;
-  }
+  st = leaf_order(I, d_leaf_members + offs[0], offs[(size_t)n_leaves] - offs[0], s);
+  if (st != PIPNN_OK) return st;
   return finish_bins(I, s, "build_leaves");
+  GUARD_END
+}
+
+pipnn_status pipnn_set_leaf_config(pipnn_index *idx, int32_t rows_per_item, int32_t persistent) {
+  GUARD_BEGIN
+  if (!idx) return fail(PIPNN_EINVAL, "NULL index");
+  Index &I = *reinterpret_cast<Index *>(idx);
+  if ((rows_per_item != 64 && rows_per_item != 128) || (persistent != 0 && persistent != 1))
+    return fail(PIPNN_EINVAL, "rows_per_item must be 64 or 128 and persistent 0 or 1");
+  if (!knn_nw_available(I.d, I.p.gemm_prec, rows_per_item / 32))
+    return fail(PIPNN_EINVAL, "%d-row work items are not built for this operand width",
+                rows_per_item);
+  I.leaf_nw = rows_per_item / 32;
+  I.leaf_persistent = persistent;
+  return PIPNN_OK;
+  GUARD_END
+}
+
+pipnn_status pipnn_autotune(pipnn_index *idx, const int64_t *d_leaf_offsets,
+                            const uint32_t *d_leaf_members, int64_t n_leaves,
+                            pipnn_tune_result *h_results, int32_t cap_results,
+                            int32_t *h_n_results, pipnn_stream_t stream) {
+  GUARD_BEGIN
+  if (!idx || !d_leaf_offsets || !d_leaf_members || n_leaves < 1)
+    return fail(PIPNN_EINVAL, "invalid argument");
+  Index &I = *reinterpret_cast<Index *>(idx);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  if (stream_capturing(s)) return fail(PIPNN_ESTATE, "autotune cannot run under capture");
+  std::vector<int64_t> offs;
+  pipnn_status st = read_offsets(d_leaf_offsets, n_leaves, s, offs);
+  if (st != PIPNN_OK) return st;
+  st = check_ids(I, d_leaf_members + offs[0], offs[(size_t)n_leaves] - offs[0], s, "autotune");
+  if (st != PIPNN_OK) return st;
+  // the first batch of leaves is the sample
+  auto batches = leaf_batches(offs, n_leaves);
+  const int64_t l0 = batches[0].first, l1 = batches[0].second;
+  const int64_t rows = offs[(size_t)l1] - offs[(size_t)l0];
+  HIPCHK(I.s_picks_c.ensure((size_t)std::max<int64_t>(rows, 1) * I.p.k * 4));
+  HIPCHK(I.s_picks_d.ensure((size_t)std::max<int64_t>(rows, 1) * I.p.k * 4));
+  std::vector<pipnn_tune_result> res;
+  for (int nw : {4, 2})
+    for (int pers : {0, 1})
+      if (knn_nw_available(I.d, I.p.gemm_prec, nw)) res.push_back({32 * nw, pers, 0.f});
+  const int32_t keep_nw = I.leaf_nw, keep_pers = I.leaf_persistent;
+  const bool keep_prof = I.profiling;
+  I.profiling = false;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  pipnn_status rs = PIPNN_OK;
+  for (auto &r : res) {
+    I.leaf_nw = r.rows_per_item / 32;
+    I.leaf_persistent = r.persistent;
+    float best = 1e30f;
+    for (int rep = 0; rep < 3 && rs == PIPNN_OK; ++rep) {
+      (void)hipEventRecord(e0, s);
+      rs = run_pick(I, offs, l0, l1, d_leaf_members + 0, I.s_picks_c.as<uint32_t>(),
+                    I.s_picks_d.as<float>(), s);
+      (void)hipEventRecord(e1, s);
+      if (hipEventSynchronize(e1) != hipSuccess) rs = fail(PIPNN_EDEVICE, "autotune timing failed");
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      if (rep > 0) best = std::min(best, ms);  // the first run warms up
+    }
+    r.ms = best;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  I.profiling = keep_prof;
+  I.stats.leaf_pairs = 0;
+  if (rs != PIPNN_OK) {
+    I.leaf_nw = keep_nw;
+    I.leaf_persistent = keep_pers;
+    return rs;
+  }
+  size_t bi = 0;
+  for (size_t i = 1; i < res.size(); ++i)
+    if (res[i].ms < res[bi].ms) bi = i;
+  I.leaf_nw = res[bi].rows_per_item / 32;
+  I.leaf_persistent = res[bi].persistent;
+  if (h_n_results) *h_n_results = (int32_t)res.size();
+  if (h_results)
+    for (size_t i = 0; i < res.size() && (int32_t)i < cap_results; ++i) h_results[i] = res[i];
+  return PIPNN_OK;
   GUARD_END
 }
 
@@ -929,7 +1196,7 @@ pipnn_status pipnn_knn_block(pipnn_index *idx, const uint32_t *d_row_ids, int64_
   jobs[0].n_cols = (int32_t)n_cols;
   jobs[0].k_sel = ksel;
   jobs[0].flags = exclude_diag ? 1 : 0;
-  std::vector<KnnItem> items = plan_items(jobs);
+  std::vector<KnnItem> items = plan_items(jobs, 32 * I.leaf_nw);
   HIPCHK(upload(I.s_jobs, jobs, s));
   HIPCHK(upload(I.s_items, items, s));
   KnnLaunch L{};
@@ -943,9 +1210,11 @@ pipnn_status pipnn_knn_block(pipnn_index *idx, const uint32_t *d_row_ids, int64_
   L.ksel = ksel;
   L.k_out = k;
   L.out_ids = 0;
-  L.recompute = 1;
+  L.recompute = gemm_is_direct(I) ? 0 : 1;
   L.rescore_k = I.p.rescore_mult ? k : 0;
   L.prec = I.p.gemm_prec;
+  L.nw = I.leaf_nw;
+  L.persistent = I.leaf_persistent;
   L.out_col = d_out_col;
   L.out_dist = d_out_dist;
   L.out_matrix = d_out_matrix;

@@ -287,6 +287,171 @@ __global__ void __launch_bounds__(64 * kRpWaves) robustprune_mfma_kernel(
   if (lane == 0) degree[x] = (uint32_t)ne;
 }
 
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+
+template <int PREC>
+__device__ __forceinline__ f32x4 rp_mfma16(uint4 a, uint4 b, f32x4 acc) {
+  if constexpr (PREC == PIPNN_PREC_BF16)
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
+                                                    __builtin_bit_cast(bf16x8, b), acc, 0, 0, 0);
+  else
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(f16x8, a),
+                                                   __builtin_bit_cast(f16x8, b), acc, 0, 0, 0);
+}
+
+// Upper-triangle index of the candidate Gram, y <= z, packed by column.
+__device__ __forceinline__ int tri_idx(int y, int z) {
+  return y <= z ? z * (z + 1) / 2 + y : y * (y + 1) / 2 + z;
+}
+
+// RobustPrune for wide operands (512 or 768 dimensions, the index's bf16 /
+// fp16 GEMM operand; up to 111 reservoir candidates, R <= 64). One wave per
+// point x. Rows are x and its candidates (reservoir order); their Gram
+// G = C C^T is accumulated on 16x16x32 MFMAs, all block pairs i <= j, with
+// the rows staged through LDS 64 dimensions at a time; the upper triangle
+// of G is kept in LDS. Distances are the GEMM form of the operand:
+// d(y,z) = G[y][y] + G[z][z] - 2 G[y][z] (squared L2) or -G[y][z] (inner
+// product). The candidates are ranked by (d(x,c), id) by counting, then
+// walked in that order: z is admitted unless an admitted y has
+// alpha * d(y,z) < d(x,z) (the sign of a fused multiply-add), until R are
+// admitted -- the lazy form of Alg. 2.
+constexpr int kRpwRows = 112;  // x + up to 111 candidates: 7 blocks of 16
+constexpr int kRpwKC = 64;     // dimensions per staged chunk
+constexpr int kRpwTri = kRpwRows * (kRpwRows + 1) / 2;
+
+template <int PREC, int DP, bool L2>
+__global__ void __launch_bounds__(256, 1) robustprune_wide_kernel(
+    const uint8_t *__restrict__ Xop, int64_t op_ld, int64_t n, const uint64_t *__restrict__ res,
+    int l_max, float alpha, int R, const uint32_t *__restrict__ order, uint32_t *__restrict__ graph,
+    uint32_t *__restrict__ degree) {
+  constexpr int LROW = kRpwKC + 8;  // staged row stride (16-bit elements)
+  constexpr int NCHUNK = DP / kRpwKC;
+  static_assert(kRpwRows * LROW / 2 <= kRpwTri, "staging fits in the Gram region");
+  __shared__ uint32_t sW[kRpWaves][kRpwTri];
+  __shared__ uint32_t sId[kRpWaves][kRpwRows];
+  __shared__ uint32_t sPos[kRpWaves][kRpwRows];
+  __shared__ uint64_t sKey[kRpWaves][kRpwRows];
+  __shared__ float sDx[kRpWaves][kRpwRows];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t item = (int64_t)xcd_item(blockIdx.x, gridDim.x) * kRpWaves + wave;
+  if (item >= n) return;
+  const uint32_t x = __builtin_amdgcn_readfirstlane(order ? order[item] : (uint32_t)item);
+  uint32_t *W = sW[wave];
+  uint32_t *ids = sId[wave];
+
+  // 1. rows: x, then the valid reservoir candidates in slot order
+  if (lane == 0) ids[0] = x;
+  int M = 0;
+  for (int b = 0; b < l_max; b += 64) {
+    const int i = b + lane;
+    uint32_t c = kEmptyId;
+    if (i < l_max) c = slot_id(res[(int64_t)x * l_max + i]);
+    const bool ok = i < l_max && c != kEmptyId && c != x && c < n;
+    const uint64_t m = __ballot(ok);
+    const int pos = __popcll(m & ((lane == 0) ? 0ull : (~0ull >> (64 - lane))));
+    if (ok && 1 + M + pos < kRpwRows) ids[1 + M + pos] = c;
+    M += __popcll(m);
+  }
+  if (M > kRpwRows - 1) M = kRpwRows - 1;
+  const int rows = M + 1;
+  const int NB = (rows + 15) >> 4;
+  wave_sync();
+
+  // 2. Gram on MFMA: acc[p] for block pair p = (i, j), i <= j < NB
+  constexpr int NP = 28;  // pairs of 7 blocks
+  f32x4 acc[NP];
+#pragma unroll
+  for (int p2 = 0; p2 < NP; ++p2) acc[p2] = f32x4{0.f, 0.f, 0.f, 0.f};
+  uint16_t *stg = reinterpret_cast<uint16_t *>(W);
+  const int q = lane >> 4, l16 = lane & 15;
+  for (int ch = 0; ch < NCHUNK; ++ch) {
+    // stage rows [0, 16*NB) x dims [ch*KC, ch*KC + KC): 8 pieces of 16 bytes per row
+    for (int pc = lane; pc < 16 * NB * 8; pc += 64) {
+      const int r = pc >> 3, part = pc & 7;
+      uint4 v = make_uint4(0u, 0u, 0u, 0u);
+      if (r < rows)
+        v = *reinterpret_cast<const uint4 *>(Xop + (int64_t)ids[r] * op_ld +
+                                             (int64_t)(ch * kRpwKC + part * 8) * 2);
+      *reinterpret_cast<uint4 *>(&stg[r * LROW + part * 8]) = v;
+    }
+    wave_sync();
+#pragma unroll
+    for (int st = 0; st < kRpwKC / 32; ++st) {
+      uint4 f[7];
+#pragma unroll
+      for (int i = 0; i < 7; ++i)
+        f[i] = (i < NB) ? *reinterpret_cast<const uint4 *>(&stg[(16 * i + l16) * LROW + st * 32 + q * 8])
+                        : make_uint4(0u, 0u, 0u, 0u);
+      int p2 = 0;
+#pragma unroll
+      for (int i = 0; i < 7; ++i)
+#pragma unroll
+        for (int j = i; j < 7; ++j, ++p2)
+          if (j < NB) acc[p2] = rp_mfma16<PREC>(f[i], f[j], acc[p2]);
+    }
+    wave_sync();
+  }
+  // 3. upper triangle of G into LDS (over the staging area)
+  {
+    int p2 = 0;
+#pragma unroll
+    for (int i = 0; i < 7; ++i)
+#pragma unroll
+      for (int j = i; j < 7; ++j, ++p2) {
+        if (j < NB) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int y = 16 * i + 4 * q + r, z = 16 * j + l16;
+            if (y <= z) W[z * (z + 1) / 2 + y] = __float_as_uint(acc[p2][r]);
+          }
+        }
+      }
+  }
+  wave_sync();
+  auto G = [&](int y, int z) { return __uint_as_float(W[tri_idx(y, z)]); };
+
+  // 4. d(x, c) and the rank of (d, id) among the candidates
+  const float g00 = G(0, 0);
+  for (int t = lane; t < M; t += 64) {
+    const int r = t + 1;
+    const float gxz = G(0, r);
+    const float dxz = L2 ? g00 + fmaf(-2.f, gxz, G(r, r)) : -gxz;
+    sDx[wave][r] = dxz;
+    sKey[wave][r] = ((uint64_t)f32_rank(dxz) << 32) | ids[r];
+  }
+  wave_sync();
+  for (int t = lane; t < M; t += 64) {
+    const uint64_t kt = sKey[wave][t + 1];
+    int rank = 0;
+    for (int u = 1; u <= M; ++u) rank += sKey[wave][u] < kt ? 1 : 0;
+    sPos[wave][rank] = (uint32_t)(t + 1);
+  }
+  wave_sync();
+
+  // 5. lazy admission: lane a holds the a-th admitted row
+  int ne = 0;
+  int my_row = 0;
+  for (int p = 0; p < M && ne < R; ++p) {
+    const int z = (int)sPos[wave][p];
+    const float dxz = sDx[wave][z];
+    bool prune = false;
+    if (lane < ne) {
+      const float gyz = G(my_row, z);
+      const float dyz = L2 ? G(my_row, my_row) + fmaf(-2.f, gyz, G(z, z)) : -gyz;
+      prune = fmaf(alpha, dyz, -dxz) < 0.f;
+    }
+    if (__ballot(prune) == 0ull) {
+      if (lane == ne) my_row = z;
+      ++ne;
+    }
+  }
+  uint32_t *grow = graph + (int64_t)x * R;
+  if (lane < R) grow[lane] = lane < ne ? ids[my_row] : kEmptyId;
+  if (lane == 0) degree[x] = (uint32_t)ne;
+}
+
 hipError_t launch_robustprune(const Index &I, const uint64_t *res, uint32_t *graph, uint32_t *degree,
                               hipStream_t s) {
   if (I.p.l_max > 256 || I.p.R > 256) return hipErrorInvalidValue;
@@ -302,6 +467,31 @@ hipError_t launch_robustprune(const Index &I, const uint64_t *res, uint32_t *gra
     else if (I.d <= 64) args(robustprune_mfma_kernel<64>);
     else if (I.d <= 96) args(robustprune_mfma_kernel<96>);
     else args(robustprune_mfma_kernel<128>);
+    return hipGetLastError();
+  }
+  const int dp = I.ldo;
+  const bool wide_op = (I.p.gemm_prec == PIPNN_PREC_FP16 || I.p.gemm_prec == PIPNN_PREC_BF16) &&
+                       (dp == 512 || dp == 768) && I.xlow.p;
+  if (wide_op && I.p.l_max <= kRpwRows - 1 && I.p.R <= 64) {
+    const int64_t blocks = xcd_grid((I.n + kRpWaves - 1) / kRpWaves);
+    const uint8_t *xop = I.xlow.as<uint8_t>();
+    const int64_t op_ld = (int64_t)dp * 2;
+    const bool l2 = I.p.metric == PIPNN_METRIC_L2;
+    auto go = [&](auto kern) {
+      hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(64 * kRpWaves), 0, s, xop, op_ld, I.n,
+                         res, I.p.l_max, I.p.alpha, I.p.R, order, graph, degree);
+    };
+    if (I.p.gemm_prec == PIPNN_PREC_FP16) {
+      if (dp == 512) l2 ? go(robustprune_wide_kernel<PIPNN_PREC_FP16, 512, true>)
+                        : go(robustprune_wide_kernel<PIPNN_PREC_FP16, 512, false>);
+      else l2 ? go(robustprune_wide_kernel<PIPNN_PREC_FP16, 768, true>)
+              : go(robustprune_wide_kernel<PIPNN_PREC_FP16, 768, false>);
+    } else {
+      if (dp == 512) l2 ? go(robustprune_wide_kernel<PIPNN_PREC_BF16, 512, true>)
+                        : go(robustprune_wide_kernel<PIPNN_PREC_BF16, 512, false>);
+      else l2 ? go(robustprune_wide_kernel<PIPNN_PREC_BF16, 768, true>)
+              : go(robustprune_wide_kernel<PIPNN_PREC_BF16, 768, false>);
+    }
     return hipGetLastError();
   }
   const int64_t blocks = (I.n + kRpWaves - 1) / kRpWaves;
@@ -352,7 +542,7 @@ hipError_t launch_leaf_order(const uint32_t *mem, int64_t cnt, int64_t n, uint32
     if ((e = launch_scan_u32(flag, pos, cnt, tmp, s)) != hipSuccess) return e;
     hipLaunchKernelGGL(order_seen_kernel, dim3(gc), dim3(256), 0, s, mem, cnt, flag, pos, order);
   } else {
-    if ((e = hipMemsetAsync(pos, 0, 8, s)) != hipSuccess) return e;
+    if ((e = launch_fill_u64(reinterpret_cast<uint64_t *>(pos), 0ull, 1, s)) != hipSuccess) return e;
   }
   hipLaunchKernelGGL(unseen_flag_kernel, dim3(gn), dim3(256), 0, s, first, n, flag);
   if ((e = launch_scan_u32(flag, pos2, n, tmp, s)) != hipSuccess) return e;

@@ -45,6 +45,26 @@ struct Index {
   std::vector<DevBuf> levels;   // partition level member arrays
   DevBuf p_asg, p_leaders, p_cm, p_bstart, p_groups, p_gout, p_gsize, p_copy;
   DevBuf rp_order;              // RobustPrune processing order (from the last leaves)
+  DevBuf s_counter;             // per-XCD work counters of the persistent leaf schedule
+  int32_t n_cu = 256;           // compute units of the device (persistent grid size)
+  int32_t leaf_nw = 4;          // waves (of 32 rows) per leaf work item: 4, or 2 where built
+  int32_t leaf_persistent = 0;  // 1: persistent workgroups take items from the counters
+  // A planned leaf set (pipnn_plan_leaves): its work lists live on the
+  // device, so that pipnn_build_leaves on it does no host work and can be
+  // captured in a graph.
+  struct PlanBatch {
+    int64_t l0 = 0, l1 = 0, rows = 0, pairs = 0;
+    int32_t n_items = 0, max_cols = 0;
+    DevBuf jobs, items;
+  };
+  struct LeafPlan {
+    const int64_t *d_off = nullptr;
+    const uint32_t *d_mem = nullptr;
+    int64_t n_leaves = -1;
+    int32_t nw = 0;
+    std::vector<int64_t> offs;
+    std::deque<PlanBatch> batches;
+  } plan;
   DevBuf o_first, o_flag, o_pos, o_pos2, o_tmp;
   bool rp_order_valid = false;
   std::deque<DevBuf> ppool;     // per-call partition buffers, reused across calls
@@ -67,6 +87,7 @@ struct Index {
 
 // Phase timing: begin/end record events on the stream when profiling is on.
 enum Phase { kPhPrepare = 0, kPhPartition, kPhLeafKnn, kPhBin, kPhMerge, kPhRobustPrune };
+bool stream_capturing(hipStream_t s);
 struct PhaseTimer {
   Index &I;
   int phase;
@@ -102,18 +123,25 @@ struct KnnLaunch {
   int32_t recompute;     // 1: FP32 direct-difference distance of the winners
   int32_t rescore_k;     // > 0: keep this many of the k_sel by the direct distance
   int32_t prec;          // PIPNN_PREC_*: the operand (FP32 for the partition)
+  int32_t nw;            // waves per work item (rows per item / 32)
+  int32_t persistent;    // 1: persistent schedule over Index::s_counter
   uint32_t *out_col;
   float *out_dist;
   float *out_matrix;
   int64_t matrix_ld;
 };
 hipError_t launch_knn(const KnnLaunch &L, hipStream_t s);
+// Operand width the leaf kernel is instantiated for (0: not supported), and
+// whether work items of 32 * nw rows exist for it.
+int knn_operand_dim(int d, int prec);
+bool knn_nw_available(int d, int prec, int nw);
 
 // Reduced-precision operands are stored zero padded to one of these
 // dimensions, so that every operand row is a whole number of 16-byte
 // vectors and the kernel never tests the dimension; 0 = not supported.
 inline int lowp_padded_dim(int d) {
-  return d <= 64 ? 64 : d <= 96 ? 96 : d <= 128 ? 128 : d <= 256 ? 256 : 0;
+  return d <= 64 ? 64 : d <= 96 ? 96 : d <= 128 ? 128 : d <= 256 ? 256 : d <= 512 ? 512
+       : d <= 768 ? 768 : 0;
 }
 
 // ---- misc kernels ----------------------------------------------------

@@ -6,13 +6,22 @@
 namespace pipnn {
 
 template <int DP>
-static hipError_t launch_dp(const KnnArgs &args, int ksel, int n_items, hipStream_t s) {
-  if (ksel <= 4) return launch_knn_shape<PIPNN_PREC_FP32, DP, 4>(args, n_items, s);
-  if (ksel <= 16) return launch_knn_shape<PIPNN_PREC_FP32, DP, 16>(args, n_items, s);
-  return launch_knn_shape<PIPNN_PREC_FP32, DP, 32>(args, n_items, s);
+static hipError_t launch_dp(const KnnArgs &args, int ksel, int n_items, int nw, int n_cu,
+                           hipStream_t s) {
+  if (ksel <= 4) return launch_knn_shape<PIPNN_PREC_FP32, DP, 4>(args, n_items, nw, n_cu, s);
+  if (ksel <= 16) return launch_knn_shape<PIPNN_PREC_FP32, DP, 16>(args, n_items, nw, n_cu, s);
+  return launch_knn_shape<PIPNN_PREC_FP32, DP, 32>(args, n_items, nw, n_cu, s);
 }
 
-int knn_rows_per_item() { return 32 * 4; }
+int knn_operand_dim(int d, int prec) {
+  if (prec != PIPNN_PREC_FP32) return lowp_padded_dim(d);
+  return d <= 32 ? 32 : d <= 64 ? 64 : d <= 96 ? 96 : d <= 128 ? 128 : d <= 192 ? 192
+       : d <= 256 ? 256 : 0;
+}
+
+bool knn_nw_available(int d, int prec, int nw) {
+  return nw == 4 || (nw == 2 && knn_has_nw2(knn_operand_dim(d, prec)));
+}
 
 hipError_t launch_knn(const KnnLaunch &L, hipStream_t s) {
   const Index &I = *L.idx;
@@ -39,21 +48,31 @@ hipError_t launch_knn(const KnnLaunch &L, hipStream_t s) {
   a.out_ids = L.out_ids;
   a.recompute = L.recompute;
   a.rescore_k = L.rescore_k;
+  a.work_counter = nullptr;
+  a.items_per_xcd = 0;
+  if (!knn_nw_available(I.d, L.prec, L.nw) || L.n_items % kNumXcd != 0) return hipErrorInvalidValue;
+  if (L.persistent) {
+    a.work_counter = I.s_counter.as<int32_t>();
+    if (!a.work_counter) return hipErrorInvalidValue;
+    hipError_t e = launch_fill_u32(I.s_counter.as<uint32_t>(), 0u, kNumXcd, s);
+    if (e != hipSuccess) return e;
+  }
+  const int nw = L.nw, n_cu = I.n_cu;
   if (lowp) {
     if (!a.Xop || a.ldo != lowp_padded_dim(I.d) || L.prec != I.p.gemm_prec)
       return hipErrorInvalidValue;
-    if (L.prec == PIPNN_PREC_BF16) return launch_knn_bf16(a, L.ksel, L.n_items, s);
-    if (L.prec == PIPNN_PREC_FP16) return launch_knn_fp16(a, L.ksel, L.n_items, s);
-    if (L.prec == PIPNN_PREC_FP8) return launch_knn_fp8(a, L.ksel, L.n_items, s);
+    if (L.prec == PIPNN_PREC_BF16) return launch_knn_bf16(a, L.ksel, L.n_items, nw, n_cu, s);
+    if (L.prec == PIPNN_PREC_FP16) return launch_knn_fp16(a, L.ksel, L.n_items, nw, n_cu, s);
+    if (L.prec == PIPNN_PREC_FP8) return launch_knn_fp8(a, L.ksel, L.n_items, nw, n_cu, s);
     return hipErrorInvalidValue;
   }
   const int d = I.d;
-  if (d <= 32) return launch_dp<32>(a, L.ksel, L.n_items, s);
-  if (d <= 64) return launch_dp<64>(a, L.ksel, L.n_items, s);
-  if (d <= 96) return launch_dp<96>(a, L.ksel, L.n_items, s);
-  if (d <= 128) return launch_dp<128>(a, L.ksel, L.n_items, s);
-  if (d <= 192) return launch_dp<192>(a, L.ksel, L.n_items, s);
-  if (d <= 256) return launch_dp<256>(a, L.ksel, L.n_items, s);
+  if (d <= 32) return launch_dp<32>(a, L.ksel, L.n_items, nw, n_cu, s);
+  if (d <= 64) return launch_dp<64>(a, L.ksel, L.n_items, nw, n_cu, s);
+  if (d <= 96) return launch_dp<96>(a, L.ksel, L.n_items, nw, n_cu, s);
+  if (d <= 128) return launch_dp<128>(a, L.ksel, L.n_items, nw, n_cu, s);
+  if (d <= 192) return launch_dp<192>(a, L.ksel, L.n_items, nw, n_cu, s);
+  if (d <= 256) return launch_dp<256>(a, L.ksel, L.n_items, nw, n_cu, s);
   return hipErrorInvalidValue;
 }
 

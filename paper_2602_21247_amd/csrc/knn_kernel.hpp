@@ -77,6 +77,11 @@ struct KnnArgs {
   int32_t ldo;           // operand row stride (elements)
   const void *Xop;       // reduced-precision operand (n x ldo, zero padded), else NULL
   const float *scale;    // fp8 operand: per-point decode scale, else NULL
+  // persistent schedule: NULL, or 8 per-XCD counters (zero at launch); the
+  // workgroups of XCD x then take items[i * 8 + x] for i = 0, 1, ... in
+  // turn until i reaches items_per_xcd
+  int32_t *work_counter;
+  int32_t items_per_xcd;
 };
 
 // Row (0..31) of accumulator entry v held by a lane in the upper (h=1) or
@@ -136,8 +141,13 @@ __device__ __forceinline__ float other_half(float x) {
 __device__ __forceinline__ uint64_t kmin(uint64_t a, uint64_t b) { return a < b ? a : b; }
 __device__ __forceinline__ uint64_t kmax(uint64_t a, uint64_t b) { return a < b ? b : a; }
 
+// Resident waves per SIMD the kernel is built for (the second launch bound
+// is waves per execution unit): operands wider than 256 dimensions take one
+// (their A fragments and tiles are large), narrower ones two.
+template <int DP> struct KnnOcc { static constexpr int v = DP > 256 ? 1 : 2; };
+
 template <int PREC, int DP, int KSEL, int NW, bool L2>
-__global__ void __launch_bounds__(NW * 64, 2) knn_kernel(KnnArgs a) {
+__device__ __forceinline__ void knn_item(const KnnArgs &a, const int item) {
   constexpr bool LP = PREC != PIPNN_PREC_FP32;  // reduced-precision operand
   constexpr bool F8 = PREC == PIPNN_PREC_FP8;
   constexpr int EB = OpBytes<PREC>::v;          // bytes per operand element
@@ -155,7 +165,10 @@ __global__ void __launch_bounds__(NW * 64, 2) knn_kernel(KnnArgs a) {
   constexpr int KST = KSEL + 1;   // LDS stride of a row's kept list (64-bit keys)
   constexpr int NTH = NW * 64;
   constexpr int CH_PER_TILE = BN * CPC;
-  constexpr int NPRE = (CH_PER_TILE + NTH - 1) / NTH;
+  constexpr int NPRE = (CH_PER_TILE + NTH - 1) / NTH;  // chunks per thread and tile
+  constexpr int PRM = (NW == 2 || DP > 256) ? 4 : 8;
+  constexpr int PR = NPRE < PRM ? NPRE : PRM;          // chunks in flight per round
+  constexpr bool ROW_REG = !LP || HALF <= 64;          // recompute row half in registers
   static_assert(LP || LDW == LDB, "FP32 column stride");
 
   __shared__ __attribute__((aligned(16))) uint32_t sBw[BN * LDW];
@@ -172,7 +185,6 @@ __global__ void __launch_bounds__(NW * 64, 2) knn_kernel(KnnArgs a) {
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int h = lane >> 5, l32 = lane & 31;
-  const int item = blockIdx.x;
   if (item >= a.n_items || a.items[item].job < 0) return;
   const KnnItem it = a.items[item];
   const KnnJob J = a.jobs[it.job];
@@ -236,17 +248,18 @@ __global__ void __launch_bounds__(NW * 64, 2) knn_kernel(KnnArgs a) {
   // lanes l32 and l32 + 32 own row wrow + l32 together
   const int orow = wave * 32 + l32;  // LDS row index
 
-  // column tile staging: thread t loads 16-byte chunks t, t+NTH, ... of the tile
-  uint4 pre[NPRE];
+  // column tile staging: thread t moves 16-byte chunks t, t+NTH, ... of the
+  // tile, PR of them in flight at a time
+  uint4 pre[PR];
   float pre_n = 0.f, pre_s = 0.f;
-  auto load_tile = [&](int c0) {
-    if (tid < BN) pre_n = (l2 && c0 + tid < n_cols) ? a.norms[cols[c0 + tid]] : 0.f;
-    if constexpr (F8) {
-      if (tid < BN) pre_s = c0 + tid < n_cols ? a.scale[cols[c0 + tid]] : 0.f;
+  auto load_tile = [&](int c0, int r0) {
+    if (r0 == 0 && tid < BN) {
+      pre_n = (l2 && c0 + tid < n_cols) ? a.norms[cols[c0 + tid]] : 0.f;
+      if constexpr (F8) pre_s = c0 + tid < n_cols ? a.scale[cols[c0 + tid]] : 0.f;
     }
 #pragma unroll
-    for (int i = 0; i < NPRE; ++i) {
-      const int q = tid + i * NTH;
+    for (int i = 0; i < PR; ++i) {
+      const int q = tid + (r0 + i) * NTH;
       uint4 v = make_uint4(0u, 0u, 0u, 0u);
       if (q < CH_PER_TILE) {
         const int c = q / CPC, kq = q % CPC;
@@ -271,14 +284,14 @@ __global__ void __launch_bounds__(NW * 64, 2) knn_kernel(KnnArgs a) {
       pre[i] = v;
     }
   };
-  auto store_tile = [&]() {
-    if (tid < BN) {
+  auto store_tile = [&](int r0) {
+    if (r0 == 0 && tid < BN) {
       sColN[tid] = pre_n;
       if constexpr (F8) sColS[tid] = pre_s;
     }
 #pragma unroll
-    for (int i = 0; i < NPRE; ++i) {
-      const int q = tid + i * NTH;
+    for (int i = 0; i < PR; ++i) {
+      const int q = tid + (r0 + i) * NTH;
       if (q < CH_PER_TILE) {
         const int c = q / CPC, kq = q % CPC;
         *reinterpret_cast<uint4 *>(&sBw[c * LDW + kq * 4]) = pre[i];
@@ -327,8 +340,11 @@ __global__ void __launch_bounds__(NW * 64, 2) knn_kernel(KnnArgs a) {
 
   for (int c0 = 0; c0 < n_cols; c0 += BN) {
     // stage the column tile (the other workgroup on the CU covers the latency)
-    load_tile(c0);
-    store_tile();
+#pragma unroll
+    for (int r0 = 0; r0 < NPRE; r0 += PR) {
+      load_tile(c0, r0);
+      store_tile(r0);
+    }
     __syncthreads();
 
 #pragma unroll
@@ -339,9 +355,16 @@ __global__ void __launch_bounds__(NW * 64, 2) knn_kernel(KnnArgs a) {
       for (int v = 0; v < 16; ++v) acc[v] = 0.f;
       if constexpr (LP) {
         const uint32_t *bw = &sBw[(32 * blk + l32) * LDW + h * (HALF * EB / 4)];
+        // groups of 8 operand vectors: a scheduling barrier between groups
+        // keeps the B fragments of wide operands from all being loaded ahead
+        constexpr int G = NA < 8 ? NA : 8;
 #pragma unroll
-        for (int s2 = 0; s2 < NA; ++s2)
-          acc = mfma16<PREC>(aw[s2], *reinterpret_cast<const uint4 *>(bw + 4 * s2), acc);
+        for (int g0 = 0; g0 < NA; g0 += G) {
+#pragma unroll
+          for (int s2 = g0; s2 < g0 + G && s2 < NA; ++s2)
+            acc = mfma16<PREC>(aw[s2], *reinterpret_cast<const uint4 *>(bw + 4 * s2), acc);
+          if constexpr (NA > 16) __builtin_amdgcn_sched_barrier(0);
+        }
       } else {
         const float *bp = &sB[(32 * blk + l32) * LDB + h * HALF];
 #pragma unroll
@@ -438,8 +461,10 @@ __global__ void __launch_bounds__(NW * 64, 2) knn_kernel(KnnArgs a) {
     const int lrow = wave * 32 + l32;
     const int kbase = h * HALF;
     // the row's FP32 half: av[] already holds it on the FP32 path
-    float xr[LP ? HALF : 1];
-    if constexpr (LP) {
+    float xr[(LP && ROW_REG) ? HALF : 1];
+    // wide operands: the row half is re-read from memory (cache resident)
+    const float *xrow = a.X + (int64_t)rows[rr < n_rows ? rr : 0] * d + kbase;
+    if constexpr (LP && ROW_REG) {
       if (rr < n_rows) {
         const float *src = a.X + (int64_t)rows[rr] * d + kbase;
         if (full_d) {
@@ -458,7 +483,8 @@ __global__ void __launch_bounds__(NW * 64, 2) knn_kernel(KnnArgs a) {
       }
     }
     auto rv = [&](int kk) -> float {
-      if constexpr (LP) return xr[kk];
+      if constexpr (LP && ROW_REG) return xr[kk];
+      else if constexpr (LP) return 0.f;
       else return av[kk];
     };
     // sum over this lane's half of the dimensions for column c
@@ -469,25 +495,36 @@ __global__ void __launch_bounds__(NW * 64, 2) knn_kernel(KnnArgs a) {
 #pragma unroll
         for (int kk = 0; kk < HALF; kk += 4) {
           const float4 q = *reinterpret_cast<const float4 *>(xc + kk);
-          if (l2) {
-            float t = rv(kk) - q.x; s = fmaf(t, t, s);
-            t = rv(kk + 1) - q.y; s = fmaf(t, t, s);
-            t = rv(kk + 2) - q.z; s = fmaf(t, t, s);
-            t = rv(kk + 3) - q.w; s = fmaf(t, t, s);
+          float r0, r1, r2, r3;
+          if constexpr (ROW_REG) {
+            r0 = rv(kk); r1 = rv(kk + 1); r2 = rv(kk + 2); r3 = rv(kk + 3);
           } else {
-            s = fmaf(rv(kk), q.x, s); s = fmaf(rv(kk + 1), q.y, s);
-            s = fmaf(rv(kk + 2), q.z, s); s = fmaf(rv(kk + 3), q.w, s);
+            const float4 rq = *reinterpret_cast<const float4 *>(xrow + kk);
+            r0 = rq.x; r1 = rq.y; r2 = rq.z; r3 = rq.w;
+          }
+          if (l2) {
+            float t = r0 - q.x; s = fmaf(t, t, s);
+            t = r1 - q.y; s = fmaf(t, t, s);
+            t = r2 - q.z; s = fmaf(t, t, s);
+            t = r3 - q.w; s = fmaf(t, t, s);
+          } else {
+            s = fmaf(r0, q.x, s); s = fmaf(r1, q.y, s);
+            s = fmaf(r2, q.z, s); s = fmaf(r3, q.w, s);
           }
         }
       } else {
 #pragma unroll
         for (int kk = 0; kk < HALF; ++kk) {
-          const float v = (kbase + kk < d) ? xc[kk] : 0.f;
+          const bool in = kbase + kk < d;
+          const float v = in ? xc[kk] : 0.f;
+          float r;
+          if constexpr (ROW_REG) r = rv(kk);
+          else r = in ? xrow[kk] : 0.f;
           if (l2) {
-            const float t = rv(kk) - v;
+            const float t = r - v;
             s = fmaf(t, t, s);
           } else {
-            s = fmaf(rv(kk), v, s);
+            s = fmaf(r, v, s);
           }
         }
       }
@@ -548,32 +585,75 @@ __global__ void __launch_bounds__(NW * 64, 2) knn_kernel(KnnArgs a) {
   }
 }
 
-template <int PREC, int DP, int KSEL>
-static hipError_t launch_knn_shape(const KnnArgs &args, int n_items, hipStream_t s) {
-  constexpr int NW = 4;
-  if (args.metric == PIPNN_METRIC_L2)
-    hipLaunchKernelGGL((knn_kernel<PREC, DP, KSEL, NW, true>), dim3(n_items), dim3(NW * 64), 0, s,
-                       args);
-  else
-    hipLaunchKernelGGL((knn_kernel<PREC, DP, KSEL, NW, false>), dim3(n_items), dim3(NW * 64), 0,
-                       s, args);
-  return hipGetLastError();
+// Static schedule: workgroup b takes item b.
+template <int PREC, int DP, int KSEL, int NW, bool L2>
+__global__ void __launch_bounds__(NW * 64, KnnOcc<DP>::v) knn_kernel(KnnArgs a) {
+  knn_item<PREC, DP, KSEL, NW, L2>(a, (int)blockIdx.x);
 }
 
-template <int PREC>
-static hipError_t launch_knn_lowp(const KnnArgs &a, int ksel, int n_items, hipStream_t s) {
-  const bool k32 = ksel > 16;
-  switch (a.ldo) {
-    case 64: return k32 ? launch_knn_shape<PREC, 64, 32>(a, n_items, s) : launch_knn_shape<PREC, 64, 16>(a, n_items, s);
-    case 96: return k32 ? launch_knn_shape<PREC, 96, 32>(a, n_items, s) : launch_knn_shape<PREC, 96, 16>(a, n_items, s);
-    case 128: return k32 ? launch_knn_shape<PREC, 128, 32>(a, n_items, s) : launch_knn_shape<PREC, 128, 16>(a, n_items, s);
-    case 256: return k32 ? launch_knn_shape<PREC, 256, 32>(a, n_items, s) : launch_knn_shape<PREC, 256, 16>(a, n_items, s);
-    default: return hipErrorInvalidValue;
+// Persistent schedule: block b runs on XCD b % 8 and serves that XCD's item
+// list from its counter until the list is exhausted.
+template <int PREC, int DP, int KSEL, int NW, bool L2>
+__global__ void __launch_bounds__(NW * 64, KnnOcc<DP>::v) knn_kernel_persistent(KnnArgs a) {
+  __shared__ int sNext;
+  const int x = (int)(blockIdx.x % kNumXcd);
+  for (;;) {
+    if (threadIdx.x == 0) sNext = atomicAdd(&a.work_counter[x], 1);
+    __syncthreads();
+    const int i = sNext;
+    __syncthreads();
+    if (i >= a.items_per_xcd) break;
+    knn_item<PREC, DP, KSEL, NW, L2>(a, i * kNumXcd + x);
+    __syncthreads();
   }
 }
 
-hipError_t launch_knn_bf16(const KnnArgs &a, int ksel, int n_items, hipStream_t s);
-hipError_t launch_knn_fp16(const KnnArgs &a, int ksel, int n_items, hipStream_t s);
-hipError_t launch_knn_fp8(const KnnArgs &a, int ksel, int n_items, hipStream_t s);
+// One launch of a kernel shape. Static schedule: one workgroup per item.
+// Persistent schedule: as many workgroups as stay resident (n_cu CUs times
+// the workgroups per CU the shape is built for, a multiple of 8), each
+// serving its XCD's item list.
+template <int PREC, int DP, int KSEL, int NW>
+static hipError_t launch_knn_nw(KnnArgs args, int n_items, int n_cu, hipStream_t s) {
+  unsigned grid = (unsigned)n_items;
+  if (args.work_counter) {
+    constexpr int per_cu = KnnOcc<DP>::v * 4 / NW;  // workgroups resident per CU
+    const int resident = (n_cu * per_cu) / kNumXcd * kNumXcd;
+    args.items_per_xcd = n_items / kNumXcd;
+    grid = (unsigned)(n_items < resident ? n_items : resident);
+  }
+  const bool l2 = args.metric == PIPNN_METRIC_L2;
+  if (args.work_counter) {
+    if (l2)
+      hipLaunchKernelGGL((knn_kernel_persistent<PREC, DP, KSEL, NW, true>), dim3(grid),
+                         dim3(NW * 64), 0, s, args);
+    else
+      hipLaunchKernelGGL((knn_kernel_persistent<PREC, DP, KSEL, NW, false>), dim3(grid),
+                         dim3(NW * 64), 0, s, args);
+  } else if (l2) {
+    hipLaunchKernelGGL((knn_kernel<PREC, DP, KSEL, NW, true>), dim3(grid), dim3(NW * 64), 0, s,
+                       args);
+  } else {
+    hipLaunchKernelGGL((knn_kernel<PREC, DP, KSEL, NW, false>), dim3(grid), dim3(NW * 64), 0, s,
+                       args);
+  }
+  return hipGetLastError();
+}
+
+// Work items of 64 rows (two waves) are built for operands of 65..128
+// dimensions; every shape has items of 128 rows (four waves).
+constexpr bool knn_has_nw2(int dp) { return dp == 96 || dp == 128; }
+
+template <int PREC, int DP, int KSEL>
+static hipError_t launch_knn_shape(const KnnArgs &args, int n_items, int nw, int n_cu,
+                                   hipStream_t s) {
+  if constexpr (knn_has_nw2(DP)) {
+    if (nw == 2) return launch_knn_nw<PREC, DP, KSEL, 2>(args, n_items, n_cu, s);
+  }
+  return launch_knn_nw<PREC, DP, KSEL, 4>(args, n_items, n_cu, s);
+}
+
+hipError_t launch_knn_bf16(const KnnArgs &a, int ksel, int n_items, int nw, int n_cu, hipStream_t s);
+hipError_t launch_knn_fp16(const KnnArgs &a, int ksel, int n_items, int nw, int n_cu, hipStream_t s);
+hipError_t launch_knn_fp8(const KnnArgs &a, int ksel, int n_items, int nw, int n_cu, hipStream_t s);
 
 }  // namespace pipnn

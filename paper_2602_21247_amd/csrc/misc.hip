@@ -295,7 +295,7 @@ static hipError_t scan_impl(const T *in, int64_t *out, int64_t n, int64_t *tmp, 
   const int64_t nt = (n + kScanTile - 1) / kScanTile;
   if (nt > kScanTile) return hipErrorInvalidValue;
   if (n == 0) {
-    return hipMemsetAsync(out, 0, sizeof(int64_t), s);
+    return launch_fill_u64(reinterpret_cast<uint64_t *>(out), 0ull, 1, s);
   }
   hipLaunchKernelGGL((scan_tiles_kernel<T>), dim3((unsigned)nt), dim3(kScanThreads), 0, s, in, out,
                      n, tmp);

@@ -44,6 +44,9 @@ class Workload:
 
 # The five workloads. Hyper-parameters: C_max, C_min, P_samp (as 1/leader_div),
 # the leader cap, fanout by depth, leaf k, hash bits m, reservoir l_max, R, alpha.
+# The inner-product workload prunes with alpha = 1: its dissimilarity -x.y is
+# negative for similar unit vectors, where alpha > 1 tightens the pruning
+# test instead of relaxing it.
 WORKLOADS = {
     1: Workload("gauss-mixture-10k-d128-f32", 10_000, 128, 1_000, METRIC_L2,
                 1024, 64, 16, 64, 32, 1.2, 12, (2, 1, 1, 1)),
@@ -52,7 +55,7 @@ WORKLOADS = {
     3: Workload("vmf-mixture-1M-d96-unit", 1_000_000, 96, 10_000, METRIC_L2,
                 2048, 64, 16, 64, 32, 1.2, 12, (2, 1, 1, 1)),
     4: Workload("aniso-mixture-2M-d768-f16-ip", 2_000_000, 768, 1_000, METRIC_IP,
-                4096, 64, 32, 96, 64, 1.2, 12, (2, 1, 1, 1)),
+                4096, 64, 32, 96, 64, 1.0, 12, (2, 1, 1, 1)),
 }
 
 # Spread of the integer mixture around its centres. The value is a choice
@@ -206,6 +209,36 @@ def zipf_leaves(n: int, labels_order_key: np.ndarray, lo: int, hi: int, s: float
         seg = labels_order_key[offsets[i]:offsets[i + 1]]
         members[offsets[i]:offsets[i + 1]] = np.sort(seg)
     return offsets, members
+
+
+def mixture_labels(cfg: int, n: int) -> np.ndarray:
+    """Mixture component of each point of ``workload_points(cfg, n)`` (the
+    first draw of the stream that generated them)."""
+    if cfg != 4:
+        raise ValueError("labels are exposed for workload 4 only")
+    return _rng(4 + 7919).integers(0, 200, size=n)
+
+
+def workload_leaves(cfg: int, n: int | None = None) -> tuple[np.ndarray, np.ndarray]:
+    """Explicit uneven leaves of workload 4 (every point in two leaves): two
+    independent orderings of the points by (mixture component, random key),
+    each cut into consecutive chunks of truncated-Zipf(1.2) sizes on
+    64..4096; members ascending within a leaf. Returns one CSR over both."""
+    if cfg != 4:
+        raise ValueError("explicit leaves are defined for workload 4 only")
+    w = WORKLOADS[cfg]
+    nn = w.n if n is None else n
+    labels = mixture_labels(cfg, nn)
+    offs, mems = [], []
+    base = 0
+    for j in range(2):
+        key = _rng(4100 + j).random(nn)
+        order = np.lexsort((key, labels)).astype(np.uint32)
+        o, m = zipf_leaves(nn, order, 64, 4096, 1.2, seed=4200 + j)
+        offs.append(o[:-1] + base if j == 0 else o + base)
+        mems.append(m)
+        base += nn
+    return np.concatenate(offs).astype(np.int64), np.concatenate(mems).astype(np.uint32)
 
 
 def workload_points(cfg: int, n: int | None = None) -> np.ndarray:

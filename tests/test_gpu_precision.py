@@ -294,8 +294,12 @@ def test_bf16_full_build_integer_bit_exact():
     idx.close()
 
 
-def test_reduced_precision_rejects_wide_vectors():
+def test_operand_width_limits():
+    X = np.zeros((10, 800), dtype=np.float32)
+    H = pi.hyperplanes(12, 800, seed=1)
+    with pytest.raises(pp.PipnnError, match="d <= 768"):
+        pp.Index(dev(X), dev(H), pp.default_params(gemm_prec=pp.PREC_BF16))
     X = np.zeros((10, 300), dtype=np.float32)
     H = pi.hyperplanes(12, 300, seed=1)
     with pytest.raises(pp.PipnnError, match="d <= 256"):
-        pp.Index(dev(X), dev(H), pp.default_params(gemm_prec=pp.PREC_BF16))
+        pp.Index(dev(X), dev(H), pp.default_params(gemm_prec=pp.PREC_FP32))
