@@ -191,6 +191,39 @@ pipnn_status pipnn_autotune(pipnn_index *idx, const int64_t *d_leaf_offsets,
                             pipnn_tune_result *h_results, int32_t cap_results,
                             int32_t *h_n_results, pipnn_stream_t stream);
 
+/* ---- serving: growing an index in place ---- */
+
+/* (sync) Make room for n_cap points: grows the index's per-point buffers
+ * (norms, sketches, float32 copy, GEMM operand), keeping their contents.
+ * The caller's X (bound at pipnn_create) must have n_cap rows, and the
+ * caller sizes its reservoirs (n_cap x l_max), graph (n_cap x R) and degree
+ * (n_cap) buffers the same way. EINVAL if n_cap >= 2^32 - 1. */
+pipnn_status pipnn_reserve(pipnn_index *idx, int64_t n_cap, pipnn_stream_t stream);
+
+/* (sync) Insert the n_new points the caller has written to rows
+ * [n, n + n_new) of X (n = the current point count), which becomes
+ * n + n_new. The paper has no insertion; this follows its leaf step:
+ *  1. the new rows get norms, sketches, GEMM operand and empty reservoirs;
+ *  2. each new point is routed to its fanout[0] nearest leaves of the last
+ *     pipnn_build_leaves, by each leaf's representative (the member nearest
+ *     to the leaf mean);
+ *  3. per (leaf, group) the new points of that group routed to the leaf are
+ *     the rows of one rectangular leaf-kernel job whose columns are the
+ *     leaf's members and those new points; each row keeps its k nearest
+ *     (same GEMM precision, rescoring and selection as the build);
+ *  4. both directed records of every pick go through HashPrune;
+ *  5. RobustPrune runs again on every point that received a record.
+ * d_group (n_new int32, may be NULL = one group) separates requests: new
+ * points of different groups are never each other's candidates, so a
+ * request gives the same graph whether it is inserted alone or with others
+ * (HashPrune does not depend on the order of its records). The leaves
+ * themselves do not grow. ESTATE before any build or under capture;
+ * EOVERFLOW past the reserved capacity; EINVAL if a leaf would exceed 65535
+ * columns. On a failure the index is left in an unspecified state. */
+pipnn_status pipnn_insert(pipnn_index *idx, int64_t n_new, const int32_t *d_group,
+                          uint64_t *d_reservoirs, uint32_t *d_graph, uint32_t *d_degree,
+                          pipnn_stream_t stream);
+
 /* Pick + Prune_And_Add_Edges for every leaf (Alg. 4, the parallel loop over
  * leaves; Sec. 4.2): per leaf, the distance matrix on MFMA, each member's
  * k nearest co-members by (GEMM distance, id) (or the rescore_mult*k

@@ -109,6 +109,7 @@ def lib():
         L.orc_e4m3_value.argtypes = [C.c_uint8]
         L.orc_quantize.argtypes = [P, i64, i32, i32, P, P, P]
         L.orc_leaf_knn_lowp.argtypes = [P, P, i32, i32, P, P, i64, i32, i32, P, P]
+        L.orc_leaf_reps.argtypes = [P, i32, P, P, i64, P]
         L.orc_get_threads.restype = i32
         _lib = L
     return _lib
@@ -372,3 +373,65 @@ def build_index(X, H, params: Params, lazy: bool = True):
     g, deg = robustprune(X, res, params.alpha, params.R, params.metric, lazy=lazy)
     return dict(offsets=off, members=mem, leader_dists=ld, cand=cand, dist=dd, S=S,
                 reservoirs=res, graph=g, degree=deg, records=(dst, cnd, dv))
+
+
+def leaf_reps(X, offsets, members) -> np.ndarray:
+    """Representative of each leaf (see orc_leaf_reps)."""
+    X = _f32(X)
+    offsets = np.ascontiguousarray(offsets, dtype=np.int64)
+    members = np.ascontiguousarray(members, dtype=np.uint32)
+    out = np.zeros(len(offsets) - 1, dtype=np.uint32)
+    lib().orc_leaf_reps(_p(X), X.shape[1], _p(offsets), _p(members), len(offsets) - 1, _p(out))
+    return out
+
+
+def insert(X_all, n0: int, groups, offsets, members, res, H, k: int, alpha: float, R: int,
+           fanout0: int = 2, metric: int = 0):
+    """Insertion of points n0.. of X_all into an index built on the leaves
+    (offsets, members) with reservoirs res (n0 x l_max), as this library
+    defines it (the paper has none):
+      1. every new point is routed to its min(fanout0, #leaves) nearest leaf
+         representatives (exact distances, ties by leaf index);
+      2. per (leaf, group), each new point of the group routed to the leaf
+         picks its k nearest (distance, id) among the leaf's members and the
+         group's new points routed there, itself excluded;
+      3. both directed records of every pick go through HashPrune (starting
+         from the old reservoirs; new points start empty);
+      4. RobustPrune of every point that received a record.
+    Returns (reservoirs n1 x l_max, touched ids, graph rows of the touched
+    ids)."""
+    X_all = _f32(X_all)
+    n1 = X_all.shape[0]
+    new = np.arange(n0, n1, dtype=np.int64)
+    groups = np.zeros(len(new), dtype=np.int32) if groups is None else np.asarray(groups)
+    reps = leaf_reps(X_all[:n0], offsets, members)
+    nl = len(reps)
+    f = min(fanout0, nl)
+    rid, _ = bruteforce_knn(X_all[reps], X_all[new], f, metric)
+    by = {}
+    for i, p in enumerate(new):
+        for L in rid[i]:
+            by.setdefault((int(L), int(groups[i])), []).append(int(p))
+    src, dst, dv = [], [], []
+    for (L, g), pts in sorted(by.items()):
+        cols = np.concatenate([np.asarray(members[offsets[L]:offsets[L + 1]], dtype=np.int64),
+                               np.asarray(pts, dtype=np.int64)])
+        kk = min(k + 1, len(cols))
+        nb, nd = bruteforce_knn(X_all[cols], X_all[np.asarray(pts)], kk, metric)
+        for r, p in enumerate(pts):
+            got = [(cols[c], dd) for c, dd in zip(nb[r], nd[r]) if c != EMPTY_ID and cols[c] != p]
+            for c, dd in got[:k]:
+                src.append(p)
+                dst.append(c)
+                dv.append(dd)
+    src, dst, dv = (np.asarray(src, dtype=np.uint32), np.asarray(dst, dtype=np.uint32),
+                    np.asarray(dv, dtype=np.float64))
+    l_max = res.shape[1]
+    res1 = np.concatenate([np.asarray(res, dtype=np.uint64),
+                           reservoir_init(n1 - n0, l_max)]) if n1 > n0 else res.copy()
+    S = sketches(X_all, H)
+    res1 = hashprune(res1, S, np.concatenate([src, dst]), np.concatenate([dst, src]),
+                     np.concatenate([dv, dv]))
+    touched = np.unique(np.concatenate([src.astype(np.int64), dst.astype(np.int64)]))
+    g, _ = robustprune(X_all, res1, alpha, R, metric=metric)
+    return res1, touched, g[touched]

@@ -1058,3 +1058,44 @@ uint32_t orc_start_node(const float *X, int64_t n, int d, double *dist_out) {
   free(mean);
   return best;
 }
+
+/* ------------------------------------------------------------------ */
+/* Insertion (an extension of this library; the paper builds only). The
+ * representative of a leaf is the member m with the smallest
+ * (sum_i (s x_mi - S_i)^2, id), S_i the sum of the members' coordinate i
+ * (in member order) and s the leaf size: s^2 times the squared distance of
+ * m to the leaf mean. Empty leaves get id 0. */
+void orc_leaf_reps(const float *X, int d, const int64_t *offsets, const uint32_t *members,
+                   int64_t n_leaves, uint32_t *rep) {
+#pragma omp parallel
+  {
+    double *S = (double *)malloc(sizeof(double) * (size_t)d);
+#pragma omp for schedule(dynamic, 1)
+    for (int64_t L = 0; L < n_leaves; L++) {
+      int64_t o = offsets[L], s = offsets[L + 1] - offsets[L];
+      if (s <= 0) {
+        rep[L] = 0;
+        continue;
+      }
+      for (int i = 0; i < d; i++) S[i] = 0.0;
+      for (int64_t j = 0; j < s; j++)
+        for (int i = 0; i < d; i++) S[i] += (double)X[(int64_t)members[o + j] * d + i];
+      double best = INFINITY;
+      uint32_t bid = 0xFFFFFFFFu;
+      for (int64_t j = 0; j < s; j++) {
+        uint32_t id = members[o + j];
+        double sc = 0.0;
+        for (int i = 0; i < d; i++) {
+          double t = (double)s * (double)X[(int64_t)id * d + i] - S[i];
+          sc += t * t;
+        }
+        if (sc < best || (sc == best && id < bid)) {
+          best = sc;
+          bid = id;
+        }
+      }
+      rep[L] = bid;
+    }
+    free(S);
+  }
+}

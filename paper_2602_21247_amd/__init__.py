@@ -28,7 +28,7 @@ EXPORTS = [
     "pipnn_robustprune", "pipnn_start_node", "pipnn_search", "pipnn_get_sketches",
     "pipnn_knn_block", "pipnn_leaf_pick", "pipnn_prepare", "pipnn_set_profiling",
     "pipnn_get_stats", "pipnn_get_operand", "pipnn_plan_leaves", "pipnn_set_leaf_config",
-    "pipnn_autotune",
+    "pipnn_autotune", "pipnn_reserve", "pipnn_insert",
 ]
 
 
@@ -96,6 +96,8 @@ def lib():
         L.pipnn_get_operand.argtypes = [P, P, P, P, P]
         L.pipnn_plan_leaves.argtypes = [P, P, P, i64, P]
         L.pipnn_set_leaf_config.argtypes = [P, i32, i32]
+        L.pipnn_reserve.argtypes = [P, i64, P]
+        L.pipnn_insert.argtypes = [P, i64, P, P, P, P, P]
         L.pipnn_autotune.argtypes = [P, P, P, i64, C.POINTER(TuneResult), i32, C.POINTER(i32), P]
         for name in EXPORTS:
             if name not in ("pipnn_version", "pipnn_last_error", "pipnn_default_params",
@@ -218,6 +220,16 @@ class Index:
                                     out, 8, C.byref(cnt), _stream()))
         return [(out[i].rows_per_item, bool(out[i].persistent), out[i].ms)
                 for i in range(cnt.value)]
+
+    def reserve(self, n_cap: int):
+        """Room for n_cap points (X must have n_cap rows)."""
+        _check(lib().pipnn_reserve(self._h, n_cap, _stream()))
+
+    def insert(self, n_new: int, reservoirs, graph, degree, groups=None):
+        """Insert rows [n, n + n_new) of X (already written by the caller)."""
+        _check(lib().pipnn_insert(self._h, n_new, None if groups is None else _ptr(groups),
+                                  _ptr(reservoirs), _ptr(graph), _ptr(degree), _stream()))
+        self.n += n_new
 
     def partition(self):
         torch = _torch()

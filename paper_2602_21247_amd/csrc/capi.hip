@@ -11,6 +11,8 @@
 #include <vector>
 
 #include "common.hpp"
+#include <map>
+
 #include "internal.hpp"
 
 using namespace pipnn;
@@ -333,6 +335,7 @@ pipnn_status pipnn_create(const pipnn_params *p, const void *d_X, int64_t n, int
         ncu >= kNumXcd)
       I->n_cu = ncu;
   }
+  I->cap = n;
   if (p->gemm_prec == PIPNN_PREC_FP32 && knn_operand_dim(d, PIPNN_PREC_FP32) == 0)
     return cleanup(fail(PIPNN_EINVAL, "a float32 leaf GEMM needs d <= 256 (use a reduced "
                                       "gemm_prec for wider vectors)"));
@@ -373,7 +376,9 @@ void pipnn_destroy(pipnn_index *idx) {
   Index *I = reinterpret_cast<Index *>(idx);
   (void)hipDeviceSynchronize();
   for (DevBuf *b : {&I->rp_order, &I->o_first, &I->o_flag, &I->o_pos, &I->o_pos2, &I->o_tmp,
-                    &I->xf32, &I->xlow, &I->xscale, &I->lnorms, &I->s_counter, &I->sketches, &I->norms, &I->flag, &I->s_jobs,
+                    &I->xf32, &I->xlow, &I->xscale, &I->lnorms, &I->s_counter, &I->q_conv, &I->q_seen,
+                    &I->lt_off, &I->lt_mem, &I->lt_rep, &I->i_rows, &I->i_cols, &I->i_assign,
+                    &I->i_flag, &I->i_pos, &I->i_list, &I->i_tmp, &I->i_segs, &I->sketches, &I->norms, &I->flag, &I->s_jobs,
                     &I->s_items, &I->s_picks_c, &I->s_picks_d, &I->s_cnt, &I->s_off, &I->s_bins,
                     &I->s_tmp0, &I->s_tmp1, &I->p_asg, &I->p_leaders, &I->p_cm, &I->p_bstart,
                     &I->p_groups, &I->p_gout, &I->p_gsize, &I->p_copy})
@@ -469,7 +474,7 @@ pipnn_status pipnn_partition(pipnn_index *idx, int64_t *d_leaf_offsets, int64_t 
       fmax = std::max(fmax, f);
       const int64_t lead_off = (int64_t)lead_idx.size();
       for (int64_t pos : leader_positions(sb.key, sb.cnt, ell)) lead_idx.push_back(sb.row_off + pos);
-      KnnJob J;
+      KnnJob J{};
       J.row_off = sb.row_off;
       J.col_off = lead_off;
       J.out_off = sb.row_off;
@@ -752,7 +757,7 @@ pipnn_status plan_pick(Index &I, const std::vector<int64_t> &offs, int64_t l0, i
   for (int64_t l = l0; l < l1; ++l) {
     const int64_t sz = offs[(size_t)l + 1] - offs[(size_t)l];
     if (sz < 2) continue;
-    KnnJob J;
+    KnnJob J{};
     J.row_off = offs[(size_t)l];
     J.col_off = offs[(size_t)l];
     J.out_off = offs[(size_t)l] - base;
@@ -937,6 +942,23 @@ static pipnn_status reserve_build(Index &I, const std::vector<int64_t> &offs,
   HIPCHK(I.o_pos2.ensure((size_t)(n + 1) * 8));
   HIPCHK(I.o_tmp.ensure((size_t)scan_tmp_elems(mx) * 8));
   HIPCHK(I.rp_order.ensure((size_t)n * 4));
+  HIPCHK(I.lt_off.ensure((size_t)(n_leaves + 1) * 8));
+  HIPCHK(I.lt_mem.ensure((size_t)std::max<int64_t>(cnt, 1) * 4));
+  return PIPNN_OK;
+}
+
+// Keep the leaves of this build for insertion (device copies; the
+// representatives are found at the first insertion).
+static pipnn_status keep_leaf_table(Index &I, const int64_t *d_off, const uint32_t *d_mem,
+                                    const std::vector<int64_t> &offs, int64_t n_leaves,
+                                    hipStream_t s) {
+  const int64_t cnt = offs[(size_t)n_leaves] - offs[0];
+  HIPCHK(launch_rebase_i64(d_off, n_leaves + 1, I.lt_off.as<int64_t>(), s));
+  HIPCHK(launch_copy_u32(d_mem + offs[0], cnt, I.lt_mem.as<uint32_t>(), s));
+  I.lt_offs.resize((size_t)n_leaves + 1);
+  for (int64_t i = 0; i <= n_leaves; ++i) I.lt_offs[(size_t)i] = offs[(size_t)i] - offs[0];
+  I.lt_n_leaves = n_leaves;
+  I.lt_reps_valid = false;
   return PIPNN_OK;
 }
 
@@ -1036,6 +1058,8 @@ pipnn_status pipnn_build_leaves(pipnn_index *idx, const int64_t *d_leaf_offsets,
     }
     st = leaf_order(I, d_leaf_members + P.offs[0], P.offs[(size_t)n_leaves] - P.offs[0], s);
     if (st != PIPNN_OK) return st;
+    st = keep_leaf_table(I, d_leaf_offsets, d_leaf_members, P.offs, n_leaves, s);
+    if (st != PIPNN_OK) return st;
     return capturing ? PIPNN_OK : finish_bins(I, s, "build_leaves");
   }
   std::vector<int64_t> offs;
@@ -1064,7 +1088,236 @@ pipnn_status pipnn_build_leaves(pipnn_index *idx, const int64_t *d_leaf_offsets,
   }
   st = leaf_order(I, d_leaf_members + offs[0], offs[(size_t)n_leaves] - offs[0], s);
   if (st != PIPNN_OK) return st;
+  st = keep_leaf_table(I, d_leaf_offsets, d_leaf_members, offs, n_leaves, s);
+  if (st != PIPNN_OK) return st;
   return finish_bins(I, s, "build_leaves");
+  GUARD_END
+}
+
+// Grow a buffer to `bytes`, keeping its first `keep` bytes.
+static hipError_t grow_keep(DevBuf &b, size_t bytes, size_t keep, hipStream_t s) {
+  if (b.p && b.cap >= bytes) return hipSuccess;
+  void *np = nullptr;
+  hipError_t e = hipMalloc(&np, std::max<size_t>(bytes, 256));
+  if (e != hipSuccess) return e;
+  if (b.p && keep) {
+    if ((e = hipMemcpyAsync(np, b.p, std::min(keep, b.cap), hipMemcpyDeviceToDevice, s)) !=
+            hipSuccess ||
+        (e = hipStreamSynchronize(s)) != hipSuccess) {
+      (void)hipFree(np);
+      return e;
+    }
+  }
+  b.release();
+  b.p = np;
+  b.cap = std::max<size_t>(bytes, 256);
+  return hipSuccess;
+}
+
+pipnn_status pipnn_reserve(pipnn_index *idx, int64_t n_cap, pipnn_stream_t stream) {
+  GUARD_BEGIN
+  if (!idx) return fail(PIPNN_EINVAL, "NULL index");
+  Index &I = *reinterpret_cast<Index *>(idx);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  if (stream_capturing(s)) return fail(PIPNN_ESTATE, "reserve cannot run under capture");
+  if (n_cap >= (int64_t)0xFFFFFFFFll) return fail(PIPNN_EINVAL, "capacity must be < 2^32 - 1");
+  if (n_cap <= I.cap) return PIPNN_OK;
+  const size_t n = (size_t)I.n, c = (size_t)n_cap, d = (size_t)I.d;
+  HIPCHK(grow_keep(I.norms, c * 4, n * 4, s));
+  HIPCHK(grow_keep(I.sketches, c * I.m * 4, n * I.m * 4, s));
+  if (I.x_dtype != PIPNN_DTYPE_F32) HIPCHK(grow_keep(I.xf32, c * d * 4, n * d * 4, s));
+  if (I.p.gemm_prec != PIPNN_PREC_FP32) {
+    const size_t eb = I.p.gemm_prec == PIPNN_PREC_FP8 ? 1 : 2;
+    HIPCHK(grow_keep(I.xlow, c * I.ldo * eb, n * I.ldo * eb, s));
+    HIPCHK(grow_keep(I.xscale, c * 4, n * 4, s));
+    HIPCHK(grow_keep(I.lnorms, c * 4, n * 4, s));
+  }
+  I.cap = n_cap;
+  return PIPNN_OK;
+  GUARD_END
+}
+
+pipnn_status pipnn_insert(pipnn_index *idx, int64_t n_new, const int32_t *d_group,
+                          uint64_t *d_reservoirs, uint32_t *d_graph, uint32_t *d_degree,
+                          pipnn_stream_t stream) {
+  GUARD_BEGIN
+  if (!idx || !d_reservoirs || !d_graph || !d_degree || n_new < 0)
+    return fail(PIPNN_EINVAL, "invalid argument");
+  Index &I = *reinterpret_cast<Index *>(idx);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  if (n_new == 0) return PIPNN_OK;
+  if (stream_capturing(s)) return fail(PIPNN_ESTATE, "insert cannot run under capture");
+  if (I.lt_n_leaves < 1) return fail(PIPNN_ESTATE, "insert needs the leaves of a build first");
+  if (I.n + n_new > I.cap)
+    return fail(PIPNN_EOVERFLOW, "insert of %lld points exceeds the reserved capacity %lld",
+                (long long)n_new, (long long)I.cap);
+  const pipnn_params &P = I.p;
+  const int64_t n0 = I.n, n1 = n0 + n_new, d = I.d;
+  const int k = P.k;
+  const int ksel = P.rescore_mult ? P.rescore_mult * k : k;
+
+  // 1. the new rows' float32 copy, norms, sketches and GEMM operand (the
+  //    count is published atomically for a search running on another thread)
+  __atomic_store_n(&I.n, n1, __ATOMIC_RELEASE);
+  I.rp_order_valid = false;  // the leaf order covers the old points only
+  if (I.x_dtype != PIPNN_DTYPE_F32) {
+    const size_t eb = I.x_dtype == PIPNN_DTYPE_F32 ? 4 : 2;
+    HIPCHK(launch_to_f32(reinterpret_cast<const uint8_t *>(I.X) + (size_t)n0 * d * eb, I.x_dtype,
+                         I.xf32.as<float>() + n0 * d, n_new * d, s));
+  }
+  HIPCHK(launch_norms_sketches_range(I, n0, n_new, s));
+  if (P.gemm_prec != PIPNN_PREC_FP32) HIPCHK(launch_quantize_range(I, n0, n_new, s));
+  HIPCHK(launch_fill_u64(d_reservoirs + n0 * P.l_max, empty_slot(), n_new * P.l_max, s));
+
+  // 2. route every new point to its f nearest leaves (by the leaf representatives)
+  const int64_t NL = I.lt_n_leaves;
+  if (NL > 65535) return fail(PIPNN_EINVAL, "insert routes over at most 65535 leaves");
+  HIPCHK(I.lt_rep.ensure((size_t)NL * 4));
+  if (!I.lt_reps_valid) {
+    HIPCHK(launch_leaf_reps(I.xf(), I.d, I.lt_off.as<int64_t>(), I.lt_mem.as<uint32_t>(), NL,
+                            I.lt_rep.as<uint32_t>(), s));
+    I.lt_reps_valid = true;
+  }
+  const int f = (int)std::min<int64_t>(std::max(1, P.fanout[0]), NL);
+  {
+    // ids n0 .. n1-1: iota plus n0
+    std::vector<KnnJob> jobs(1);
+    jobs[0] = KnnJob{};
+    jobs[0].n_rows = (int32_t)n_new;
+    jobs[0].n_cols = (int32_t)NL;
+    jobs[0].k_sel = f;
+    if (n_new > 0x7FFFFFFF) return fail(PIPNN_EINVAL, "insert batch too large");
+    std::vector<KnnItem> items = plan_items(jobs, 128);
+    HIPCHK(upload(I.s_jobs, jobs, s));
+    HIPCHK(upload(I.s_items, items, s));
+    std::vector<uint32_t> ids((size_t)n_new);
+    for (int64_t i = 0; i < n_new; ++i) ids[(size_t)i] = (uint32_t)(n0 + i);
+    HIPCHK(upload(I.i_rows, ids, s));
+    HIPCHK(I.i_assign.ensure((size_t)n_new * f * 4));
+    KnnLaunch L{};
+    L.idx = &I;
+    L.row_base = I.i_rows.as<uint32_t>();
+    L.col_base = I.lt_rep.as<uint32_t>();
+    L.jobs = I.s_jobs.as<KnnJob>();
+    L.items = I.s_items.as<KnnItem>();
+    L.n_items = (int32_t)items.size();
+    L.max_cols = (int32_t)NL;
+    L.ksel = f;
+    L.k_out = f;
+    L.out_ids = 0;
+    L.recompute = 0;
+    L.rescore_k = 0;
+    L.prec = knn_operand_dim(I.d, PIPNN_PREC_FP32) ? PIPNN_PREC_FP32 : P.gemm_prec;
+    L.nw = 4;
+    L.persistent = 0;
+    L.out_col = I.i_assign.as<uint32_t>();
+    L.out_dist = nullptr;
+    L.out_matrix = nullptr;
+    HIPCHK(launch_knn(L, s));
+  }
+  std::vector<uint32_t> asg((size_t)n_new * f);
+  std::vector<int32_t> grp((size_t)n_new, 0);
+  HIPCHK(hipMemcpyAsync(asg.data(), I.i_assign.p, asg.size() * 4, hipMemcpyDeviceToHost, s));
+  if (d_group)
+    HIPCHK(hipMemcpyAsync(grp.data(), d_group, grp.size() * 4, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+
+  // 3. one job per (leaf, group): rows = the group's new points routed to the
+  //    leaf; columns = the leaf's members, then those new points
+  std::map<std::pair<int64_t, int32_t>, std::vector<uint32_t>> by;
+  for (int64_t i = 0; i < n_new; ++i)
+    for (int j = 0; j < f; ++j) {
+      const uint32_t L = asg[(size_t)i * f + j];
+      if (L < (uint32_t)NL) by[{(int64_t)L, grp[(size_t)i]}].push_back((uint32_t)(n0 + i));
+    }
+  std::vector<KnnJob> jobs;
+  std::vector<uint32_t> rows_h, cols_h;
+  std::vector<const uint32_t *> seg_src;
+  std::vector<int64_t> seg_dst;
+  std::vector<int32_t> seg_len;
+  for (auto &kv : by) {
+    const int64_t L = kv.first.first;
+    const auto &pts = kv.second;
+    const int64_t mo = I.lt_offs[(size_t)L], ms = I.lt_offs[(size_t)L + 1] - mo;
+    if (ms + (int64_t)pts.size() > 65535) return fail(PIPNN_EINVAL, "leaf %lld grows past 65535",
+                                                     (long long)L);
+    KnnJob J{};
+    J.row_off = (int64_t)rows_h.size();
+    J.col_off = (int64_t)cols_h.size();
+    J.out_off = (int64_t)rows_h.size();
+    J.n_rows = (int32_t)pts.size();
+    J.n_cols = (int32_t)(ms + (int64_t)pts.size());
+    J.k_sel = ksel;
+    J.flags = 1;
+    J.self_off = (int32_t)ms;
+    jobs.push_back(J);
+    seg_src.push_back(I.lt_mem.as<uint32_t>() + mo);
+    seg_dst.push_back((int64_t)cols_h.size());
+    seg_len.push_back((int32_t)ms);
+    cols_h.resize(cols_h.size() + (size_t)ms, 0u);
+    cols_h.insert(cols_h.end(), pts.begin(), pts.end());
+    rows_h.insert(rows_h.end(), pts.begin(), pts.end());
+  }
+  const int64_t rows = (int64_t)rows_h.size();
+  HIPCHK(upload(I.i_rows, rows_h, s));
+  HIPCHK(upload(I.i_cols, cols_h, s));
+  HIPCHK(upload(I.i_segs, seg_src, s));
+  HIPCHK(I.i_tmp.ensure((seg_dst.size() + 1) * 8 + (seg_len.size() + 1) * 4));
+  HIPCHK(hipMemcpyAsync(I.i_tmp.p, seg_dst.data(), seg_dst.size() * 8, hipMemcpyHostToDevice, s));
+  int32_t *d_len = reinterpret_cast<int32_t *>(I.i_tmp.as<int64_t>() + seg_dst.size() + 1);
+  HIPCHK(hipMemcpyAsync(d_len, seg_len.data(), seg_len.size() * 4, hipMemcpyHostToDevice, s));
+  HIPCHK(launch_copy_segments(I.i_segs.as<const uint32_t *>(), I.i_tmp.as<int64_t>(), d_len,
+                              (int32_t)seg_len.size(), I.i_cols.as<uint32_t>(), s));
+  HIPCHK(I.s_picks_c.ensure((size_t)rows * k * 4));
+  HIPCHK(I.s_picks_d.ensure((size_t)rows * k * 4));
+  {
+    std::vector<KnnItem> items = plan_items(jobs, 32 * I.leaf_nw);
+    HIPCHK(upload(I.s_jobs, jobs, s));
+    HIPCHK(upload(I.s_items, items, s));
+    HIPCHK(launch_fill_u32(I.s_picks_c.as<uint32_t>(), kEmptyId, rows * k, s));
+    HIPCHK(launch_fill_u32(I.s_picks_d.as<uint32_t>(), 0x7F800000u, rows * k, s));
+    KnnLaunch L{};
+    L.idx = &I;
+    L.row_base = I.i_rows.as<uint32_t>();
+    L.col_base = I.i_cols.as<uint32_t>();
+    L.jobs = I.s_jobs.as<KnnJob>();
+    L.items = I.s_items.as<KnnItem>();
+    L.n_items = (int32_t)items.size();
+    L.ksel = ksel;
+    L.k_out = k;
+    L.out_ids = 1;
+    L.recompute = gemm_is_direct(I) ? 0 : 1;
+    L.rescore_k = P.rescore_mult ? k : 0;
+    L.prec = P.gemm_prec;
+    L.nw = I.leaf_nw;
+    L.persistent = 0;
+    L.out_col = I.s_picks_c.as<uint32_t>();
+    L.out_dist = I.s_picks_d.as<float>();
+    L.out_matrix = nullptr;
+    HIPCHK(launch_knn(L, s));
+  }
+  // 4. both directed records of every pick into HashPrune
+  pipnn_status st = bin_and_merge(I, true, I.i_rows.as<uint32_t>(), I.s_picks_c.as<uint32_t>(),
+                                  I.s_picks_d.as<float>(), rows, k, d_reservoirs, s);
+  if (st != PIPNN_OK) return st;
+  // 5. RobustPrune of every point whose reservoir may have changed
+  HIPCHK(I.i_flag.ensure((size_t)n1 * 4));
+  HIPCHK(I.i_pos.ensure((size_t)(n1 + 1) * 8));
+  HIPCHK(I.i_list.ensure((size_t)n1 * 4));
+  HIPCHK(I.o_tmp.ensure((size_t)scan_tmp_elems(n1) * 8));
+  HIPCHK(launch_fill_u32(I.i_flag.as<uint32_t>(), 0u, n1, s));
+  HIPCHK(launch_mark_ids(I.i_rows.as<uint32_t>(), rows, n1, I.i_flag.as<uint32_t>(), s));
+  HIPCHK(launch_mark_ids(I.s_picks_c.as<uint32_t>(), rows * k, n1, I.i_flag.as<uint32_t>(), s));
+  HIPCHK(launch_scan_u32(I.i_flag.as<uint32_t>(), I.i_pos.as<int64_t>(), n1,
+                         I.o_tmp.as<int64_t>(), s));
+  HIPCHK(launch_compact_flags(I.i_flag.as<uint32_t>(), I.i_pos.as<int64_t>(), n1,
+                              I.i_list.as<uint32_t>(), s));
+  int64_t touched = 0;
+  HIPCHK(hipMemcpyAsync(&touched, I.i_pos.as<int64_t>() + n1, 8, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  HIPCHK(launch_robustprune(I, d_reservoirs, d_graph, d_degree, I.i_list.as<uint32_t>(), touched,
+                            s));
+  return finish_bins(I, s, "insert");
   GUARD_END
 }
 
@@ -1269,7 +1522,7 @@ pipnn_status pipnn_robustprune(pipnn_index *idx, const uint64_t *d_reservoirs, u
   if (!idx || !d_reservoirs || !d_graph || !d_degree) return fail(PIPNN_EINVAL, "NULL argument");
   Index &I = *reinterpret_cast<Index *>(idx);
   PhaseTimer t(I, kPhRobustPrune, reinterpret_cast<hipStream_t>(stream));
-  HIPCHK(launch_robustprune(I, d_reservoirs, d_graph, d_degree,
+  HIPCHK(launch_robustprune(I, d_reservoirs, d_graph, d_degree, nullptr, 0,
                             reinterpret_cast<hipStream_t>(stream)));
   return PIPNN_OK;
   GUARD_END
@@ -1300,26 +1553,28 @@ pipnn_status pipnn_search(pipnn_index *idx, const uint32_t *d_graph, const void 
   Index &I = *reinterpret_cast<Index *>(idx);
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   if (k < 1 || k > L || L > 1024) return fail(PIPNN_EINVAL, "need 1 <= k <= L <= 1024");
-  if ((int64_t)start >= I.n) return fail(PIPNN_EINVAL, "start >= n");
+  // one reading of the point count: an insertion on another thread may grow it
+  const int64_t n = __atomic_load_n(&I.n, __ATOMIC_ACQUIRE);
+  if ((int64_t)start >= n) return fail(PIPNN_EINVAL, "start >= n");
   if (q_dtype != PIPNN_DTYPE_F32 && q_dtype != PIPNN_DTYPE_F16 && q_dtype != PIPNN_DTYPE_BF16)
     return fail(PIPNN_EINVAL, "unknown q_dtype");
   if (nq == 0) return PIPNN_OK;
   const float *Q = reinterpret_cast<const float *>(d_Q);
   if (q_dtype != PIPNN_DTYPE_F32) {
-    HIPCHK(I.s_tmp0.ensure((size_t)nq * I.d * 4));
-    HIPCHK(launch_to_f32(d_Q, q_dtype, I.s_tmp0.as<float>(), nq * (int64_t)I.d, s));
-    Q = I.s_tmp0.as<float>();
+    HIPCHK(I.q_conv.ensure((size_t)nq * I.d * 4));
+    HIPCHK(launch_to_f32(d_Q, q_dtype, I.q_conv.as<float>(), nq * (int64_t)I.d, s));
+    Q = I.q_conv.as<float>();
   }
-  const int64_t words = (I.n + 31) / 32;
+  const int64_t words = (n + 31) / 32;
   const int64_t budget_words = (int64_t)1 << 26;  // 256 MiB of seen bitmaps
   const int64_t batch = std::max<int64_t>(1, std::min<int64_t>(nq, budget_words / words));
-  HIPCHK(I.s_tmp1.ensure((size_t)batch * words * 4));
+  HIPCHK(I.q_seen.ensure((size_t)batch * words * 4));
   for (int64_t q0 = 0; q0 < nq; q0 += batch) {
     const int64_t nb = std::min(batch, nq - q0);
-    HIPCHK(hipMemsetAsync(I.s_tmp1.p, 0, (size_t)nb * words * 4, s));
-    HIPCHK(launch_search(I, d_graph, Q + q0 * I.d, nb, k, L, start, d_out_ids + q0 * k,
+    HIPCHK(hipMemsetAsync(I.q_seen.p, 0, (size_t)nb * words * 4, s));
+    HIPCHK(launch_search(I, n, d_graph, Q + q0 * I.d, nb, k, L, start, d_out_ids + q0 * k,
                          d_out_dist ? d_out_dist + q0 * k : nullptr,
-                         d_out_cmps ? d_out_cmps + q0 : nullptr, I.s_tmp1.as<uint32_t>(), words,
+                         d_out_cmps ? d_out_cmps + q0 : nullptr, I.q_seen.as<uint32_t>(), words,
                          s));
   }
   return PIPNN_OK;

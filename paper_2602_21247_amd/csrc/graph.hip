@@ -76,12 +76,14 @@ constexpr int kRpWaves = 4;
 
 __global__ void __launch_bounds__(64 * kRpWaves) robustprune_kernel(
     const float *__restrict__ X, int64_t n, int d, int metric, const uint64_t *__restrict__ res,
-    int l_max, float alpha, int R, uint32_t *__restrict__ graph, uint32_t *__restrict__ degree) {
+    int l_max, float alpha, int R, const uint32_t *__restrict__ order, int64_t n_items,
+    uint32_t *__restrict__ graph, uint32_t *__restrict__ degree) {
   __shared__ uint64_t sK[kRpWaves][256];
   __shared__ uint32_t sE[kRpWaves][256];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int64_t x = (int64_t)blockIdx.x * kRpWaves + wave;
-  if (x >= n) return;
+  const int64_t it = (int64_t)blockIdx.x * kRpWaves + wave;
+  if (it >= n_items) return;
+  const int64_t x = order ? (int64_t)order[it] : it;
   const bool l2 = metric == PIPNN_METRIC_L2;
   uint64_t *K = sK[wave];
   uint32_t *E = sE[wave];
@@ -160,7 +162,7 @@ template <int DP>
 __global__ void __launch_bounds__(64 * kRpWaves) robustprune_mfma_kernel(
     const float *__restrict__ X, const float *__restrict__ norms, int64_t n, int d, int metric,
     const uint64_t *__restrict__ res, int l_max, float alpha, int R,
-    const uint32_t *__restrict__ order, uint32_t *__restrict__ graph,
+    const uint32_t *__restrict__ order, int64_t n_items, uint32_t *__restrict__ graph,
     uint32_t *__restrict__ degree) {
   constexpr int HALF = DP / 2;
   __shared__ uint64_t sK[kRpWaves][64];
@@ -170,7 +172,7 @@ __global__ void __launch_bounds__(64 * kRpWaves) robustprune_mfma_kernel(
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int h = lane >> 5, l32 = lane & 31;
   const int64_t item = (int64_t)xcd_item(blockIdx.x, gridDim.x) * kRpWaves + wave;
-  if (item >= n) return;
+  if (item >= n_items) return;
   const uint32_t x = __builtin_amdgcn_readfirstlane(order ? order[item] : (uint32_t)item);
   const bool l2 = metric == PIPNN_METRIC_L2;
   const bool full_d = d == DP;
@@ -324,8 +326,8 @@ constexpr int kRpwTri = kRpwRows * (kRpwRows + 1) / 2;
 template <int PREC, int DP, bool L2>
 __global__ void __launch_bounds__(256, 1) robustprune_wide_kernel(
     const uint8_t *__restrict__ Xop, int64_t op_ld, int64_t n, const uint64_t *__restrict__ res,
-    int l_max, float alpha, int R, const uint32_t *__restrict__ order, uint32_t *__restrict__ graph,
-    uint32_t *__restrict__ degree) {
+    int l_max, float alpha, int R, const uint32_t *__restrict__ order, int64_t n_items,
+    uint32_t *__restrict__ graph, uint32_t *__restrict__ degree) {
   constexpr int LROW = kRpwKC + 8;  // staged row stride (16-bit elements)
   constexpr int NCHUNK = DP / kRpwKC;
   static_assert(kRpwRows * LROW / 2 <= kRpwTri, "staging fits in the Gram region");
@@ -336,7 +338,7 @@ __global__ void __launch_bounds__(256, 1) robustprune_wide_kernel(
   __shared__ float sDx[kRpWaves][kRpwRows];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t item = (int64_t)xcd_item(blockIdx.x, gridDim.x) * kRpWaves + wave;
-  if (item >= n) return;
+  if (item >= n_items) return;
   const uint32_t x = __builtin_amdgcn_readfirstlane(order ? order[item] : (uint32_t)item);
   uint32_t *W = sW[wave];
   uint32_t *ids = sId[wave];
@@ -453,15 +455,18 @@ __global__ void __launch_bounds__(256, 1) robustprune_wide_kernel(
 }
 
 hipError_t launch_robustprune(const Index &I, const uint64_t *res, uint32_t *graph, uint32_t *degree,
-                              hipStream_t s) {
+                              const uint32_t *subset, int64_t n_subset, hipStream_t s) {
   if (I.p.l_max > 256 || I.p.R > 256) return hipErrorInvalidValue;
-  const uint32_t *order = I.rp_order_valid ? I.rp_order.as<uint32_t>() : nullptr;
+  const uint32_t *order =
+      subset ? subset : (I.rp_order_valid ? I.rp_order.as<uint32_t>() : nullptr);
+  const int64_t n_items = subset ? n_subset : I.n;
+  if (n_items <= 0) return hipSuccess;
   if (I.p.l_max <= 64 && I.d <= 128) {
-    const int64_t blocks = xcd_grid((I.n + kRpWaves - 1) / kRpWaves);
+    const int64_t blocks = xcd_grid((n_items + kRpWaves - 1) / kRpWaves);
     auto args = [&](auto kern) {
       hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(64 * kRpWaves), 0, s, I.xf(),
                          I.norms.as<float>(), I.n, I.d, I.p.metric, res, I.p.l_max, I.p.alpha,
-                         I.p.R, order, graph, degree);
+                         I.p.R, order, n_items, graph, degree);
     };
     if (I.d <= 32) args(robustprune_mfma_kernel<32>);
     else if (I.d <= 64) args(robustprune_mfma_kernel<64>);
@@ -473,13 +478,13 @@ hipError_t launch_robustprune(const Index &I, const uint64_t *res, uint32_t *gra
   const bool wide_op = (I.p.gemm_prec == PIPNN_PREC_FP16 || I.p.gemm_prec == PIPNN_PREC_BF16) &&
                        (dp == 512 || dp == 768) && I.xlow.p;
   if (wide_op && I.p.l_max <= kRpwRows - 1 && I.p.R <= 64) {
-    const int64_t blocks = xcd_grid((I.n + kRpWaves - 1) / kRpWaves);
+    const int64_t blocks = xcd_grid((n_items + kRpWaves - 1) / kRpWaves);
     const uint8_t *xop = I.xlow.as<uint8_t>();
     const int64_t op_ld = (int64_t)dp * 2;
     const bool l2 = I.p.metric == PIPNN_METRIC_L2;
     auto go = [&](auto kern) {
       hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(64 * kRpWaves), 0, s, xop, op_ld, I.n,
-                         res, I.p.l_max, I.p.alpha, I.p.R, order, graph, degree);
+                         res, I.p.l_max, I.p.alpha, I.p.R, order, n_items, graph, degree);
     };
     if (I.p.gemm_prec == PIPNN_PREC_FP16) {
       if (dp == 512) l2 ? go(robustprune_wide_kernel<PIPNN_PREC_FP16, 512, true>)
@@ -494,9 +499,10 @@ hipError_t launch_robustprune(const Index &I, const uint64_t *res, uint32_t *gra
     }
     return hipGetLastError();
   }
-  const int64_t blocks = (I.n + kRpWaves - 1) / kRpWaves;
+  const int64_t blocks = (n_items + kRpWaves - 1) / kRpWaves;
   hipLaunchKernelGGL(robustprune_kernel, dim3((unsigned)blocks), dim3(64 * kRpWaves), 0, s, I.xf(),
-                     I.n, I.d, I.p.metric, res, I.p.l_max, I.p.alpha, I.p.R, graph, degree);
+                     I.n, I.d, I.p.metric, res, I.p.l_max, I.p.alpha, I.p.R, order, n_items, graph,
+                     degree);
   return hipGetLastError();
 }
 
@@ -697,13 +703,14 @@ __global__ void __launch_bounds__(64) search_kernel(const float *__restrict__ X,
   if (out_cmps && lane == 0) out_cmps[qi] = cmps;
 }
 
-hipError_t launch_search(const Index &I, const uint32_t *graph, const float *Q, int64_t nq,
-                         int32_t k, int32_t L, uint32_t start, uint32_t *out_ids, float *out_dist,
-                         uint32_t *out_cmps, uint32_t *visited_bits, int64_t words_per_query,
-                         hipStream_t s) {
+hipError_t launch_search(const Index &I, int64_t n, const uint32_t *graph, const float *Q,
+                         int64_t nq, int32_t k, int32_t L, uint32_t start, uint32_t *out_ids,
+                         float *out_dist, uint32_t *out_cmps, uint32_t *visited_bits,
+                         int64_t words_per_query, hipStream_t s) {
   if (nq == 0) return hipSuccess;
-  if (L > kMaxL || I.p.R > kMaxR || I.d > kMaxQD) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(search_kernel, dim3((unsigned)nq), dim3(64), 0, s, I.xf(), I.n, I.d,
+  if (L > kMaxL || I.p.R > kMaxR || I.d > kMaxQD || words_per_query * 32 < n)
+    return hipErrorInvalidValue;
+  hipLaunchKernelGGL(search_kernel, dim3((unsigned)nq), dim3(64), 0, s, I.xf(), n, I.d,
                      I.p.metric, graph, I.p.R, Q, k, L, start, out_ids, out_dist, out_cmps,
                      visited_bits, words_per_query);
   return hipGetLastError();

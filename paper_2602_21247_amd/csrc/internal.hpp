@@ -46,6 +46,15 @@ struct Index {
   DevBuf p_asg, p_leaders, p_cm, p_bstart, p_groups, p_gout, p_gsize, p_copy;
   DevBuf rp_order;              // RobustPrune processing order (from the last leaves)
   DevBuf s_counter;             // per-XCD work counters of the persistent leaf schedule
+  // the leaves of the last build, kept for insertion: CSR rebased to 0 (a
+  // host copy of the offsets too) and one representative member per leaf
+  DevBuf lt_off, lt_mem, lt_rep;
+  std::vector<int64_t> lt_offs;
+  int64_t lt_n_leaves = 0;
+  bool lt_reps_valid = false;
+  int64_t cap = 0;              // rows the per-point buffers hold (pipnn_reserve)
+  DevBuf i_rows, i_cols, i_assign, i_flag, i_pos, i_list, i_tmp, i_segs;
+  DevBuf q_conv, q_seen;        // search scratch (search may overlap an insertion)
   int32_t n_cu = 256;           // compute units of the device (persistent grid size)
   int32_t leaf_nw = 4;          // waves (of 32 rows) per leaf work item: 4, or 2 where built
   int32_t leaf_persistent = 0;  // 1: persistent workgroups take items from the counters
@@ -104,7 +113,9 @@ struct KnnJob {
   int64_t out_off;   // first output row
   int32_t n_rows, n_cols;
   int32_t k_sel;     // number of GEMM-nearest kept (<= KSEL)
-  int32_t flags;     // bit 0: exclude the column at the row's own position
+  int32_t flags;     // bit 0: exclude column self_off + r for row r (the row itself)
+  int32_t self_off;  // column of row 0 when bit 0 is set
+  int32_t pad_;
 };
 struct KnnItem {
   int32_t job, rb;
@@ -150,6 +161,19 @@ hipError_t launch_norms_sketches(const Index &I, hipStream_t s);
 // (n x I.ldo), decode scales into I.xscale (fp8), squared norms of the
 // decoded vectors into I.lnorms.
 hipError_t launch_quantize(const Index &I, hipStream_t s);
+// the same for points [p0, p0 + cnt) only
+hipError_t launch_norms_sketches_range(const Index &I, int64_t p0, int64_t cnt, hipStream_t s);
+hipError_t launch_quantize_range(const Index &I, int64_t p0, int64_t cnt, hipStream_t s);
+// leaf table: offsets rebased to 0, member copy, one representative per leaf
+hipError_t launch_rebase_i64(const int64_t *in, int64_t n, int64_t *out, hipStream_t s);
+hipError_t launch_copy_u32(const uint32_t *in, int64_t n, uint32_t *out, hipStream_t s);
+hipError_t launch_leaf_reps(const float *X, int d, const int64_t *off, const uint32_t *mem,
+                            int64_t n_leaves, uint32_t *rep, hipStream_t s);
+// flag[v] = 1 for every id v < n in ids; out[pos[i]] = i for flagged i
+hipError_t launch_mark_ids(const uint32_t *ids, int64_t cnt, int64_t n, uint32_t *flag,
+                           hipStream_t s);
+hipError_t launch_compact_flags(const uint32_t *flag, const int64_t *pos, int64_t n, uint32_t *out,
+                                hipStream_t s);
 hipError_t launch_to_f32(const void *src, int dtype, float *dst, int64_t count, hipStream_t s);
 hipError_t launch_iota(uint32_t *dst, int64_t n, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *dst, uint32_t v, int64_t n, hipStream_t s);
@@ -207,15 +231,18 @@ hipError_t launch_reservoir_canonical(const uint64_t *in, uint64_t *out, int64_t
                                       hipStream_t s);
 
 // ---- RobustPrune / search ---------------------------------------------
+// RobustPrune of every point (subset NULL; in leaf order when known) or of
+// the n_subset points listed in subset.
 hipError_t launch_robustprune(const Index &I, const uint64_t *res, uint32_t *graph, uint32_t *degree,
-                              hipStream_t s);
+                              const uint32_t *subset, int64_t n_subset, hipStream_t s);
 hipError_t launch_leaf_order(const uint32_t *mem, int64_t cnt, int64_t n, uint32_t *first,
                              uint32_t *flag, int64_t *pos, int64_t *pos2, int64_t *tmp,
                              uint32_t *order, hipStream_t s);
 hipError_t launch_start_node(const Index &I, double *tmp, uint32_t *out, hipStream_t s);
-hipError_t launch_search(const Index &I, const uint32_t *graph, const float *Q, int64_t nq,
-                         int32_t k, int32_t L, uint32_t start, uint32_t *out_ids, float *out_dist,
-                         uint32_t *out_cmps, uint32_t *visited_bits, int64_t words_per_query,
-                         hipStream_t s);
+// n: the point count the graph covers (ids >= n are not visited)
+hipError_t launch_search(const Index &I, int64_t n, const uint32_t *graph, const float *Q,
+                         int64_t nq, int32_t k, int32_t L, uint32_t start, uint32_t *out_ids,
+                         float *out_dist, uint32_t *out_cmps, uint32_t *visited_bits,
+                         int64_t words_per_query, hipStream_t s);
 
 }  // namespace pipnn

@@ -406,7 +406,7 @@ __device__ __forceinline__ void knn_item(const KnnArgs &a, const int item) {
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
         const int rr = wrow + acc_row(v, h);
-        const bool ok = vc && dv[v] <= tau[v] && !(excl && rr == cc);
+        const bool ok = vc && dv[v] <= tau[v] && !(excl && rr + J.self_off == cc);
         pass |= (ok ? 1u : 0u) << v;
       }
       if (__ballot(pass != 0) == 0ull) continue;

@@ -236,7 +236,7 @@ __device__ __forceinline__ void knn_wide_item(const KnnArgs &a, const int item) 
         dv[g][j] = l2 ? sNr[rl] + fmaf(-2.f, x, nc) : -x;
         if (a.out_matrix && vc && wrow + 4 * q + j < n_rows)
           a.out_matrix[(J.out_off + wrow + 4 * q + j) * a.matrix_ld + cc] = dv[g][j];
-        const bool ok = vc && dv[g][j] <= sTau[rl] && !(excl && wrow + 4 * q + j == cc);
+        const bool ok = vc && dv[g][j] <= sTau[rl] && !(excl && wrow + 4 * q + j + J.self_off == cc);
         pass |= (ok ? 1u : 0u) << (4 * g + j);
       }
     }

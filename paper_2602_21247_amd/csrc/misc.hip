@@ -54,10 +54,16 @@ __global__ void __launch_bounds__(256) norms_sketches_kernel(const float *__rest
 }
 
 hipError_t launch_norms_sketches(const Index &I, hipStream_t s) {
-  const int64_t blocks = (I.n + 255) / 256;
+  return launch_norms_sketches_range(I, 0, I.n, s);
+}
+
+hipError_t launch_norms_sketches_range(const Index &I, int64_t p0, int64_t cnt, hipStream_t s) {
+  if (cnt <= 0) return hipSuccess;
+  const int64_t blocks = (cnt + 255) / 256;
   const size_t lds = (size_t)I.m * I.d * sizeof(float);
-  hipLaunchKernelGGL(norms_sketches_kernel, dim3((unsigned)blocks), dim3(256), lds, s, I.xf(), I.n,
-                     I.d, I.H, I.m, I.norms.as<float>(), I.sketches.as<float>());
+  hipLaunchKernelGGL(norms_sketches_kernel, dim3((unsigned)blocks), dim3(256), lds, s,
+                     I.xf() + p0 * I.d, cnt, I.d, I.H, I.m, I.norms.as<float>() + p0,
+                     I.sketches.as<float>() + p0 * I.m);
   return hipGetLastError();
 }
 
@@ -138,9 +144,131 @@ __global__ void __launch_bounds__(256) quantize_kernel(const float *__restrict__
 }
 
 hipError_t launch_quantize(const Index &I, hipStream_t s) {
-  const int64_t blocks = (I.n + 3) / 4;
-  hipLaunchKernelGGL(quantize_kernel, dim3((unsigned)blocks), dim3(256), 0, s, I.xf(), I.n, I.d,
-                     I.ldo, I.p.gemm_prec, I.xlow.p, I.xscale.as<float>(), I.lnorms.as<float>());
+  return launch_quantize_range(I, 0, I.n, s);
+}
+
+hipError_t launch_quantize_range(const Index &I, int64_t p0, int64_t cnt, hipStream_t s) {
+  if (cnt <= 0) return hipSuccess;
+  const int64_t blocks = (cnt + 3) / 4;
+  const size_t eb = I.p.gemm_prec == PIPNN_PREC_FP8 ? 1 : 2;
+  hipLaunchKernelGGL(quantize_kernel, dim3((unsigned)blocks), dim3(256), 0, s, I.xf() + p0 * I.d,
+                     cnt, I.d, I.ldo, I.p.gemm_prec,
+                     reinterpret_cast<void *>(I.xlow.as<uint8_t>() + p0 * I.ldo * eb),
+                     I.xscale.as<float>() + p0, I.lnorms.as<float>() + p0);
+  return hipGetLastError();
+}
+
+// ---- leaf table of an index (kept for insertion) ------------------------
+__global__ void rebase_i64_kernel(const int64_t *in, int64_t n, int64_t *out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = in[i] - in[0];
+}
+__global__ void copy_u32_kernel(const uint32_t *in, int64_t n, uint32_t *out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = in[i];
+}
+hipError_t launch_rebase_i64(const int64_t *in, int64_t n, int64_t *out, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(rebase_i64_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, in, n,
+                     out);
+  return hipGetLastError();
+}
+hipError_t launch_copy_u32(const uint32_t *in, int64_t n, uint32_t *out, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(copy_u32_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, in, n,
+                     out);
+  return hipGetLastError();
+}
+
+// Representative of each leaf: the member m with the smallest
+// (sum_i (s * x_mi - S_i)^2, id), S_i = sum of the leaf's members in
+// dimension i and s the leaf size -- s^2 times m's squared distance to the
+// leaf mean, without a division -- in FP64 (exact for integer-valued data).
+// One workgroup per leaf.
+__global__ void __launch_bounds__(256) leaf_rep_kernel(const float *__restrict__ X, int d,
+                                                       const int64_t *__restrict__ off,
+                                                       const uint32_t *__restrict__ mem,
+                                                       uint32_t *__restrict__ rep) {
+  extern __shared__ double sS[];  // d doubles
+  __shared__ double sBd[256];
+  __shared__ uint32_t sBi[256];
+  const int64_t L = blockIdx.x;
+  const int64_t o = off[L], s = off[L + 1] - off[L];
+  if (s <= 0) {
+    if (threadIdx.x == 0) rep[L] = 0u;  // any valid id: an empty leaf adds no members
+    return;
+  }
+  for (int i = threadIdx.x; i < d; i += blockDim.x) {
+    double acc = 0.0;
+    for (int64_t j = 0; j < s; ++j) acc += (double)X[(int64_t)mem[o + j] * d + i];
+    sS[i] = acc;
+  }
+  __syncthreads();
+  double bd = INFINITY;
+  uint32_t bi = 0xFFFFFFFFu;
+  const double sd = (double)s;
+  for (int64_t j = threadIdx.x; j < s; j += blockDim.x) {
+    const uint32_t id = mem[o + j];
+    const float *x = X + (int64_t)id * d;
+    double dd = 0.0;
+    for (int i = 0; i < d; ++i) {
+      const double t = sd * (double)x[i] - sS[i];
+      dd = fma(t, t, dd);
+    }
+    if (dd < bd || (dd == bd && id < bi)) {
+      bd = dd;
+      bi = id;
+    }
+  }
+  sBd[threadIdx.x] = bd;
+  sBi[threadIdx.x] = bi;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      const double od = sBd[threadIdx.x + w];
+      const uint32_t oi = sBi[threadIdx.x + w];
+      if (od < sBd[threadIdx.x] || (od == sBd[threadIdx.x] && oi < sBi[threadIdx.x])) {
+        sBd[threadIdx.x] = od;
+        sBi[threadIdx.x] = oi;
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) rep[L] = sBi[0];
+}
+hipError_t launch_leaf_reps(const float *X, int d, const int64_t *off, const uint32_t *mem,
+                            int64_t n_leaves, uint32_t *rep, hipStream_t s) {
+  if (n_leaves <= 0) return hipSuccess;
+  hipLaunchKernelGGL(leaf_rep_kernel, dim3((unsigned)n_leaves), dim3(256), (size_t)d * 8, s, X, d,
+                     off, mem, rep);
+  return hipGetLastError();
+}
+
+// ---- touched-set compaction -----------------------------------------------
+__global__ void mark_ids_kernel(const uint32_t *ids, int64_t cnt, int64_t n, uint32_t *flag) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < cnt) {
+    const uint32_t v = ids[i];
+    if (v < n) flag[v] = 1u;
+  }
+}
+__global__ void compact_flags_kernel(const uint32_t *flag, const int64_t *pos, int64_t n,
+                                     uint32_t *out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && flag[i]) out[pos[i]] = (uint32_t)i;
+}
+hipError_t launch_mark_ids(const uint32_t *ids, int64_t cnt, int64_t n, uint32_t *flag,
+                           hipStream_t s) {
+  if (cnt <= 0) return hipSuccess;
+  hipLaunchKernelGGL(mark_ids_kernel, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, ids,
+                     cnt, n, flag);
+  return hipGetLastError();
+}
+hipError_t launch_compact_flags(const uint32_t *flag, const int64_t *pos, int64_t n, uint32_t *out,
+                                hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(compact_flags_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                     flag, pos, n, out);
   return hipGetLastError();
 }
 
