@@ -57,6 +57,10 @@ def parse():
     ap.add_argument("--queries", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-recall", action="store_true")
+    ap.add_argument("--no-serving", action="store_true",
+                    help="skip the insert/query serving stage")
+    ap.add_argument("--serve-requests", type=int, default=200,
+                    help="requests of the serving stage (80%% queries, 20%% insertions)")
     ap.add_argument("--cpu-budget", type=float, default=4.0,
                     help="target seconds of oracle work per sampled phase")
     ap.add_argument("--prec", default=None, choices=sorted(PREC_CODES),
@@ -200,6 +204,109 @@ def cpu_baseline(X, H, off, mem, res_np, stats, w, budget):
         "phase_s": {"sketches": t_sk, "partition": t_part, "leaf_pick": t_leaf,
                     "hashprune": t_hp, "robustprune": t_rp},
     }
+
+
+def serving_stage(args, torch, np, pp, pi, w, cfg, X, H, p_kw, L_serve):
+    """Insert/query serving on the workload's index: the seeded request
+    stream (80% k=10 query batches of floor(exp(U(0, ln 4097))) queries, 20%
+    insertion batches of floor(exp(U(0, ln 50001))) fresh points of the same
+    mixture) first arrives all at once (closed loop: the capacity in
+    requests/s), then as a Poisson process at half that capacity on a fresh
+    copy of the index; latencies of the second run are reported."""
+    from paper_2602_21247_amd import serving
+    rng = np.random.default_rng(5)
+    n = X.shape[0]
+    kinds = rng.random(args.serve_requests) < 0.8
+    sizes_q = np.floor(np.exp(rng.uniform(0, np.log(4097), args.serve_requests))).astype(int)
+    sizes_i = np.floor(np.exp(rng.uniform(0, np.log(50001), args.serve_requests))).astype(int)
+    n_ins = int(sizes_i[~kinds].sum())
+    cap = n + n_ins
+    newpts = pi.integer_mixture(n_ins, w.d, 1000, pi.INT_MIXTURE_SIGMA, seed=5005,
+                                center_seed=2) if cfg == 2 else pi.workload_points(cfg, cap)[n:]
+    nq = int(sizes_q[kinds].sum())
+    Qall = pi.workload_queries(cfg, nq)
+    reqs_proto = []
+    qo = io = 0
+    for rid in range(args.serve_requests):
+        if kinds[rid]:
+            m = int(sizes_q[rid])
+            reqs_proto.append(("query", Qall[qo:qo + m]))
+            qo += m
+        else:
+            m = int(sizes_i[rid])
+            reqs_proto.append(("insert", newpts[io:io + m]))
+            io += m
+
+    def fresh():
+        Xc = torch.empty((cap, w.d), dtype=torch.float32, device="cuda")
+        Xc[:n].copy_(torch.from_numpy(X))
+        params = pp.default_params(**p_kw)
+        idx = pp.Index(Xc[:n], torch.from_numpy(H).cuda(), params)
+        off, mem = idx.partition()
+        res = torch.empty((cap, w.l_max), dtype=torch.int64, device="cuda")
+        pp.reservoir_init(n, w.l_max, out=res[:n])
+        idx.build_leaves(off, mem, res[:n])
+        g = torch.full((cap, w.R), -1, dtype=torch.int32, device="cuda")
+        deg = torch.zeros(cap, dtype=torch.int32, device="cuda")
+        idx.robustprune(res[:n], g[:n], deg[:n])
+        idx.reserve(cap)
+        start = idx.start_node()
+        torch.cuda.synchronize()
+        return idx, Xc, res, g, deg, start
+
+    def run(arrivals):
+        idx, Xc, res, g, deg, start = fresh()
+        reqs = [serving.Request(i, kd, float(arrivals[i]), data)
+                for i, (kd, data) in enumerate(reqs_proto)]
+        srv = serving.Server(idx, Xc, res, g, deg, start, serving.ServerConfig(L=L_serve))
+        t0 = time.perf_counter()
+        out = srv.run(reqs)
+        wall = time.perf_counter() - t0
+        return out, wall, idx, Xc, srv
+
+    out, wall, idx, Xc, srv = run(np.zeros(args.serve_requests))
+    capacity = args.serve_requests / wall
+    idx.close()
+    del Xc, srv
+    log(f"[bench] serving: closed loop {args.serve_requests} requests in {wall:.2f} s "
+        f"({capacity:.1f} requests/s)")
+    rate = 0.5 * capacity
+    arr = np.cumsum(np.random.default_rng(55).exponential(1.0 / rate, args.serve_requests))
+    out, wall, idx, Xc, srv = run(arr)
+    summ = serving.summarize(out, wall)
+    ins_pts = sum(len(d) for kd, d in reqs_proto if kd == "insert")
+    qs = sum(len(d) for kd, d in reqs_proto if kd == "query")
+    # recall@10 of a sample of queries against the points committed at their epoch
+    epochs = {}
+    for r in out.values():
+        if r.kind == "query":
+            epochs.setdefault(r.epoch, []).append(r)
+    commit_n = {0: n}
+    for r in sorted((r for r in out.values() if r.kind == "insert"), key=lambda r: r.first_id):
+        commit_n[r.batch + 1] = r.first_id + len(reqs_proto[r.rid][1])
+    hits = tot = 0
+    budget = 2000
+    for e, rs in sorted(epochs.items()):
+        if tot >= budget:
+            break
+        ne = max(v for b, v in commit_n.items() if b <= e)
+        for r in rs:
+            if tot >= budget:
+                break
+            Qd = torch.from_numpy(reqs_proto[r.rid][1]).cuda()
+            kth = ground_truth(torch, Xc[:ne], Qd, w.metric)
+            hits += int((torch.from_numpy(r.dist).cuda().double() <= kth[:, None]).sum().item())
+            tot += r.ids.shape[0] * 10
+    recall = hits / max(1, tot)
+    idx.close()
+    res = {"requests": args.serve_requests, "closed_loop_requests_per_s": capacity,
+           "offered_requests_per_s": rate, "wall_s": wall, "L": L_serve,
+           "inserted_points": ins_pts, "queries": qs,
+           "inserts_per_s": ins_pts / wall, "qps": qs / wall,
+           "recall_at_10_sampled": recall, "recall_sample_queries": tot // 10}
+    res.update(summ)
+    log(f"[bench] serving at {rate:.1f} requests/s: {summ}; recall@10 {recall:.4f}")
+    return res
 
 
 def main():
@@ -378,6 +485,15 @@ def main():
         f.pop("stats")
         variants.append(f)
 
+    serve = None
+    if not args.no_serving and cfg in (2, 3):
+        p_kw = dict(metric=w.metric, c_max=w.c_max, c_min=w.c_min, k=w.k, l_max=w.l_max, R=w.R,
+                    alpha=w.alpha, hash_bits=w.hash_bits, leader_div=w.leader_div,
+                    leader_cap=w.leader_cap, fanout=w.fanout, seed=pi.workload_seed(cfg),
+                    gemm_prec=PREC_CODES[args.prec], rescore_mult=args.rescore_mult)
+        L_serve = main_form["L_at_recall_0.95"] or 128
+        serve = serving_stage(args, torch, np, pp, pi, w, cfg, X, H, p_kw, L_serve)
+
     traffic = traffic_from_profiles() if args.prec == "fp32" else None
     peak = PEAK_MFMA_TFLOPS[args.prec]
     gemm = f"{args.prec}-mfma" + (f", fp32 rescore of top-{args.rescore_mult}k"
@@ -403,7 +519,8 @@ def main():
         "L_at_recall_0.95": main_form["L_at_recall_0.95"],
         "recall_curve": main_form["recall_curve"],
         "leaf_gemm_tflops": achieved,
-        "insert_p99_ms": None,
+        "insert_p99_ms": serve["insert"]["p99_ms"] if serve and "insert" in serve else None,
+        "serving": serve,
         "phase_ms": main_form["phase_ms"],
         "build_stats": {k: st[k] for k in ("n_leaves", "n_members", "leader_dists", "levels",
                                            "leaf_pairs", "records")},

@@ -110,6 +110,7 @@ def lib():
         L.orc_quantize.argtypes = [P, i64, i32, i32, P, P, P]
         L.orc_leaf_knn_lowp.argtypes = [P, P, i32, i32, P, P, i64, i32, i32, P, P]
         L.orc_leaf_reps.argtypes = [P, i32, P, P, i64, P]
+        L.orc_robustprune_points.argtypes = [P, i32, i32, P, P, i64, i32, C.c_float, i32, P, P]
         L.orc_get_threads.restype = i32
         _lib = L
     return _lib
@@ -308,6 +309,19 @@ def robustprune(X, res, alpha: float, R: int, metric: int = 0, lazy: bool = True
     deg = np.zeros(n, dtype=np.uint32)
     lib().orc_robustprune(_p(X), X.shape[1], metric, _p(res), n, l_max, alpha, R,
                           1 if lazy else 0, _p(g), _p(deg))
+    return g, deg
+
+
+def robustprune_points(X, res_rows, xs, alpha: float, R: int, metric: int = 0):
+    """Lazy RobustPrune of points xs from their reservoir rows res_rows."""
+    X = _f32(X)
+    res_rows = np.ascontiguousarray(res_rows, dtype=np.uint64)
+    xs = np.ascontiguousarray(xs, dtype=np.uint32)
+    nx, l_max = res_rows.shape
+    g = np.zeros((nx, R), dtype=np.uint32)
+    deg = np.zeros(nx, dtype=np.uint32)
+    lib().orc_robustprune_points(_p(X), X.shape[1], metric, _p(res_rows), _p(xs), nx, l_max,
+                                 alpha, R, _p(g), _p(deg))
     return g, deg
 
 

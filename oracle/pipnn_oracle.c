@@ -946,6 +946,47 @@ void orc_robustprune(const float *X, int d, int metric, const uint64_t *res, int
  * unseen neighbours, and truncates B to L. It stops when every beam entry
  * is visited and returns the first k entries. cmps counts evaluations of
  * d(q, .), the start included. */
+/* Lazy RobustPrune (as in orc_robustprune) of the listed points only:
+ * point xs[i] uses reservoir row res[i] and writes graph row i. */
+void orc_robustprune_points(const float *X, int d, int metric, const uint64_t *res,
+                            const uint32_t *xs, int64_t nx, int l_max, float alpha_f, int R,
+                            uint32_t *graph, uint32_t *degree) {
+  double alpha = (double)alpha_f;
+#pragma omp parallel
+  {
+    dcand *N = (dcand *)malloc(sizeof(dcand) * (size_t)l_max);
+    uint32_t *E = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)(R > 0 ? R : 1));
+#pragma omp for schedule(dynamic, 16)
+    for (int64_t i0 = 0; i0 < nx; i0++) {
+      const uint32_t x = xs[i0];
+      const float *xv = X + (int64_t)x * d;
+      int nn = 0;
+      for (int i = 0; i < l_max; i++) {
+        uint32_t c = slot_id(res[i0 * l_max + i]);
+        if (c == ORC_EMPTY_ID || c == x) continue;
+        N[nn].id = c;
+        N[nn].d = orc_dist(xv, X + (int64_t)c * d, d, metric);
+        nn++;
+      }
+      qsort(N, (size_t)nn, sizeof(dcand), cmp_dcand);
+      int ne = 0;
+      for (int i = 0; i < nn && ne < R; i++) {
+        const float *cv = X + (int64_t)N[i].id * d;
+        int pruned = 0;
+        for (int e = 0; e < ne && !pruned; e++) {
+          double dyc = orc_dist(X + (int64_t)E[e] * d, cv, d, metric);
+          if (alpha * dyc < N[i].d) pruned = 1;
+        }
+        if (!pruned) E[ne++] = N[i].id;
+      }
+      for (int i = 0; i < R; i++) graph[i0 * R + i] = i < ne ? E[i] : ORC_EMPTY_ID;
+      degree[i0] = (uint32_t)ne;
+    }
+    free(N);
+    free(E);
+  }
+}
+
 void orc_beam_search(const float *X, int64_t n, int d, int metric, const uint32_t *graph, int R,
                      const float *Q, int64_t nq, int k, int L, uint32_t start, uint32_t *out_ids,
                      double *out_dist, uint32_t *out_cmps) {

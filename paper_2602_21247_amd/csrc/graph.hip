@@ -148,16 +148,20 @@ __device__ __forceinline__ int acc_row32(int v, int h) { return (v & 3) + 8 * (v
 
 // RobustPrune with the candidate Gram on MFMA (up to 64 candidates,
 // d <= DP <= 128). One wave per point x:
-//  1. d(x,c) for every reservoir candidate by FP32 direct difference, and a
-//     sort of the candidates by (d(x,c), id);
-//  2. the rows of the sorted candidates are loaded once into MFMA operand
-//     fragments (lane l: candidate l%32 of a 32-block, dims of its half);
-//     G = C C^T on v_mfma_f32_32x32x2_f32, only the blocks with y < z;
+//  1. the valid reservoir candidates, compacted in slot order;
+//  2. their rows loaded once into MFMA operand fragments (lane l: candidate
+//     l%32 of a 32-block, the dims of its half); d(x,c) by FP32 direct
+//     difference from those registers (each half summed in index order, the
+//     lower half's sum plus the upper half's); G = C C^T on
+//     v_mfma_f32_32x32x2_f32;
 //  3. d(y,z) = |y|^2 + |z|^2 - 2 G[y][z] (or -G for inner product), and bit y
 //     of z's 64-bit mask is set when alpha*d(y,z) < d(x,z) (sign of a fused
-//     multiply-add) for y before z in the sorted order;
-//  4. the lazy scan: z is admitted iff its mask has no admitted bit, until R
-//     are admitted. This admits exactly the candidates of Alg. 2.
+//     multiply-add);
+//  4. the candidates ranked by (d(x,c), id) by counting, and the lazy scan in
+//     that order: z is admitted iff its mask has no admitted bit, until R are
+//     admitted. Admitted candidates all come before z in the order, so the
+//     mask may hold later ones too. This admits exactly the candidates of
+//     Alg. 2.
 template <int DP>
 __global__ void __launch_bounds__(64 * kRpWaves) robustprune_mfma_kernel(
     const float *__restrict__ X, const float *__restrict__ norms, int64_t n, int d, int metric,
@@ -169,6 +173,7 @@ __global__ void __launch_bounds__(64 * kRpWaves) robustprune_mfma_kernel(
   __shared__ float sD[kRpWaves][64];
   __shared__ float sN[kRpWaves][64];
   __shared__ uint32_t sI[kRpWaves][64];
+  __shared__ uint32_t sS[kRpWaves][64];  // sorted position -> slot
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int h = lane >> 5, l32 = lane & 31;
   const int64_t item = (int64_t)xcd_item(blockIdx.x, gridDim.x) * kRpWaves + wave;
@@ -176,55 +181,94 @@ __global__ void __launch_bounds__(64 * kRpWaves) robustprune_mfma_kernel(
   const uint32_t x = __builtin_amdgcn_readfirstlane(order ? order[item] : (uint32_t)item);
   const bool l2 = metric == PIPNN_METRIC_L2;
   const bool full_d = d == DP;
-  uint64_t *K = sK[wave];
 
-  // 1. candidates, their distance to x, sorted by (distance, id)
+  // 1. valid candidates in slot order
+  int nv;
   {
-    uint64_t key = kNoKey;
-    if (lane < l_max) {
-      const uint32_t c = slot_id(res[(int64_t)x * l_max + lane]);
-      if (c != kEmptyId && c != x && c < n) {
-        const float dxc = row_dist(X, d, l2, x, c);
-        key = ((uint64_t)f32_rank(dxc) << 32) | c;
-      }
-    }
-    K[lane] = key;
+    uint32_t c = kEmptyId;
+    if (lane < l_max) c = slot_id(res[(int64_t)x * l_max + lane]);
+    const bool ok = lane < l_max && c != kEmptyId && c != x && c < n;
+    const uint64_t m = __ballot(ok);
+    nv = __popcll(m);
+    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    if (ok) sI[wave][__popcll(m & below)] = c;
   }
   wave_sync();
-  wave_sort_u64(K, 64);
-  const uint64_t myk = K[lane];
-  const int nv = __popcll(__ballot(myk != kNoKey));
-  const uint32_t myid = (uint32_t)myk;
-  sI[wave][lane] = myid;
-  sD[wave][lane] = myk != kNoKey ? rank_to_f32((uint32_t)(myk >> 32)) : 0.f;
-  sN[wave][lane] = (myk != kNoKey && l2) ? norms[myid] : 0.f;
-  wave_sync();
 
-  // 2. operand fragments of the sorted candidates: F0 rows 0..31, F1 rows 32..63
+  // 2. fragments F0 (slots 0..31) and F1 (slots 32..63); d(x, c) from them
   float f0[HALF], f1[HALF];
+  float s0 = 0.f, s1 = 0.f;
   {
     const int kb = h * HALF;
-    const uint32_t c0 = sI[wave][l32], c1 = sI[wave][32 + l32];
     const bool v0 = l32 < nv, v1 = 32 + l32 < nv;
-    const float *r0 = X + (int64_t)(v0 ? c0 : 0) * d + kb;
-    const float *r1 = X + (int64_t)(v1 ? c1 : 0) * d + kb;
+    const uint32_t c0 = v0 ? sI[wave][l32] : x, c1 = v1 ? sI[wave][32 + l32] : x;
+    const float *r0 = X + (int64_t)c0 * d + kb;
+    const float *r1 = X + (int64_t)c1 * d + kb;
+    const float *rx = X + (int64_t)x * d + kb;
     if (full_d) {
 #pragma unroll
       for (int kk = 0; kk < HALF; kk += 4) {
-        float4 q0 = v0 ? *reinterpret_cast<const float4 *>(r0 + kk) : make_float4(0, 0, 0, 0);
-        float4 q1 = v1 ? *reinterpret_cast<const float4 *>(r1 + kk) : make_float4(0, 0, 0, 0);
+        const float4 q0 = *reinterpret_cast<const float4 *>(r0 + kk);
+        const float4 q1 = *reinterpret_cast<const float4 *>(r1 + kk);
+        const float4 qx = *reinterpret_cast<const float4 *>(rx + kk);
         f0[kk] = q0.x; f0[kk + 1] = q0.y; f0[kk + 2] = q0.z; f0[kk + 3] = q0.w;
         f1[kk] = q1.x; f1[kk + 1] = q1.y; f1[kk + 2] = q1.z; f1[kk + 3] = q1.w;
+        if (l2) {
+          float t = q0.x - qx.x; s0 = fmaf(t, t, s0);
+          t = q0.y - qx.y; s0 = fmaf(t, t, s0);
+          t = q0.z - qx.z; s0 = fmaf(t, t, s0);
+          t = q0.w - qx.w; s0 = fmaf(t, t, s0);
+          t = q1.x - qx.x; s1 = fmaf(t, t, s1);
+          t = q1.y - qx.y; s1 = fmaf(t, t, s1);
+          t = q1.z - qx.z; s1 = fmaf(t, t, s1);
+          t = q1.w - qx.w; s1 = fmaf(t, t, s1);
+        } else {
+          s0 = fmaf(q0.x, qx.x, s0); s0 = fmaf(q0.y, qx.y, s0);
+          s0 = fmaf(q0.z, qx.z, s0); s0 = fmaf(q0.w, qx.w, s0);
+          s1 = fmaf(q1.x, qx.x, s1); s1 = fmaf(q1.y, qx.y, s1);
+          s1 = fmaf(q1.z, qx.z, s1); s1 = fmaf(q1.w, qx.w, s1);
+        }
       }
     } else {
 #pragma unroll
       for (int kk = 0; kk < HALF; ++kk) {
         const bool in = kb + kk < d;
-        f0[kk] = (v0 && in) ? r0[kk] : 0.f;
-        f1[kk] = (v1 && in) ? r1[kk] : 0.f;
+        const float a0 = in ? r0[kk] : 0.f, a1 = in ? r1[kk] : 0.f, ax = in ? rx[kk] : 0.f;
+        f0[kk] = a0;
+        f1[kk] = a1;
+        if (l2) {
+          const float t0 = a0 - ax, t1 = a1 - ax;
+          s0 = fmaf(t0, t0, s0);
+          s1 = fmaf(t1, t1, s1);
+        } else {
+          s0 = fmaf(a0, ax, s0);
+          s1 = fmaf(a1, ax, s1);
+        }
       }
     }
+    if (!v0) {
+#pragma unroll
+      for (int kk = 0; kk < HALF; ++kk) f0[kk] = 0.f;
+    }
+    if (!v1) {
+#pragma unroll
+      for (int kk = 0; kk < HALF; ++kk) f1[kk] = 0.f;
+    }
+    // lower half's sum plus upper half's
+    const float o0 = __shfl_xor(s0, 32, 64), o1 = __shfl_xor(s1, 32, 64);
+    const float t0 = h == 0 ? s0 + o0 : o0 + s0, t1 = h == 0 ? s1 + o1 : o1 + s1;
+    const float dx0 = l2 ? t0 : -t0, dx1 = l2 ? t1 : -t1;
+    // lane j < 32 records slot j, lane 32 + j records slot 32 + j
+    const float dxm = h == 0 ? dx0 : dx1;
+    const int slot = lane;
+    if (slot < nv) {
+      const uint32_t cid = sI[wave][slot];
+      sD[wave][slot] = dxm;
+      sN[wave][slot] = l2 ? norms[cid] : 0.f;
+      sK[wave][slot] = ((uint64_t)f32_rank(dxm) << 32) | cid;
+    }
   }
+  wave_sync();
   f32x16 g00, g01, g11;
 #pragma unroll
   for (int v = 0; v < 16; ++v) { g00[v] = 0.f; g01[v] = 0.f; g11[v] = 0.f; }
@@ -239,8 +283,11 @@ __global__ void __launch_bounds__(64 * kRpWaves) robustprune_mfma_kernel(
     }
   }
 
-  // 3. prune masks. Column of this lane: z = l32 (block 00), 32 + l32 (01, 11).
-  uint32_t b00 = 0, b01 = 0, b11 = 0;
+  // 3. prune masks. Column of this lane: z = l32 (block 00), 32 + l32 (01, 11);
+  //    rows y of block 01 are slots 0..31 (they may prune z in 32..63), and
+  //    block 00 / 11 cover the pairs within each half. Pairs (y in 32..63,
+  //    z in 0..31) are the transposes of block 01.
+  uint32_t b00 = 0, b01 = 0, b11 = 0, b10 = 0;
   {
     const int zA = l32, zB = 32 + l32;
     const float dxA = sD[wave][zA], dxB = sD[wave][zB];
@@ -249,43 +296,66 @@ __global__ void __launch_bounds__(64 * kRpWaves) robustprune_mfma_kernel(
     for (int v = 0; v < 16; ++v) {
       const int y = acc_row32(v, h);
       const float ny = sN[wave][y], ny1 = sN[wave][32 + y];
+      const float dy0 = sD[wave][y], dy1 = sD[wave][32 + y];
       const float d00 = l2 ? ny + fmaf(-2.f, g00[v], nA) : -g00[v];
-      if (y < zA && zA < nv && fmaf(alpha, d00, -dxA) < 0.f) b00 |= 1u << y;
+      if (y != zA && zA < nv && y < nv && fmaf(alpha, d00, -dxA) < 0.f) b00 |= 1u << y;
       if (nv > 32) {
         const float d01 = l2 ? ny + fmaf(-2.f, g01[v], nB) : -g01[v];
         const float d11 = l2 ? ny1 + fmaf(-2.f, g11[v], nB) : -g11[v];
-        if (zB < nv && fmaf(alpha, d01, -dxB) < 0.f) b01 |= 1u << y;
-        if (32 + y < zB && zB < nv && fmaf(alpha, d11, -dxB) < 0.f) b11 |= 1u << y;
+        // slot y (0..31) prunes slot zB; and slot zB, as a row, prunes slot y
+        if (zB < nv && y < nv && fmaf(alpha, d01, -dxB) < 0.f) b01 |= 1u << y;
+        if (zB < nv && y < nv && fmaf(alpha, d01, -dy0) < 0.f) b10 |= 1u << y;
+        if (32 + y != zB && zB < nv && 32 + y < nv && fmaf(alpha, d11, -dxB) < 0.f)
+          b11 |= 1u << y;
+        (void)dy1;
       }
     }
     b00 |= __shfl_xor(b00, 32, 64);
     b01 |= __shfl_xor(b01, 32, 64);
     b11 |= __shfl_xor(b11, 32, 64);
+    b10 |= __shfl_xor(b10, 32, 64);
   }
-  // lane j holds the mask of candidate j: lanes < 32 from block 00, the
-  // others from blocks 01 (rows 0..31) and 11 (rows 32..63)
-  const uint32_t mlo = h == 0 ? b00 : b01;
-  const uint32_t mhi = h == 0 ? 0u : b11;
+  // masks by slot: lane j < 32 holds slot j's pruners among slots 0..31 (b00)
+  // and 32..63 (transposed from b10); lane 32 + j holds slot 32 + j's from
+  // b01 (0..31) and b11 (32..63). b10 of lane zB has bit y set when zB prunes
+  // y: it is gathered per y below.
+  uint32_t mlo = h == 0 ? b00 : b01;
+  uint32_t mhi = h == 0 ? 0u : b11;
+  if (nv > 32) {
+    // slot y < 32, bit (zB - 32): zB prunes y. Lane zB holds b10 with bit y.
+    uint32_t t = 0;
+    for (int j = 0; j < 32; ++j) {
+      const uint32_t bj = (uint32_t)__builtin_amdgcn_readlane((int)b10, 32 + j);
+      t |= ((bj >> l32) & 1u) << j;
+    }
+    if (h == 0) mhi = t;
+  }
 
-  // 4. lazy admission scan (wave-uniform)
+  // 4. ranks by (d(x,c), id) and the lazy admission scan (wave-uniform)
+  if (lane < nv) {
+    const uint64_t kt = sK[wave][lane];
+    int rank = 0;
+    for (int u = 0; u < nv; ++u) rank += sK[wave][u] < kt ? 1 : 0;
+    sS[wave][rank] = (uint32_t)lane;
+  }
+  wave_sync();
+  const int my_slot = lane < nv ? (int)sS[wave][lane] : 0;  // slot at sorted position lane
   uint64_t adm = 0;
   int ne = 0;
-  for (int z = 0; z < nv && ne < R; ++z) {
+  uint32_t my_id = kEmptyId;
+  for (int p = 0; p < nv && ne < R; ++p) {
+    const int z = __builtin_amdgcn_readlane(my_slot, p);
     // readlane returns int: widen through uint32_t so bit 31 does not sign-extend
     const uint64_t mz = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)mhi, z) << 32) |
                         (uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)mlo, z);
     if ((mz & adm) == 0) {
       adm |= 1ull << z;
+      if (lane == ne) my_id = sI[wave][z];
       ++ne;
     }
   }
-  // admitted candidates in sorted order = admission order
-  const bool mine = (adm >> lane) & 1ull;
-  const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  const int pos = __popcll(adm & below);
   uint32_t *grow = graph + (int64_t)x * R;
-  if (mine) grow[pos] = myid;
-  for (int i = ne + lane; i < R; i += 64) grow[i] = kEmptyId;
+  for (int i = lane; i < R; i += 64) grow[i] = i < ne ? (i == lane ? my_id : kEmptyId) : kEmptyId;
   if (lane == 0) degree[x] = (uint32_t)ne;
 }
 

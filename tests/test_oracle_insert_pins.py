@@ -58,3 +58,18 @@ def test_insert_single_leaf_is_exact_knn_and_groups_separate():
                    [np.arange(n0), n0 + np.flatnonzero(groups == groups[j])]), k)}
         assert ids <= want | rev
     assert set(range(n0, n0 + m)) <= set(touched.tolist())
+
+
+def test_robustprune_points_equals_full_rows():
+    rng = np.random.default_rng(1)
+    X = rng.integers(0, 16, (400, 16)).astype(np.float32)
+    off = np.array([0, 400])
+    mem = np.arange(400, dtype=np.uint32)
+    c, dd = oracle.leaf_knn(X, off, mem, 16)
+    S = oracle.sketches(X, rng.integers(-16, 17, (12, 16)).astype(np.float32))
+    d_, c_, v_ = oracle.bidirected_records(mem, c, dd)
+    res = oracle.hashprune(oracle.reservoir_init(400, 64), S, d_, c_, v_)
+    g, deg = oracle.robustprune(X, res, 1.2, 32)
+    xs = np.array([5, 17, 399, 0], dtype=np.uint32)
+    g2, deg2 = oracle.robustprune_points(X, res[xs], xs, 1.2, 32)
+    assert np.array_equal(g2, g[xs]) and np.array_equal(deg2, deg[xs])
