@@ -212,6 +212,8 @@ const float *Index::xf() const {
   return x_dtype == PIPNN_DTYPE_F32 ? reinterpret_cast<const float *>(X) : xf32.as<float>();
 }
 
+const float *Index::xop32() const { return xpad.p ? xpad.as<float>() : xf(); }
+
 static hipEvent_t take_event(Index &I) {
   if (!I.ev_free.empty()) {
     hipEvent_t e = I.ev_free.back();
@@ -352,6 +354,15 @@ pipnn_status pipnn_create(const pipnn_params *p, const void *d_X, int64_t n, int
   }
   if ((e = launch_norms_sketches(*I, s)) != hipSuccess)
     return cleanup(fail(PIPNN_EDEVICE, "sketch launch failed: %s", hipGetErrorString(e)));
+  // the float32 GEMM operand: X itself when its rows are whole 16-byte
+  // vectors of an instantiated width, else a zero-padded copy
+  I->ldf = knn_operand_dim(d, PIPNN_PREC_FP32);
+  if (I->ldf != 0 && (I->ldf != d || (reinterpret_cast<uintptr_t>(I->xf()) & 15u) != 0)) {
+    if ((e = I->xpad.ensure((size_t)n * I->ldf * 4)) != hipSuccess)
+      return cleanup(fail(PIPNN_ENOMEM, "device allocation failed: %s", hipGetErrorString(e)));
+    if ((e = launch_pad_range(*I, 0, n, s)) != hipSuccess)
+      return cleanup(fail(PIPNN_EDEVICE, "pad launch failed: %s", hipGetErrorString(e)));
+  }
   if (p->gemm_prec != PIPNN_PREC_FP32) {
     I->ldo = lowp_padded_dim(d);
     if (I->ldo == 0)
@@ -376,7 +387,7 @@ void pipnn_destroy(pipnn_index *idx) {
   Index *I = reinterpret_cast<Index *>(idx);
   (void)hipDeviceSynchronize();
   for (DevBuf *b : {&I->rp_order, &I->o_first, &I->o_flag, &I->o_pos, &I->o_pos2, &I->o_tmp,
-                    &I->xf32, &I->xlow, &I->xscale, &I->lnorms, &I->s_counter, &I->q_conv, &I->q_seen,
+                    &I->xf32, &I->xpad, &I->xlow, &I->xscale, &I->lnorms, &I->s_counter, &I->q_conv, &I->q_seen,
                     &I->lt_off, &I->lt_mem, &I->lt_rep, &I->i_rows, &I->i_cols, &I->i_assign,
                     &I->i_flag, &I->i_pos, &I->i_list, &I->i_tmp, &I->i_segs, &I->sketches, &I->norms, &I->flag, &I->s_jobs,
                     &I->s_items, &I->s_picks_c, &I->s_picks_d, &I->s_cnt, &I->s_off, &I->s_bins,
@@ -1126,6 +1137,7 @@ pipnn_status pipnn_reserve(pipnn_index *idx, int64_t n_cap, pipnn_stream_t strea
   HIPCHK(grow_keep(I.norms, c * 4, n * 4, s));
   HIPCHK(grow_keep(I.sketches, c * I.m * 4, n * I.m * 4, s));
   if (I.x_dtype != PIPNN_DTYPE_F32) HIPCHK(grow_keep(I.xf32, c * d * 4, n * d * 4, s));
+  if (I.xpad.p) HIPCHK(grow_keep(I.xpad, c * I.ldf * 4, n * I.ldf * 4, s));
   if (I.p.gemm_prec != PIPNN_PREC_FP32) {
     const size_t eb = I.p.gemm_prec == PIPNN_PREC_FP8 ? 1 : 2;
     HIPCHK(grow_keep(I.xlow, c * I.ldo * eb, n * I.ldo * eb, s));
@@ -1166,6 +1178,7 @@ pipnn_status pipnn_insert(pipnn_index *idx, int64_t n_new, const int32_t *d_grou
                          I.xf32.as<float>() + n0 * d, n_new * d, s));
   }
   HIPCHK(launch_norms_sketches_range(I, n0, n_new, s));
+  HIPCHK(launch_pad_range(I, n0, n_new, s));
   if (P.gemm_prec != PIPNN_PREC_FP32) HIPCHK(launch_quantize_range(I, n0, n_new, s));
   HIPCHK(launch_fill_u64(d_reservoirs + n0 * P.l_max, empty_slot(), n_new * P.l_max, s));
 
@@ -1590,6 +1603,7 @@ pipnn_status pipnn_prepare(pipnn_index *idx, pipnn_stream_t stream) {
   if (I.x_dtype != PIPNN_DTYPE_F32)
     HIPCHK(launch_to_f32(I.X, I.x_dtype, I.xf32.as<float>(), I.n * (int64_t)I.d, s));
   HIPCHK(launch_norms_sketches(I, s));
+  HIPCHK(launch_pad_range(I, 0, I.n, s));
   if (I.p.gemm_prec != PIPNN_PREC_FP32) HIPCHK(launch_quantize(I, s));
   return PIPNN_OK;
   GUARD_END

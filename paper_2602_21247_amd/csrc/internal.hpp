@@ -36,6 +36,8 @@ struct Index {
   DevBuf xscale;    // per-point fp8 decode scale (value = code * scale)
   DevBuf lnorms;    // n float32, squared norms of the decoded low-precision operand
   int32_t ldo = 0;  // row stride (elements) of xlow: d padded by lowp_padded_dim
+  DevBuf xpad;      // float32 GEMM operand zero padded to ldf, when X itself cannot serve
+  int32_t ldf = 0;  // row stride (floats) of the float32 GEMM operand; 0: d > 256
   DevBuf sketches;  // n x m float32
   DevBuf norms;     // n float32, squared norms of the float32 vectors
   DevBuf flag;      // int32 device error flag
@@ -92,6 +94,7 @@ struct Index {
   int leaf_launches = 0;
 
   const float *xf() const;
+  const float *xop32() const;  // the float32 GEMM operand: xpad if allocated, else xf()
 };
 
 // Phase timing: begin/end record events on the stream when profiling is on.
@@ -164,6 +167,8 @@ hipError_t launch_quantize(const Index &I, hipStream_t s);
 // the same for points [p0, p0 + cnt) only
 hipError_t launch_norms_sketches_range(const Index &I, int64_t p0, int64_t cnt, hipStream_t s);
 hipError_t launch_quantize_range(const Index &I, int64_t p0, int64_t cnt, hipStream_t s);
+// Rows [p0, p0 + cnt) of the zero-padded float32 operand I.xpad.
+hipError_t launch_pad_range(const Index &I, int64_t p0, int64_t cnt, hipStream_t s);
 // leaf table: offsets rebased to 0, member copy, one representative per leaf
 hipError_t launch_rebase_i64(const int64_t *in, int64_t n, int64_t *out, hipStream_t s);
 hipError_t launch_copy_u32(const uint32_t *in, int64_t n, uint32_t *out, hipStream_t s);

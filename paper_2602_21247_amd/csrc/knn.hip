@@ -29,7 +29,7 @@ hipError_t launch_knn(const KnnLaunch &L, hipStream_t s) {
   const bool lowp = L.prec != PIPNN_PREC_FP32;
   KnnArgs a;
   a.X = I.xf();
-  a.Xop = lowp ? I.xlow.p : nullptr;
+  a.Xop = lowp ? I.xlow.p : reinterpret_cast<const void *>(I.xop32());
   a.norms = lowp ? I.lnorms.as<float>() : I.norms.as<float>();
   a.scale = L.prec == PIPNN_PREC_FP8 ? I.xscale.as<float>() : nullptr;
   a.row_base = L.row_base;
@@ -42,7 +42,7 @@ hipError_t launch_knn(const KnnLaunch &L, hipStream_t s) {
   a.matrix_ld = L.matrix_ld;
   a.n_items = L.n_items;
   a.d = I.d;
-  a.ldo = lowp ? I.ldo : I.d;
+  a.ldo = lowp ? I.ldo : I.ldf;
   a.metric = I.p.metric;
   a.k_out = L.k_out;
   a.out_ids = L.out_ids;
@@ -66,14 +66,16 @@ hipError_t launch_knn(const KnnLaunch &L, hipStream_t s) {
     if (L.prec == PIPNN_PREC_FP8) return launch_knn_fp8(a, L.ksel, L.n_items, nw, n_cu, s);
     return hipErrorInvalidValue;
   }
-  const int d = I.d;
-  if (d <= 32) return launch_dp<32>(a, L.ksel, L.n_items, nw, n_cu, s);
-  if (d <= 64) return launch_dp<64>(a, L.ksel, L.n_items, nw, n_cu, s);
-  if (d <= 96) return launch_dp<96>(a, L.ksel, L.n_items, nw, n_cu, s);
-  if (d <= 128) return launch_dp<128>(a, L.ksel, L.n_items, nw, n_cu, s);
-  if (d <= 192) return launch_dp<192>(a, L.ksel, L.n_items, nw, n_cu, s);
-  if (d <= 256) return launch_dp<256>(a, L.ksel, L.n_items, nw, n_cu, s);
-  return hipErrorInvalidValue;
+  if (I.ldf != knn_operand_dim(I.d, PIPNN_PREC_FP32)) return hipErrorInvalidValue;
+  switch (I.ldf) {
+    case 32: return launch_dp<32>(a, L.ksel, L.n_items, nw, n_cu, s);
+    case 64: return launch_dp<64>(a, L.ksel, L.n_items, nw, n_cu, s);
+    case 96: return launch_dp<96>(a, L.ksel, L.n_items, nw, n_cu, s);
+    case 128: return launch_dp<128>(a, L.ksel, L.n_items, nw, n_cu, s);
+    case 192: return launch_dp<192>(a, L.ksel, L.n_items, nw, n_cu, s);
+    case 256: return launch_dp<256>(a, L.ksel, L.n_items, nw, n_cu, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 }  // namespace pipnn

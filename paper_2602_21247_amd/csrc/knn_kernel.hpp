@@ -12,21 +12,25 @@
 // Work decomposition: a work item is (job, block of 32*NW rows). A
 // workgroup of NW waves owns one item; wave w owns 32 rows and keeps their
 // A operand (the row vectors) in registers for the whole item. Column
-// tiles of 64 points are staged in LDS (row stride d+4 floats, so the
-// 16-byte fragment reads are bank-conflict free) and shared by the NW
-// waves. The host lists the work items in launch order (block b
+// tiles of 32 points are staged in LDS by direct global-to-LDS transfers
+// into two buffers: the transfer of tile t+1 is in flight while the MFMAs
+// and the selection of tile t run, and one barrier per tile hands the
+// buffers over. The columns of a tile sit back to back with their 16-byte
+// chunks permuted per column (chunk_swz), so the fragment reads are free
+// of bank conflicts. The host lists the work items in launch order (block b
 // runs on XCD b % 8): whole small jobs go to one XCD so that their column
 // vectors stay in that XCD's L2, and jobs are dealt to XCDs largest first
 // by work so that the eight XCDs finish together. Two workgroups fit on a
 // CU, so one's selection and epilogue overlap the other's MFMA work.
 //
-// Selection: each row keeps its KSEL best (distance, column) pairs in LDS
-// and a threshold tau (the worst kept pair once KSEL are kept). After each
-// 32x32 MFMA block, every lane tests its 16 accumulator entries against the
-// tau of their rows and appends the survivors to the row's LDS buffer; one
-// owner lane per row then drains the buffer into the kept set. The filter
-// uses <= so that equal distances with a smaller column are not lost; the
-// drain applies the exact (distance, column) order.
+// Selection: each row keeps its KSEL best (distance, column) pairs in
+// registers (split over its two lanes) and a threshold tau in LDS (the
+// worst kept pair once KSEL are kept). After each 32x32 MFMA block, every
+// lane tests its 16 accumulator entries against the tau of their rows and
+// appends the survivors to the row's LDS buffer; the row's lane pair then
+// drains the buffer into the kept set. The filter uses <= so that equal
+// distances with a smaller column are not lost; the drain applies the exact
+// (distance, column) order.
 //
 // Epilogue: the kept pairs are sorted by (GEMM distance, column); when
 // asked, each winner's FP32 distance is recomputed by direct difference,
@@ -36,7 +40,7 @@
 // winners are re-ranked by (direct distance, column) and the first k kept.
 //
 // Operand precision: the FP32 form runs v_mfma_f32_32x32x2_f32 on the
-// float32 vectors. The reduced-precision forms (bf16, fp16, OCP e4m3 with a
+// float32 vectors (zero padded to DP when d is not DP). The reduced-precision forms (bf16, fp16, OCP e4m3 with a
 // per-point scale) read a copy of the vectors in that format, made once per
 // index and zero padded to DP, and run the 32x32x16 MFMAs with FP32
 // accumulation; their squared norms are those of the decoded operand, so the
@@ -74,8 +78,8 @@ struct KnnArgs {
   int32_t out_ids;
   int32_t recompute;
   int32_t rescore_k;
-  int32_t ldo;           // operand row stride (elements)
-  const void *Xop;       // reduced-precision operand (n x ldo, zero padded), else NULL
+  int32_t ldo;           // operand row stride (elements): the padded width DP
+  const void *Xop;       // GEMM operand (n x ldo, zero padded, 16-byte aligned rows)
   const float *scale;    // fp8 operand: per-point decode scale, else NULL
   // persistent schedule: NULL, or 8 per-XCD counters (zero at launch); the
   // workgroups of XCD x then take items[i * 8 + x] for i = 0, 1, ... in
@@ -142,9 +146,52 @@ __device__ __forceinline__ uint64_t kmin(uint64_t a, uint64_t b) { return a < b 
 __device__ __forceinline__ uint64_t kmax(uint64_t a, uint64_t b) { return a < b ? b : a; }
 
 // Resident waves per SIMD the kernel is built for (the second launch bound
-// is waves per execution unit): operands wider than 256 dimensions take one
-// (their A fragments and tiles are large), narrower ones two.
-template <int DP> struct KnnOcc { static constexpr int v = DP > 256 ? 1 : 2; };
+// is waves per execution unit): operand rows wider than 768 bytes take one
+// (their A fragments and double-buffered tiles are large), narrower ones two.
+template <int PREC, int DP> struct KnnOcc {
+  static constexpr int v = DP * OpBytes<PREC>::v > 768 ? 1 : 2;
+};
+
+// 16-byte chunk q of staged column c sits at LDS chunk position
+// q ^ swz(c) of the column's row: consecutive columns then spread the same
+// chunk over different banks, so the B-fragment reads (lane l32 reads
+// column l32) are free of bank conflicts although the columns are staged
+// back to back, as the 1 KiB global-to-LDS transfers require. The mask stays
+// below the largest power of two dividing CPC, so the map is a permutation
+// of each column's chunks.
+template <int CPC> __device__ __forceinline__ int chunk_swz(int c) {
+  if constexpr (CPC % 16 == 0) return c & 15;
+  else if constexpr (CPC % 8 == 0) return (c >> 1) & 7;
+  else if constexpr (CPC % 4 == 0) return (c >> 2) & 3;
+  else if constexpr (CPC % 2 == 0) return (c >> 3) & 1;
+  else return 0;
+}
+
+typedef __attribute__((address_space(3))) void lds_void_t;
+
+// s_waitcnt with vmcnt(0) and the other counters unconstrained (gfx9
+// encoding: vmcnt bits 3:0 and 15:14, expcnt 6:4, lgkmcnt 11:8). As a
+// builtin the compiler's own wait tracking sees it.
+constexpr int kWaitVmcnt0 = 0x0F70;
+
+// 16 bytes per lane from global memory straight into LDS: lane i of the
+// wave writes LDS bytes [lds + 16 i, lds + 16 i + 16). Written as asm so that
+// the compiler does not order every later LDS read behind the transfer (it
+// cannot tell the two tile buffers apart); the caller waits for the transfer
+// with s_waitcnt vmcnt(0) before the barrier that publishes the tile. The
+// instruction has no register result, and M0 is set right before it.
+#pragma clang diagnostic push
+#pragma clang diagnostic ignored "-Winline-asm"
+__device__ __forceinline__ void lds_dma16(const void *src, const void *lds) {
+  const uint32_t base = __builtin_amdgcn_readfirstlane(
+      (uint32_t)(uintptr_t)reinterpret_cast<const __attribute__((address_space(3))) char *>(
+          (const __attribute__((address_space(3))) char *)lds));
+  asm volatile("s_mov_b32 m0, %1\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, off"
+               :
+               : "v"(src), "s"(base)
+               : "memory", "m0");
+}
+#pragma clang diagnostic pop
 
 template <int PREC, int DP, int KSEL, int NW, bool L2>
 __device__ __forceinline__ void knn_item(const KnnArgs &a, const int item) {
@@ -152,36 +199,30 @@ __device__ __forceinline__ void knn_item(const KnnArgs &a, const int item) {
   constexpr bool F8 = PREC == PIPNN_PREC_FP8;
   constexpr int EB = OpBytes<PREC>::v;          // bytes per operand element
   constexpr int BM = 32 * NW;     // rows per workgroup
-  constexpr int BN = 64;          // columns per tile
-  constexpr int LDB = DP + 4;     // FP32: LDS stride of a staged column vector (floats)
-  constexpr int LDW = DP * EB / 4 + 4;  // LDS stride of a staged column (32-bit words)
+  constexpr int BN = 32;          // columns per staged tile
+  constexpr int CB = DP * EB;     // bytes per operand row
+  constexpr int CPC = CB / 16;    // 16-byte chunks per operand row
+  constexpr int TB = BN * CB;     // bytes per staged tile
+  constexpr int NI = TB / 1024;   // 1 KiB wave transfers per tile
   constexpr int HALF = DP / 2;    // k-range owned by each half of the wave
-  constexpr int NA = HALF * EB / 16;    // 16-byte operand vectors per lane (reduced precision)
-  constexpr int CPC = DP * EB / 16;     // 16-byte chunks per column vector
+  constexpr int NA = CPC / 2;     // 16-byte operand vectors per lane
   constexpr int CAP = 32;         // per-row buffer: a 32-column block appends at most 32
   constexpr int BUFD = CAP + 1;
   constexpr int BUFC = CAP + 2;
-  constexpr int KH = KSEL / 2;     // kept-list entries held by each lane of a row's pair
-  constexpr int KST = KSEL + 1;   // LDS stride of a row's kept list (64-bit keys)
+  constexpr int KH = KSEL / 2;    // kept-list entries held by each lane of a row's pair
   constexpr int NTH = NW * 64;
-  constexpr int CH_PER_TILE = BN * CPC;
-  constexpr int NPRE = (CH_PER_TILE + NTH - 1) / NTH;  // chunks per thread and tile
-  constexpr int PRM = (NW == 2 || DP > 256) ? 4 : 8;
-  constexpr int PR = NPRE < PRM ? NPRE : PRM;          // chunks in flight per round
-  constexpr bool ROW_REG = !LP || HALF <= 64;          // recompute row half in registers
-  static_assert(LP || LDW == LDB, "FP32 column stride");
+  constexpr bool ROW_REG = !LP || HALF <= 64;   // recompute row half in registers
+  static_assert(TB % 1024 == 0 && KSEL <= CAP, "tile shape");
 
-  __shared__ __attribute__((aligned(16))) uint32_t sBw[BN * LDW];
+  __shared__ __attribute__((aligned(16))) uint8_t sT[2 * TB];
+  __shared__ float sColN[2 * BN];
+  __shared__ float sColS[F8 ? 2 * BN : 1];
   __shared__ float sBufD[BM * BUFD];
   __shared__ uint16_t sBufC[BM * BUFC];
-  __shared__ uint64_t sKeep[BM * KST];
   __shared__ float sTau[BM];
   __shared__ int sBufN[BM];
-  __shared__ float sColN[BN];
   __shared__ float sNr[BM];
-  __shared__ float sColS[F8 ? BN : 1];
   __shared__ float sRs[F8 ? BM : 1];
-  float *sB = reinterpret_cast<float *>(sBw);
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int h = lane >> 5, l32 = lane & 31;
@@ -198,10 +239,8 @@ __device__ __forceinline__ void knn_item(const KnnArgs &a, const int item) {
   const bool full_d = (d == DP);
   const int n_rows = J.n_rows, n_cols = J.n_cols;
   const uint8_t *xop = reinterpret_cast<const uint8_t *>(a.Xop);
-  const int64_t op_ld = (int64_t)a.ldo * EB;  // bytes per operand row
 
   // per-row squared norm and selection threshold (-inf past the last row)
-  for (int i = tid; i < BM * KST; i += NTH) sKeep[i] = kEmptyKey;
   for (int r = tid; r < BM; r += NTH) {
     const bool ok = rbase + r < n_rows;
     sTau[r] = ok ? INFINITY : -INFINITY;
@@ -213,105 +252,80 @@ __device__ __forceinline__ void knn_item(const KnnArgs &a, const int item) {
 #pragma unroll
   for (int v = 0; v < 16; ++v) rowmask |= (wrow + acc_row(v, h) < n_rows ? 1u : 0u) << v;
 
-  // A operand: lane holds row l32 of this wave, dims [h*HALF, h*HALF+HALF).
-  float av[LP ? 1 : HALF];
-  uint4 aw[LP ? NA : 1];
+  // A operand: lane holds row l32 of this wave, dims [h*HALF, h*HALF+HALF)
+  // of the zero-padded operand, as NA 16-byte vectors
+  uint4 aw[NA];
   {
     const int r = wrow + l32;
-    if constexpr (LP) {
-      if (r < n_rows) {
-        const uint4 *src = reinterpret_cast<const uint4 *>(xop + (int64_t)rows[r] * op_ld + h * HALF * EB);
+    if (r < n_rows) {
+      const uint4 *src = reinterpret_cast<const uint4 *>(xop + (int64_t)rows[r] * CB + h * (CB / 2));
 #pragma unroll
-        for (int s = 0; s < NA; ++s) aw[s] = src[s];
-      } else {
-#pragma unroll
-        for (int s = 0; s < NA; ++s) aw[s] = make_uint4(0u, 0u, 0u, 0u);
-      }
-    } else if (r < n_rows) {
-      const float *src = a.X + (int64_t)rows[r] * d + h * HALF;
-      if (full_d) {
-#pragma unroll
-        for (int kk = 0; kk < HALF; kk += 4) {
-          float4 q = *reinterpret_cast<const float4 *>(src + kk);
-          av[kk] = q.x; av[kk + 1] = q.y; av[kk + 2] = q.z; av[kk + 3] = q.w;
-        }
-      } else {
-#pragma unroll
-        for (int kk = 0; kk < HALF; ++kk) av[kk] = (h * HALF + kk < d) ? src[kk] : 0.f;
-      }
+      for (int s = 0; s < NA; ++s) aw[s] = src[s];
     } else {
 #pragma unroll
-      for (int kk = 0; kk < HALF; ++kk) av[kk] = 0.f;
+      for (int s = 0; s < NA; ++s) aw[s] = make_uint4(0u, 0u, 0u, 0u);
     }
   }
+  // FP32 operand: element kk of this lane's half
+  auto afl = [&](int kk) -> float {
+    const uint4 q = aw[kk >> 2];
+    const uint32_t w = (kk & 3) == 0 ? q.x : (kk & 3) == 1 ? q.y : (kk & 3) == 2 ? q.z : q.w;
+    return __uint_as_float(w);
+  };
 
   // lanes l32 and l32 + 32 own row wrow + l32 together
   const int orow = wave * 32 + l32;  // LDS row index
 
-  // column tile staging: thread t moves 16-byte chunks t, t+NTH, ... of the
-  // tile, PR of them in flight at a time
-  uint4 pre[PR];
+  // Column tiles are staged by global-to-LDS transfers (no register
+  // round trip), one tile ahead of the MFMA work: transfer g of a tile moves
+  // its 16-byte chunks [64g, 64g+64); lane i of the wave lands at LDS
+  // position 64g + i and fetches the chunk that the swizzle puts there.
+  // Lanes < BN hold the column ids of the tile being fetched (cid); the
+  // column norms (and fp8 scales) travel through a register.
+  auto col_id = [&](int c0) -> uint32_t {
+    const int c = c0 + l32;
+    return cols[c < n_cols ? c : 0];
+  };
   float pre_n = 0.f, pre_s = 0.f;
-  auto load_tile = [&](int c0, int r0) {
-    if (r0 == 0 && tid < BN) {
-      pre_n = (l2 && c0 + tid < n_cols) ? a.norms[cols[c0 + tid]] : 0.f;
-      if constexpr (F8) pre_s = c0 + tid < n_cols ? a.scale[cols[c0 + tid]] : 0.f;
-    }
+  auto fetch = [&](int buf, uint32_t cid, int c0) {
+    uint8_t *dst = sT + buf * TB;
 #pragma unroll
-    for (int i = 0; i < PR; ++i) {
-      const int q = tid + (r0 + i) * NTH;
-      uint4 v = make_uint4(0u, 0u, 0u, 0u);
-      if (q < CH_PER_TILE) {
-        const int c = q / CPC, kq = q % CPC;
-        const int cc = c0 + c;
-        if (cc < n_cols) {
-          if constexpr (LP) {
-            v = *reinterpret_cast<const uint4 *>(xop + (int64_t)cols[cc] * op_ld + kq * 16);
-          } else {
-            const int k4 = kq * 4;
-            const float *src = a.X + (int64_t)cols[cc] * d + k4;
-            if (full_d) {
-              v = *reinterpret_cast<const uint4 *>(src);
-            } else {
-              v.x = k4 < d ? __float_as_uint(src[0]) : 0u;
-              v.y = k4 + 1 < d ? __float_as_uint(src[1]) : 0u;
-              v.z = k4 + 2 < d ? __float_as_uint(src[2]) : 0u;
-              v.w = k4 + 3 < d ? __float_as_uint(src[3]) : 0u;
-            }
-          }
-        }
+    for (int j = 0; j < (NI + NW - 1) / NW; ++j) {
+      const int g = wave + j * NW;
+      if (NI % NW == 0 || g < NI) {
+        const int t = g * 64 + lane;
+        const int c = t / CPC, p = t - c * CPC;
+        const uint32_t id = (uint32_t)__shfl((int)cid, c, 64);
+        const int q = p ^ chunk_swz<CPC>(c);
+        lds_dma16(xop + (int64_t)id * CB + q * 16, dst + g * 1024);
       }
-      pre[i] = v;
+    }
+    if (tid < BN) {
+      pre_n = (l2 && c0 + tid < n_cols) ? a.norms[cid] : 0.f;
+      if constexpr (F8) pre_s = c0 + tid < n_cols ? a.scale[cid] : 0.f;
     }
   };
-  auto store_tile = [&](int r0) {
-    if (r0 == 0 && tid < BN) {
-      sColN[tid] = pre_n;
-      if constexpr (F8) sColS[tid] = pre_s;
-    }
-#pragma unroll
-    for (int i = 0; i < PR; ++i) {
-      const int q = tid + (r0 + i) * NTH;
-      if (q < CH_PER_TILE) {
-        const int c = q / CPC, kq = q % CPC;
-        *reinterpret_cast<uint4 *>(&sBw[c * LDW + kq * 4]) = pre[i];
-      }
+  auto put_norms = [&](int buf) {
+    if (tid < BN) {
+      sColN[buf * BN + tid] = pre_n;
+      if constexpr (F8) sColS[buf * BN + tid] = pre_s;
     }
   };
 
-  // Drain: the row's kept list is sorted in descending key order and split
-  // between its two lanes (lane h holds positions [h*KH, h*KH+KH)). A key x
-  // enters by b[i] = max(a[i+1], min(a[i], x)): the largest entry drops out
-  // when x is smaller, and nothing changes otherwise. Every entry is
-  // independent of the others, so the update has no select chain and no
-  // rescan; the lane holding the upper half needs only the first entry of
-  // the lower half.
+  // the row's kept list, sorted in descending key order and split between
+  // its two lanes (lane h holds positions [h*KH, h*KH+KH))
+  uint64_t ks[KH];
+#pragma unroll
+  for (int i = 0; i < KH; ++i) ks[i] = kEmptyKey;
+
+  // Drain: a key x enters by b[i] = max(a[i+1], min(a[i], x)): the largest
+  // entry drops out when x is smaller, and nothing changes otherwise. Every
+  // entry is independent of the others, so the update has no select chain
+  // and no rescan; the lane holding the upper half needs only the first
+  // entry of the lower half.
   auto drain = [&]() {
     const int nb = (wrow + l32 < n_rows) ? sBufN[orow] : 0;
     if (nb > 0) {
-      uint64_t ks[KH];
-#pragma unroll
-      for (int i = 0; i < KH; ++i) ks[i] = sKeep[orow * KST + h * KH + i];
       float nd = sBufD[orow * BUFD];
       uint32_t ncv = sBufC[orow * BUFC];
       for (int e = 0; e < nb; ++e) {
@@ -329,8 +343,6 @@ __device__ __forceinline__ void knn_item(const KnnArgs &a, const int item) {
           ks[i] = kmax(nxt, kmin(ks[i], x));
         }
       }
-#pragma unroll
-      for (int i = 0; i < KH; ++i) sKeep[orow * KST + h * KH + i] = ks[i];
       if (h == 0) {
         sBufN[orow] = 0;
         sTau[orow] = ks[0] == kEmptyKey ? INFINITY : key_dist(ks[0]);
@@ -338,98 +350,114 @@ __device__ __forceinline__ void knn_item(const KnnArgs &a, const int item) {
     }
   };
 
-  for (int c0 = 0; c0 < n_cols; c0 += BN) {
-    // stage the column tile (the other workgroup on the CU covers the latency)
-#pragma unroll
-    for (int r0 = 0; r0 < NPRE; r0 += PR) {
-      load_tile(c0, r0);
-      store_tile(r0);
-    }
-    __syncthreads();
+  // waves whose 32 rows all lie past the job's last row only stage tiles
+  const bool active = wrow < n_rows;
+  uint32_t cid = 0;
+  if (n_cols > 0) {
+    cid = col_id(0);
+    fetch(0, cid, 0);
+    cid = col_id(BN);
+    put_norms(0);
+  }
+  __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
+  __syncthreads();
 
-#pragma unroll
-    for (int blk = 0; blk < 2; ++blk) {
-      // MFMA: this wave's 32 rows against columns c0 + 32*blk + [0, 32)
+  for (int t = 0, c0 = 0; c0 < n_cols; ++t, c0 += BN) {
+    const int buf = t & 1;
+    const bool more = c0 + BN < n_cols;
+    if (more) {
+      fetch(buf ^ 1, cid, c0 + BN);
+      cid = col_id(c0 + 2 * BN);
+    }
+    if (active) {
+      // Per-tile bases of the LDS and output addressing. They are passed
+      // through an empty asm so that the compiler forms each access as one
+      // base plus a constant offset inside the tile, instead of holding
+      // dozens of precomputed addresses live across the whole loop.
+      int rb = wave * 32 + 4 * h;             // LDS row of accumulator entry 0
+      int hn = h * NA;                        // this lane's first chunk
+      int sw = chunk_swz<CPC>(l32);           // the column's chunk permutation
+      int tb = buf * TB + l32 * CB;           // this lane's column in the tile
+      asm volatile("" : "+v"(rb), "+v"(hn), "+v"(sw), "+v"(tb));
+      // MFMA: this wave's 32 rows against columns c0 + [0, 32)
       f32x16 acc;
 #pragma unroll
       for (int v = 0; v < 16; ++v) acc[v] = 0.f;
-      if constexpr (LP) {
-        const uint32_t *bw = &sBw[(32 * blk + l32) * LDW + h * (HALF * EB / 4)];
-        // groups of 8 operand vectors: a scheduling barrier between groups
-        // keeps the B fragments of wide operands from all being loaded ahead
-        constexpr int G = NA < 8 ? NA : 8;
 #pragma unroll
-        for (int g0 = 0; g0 < NA; g0 += G) {
-#pragma unroll
-          for (int s2 = g0; s2 < g0 + G && s2 < NA; ++s2)
-            acc = mfma16<PREC>(aw[s2], *reinterpret_cast<const uint4 *>(bw + 4 * s2), acc);
-          if constexpr (NA > 16) __builtin_amdgcn_sched_barrier(0);
-        }
-      } else {
-        const float *bp = &sB[(32 * blk + l32) * LDB + h * HALF];
-#pragma unroll
-        for (int kk = 0; kk < HALF; kk += 4) {
-          const float4 b = *reinterpret_cast<const float4 *>(bp + kk);
-          acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av[kk], b.x, acc, 0, 0, 0);
-          acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av[kk + 1], b.y, acc, 0, 0, 0);
-          acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av[kk + 2], b.z, acc, 0, 0, 0);
-          acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av[kk + 3], b.w, acc, 0, 0, 0);
+      for (int s = 0; s < NA; ++s) {
+        const uint4 b = *reinterpret_cast<const uint4 *>(sT + tb + (((hn + s) ^ sw) << 4));
+        if constexpr (LP) {
+          acc = mfma16<PREC>(aw[s], b, acc);
+        } else {
+          acc = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(aw[s].x), __uint_as_float(b.x), acc, 0, 0, 0);
+          acc = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(aw[s].y), __uint_as_float(b.y), acc, 0, 0, 0);
+          acc = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(aw[s].z), __uint_as_float(b.z), acc, 0, 0, 0);
+          acc = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(aw[s].w), __uint_as_float(b.w), acc, 0, 0, 0);
         }
       }
-      const int cc = c0 + 32 * blk + l32;
+      constexpr auto accr = [](int v) { return (v & 3) + 8 * (v >> 2); };  // acc_row(v, 0)
+      const int cc = c0 + l32;
       const bool vc = cc < n_cols;
-      const float nc = sColN[32 * blk + l32];
+      const float nc = sColN[buf * BN + l32];
       float nr[16], tau[16];
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
-        nr[v] = sNr[wave * 32 + acc_row(v, h)];
-        tau[v] = sTau[wave * 32 + acc_row(v, h)];
+        nr[v] = sNr[rb + accr(v)];
+        tau[v] = sTau[rb + accr(v)];
       }
       if constexpr (F8) {
         // decode scales: x.y = (codes_x . codes_y) * scale_x * scale_y
-        const float cs = sColS[32 * blk + l32];
+        const float cs = sColS[buf * BN + l32];
 #pragma unroll
-        for (int v = 0; v < 16; ++v) acc[v] = acc[v] * sRs[wave * 32 + acc_row(v, h)] * cs;
+        for (int v = 0; v < 16; ++v) acc[v] = acc[v] * sRs[rb + accr(v)] * cs;
       }
       float dv[16];
 #pragma unroll
       for (int v = 0; v < 16; ++v) dv[v] = l2 ? nr[v] + fmaf(-2.f, acc[v], nc) : -acc[v];
       if (a.out_matrix && vc) {
         // test-only: the GEMM distance of every pair
+        int64_t mrow = J.out_off + wrow + 4 * h;
+        asm volatile("" : "+v"(mrow));
+        float *mo = a.out_matrix + mrow * a.matrix_ld + cc;
 #pragma unroll
         for (int v = 0; v < 16; ++v)
-          if ((rowmask >> v) & 1u)
-            a.out_matrix[(J.out_off + wrow + acc_row(v, h)) * a.matrix_ld + cc] = dv[v];
+          if ((rowmask >> v) & 1u) mo[accr(v) * a.matrix_ld] = dv[v];
       }
       // branch-free pass test; a block without any survivor costs one ballot
       uint32_t pass = 0;
+      const int self = excl ? cc - J.self_off - (wrow + 4 * h) : -1;  // accr(v) of the own column
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
-        const int rr = wrow + acc_row(v, h);
-        const bool ok = vc && dv[v] <= tau[v] && !(excl && rr + J.self_off == cc);
+        const bool ok = vc && dv[v] <= tau[v] && self != accr(v);
         pass |= (ok ? 1u : 0u) << v;
       }
-      if (__ballot(pass != 0) == 0ull) continue;
-      // append: a row's survivors go to its buffer (empty after every
-      // drain) at their rank among the row's survivors, from one ballot
+      if (__ballot(pass != 0) != 0ull) {
+        // append: a row's survivors go to its buffer (empty after every
+        // drain) at their rank among the row's survivors, from one ballot
+        float *bd = sBufD + rb * BUFD;
+        uint16_t *bc = sBufC + rb * BUFC;
+        int *bn = sBufN + rb;
 #pragma unroll
-      for (int v = 0; v < 16; ++v) {
-        const uint64_t m = __ballot((pass >> v) & 1u);
-        if (m == 0ull) continue;
-        if ((pass >> v) & 1u) {
-          const uint32_t hm = h ? (uint32_t)(m >> 32) : (uint32_t)m;
-          const int pos = __popc(hm & ((1u << l32) - 1u));
-          const int rl = wave * 32 + acc_row(v, h);
-          sBufD[rl * BUFD + pos] = dv[v];
-          sBufC[rl * BUFC + pos] = (uint16_t)cc;
-          if (pos == __popc(hm) - 1) sBufN[rl] = pos + 1;
+        for (int v = 0; v < 16; ++v) {
+          const uint64_t m = __ballot((pass >> v) & 1u);
+          if (m == 0ull) continue;
+          if ((pass >> v) & 1u) {
+            const uint32_t hm = h ? (uint32_t)(m >> 32) : (uint32_t)m;
+            const int pos = __popc(hm & ((1u << l32) - 1u));
+            bd[accr(v) * BUFD + pos] = dv[v];
+            bc[accr(v) * BUFC + pos] = (uint16_t)cc;
+            if (pos == __popc(hm) - 1) bn[accr(v)] = pos + 1;
+          }
         }
+        wave_sync();
+        drain();
+        wave_sync();
       }
-      wave_sync();
-      drain();
-      wave_sync();
     }
-    __syncthreads();  // every wave is done with sB
+    if (more) put_norms(buf ^ 1);
+    // the next tile has landed and every wave is done with this one
+    __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
+    __syncthreads();
   }
 
   // ---- epilogue: this wave's 32 rows ----
@@ -440,7 +468,7 @@ __device__ __forceinline__ void knn_item(const KnnArgs &a, const int item) {
     int empty = 0;
 #pragma unroll
     for (int i = 0; i < KH; ++i) {
-      const uint64_t k = sKeep[orow * KST + h * KH + i];
+      const uint64_t k = ks[i];
       const int q = KSEL - 1 - (h * KH + i);
       empty += k == kEmptyKey ? 1 : 0;
       sBufD[orow * BUFD + q] = k == kEmptyKey ? INFINITY : key_dist(k);
@@ -460,7 +488,7 @@ __device__ __forceinline__ void knn_item(const KnnArgs &a, const int item) {
     const int cnt = rr < n_rows ? (tn < ksel_job ? tn : ksel_job) : 0;
     const int lrow = wave * 32 + l32;
     const int kbase = h * HALF;
-    // the row's FP32 half: av[] already holds it on the FP32 path
+    // the row's FP32 half: the A operand already holds it on the FP32 path
     float xr[(LP && ROW_REG) ? HALF : 1];
     // wide operands: the row half is re-read from memory (cache resident)
     const float *xrow = a.X + (int64_t)rows[rr < n_rows ? rr : 0] * d + kbase;
@@ -485,7 +513,7 @@ __device__ __forceinline__ void knn_item(const KnnArgs &a, const int item) {
     auto rv = [&](int kk) -> float {
       if constexpr (LP && ROW_REG) return xr[kk];
       else if constexpr (LP) return 0.f;
-      else return av[kk];
+      else return afl(kk);
     };
     // sum over this lane's half of the dimensions for column c
     auto half_dist = [&](uint32_t c) -> float {
@@ -587,14 +615,14 @@ __device__ __forceinline__ void knn_item(const KnnArgs &a, const int item) {
 
 // Static schedule: workgroup b takes item b.
 template <int PREC, int DP, int KSEL, int NW, bool L2>
-__global__ void __launch_bounds__(NW * 64, KnnOcc<DP>::v) knn_kernel(KnnArgs a) {
+__global__ void __launch_bounds__(NW * 64, (KnnOcc<PREC, DP>::v)) knn_kernel(KnnArgs a) {
   knn_item<PREC, DP, KSEL, NW, L2>(a, (int)blockIdx.x);
 }
 
 // Persistent schedule: block b runs on XCD b % 8 and serves that XCD's item
 // list from its counter until the list is exhausted.
 template <int PREC, int DP, int KSEL, int NW, bool L2>
-__global__ void __launch_bounds__(NW * 64, KnnOcc<DP>::v) knn_kernel_persistent(KnnArgs a) {
+__global__ void __launch_bounds__(NW * 64, (KnnOcc<PREC, DP>::v)) knn_kernel_persistent(KnnArgs a) {
   __shared__ int sNext;
   const int x = (int)(blockIdx.x % kNumXcd);
   for (;;) {
@@ -616,7 +644,7 @@ template <int PREC, int DP, int KSEL, int NW>
 static hipError_t launch_knn_nw(KnnArgs args, int n_items, int n_cu, hipStream_t s) {
   unsigned grid = (unsigned)n_items;
   if (args.work_counter) {
-    constexpr int per_cu = KnnOcc<DP>::v * 4 / NW;  // workgroups resident per CU
+    constexpr int per_cu = KnnOcc<PREC, DP>::v * 4 / NW;  // workgroups resident per CU
     const int resident = (n_cu * per_cu) / kNumXcd * kNumXcd;
     args.items_per_xcd = n_items / kNumXcd;
     grid = (unsigned)(n_items < resident ? n_items : resident);

@@ -143,6 +143,33 @@ __global__ void __launch_bounds__(256) quantize_kernel(const float *__restrict__
   if (lane == 0) norms[p] = nn;
 }
 
+// One thread per 16-byte chunk of the padded rows: float32 values, zeros
+// past d.
+__global__ void __launch_bounds__(256) pad_kernel(const float *__restrict__ X, int64_t n, int d,
+                                                  int ldf, float4 *__restrict__ out) {
+  const int cpr = ldf / 4;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n * cpr) return;
+  const int64_t p = i / cpr;
+  const int k = (int)(i - p * cpr) * 4;
+  const float *x = X + p * d;
+  float4 v;
+  v.x = k < d ? x[k] : 0.f;
+  v.y = k + 1 < d ? x[k + 1] : 0.f;
+  v.z = k + 2 < d ? x[k + 2] : 0.f;
+  v.w = k + 3 < d ? x[k + 3] : 0.f;
+  out[i] = v;
+}
+
+hipError_t launch_pad_range(const Index &I, int64_t p0, int64_t cnt, hipStream_t s) {
+  if (cnt <= 0 || !I.xpad.p) return hipSuccess;
+  const int64_t chunks = cnt * (I.ldf / 4);
+  hipLaunchKernelGGL(pad_kernel, dim3((unsigned)((chunks + 255) / 256)), dim3(256), 0, s,
+                     I.xf() + p0 * I.d, cnt, I.d, I.ldf,
+                     reinterpret_cast<float4 *>(I.xpad.as<float>() + p0 * I.ldf));
+  return hipGetLastError();
+}
+
 hipError_t launch_quantize(const Index &I, hipStream_t s) {
   return launch_quantize_range(I, 0, I.n, s);
 }
