@@ -168,16 +168,32 @@ pipnn_status pipnn_plan_leaves(pipnn_index *idx, const int64_t *d_leaf_offsets,
                                const uint32_t *d_leaf_members, int64_t n_leaves,
                                pipnn_stream_t stream);
 
-/* Leaf-kernel configuration of the index: rows_per_item 128 (four waves of
- * 32 rows) or 64 (two waves; built for operands of 65..128 dimensions), and
- * persistent 0 (one workgroup per work item, dealt to the XCDs by the host)
- * or 1 (resident workgroups take the items of their XCD from a device
- * counter, which balances uneven leaves at run time). Results do not depend
- * on it. EINVAL for other values or a shape that is not built. */
-pipnn_status pipnn_set_leaf_config(pipnn_index *idx, int32_t rows_per_item, int32_t persistent);
+/* Leaf-kernel layouts. PAIR: a row's operand is split over two lanes
+ * (32x32 MFMA tiles, a wave owns 32 rows; operands of up to 256
+ * dimensions). QUAD: over four lanes (16x16 MFMA tiles, a wave owns 16 rows,
+ * half the registers per row, so more waves share a compute unit; every
+ * width but the 96-dimension e4m3 operand, and the only layout above 256
+ * dimensions). */
+#define PIPNN_LAYOUT_PAIR 0
+#define PIPNN_LAYOUT_QUAD 1
+
+/* Leaf-kernel configuration of the index: layout (above); rows_per_item
+ * 128 (PAIR: four waves of 32 rows; QUAD: eight waves of 16) or 64 (PAIR
+ * only, built for operands of 65..128 dimensions); persistent 0 (one
+ * workgroup per work item, dealt to the XCDs by the host) or 1 (resident
+ * workgroups take the items of their XCD from a device counter, which
+ * balances uneven leaves at run time). rows_per_item and persistent do not
+ * change results. The two layouts sum the GEMM's products in different
+ * orders, so where that arithmetic rounds (non-integer data) GEMM distances
+ * can differ in the last bits between them, and with them the choice among
+ * near-tied candidates; the FP32 recomputed distances of a pair do not
+ * depend on the layout. EINVAL for other values or a shape that is not
+ * built. */
+pipnn_status pipnn_set_leaf_config(pipnn_index *idx, int32_t rows_per_item, int32_t persistent,
+                                   int32_t layout);
 
 typedef struct {
-  int32_t rows_per_item, persistent;
+  int32_t rows_per_item, persistent, layout;
   float ms; /* best of the timed runs of the leaf pick on the sample */
 } pipnn_tune_result;
 

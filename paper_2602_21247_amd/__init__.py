@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(HERE, "libpipnn.so")
 METRIC_L2, METRIC_IP = 0, 1
 DTYPE_F32, DTYPE_F16, DTYPE_BF16 = 0, 1, 2
 PREC_FP32, PREC_BF16, PREC_FP8, PREC_FP16 = 0, 1, 2, 3
+LAYOUT_PAIR, LAYOUT_QUAD = 0, 1
 EMPTY_ID = 0xFFFFFFFF
 EMPTY_SLOT = 0x7F80 << 48 | 0xFFFFFFFF
 
@@ -95,7 +96,7 @@ def lib():
         L.pipnn_get_stats.argtypes = [P, C.POINTER(Stats)]
         L.pipnn_get_operand.argtypes = [P, P, P, P, P]
         L.pipnn_plan_leaves.argtypes = [P, P, P, i64, P]
-        L.pipnn_set_leaf_config.argtypes = [P, i32, i32]
+        L.pipnn_set_leaf_config.argtypes = [P, i32, i32, i32]
         L.pipnn_reserve.argtypes = [P, i64, P]
         L.pipnn_insert.argtypes = [P, i64, P, P, P, P, P]
         L.pipnn_autotune.argtypes = [P, P, P, i64, C.POINTER(TuneResult), i32, C.POINTER(i32), P]
@@ -162,7 +163,8 @@ def reservoir_init(n: int, l_max: int, out=None):
 
 
 class TuneResult(C.Structure):
-    _fields_ = [("rows_per_item", C.c_int32), ("persistent", C.c_int32), ("ms", C.c_float)]
+    _fields_ = [("rows_per_item", C.c_int32), ("persistent", C.c_int32), ("layout", C.c_int32),
+                ("ms", C.c_float)]
 
 
 class Index:
@@ -208,17 +210,19 @@ class Index:
         _check(lib().pipnn_plan_leaves(self._h, _ptr(offsets), _ptr(members),
                                        offsets.numel() - 1, _stream()))
 
-    def set_leaf_config(self, rows_per_item: int = 128, persistent: bool = False):
-        _check(lib().pipnn_set_leaf_config(self._h, rows_per_item, 1 if persistent else 0))
+    def set_leaf_config(self, rows_per_item: int = 128, persistent: bool = False,
+                        layout: int = LAYOUT_PAIR):
+        _check(lib().pipnn_set_leaf_config(self._h, rows_per_item, 1 if persistent else 0,
+                                           layout))
 
     def autotune(self, offsets, members):
         """Time every leaf-kernel configuration on these leaves and keep the
-        fastest; returns [(rows_per_item, persistent, ms), ...]."""
-        out = (TuneResult * 8)()
+        fastest; returns [(rows_per_item, persistent, layout, ms), ...]."""
+        out = (TuneResult * 16)()
         cnt = C.c_int32()
         _check(lib().pipnn_autotune(self._h, _ptr(offsets), _ptr(members), offsets.numel() - 1,
-                                    out, 8, C.byref(cnt), _stream()))
-        return [(out[i].rows_per_item, bool(out[i].persistent), out[i].ms)
+                                    out, 16, C.byref(cnt), _stream()))
+        return [(out[i].rows_per_item, bool(out[i].persistent), out[i].layout, out[i].ms)
                 for i in range(cnt.value)]
 
     def reserve(self, n_cap: int):

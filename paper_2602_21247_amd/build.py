@@ -15,7 +15,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libpipnn.so")
 BUILD_DIR = os.path.join(HERE, "_build")
-SOURCES = ["knn.hip", "knn_bf16.hip", "knn_fp16.hip", "knn_fp8.hip", "capi.hip", "misc.hip",
+SOURCES = ["knn.hip", "knn_fp32q.hip", "knn_bf16.hip", "knn_fp16.hip", "knn_fp8.hip", "capi.hip",
+           "misc.hip",
            "hashprune.hip", "graph.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -815,6 +815,7 @@ pipnn_status launch_pick(Index &I, const KnnJob *d_jobs, const KnnItem *d_items,
   L.prec = P.gemm_prec;
   L.nw = I.leaf_nw;
   L.persistent = I.leaf_persistent;
+  L.quad = I.leaf_quad;
   L.out_col = pick_c;
   L.out_dist = pick_d;
   L.out_matrix = nullptr;
@@ -1304,6 +1305,7 @@ pipnn_status pipnn_insert(pipnn_index *idx, int64_t n_new, const int32_t *d_grou
     L.prec = P.gemm_prec;
     L.nw = I.leaf_nw;
     L.persistent = 0;
+    L.quad = I.leaf_quad;
     L.out_col = I.s_picks_c.as<uint32_t>();
     L.out_dist = I.s_picks_d.as<float>();
     L.out_matrix = nullptr;
@@ -1334,17 +1336,28 @@ pipnn_status pipnn_insert(pipnn_index *idx, int64_t n_new, const int32_t *d_grou
   GUARD_END
 }
 
-pipnn_status pipnn_set_leaf_config(pipnn_index *idx, int32_t rows_per_item, int32_t persistent) {
+// Whether the index can run leaf picks in this configuration.
+static bool leaf_config_ok(const Index &I, int32_t rows_per_item, int32_t persistent,
+                           int32_t layout) {
+  if (persistent != 0 && persistent != 1) return false;
+  if (layout == PIPNN_LAYOUT_QUAD)
+    return rows_per_item == 128 && knn_quad_available(I.d, I.p.gemm_prec);
+  if (layout != PIPNN_LAYOUT_PAIR || (rows_per_item != 64 && rows_per_item != 128)) return false;
+  return knn_pair_available(I.d, I.p.gemm_prec) &&
+         knn_nw_available(I.d, I.p.gemm_prec, rows_per_item / 32);
+}
+
+pipnn_status pipnn_set_leaf_config(pipnn_index *idx, int32_t rows_per_item, int32_t persistent,
+                                   int32_t layout) {
   GUARD_BEGIN
   if (!idx) return fail(PIPNN_EINVAL, "NULL index");
   Index &I = *reinterpret_cast<Index *>(idx);
-  if ((rows_per_item != 64 && rows_per_item != 128) || (persistent != 0 && persistent != 1))
-    return fail(PIPNN_EINVAL, "rows_per_item must be 64 or 128 and persistent 0 or 1");
-  if (!knn_nw_available(I.d, I.p.gemm_prec, rows_per_item / 32))
-    return fail(PIPNN_EINVAL, "%d-row work items are not built for this operand width",
-                rows_per_item);
+  if (!leaf_config_ok(I, rows_per_item, persistent, layout))
+    return fail(PIPNN_EINVAL, "leaf configuration (%d rows, persistent %d, layout %d) is not built "
+                "for this operand", rows_per_item, persistent, layout);
   I.leaf_nw = rows_per_item / 32;
   I.leaf_persistent = persistent;
+  I.leaf_quad = layout == PIPNN_LAYOUT_QUAD ? 1 : 0;
   return PIPNN_OK;
   GUARD_END
 }
@@ -1371,10 +1384,11 @@ pipnn_status pipnn_autotune(pipnn_index *idx, const int64_t *d_leaf_offsets,
   HIPCHK(I.s_picks_c.ensure((size_t)std::max<int64_t>(rows, 1) * I.p.k * 4));
   HIPCHK(I.s_picks_d.ensure((size_t)std::max<int64_t>(rows, 1) * I.p.k * 4));
   std::vector<pipnn_tune_result> res;
-  for (int nw : {4, 2})
-    for (int pers : {0, 1})
-      if (knn_nw_available(I.d, I.p.gemm_prec, nw)) res.push_back({32 * nw, pers, 0.f});
-  const int32_t keep_nw = I.leaf_nw, keep_pers = I.leaf_persistent;
+  for (int layout : {PIPNN_LAYOUT_PAIR, PIPNN_LAYOUT_QUAD})
+    for (int rows : {128, 64})
+      for (int pers : {0, 1})
+        if (leaf_config_ok(I, rows, pers, layout)) res.push_back({rows, pers, layout, 0.f});
+  const int32_t keep_nw = I.leaf_nw, keep_pers = I.leaf_persistent, keep_quad = I.leaf_quad;
   const bool keep_prof = I.profiling;
   I.profiling = false;
   hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -1384,6 +1398,7 @@ pipnn_status pipnn_autotune(pipnn_index *idx, const int64_t *d_leaf_offsets,
   for (auto &r : res) {
     I.leaf_nw = r.rows_per_item / 32;
     I.leaf_persistent = r.persistent;
+    I.leaf_quad = r.layout == PIPNN_LAYOUT_QUAD ? 1 : 0;
     float best = 1e30f;
     for (int rep = 0; rep < 3 && rs == PIPNN_OK; ++rep) {
       (void)hipEventRecord(e0, s);
@@ -1404,6 +1419,7 @@ pipnn_status pipnn_autotune(pipnn_index *idx, const int64_t *d_leaf_offsets,
   if (rs != PIPNN_OK) {
     I.leaf_nw = keep_nw;
     I.leaf_persistent = keep_pers;
+    I.leaf_quad = keep_quad;
     return rs;
   }
   size_t bi = 0;
@@ -1411,6 +1427,7 @@ pipnn_status pipnn_autotune(pipnn_index *idx, const int64_t *d_leaf_offsets,
     if (res[i].ms < res[bi].ms) bi = i;
   I.leaf_nw = res[bi].rows_per_item / 32;
   I.leaf_persistent = res[bi].persistent;
+  I.leaf_quad = res[bi].layout == PIPNN_LAYOUT_QUAD ? 1 : 0;
   if (h_n_results) *h_n_results = (int32_t)res.size();
   if (h_results)
     for (size_t i = 0; i < res.size() && (int32_t)i < cap_results; ++i) h_results[i] = res[i];
@@ -1481,6 +1498,7 @@ pipnn_status pipnn_knn_block(pipnn_index *idx, const uint32_t *d_row_ids, int64_
   L.prec = I.p.gemm_prec;
   L.nw = I.leaf_nw;
   L.persistent = I.leaf_persistent;
+  L.quad = I.leaf_quad;
   L.out_col = d_out_col;
   L.out_dist = d_out_dist;
   L.out_matrix = d_out_matrix;

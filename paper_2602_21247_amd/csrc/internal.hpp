@@ -60,6 +60,7 @@ struct Index {
   int32_t n_cu = 256;           // compute units of the device (persistent grid size)
   int32_t leaf_nw = 4;          // waves (of 32 rows) per leaf work item: 4, or 2 where built
   int32_t leaf_persistent = 0;  // 1: persistent workgroups take items from the counters
+  int32_t leaf_quad = 0;        // 1: four lanes per row (128-row items)
   // A planned leaf set (pipnn_plan_leaves): its work lists live on the
   // device, so that pipnn_build_leaves on it does no host work and can be
   // captured in a graph.
@@ -139,6 +140,7 @@ struct KnnLaunch {
   int32_t prec;          // PIPNN_PREC_*: the operand (FP32 for the partition)
   int32_t nw;            // waves per work item (rows per item / 32)
   int32_t persistent;    // 1: persistent schedule over Index::s_counter
+  int32_t quad = 0;      // 1: four lanes per row (knn_quad.hpp), on 128-row items
   uint32_t *out_col;
   float *out_dist;
   float *out_matrix;
@@ -149,6 +151,9 @@ hipError_t launch_knn(const KnnLaunch &L, hipStream_t s);
 // whether work items of 32 * nw rows exist for it.
 int knn_operand_dim(int d, int prec);
 bool knn_nw_available(int d, int prec, int nw);
+// Whether the four-lane layout is built for the operand, and the two-lane one.
+bool knn_quad_available(int d, int prec);
+bool knn_pair_available(int d, int prec);
 
 // Reduced-precision operands are stored zero padded to one of these
 // dimensions, so that every operand row is a whole number of 16-byte

@@ -20,7 +20,19 @@ int knn_operand_dim(int d, int prec) {
 }
 
 bool knn_nw_available(int d, int prec, int nw) {
-  return nw == 4 || (nw == 2 && knn_has_nw2(knn_operand_dim(d, prec)));
+  const int dp = knn_operand_dim(d, prec);
+  return dp != 0 && (nw == 4 || (nw == 2 && dp <= 256 && knn_has_nw2(dp)));
+}
+
+bool knn_quad_available(int d, int prec) {
+  const int dp = knn_operand_dim(d, prec);
+  const int eb = prec == PIPNN_PREC_FP32 ? 4 : prec == PIPNN_PREC_FP8 ? 1 : 2;
+  return dp != 0 && (dp * eb) % 64 == 0;
+}
+
+bool knn_pair_available(int d, int prec) {
+  const int dp = knn_operand_dim(d, prec);
+  return dp != 0 && dp <= 256;
 }
 
 hipError_t launch_knn(const KnnLaunch &L, hipStream_t s) {
@@ -51,6 +63,9 @@ hipError_t launch_knn(const KnnLaunch &L, hipStream_t s) {
   a.work_counter = nullptr;
   a.items_per_xcd = 0;
   if (!knn_nw_available(I.d, L.prec, L.nw) || L.n_items % kNumXcd != 0) return hipErrorInvalidValue;
+  // operands wider than 256 dimensions exist in the four-lane layout only
+  const bool quad = L.quad || !knn_pair_available(I.d, L.prec);
+  if (quad && (L.nw != 4 || !knn_quad_available(I.d, L.prec))) return hipErrorInvalidValue;
   if (L.persistent) {
     a.work_counter = I.s_counter.as<int32_t>();
     if (!a.work_counter) return hipErrorInvalidValue;
@@ -61,12 +76,13 @@ hipError_t launch_knn(const KnnLaunch &L, hipStream_t s) {
   if (lowp) {
     if (!a.Xop || a.ldo != lowp_padded_dim(I.d) || L.prec != I.p.gemm_prec)
       return hipErrorInvalidValue;
-    if (L.prec == PIPNN_PREC_BF16) return launch_knn_bf16(a, L.ksel, L.n_items, nw, n_cu, s);
-    if (L.prec == PIPNN_PREC_FP16) return launch_knn_fp16(a, L.ksel, L.n_items, nw, n_cu, s);
-    if (L.prec == PIPNN_PREC_FP8) return launch_knn_fp8(a, L.ksel, L.n_items, nw, n_cu, s);
+    if (L.prec == PIPNN_PREC_BF16) return launch_knn_bf16(a, L.ksel, L.n_items, nw, quad, n_cu, s);
+    if (L.prec == PIPNN_PREC_FP16) return launch_knn_fp16(a, L.ksel, L.n_items, nw, quad, n_cu, s);
+    if (L.prec == PIPNN_PREC_FP8) return launch_knn_fp8(a, L.ksel, L.n_items, nw, quad, n_cu, s);
     return hipErrorInvalidValue;
   }
   if (I.ldf != knn_operand_dim(I.d, PIPNN_PREC_FP32)) return hipErrorInvalidValue;
+  if (quad) return launch_knn_fp32_quad(a, L.ksel, L.n_items, n_cu, s);
   switch (I.ldf) {
     case 32: return launch_dp<32>(a, L.ksel, L.n_items, nw, n_cu, s);
     case 64: return launch_dp<64>(a, L.ksel, L.n_items, nw, n_cu, s);

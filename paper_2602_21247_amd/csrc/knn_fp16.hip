@@ -1,11 +1,11 @@
 // Leaf kernel instantiations for the fp16 GEMM operand (FP32 accumulation).
-#include "knn_wide.hpp"
+#include "knn_quad.hpp"
 
 namespace pipnn {
 
-hipError_t launch_knn_fp16(const KnnArgs &a, int ksel, int n_items, int nw, int n_cu,
+hipError_t launch_knn_fp16(const KnnArgs &a, int ksel, int n_items, int nw, bool quad, int n_cu,
                           hipStream_t s) {
-  return launch_knn_lowp<PIPNN_PREC_FP16>(a, ksel, n_items, nw, n_cu, s);
+  return launch_knn_lowp<PIPNN_PREC_FP16>(a, ksel, n_items, nw, quad, n_cu, s);
 }
 
 }  // namespace pipnn

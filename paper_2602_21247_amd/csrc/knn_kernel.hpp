@@ -680,8 +680,15 @@ static hipError_t launch_knn_shape(const KnnArgs &args, int n_items, int nw, int
   return launch_knn_nw<PREC, DP, KSEL, 4>(args, n_items, n_cu, s);
 }
 
-hipError_t launch_knn_bf16(const KnnArgs &a, int ksel, int n_items, int nw, int n_cu, hipStream_t s);
-hipError_t launch_knn_fp16(const KnnArgs &a, int ksel, int n_items, int nw, int n_cu, hipStream_t s);
-hipError_t launch_knn_fp8(const KnnArgs &a, int ksel, int n_items, int nw, int n_cu, hipStream_t s);
+// Launches of the reduced-precision operands (nw: rows per item / 32; quad:
+// the four-lane layout of knn_quad.hpp, on 128-row items) and of the
+// float32 operand in the four-lane layout.
+hipError_t launch_knn_bf16(const KnnArgs &a, int ksel, int n_items, int nw, bool quad, int n_cu,
+                           hipStream_t s);
+hipError_t launch_knn_fp16(const KnnArgs &a, int ksel, int n_items, int nw, bool quad, int n_cu,
+                           hipStream_t s);
+hipError_t launch_knn_fp8(const KnnArgs &a, int ksel, int n_items, int nw, bool quad, int n_cu,
+                          hipStream_t s);
+hipError_t launch_knn_fp32_quad(const KnnArgs &a, int ksel, int n_items, int n_cu, hipStream_t s);
 
 }  // namespace pipnn

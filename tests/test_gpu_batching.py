@@ -112,6 +112,10 @@ def test_wide_leaf_pick_against_fp64(wide):
 
 @pytest.mark.parametrize("case", ["int128-fp32", "vmf96-bf16", "wide768-fp16"])
 def test_leaf_configs_give_identical_picks(case, wide):
+    """Work-item size and schedule never change a pick. The two register
+    layouts sum the GEMM products in different orders: on integer data
+    (exact arithmetic) they agree bit for bit too, elsewhere their FP32
+    distances of a pair agree bit for bit and the picks almost everywhere."""
     if case == "int128-fp32":
         X = pi.integer_mixture(20000, 128, 60, 40.0, seed=41)
         H = pi.hyperplanes(12, 128, seed=42, integer=True)
@@ -132,26 +136,43 @@ def test_leaf_configs_give_identical_picks(case, wide):
         p = wide_params()
     idx = pp.Index(dev(Xs), dev(H), p)
     outs = {}
-    for rows in (128, 64):
-        for pers in (False, True):
-            try:
-                idx.set_leaf_config(rows, pers)
-            except pp.PipnnError:
-                assert rows == 64 and case == "wide768-fp16"
-                continue
-            oc, od = idx.leaf_pick(dev(off), dev(mem))
-            torch.cuda.synchronize()
-            outs[(rows, pers)] = (u32(oc).copy(), od.cpu().numpy().copy())
-    first = next(iter(outs.values()))
-    for key, (c, d) in outs.items():
-        assert np.array_equal(c, first[0]), key
-        assert np.array_equal(d, first[1]), key
+    for layout in (pp.LAYOUT_PAIR, pp.LAYOUT_QUAD):
+        for rows in (128, 64):
+            for pers in (False, True):
+                try:
+                    idx.set_leaf_config(rows, pers, layout)
+                except pp.PipnnError:
+                    # 64-row items: two-lane layout at 65..128 dimensions only;
+                    # the 768-d operand exists in the four-lane layout only
+                    assert rows == 64 or (case == "wide768-fp16" and layout == pp.LAYOUT_PAIR)
+                    continue
+                oc, od = idx.leaf_pick(dev(off), dev(mem))
+                torch.cuda.synchronize()
+                outs[(layout, rows, pers)] = (u32(oc).copy(), od.cpu().numpy().copy())
+    assert len(outs) >= 2
+    for layout in (pp.LAYOUT_PAIR, pp.LAYOUT_QUAD):
+        same = [v for k, v in outs.items() if k[0] == layout]
+        for c, d in same[1:]:
+            assert np.array_equal(c, same[0][0]), layout
+            assert np.array_equal(d, same[0][1]), layout
+    keys = sorted(outs)
+    if keys[0][0] != keys[-1][0]:
+        (c0, d0), (c1, d1) = outs[keys[0]], outs[keys[-1]]
+        if case == "int128-fp32":
+            assert np.array_equal(c0, c1) and np.array_equal(d0, d1)
+        else:
+            same_pick = c0 == c1
+            print(case, f"layouts: same picks {same_pick.mean():.5f}")
+            assert same_pick.mean() >= 0.999
+            # where both layouts pick the same pair, its recomputed distance is the same
+            assert np.array_equal(d0[same_pick], d1[same_pick])
     res = idx.autotune(dev(off), dev(mem))
     print(case, "autotune:", res)
-    assert len(res) == len(outs) and all(r[2] > 0 for r in res)
+    assert len(res) == len(outs) and all(r[3] > 0 for r in res)
     oc, od = idx.leaf_pick(dev(off), dev(mem))
     torch.cuda.synchronize()
-    assert np.array_equal(u32(oc), first[0])
+    best = min(res, key=lambda r: r[3])
+    assert np.array_equal(u32(oc), outs[(best[2], best[0], best[1])][0])
     idx.close()
 
 
