@@ -90,8 +90,13 @@ typedef int32_t pipnn_status;
  *  gemm_prec    PIPNN_PREC_*: arithmetic of the leaf distance GEMM. BF16,
  *               FP16 and FP8 multiply a copy of X in that format (made by
  *               pipnn_create / pipnn_prepare, d <= 768) and accumulate in
- *               FP32; FP32 needs d <= 256. Partition distances use the
- *               float32 vectors for d <= 256, the reduced operand above.
+ *               FP32; FP32 needs d <= 256. When every value of X survives
+ *               the encoding (the copy holds X exactly, as bf16 does for
+ *               integers of up to 8 significant bits), the partition's
+ *               distances and RobustPrune's rows are read from the copy
+ *               too (half the bytes; the same values); otherwise the
+ *               partition uses the float32 vectors for d <= 256 and the
+ *               copy above.
  *  rescore_mult 0, or r >= 2: select the r*k nearest by the GEMM distance
  *               and keep the k nearest by an FP32 direct-difference rescore.
  *  seed         root key of the leader sampling (Alg. 5, SampleLeaders).
@@ -187,8 +192,9 @@ pipnn_status pipnn_plan_leaves(pipnn_index *idx, const int64_t *d_leaf_offsets,
  * orders, so where that arithmetic rounds (non-integer data) GEMM distances
  * can differ in the last bits between them, and with them the choice among
  * near-tied candidates; the FP32 recomputed distances of a pair do not
- * depend on the layout. EINVAL for other values or a shape that is not
- * built. */
+ * depend on the layout. The index starts with QUAD, 128 rows, static for a
+ * float32 GEMM operand and PAIR, 128 rows, static otherwise (QUAD where PAIR
+ * is not built). EINVAL for other values or a shape that is not built. */
 pipnn_status pipnn_set_leaf_config(pipnn_index *idx, int32_t rows_per_item, int32_t persistent,
                                    int32_t layout);
 
@@ -292,11 +298,16 @@ pipnn_status pipnn_reservoir_canonical(const pipnn_index *idx, const uint64_t *d
 
 /* Final prune (Alg. 4, PruneNode; Sec. 4.3): RobustPrune (Alg. 2) in its
  * lazy form (Supplement, "Optimizing RobustPrune") on every reservoir. The
- * candidates of x are its reservoir ids; d(x,c) and d(y,c) are FP32
- * direct-difference distances; candidates are taken in (distance, id)
- * order and c is admitted unless an admitted y has alpha*d(y,c) < d(x,c)
- * (evaluated as the sign of one fused multiply-add). Writes d_graph (n x R,
- * admission order, 0xFFFFFFFF padding) and d_degree (n). */
+ * candidates of x are its reservoir ids; d(x,c) is the FP32 direct-
+ * difference distance, and d(y,c) between candidates the FP32 GEMM form
+ * |y|^2 + |c|^2 - 2 y.c (or -y.c) from a Gram on MFMA (up to 64 candidates
+ * and 128 dimensions; the 16-bit copy of X when it holds X exactly, see
+ * gemm_prec), for 512 / 768-dimension bf16 / fp16 operands both come from
+ * the operand's Gram, and otherwise both are direct differences.
+ * Candidates are taken in (d(x,c), id) order and c is admitted unless an
+ * admitted y has alpha*d(y,c) < d(x,c) (evaluated as the sign of one fused
+ * multiply-add). Writes d_graph (n x R, admission order, 0xFFFFFFFF
+ * padding) and d_degree (n). */
 pipnn_status pipnn_robustprune(pipnn_index *idx, const uint64_t *d_reservoirs, uint32_t *d_graph,
                                uint32_t *d_degree, pipnn_stream_t stream);
 
@@ -330,6 +341,8 @@ typedef struct {
   int32_t leaf_knn_launches;     /* leaf kernel launches since profiling on */
   int64_t leaf_pairs;            /* sum of s^2 over the leaves of the last build */
   int64_t records;               /* candidate records binned by the last build */
+  int32_t operand_exact;         /* 1: the reduced-precision copy holds X exactly */
+  int32_t reserved_;
   double ms_prepare, ms_partition, ms_leaf_knn, ms_bin, ms_merge, ms_robustprune;
 } pipnn_stats;
 

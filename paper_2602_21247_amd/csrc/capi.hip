@@ -338,6 +338,10 @@ pipnn_status pipnn_create(const pipnn_params *p, const void *d_X, int64_t n, int
       I->n_cu = ncu;
   }
   I->cap = n;
+  // leaf-kernel default: four lanes per row for the float32 operand (its MFMA
+  // work dominates and the smaller A fragment leaves room for more waves),
+  // two lanes for the reduced-precision operands; pipnn_autotune may change it
+  I->leaf_quad = (p->gemm_prec == PIPNN_PREC_FP32 && knn_quad_available(d, PIPNN_PREC_FP32)) ? 1 : 0;
   if (p->gemm_prec == PIPNN_PREC_FP32 && knn_operand_dim(d, PIPNN_PREC_FP32) == 0)
     return cleanup(fail(PIPNN_EINVAL, "a float32 leaf GEMM needs d <= 256 (use a reduced "
                                       "gemm_prec for wider vectors)"));
@@ -370,9 +374,11 @@ pipnn_status pipnn_create(const pipnn_params *p, const void *d_X, int64_t n, int
     const size_t eb = p->gemm_prec == PIPNN_PREC_FP8 ? 1 : 2;
     if ((e = I->xlow.ensure((size_t)n * I->ldo * eb)) != hipSuccess ||
         (e = I->xscale.ensure((size_t)n * 4)) != hipSuccess ||
-        (e = I->lnorms.ensure((size_t)n * 4)) != hipSuccess)
+        (e = I->lnorms.ensure((size_t)n * 4)) != hipSuccess ||
+        (e = I->op_flag.ensure(64)) != hipSuccess)
       return cleanup(fail(PIPNN_ENOMEM, "device allocation failed: %s", hipGetErrorString(e)));
-    if ((e = launch_quantize(*I, s)) != hipSuccess)
+    if ((e = clear_op_flag(*I, s)) != hipSuccess || (e = launch_quantize(*I, s)) != hipSuccess ||
+        (e = read_op_flag(*I, true, s)) != hipSuccess)
       return cleanup(fail(PIPNN_EDEVICE, "quantize launch failed: %s", hipGetErrorString(e)));
   }
   if ((e = hipMemsetAsync(I->flag.p, 0, 64, s)) != hipSuccess)
@@ -387,7 +393,7 @@ void pipnn_destroy(pipnn_index *idx) {
   Index *I = reinterpret_cast<Index *>(idx);
   (void)hipDeviceSynchronize();
   for (DevBuf *b : {&I->rp_order, &I->o_first, &I->o_flag, &I->o_pos, &I->o_pos2, &I->o_tmp,
-                    &I->xf32, &I->xpad, &I->xlow, &I->xscale, &I->lnorms, &I->s_counter, &I->q_conv, &I->q_seen,
+                    &I->xf32, &I->xpad, &I->xlow, &I->op_flag, &I->xscale, &I->lnorms, &I->s_counter, &I->q_conv, &I->q_seen,
                     &I->lt_off, &I->lt_mem, &I->lt_rep, &I->i_rows, &I->i_cols, &I->i_assign,
                     &I->i_flag, &I->i_pos, &I->i_list, &I->i_tmp, &I->i_segs, &I->sketches, &I->norms, &I->flag, &I->s_jobs,
                     &I->s_items, &I->s_picks_c, &I->s_picks_d, &I->s_cnt, &I->s_off, &I->s_bins,
@@ -419,10 +425,12 @@ pipnn_status pipnn_partition(pipnn_index *idx, int64_t *d_leaf_offsets, int64_t 
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   const pipnn_params &P = I.p;
   const int64_t n = I.n;
-  // point-to-leader distances in float32 where the float32 kernel is built
-  // (d <= 256), else on the index's reduced-precision operand
+  // point-to-leader distances on the index's reduced-precision operand when
+  // it holds X exactly or the float32 kernel is not built (d > 256), else
+  // in float32
   const int32_t part_prec =
-      knn_operand_dim(I.d, PIPNN_PREC_FP32) ? PIPNN_PREC_FP32 : P.gemm_prec;
+      (P.gemm_prec != PIPNN_PREC_FP32 && (I.op_exact || !knn_operand_dim(I.d, PIPNN_PREC_FP32)))
+          ? P.gemm_prec : PIPNN_PREC_FP32;
   if (knn_operand_dim(I.d, part_prec) == 0)
     return fail(PIPNN_EINVAL, "partition of d = %d needs a reduced gemm_prec (float32 partition "
                               "distances are built for d <= 256)", I.d);
@@ -523,6 +531,9 @@ pipnn_status pipnn_partition(pipnn_index *idx, int64_t *d_leaf_offsets, int64_t 
     L.prec = part_prec;
     L.nw = 4;
     L.persistent = 0;
+    // float32 leader distances in the four-lane layout (where built), the
+    // reduced-precision ones in the two-lane layout
+    L.quad = part_prec == PIPNN_PREC_FP32 && knn_quad_available(I.d, PIPNN_PREC_FP32) ? 1 : 0;
     L.out_col = I.p_asg.as<uint32_t>();
     L.out_dist = nullptr;
     L.out_matrix = nullptr;
@@ -1180,7 +1191,11 @@ pipnn_status pipnn_insert(pipnn_index *idx, int64_t n_new, const int32_t *d_grou
   }
   HIPCHK(launch_norms_sketches_range(I, n0, n_new, s));
   HIPCHK(launch_pad_range(I, n0, n_new, s));
-  if (P.gemm_prec != PIPNN_PREC_FP32) HIPCHK(launch_quantize_range(I, n0, n_new, s));
+  if (P.gemm_prec != PIPNN_PREC_FP32) {
+    HIPCHK(clear_op_flag(I, s));
+    HIPCHK(launch_quantize_range(I, n0, n_new, s));
+    HIPCHK(read_op_flag(I, false, s));
+  }
   HIPCHK(launch_fill_u64(d_reservoirs + n0 * P.l_max, empty_slot(), n_new * P.l_max, s));
 
   // 2. route every new point to its f nearest leaves (by the leaf representatives)
@@ -1622,7 +1637,13 @@ pipnn_status pipnn_prepare(pipnn_index *idx, pipnn_stream_t stream) {
     HIPCHK(launch_to_f32(I.X, I.x_dtype, I.xf32.as<float>(), I.n * (int64_t)I.d, s));
   HIPCHK(launch_norms_sketches(I, s));
   HIPCHK(launch_pad_range(I, 0, I.n, s));
-  if (I.p.gemm_prec != PIPNN_PREC_FP32) HIPCHK(launch_quantize(I, s));
+  if (I.p.gemm_prec != PIPNN_PREC_FP32) {
+    HIPCHK(clear_op_flag(I, s));
+    HIPCHK(launch_quantize(I, s));
+    // outside capture the operand's exactness is taken again; a captured
+    // prepare keeps the one found by the last uncaptured encode
+    if (!stream_capturing(s)) HIPCHK(read_op_flag(I, true, s));
+  }
   return PIPNN_OK;
   GUARD_END
 }
@@ -1646,6 +1667,7 @@ pipnn_status pipnn_get_stats(pipnn_index *idx, pipnn_stats *h_out) {
   flush_events(I);
   pipnn_stats st = I.stats;
   st.leaf_knn_launches = I.leaf_launches;
+  st.operand_exact = I.op_exact ? 1 : 0;
   st.ms_prepare = I.phase_ms[kPhPrepare];
   st.ms_partition = I.phase_ms[kPhPartition];
   st.ms_leaf_knn = I.phase_ms[kPhLeafKnn];

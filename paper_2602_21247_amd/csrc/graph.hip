@@ -162,6 +162,92 @@ __device__ __forceinline__ int acc_row32(int v, int h) { return (v & 3) + 8 * (v
 //     admitted. Admitted candidates all come before z in the order, so the
 //     mask may hold later ones too. This admits exactly the candidates of
 //     Alg. 2.
+// Steps 3 and 4 of the MFMA RobustPrune described above, shared by its operand forms:
+// from the Gram blocks and the per-slot d(x,c), norms and ranking keys in
+// LDS to the admitted neighbours of x.
+__device__ __forceinline__ void rp_finish(const f32x16 &g00, const f32x16 &g01, const f32x16 &g11,
+                                          int nv, bool l2, float alpha, int R, uint32_t x,
+                                          const float *sDw, const float *sNw, const uint64_t *sKw,
+                                          const uint32_t *sIw, uint32_t *sSw,
+                                          uint32_t *__restrict__ graph,
+                                          uint32_t *__restrict__ degree) {
+  const int lane = threadIdx.x & 63;
+  const int h = lane >> 5, l32 = lane & 31;
+  // 3. prune masks. Column of this lane: z = l32 (block 00), 32 + l32 (01, 11);
+  //    rows y of block 01 are slots 0..31 (they may prune z in 32..63), and
+  //    block 00 / 11 cover the pairs within each half. Pairs (y in 32..63,
+  //    z in 0..31) are the transposes of block 01.
+  uint32_t b00 = 0, b01 = 0, b11 = 0, b10 = 0;
+  {
+    const int zA = l32, zB = 32 + l32;
+    const float dxA = sDw[zA], dxB = sDw[zB];
+    const float nA = sNw[zA], nB = sNw[zB];
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int y = acc_row32(v, h);
+      const float ny = sNw[y], ny1 = sNw[32 + y];
+      const float dy0 = sDw[y], dy1 = sDw[32 + y];
+      const float d00 = l2 ? ny + fmaf(-2.f, g00[v], nA) : -g00[v];
+      if (y != zA && zA < nv && y < nv && fmaf(alpha, d00, -dxA) < 0.f) b00 |= 1u << y;
+      if (nv > 32) {
+        const float d01 = l2 ? ny + fmaf(-2.f, g01[v], nB) : -g01[v];
+        const float d11 = l2 ? ny1 + fmaf(-2.f, g11[v], nB) : -g11[v];
+        // slot y (0..31) prunes slot zB; and slot zB, as a row, prunes slot y
+        if (zB < nv && y < nv && fmaf(alpha, d01, -dxB) < 0.f) b01 |= 1u << y;
+        if (zB < nv && y < nv && fmaf(alpha, d01, -dy0) < 0.f) b10 |= 1u << y;
+        if (32 + y != zB && zB < nv && 32 + y < nv && fmaf(alpha, d11, -dxB) < 0.f)
+          b11 |= 1u << y;
+        (void)dy1;
+      }
+    }
+    b00 |= __shfl_xor(b00, 32, 64);
+    b01 |= __shfl_xor(b01, 32, 64);
+    b11 |= __shfl_xor(b11, 32, 64);
+    b10 |= __shfl_xor(b10, 32, 64);
+  }
+  // masks by slot: lane j < 32 holds slot j's pruners among slots 0..31 (b00)
+  // and 32..63 (transposed from b10); lane 32 + j holds slot 32 + j's from
+  // b01 (0..31) and b11 (32..63). b10 of lane zB has bit y set when zB prunes
+  // y: it is gathered per y below.
+  uint32_t mlo = h == 0 ? b00 : b01;
+  uint32_t mhi = h == 0 ? 0u : b11;
+  if (nv > 32) {
+    // slot y < 32, bit (zB - 32): zB prunes y. Lane zB holds b10 with bit y.
+    uint32_t t = 0;
+    for (int j = 0; j < 32; ++j) {
+      const uint32_t bj = (uint32_t)__builtin_amdgcn_readlane((int)b10, 32 + j);
+      t |= ((bj >> l32) & 1u) << j;
+    }
+    if (h == 0) mhi = t;
+  }
+
+  // 4. ranks by (d(x,c), id) and the lazy admission scan (wave-uniform)
+  if (lane < nv) {
+    const uint64_t kt = sKw[lane];
+    int rank = 0;
+    for (int u = 0; u < nv; ++u) rank += sKw[u] < kt ? 1 : 0;
+    sSw[rank] = (uint32_t)lane;
+  }
+  wave_sync();
+  const int my_slot = lane < nv ? (int)sSw[lane] : 0;  // slot at sorted position lane
+  uint64_t adm = 0;
+  int ne = 0;
+  uint32_t my_id = kEmptyId;
+  for (int p = 0; p < nv && ne < R; ++p) {
+    const int z = __builtin_amdgcn_readlane(my_slot, p);
+    // readlane returns int: widen through uint32_t so bit 31 does not sign-extend
+    const uint64_t mz = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)mhi, z) << 32) |
+                        (uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)mlo, z);
+    if ((mz & adm) == 0) {
+      adm |= 1ull << z;
+      if (lane == ne) my_id = sIw[z];
+      ++ne;
+    }
+  }
+  uint32_t *grow = graph + (int64_t)x * R;
+  for (int i = lane; i < R; i += 64) grow[i] = i < ne ? (i == lane ? my_id : kEmptyId) : kEmptyId;
+  if (lane == 0) degree[x] = (uint32_t)ne;}
+
 template <int DP>
 __global__ void __launch_bounds__(64 * kRpWaves) robustprune_mfma_kernel(
     const float *__restrict__ X, const float *__restrict__ norms, int64_t n, int d, int metric,
@@ -283,80 +369,128 @@ __global__ void __launch_bounds__(64 * kRpWaves) robustprune_mfma_kernel(
     }
   }
 
-  // 3. prune masks. Column of this lane: z = l32 (block 00), 32 + l32 (01, 11);
-  //    rows y of block 01 are slots 0..31 (they may prune z in 32..63), and
-  //    block 00 / 11 cover the pairs within each half. Pairs (y in 32..63,
-  //    z in 0..31) are the transposes of block 01.
-  uint32_t b00 = 0, b01 = 0, b11 = 0, b10 = 0;
-  {
-    const int zA = l32, zB = 32 + l32;
-    const float dxA = sD[wave][zA], dxB = sD[wave][zB];
-    const float nA = sN[wave][zA], nB = sN[wave][zB];
-#pragma unroll
-    for (int v = 0; v < 16; ++v) {
-      const int y = acc_row32(v, h);
-      const float ny = sN[wave][y], ny1 = sN[wave][32 + y];
-      const float dy0 = sD[wave][y], dy1 = sD[wave][32 + y];
-      const float d00 = l2 ? ny + fmaf(-2.f, g00[v], nA) : -g00[v];
-      if (y != zA && zA < nv && y < nv && fmaf(alpha, d00, -dxA) < 0.f) b00 |= 1u << y;
-      if (nv > 32) {
-        const float d01 = l2 ? ny + fmaf(-2.f, g01[v], nB) : -g01[v];
-        const float d11 = l2 ? ny1 + fmaf(-2.f, g11[v], nB) : -g11[v];
-        // slot y (0..31) prunes slot zB; and slot zB, as a row, prunes slot y
-        if (zB < nv && y < nv && fmaf(alpha, d01, -dxB) < 0.f) b01 |= 1u << y;
-        if (zB < nv && y < nv && fmaf(alpha, d01, -dy0) < 0.f) b10 |= 1u << y;
-        if (32 + y != zB && zB < nv && 32 + y < nv && fmaf(alpha, d11, -dxB) < 0.f)
-          b11 |= 1u << y;
-        (void)dy1;
-      }
-    }
-    b00 |= __shfl_xor(b00, 32, 64);
-    b01 |= __shfl_xor(b01, 32, 64);
-    b11 |= __shfl_xor(b11, 32, 64);
-    b10 |= __shfl_xor(b10, 32, 64);
-  }
-  // masks by slot: lane j < 32 holds slot j's pruners among slots 0..31 (b00)
-  // and 32..63 (transposed from b10); lane 32 + j holds slot 32 + j's from
-  // b01 (0..31) and b11 (32..63). b10 of lane zB has bit y set when zB prunes
-  // y: it is gathered per y below.
-  uint32_t mlo = h == 0 ? b00 : b01;
-  uint32_t mhi = h == 0 ? 0u : b11;
-  if (nv > 32) {
-    // slot y < 32, bit (zB - 32): zB prunes y. Lane zB holds b10 with bit y.
-    uint32_t t = 0;
-    for (int j = 0; j < 32; ++j) {
-      const uint32_t bj = (uint32_t)__builtin_amdgcn_readlane((int)b10, 32 + j);
-      t |= ((bj >> l32) & 1u) << j;
-    }
-    if (h == 0) mhi = t;
-  }
+  rp_finish(g00, g01, g11, nv, l2, alpha, R, x, sD[wave], sN[wave], sK[wave], sI[wave], sS[wave],
+            graph, degree);
+}
 
-  // 4. ranks by (d(x,c), id) and the lazy admission scan (wave-uniform)
-  if (lane < nv) {
-    const uint64_t kt = sK[wave][lane];
-    int rank = 0;
-    for (int u = 0; u < nv; ++u) rank += sK[wave][u] < kt ? 1 : 0;
-    sS[wave][rank] = (uint32_t)lane;
+// The same RobustPrune reading a 16-bit operand (the index's bf16 / fp16
+// copy, n x DP, zero padded) when that copy holds X exactly: the rows are
+// half the bytes, d(x,c) is the same FP32 direct difference (of the same
+// values, in the same order), and the Gram runs on v_mfma_f32_32x32x16 with
+// FP32 accumulation of exact products, so where those sums are exact
+// (integer data) every decision is the float32 kernel's.
+template <int PREC, int DP>
+__global__ void __launch_bounds__(64 * kRpWaves) robustprune_mfma16_kernel(
+    const uint8_t *__restrict__ Xop, const float *__restrict__ norms, int64_t n, int metric,
+    const uint64_t *__restrict__ res, int l_max, float alpha, int R,
+    const uint32_t *__restrict__ order, int64_t n_items, uint32_t *__restrict__ graph,
+    uint32_t *__restrict__ degree) {
+  constexpr int HALF = DP / 2;
+  constexpr int NA = HALF / 8;        // 16-byte vectors (8 values) per lane
+  constexpr int CB = DP * 2;          // bytes per operand row
+  __shared__ uint64_t sK[kRpWaves][64];
+  __shared__ float sD[kRpWaves][64];
+  __shared__ float sN[kRpWaves][64];
+  __shared__ uint32_t sI[kRpWaves][64];
+  __shared__ uint32_t sS[kRpWaves][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int h = lane >> 5, l32 = lane & 31;
+  const int64_t item = (int64_t)xcd_item(blockIdx.x, gridDim.x) * kRpWaves + wave;
+  if (item >= n_items) return;
+  const uint32_t x = __builtin_amdgcn_readfirstlane(order ? order[item] : (uint32_t)item);
+  const bool l2 = metric == PIPNN_METRIC_L2;
+
+  int nv;
+  {
+    uint32_t c = kEmptyId;
+    if (lane < l_max) c = slot_id(res[(int64_t)x * l_max + lane]);
+    const bool ok = lane < l_max && c != kEmptyId && c != x && c < n;
+    const uint64_t m = __ballot(ok);
+    nv = __popcll(m);
+    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    if (ok) sI[wave][__popcll(m & below)] = c;
   }
   wave_sync();
-  const int my_slot = lane < nv ? (int)sS[wave][lane] : 0;  // slot at sorted position lane
-  uint64_t adm = 0;
-  int ne = 0;
-  uint32_t my_id = kEmptyId;
-  for (int p = 0; p < nv && ne < R; ++p) {
-    const int z = __builtin_amdgcn_readlane(my_slot, p);
-    // readlane returns int: widen through uint32_t so bit 31 does not sign-extend
-    const uint64_t mz = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)mhi, z) << 32) |
-                        (uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)mlo, z);
-    if ((mz & adm) == 0) {
-      adm |= 1ull << z;
-      if (lane == ne) my_id = sI[wave][z];
-      ++ne;
+
+  auto val = [](uint32_t code) -> float {
+    if constexpr (PREC == PIPNN_PREC_BF16) return __uint_as_float(code << 16);
+    else return (float)__builtin_bit_cast(_Float16, (uint16_t)code);
+  };
+  uint4 a0[NA], a1[NA];
+  float s0 = 0.f, s1 = 0.f;
+  {
+    const bool v0 = l32 < nv, v1 = 32 + l32 < nv;
+    const uint32_t c0 = v0 ? sI[wave][l32] : x, c1 = v1 ? sI[wave][32 + l32] : x;
+    const uint4 *r0 = reinterpret_cast<const uint4 *>(Xop + (int64_t)c0 * CB + h * HALF * 2);
+    const uint4 *r1 = reinterpret_cast<const uint4 *>(Xop + (int64_t)c1 * CB + h * HALF * 2);
+    const uint4 *rx = reinterpret_cast<const uint4 *>(Xop + (int64_t)x * CB + h * HALF * 2);
+#pragma unroll
+    for (int sv = 0; sv < NA; ++sv) {
+      const uint4 q0 = r0[sv], q1 = r1[sv], qx = rx[sv];
+      a0[sv] = q0;
+      a1[sv] = q1;
+      const uint32_t w0[4] = {q0.x, q0.y, q0.z, q0.w}, w1[4] = {q1.x, q1.y, q1.z, q1.w};
+      const uint32_t wx[4] = {qx.x, qx.y, qx.z, qx.w};
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const float c0v = val((w0[e >> 1] >> (16 * (e & 1))) & 0xFFFFu);
+        const float c1v = val((w1[e >> 1] >> (16 * (e & 1))) & 0xFFFFu);
+        const float xv = val((wx[e >> 1] >> (16 * (e & 1))) & 0xFFFFu);
+        if (l2) {
+          const float t0 = c0v - xv, t1 = c1v - xv;
+          s0 = fmaf(t0, t0, s0);
+          s1 = fmaf(t1, t1, s1);
+        } else {
+          s0 = fmaf(c0v, xv, s0);
+          s1 = fmaf(c1v, xv, s1);
+        }
+      }
+    }
+    if (!v0) {
+#pragma unroll
+      for (int sv = 0; sv < NA; ++sv) a0[sv] = make_uint4(0u, 0u, 0u, 0u);
+    }
+    if (!v1) {
+#pragma unroll
+      for (int sv = 0; sv < NA; ++sv) a1[sv] = make_uint4(0u, 0u, 0u, 0u);
+    }
+    const float o0 = __shfl_xor(s0, 32, 64), o1 = __shfl_xor(s1, 32, 64);
+    const float t0 = h == 0 ? s0 + o0 : o0 + s0, t1 = h == 0 ? s1 + o1 : o1 + s1;
+    const float dx0 = l2 ? t0 : -t0, dx1 = l2 ? t1 : -t1;
+    const float dxm = h == 0 ? dx0 : dx1;
+    const int slot = lane;
+    if (slot < nv) {
+      const uint32_t cid = sI[wave][slot];
+      sD[wave][slot] = dxm;
+      sN[wave][slot] = l2 ? norms[cid] : 0.f;
+      sK[wave][slot] = ((uint64_t)f32_rank(dxm) << 32) | cid;
     }
   }
-  uint32_t *grow = graph + (int64_t)x * R;
-  for (int i = lane; i < R; i += 64) grow[i] = i < ne ? (i == lane ? my_id : kEmptyId) : kEmptyId;
-  if (lane == 0) degree[x] = (uint32_t)ne;
+  wave_sync();
+  typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+  typedef _Float16 f16x8_t __attribute__((ext_vector_type(8)));
+  auto mm = [](uint4 p, uint4 q, f32x16 acc) -> f32x16 {
+    if constexpr (PREC == PIPNN_PREC_BF16)
+      return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8_t, p),
+                                                      __builtin_bit_cast(bf16x8_t, q), acc, 0, 0, 0);
+    else
+      return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8_t, p),
+                                                     __builtin_bit_cast(f16x8_t, q), acc, 0, 0, 0);
+  };
+  f32x16 g00, g01, g11;
+#pragma unroll
+  for (int v = 0; v < 16; ++v) { g00[v] = 0.f; g01[v] = 0.f; g11[v] = 0.f; }
+#pragma unroll
+  for (int sv = 0; sv < NA; ++sv) g00 = mm(a0[sv], a0[sv], g00);
+  if (nv > 32) {
+#pragma unroll
+    for (int sv = 0; sv < NA; ++sv) {
+      g01 = mm(a0[sv], a1[sv], g01);
+      g11 = mm(a1[sv], a1[sv], g11);
+    }
+  }
+  rp_finish(g00, g01, g11, nv, l2, alpha, R, x, sD[wave], sN[wave], sK[wave], sI[wave], sS[wave],
+            graph, degree);
 }
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
@@ -531,6 +665,24 @@ hipError_t launch_robustprune(const Index &I, const uint64_t *res, uint32_t *gra
       subset ? subset : (I.rp_order_valid ? I.rp_order.as<uint32_t>() : nullptr);
   const int64_t n_items = subset ? n_subset : I.n;
   if (n_items <= 0) return hipSuccess;
+  const bool op16 = (I.p.gemm_prec == PIPNN_PREC_BF16 || I.p.gemm_prec == PIPNN_PREC_FP16) &&
+                    I.op_exact && I.xlow.p;
+  if (I.p.l_max <= 64 && op16 && (I.ldo == 64 || I.ldo == 96 || I.ldo == 128)) {
+    const int64_t blocks = xcd_grid((n_items + kRpWaves - 1) / kRpWaves);
+    auto go = [&](auto kern) {
+      hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(64 * kRpWaves), 0, s,
+                         I.xlow.as<uint8_t>(), I.norms.as<float>(), I.n, I.p.metric, res,
+                         I.p.l_max, I.p.alpha, I.p.R, order, n_items, graph, degree);
+    };
+    const bool b = I.p.gemm_prec == PIPNN_PREC_BF16;
+    if (I.ldo == 64) b ? go(robustprune_mfma16_kernel<PIPNN_PREC_BF16, 64>)
+                       : go(robustprune_mfma16_kernel<PIPNN_PREC_FP16, 64>);
+    else if (I.ldo == 96) b ? go(robustprune_mfma16_kernel<PIPNN_PREC_BF16, 96>)
+                            : go(robustprune_mfma16_kernel<PIPNN_PREC_FP16, 96>);
+    else b ? go(robustprune_mfma16_kernel<PIPNN_PREC_BF16, 128>)
+           : go(robustprune_mfma16_kernel<PIPNN_PREC_FP16, 128>);
+    return hipGetLastError();
+  }
   if (I.p.l_max <= 64 && I.d <= 128) {
     const int64_t blocks = xcd_grid((n_items + kRpWaves - 1) / kRpWaves);
     auto args = [&](auto kern) {

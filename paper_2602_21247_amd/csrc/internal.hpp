@@ -35,6 +35,8 @@ struct Index {
   DevBuf xlow;      // low-precision copy for the leaf GEMM (bf16 / fp16 / fp8)
   DevBuf xscale;    // per-point fp8 decode scale (value = code * scale)
   DevBuf lnorms;    // n float32, squared norms of the decoded low-precision operand
+  DevBuf op_flag;   // int32: set by the encoder when a value does not survive encoding
+  bool op_exact = false;  // the reduced-precision operand holds X exactly
   int32_t ldo = 0;  // row stride (elements) of xlow: d padded by lowp_padded_dim
   DevBuf xpad;      // float32 GEMM operand zero padded to ldf, when X itself cannot serve
   int32_t ldf = 0;  // row stride (floats) of the float32 GEMM operand; 0: d > 256
@@ -172,6 +174,11 @@ hipError_t launch_quantize(const Index &I, hipStream_t s);
 // the same for points [p0, p0 + cnt) only
 hipError_t launch_norms_sketches_range(const Index &I, int64_t p0, int64_t cnt, hipStream_t s);
 hipError_t launch_quantize_range(const Index &I, int64_t p0, int64_t cnt, hipStream_t s);
+// Clear the encoder's inexact flag (a fill kernel, so it may be captured),
+// and, outside capture, read it back into I.op_exact (synchronizes s):
+// `reset` clears op_exact first for a full re-encode.
+hipError_t clear_op_flag(Index &I, hipStream_t s);
+hipError_t read_op_flag(Index &I, bool reset, hipStream_t s);
 // Rows [p0, p0 + cnt) of the zero-padded float32 operand I.xpad.
 hipError_t launch_pad_range(const Index &I, int64_t p0, int64_t cnt, hipStream_t s);
 // leaf table: offsets rebased to 0, member copy, one representative per leaf

@@ -551,8 +551,9 @@ static hipError_t launch_knn_quad(KnnArgs args, int n_items, int n_cu, hipStream
   return hipGetLastError();
 }
 
-// Selection sizes built for each layout: 4 (the partition's nearest
-// leaders, FP32 operand only), 16 and 32.
+// Selection sizes built: 4 (the partition's nearest leaders; two-lane
+// layout for the reduced-precision operands, both layouts for float32), 16
+// and 32.
 template <int PREC, int DP>
 static hipError_t launch_knn_quad_k(const KnnArgs &a, int ksel, int n_items, int n_cu,
                                     hipStream_t s) {
@@ -577,6 +578,7 @@ static hipError_t launch_knn_lowp(const KnnArgs &a, int ksel, int n_items, int n
       if (quad && nw == 4) return launch_knn_quad_k<PREC, DPV>(a, ksel, n_items, n_cu, s); \
     }                                                                                    \
     if (quad) return hipErrorInvalidValue;                                               \
+    if (ksel <= 4) return launch_knn_shape<PREC, DPV, 4>(a, n_items, nw, n_cu, s);       \
     return k32 ? launch_knn_shape<PREC, DPV, 32>(a, n_items, nw, n_cu, s)                \
                : launch_knn_shape<PREC, DPV, 16>(a, n_items, nw, n_cu, s);
   switch (a.ldo) {

@@ -103,7 +103,8 @@ __device__ __forceinline__ float dec_e4m3(uint32_t c) {
 __global__ void __launch_bounds__(256) quantize_kernel(const float *__restrict__ X, int64_t n, int d,
                                                        int ldo, int prec, void *out,
                                                        float *__restrict__ scale,
-                                                       float *__restrict__ norms) {
+                                                       float *__restrict__ norms,
+                                                       int *__restrict__ inexact) {
   const int lane = threadIdx.x & 63;
   const int64_t p = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (p >= n) return;
@@ -121,6 +122,7 @@ __global__ void __launch_bounds__(256) quantize_kernel(const float *__restrict__
     if (lane == 0) scale[p] = inv;
   }
   float nn = 0.f;
+  bool lossy = false;
   for (int i = lane; i < ldo; i += 64) {
     const float v = i < d ? x[i] : 0.f;
     float q;
@@ -138,9 +140,13 @@ __global__ void __launch_bounds__(256) quantize_kernel(const float *__restrict__
       q = dec_e4m3(c) * inv;
     }
     nn = fmaf(q, q, nn);
+    lossy |= q != v;
   }
   nn = wave_sum(nn);
   if (lane == 0) norms[p] = nn;
+  // every writer stores the same 1, so no read-modify-write is needed; a
+  // wave that already sees the flag set skips the store
+  if (__ballot(lossy) != 0ull && lane == 0 && *(volatile int *)inexact == 0) *inexact = 1;
 }
 
 // One thread per 16-byte chunk of the padded rows: float32 values, zeros
@@ -181,8 +187,23 @@ hipError_t launch_quantize_range(const Index &I, int64_t p0, int64_t cnt, hipStr
   hipLaunchKernelGGL(quantize_kernel, dim3((unsigned)blocks), dim3(256), 0, s, I.xf() + p0 * I.d,
                      cnt, I.d, I.ldo, I.p.gemm_prec,
                      reinterpret_cast<void *>(I.xlow.as<uint8_t>() + p0 * I.ldo * eb),
-                     I.xscale.as<float>() + p0, I.lnorms.as<float>() + p0);
+                     I.xscale.as<float>() + p0, I.lnorms.as<float>() + p0, I.op_flag.as<int>());
   return hipGetLastError();
+}
+
+hipError_t clear_op_flag(Index &I, hipStream_t s) {
+  return launch_fill_u32(I.op_flag.as<uint32_t>(), 0u, 1, s);
+}
+
+hipError_t read_op_flag(Index &I, bool reset, hipStream_t s) {
+  if (reset) I.op_exact = false;
+  int32_t f = 1;
+  hipError_t e = hipMemcpyAsync(&f, I.op_flag.p, 4, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return e;
+  if (reset) I.op_exact = f == 0;
+  else if (f != 0) I.op_exact = false;
+  return hipSuccess;
 }
 
 // ---- leaf table of an index (kept for insertion) ------------------------

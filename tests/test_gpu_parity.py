@@ -360,6 +360,36 @@ def test_build_order_independence(exact_build):
     idx.close()
 
 
+@pytest.mark.parametrize("prec", ["bf16", "fp16"])
+def test_exact_16bit_operand_build(exact_build, prec):
+    """Integer features of at most 8 significant bits survive bf16 / fp16
+    encoding, so the 16-bit copy holds X exactly: the partition reads the
+    copy, the leaf GEMM multiplies it, RobustPrune loads its rows from it,
+    and the whole build is still the oracle's bit for bit. A copy that does
+    not hold X (the same data plus 1/3) keeps the float32 paths."""
+    X, H, p, ref = exact_build
+    code = {"bf16": pp.PREC_BF16, "fp16": pp.PREC_FP16}[prec]
+    kw = {f: getattr(p, f) for f in ("c_max", "c_min", "k", "l_max", "R", "seed")}
+    p16 = gpu_params(gemm_prec=code, **kw)
+    idx, off, mem, res, g, deg = pp.build(dev(X), dev(H), p16)
+    torch.cuda.synchronize()
+    assert idx.stats()["operand_exact"] == 1
+    assert leaf_sets(off.cpu().numpy(), mem.cpu().numpy()) == leaf_sets(ref["offsets"],
+                                                                         ref["members"])
+    assert np.array_equal(u64(res), ref["reservoirs"])
+    assert np.array_equal(u32(g), ref["graph"])
+    assert np.array_equal(u32(deg), ref["degree"])
+    # RobustPrune alone on the oracle's reservoirs
+    g2, deg2 = idx.robustprune(dev(ref["reservoirs"]))
+    torch.cuda.synchronize()
+    assert np.array_equal(u32(g2), ref["graph"])
+    idx.close()
+    Xf = (X + np.float32(1.0 / 3.0)).astype(np.float32)
+    idx = pp.Index(dev(Xf), dev(H), p16)
+    assert idx.stats()["operand_exact"] == 0
+    idx.close()
+
+
 def test_robustprune_exact_on_oracle_reservoirs(exact_build):
     X, H, p, ref = exact_build
     idx = pp.Index(dev(X), dev(H), p)
