@@ -158,10 +158,10 @@ __device__ __forceinline__ int acc_row32(int v, int h) { return (v & 3) + 8 * (v
 //     of z's 64-bit mask is set when alpha*d(y,z) < d(x,z) (sign of a fused
 //     multiply-add);
 //  4. the candidates ranked by (d(x,c), id) by counting, and the lazy scan in
-//     that order: z is admitted iff its mask has no admitted bit, until R are
-//     admitted. Admitted candidates all come before z in the order, so the
-//     mask may hold later ones too. This admits exactly the candidates of
-//     Alg. 2.
+//     that order -- z is admitted iff no admitted candidate ranked before it
+//     prunes it, the first R admitted kept -- run as rounds over the whole
+//     wave on the masks restricted to earlier candidates. This admits exactly
+//     the candidates of Alg. 2.
 // Steps 3 and 4 of the MFMA RobustPrune described above, shared by its operand forms:
 // from the Gram blocks and the per-slot d(x,c), norms and ranking keys in
 // LDS to the admitted neighbours of x.
@@ -221,35 +221,60 @@ __device__ __forceinline__ void rp_finish(const f32x16 &g00, const f32x16 &g01, 
     if (h == 0) mhi = t;
   }
 
-  // 4. ranks by (d(x,c), id) and the lazy admission scan (wave-uniform)
+  // 4. ranks by (d(x,c), id) by counting
+  int my_rank = 64;
   if (lane < nv) {
     const uint64_t kt = sKw[lane];
     int rank = 0;
     for (int u = 0; u < nv; ++u) rank += sKw[u] < kt ? 1 : 0;
     sSw[rank] = (uint32_t)lane;
+    my_rank = rank;
   }
   wave_sync();
-  const int my_slot = lane < nv ? (int)sSw[lane] : 0;  // slot at sorted position lane
-  uint64_t adm = 0;
-  int ne = 0;
-  uint32_t my_id = kEmptyId;
-  for (int p = 0; p < nv && ne < R; ++p) {
-    const int z = __builtin_amdgcn_readlane(my_slot, p);
-    // readlane returns int: widen through uint32_t so bit 31 does not sign-extend
-    const uint64_t mz = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)mhi, z) << 32) |
-                        (uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)mlo, z);
-    if ((mz & adm) == 0) {
-      adm |= 1ull << z;
-      if (lane == ne) my_id = sIw[z];
-      ++ne;
-    }
+  auto shfl64 = [](uint64_t v, int src) -> uint64_t {
+    const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)v, src, 64);
+    const uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(v >> 32), src, 64);
+    return ((uint64_t)hi << 32) | lo;
+  };
+  // slots ranked before each slot: a prefix OR over the sorted positions
+  // (position q contributes its slot's bit), read back at the slot's rank
+  uint64_t pre = lane < nv ? (1ull << sSw[lane]) : 0ull;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint64_t o = shfl64(pre, lane >= off ? lane - off : lane);
+    if (lane >= off) pre |= o;
   }
+  uint64_t excl = shfl64(pre, lane > 0 ? lane - 1 : 0);
+  if (lane == 0) excl = 0ull;
+  const uint64_t before = lane < nv ? shfl64(excl, my_rank < 64 ? my_rank : 0) : 0ull;
+  // the lazy scan of Alg. 2 in rounds: a candidate is admitted once none of
+  // its earlier pruners is admitted or undecided, rejected once one of them
+  // is admitted; each round decides at least the earliest undecided one, and
+  // the outcome is the sequential scan's
+  const uint64_t pr = (((uint64_t)mhi << 32) | mlo) & before;
+  uint64_t adm = 0ull, und = nv >= 64 ? ~0ull : ((1ull << nv) - 1ull);
+  while (und != 0ull) {
+    const bool u = (und >> lane) & 1ull;
+    const bool rej = u && (pr & adm) != 0ull;
+    const bool ok = u && !rej && (pr & und) == 0ull;
+    const uint64_t ma = __ballot(ok), mr = __ballot(rej);
+    adm |= ma;
+    und &= ~(ma | mr);
+  }
+  // the first R admitted in rank order
+  const int na = __popcll(adm);
+  const int ne = na < R ? na : R;
   uint32_t *grow = graph + (int64_t)x * R;
-  for (int i = lane; i < R; i += 64) grow[i] = i < ne ? (i == lane ? my_id : kEmptyId) : kEmptyId;
-  if (lane == 0) degree[x] = (uint32_t)ne;}
+  if (lane < nv && ((adm >> lane) & 1ull)) {
+    const int pos = __popcll(adm & before);
+    if (pos < R) grow[pos] = sIw[lane];
+  }
+  for (int i = ne + lane; i < R; i += 64) grow[i] = kEmptyId;
+  if (lane == 0) degree[x] = (uint32_t)ne;
+}
 
 template <int DP>
-__global__ void __launch_bounds__(64 * kRpWaves) robustprune_mfma_kernel(
+__global__ void __launch_bounds__(64 * kRpWaves, 4) robustprune_mfma_kernel(
     const float *__restrict__ X, const float *__restrict__ norms, int64_t n, int d, int metric,
     const uint64_t *__restrict__ res, int l_max, float alpha, int R,
     const uint32_t *__restrict__ order, int64_t n_items, uint32_t *__restrict__ graph,
@@ -281,8 +306,15 @@ __global__ void __launch_bounds__(64 * kRpWaves) robustprune_mfma_kernel(
   }
   wave_sync();
 
-  // 2. fragments F0 (slots 0..31) and F1 (slots 32..63); d(x, c) from them
-  float f0[HALF], f1[HALF];
+  // 2. fragments F0 (slots 0..31) and F1 (slots 32..63), taken CH
+  //    dimensions of each half at a time: each chunk's rows feed the direct
+  //    sums for d(x, c) (continued in index order) and the Gram's MFMAs (in
+  //    the same k order as whole rows would), so only one chunk is live
+  constexpr int CH = HALF < 16 ? HALF : 16;
+  static_assert(HALF % CH == 0, "chunking");
+  f32x16 g00, g01, g11;
+#pragma unroll
+  for (int v = 0; v < 16; ++v) { g00[v] = 0.f; g01[v] = 0.f; g11[v] = 0.f; }
   float s0 = 0.f, s1 = 0.f;
   {
     const int kb = h * HALF;
@@ -291,54 +323,55 @@ __global__ void __launch_bounds__(64 * kRpWaves) robustprune_mfma_kernel(
     const float *r0 = X + (int64_t)c0 * d + kb;
     const float *r1 = X + (int64_t)c1 * d + kb;
     const float *rx = X + (int64_t)x * d + kb;
-    if (full_d) {
+    const bool both = nv > 32;
+#pragma unroll 2
+    for (int k0 = 0; k0 < HALF; k0 += CH) {
+      float f0[CH], f1[CH], fx[CH];
+      if (full_d) {
 #pragma unroll
-      for (int kk = 0; kk < HALF; kk += 4) {
-        const float4 q0 = *reinterpret_cast<const float4 *>(r0 + kk);
-        const float4 q1 = *reinterpret_cast<const float4 *>(r1 + kk);
-        const float4 qx = *reinterpret_cast<const float4 *>(rx + kk);
-        f0[kk] = q0.x; f0[kk + 1] = q0.y; f0[kk + 2] = q0.z; f0[kk + 3] = q0.w;
-        f1[kk] = q1.x; f1[kk + 1] = q1.y; f1[kk + 2] = q1.z; f1[kk + 3] = q1.w;
-        if (l2) {
-          float t = q0.x - qx.x; s0 = fmaf(t, t, s0);
-          t = q0.y - qx.y; s0 = fmaf(t, t, s0);
-          t = q0.z - qx.z; s0 = fmaf(t, t, s0);
-          t = q0.w - qx.w; s0 = fmaf(t, t, s0);
-          t = q1.x - qx.x; s1 = fmaf(t, t, s1);
-          t = q1.y - qx.y; s1 = fmaf(t, t, s1);
-          t = q1.z - qx.z; s1 = fmaf(t, t, s1);
-          t = q1.w - qx.w; s1 = fmaf(t, t, s1);
-        } else {
-          s0 = fmaf(q0.x, qx.x, s0); s0 = fmaf(q0.y, qx.y, s0);
-          s0 = fmaf(q0.z, qx.z, s0); s0 = fmaf(q0.w, qx.w, s0);
-          s1 = fmaf(q1.x, qx.x, s1); s1 = fmaf(q1.y, qx.y, s1);
-          s1 = fmaf(q1.z, qx.z, s1); s1 = fmaf(q1.w, qx.w, s1);
+        for (int j = 0; j < CH; j += 4) {
+          const float4 q0 = *reinterpret_cast<const float4 *>(r0 + k0 + j);
+          const float4 q1 = *reinterpret_cast<const float4 *>(r1 + k0 + j);
+          const float4 qx = *reinterpret_cast<const float4 *>(rx + k0 + j);
+          f0[j] = q0.x; f0[j + 1] = q0.y; f0[j + 2] = q0.z; f0[j + 3] = q0.w;
+          f1[j] = q1.x; f1[j + 1] = q1.y; f1[j + 2] = q1.z; f1[j + 3] = q1.w;
+          fx[j] = qx.x; fx[j + 1] = qx.y; fx[j + 2] = qx.z; fx[j + 3] = qx.w;
+        }
+      } else {
+#pragma unroll
+        for (int j = 0; j < CH; ++j) {
+          const bool in = kb + k0 + j < d;
+          f0[j] = in ? r0[k0 + j] : 0.f;
+          f1[j] = in ? r1[k0 + j] : 0.f;
+          fx[j] = in ? rx[k0 + j] : 0.f;
         }
       }
-    } else {
 #pragma unroll
-      for (int kk = 0; kk < HALF; ++kk) {
-        const bool in = kb + kk < d;
-        const float a0 = in ? r0[kk] : 0.f, a1 = in ? r1[kk] : 0.f, ax = in ? rx[kk] : 0.f;
-        f0[kk] = a0;
-        f1[kk] = a1;
+      for (int j = 0; j < CH; ++j) {
         if (l2) {
-          const float t0 = a0 - ax, t1 = a1 - ax;
+          const float t0 = f0[j] - fx[j], t1 = f1[j] - fx[j];
           s0 = fmaf(t0, t0, s0);
           s1 = fmaf(t1, t1, s1);
         } else {
-          s0 = fmaf(a0, ax, s0);
-          s1 = fmaf(a1, ax, s1);
+          s0 = fmaf(f0[j], fx[j], s0);
+          s1 = fmaf(f1[j], fx[j], s1);
         }
       }
-    }
-    if (!v0) {
 #pragma unroll
-      for (int kk = 0; kk < HALF; ++kk) f0[kk] = 0.f;
-    }
-    if (!v1) {
+      for (int j = 0; j < CH; ++j) {
+        f0[j] = v0 ? f0[j] : 0.f;
+        f1[j] = v1 ? f1[j] : 0.f;
+      }
 #pragma unroll
-      for (int kk = 0; kk < HALF; ++kk) f1[kk] = 0.f;
+      for (int j = 0; j < CH; ++j)
+        g00 = __builtin_amdgcn_mfma_f32_32x32x2f32(f0[j], f0[j], g00, 0, 0, 0);
+      if (both) {
+#pragma unroll
+        for (int j = 0; j < CH; ++j) {
+          g01 = __builtin_amdgcn_mfma_f32_32x32x2f32(f0[j], f1[j], g01, 0, 0, 0);
+          g11 = __builtin_amdgcn_mfma_f32_32x32x2f32(f1[j], f1[j], g11, 0, 0, 0);
+        }
+      }
     }
     // lower half's sum plus upper half's
     const float o0 = __shfl_xor(s0, 32, 64), o1 = __shfl_xor(s1, 32, 64);
@@ -355,20 +388,6 @@ __global__ void __launch_bounds__(64 * kRpWaves) robustprune_mfma_kernel(
     }
   }
   wave_sync();
-  f32x16 g00, g01, g11;
-#pragma unroll
-  for (int v = 0; v < 16; ++v) { g00[v] = 0.f; g01[v] = 0.f; g11[v] = 0.f; }
-#pragma unroll
-  for (int kk = 0; kk < HALF; ++kk)
-    g00 = __builtin_amdgcn_mfma_f32_32x32x2f32(f0[kk], f0[kk], g00, 0, 0, 0);
-  if (nv > 32) {
-#pragma unroll
-    for (int kk = 0; kk < HALF; ++kk) {
-      g01 = __builtin_amdgcn_mfma_f32_32x32x2f32(f0[kk], f1[kk], g01, 0, 0, 0);
-      g11 = __builtin_amdgcn_mfma_f32_32x32x2f32(f1[kk], f1[kk], g11, 0, 0, 0);
-    }
-  }
-
   rp_finish(g00, g01, g11, nv, l2, alpha, R, x, sD[wave], sN[wave], sK[wave], sI[wave], sS[wave],
             graph, degree);
 }
@@ -380,7 +399,7 @@ __global__ void __launch_bounds__(64 * kRpWaves) robustprune_mfma_kernel(
 // FP32 accumulation of exact products, so where those sums are exact
 // (integer data) every decision is the float32 kernel's.
 template <int PREC, int DP>
-__global__ void __launch_bounds__(64 * kRpWaves) robustprune_mfma16_kernel(
+__global__ void __launch_bounds__(64 * kRpWaves, 4) robustprune_mfma16_kernel(
     const uint8_t *__restrict__ Xop, const float *__restrict__ norms, int64_t n, int metric,
     const uint64_t *__restrict__ res, int l_max, float alpha, int R,
     const uint32_t *__restrict__ order, int64_t n_items, uint32_t *__restrict__ graph,
