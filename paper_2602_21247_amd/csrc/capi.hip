@@ -804,7 +804,7 @@ pipnn_status plan_pick(Index &I, const std::vector<int64_t> &offs, int64_t l0, i
 // one leaf-kernel launch.
 pipnn_status launch_pick(Index &I, const KnnJob *d_jobs, const KnnItem *d_items, int32_t n_items,
                          int32_t max_cols, int64_t rows, const uint32_t *d_members,
-                         uint32_t *pick_c, float *pick_d, hipStream_t s) {
+                         uint32_t *pick_c, float *pick_d, hipStream_t s, bool local = false) {
   const pipnn_params &P = I.p;
   const int ksel = P.rescore_mult ? P.rescore_mult * P.k : P.k;
   HIPCHK(launch_fill_u32(pick_c, kEmptyId, rows * P.k, s));
@@ -820,7 +820,7 @@ pipnn_status launch_pick(Index &I, const KnnJob *d_jobs, const KnnItem *d_items,
   L.max_cols = max_cols;
   L.ksel = ksel;
   L.k_out = P.k;
-  L.out_ids = 1;
+  L.out_ids = local ? 0 : 1;
   L.recompute = gemm_is_direct(I) ? 0 : 1;
   L.rescore_k = P.rescore_mult ? P.k : 0;
   L.prec = P.gemm_prec;
@@ -840,14 +840,15 @@ pipnn_status launch_pick(Index &I, const KnnJob *d_jobs, const KnnItem *d_items,
 
 // Run the pick on leaves [l0, l1) into picks indexed from offs[l0].
 pipnn_status run_pick(Index &I, const std::vector<int64_t> &offs, int64_t l0, int64_t l1,
-                      const uint32_t *d_members, uint32_t *pick_c, float *pick_d, hipStream_t s) {
+                      const uint32_t *d_members, uint32_t *pick_c, float *pick_d, hipStream_t s,
+                      bool local = false) {
   int32_t n_items = 0, max_cols = 0;
   int64_t pairs = 0;
   pipnn_status st = plan_pick(I, offs, l0, l1, I.s_jobs, I.s_items, n_items, max_cols, pairs, s);
   if (st != PIPNN_OK) return st;
   const int64_t rows = offs[(size_t)l1] - offs[(size_t)l0];
   st = launch_pick(I, I.s_jobs.as<KnnJob>(), I.s_items.as<KnnItem>(), n_items, max_cols, rows,
-                   d_members, pick_c, pick_d, s);
+                   d_members, pick_c, pick_d, s, local);
   I.stats.leaf_pairs += pairs;
   return st;
 }
@@ -881,6 +882,39 @@ pipnn_status bin_and_merge(Index &I, bool from_picks, const uint32_t *a, const u
       HIPCHK(launch_rec_scatter(a, b, dist, count, I.sketches.as<float>(), I.m,
                                 I.s_off.as<int64_t>(), I.s_cnt.as<uint32_t>(),
                                 I.s_bins.as<uint64_t>(), n, s));
+  }
+  {
+    PhaseTimer tm(I, kPhMerge, s);
+    HIPCHK(launch_hashprune_merge(res, n, I.p.l_max, I.s_bins.as<uint64_t>(),
+                                  I.s_off.as<int64_t>(), s));
+  }
+  return PIPNN_OK;
+}
+
+// The same for the picks of a batch of leaves written as local column
+// indices (leaves of at most kLeafBinMaxRows rows): leaf-local binning.
+pipnn_status bin_and_merge_leaves(Index &I, const int64_t *d_leaf_off, int64_t off0,
+                                  int64_t n_leaves, const uint32_t *members,
+                                  const uint32_t *picks, const float *dist, int64_t rows,
+                                  int32_t k, uint64_t *res, hipStream_t s) {
+  const int64_t n = I.n;
+  const int64_t max_rec = 2 * rows * k;
+  HIPCHK(I.s_cnt.ensure((size_t)n * 4));
+  HIPCHK(I.s_off.ensure((size_t)(n + 1) * 8));
+  HIPCHK(I.s_tmp0.ensure((size_t)scan_tmp_elems(n) * 8));
+  HIPCHK(I.s_bins.ensure((size_t)std::max<int64_t>(max_rec, 1) * 8));
+  {
+    PhaseTimer tb(I, kPhBin, s);
+    HIPCHK(launch_fill_u32(I.s_cnt.as<uint32_t>(), 0u, n, s));
+    HIPCHK(launch_leaf_bin(false, d_leaf_off, off0, n_leaves, members, picks, dist, k,
+                           I.sketches.as<float>(), I.m, nullptr, I.s_cnt.as<uint32_t>(), nullptr,
+                           s));
+    HIPCHK(launch_scan_u32(I.s_cnt.as<uint32_t>(), I.s_off.as<int64_t>(), n,
+                           I.s_tmp0.as<int64_t>(), s));
+    HIPCHK(launch_fill_u32(I.s_cnt.as<uint32_t>(), 0u, n, s));
+    HIPCHK(launch_leaf_bin(true, d_leaf_off, off0, n_leaves, members, picks, dist, k,
+                           I.sketches.as<float>(), I.m, I.s_off.as<int64_t>(),
+                           I.s_cnt.as<uint32_t>(), I.s_bins.as<uint64_t>(), s));
   }
   {
     PhaseTimer tm(I, kPhMerge, s);
@@ -1065,14 +1099,21 @@ pipnn_status pipnn_build_leaves(pipnn_index *idx, const int64_t *d_leaf_offsets,
     }
     for (size_t i = 0; i < P.batches.size(); ++i) {
       const Index::PlanBatch &B = P.batches[i];
+      const bool local = B.max_cols <= kLeafBinMaxRows;
       st = launch_pick(I, B.jobs.as<KnnJob>(), B.items.as<KnnItem>(), B.n_items, B.max_cols,
                        B.rows, d_leaf_members, I.s_picks_c.as<uint32_t>(),
-                       I.s_picks_d.as<float>(), s);
+                       I.s_picks_d.as<float>(), s, local);
       if (st != PIPNN_OK) return st;
       if (!capturing) I.stats.leaf_pairs += B.pairs;
-      st = bin_and_merge(I, true, d_leaf_members + P.offs[(size_t)B.l0],
-                         I.s_picks_c.as<uint32_t>(), I.s_picks_d.as<float>(), B.rows, k,
-                         d_reservoirs, s);
+      if (local)
+        st = bin_and_merge_leaves(I, d_leaf_offsets + B.l0, P.offs[(size_t)B.l0], B.l1 - B.l0,
+                                  d_leaf_members + P.offs[(size_t)B.l0],
+                                  I.s_picks_c.as<uint32_t>(), I.s_picks_d.as<float>(), B.rows, k,
+                                  d_reservoirs, s);
+      else
+        st = bin_and_merge(I, true, d_leaf_members + P.offs[(size_t)B.l0],
+                           I.s_picks_c.as<uint32_t>(), I.s_picks_d.as<float>(), B.rows, k,
+                           d_reservoirs, s);
       if (st != PIPNN_OK) return st;
       if (!capturing && i + 1 < P.batches.size()) {
         st = finish_bins(I, s, "build_leaves");
@@ -1098,11 +1139,20 @@ pipnn_status pipnn_build_leaves(pipnn_index *idx, const int64_t *d_leaf_offsets,
   for (size_t i = 0; i < batches.size(); ++i) {
     const int64_t l0 = batches[i].first, l1 = batches[i].second;
     const int64_t rows = offs[(size_t)l1] - offs[(size_t)l0];
+    int64_t biggest = 0;
+    for (int64_t l = l0; l < l1; ++l)
+      biggest = std::max<int64_t>(biggest, offs[(size_t)l + 1] - offs[(size_t)l]);
+    const bool local = biggest <= kLeafBinMaxRows;
     st = run_pick(I, offs, l0, l1, d_leaf_members, I.s_picks_c.as<uint32_t>(),
-                  I.s_picks_d.as<float>(), s);
+                  I.s_picks_d.as<float>(), s, local);
     if (st != PIPNN_OK) return st;
-    st = bin_and_merge(I, true, d_leaf_members + offs[(size_t)l0], I.s_picks_c.as<uint32_t>(),
-                       I.s_picks_d.as<float>(), rows, k, d_reservoirs, s);
+    if (local)
+      st = bin_and_merge_leaves(I, d_leaf_offsets + l0, offs[(size_t)l0], l1 - l0,
+                                d_leaf_members + offs[(size_t)l0], I.s_picks_c.as<uint32_t>(),
+                                I.s_picks_d.as<float>(), rows, k, d_reservoirs, s);
+    else
+      st = bin_and_merge(I, true, d_leaf_members + offs[(size_t)l0], I.s_picks_c.as<uint32_t>(),
+                         I.s_picks_d.as<float>(), rows, k, d_reservoirs, s);
     if (st != PIPNN_OK) return st;
     if (i + 1 < batches.size()) {
       st = finish_bins(I, s, "build_leaves");

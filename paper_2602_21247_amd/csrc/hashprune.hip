@@ -110,6 +110,90 @@ __global__ void __launch_bounds__(256) bin_scatter_kernel(const uint32_t *row_id
   bins[pj] = slot_pack(i, hji, bf);
 }
 
+// Leaf-local binning. Every record of a leaf pick joins two members of the
+// same leaf, so one workgroup per leaf can group them in LDS: the forward
+// records of row r are its valid picks, its reverse records the picks of the
+// leaf's other rows that name r. The count pass adds each row's total to its
+// point's count with one global atomic; the scatter pass reserves the row's
+// run of its point's bin with one atomic and writes the run (reverse records
+// first, then forward) at positions taken from LDS counters. Picks are local
+// column indices (kEmptyId or any value >= the leaf size marks an unused
+// pick). The records and their bins are those of the global scheme; only
+// their order inside a bin differs, which the merge does not see.
+
+template <bool SCATTER>
+__global__ void __launch_bounds__(256) leaf_bin_kernel(
+    const int64_t *__restrict__ leaf_off, int64_t off0, const uint32_t *__restrict__ members,
+    const uint32_t *__restrict__ picks, const float *__restrict__ dist, int k,
+    const float *__restrict__ S, int m, const int64_t *__restrict__ bin_off,
+    uint32_t *__restrict__ cnt, uint64_t *__restrict__ bins) {
+  __shared__ uint32_t sF[kLeafBinMaxRows];   // forward records of each row (count, then cursor)
+  __shared__ uint32_t sR[kLeafBinMaxRows];   // reverse records of each row (count, then cursor)
+  __shared__ uint32_t sRn[SCATTER ? kLeafBinMaxRows : 1];  // reverse total of each row
+  __shared__ int64_t sB[SCATTER ? kLeafBinMaxRows : 1];    // the row's first bin position
+  const int64_t r0 = leaf_off[blockIdx.x] - off0;
+  const int mm = (int)(leaf_off[blockIdx.x + 1] - off0 - r0);
+  const int tid = threadIdx.x;
+  for (int r = tid; r < mm; r += 256) {
+    sF[r] = 0u;
+    sR[r] = 0u;
+  }
+  __syncthreads();
+  const int tot = mm * k;
+  for (int t = tid; t < tot; t += 256) {
+    const int r = t / k;
+    const uint32_t c = picks[(r0 + r) * k + (t - r * k)];
+    if (c < (uint32_t)mm && c != (uint32_t)r) {
+      atomicAdd(&sF[r], 1u);
+      atomicAdd(&sR[c], 1u);
+    }
+  }
+  __syncthreads();
+  if constexpr (!SCATTER) {
+    for (int r = tid; r < mm; r += 256) {
+      const uint32_t n_r = sF[r] + sR[r];
+      if (n_r) atomicAdd(&cnt[members[r0 + r]], n_r);
+    }
+  } else {
+    for (int r = tid; r < mm; r += 256) {
+      const uint32_t n_r = sF[r] + sR[r];
+      const uint32_t p = members[r0 + r];
+      sRn[r] = sR[r];
+      sB[r] = n_r ? bin_off[p] + atomicAdd(&cnt[p], n_r) : 0;
+    }
+    __syncthreads();
+    for (int t = tid; t < tot; t += 256) {
+      const int r = t / k;
+      const int64_t g = (r0 + r) * k + (t - r * k);
+      const uint32_t c = picks[g];
+      if (c < (uint32_t)mm && c != (uint32_t)r) {
+        const uint32_t i = members[r0 + r], j = members[r0 + c];
+        uint32_t hij, hji;
+        hash_pair(S, m, i, j, hij, hji);
+        const uint32_t bf = bf16_rne(dist[g]);
+        const uint32_t pf = atomicSub(&sF[r], 1u) - 1u;
+        bins[sB[r] + sRn[r] + pf] = slot_pack(j, hij, bf);
+        const uint32_t pr = atomicSub(&sR[c], 1u) - 1u;
+        bins[sB[c] + pr] = slot_pack(i, hji, bf);
+      }
+    }
+  }
+}
+
+hipError_t launch_leaf_bin(bool scatter, const int64_t *leaf_off, int64_t off0, int64_t n_leaves,
+                           const uint32_t *members, const uint32_t *picks, const float *dist,
+                           int32_t k, const float *sketch, int32_t m, const int64_t *bin_off,
+                           uint32_t *cnt, uint64_t *bins, hipStream_t s) {
+  if (n_leaves <= 0) return hipSuccess;
+  if (scatter)
+    hipLaunchKernelGGL(leaf_bin_kernel<true>, dim3((unsigned)n_leaves), dim3(256), 0, s, leaf_off,
+                       off0, members, picks, dist, k, sketch, m, bin_off, cnt, bins);
+  else
+    hipLaunchKernelGGL(leaf_bin_kernel<false>, dim3((unsigned)n_leaves), dim3(256), 0, s, leaf_off,
+                       off0, members, picks, dist, k, sketch, m, bin_off, cnt, bins);
+  return hipGetLastError();
+}
+
 hipError_t launch_bin_count(const uint32_t *row_ids, const uint32_t *picks, int64_t n_rows,
                             int32_t k, uint32_t *cnt, int64_t n, int32_t *flag, hipStream_t s) {
   const int64_t tot = n_rows * k;

@@ -231,6 +231,15 @@ hipError_t launch_copy_segments(const uint32_t *const *src, const int64_t *dst_o
                                 const int32_t *len, int32_t n_segs, uint32_t *dst, hipStream_t s);
 
 // ---- HashPrune -------------------------------------------------------
+// Leaf-local binning of the picks of leaves [0, n_leaves) of a batch
+// (leaf_off: their absolute offsets, off0 the batch's first row; picks as
+// local column indices): count pass (scatter = false: adds to cnt) or
+// scatter pass (cnt as the per-point cursor, bins at bin_off).
+constexpr int kLeafBinMaxRows = 4096;
+hipError_t launch_leaf_bin(bool scatter, const int64_t *leaf_off, int64_t off0, int64_t n_leaves,
+                           const uint32_t *members, const uint32_t *picks, const float *dist,
+                           int32_t k, const float *sketch, int32_t m, const int64_t *bin_off,
+                           uint32_t *cnt, uint64_t *bins, hipStream_t s);
 hipError_t launch_bin_count(const uint32_t *row_ids, const uint32_t *picks, int64_t n_rows,
                             int32_t k, uint32_t *cnt, int64_t n, int32_t *flag, hipStream_t s);
 hipError_t launch_bin_scatter(const uint32_t *row_ids, const uint32_t *picks, const float *dist,
