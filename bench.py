@@ -100,6 +100,11 @@ def ground_truth(torch, Xd, Qd, metric=0, k=10):
     return kth
 
 
+# the sources of the float32 leaf kernel (four-lane layout) the committed
+# counter runs were taken on
+LEAF_KERNEL_SOURCES = ("knn_kernel.hpp", "knn_quad.hpp", "knn_fp32q.hip", "knn.hip")
+
+
 def traffic_from_profiles():
     """HBM bytes per leaf-kernel launch from committed counter runs, if they
     were taken on the current kernel source."""
@@ -108,7 +113,7 @@ def traffic_from_profiles():
     try:
         rec = json.load(open(path))
         h = hashlib.sha256(b"".join(open(os.path.join(csrc, f), "rb").read()
-                                    for f in ("knn_kernel.hpp", "knn.hip"))).hexdigest()
+                                    for f in LEAF_KERNEL_SOURCES)).hexdigest()
         if rec.get("knn_hip_sha256") != h:
             return None
         return rec.get("bytes_per_launch")
