@@ -350,7 +350,7 @@ def main():
 
     leaves = None
     if cfg == 4:
-        lo, lm = pi.workload_leaves(cfg, n)
+        lo, lm = pi.workload_leaves(cfg, n, X=X)
         leaves = (torch.from_numpy(lo).cuda(), torch.from_numpy(lm.view(np.int32)).cuda())
         log(f"[bench] explicit leaves: {len(lo) - 1}, sizes {np.diff(lo).min()}..{np.diff(lo).max()}")
 

@@ -219,21 +219,54 @@ def mixture_labels(cfg: int, n: int) -> np.ndarray:
     return _rng(4 + 7919).integers(0, 200, size=n)
 
 
-def workload_leaves(cfg: int, n: int | None = None) -> tuple[np.ndarray, np.ndarray]:
+def rp_tree_order(X: np.ndarray, seed: int, leaf: int = 32) -> np.ndarray:
+    """An ordering of the rows of X in which nearby points sit close: a
+    random-projection tree (one random direction per level, every segment
+    longer than ``leaf`` split at its median projection), read in order."""
+    rng = _rng(seed)
+    n, d = X.shape
+    idx = np.arange(n, dtype=np.int64)
+    start = np.zeros(n, dtype=np.int64)     # first position of each position's segment
+    length = np.full(n, n, dtype=np.int64)  # its length
+    pos = np.arange(n, dtype=np.int64)
+    X32 = X if X.dtype == np.float32 else X.astype(np.float32)
+    while length.max() > leaf:
+        u = rng.standard_normal(d).astype(np.float32)
+        proj = X32 @ u
+        # sort every segment by projection (segments stay in place)
+        idx = idx[np.lexsort((proj[idx], start))]
+        split = length > leaf
+        half = length // 2
+        upper = split & (pos - start >= half)
+        new_start = np.where(upper, start + half, start)
+        new_len = np.where(split, np.where(upper, length - half, half), length)
+        start, length = new_start, new_len
+    return idx
+
+
+def workload_leaves(cfg: int, n: int | None = None,
+                    X: np.ndarray | None = None) -> tuple[np.ndarray, np.ndarray]:
     """Explicit uneven leaves of workload 4 (every point in two leaves): two
-    independent orderings of the points by (mixture component, random key),
-    each cut into consecutive chunks of truncated-Zipf(1.2) sizes on
-    64..4096; members ascending within a leaf. Returns one CSR over both."""
+    orderings of the points, each cut into consecutive chunks of
+    truncated-Zipf(1.2) sizes on 64..4096; members ascending within a leaf.
+    The first ordering keeps each mixture component together and orders it
+    by a random-projection tree; the second is a random-projection tree over
+    all points, so leaves also join nearby points of different components.
+    Returns one CSR over both. ``X``: the workload's points if already made."""
     if cfg != 4:
         raise ValueError("explicit leaves are defined for workload 4 only")
     w = WORKLOADS[cfg]
     nn = w.n if n is None else n
+    if X is None:
+        X = workload_points(cfg, nn)
     labels = mixture_labels(cfg, nn)
     offs, mems = [], []
     base = 0
     for j in range(2):
-        key = _rng(4100 + j).random(nn)
-        order = np.lexsort((key, labels)).astype(np.uint32)
+        tree = rp_tree_order(X, 4100 + j)
+        rank = np.empty(nn, dtype=np.int64)
+        rank[tree] = np.arange(nn)
+        order = (np.lexsort((rank, labels)) if j == 0 else tree).astype(np.uint32)
         o, m = zipf_leaves(nn, order, 64, 4096, 1.2, seed=4200 + j)
         offs.append(o[:-1] + base if j == 0 else o + base)
         mems.append(m)

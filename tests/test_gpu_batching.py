@@ -60,7 +60,7 @@ def wide_params(**kw):
 def wide():
     n = 8000
     X16 = pi.workload_points(4, n)
-    off, mem = pi.workload_leaves(4, n)
+    off, mem = pi.workload_leaves(4, n, X=X16)
     H = pi.workload_hyperplanes(4)
     return X16, H, off, mem
 
