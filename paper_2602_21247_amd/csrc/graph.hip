@@ -591,17 +591,34 @@ __global__ void __launch_bounds__(256, 1) robustprune_wide_kernel(
   for (int p2 = 0; p2 < NP; ++p2) acc[p2] = f32x4{0.f, 0.f, 0.f, 0.f};
   uint16_t *stg = reinterpret_cast<uint16_t *>(W);
   const int q = lane >> 4, l16 = lane & 15;
-  for (int ch = 0; ch < NCHUNK; ++ch) {
-    // stage rows [0, 16*NB) x dims [ch*KC, ch*KC + KC): 8 pieces of 16 bytes per row
-    for (int pc = lane; pc < 16 * NB * 8; pc += 64) {
+  // Staging of rows [0, 16*NB) x dims [ch*KC, ch*KC + KC), 8 pieces of 16
+  // bytes per row, lane-strided: piece pc = lane + 64 i. The pieces of chunk
+  // ch + 1 are loaded into registers while chunk ch's MFMAs run.
+  constexpr int NPC = kRpwRows * 8 / 64;  // pieces per lane at most (14)
+  const int npc = 16 * NB * 8;
+  uint4 nxt[NPC];
+  auto load_chunk = [&](int ch) {
+#pragma unroll
+    for (int i = 0; i < NPC; ++i) {
+      const int pc = lane + 64 * i;
       const int r = pc >> 3, part = pc & 7;
       uint4 v = make_uint4(0u, 0u, 0u, 0u);
-      if (r < rows)
+      if (pc < npc && r < rows)
         v = *reinterpret_cast<const uint4 *>(Xop + (int64_t)ids[r] * op_ld +
                                              (int64_t)(ch * kRpwKC + part * 8) * 2);
-      *reinterpret_cast<uint4 *>(&stg[r * LROW + part * 8]) = v;
+      nxt[i] = v;
+    }
+  };
+  load_chunk(0);
+  for (int ch = 0; ch < NCHUNK; ++ch) {
+#pragma unroll
+    for (int i = 0; i < NPC; ++i) {
+      const int pc = lane + 64 * i;
+      const int r = pc >> 3, part = pc & 7;
+      if (pc < npc) *reinterpret_cast<uint4 *>(&stg[r * LROW + part * 8]) = nxt[i];
     }
     wave_sync();
+    if (ch + 1 < NCHUNK) load_chunk(ch + 1);
 #pragma unroll
     for (int st = 0; st < kRpwKC / 32; ++st) {
       uint4 f[7];
