@@ -8,9 +8,10 @@
 // One wave then merges a point's reservoir with its bin. By the
 // history-independence lemma the result is the l_max smallest keys among
 // the per-bucket minimum keys of (reservoir U bin), where a key is
-// (bf16 distance, id). The merge computes exactly that: a bitonic sort of
-// (hash, key) in LDS, the first entry of every hash run (its bucket's
-// minimum), a second sort by key, and the first l_max. Large bins are taken
+// (bf16 distance, id). The merge computes exactly that: the bucket minima
+// in an LDS hash table (compare-and-swap to claim a bucket's slot, atomic
+// min to keep its smallest key), a bitonic sort of the minima by key, and
+// the first l_max. Large bins are taken
 // in chunks; since dropped bucket minima can never re-enter (every kept key
 // is smaller and sits in a different bucket), merging chunk by chunk gives
 // the same reservoir as one merge. Atomics decide only record positions
@@ -318,14 +319,16 @@ __device__ __forceinline__ int pow2_at_least(int v) {
 __global__ void __launch_bounds__(64 * kMergeWaves) hashprune_merge_kernel(
     uint64_t *__restrict__ res, int64_t n, int l_max, const uint64_t *__restrict__ bins,
     const int64_t *__restrict__ off) {
-  __shared__ uint64_t sA[kMergeWaves][kMergeArr];
+  // sT: open-addressing table of bucket minima (key1, hashed by bucket);
+  // sB: the reservoir in key2 order
+  __shared__ uint64_t sT[kMergeWaves][2 * kMergeArr];
   __shared__ uint64_t sB[kMergeWaves][kMergeArr];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t p = (int64_t)blockIdx.x * kMergeWaves + wave;
   if (p >= n) return;
   const int64_t b0 = off[p], b1 = off[p + 1];
   if (b1 == b0) return;
-  uint64_t *A = sA[wave];
+  uint64_t *T = sT[wave];
   uint64_t *B = sB[wave];
   uint64_t *r = res + p * l_max;
   const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
@@ -346,28 +349,37 @@ __global__ void __launch_bounds__(64 * kMergeWaves) hashprune_merge_kernel(
   for (int64_t c0 = b0; c0 < b1; c0 += chunk_cap) {
     const int nc = (int)min((int64_t)chunk_cap, b1 - c0);
     const int tot = nres + nc;
-    const int P = pow2_at_least(tot);
-    for (int i = lane; i < P; i += 64) {
-      uint64_t k1 = kNone;
-      if (i < nres) {
-        k1 = key1_of_key2(B[i]);
-      } else if (i < tot) {
-        k1 = key1_of_slot(bins[c0 + (i - nres)]);
+    // a table of twice the entries' power of two, so probes stay short
+    const int TS = 2 * pow2_at_least(tot);
+    const int tbits = 31 - __clz(TS);
+    for (int i = lane; i < TS; i += 64) T[i] = kNone;
+    wave_sync();
+    // each entry's bucket keeps its minimum key1: a slot is claimed for a
+    // bucket by compare-and-swap from empty, and keys of the same bucket
+    // meet there by atomic min (they share the hash in the top 16 bits, so
+    // the minimum keeps it)
+    for (int i = lane; i < tot; i += 64) {
+      const uint64_t k1 = i < nres ? key1_of_key2(B[i]) : key1_of_slot(bins[c0 + (i - nres)]);
+      const uint32_t h = (uint32_t)(k1 >> 48);
+      uint32_t slot = (h * 2654435761u) >> (32 - tbits);
+      for (;;) {
+        const uint64_t prev = atomicCAS((unsigned long long *)&T[slot], (unsigned long long)kNone,
+                                        (unsigned long long)k1);
+        if (prev == kNone) break;
+        if ((uint32_t)(prev >> 48) == h) {
+          atomicMin((unsigned long long *)&T[slot], (unsigned long long)k1);
+          break;
+        }
+        slot = (slot + 1) & (TS - 1);
       }
-      A[i] = k1;
     }
     wave_sync();
-    wave_bitonic_sort(A, P);
-    // first entry of each hash run = the bucket's minimum key
+    // the bucket minima, compacted into B as key2
     int nk = 0;
-    for (int base = 0; base < P; base += 64) {
+    for (int base = 0; base < TS; base += 64) {
       const int i = base + lane;
-      bool keep = false;
-      uint64_t k1 = kNone;
-      if (i < P) {
-        k1 = A[i];
-        keep = k1 != kNone && (i == 0 || (A[i - 1] >> 48) != (k1 >> 48));
-      }
+      const uint64_t k1 = i < TS ? T[i] : kNone;
+      const bool keep = k1 != kNone;
       const uint64_t mask = __ballot(keep);
       if (keep) B[nk + __popcll(mask & below)] = key2_of_key1(k1);
       nk += __popcll(mask);
