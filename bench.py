@@ -14,8 +14,9 @@ queries from the same mixture for recall@10 against exact brute force
 
 `--prec` / `--rescore-mult` choose the leaf-GEMM form of the measured build
 (default FP32). `variants` lists other forms (by default bf16 exact, bf16
-with FP32 rescoring of the top-2k, fp8 with rescoring) built, timed and
-searched the same way on the same points after the main measurement.
+with FP32 rescoring of the top-2k, fp8 with rescoring, and FP32 with two
+replicas of the partition) built, timed and searched the same way on the
+same points after the main measurement.
 
 Printed: one JSON line. `roofline` is for the fused leaf distance +
 selection kernel (the dominant kernel): its average launch time comes from
@@ -68,8 +69,8 @@ def parse():
                          "fp32, or fp16 for the 768-d workload)")
     ap.add_argument("--rescore-mult", type=int, default=0,
                     help="select rescore_mult*k by the GEMM distance, keep k by FP32 rescoring")
-    ap.add_argument("--variants", default="bf16:0,bf16:2,fp8:2",
-                    help="other leaf-GEMM forms (prec:rescore_mult, comma separated) built and "
+    ap.add_argument("--variants", default="bf16:0,bf16:2,fp8:2,fp32:0:2",
+                    help="other forms (prec:rescore_mult[:replicas], comma separated) built and "
                          "timed after the main one on the same workload; '' for none")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="after the timed steps, copy this many MiB once (a plain copy of known "
@@ -354,9 +355,10 @@ def main():
         leaves = (torch.from_numpy(lo).cuda(), torch.from_numpy(lm.view(np.int32)).cuda())
         log(f"[bench] explicit leaves: {len(lo) - 1}, sizes {np.diff(lo).min()}..{np.diff(lo).max()}")
 
-    def run_form(prec, mult, steps, warmup, keep=False):
+    def run_form(prec, mult, steps, warmup, keep=False, replicas=1):
         """Build the whole index `warmup + steps` times with one leaf-GEMM
-        form; time the last `steps`; search the last graph for recall@10.
+        form (and `replicas` independent partitions feeding the reservoirs);
+        time the last `steps`; search the last graph for recall@10.
         With given leaves, the leaf kernel is autotuned on them, one eager
         build is profiled for the phase times, and the timed builds are
         replays of one captured HIP graph of the whole step."""
@@ -372,16 +374,17 @@ def main():
         if leaves is None:
             def step():
                 idx.prepare()
-                off, mem = idx.partition()
                 pp.reservoir_init(n, w.l_max, out=res)
-                idx.build_leaves(off, mem, res)
+                for r in range(replicas):
+                    off, mem = idx.partition(r)
+                    idx.build_leaves(off, mem, res)
                 g, deg = idx.robustprune(res)
                 return off, mem, g, deg
 
             for i in range(warmup):
                 step()
                 torch.cuda.synchronize()
-                log(f"[bench] {prec} x{mult}: warmup {i + 1}/{warmup} done")
+                log(f"[bench] {prec} x{mult} r{replicas}: warmup {i + 1}/{warmup} done")
             torch.cuda.synchronize()
             idx.set_profiling(True)
             t0 = time.perf_counter()
@@ -395,7 +398,7 @@ def main():
         else:
             off, mem = leaves
             tune = idx.autotune(off, mem)
-            log(f"[bench] {prec} x{mult}: autotune {tune}")
+            log(f"[bench] {prec} x{mult} r{replicas}: autotune {tune}")
             g = torch.empty((n, w.R), dtype=torch.int32, device="cuda")
             deg = torch.empty(n, dtype=torch.int32, device="cuda")
 
@@ -421,14 +424,14 @@ def main():
             for i in range(warmup):
                 graph.replay()
                 torch.cuda.synchronize()
-                log(f"[bench] {prec} x{mult}: warmup replay {i + 1}/{warmup} done")
+                log(f"[bench] {prec} x{mult} r{replicas}: warmup replay {i + 1}/{warmup} done")
             t0 = time.perf_counter()
             for i in range(steps):
                 graph.replay()
             torch.cuda.synchronize()
             t1 = time.perf_counter()
         ms = (t1 - t0) * 1000.0 / steps
-        log(f"[bench] {prec} x{mult}: {steps} steps, {ms:.2f} ms/step")
+        log(f"[bench] {prec} x{mult} r{replicas}: {steps} steps, {ms:.2f} ms/step")
         # leaf kernel roofline: dense flops 2 s^2 d per leaf, per launch
         launches = max(1, st["leaf_knn_launches"])
         flops_per_launch = 2.0 * st["leaf_pairs"] * w.d * steps / launches
@@ -445,13 +448,14 @@ def main():
                 hits = (dist.double() <= kth[:, None]).sum().item()
                 r = hits / (nq * 10.0)
                 curve[L] = {"recall": round(r, 5), "cmps": round(cmps.double().mean().item(), 1)}
-                log(f"[bench] {prec} x{mult}: L={L} recall@10={r:.4f} cmps={curve[L]['cmps']}")
+                log(f"[bench] {prec} x{mult} r{replicas}: L={L} recall@10={r:.4f} cmps={curve[L]['cmps']}")
                 if r >= 0.95:
                     l_at, recall = L, r
                     break
             if recall is None:
                 recall = max(v["recall"] for v in curve.values())
-        form = {"prec": prec, "rescore_mult": mult, "ms_per_step": ms, "value": n / (ms / 1000.0),
+        form = {"prec": prec, "rescore_mult": mult, "replicas": replicas, "ms_per_step": ms,
+                "value": n / (ms / 1000.0),
                 "leaf_gemm_tflops": achieved, "peak": PEAK_MFMA_TFLOPS[prec],
                 "frac": achieved / PEAK_MFMA_TFLOPS[prec], "recall_at_10": recall,
                 "L_at_recall_0.95": l_at, "recall_curve": curve, "phase_ms": phases,
@@ -483,10 +487,14 @@ def main():
 
     variants = []
     for spec in [v for v in args.variants.split(",") if v.strip()]:
-        vp, vm = spec.split(":")
-        if (vp, int(vm)) == (args.prec, args.rescore_mult):
+        parts = spec.split(":")
+        vp, vm = parts[0], int(parts[1])
+        vr = int(parts[2]) if len(parts) > 2 else 1
+        if (vp, vm, vr) == (args.prec, args.rescore_mult, 1):
             continue
-        f = run_form(vp, int(vm), args.steps, 1)
+        if leaves is not None and vr > 1:
+            continue  # explicit leaves: no partition to replicate
+        f = run_form(vp, vm, args.steps, 1, replicas=vr)
         f.pop("stats")
         variants.append(f)
 

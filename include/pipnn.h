@@ -160,6 +160,18 @@ pipnn_status pipnn_partition(pipnn_index *idx, int64_t *d_leaf_offsets, int64_t 
                              uint32_t *d_leaf_members, int64_t cap_members, int64_t *h_n_leaves,
                              int64_t *h_n_members, pipnn_stream_t stream);
 
+/* (sync) An independent replica of the partition (the paper's replication:
+ * another ball carving of the same points with other random leaders):
+ * pipnn_partition with the root key of replica r -- the seed for r = 0,
+ * else the first splitmix64 output from seed xor r * 0xD1B54A32D192ED03.
+ * pipnn_build_leaves on each replica's leaves into the same reservoirs
+ * builds the replicated index (HashPrune is order-free). EINVAL if r < 0;
+ * otherwise as pipnn_partition. */
+pipnn_status pipnn_partition_replica(pipnn_index *idx, int32_t replica, int64_t *d_leaf_offsets,
+                                     int64_t cap_leaves, uint32_t *d_leaf_members,
+                                     int64_t cap_members, int64_t *h_n_leaves,
+                                     int64_t *h_n_members, pipnn_stream_t stream);
+
 /* (sync) Plan the leaves of a later pipnn_build_leaves call: reads the
  * offsets, checks the member ids, builds the leaf kernel's work lists on the
  * device and reserves every scratch buffer of the build. pipnn_build_leaves

@@ -205,8 +205,22 @@ def slot_fields(res):
     return ids, hsh, bfv
 
 
-def partition(X, params: Params):
-    """Randomized Ball Carving (Alg. 5). Returns (offsets, members, leader_dists)."""
+def replica_key(seed: int, r: int) -> int:
+    """Root key of partition replica r (the paper's replication: an
+    independent carving): the seed for r = 0, else the first splitmix64
+    output from seed xor r * 0xD1B54A32D192ED03 (mod 2^64)."""
+    if r == 0:
+        return int(seed)
+    return int(splitmix64((int(seed) ^ (r * 0xD1B54A32D192ED03)) & 0xFFFFFFFFFFFFFFFF, 1)[0])
+
+
+def partition(X, params: Params, replica: int = 0):
+    """Randomized Ball Carving (Alg. 5). Returns (offsets, members, leader_dists).
+    Replica r > 0 is the same carving from root key replica_key(seed, r)."""
+    if replica:
+        q = Params.from_buffer_copy(params)
+        q.seed = replica_key(params.seed, replica)
+        params = q
     X = _f32(X)
     n, d = X.shape
     cap_l, cap_m = max(16, n // 8), 4 * n
@@ -374,16 +388,20 @@ def recall_at_k(found_ids, X, Q, gt_dist, metric: int = 0) -> float:
     return hits / float(nq * k)
 
 
-def build_index(X, H, params: Params, lazy: bool = True):
+def build_index(X, H, params: Params, lazy: bool = True, replicas: int = 1):
     """Alg. 4 end to end: partition, pick, HashPrune, final RobustPrune.
-    Returns a dict of every intermediate."""
+    With replicas > 1, the records of that many independent partitions go
+    into the same reservoirs. Returns a dict of every intermediate (the
+    leaves, picks and records of the last replica)."""
     X = _f32(X)
     n = X.shape[0]
-    off, mem, ld = partition(X, params)
-    cand, dd = leaf_knn(X, off, mem, params.k, params.metric)
-    dst, cnd, dv = bidirected_records(mem, cand, dd)
     S = sketches(X, H)
-    res = hashprune(reservoir_init(n, params.l_max), S, dst, cnd, dv)
+    res = reservoir_init(n, params.l_max)
+    for r in range(replicas):
+        off, mem, ld = partition(X, params, replica=r)
+        cand, dd = leaf_knn(X, off, mem, params.k, params.metric)
+        dst, cnd, dv = bidirected_records(mem, cand, dd)
+        res = hashprune(res, S, dst, cnd, dv)
     g, deg = robustprune(X, res, params.alpha, params.R, params.metric, lazy=lazy)
     return dict(offsets=off, members=mem, leader_dists=ld, cand=cand, dist=dd, S=S,
                 reservoirs=res, graph=g, degree=deg, records=(dst, cnd, dv))

@@ -24,7 +24,8 @@ EMPTY_SLOT = 0x7F80 << 48 | 0xFFFFFFFF
 
 EXPORTS = [
     "pipnn_version", "pipnn_last_error", "pipnn_default_params", "pipnn_workspace_bytes",
-    "pipnn_create", "pipnn_destroy", "pipnn_partition", "pipnn_build_leaves",
+    "pipnn_create", "pipnn_destroy", "pipnn_partition", "pipnn_partition_replica",
+    "pipnn_build_leaves",
     "pipnn_hashprune_insert", "pipnn_reservoir_init", "pipnn_reservoir_canonical",
     "pipnn_robustprune", "pipnn_start_node", "pipnn_search", "pipnn_get_sketches",
     "pipnn_knn_block", "pipnn_leaf_pick", "pipnn_prepare", "pipnn_set_profiling",
@@ -82,6 +83,8 @@ def lib():
         L.pipnn_destroy.argtypes = [P]
         L.pipnn_destroy.restype = None
         L.pipnn_partition.argtypes = [P, P, i64, P, i64, C.POINTER(i64), C.POINTER(i64), P]
+        L.pipnn_partition_replica.argtypes = [P, i32, P, i64, P, i64, C.POINTER(i64),
+                                              C.POINTER(i64), P]
         L.pipnn_build_leaves.argtypes = [P, P, P, i64, P, P]
         L.pipnn_hashprune_insert.argtypes = [P, P, P, P, i64, P, P]
         L.pipnn_reservoir_init.argtypes = [P, i64, i32, P]
@@ -236,15 +239,17 @@ class Index:
                                   _ptr(reservoirs), _ptr(graph), _ptr(degree), _stream()))
         self.n += n_new
 
-    def partition(self):
+    def partition(self, replica: int = 0):
+        """Ball carving (Alg. 5); replica r > 0 is an independent carving
+        with another root key."""
         torch = _torch()
         nl, nm = C.c_int64(), C.c_int64()
         cap_l, cap_m = max(16, self.n // 64), 2 * self.n
         for _ in range(2):
             off = torch.empty(cap_l + 1, dtype=torch.int64, device="cuda")
             mem = torch.empty(max(cap_m, 1), dtype=torch.int32, device="cuda")
-            st = lib().pipnn_partition(self._h, _ptr(off), cap_l, _ptr(mem), cap_m,
-                                       C.byref(nl), C.byref(nm), _stream())
+            st = lib().pipnn_partition_replica(self._h, replica, _ptr(off), cap_l, _ptr(mem),
+                                               cap_m, C.byref(nl), C.byref(nm), _stream())
             if st == 0:
                 return off[: nl.value + 1], mem[: nm.value]
             if st != -3:
@@ -334,12 +339,15 @@ class Index:
         return oc, od
 
 
-def build(X, H, params: Params):
+def build(X, H, params: Params, replicas: int = 1):
     """Alg. 4 on the GPU: partition, leaf pick + HashPrune, final RobustPrune.
-    Returns (index, offsets, members, reservoirs, graph, degree)."""
+    With replicas > 1, that many independent partitions feed the same
+    reservoirs. Returns (index, offsets, members, reservoirs, graph, degree)
+    with the last replica's leaves."""
     idx = Index(X, H, params)
-    off, mem = idx.partition()
     res = reservoir_init(idx.n, params.l_max)
-    idx.build_leaves(off, mem, res)
+    for r in range(replicas):
+        off, mem = idx.partition(r)
+        idx.build_leaves(off, mem, res)
     g, deg = idx.robustprune(res)
     return idx, off, mem, res, g, deg

@@ -69,6 +69,15 @@ uint64_t sm64_next(uint64_t &state) {
   return z ^ (z >> 31);
 }
 
+// Root key of partition replica r: the seed itself for r = 0, else the
+// first splitmix64 output from the seed xor r times a second odd constant
+// (distinct from the child-key constant below).
+uint64_t replica_key(uint64_t seed, int64_t r) {
+  if (r == 0) return seed;
+  uint64_t s = seed ^ ((uint64_t)r * 0xD1B54A32D192ED03ull);
+  return sm64_next(s);
+}
+
 // Key of the subproblem formed by bucket t of a subproblem with key `key`.
 uint64_t sub_key(uint64_t key, int64_t t) {
   uint64_t s = key ^ ((uint64_t)(t + 1) * 0x9E3779B97F4A7C15ull);
@@ -419,8 +428,17 @@ void pipnn_destroy(pipnn_index *idx) {
 pipnn_status pipnn_partition(pipnn_index *idx, int64_t *d_leaf_offsets, int64_t cap_leaves,
                              uint32_t *d_leaf_members, int64_t cap_members, int64_t *h_n_leaves,
                              int64_t *h_n_members, pipnn_stream_t stream) {
+  return pipnn_partition_replica(idx, 0, d_leaf_offsets, cap_leaves, d_leaf_members, cap_members,
+                                 h_n_leaves, h_n_members, stream);
+}
+
+pipnn_status pipnn_partition_replica(pipnn_index *idx, int32_t replica, int64_t *d_leaf_offsets,
+                                     int64_t cap_leaves, uint32_t *d_leaf_members,
+                                     int64_t cap_members, int64_t *h_n_leaves,
+                                     int64_t *h_n_members, pipnn_stream_t stream) {
   GUARD_BEGIN
   if (!idx || !h_n_leaves || !h_n_members) return fail(PIPNN_EINVAL, "NULL argument");
+  if (replica < 0) return fail(PIPNN_EINVAL, "replica must be >= 0");
   Index &I = *reinterpret_cast<Index *>(idx);
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   const pipnn_params &P = I.p;
@@ -467,7 +485,7 @@ pipnn_status pipnn_partition(pipnn_index *idx, int64_t *d_leaf_offsets, int64_t 
   if (n <= P.c_max) {
     leaves.push_back({A0->as<uint32_t>(), n, nullptr, 0});
   } else {
-    subs.push_back({0, n, P.seed, 0});
+    subs.push_back({0, n, replica_key(P.seed, replica), 0});
   }
   DevBuf *A = A0;
   std::vector<int32_t> gsize_host;

@@ -390,6 +390,22 @@ def test_exact_16bit_operand_build(exact_build, prec):
     idx.close()
 
 
+def test_replicated_build_bit_exact(exact_build):
+    """Two independent partitions (replication) into the same reservoirs:
+    the second carving's leaves and the final reservoirs and graph equal the
+    oracle's replicated build bit for bit."""
+    X, H, p, _ = exact_build
+    ref = oracle.build_index(X, H, oracle_params(p), replicas=2)
+    idx, off, mem, res, g, deg = pp.build(dev(X), dev(H), p, replicas=2)
+    torch.cuda.synchronize()
+    assert leaf_sets(off.cpu().numpy(), mem.cpu().numpy()) == leaf_sets(ref["offsets"],
+                                                                         ref["members"])
+    assert np.array_equal(u64(res), ref["reservoirs"])
+    assert np.array_equal(u32(g), ref["graph"])
+    assert np.array_equal(u32(deg), ref["degree"])
+    idx.close()
+
+
 def test_robustprune_exact_on_oracle_reservoirs(exact_build):
     X, H, p, ref = exact_build
     idx = pp.Index(dev(X), dev(H), p)

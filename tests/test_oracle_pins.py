@@ -496,3 +496,40 @@ def test_recall_definition():
     assert oracle.recall_at_k(gi, X, Q, gd) == 1.0
     half = gi.copy(); half[0, 5:] = np.arange(15, 20)
     assert oracle.recall_at_k(half, X, Q, gd) == 0.5
+
+
+def test_partition_replicas():
+    """Replication (an independent second carving): replica 0 is the plain
+    partition, replica 1 another valid partition from the derived root key;
+    the replicated build's reservoirs do not depend on the replicas' order
+    (HashPrune is order-free), and a point's reservoir never holds fewer
+    entries than with one replica (its records, so its buckets, only grow)."""
+    X = pi.gaussian_mixture(1500, 16, 10, 0.3, seed=61, center_seed=61)
+    H = pi.hyperplanes(12, 16, seed=62)
+    p = oracle.make_params(c_max=200, c_min=16, k=8, l_max=24, R=12, seed=63)
+    assert oracle.replica_key(63, 0) == 63
+    assert oracle.replica_key(63, 1) == int(oracle.splitmix64(63 ^ 0xD1B54A32D192ED03, 1)[0])
+    o0, m0, _ = oracle.partition(X, p)
+    a0, b0, _ = oracle.partition(X, p, replica=0)
+    o1, m1, _ = oracle.partition(X, p, replica=1)
+    assert np.array_equal(o0, a0) and np.array_equal(m0, b0)
+    s0 = sorted(tuple(m0[o0[i]:o0[i + 1]]) for i in range(len(o0) - 1))
+    s1 = sorted(tuple(m1[o1[i]:o1[i + 1]]) for i in range(len(o1) - 1))
+    assert s0 != s1
+    assert np.diff(o1).max() <= 200 and set(np.unique(m1)) == set(range(1500))
+    ref = oracle.build_index(X, H, p, replicas=2)
+    S = oracle.sketches(X, H)
+    res = oracle.reservoir_init(len(X), p.l_max)
+    for r in (1, 0):
+        o, m, _ = oracle.partition(X, p, replica=r)
+        cand, dd = oracle.leaf_knn(X, o, m, p.k)
+        res = oracle.hashprune(res, S, *oracle.bidirected_records(m, cand, dd))
+    assert np.array_equal(res, ref["reservoirs"])
+    one = oracle.build_index(X, H, p)
+    ids2, _, bf2 = oracle.slot_fields(ref["reservoirs"])
+    ids1, _, bf1 = oracle.slot_fields(one["reservoirs"])
+    # per point, the two-replica reservoir's k-th key is no larger
+    for i in range(0, 1500, 50):
+        k1 = sorted(int(b) for b, c in zip(bf1[i], ids1[i]) if c != oracle.EMPTY_ID)
+        k2 = sorted(int(b) for b, c in zip(bf2[i], ids2[i]) if c != oracle.EMPTY_ID)
+        assert len(k2) >= len(k1)
