@@ -264,7 +264,9 @@ pipnn_status pipnn_insert(pipnn_index *idx, int64_t n_new, const int32_t *d_grou
  * nearest, rescored), the FP32 direct-difference distance of each winner
  * (for the inner product on an operand equal to the data -- FP32, or fp16 /
  * bf16 data with the same gemm_prec -- the GEMM's own FP32 sum, which has no
- * norm-expansion cancellation to repair), and both directed records of each
+ * norm-expansion cancellation to repair; for squared L2 without rescoring
+ * on data the integer check found exact -- see pipnn_stats.data_int_exact --
+ * the GEMM distance, which then is the same integer), and both directed records of each
  * picked edge inserted into HashPrune.
  * d_leaf_offsets/d_leaf_members is any CSR of leaves with ascending member
  * ids (RBC output or explicit leaves); leaves of size 1 contribute nothing.
@@ -339,7 +341,11 @@ pipnn_status pipnn_search(pipnn_index *idx, const uint32_t *d_graph, const void 
                           pipnn_stream_t stream);
 
 /* Recompute the per-point squared norms and sketches from X (call after the
- * caller changed X in place; pipnn_create already does this once). */
+ * caller changed X in place; pipnn_create already does this once), with the
+ * integer check of X (every coordinate an integer, d*A^2 <= 2^23 and
+ * d*W^2 <= 2^24 for the largest magnitude A and the range W; read back
+ * with one synchronization, except under stream capture, where the last
+ * result is kept). */
 pipnn_status pipnn_prepare(pipnn_index *idx, pipnn_stream_t stream);
 
 /* Counters and phase timings of the most recent calls on an index.
@@ -354,7 +360,9 @@ typedef struct {
   int64_t leaf_pairs;            /* sum of s^2 over the leaves of the last build */
   int64_t records;               /* candidate records binned by the last build */
   int32_t operand_exact;         /* 1: the reduced-precision copy holds X exactly */
-  int32_t reserved_;
+  int32_t data_int_exact;        /* 1: X is integral with a range that makes every squared-L2
+                                    form exact in float32, so the leaf picks skip the winners'
+                                    FP32 recompute (no rescoring) */
   double ms_prepare, ms_partition, ms_leaf_knn, ms_bin, ms_merge, ms_robustprune;
 } pipnn_stats;
 

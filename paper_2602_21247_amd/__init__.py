@@ -53,7 +53,7 @@ class Stats(C.Structure):
     _fields_ = [("n_leaves", C.c_int64), ("n_members", C.c_int64), ("leader_dists", C.c_int64),
                 ("levels", C.c_int32), ("leaf_knn_launches", C.c_int32),
                 ("leaf_pairs", C.c_int64), ("records", C.c_int64),
-                ("operand_exact", C.c_int32), ("reserved_", C.c_int32),
+                ("operand_exact", C.c_int32), ("data_int_exact", C.c_int32),
                 ("ms_prepare", C.c_double), ("ms_partition", C.c_double),
                 ("ms_leaf_knn", C.c_double), ("ms_bin", C.c_double), ("ms_merge", C.c_double),
                 ("ms_robustprune", C.c_double)]

@@ -357,6 +357,7 @@ pipnn_status pipnn_create(const pipnn_params *p, const void *d_X, int64_t n, int
   if ((e = I->s_counter.ensure(64)) != hipSuccess ||
       (e = I->sketches.ensure((size_t)n * I->m * 4)) != hipSuccess ||
       (e = I->norms.ensure((size_t)n * 4)) != hipSuccess ||
+      (e = I->int_chk.ensure(64)) != hipSuccess ||
       (e = I->flag.ensure(64)) != hipSuccess)
     return cleanup(fail(PIPNN_ENOMEM, "device allocation failed: %s", hipGetErrorString(e)));
   if (x_dtype != PIPNN_DTYPE_F32) {
@@ -365,7 +366,8 @@ pipnn_status pipnn_create(const pipnn_params *p, const void *d_X, int64_t n, int
     if ((e = launch_to_f32(d_X, x_dtype, I->xf32.as<float>(), n * (int64_t)d, s)) != hipSuccess)
       return cleanup(fail(PIPNN_EDEVICE, "conversion launch failed: %s", hipGetErrorString(e)));
   }
-  if ((e = launch_norms_sketches(*I, s)) != hipSuccess)
+  if ((e = clear_int_check(*I, s)) != hipSuccess || (e = launch_norms_sketches(*I, s)) != hipSuccess ||
+      (e = read_int_check(*I, true, s)) != hipSuccess)
     return cleanup(fail(PIPNN_EDEVICE, "sketch launch failed: %s", hipGetErrorString(e)));
   // the float32 GEMM operand: X itself when its rows are whole 16-byte
   // vectors of an instantiated width, else a zero-padded copy
@@ -402,7 +404,7 @@ void pipnn_destroy(pipnn_index *idx) {
   Index *I = reinterpret_cast<Index *>(idx);
   (void)hipDeviceSynchronize();
   for (DevBuf *b : {&I->rp_order, &I->o_first, &I->o_flag, &I->o_pos, &I->o_pos2, &I->o_tmp,
-                    &I->xf32, &I->xpad, &I->xlow, &I->op_flag, &I->xscale, &I->lnorms, &I->s_counter, &I->q_conv, &I->q_seen,
+                    &I->xf32, &I->xpad, &I->xlow, &I->op_flag, &I->int_chk, &I->xscale, &I->lnorms, &I->s_counter, &I->q_conv, &I->q_seen,
                     &I->lt_off, &I->lt_mem, &I->lt_rep, &I->i_rows, &I->i_cols, &I->i_assign,
                     &I->i_flag, &I->i_pos, &I->i_list, &I->i_tmp, &I->i_segs, &I->sketches, &I->norms, &I->flag, &I->s_jobs,
                     &I->s_items, &I->s_picks_c, &I->s_picks_d, &I->s_cnt, &I->s_off, &I->s_bins,
@@ -773,11 +775,19 @@ pipnn_status read_offsets(const int64_t *d_off, int64_t n_leaves, hipStream_t s,
   return PIPNN_OK;
 }
 
-// True when the leaf GEMM's distance already is a direct FP32 evaluation:
-// the inner product (no norm expansion, hence no cancellation) on an
-// operand that holds the data exactly. The winners are then not recomputed.
+// True when the leaf GEMM's distance already is the value the winners'
+// recompute would emit, which is then skipped:
+// - the inner product (no norm expansion, hence no cancellation) on an
+//   operand that holds the data exactly;
+// - the squared L2 distance without rescoring, on integer data whose range
+//   makes every form exact in float32 (int_exact), with a float32 operand
+//   or a 16-bit copy that holds X exactly: the norm expansion and the
+//   direct difference are then the same integer.
 static bool gemm_is_direct(const Index &I) {
-  if (I.p.metric != PIPNN_METRIC_IP) return false;
+  if (I.p.metric != PIPNN_METRIC_IP)
+    return I.p.metric == PIPNN_METRIC_L2 && I.p.rescore_mult == 0 && I.int_exact &&
+           (I.p.gemm_prec == PIPNN_PREC_FP32 ||
+            (I.op_exact && (I.p.gemm_prec == PIPNN_PREC_BF16 || I.p.gemm_prec == PIPNN_PREC_FP16)));
   return I.p.gemm_prec == PIPNN_PREC_FP32 ||
          (I.p.gemm_prec == PIPNN_PREC_FP16 && I.x_dtype == PIPNN_DTYPE_F16) ||
          (I.p.gemm_prec == PIPNN_PREC_BF16 && I.x_dtype == PIPNN_DTYPE_BF16);
@@ -1257,7 +1267,9 @@ pipnn_status pipnn_insert(pipnn_index *idx, int64_t n_new, const int32_t *d_grou
     HIPCHK(launch_to_f32(reinterpret_cast<const uint8_t *>(I.X) + (size_t)n0 * d * eb, I.x_dtype,
                          I.xf32.as<float>() + n0 * d, n_new * d, s));
   }
+  HIPCHK(clear_int_check(I, s));
   HIPCHK(launch_norms_sketches_range(I, n0, n_new, s));
+  HIPCHK(read_int_check(I, false, s));
   HIPCHK(launch_pad_range(I, n0, n_new, s));
   if (P.gemm_prec != PIPNN_PREC_FP32) {
     HIPCHK(clear_op_flag(I, s));
@@ -1703,7 +1715,11 @@ pipnn_status pipnn_prepare(pipnn_index *idx, pipnn_stream_t stream) {
   PhaseTimer t(I, kPhPrepare, s);
   if (I.x_dtype != PIPNN_DTYPE_F32)
     HIPCHK(launch_to_f32(I.X, I.x_dtype, I.xf32.as<float>(), I.n * (int64_t)I.d, s));
+  HIPCHK(clear_int_check(I, s));
   HIPCHK(launch_norms_sketches(I, s));
+  // outside capture the integer check is taken again (as the operand's
+  // exactness below); a captured prepare keeps the last one
+  if (!stream_capturing(s)) HIPCHK(read_int_check(I, true, s));
   HIPCHK(launch_pad_range(I, 0, I.n, s));
   if (I.p.gemm_prec != PIPNN_PREC_FP32) {
     HIPCHK(clear_op_flag(I, s));
@@ -1736,6 +1752,7 @@ pipnn_status pipnn_get_stats(pipnn_index *idx, pipnn_stats *h_out) {
   pipnn_stats st = I.stats;
   st.leaf_knn_launches = I.leaf_launches;
   st.operand_exact = I.op_exact ? 1 : 0;
+  st.data_int_exact = I.int_exact ? 1 : 0;
   st.ms_prepare = I.phase_ms[kPhPrepare];
   st.ms_partition = I.phase_ms[kPhPartition];
   st.ms_leaf_knn = I.phase_ms[kPhLeafKnn];

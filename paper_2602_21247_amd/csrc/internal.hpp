@@ -37,6 +37,12 @@ struct Index {
   DevBuf lnorms;    // n float32, squared norms of the decoded low-precision operand
   DevBuf op_flag;   // int32: set by the encoder when a value does not survive encoding
   bool op_exact = false;  // the reduced-precision operand holds X exactly
+  // Integer check of X, taken with the norms: int32 [not integral or
+  // |v| > 2^20, min, max]; int_exact when every coordinate is an integer
+  // and the range keeps every distance form exact in float32.
+  DevBuf int_chk;
+  bool int_exact = false;
+  int64_t int_lo = 0, int_hi = 0;
   int32_t ldo = 0;  // row stride (elements) of xlow: d padded by lowp_padded_dim
   DevBuf xpad;      // float32 GEMM operand zero padded to ldf, when X itself cannot serve
   int32_t ldf = 0;  // row stride (floats) of the float32 GEMM operand; 0: d > 256
@@ -178,6 +184,10 @@ hipError_t launch_quantize_range(const Index &I, int64_t p0, int64_t cnt, hipStr
 // and, outside capture, read it back into I.op_exact (synchronizes s):
 // `reset` clears op_exact first for a full re-encode.
 hipError_t clear_op_flag(Index &I, hipStream_t s);
+hipError_t clear_int_check(Index &I, hipStream_t s);
+// (sync) reads the integer check of the points normed since the last clear;
+// reset: those are all the points, else they are added to the earlier ones
+hipError_t read_int_check(Index &I, bool reset, hipStream_t s);
 hipError_t read_op_flag(Index &I, bool reset, hipStream_t s);
 // Rows [p0, p0 + cnt) of the zero-padded float32 operand I.xpad.
 hipError_t launch_pad_range(const Index &I, int64_t p0, int64_t cnt, hipStream_t s);

@@ -59,6 +59,10 @@ __device__ __forceinline__ f32x4 mfma16x16(uint4 a, uint4 b, f32x4 acc) {
   }
 }
 
+// Lane-mask compares (one v_cmp writing a wave mask; the predicates are
+// LLVM's CmpInst codes: ordered <=, signed <, ==).
+constexpr int kFcmpOle = 5, kIcmpEq = 32, kIcmpSlt = 40;
+
 // The value of lane (lane & ~3) + ((lane & 3) + 1), i.e. the next lane of
 // the same group of four (lane 3 of a group reads itself), by a DPP
 // quad permutation.
@@ -113,13 +117,14 @@ __device__ __forceinline__ void knn_quad_item(const KnnArgs &a, const int item) 
   __shared__ float sColS[F8 ? 2 * BN : 1];
   __shared__ float sBufD[BM * BUFD];
   __shared__ uint16_t sBufC[BM * BUFC];
-  __shared__ float sTau[BM];
+  __shared__ __attribute__((aligned(16))) float sTau[BM];
   __shared__ int sBufN[BM];
-  __shared__ int sWmax[2][NW];    // per tile parity: each wave's largest buffer count
-  __shared__ float sNr[BM];
-  __shared__ float sRs[F8 ? BM : 1];
+  __shared__ __attribute__((aligned(16))) int sWmax[2][NW];  // per tile parity: each wave's largest buffer count
+  __shared__ __attribute__((aligned(16))) float sNr[BM];
+  __shared__ __attribute__((aligned(16))) float sRs[F8 ? BM : 4];
 
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform over the wave
   const int q = lane >> 4, l16 = lane & 15;  // MFMA lane group and column
   if (item >= a.n_items || a.items[item].job < 0) return;
   const KnnItem it = a.items[item];
@@ -238,6 +243,17 @@ __device__ __forceinline__ void knn_quad_item(const KnnArgs &a, const int item) 
   __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
   __syncthreads();
 
+  // The filter's per-row operands live in registers: accumulator entry j of
+  // a lane belongs to row wave * RW + 4q + j, whose norm (and e4m3 scale)
+  // never changes and whose threshold changes only when the rows are drained.
+  const int rq = wave * RW + 4 * q;
+  const f32x4 nr4 = *reinterpret_cast<const f32x4 *>(sNr + rq);
+  const f32x4 rs4 = F8 ? *reinterpret_cast<const f32x4 *>(sRs + rq) : f32x4{1.f, 1.f, 1.f, 1.f};
+  f32x4 tau4 = *reinterpret_cast<const f32x4 *>(sTau + rq);
+  // the wave's own columns (leaf self-joins) fall in the tiles holding
+  // columns [diag0, diag0 + RW)
+  const int diag0 = excl ? J.self_off + wrow : -(1 << 30);
+
   for (int t = 0, c0 = 0; c0 < n_cols; ++t, c0 += BN) {
     const int buf = t & 1;
     const bool more = c0 + BN < n_cols;
@@ -257,6 +273,7 @@ __device__ __forceinline__ void knn_quad_item(const KnnArgs &a, const int item) 
 #pragma unroll
         for (int j = 0; j < 4; ++j) cntj[j] = 0;
         wave_sync();
+        tau4 = *reinterpret_cast<const f32x4 *>(sTau + rq);
       }
     }
     if (active) {
@@ -275,33 +292,46 @@ __device__ __forceinline__ void knn_quad_item(const KnnArgs &a, const int item) 
         acc0 = mfma16x16<PREC>(aw[s], b0, acc0);
         acc1 = mfma16x16<PREC>(aw[s], b1, acc1);
       }
+      // survivors as wave masks: bit l of mk[g][j] is lane l's entry j of
+      // group g (no branch per entry; the masks are the append's ranks)
       float dv[2][4];
-      uint32_t pass = 0;  // bit 4g + j
-      const int self = excl ? c0 + l16 - J.self_off - (wrow + 4 * q) : -100;  // j of the own column (group 0)
+      uint64_t mk[2][4];
 #pragma unroll
       for (int g = 0; g < 2; ++g) {
         const f32x4 acc = g ? acc1 : acc0;
         const int cc = c0 + 16 * g + l16;
         const bool vc = cc < n_cols;
+        const uint64_t vcm = __builtin_amdgcn_sicmpl((int64_t)cc, (int64_t)n_cols, kIcmpSlt);
         const float nc = sColN[buf * BN + 16 * g + l16];
         const float cs = F8 ? sColS[buf * BN + 16 * g + l16] : 1.f;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           float x = acc[j];
-          if constexpr (F8) x = x * sRs[rb + j] * cs;
-          dv[g][j] = l2 ? sNr[rb + j] + fmaf(-2.f, x, nc) : -x;
-          const bool ok = vc && dv[g][j] <= sTau[rb + j] && self + 16 * g != j;
-          pass |= (ok ? 1u : 0u) << (4 * g + j);
+          if constexpr (F8) x = x * rs4[j] * cs;
+          dv[g][j] = l2 ? nr4[j] + fmaf(-2.f, x, nc) : -x;
+          mk[g][j] = vcm & __builtin_amdgcn_fcmpf(dv[g][j], tau4[j], kFcmpOle);
         }
-        if (a.out_matrix && vc) {
+        if (a.out_matrix) {
           // test-only: the GEMM distance of every pair
 #pragma unroll
           for (int j = 0; j < 4; ++j)
-            if (wrow + 4 * q + j < n_rows)
+            if (vc && wrow + 4 * q + j < n_rows)
               a.out_matrix[(J.out_off + wrow + 4 * q + j) * a.matrix_ld + cc] = dv[g][j];
         }
       }
-      if (__ballot(pass != 0) != 0ull) {
+      if (c0 < diag0 + RW && c0 + BN > diag0) {
+        // drop each row's own column: entry j of group g at column
+        // c0 + 16g + l16 is row wrow + 4q + j's own when the two coincide
+        const int self = c0 + l16 - diag0 - 4 * q;
+#pragma unroll
+        for (int g = 0; g < 2; ++g)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) mk[g][j] &= ~__builtin_amdgcn_sicmp(self + 16 * g, j, kIcmpEq);
+      }
+      uint64_t any = 0;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) any |= mk[0][j] | mk[1][j];
+      if (any != 0ull) {
         // append at the rank among the row's survivors of this tile (group
         // 0's columns first, then group 1's)
         const uint32_t below = (1u << l16) - 1u;
@@ -309,18 +339,17 @@ __device__ __forceinline__ void knn_quad_item(const KnnArgs &a, const int item) 
         uint16_t *bc = sBufC + rb * BUFC;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          const uint64_t m0 = __ballot((pass >> j) & 1u);
-          const uint64_t m1 = __ballot((pass >> (4 + j)) & 1u);
+          const uint64_t m0 = mk[0][j], m1 = mk[1][j];
           if ((m0 | m1) == 0ull) continue;
           const uint32_t g0m = (uint32_t)(m0 >> (16 * q)) & 0xFFFFu;
           const uint32_t g1m = (uint32_t)(m1 >> (16 * q)) & 0xFFFFu;
           const int c0n = cntj[j] + __popc(g0m);
-          if ((pass >> j) & 1u) {
+          if ((g0m >> l16) & 1u) {
             const int pos = cntj[j] + __popc(g0m & below);
             bd[j * BUFD + pos] = dv[0][j];
             bc[j * BUFC + pos] = (uint16_t)(c0 + l16);
           }
-          if ((pass >> (4 + j)) & 1u) {
+          if ((g1m >> l16) & 1u) {
             const int pos = c0n + __popc(g1m & below);
             bd[j * BUFD + pos] = dv[1][j];
             bc[j * BUFC + pos] = (uint16_t)(c0 + 16 + l16);

@@ -9,48 +9,83 @@ namespace pipnn {
 // Squared norms (for the GEMM distance form) and sketches
 // Sketch(v)_b = H_b . v (Sec. 3, Implementation). One thread per point
 // reads its row with 16-byte loads and accumulates every output in
-// dimension order; the hyperplanes are broadcast from LDS.
+// dimension order; the hyperplanes are broadcast from LDS. The same pass
+// takes the integer check: chk[0] is set when a coordinate is not an
+// integer of magnitude <= 2^20, chk[1] / chk[2] collect the smallest and
+// largest coordinate (one atomic per wave, only when it would change them).
+__device__ __forceinline__ void coord_check(float v, bool &bad, float &lo, float &hi) {
+  bad |= !(fabsf(v) <= 1048576.f) || v != rintf(v);
+  lo = fminf(lo, v);
+  hi = fmaxf(hi, v);
+}
+
 __global__ void __launch_bounds__(256) norms_sketches_kernel(const float *__restrict__ X, int64_t n,
                                                              int d, const float *__restrict__ H,
                                                              int m, float *__restrict__ norms,
-                                                             float *__restrict__ S) {
+                                                             float *__restrict__ S,
+                                                             int *__restrict__ chk) {
   extern __shared__ float sH[];  // m x d
   for (int i = threadIdx.x; i < m * d; i += blockDim.x) sH[i] = H[i];
   __syncthreads();
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= n) return;
-  const float *x = X + p * d;
-  float nn = 0.f;
-  float s[16];
+  bool bad = false;
+  float lo = INFINITY, hi = -INFINITY;
+  if (p < n) {
+    const float *x = X + p * d;
+    lo = hi = x[0];
+    float nn = 0.f;
+    float s[16];
 #pragma unroll
-  for (int b = 0; b < 16; ++b) s[b] = 0.f;
-  if ((d & 3) == 0) {
-    for (int i = 0; i < d; i += 4) {
-      const float4 v = *reinterpret_cast<const float4 *>(x + i);
-      nn = fmaf(v.x, v.x, nn); nn = fmaf(v.y, v.y, nn);
-      nn = fmaf(v.z, v.z, nn); nn = fmaf(v.w, v.w, nn);
+    for (int b = 0; b < 16; ++b) s[b] = 0.f;
+    if ((d & 3) == 0) {
+      for (int i = 0; i < d; i += 4) {
+        const float4 v = *reinterpret_cast<const float4 *>(x + i);
+        nn = fmaf(v.x, v.x, nn); nn = fmaf(v.y, v.y, nn);
+        nn = fmaf(v.z, v.z, nn); nn = fmaf(v.w, v.w, nn);
+        coord_check(v.x, bad, lo, hi); coord_check(v.y, bad, lo, hi);
+        coord_check(v.z, bad, lo, hi); coord_check(v.w, bad, lo, hi);
 #pragma unroll
-      for (int b = 0; b < 16; ++b) {
-        if (b < m) {
-          const float *h = sH + b * d + i;
-          s[b] = fmaf(h[0], v.x, s[b]); s[b] = fmaf(h[1], v.y, s[b]);
-          s[b] = fmaf(h[2], v.z, s[b]); s[b] = fmaf(h[3], v.w, s[b]);
+        for (int b = 0; b < 16; ++b) {
+          if (b < m) {
+            const float *h = sH + b * d + i;
+            s[b] = fmaf(h[0], v.x, s[b]); s[b] = fmaf(h[1], v.y, s[b]);
+            s[b] = fmaf(h[2], v.z, s[b]); s[b] = fmaf(h[3], v.w, s[b]);
+          }
         }
       }
-    }
-  } else {
-    for (int i = 0; i < d; ++i) {
-      const float v = x[i];
-      nn = fmaf(v, v, nn);
+    } else {
+      for (int i = 0; i < d; ++i) {
+        const float v = x[i];
+        nn = fmaf(v, v, nn);
+        coord_check(v, bad, lo, hi);
 #pragma unroll
-      for (int b = 0; b < 16; ++b)
-        if (b < m) s[b] = fmaf(sH[b * d + i], v, s[b]);
+        for (int b = 0; b < 16; ++b)
+          if (b < m) s[b] = fmaf(sH[b * d + i], v, s[b]);
+      }
+    }
+    norms[p] = nn;
+#pragma unroll
+    for (int b = 0; b < 16; ++b)
+      if (b < m) S[p * m + b] = s[b];
+  }
+  // the wave's check (lanes past n hold the neutral +inf / -inf)
+  const bool wbad = __ballot(bad) != 0ull;
+  if (!wbad) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+      lo = fminf(lo, __shfl_xor(lo, off, 64));
+      hi = fmaxf(hi, __shfl_xor(hi, off, 64));
     }
   }
-  norms[p] = nn;
-#pragma unroll
-  for (int b = 0; b < 16; ++b)
-    if (b < m) S[p * m + b] = s[b];
+  if ((threadIdx.x & 63) == 0 && chk) {
+    if (wbad) {
+      if (*(volatile int *)chk == 0) atomicOr(chk, 1);
+    } else if (lo <= hi) {  // some lane of the wave holds a point
+      const int ilo = (int)lo, ihi = (int)hi;
+      if (*(volatile int *)(chk + 1) > ilo) atomicMin(chk + 1, ilo);
+      if (*(volatile int *)(chk + 2) < ihi) atomicMax(chk + 2, ihi);
+    }
+  }
 }
 
 hipError_t launch_norms_sketches(const Index &I, hipStream_t s) {
@@ -63,8 +98,54 @@ hipError_t launch_norms_sketches_range(const Index &I, int64_t p0, int64_t cnt, 
   const size_t lds = (size_t)I.m * I.d * sizeof(float);
   hipLaunchKernelGGL(norms_sketches_kernel, dim3((unsigned)blocks), dim3(256), lds, s,
                      I.xf() + p0 * I.d, cnt, I.d, I.H, I.m, I.norms.as<float>() + p0,
-                     I.sketches.as<float>() + p0 * I.m);
+                     I.sketches.as<float>() + p0 * I.m, I.int_chk.as<int>());
   return hipGetLastError();
+}
+
+__global__ void int_check_init_kernel(int *chk) {
+  if (threadIdx.x == 0) {
+    chk[0] = 0;
+    chk[1] = 0x7FFFFFFF;
+    chk[2] = (int)0x80000000;
+  }
+}
+
+hipError_t clear_int_check(Index &I, hipStream_t s) {
+  hipLaunchKernelGGL(int_check_init_kernel, dim3(1), dim3(64), 0, s, I.int_chk.as<int>());
+  return hipGetLastError();
+}
+
+// Every distance form is exact in float32 when the coordinates are integers
+// whose squared norms sum to at most 2^24 for any pair (d * A^2 <= 2^23,
+// A = the largest magnitude) and whose squared differences sum to at most
+// 2^24 (d * W^2 <= 2^24, W = the range): every product, partial sum and
+// result of the direct difference, the norms and the norm expansion is then
+// an integer of magnitude <= 2^24.
+hipError_t read_int_check(Index &I, bool reset, hipStream_t s) {
+  int32_t h[3] = {1, 0, 0};
+  hipError_t e = hipMemcpyAsync(h, I.int_chk.p, sizeof(h), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return e;
+  const bool had = !reset && I.int_exact;
+  if (h[0] != 0 || (!reset && !I.int_exact)) {
+    I.int_exact = false;
+    return hipSuccess;
+  }
+  int64_t lo = h[1], hi = h[2];
+  if (lo > hi) {  // no points were checked
+    I.int_exact = had;
+    return hipSuccess;
+  }
+  if (had) {
+    lo = std::min(lo, I.int_lo);
+    hi = std::max(hi, I.int_hi);
+  }
+  const int64_t A = std::max(-lo, hi), W = hi - lo;
+  const int64_t d = I.d;
+  I.int_lo = lo;
+  I.int_hi = hi;
+  I.int_exact = d * A * A <= (int64_t(1) << 23) && d * W * W <= (int64_t(1) << 24);
+  return hipSuccess;
 }
 
 // ---- reduced-precision GEMM operand -------------------------------------

@@ -390,6 +390,57 @@ def test_exact_16bit_operand_build(exact_build, prec):
     idx.close()
 
 
+@pytest.mark.parametrize("lo,hi,d,want", [
+    (0, 255, 128, 1),      # d * 255^2 <= 2^23: the 8-bit workloads
+    (0, 256, 128, 1),      # d * A^2 == 2^23 exactly
+    (0, 257, 128, 0),      # d * A^2 > 2^23
+    (-128, 127, 128, 1),
+    (-200, 200, 128, 0),   # A fits, the range does not: d * W^2 > 2^24
+    (0, 1020, 128, 0),
+    (0, 511, 32, 1),       # fewer dimensions, wider values
+])
+def test_integer_check(lo, hi, d, want):
+    """The check behind skipping the winners' recompute (every distance form
+    an exact integer in float32): integral coordinates, d*A^2 <= 2^23 and
+    d*W^2 <= 2^24. Non-integral data never passes; prepare takes the check
+    again after the caller changes X in place."""
+    rng = np.random.default_rng(abs(lo) * 7 + hi + d)
+    X = rng.integers(lo, hi + 1, size=(3001, d)).astype(np.float32)
+    X[0, 0], X[1, 1] = lo, hi            # the extremes are present
+    H = pi.hyperplanes(8, d, 1, integer=True)
+    Xd = dev(X)
+    idx = pp.Index(Xd, dev(H), gpu_params(k=4))
+    assert idx.stats()["data_int_exact"] == want
+    Xd[5, 0] += 0.5                      # one non-integral coordinate
+    idx.prepare()
+    assert idx.stats()["data_int_exact"] == 0
+    Xd[5, 0] -= 0.5
+    idx.prepare()
+    assert idx.stats()["data_int_exact"] == want
+    idx.close()
+
+
+def test_leaf_pick_without_recompute_matches_recompute(exact_build):
+    """On integer data within the bound the leaf pick emits the GEMM distance
+    (no recompute); the same leaves with rescoring (which always recomputes,
+    and on exact distances keeps the same winners) give the same picks and
+    the same distances, and both equal the oracle's."""
+    X, H, p, ref = exact_build
+    idx = pp.Index(dev(X), dev(H), p)
+    assert idx.stats()["data_int_exact"] == 1
+    oc, od = idx.leaf_pick(dev(ref["offsets"]), dev(ref["members"]))
+    kw = {f: getattr(p, f) for f in ("c_max", "c_min", "k", "l_max", "R", "seed")}
+    idx2 = pp.Index(dev(X), dev(H), gpu_params(rescore_mult=2, **kw))
+    oc2, od2 = idx2.leaf_pick(dev(ref["offsets"]), dev(ref["members"]))
+    torch.cuda.synchronize()
+    assert np.array_equal(u32(oc), u32(oc2))
+    assert np.array_equal(od.cpu().numpy(), od2.cpu().numpy())
+    valid = ref["cand"] != oracle.EMPTY_ID
+    assert np.array_equal(od.cpu().numpy()[valid].astype(np.float64), ref["dist"][valid])
+    idx.close()
+    idx2.close()
+
+
 def test_replicated_build_bit_exact(exact_build):
     """Two independent partitions (replication) into the same reservoirs:
     the second carving's leaves and the final reservoirs and graph equal the
