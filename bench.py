@@ -72,6 +72,14 @@ def parse():
     ap.add_argument("--variants", default="bf16:0,bf16:2,fp8:2,fp32:0:2",
                     help="other forms (prec:rescore_mult[:replicas], comma separated) built and "
                          "timed after the main one on the same workload; '' for none")
+    ap.add_argument("--frontier", action="store_true",
+                    help="also build (float32) with other fanouts, leaf k and l_max, and report "
+                         "each one's build rate, the beam width reaching recall@10 >= 0.95 and "
+                         "the search QPS there")
+    ap.add_argument("--knn-graph", default="",
+                    help="beam widths (comma separated): search every point of the main build's "
+                         "graph for its 10 nearest other points (an approximate 10-NN graph), "
+                         "timed, with recall@10 on a sample of 10,000 points")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="after the timed steps, copy this many MiB once (a plain copy of known "
                          "size, used to scale hardware byte counters)")
@@ -99,6 +107,60 @@ def ground_truth(torch, Xd, Qd, metric=0, k=10):
             kth[q0:q0 + 512] = dd.max(1).values
         del D
     return kth
+
+
+# Settings of the frontier: the paper's knobs around the workload's own
+# (fanout {2,1,1,1}, leaf k 16, l_max 64): the leaf k, the reservoir bound
+# and single- or multi-level fanout.
+FRONTIER = [
+    {"fanout": (2, 1, 1, 1), "k": 16, "l_max": 64},
+    {"fanout": (2, 1, 1, 1), "k": 8, "l_max": 64},
+    {"fanout": (2, 1, 1, 1), "k": 12, "l_max": 64},
+    {"fanout": (2, 1, 1, 1), "k": 24, "l_max": 64},
+    {"fanout": (2, 1, 1, 1), "k": 16, "l_max": 32},
+    {"fanout": (2, 1, 1, 1), "k": 16, "l_max": 48},
+    {"fanout": (3, 1, 1, 1), "k": 16, "l_max": 64},
+    {"fanout": (2, 2, 1, 1), "k": 16, "l_max": 64},
+    {"fanout": (3, 2, 1, 1), "k": 12, "l_max": 64},
+]
+
+
+def knn_graph_stage(torch, np, idx, g, Xd, w, Ls, sample=10000):
+    """Approximate 10-NN graph of the points: every point searched on the
+    built graph (11 results, its own id dropped, else the 11th), in batches
+    whose visited bitmaps (n bits per query) stay within 1 GiB; recall@10 on
+    a sample against exact ground truth (the 11th nearest including itself is
+    the 10th nearest other point)."""
+    n = Xd.shape[0]
+    start = idx.start_node()
+    rng = np.random.default_rng(2602)
+    samp = np.sort(rng.choice(n, size=min(sample, n), replace=False)).astype(np.int64)
+    sd = torch.from_numpy(samp).cuda()
+    kth = ground_truth(torch, Xd, Xd[sd], w.metric, k=11)
+    chunk = max(1, min(8192, (1 << 30) // (((n + 31) // 32) * 4)))
+    out = []
+    for L in Ls:
+        ids_all = torch.empty((n, 11), dtype=torch.int32, device="cuda")
+        dist_all = torch.empty((n, 11), dtype=torch.float32, device="cuda")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for q0 in range(0, n, chunk):
+            q1 = min(n, q0 + chunk)
+            ids, dist, _ = idx.search(g, Xd[q0:q1], 11, max(11, L), start, want_cmps=False)
+            ids_all[q0:q1] = ids
+            dist_all[q0:q1] = dist
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        si, sdist = ids_all[sd], dist_all[sd]
+        own = si == sd[:, None].to(torch.int32)
+        keep = ~own
+        keep[:, 10] &= own.any(1)  # no own id among the 11: the 11th is dropped
+        hits = ((sdist.double() <= kth[:, None]) & keep).sum().item()
+        r = hits / (10.0 * len(samp))
+        log(f"[bench] knn graph: L={L} {t:.2f} s ({n / t:.0f} points/s), recall@10 {r:.4f}")
+        out.append({"L": L, "seconds": t, "points_per_s": n / t, "recall_at_10_sampled": r,
+                    "sample": len(samp), "batch": chunk})
+    return out
 
 
 # the sources of the float32 leaf kernel (four-lane layout) the committed
@@ -355,26 +417,29 @@ def main():
         leaves = (torch.from_numpy(lo).cuda(), torch.from_numpy(lm.view(np.int32)).cuda())
         log(f"[bench] explicit leaves: {len(lo) - 1}, sizes {np.diff(lo).min()}..{np.diff(lo).max()}")
 
-    def run_form(prec, mult, steps, warmup, keep=False, replicas=1):
+    def run_form(prec, mult, steps, warmup, keep=False, replicas=1, over=None):
         """Build the whole index `warmup + steps` times with one leaf-GEMM
         form (and `replicas` independent partitions feeding the reservoirs);
         time the last `steps`; search the last graph for recall@10.
         With given leaves, the leaf kernel is autotuned on them, one eager
         build is profiled for the phase times, and the timed builds are
-        replays of one captured HIP graph of the whole step."""
-        p = pp.default_params(metric=w.metric, c_max=w.c_max, c_min=w.c_min, k=w.k,
-                              l_max=w.l_max, R=w.R, alpha=w.alpha, hash_bits=w.hash_bits,
-                              leader_div=w.leader_div, leader_cap=w.leader_cap, fanout=w.fanout,
+        replays of one captured HIP graph of the whole step. `over` replaces
+        the workload's fanout, k or l_max."""
+        over = over or {}
+        fk, fl, ff = over.get("k", w.k), over.get("l_max", w.l_max), over.get("fanout", w.fanout)
+        p = pp.default_params(metric=w.metric, c_max=w.c_max, c_min=w.c_min, k=fk,
+                              l_max=fl, R=w.R, alpha=w.alpha, hash_bits=w.hash_bits,
+                              leader_div=w.leader_div, leader_cap=w.leader_cap, fanout=ff,
                               seed=pi.workload_seed(cfg), gemm_prec=PREC_CODES[prec],
                               rescore_mult=mult)
         idx = pp.Index(Xd, Hd, p)
-        res = torch.empty((n, w.l_max), dtype=torch.int64, device="cuda")
+        res = torch.empty((n, fl), dtype=torch.int64, device="cuda")
         tune = None
 
         if leaves is None:
             def step():
                 idx.prepare()
-                pp.reservoir_init(n, w.l_max, out=res)
+                pp.reservoir_init(n, fl, out=res)
                 for r in range(replicas):
                     off, mem = idx.partition(r)
                     idx.build_leaves(off, mem, res)
@@ -404,7 +469,7 @@ def main():
 
             def step():
                 idx.prepare()
-                pp.reservoir_init(n, w.l_max, out=res)
+                pp.reservoir_init(n, fl, out=res)
                 idx.build_leaves(off, mem, res)
                 idx.robustprune(res, g, deg)
 
@@ -439,7 +504,7 @@ def main():
         achieved = flops_per_launch / avg_launch_s / 1e12
         phases = {k: st[k] / steps for k in ("ms_prepare", "ms_partition", "ms_leaf_knn",
                                               "ms_bin", "ms_merge", "ms_robustprune")}
-        recall, l_at, curve = None, None, {}
+        recall, l_at, curve, qps = None, None, {}, None
         if Qd is not None:
             start = idx.start_node()
             nq = Qd.shape[0]
@@ -454,12 +519,20 @@ def main():
                     break
             if recall is None:
                 recall = max(v["recall"] for v in curve.values())
+            # search throughput at that beam width: the same batch once more, timed
+            torch.cuda.synchronize()
+            tq = time.perf_counter()
+            idx.search(g, Qd, 10, l_at or RECALL_LS[-1], start, want_cmps=False)
+            torch.cuda.synchronize()
+            qps = nq / (time.perf_counter() - tq)
         form = {"prec": prec, "rescore_mult": mult, "replicas": replicas, "ms_per_step": ms,
                 "value": n / (ms / 1000.0),
                 "leaf_gemm_tflops": achieved, "peak": PEAK_MFMA_TFLOPS[prec],
                 "frac": achieved / PEAK_MFMA_TFLOPS[prec], "recall_at_10": recall,
-                "L_at_recall_0.95": l_at, "recall_curve": curve, "phase_ms": phases,
-                "stats": st, "autotune": tune}
+                "L_at_recall_0.95": l_at, "search_qps_at_L": qps, "recall_curve": curve,
+                "phase_ms": phases, "stats": st, "autotune": tune}
+        if over:
+            form["params"] = {"fanout": list(ff), "k": fk, "l_max": fl}
         if keep:
             form["_out"] = (idx, res, off, mem, g, deg)
         else:
@@ -497,6 +570,20 @@ def main():
         f = run_form(vp, vm, args.steps, 1, replicas=vr)
         f.pop("stats")
         variants.append(f)
+
+    frontier = None
+    if args.frontier and leaves is None:
+        frontier = []
+        for o in FRONTIER:
+            f = run_form("fp32", 0, 2, 1, over=o)
+            f.pop("stats")
+            f.pop("recall_curve")
+            frontier.append(f)
+
+    knn_graph = None
+    if args.knn_graph:
+        knn_graph = knn_graph_stage(torch, np, idx, g, Xd, w,
+                                    [int(v) for v in args.knn_graph.split(",") if v.strip()])
 
     serve = None
     if not args.no_serving and cfg in (2, 3):
@@ -542,6 +629,10 @@ def main():
         "cpu_baseline": cpu,
         "variants": variants,
     }
+    if frontier is not None:
+        line["frontier"] = frontier
+    if knn_graph is not None:
+        line["knn_graph"] = knn_graph
     print(json.dumps(line), flush=True)
     idx.close()
 
