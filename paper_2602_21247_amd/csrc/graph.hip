@@ -309,8 +309,10 @@ __global__ void __launch_bounds__(64 * kRpWaves, 4) robustprune_mfma_kernel(
   // 2. fragments F0 (slots 0..31) and F1 (slots 32..63), taken CH
   //    dimensions of each half at a time: each chunk's rows feed the direct
   //    sums for d(x, c) (continued in index order) and the Gram's MFMAs (in
-  //    the same k order as whole rows would), so only one chunk is live
-  constexpr int CH = HALF < 16 ? HALF : 16;
+  //    the same k order as whole rows would). The next chunk's rows are
+  //    loaded into registers while the current chunk's MFMAs run, so two
+  //    chunks are live.
+  constexpr int CH = HALF < 8 ? HALF : 8;
   static_assert(HALF % CH == 0, "chunking");
   f32x16 g00, g01, g11;
 #pragma unroll
@@ -324,28 +326,39 @@ __global__ void __launch_bounds__(64 * kRpWaves, 4) robustprune_mfma_kernel(
     const float *r1 = X + (int64_t)c1 * d + kb;
     const float *rx = X + (int64_t)x * d + kb;
     const bool both = nv > 32;
-#pragma unroll 2
-    for (int k0 = 0; k0 < HALF; k0 += CH) {
-      float f0[CH], f1[CH], fx[CH];
+    float n0[CH], n1[CH], nx[CH];
+    auto load_chunk = [&](int k0) {
       if (full_d) {
 #pragma unroll
         for (int j = 0; j < CH; j += 4) {
           const float4 q0 = *reinterpret_cast<const float4 *>(r0 + k0 + j);
           const float4 q1 = *reinterpret_cast<const float4 *>(r1 + k0 + j);
           const float4 qx = *reinterpret_cast<const float4 *>(rx + k0 + j);
-          f0[j] = q0.x; f0[j + 1] = q0.y; f0[j + 2] = q0.z; f0[j + 3] = q0.w;
-          f1[j] = q1.x; f1[j + 1] = q1.y; f1[j + 2] = q1.z; f1[j + 3] = q1.w;
-          fx[j] = qx.x; fx[j + 1] = qx.y; fx[j + 2] = qx.z; fx[j + 3] = qx.w;
+          n0[j] = q0.x; n0[j + 1] = q0.y; n0[j + 2] = q0.z; n0[j + 3] = q0.w;
+          n1[j] = q1.x; n1[j + 1] = q1.y; n1[j + 2] = q1.z; n1[j + 3] = q1.w;
+          nx[j] = qx.x; nx[j + 1] = qx.y; nx[j + 2] = qx.z; nx[j + 3] = qx.w;
         }
       } else {
 #pragma unroll
         for (int j = 0; j < CH; ++j) {
           const bool in = kb + k0 + j < d;
-          f0[j] = in ? r0[k0 + j] : 0.f;
-          f1[j] = in ? r1[k0 + j] : 0.f;
-          fx[j] = in ? rx[k0 + j] : 0.f;
+          n0[j] = in ? r0[k0 + j] : 0.f;
+          n1[j] = in ? r1[k0 + j] : 0.f;
+          nx[j] = in ? rx[k0 + j] : 0.f;
         }
       }
+    };
+    load_chunk(0);
+#pragma unroll
+    for (int k0 = 0; k0 < HALF; k0 += CH) {
+      float f0[CH], f1[CH], fx[CH];
+#pragma unroll
+      for (int j = 0; j < CH; ++j) {
+        f0[j] = n0[j];
+        f1[j] = n1[j];
+        fx[j] = nx[j];
+      }
+      if (k0 + CH < HALF) load_chunk(k0 + CH);
 #pragma unroll
       for (int j = 0; j < CH; ++j) {
         if (l2) {

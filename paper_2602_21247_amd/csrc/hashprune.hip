@@ -122,22 +122,40 @@ __global__ void __launch_bounds__(256) bin_scatter_kernel(const uint32_t *row_id
 // pick). The records and their bins are those of the global scheme; only
 // their order inside a bin differs, which the merge does not see.
 
+// The scatter pass stages the leaf's member sketches in LDS when they fit
+// beside the row counters (about 1,200 rows at m = 12), so each record's two
+// hashes compare LDS copies instead of gathering two sketches from memory;
+// larger leaves read the sketches from memory. The compares are the same.
+constexpr int kLeafBinLds = kLeafBinMaxRows * 20;  // bytes: int64 base + 3 uint32 counters per row
+
 template <bool SCATTER>
 __global__ void __launch_bounds__(256) leaf_bin_kernel(
     const int64_t *__restrict__ leaf_off, int64_t off0, const uint32_t *__restrict__ members,
     const uint32_t *__restrict__ picks, const float *__restrict__ dist, int k,
     const float *__restrict__ S, int m, const int64_t *__restrict__ bin_off,
     uint32_t *__restrict__ cnt, uint64_t *__restrict__ bins) {
-  __shared__ uint32_t sF[kLeafBinMaxRows];   // forward records of each row (count, then cursor)
-  __shared__ uint32_t sR[kLeafBinMaxRows];   // reverse records of each row (count, then cursor)
-  __shared__ uint32_t sRn[SCATTER ? kLeafBinMaxRows : 1];  // reverse total of each row
-  __shared__ int64_t sB[SCATTER ? kLeafBinMaxRows : 1];    // the row's first bin position
+  // per row: sB (the row's first bin position), sF / sR (forward / reverse
+  // records: count, then cursor), sRn (reverse total); then the sketches
+  __shared__ __attribute__((aligned(16))) uint8_t sMem[SCATTER ? kLeafBinLds : kLeafBinMaxRows * 8];
   const int64_t r0 = leaf_off[blockIdx.x] - off0;
   const int mm = (int)(leaf_off[blockIdx.x + 1] - off0 - r0);
+  const bool lds_sk = SCATTER && (int64_t)mm * (20 + 4 * m) <= kLeafBinLds;
+  const int cap = lds_sk ? mm : kLeafBinMaxRows;
+  int64_t *sB = reinterpret_cast<int64_t *>(sMem);
+  uint32_t *sF = reinterpret_cast<uint32_t *>(sMem + (SCATTER ? (size_t)cap * 8 : 0));
+  uint32_t *sR = sF + cap;
+  uint32_t *sRn = sR + cap;
+  float *sS = reinterpret_cast<float *>(sRn + cap);
   const int tid = threadIdx.x;
   for (int r = tid; r < mm; r += 256) {
     sF[r] = 0u;
     sR[r] = 0u;
+  }
+  if (lds_sk) {
+    for (int t = tid; t < mm * m; t += 256) {
+      const int r = t / m;
+      sS[t] = S[(int64_t)members[r0 + r] * m + (t - r * m)];
+    }
   }
   __syncthreads();
   const int tot = mm * k;
@@ -170,7 +188,20 @@ __global__ void __launch_bounds__(256) leaf_bin_kernel(
       if (c < (uint32_t)mm && c != (uint32_t)r) {
         const uint32_t i = members[r0 + r], j = members[r0 + c];
         uint32_t hij, hji;
-        hash_pair(S, m, i, j, hij, hji);
+        if (lds_sk) {
+          // bit b of h_i(j): Sketch(j)_b >= Sketch(i)_b; of h_j(i): the reverse
+          const float *si = sS + r * m, *sj = sS + c * m;
+          uint32_t a = 0, b = 0;
+          for (int e = 0; e < m; ++e) {
+            const float x = si[e], y = sj[e];
+            a |= (y >= x ? 1u : 0u) << e;
+            b |= (x >= y ? 1u : 0u) << e;
+          }
+          hij = a;
+          hji = b;
+        } else {
+          hash_pair(S, m, i, j, hij, hji);
+        }
         const uint32_t bf = bf16_rne(dist[g]);
         const uint32_t pf = atomicSub(&sF[r], 1u) - 1u;
         bins[sB[r] + sRn[r] + pf] = slot_pack(j, hij, bf);
