@@ -299,7 +299,6 @@ hipError_t launch_rec_scatter(const uint32_t *dst, const uint32_t *cand, const f
 }
 
 // ---------------------------------------------------------------------
-constexpr int kMergeArr = 512;          // LDS entries per wave and array
 constexpr int kMergeWaves = 4;
 constexpr uint64_t kNone = ~0ull;
 
@@ -347,13 +346,17 @@ __device__ __forceinline__ int pow2_at_least(int v) {
   return P;
 }
 
+// ARR: LDS entries per wave for the reservoir plus one chunk of records
+// (the table has 2 ARR); a point's records are taken ARR - l_max at a time.
+// The smaller arrays (l_max <= 128) keep twice the waves resident.
+template <int ARR>
 __global__ void __launch_bounds__(64 * kMergeWaves) hashprune_merge_kernel(
     uint64_t *__restrict__ res, int64_t n, int l_max, const uint64_t *__restrict__ bins,
     const int64_t *__restrict__ off) {
   // sT: open-addressing table of bucket minima (key1, hashed by bucket);
   // sB: the reservoir in key2 order
-  __shared__ uint64_t sT[kMergeWaves][2 * kMergeArr];
-  __shared__ uint64_t sB[kMergeWaves][kMergeArr];
+  __shared__ uint64_t sT[kMergeWaves][2 * ARR];
+  __shared__ uint64_t sB[kMergeWaves][ARR];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t p = (int64_t)blockIdx.x * kMergeWaves + wave;
   if (p >= n) return;
@@ -376,7 +379,7 @@ __global__ void __launch_bounds__(64 * kMergeWaves) hashprune_merge_kernel(
   }
   wave_sync();
 
-  const int chunk_cap = kMergeArr - l_max;
+  const int chunk_cap = ARR - l_max;
   for (int64_t c0 = b0; c0 < b1; c0 += chunk_cap) {
     const int nc = (int)min((int64_t)chunk_cap, b1 - c0);
     const int tot = nres + nc;
@@ -429,8 +432,12 @@ hipError_t launch_hashprune_merge(uint64_t *res, int64_t n, int32_t l_max, const
                                   const int64_t *off, hipStream_t s) {
   if (l_max > 256) return hipErrorInvalidValue;
   const int64_t blocks = (n + kMergeWaves - 1) / kMergeWaves;
-  hipLaunchKernelGGL(hashprune_merge_kernel, dim3((unsigned)blocks), dim3(64 * kMergeWaves), 0, s,
-                     res, n, l_max, bins, off);
+  if (l_max <= 128)
+    hipLaunchKernelGGL(hashprune_merge_kernel<256>, dim3((unsigned)blocks), dim3(64 * kMergeWaves),
+                       0, s, res, n, l_max, bins, off);
+  else
+    hipLaunchKernelGGL(hashprune_merge_kernel<512>, dim3((unsigned)blocks), dim3(64 * kMergeWaves),
+                       0, s, res, n, l_max, bins, off);
   return hipGetLastError();
 }
 
