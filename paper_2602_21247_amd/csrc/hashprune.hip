@@ -127,9 +127,10 @@ __global__ void __launch_bounds__(256) bin_scatter_kernel(const uint32_t *row_id
 // hashes compare LDS copies instead of gathering two sketches from memory;
 // larger leaves read the sketches from memory. The compares are the same.
 constexpr int kLeafBinLds = kLeafBinMaxRows * 20;  // bytes: int64 base + 3 uint32 counters per row
+constexpr int kLeafBinThreads = 1024;  // 16 waves: the LDS admits two workgroups per CU
 
 template <bool SCATTER>
-__global__ void __launch_bounds__(256) leaf_bin_kernel(
+__global__ void __launch_bounds__(kLeafBinThreads) leaf_bin_kernel(
     const int64_t *__restrict__ leaf_off, int64_t off0, const uint32_t *__restrict__ members,
     const uint32_t *__restrict__ picks, const float *__restrict__ dist, int k,
     const float *__restrict__ S, int m, const int64_t *__restrict__ bin_off,
@@ -147,19 +148,19 @@ __global__ void __launch_bounds__(256) leaf_bin_kernel(
   uint32_t *sRn = sR + cap;
   float *sS = reinterpret_cast<float *>(sRn + cap);
   const int tid = threadIdx.x;
-  for (int r = tid; r < mm; r += 256) {
+  for (int r = tid; r < mm; r += kLeafBinThreads) {
     sF[r] = 0u;
     sR[r] = 0u;
   }
   if (lds_sk) {
-    for (int t = tid; t < mm * m; t += 256) {
+    for (int t = tid; t < mm * m; t += kLeafBinThreads) {
       const int r = t / m;
       sS[t] = S[(int64_t)members[r0 + r] * m + (t - r * m)];
     }
   }
   __syncthreads();
   const int tot = mm * k;
-  for (int t = tid; t < tot; t += 256) {
+  for (int t = tid; t < tot; t += kLeafBinThreads) {
     const int r = t / k;
     const uint32_t c = picks[(r0 + r) * k + (t - r * k)];
     if (c < (uint32_t)mm && c != (uint32_t)r) {
@@ -169,19 +170,19 @@ __global__ void __launch_bounds__(256) leaf_bin_kernel(
   }
   __syncthreads();
   if constexpr (!SCATTER) {
-    for (int r = tid; r < mm; r += 256) {
+    for (int r = tid; r < mm; r += kLeafBinThreads) {
       const uint32_t n_r = sF[r] + sR[r];
       if (n_r) atomicAdd(&cnt[members[r0 + r]], n_r);
     }
   } else {
-    for (int r = tid; r < mm; r += 256) {
+    for (int r = tid; r < mm; r += kLeafBinThreads) {
       const uint32_t n_r = sF[r] + sR[r];
       const uint32_t p = members[r0 + r];
       sRn[r] = sR[r];
       sB[r] = n_r ? bin_off[p] + atomicAdd(&cnt[p], n_r) : 0;
     }
     __syncthreads();
-    for (int t = tid; t < tot; t += 256) {
+    for (int t = tid; t < tot; t += kLeafBinThreads) {
       const int r = t / k;
       const int64_t g = (r0 + r) * k + (t - r * k);
       const uint32_t c = picks[g];
@@ -218,10 +219,10 @@ hipError_t launch_leaf_bin(bool scatter, const int64_t *leaf_off, int64_t off0, 
                            uint32_t *cnt, uint64_t *bins, hipStream_t s) {
   if (n_leaves <= 0) return hipSuccess;
   if (scatter)
-    hipLaunchKernelGGL(leaf_bin_kernel<true>, dim3((unsigned)n_leaves), dim3(256), 0, s, leaf_off,
+    hipLaunchKernelGGL(leaf_bin_kernel<true>, dim3((unsigned)n_leaves), dim3(kLeafBinThreads), 0, s, leaf_off,
                        off0, members, picks, dist, k, sketch, m, bin_off, cnt, bins);
   else
-    hipLaunchKernelGGL(leaf_bin_kernel<false>, dim3((unsigned)n_leaves), dim3(256), 0, s, leaf_off,
+    hipLaunchKernelGGL(leaf_bin_kernel<false>, dim3((unsigned)n_leaves), dim3(kLeafBinThreads), 0, s, leaf_off,
                        off0, members, picks, dist, k, sketch, m, bin_off, cnt, bins);
   return hipGetLastError();
 }
