@@ -8,8 +8,8 @@ namespace pipnn {
 // ---------------------------------------------------------------------
 // Squared norms (for the GEMM distance form) and sketches
 // Sketch(v)_b = H_b . v (Sec. 3, Implementation). One thread per point
-// reads its row with 16-byte loads and accumulates every output in
-// dimension order; the hyperplanes are broadcast from LDS. The same pass
+// accumulates every output in dimension order; the rows are staged through
+// LDS and the hyperplanes broadcast from it. The same pass
 // takes the integer check: chk[0] is set when a coordinate is not an
 // integer of magnitude <= 2^20, chk[1] / chk[2] collect the smallest and
 // largest coordinate (one atomic per wave, only when it would change them).
@@ -24,49 +24,57 @@ __global__ void __launch_bounds__(256) norms_sketches_kernel(const float *__rest
                                                              int m, float *__restrict__ norms,
                                                              float *__restrict__ S,
                                                              int *__restrict__ chk) {
-  extern __shared__ float sH[];  // m x d
+  // The block's 256 rows pass through LDS 16 dimensions at a time: the slab
+  // is loaded with consecutive lanes on consecutive 16-byte pieces of the
+  // rows (coalesced), then each thread continues its own row's sums in
+  // dimension order from LDS.
+  constexpr int KD = 16;
+  extern __shared__ float sH[];                 // m x d
+  __shared__ float sX[256][KD + 1];             // the slab (+1: conflict-free row reads)
   for (int i = threadIdx.x; i < m * d; i += blockDim.x) sH[i] = H[i];
-  __syncthreads();
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t p0 = (int64_t)blockIdx.x * 256;
+  const int64_t p = p0 + threadIdx.x;
+  const int rows = (int)min<int64_t>(256, n - p0);
   bool bad = false;
   float lo = INFINITY, hi = -INFINITY;
-  if (p < n) {
-    const float *x = X + p * d;
-    lo = hi = x[0];
-    float nn = 0.f;
-    float s[16];
+  float nn = 0.f;
+  float sk[16];
 #pragma unroll
-    for (int b = 0; b < 16; ++b) s[b] = 0.f;
+  for (int b = 0; b < 16; ++b) sk[b] = 0.f;
+  for (int k0 = 0; k0 < d; k0 += KD) {
+    const int kw = min(KD, d - k0);
+    __syncthreads();  // the previous slab is consumed (and sH is loaded)
     if ((d & 3) == 0) {
-      for (int i = 0; i < d; i += 4) {
-        const float4 v = *reinterpret_cast<const float4 *>(x + i);
-        nn = fmaf(v.x, v.x, nn); nn = fmaf(v.y, v.y, nn);
-        nn = fmaf(v.z, v.z, nn); nn = fmaf(v.w, v.w, nn);
-        coord_check(v.x, bad, lo, hi); coord_check(v.y, bad, lo, hi);
-        coord_check(v.z, bad, lo, hi); coord_check(v.w, bad, lo, hi);
-#pragma unroll
-        for (int b = 0; b < 16; ++b) {
-          if (b < m) {
-            const float *h = sH + b * d + i;
-            s[b] = fmaf(h[0], v.x, s[b]); s[b] = fmaf(h[1], v.y, s[b]);
-            s[b] = fmaf(h[2], v.z, s[b]); s[b] = fmaf(h[3], v.w, s[b]);
-          }
-        }
+      // kw is a multiple of 4: 4-float pieces, kw / 4 per row
+      const int pr = kw >> 2;
+      for (int t = threadIdx.x; t < rows * pr; t += 256) {
+        const int r = t / pr, c = (t - r * pr) * 4;
+        const float4 v = *reinterpret_cast<const float4 *>(X + (p0 + r) * d + k0 + c);
+        sX[r][c] = v.x; sX[r][c + 1] = v.y; sX[r][c + 2] = v.z; sX[r][c + 3] = v.w;
       }
     } else {
-      for (int i = 0; i < d; ++i) {
-        const float v = x[i];
+      for (int t = threadIdx.x; t < rows * kw; t += 256) {
+        const int r = t / kw, c = t - r * kw;
+        sX[r][c] = X[(p0 + r) * d + k0 + c];
+      }
+    }
+    __syncthreads();
+    if (p < n) {
+      for (int j = 0; j < kw; ++j) {
+        const float v = sX[threadIdx.x][j];
         nn = fmaf(v, v, nn);
         coord_check(v, bad, lo, hi);
 #pragma unroll
         for (int b = 0; b < 16; ++b)
-          if (b < m) s[b] = fmaf(sH[b * d + i], v, s[b]);
+          if (b < m) sk[b] = fmaf(sH[b * d + k0 + j], v, sk[b]);
       }
     }
+  }
+  if (p < n) {
     norms[p] = nn;
 #pragma unroll
     for (int b = 0; b < 16; ++b)
-      if (b < m) S[p * m + b] = s[b];
+      if (b < m) S[p * m + b] = sk[b];
   }
   // the wave's check (lanes past n hold the neutral +inf / -inf)
   const bool wbad = __ballot(bad) != 0ull;
