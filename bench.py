@@ -393,8 +393,8 @@ def main():
         print("bench.py needs a ROCm GPU", file=sys.stderr)
         sys.exit(2)
     if not os.path.exists(pp.LIB_PATH):
-        from paper_2602_21247_amd import build as libbuild
-        libbuild.build()
+        from paper_2602_21247_amd import hipbuild
+        hipbuild.build()
     cfg = args.workload
     w = pi.WORKLOADS[cfg]
     if args.prec is None:

@@ -71,7 +71,7 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with "
-                               "python -m paper_2602_21247_amd.build")
+                               "python -m paper_2602_21247_amd.hipbuild")
         L = C.CDLL(LIB_PATH)
         P, i64, i32, u32 = C.c_void_p, C.c_int64, C.c_int32, C.c_uint32
         L.pipnn_version.restype = C.c_char_p

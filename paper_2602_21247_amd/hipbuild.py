@@ -2,7 +2,7 @@
 
 Every HIP source is compiled for gfx950 only, with packed-FP32 code
 generation turned off, then linked into one shared library next to this
-file. Run ``python -m paper_2602_21247_amd.build``.
+file. Run ``python -m paper_2602_21247_amd.hipbuild``.
 """
 from __future__ import annotations
 

@@ -23,8 +23,8 @@ def _declared():
 @pytest.fixture(scope="module")
 def L():
     if not os.path.exists(pp.LIB_PATH):
-        from paper_2602_21247_amd import build
-        build.build()
+        from paper_2602_21247_amd import hipbuild
+        hipbuild.build()
     return pp.lib()
 
 
@@ -82,3 +82,12 @@ def test_null_arguments_fail_cleanly(L):
     assert L.pipnn_search(None, None, None, 0, 0, 10, 10, 0, None, None, None, None) == -1
     assert L.pipnn_reservoir_init(None, 10, 4, None) == -1
     L.pipnn_destroy(None)
+
+
+def test_compile_step_does_not_shadow_the_index_build():
+    """Importing the compile step (as the entry point's build() does) leaves
+    the package's index build() in place, so a later smoke() in the same
+    process still reaches it."""
+    import types
+    from paper_2602_21247_amd import hipbuild  # noqa: F401
+    assert callable(pp.build) and not isinstance(pp.build, types.ModuleType)
