@@ -168,16 +168,16 @@ def knn_graph_stage(torch, np, idx, g, Xd, w, Ls, sample=10000):
 LEAF_KERNEL_SOURCES = ("knn_kernel.hpp", "knn_quad.hpp", "knn_fp32q.hip", "knn.hip")
 
 
-def traffic_from_profiles():
+def traffic_from_profiles(workload):
     """HBM bytes per leaf-kernel launch from committed counter runs, if they
-    were taken on the current kernel source."""
+    were taken on the current kernel source and on this workload."""
     path = os.path.join(ROOT, "profiles", "leaf_knn_hbm_traffic.json")
     csrc = os.path.join(ROOT, "paper_2602_21247_amd", "csrc")
     try:
         rec = json.load(open(path))
         h = hashlib.sha256(b"".join(open(os.path.join(csrc, f), "rb").read()
                                     for f in LEAF_KERNEL_SOURCES)).hexdigest()
-        if rec.get("knn_hip_sha256") != h:
+        if rec.get("knn_hip_sha256") != h or workload not in rec.get("kernel", ""):
             return None
         return rec.get("bytes_per_launch")
     except Exception:
@@ -594,7 +594,7 @@ def main():
         L_serve = main_form["L_at_recall_0.95"] or 128
         serve = serving_stage(args, torch, np, pp, pi, w, cfg, X, H, p_kw, L_serve)
 
-    traffic = traffic_from_profiles() if args.prec == "fp32" else None
+    traffic = traffic_from_profiles(w.name) if args.prec == "fp32" else None
     peak = PEAK_MFMA_TFLOPS[args.prec]
     gemm = f"{args.prec}-mfma" + (f", fp32 rescore of top-{args.rescore_mult}k"
                                   if args.rescore_mult else "")
