@@ -422,10 +422,48 @@ __global__ void to_f32_kernel(const void *src, int dtype, float *dst, int64_t co
   }
 }
 
+// Eight 16-bit values per thread: one 16-byte load, two 16-byte stores
+// (16-byte aligned source and destination; the conversions are exact).
+__global__ void to_f32_x8_kernel(const uint4 *__restrict__ src, int dtype, float4 *__restrict__ dst,
+                                 int64_t n8) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n8) return;
+  const uint4 v = src[i];
+  const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+  float f[8];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const uint32_t lo = w[j] & 0xFFFFu, hi = w[j] >> 16;
+    if (dtype == PIPNN_DTYPE_F16) {
+      f[2 * j] = (float)__builtin_bit_cast(_Float16, (uint16_t)lo);
+      f[2 * j + 1] = (float)__builtin_bit_cast(_Float16, (uint16_t)hi);
+    } else {
+      f[2 * j] = __uint_as_float(lo << 16);
+      f[2 * j + 1] = __uint_as_float(hi << 16);
+    }
+  }
+  dst[2 * i] = make_float4(f[0], f[1], f[2], f[3]);
+  dst[2 * i + 1] = make_float4(f[4], f[5], f[6], f[7]);
+}
+
 hipError_t launch_to_f32(const void *src, int dtype, float *dst, int64_t count, hipStream_t s) {
   if (count == 0) return hipSuccess;
-  hipLaunchKernelGGL(to_f32_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, src,
-                     dtype, dst, count);
+  int64_t head = 0;
+  if (dtype != PIPNN_DTYPE_F32 && ((uintptr_t)src & 15) == 0 && ((uintptr_t)dst & 15) == 0) {
+    const int64_t n8 = count / 8;
+    if (n8 > 0)
+      hipLaunchKernelGGL(to_f32_x8_kernel, dim3((unsigned)((n8 + 255) / 256)), dim3(256), 0, s,
+                         reinterpret_cast<const uint4 *>(src), dtype,
+                         reinterpret_cast<float4 *>(dst), n8);
+    head = n8 * 8;
+  }
+  if (head < count) {
+    const int64_t rest = count - head;
+    const size_t eb = dtype == PIPNN_DTYPE_F32 ? 4 : 2;
+    hipLaunchKernelGGL(to_f32_kernel, dim3((unsigned)((rest + 255) / 256)), dim3(256), 0, s,
+                       reinterpret_cast<const void *>(reinterpret_cast<const uint8_t *>(src) + head * eb),
+                       dtype, dst + head, rest);
+  }
   return hipGetLastError();
 }
 
