@@ -8,8 +8,8 @@ namespace pipnn {
 // ---------------------------------------------------------------------
 // Squared norms (for the GEMM distance form) and sketches
 // Sketch(v)_b = H_b . v (Sec. 3, Implementation). One thread per point
-// accumulates every output in dimension order; the rows are staged through
-// LDS and the hyperplanes broadcast from it. The same pass
+// accumulates every output in dimension order; the rows and the matching
+// columns of the hyperplanes are staged through LDS. The same pass
 // takes the integer check: chk[0] is set when a coordinate is not an
 // integer of magnitude <= 2^20, chk[1] / chk[2] collect the smallest and
 // largest coordinate (one atomic per wave, only when it would change them).
@@ -29,9 +29,8 @@ __global__ void __launch_bounds__(256) norms_sketches_kernel(const float *__rest
   // rows (coalesced), then each thread continues its own row's sums in
   // dimension order from LDS.
   constexpr int KD = 16;
-  extern __shared__ float sH[];                 // m x d
   __shared__ float sX[256][KD + 1];             // the slab (+1: conflict-free row reads)
-  for (int i = threadIdx.x; i < m * d; i += blockDim.x) sH[i] = H[i];
+  __shared__ float sHk[16][KD];                 // the slab's columns of the hyperplanes
   const int64_t p0 = (int64_t)blockIdx.x * 256;
   const int64_t p = p0 + threadIdx.x;
   const int rows = (int)min<int64_t>(256, n - p0);
@@ -43,7 +42,11 @@ __global__ void __launch_bounds__(256) norms_sketches_kernel(const float *__rest
   for (int b = 0; b < 16; ++b) sk[b] = 0.f;
   for (int k0 = 0; k0 < d; k0 += KD) {
     const int kw = min(KD, d - k0);
-    __syncthreads();  // the previous slab is consumed (and sH is loaded)
+    __syncthreads();  // the previous slab is consumed
+    for (int t = threadIdx.x; t < m * kw; t += 256) {
+      const int b = t / kw, c = t - b * kw;
+      sHk[b][c] = H[b * d + k0 + c];
+    }
     if ((d & 3) == 0) {
       // kw is a multiple of 4: 4-float pieces, kw / 4 per row
       const int pr = kw >> 2;
@@ -66,7 +69,7 @@ __global__ void __launch_bounds__(256) norms_sketches_kernel(const float *__rest
         coord_check(v, bad, lo, hi);
 #pragma unroll
         for (int b = 0; b < 16; ++b)
-          if (b < m) sk[b] = fmaf(sH[b * d + k0 + j], v, sk[b]);
+          if (b < m) sk[b] = fmaf(sHk[b][j], v, sk[b]);
       }
     }
   }
@@ -103,8 +106,7 @@ hipError_t launch_norms_sketches(const Index &I, hipStream_t s) {
 hipError_t launch_norms_sketches_range(const Index &I, int64_t p0, int64_t cnt, hipStream_t s) {
   if (cnt <= 0) return hipSuccess;
   const int64_t blocks = (cnt + 255) / 256;
-  const size_t lds = (size_t)I.m * I.d * sizeof(float);
-  hipLaunchKernelGGL(norms_sketches_kernel, dim3((unsigned)blocks), dim3(256), lds, s,
+  hipLaunchKernelGGL(norms_sketches_kernel, dim3((unsigned)blocks), dim3(256), 0, s,
                      I.xf() + p0 * I.d, cnt, I.d, I.H, I.m, I.norms.as<float>() + p0,
                      I.sketches.as<float>() + p0 * I.m, I.int_chk.as<int>());
   return hipGetLastError();
