@@ -30,7 +30,7 @@ __global__ void __launch_bounds__(256) norms_sketches_kernel(const float *__rest
   // dimension order from LDS.
   constexpr int KD = 16;
   __shared__ float sX[256][KD + 1];             // the slab (+1: conflict-free row reads)
-  __shared__ float sHk[16][KD];                 // the slab's columns of the hyperplanes
+  __shared__ float sHk[16][KD];                 // the slab's columns of the hyperplanes (m <= 16)
   const int64_t p0 = (int64_t)blockIdx.x * 256;
   const int64_t p = p0 + threadIdx.x;
   const int rows = (int)min<int64_t>(256, n - p0);
