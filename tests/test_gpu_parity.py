@@ -279,6 +279,29 @@ def test_partition_bit_exact(kind, kw):
     idx.close()
 
 
+def test_partition_hand_worked_golden():
+    """The hand-worked carving of tests/golden/partition_merge_recursion.json
+    (Alg. 5, Sec. 4.1: merge by the sum of sizes, a duplicate in a merged
+    group, kept buckets of exactly C_min and C_max, recursion with a derived
+    child key, a no-progress chunk) on the GPU planner: the same leaves."""
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(__file__), "golden",
+                           "partition_merge_recursion.json")) as f:
+        g = json.load(f)
+    X = np.array(g["points_1d"], dtype=np.float32)[:, None]
+    P = g["params"]
+    p = gpu_params(c_max=P["c_max"], c_min=P["c_min"], leader_div=P["leader_div"],
+                   leader_cap=P["leader_cap"], fanout=tuple(P["fanout"]), seed=P["seed"])
+    idx = pp.Index(dev(X), dev(pi.hyperplanes(12, 1, 1, integer=True)), p)
+    off, mem = idx.partition()
+    torch.cuda.synchronize()
+    got = leaf_sets(off.cpu().numpy(), mem.cpu().numpy())
+    assert got == sorted(tuple(v) for v in g["expected_leaves"])
+    assert idx.stats()["leader_dists"] == g["expected_leader_dists"]
+    idx.close()
+
+
 def test_partition_single_leaf_and_duplicates():
     X = int_points(500, 16, seed=33)
     idx = pp.Index(dev(X), dev(pi.hyperplanes(4, 16, 1, integer=True)), gpu_params(c_max=1024))

@@ -435,6 +435,47 @@ def test_partition_merge_and_recursion_rules():
     assert np.bincount(mem, minlength=5000).min() >= 1
 
 
+def test_partition_merge_and_recursion_golden():
+    """Hand-worked carving of 17 points on a line (tests/golden/
+    partition_merge_recursion.json; Alg. 5 and Sec. 4.1): a merged group
+    that holds one id twice, a group boundary set by the sum of bucket sizes
+    (the union would still fit), a bucket of exactly C_min kept, a bucket of
+    exactly C_max kept, a recursion whose leaders come from the derived child
+    key (with a Fisher-Yates swap that lands on an already swapped position)
+    and a no-progress bucket cut into runs of 4 and 3."""
+    g = _gold("partition_merge_recursion.json")
+    gamma, mask = 0x9E3779B97F4A7C15, (1 << 64) - 1
+    x = g["points_1d"]
+    for sp in g["subproblems"]:
+        key = int(sp["key"])
+        if "parent_key" in sp:      # child key from the pinned generator
+            st = int(sp["parent_key"]) ^ (((sp["parent_t"] + 1) * gamma) & mask)
+            assert int(oracle.splitmix64(st, 1)[0]) == key
+        ids, ell = sp["ids"], sp["ell"]
+        assert [int(v) for v in oracle.splitmix64(key, ell)] == [int(r) for r in sp["draws"]]
+        perm = list(range(len(ids)))
+        for t, r in enumerate(sp["draws"]):
+            j = t + ((int(r) * (len(ids) - t)) >> 64)
+            assert j == sp["j"][t]
+            perm[t], perm[j] = perm[j], perm[t]
+        assert [ids[perm[t]] for t in range(ell)] == sp["leaders"]
+        # the worked buckets follow from the nearest leaders by (distance, t)
+        buckets = [[] for _ in range(ell)]
+        for p in ids:
+            near = sorted(((x[p] - x[lid]) ** 2, t) for t, lid in enumerate(sp["leaders"]))
+            for _, t in near[:sp["fanout"]]:
+                buckets[t].append(p)
+        assert buckets == sp["buckets"]
+    X = np.array(x, dtype=np.float32)[:, None]
+    P = g["params"]
+    prm = oracle.make_params(c_max=P["c_max"], c_min=P["c_min"], leader_div=P["leader_div"],
+                             leader_cap=P["leader_cap"], fanout=P["fanout"], seed=P["seed"])
+    off, mem, ld = oracle.partition(X, prm)
+    got = sorted(tuple(mem[off[i]:off[i + 1]].tolist()) for i in range(len(off) - 1))
+    assert got == sorted(tuple(v) for v in g["expected_leaves"])
+    assert ld == g["expected_leader_dists"]
+
+
 def test_partition_no_progress_chunks():
     """All points identical: every point picks leaders 0 and 1, both buckets
     equal the parent, and each is cut into near-equal runs of ascending ids."""
