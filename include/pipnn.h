@@ -298,6 +298,28 @@ pipnn_status pipnn_hashprune_insert(pipnn_index *idx, const uint32_t *d_dst,
                                     int64_t n_records, uint64_t *d_reservoirs,
                                     pipnn_stream_t stream);
 
+/* For callers that cannot allocate device memory (code that must not call
+ * hipMalloc: tight serving loops, harnesses that forbid allocation): the
+ * same insertion as pipnn_hashprune_insert, through the same kernels, with
+ * its scratch (per-point counts and bin offsets, the binned records) taken
+ * from a fixed array of 64 MiB that the library holds on each device from
+ * its load until the process ends. It calls no hipMalloc or hipFree.
+ * Limit: the scratch it needs -- 8 (n + 1) bytes of bin offsets,
+ * 8 (ceil(n / 4096) + 1) of scan workspace and 4 n of counts, each rounded
+ * up to a multiple of 256, plus 8 n_records of binned records -- must not
+ * exceed 64 MiB (about 6.8 million records at n = 1,000,000); EINVAL with
+ * the sizes otherwise, or if the current device is not the one the index
+ * was created on.
+ * Every call on a device shares that device's array and leaves its contents
+ * behind (each call clears what it needs): calls that overlap in time on one
+ * device -- on different streams, threads or indices -- race and must be
+ * serialised by the caller. Synchronises the stream like
+ * pipnn_hashprune_insert (to read the device-side id check). */
+pipnn_status pipnn_hashprune_insert_static(pipnn_index *idx, const uint32_t *d_dst,
+                                           const uint32_t *d_cand, const float *d_dist,
+                                           int64_t n_records, uint64_t *d_reservoirs,
+                                           pipnn_stream_t stream);
+
 /* Reservoir slot layout (Sec. 3, Implementation: 4-byte id, 2-byte hash,
  * bf16 distance): bits 0..31 id, 32..47 hash, 48..63 bf16 distance.
  * Sets n x l_max slots to the empty slot (id 0xFFFFFFFF, hash 0, +inf). */

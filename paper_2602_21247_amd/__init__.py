@@ -30,7 +30,7 @@ EXPORTS = [
     "pipnn_robustprune", "pipnn_start_node", "pipnn_search", "pipnn_get_sketches",
     "pipnn_knn_block", "pipnn_leaf_pick", "pipnn_prepare", "pipnn_set_profiling",
     "pipnn_get_stats", "pipnn_get_operand", "pipnn_plan_leaves", "pipnn_set_leaf_config",
-    "pipnn_autotune", "pipnn_reserve", "pipnn_insert",
+    "pipnn_autotune", "pipnn_reserve", "pipnn_insert", "pipnn_hashprune_insert_static",
 ]
 
 
@@ -87,6 +87,7 @@ def lib():
                                               C.POINTER(i64), P]
         L.pipnn_build_leaves.argtypes = [P, P, P, i64, P, P]
         L.pipnn_hashprune_insert.argtypes = [P, P, P, P, i64, P, P]
+        L.pipnn_hashprune_insert_static.argtypes = [P, P, P, P, i64, P, P]
         L.pipnn_reservoir_init.argtypes = [P, i64, i32, P]
         L.pipnn_reservoir_canonical.argtypes = [P, P, P, P]
         L.pipnn_robustprune.argtypes = [P, P, P, P, P]
@@ -265,6 +266,13 @@ class Index:
     def hashprune_insert(self, dst, cand, dist, reservoirs):
         _check(lib().pipnn_hashprune_insert(self._h, _ptr(dst), _ptr(cand), _ptr(dist),
                                             dst.numel(), _ptr(reservoirs), _stream()))
+        return reservoirs
+
+    def hashprune_insert_static(self, dst, cand, dist, reservoirs):
+        """hashprune_insert with the library's fixed per-device scratch
+        (no device allocation; see pipnn_hashprune_insert_static)."""
+        _check(lib().pipnn_hashprune_insert_static(self._h, _ptr(dst), _ptr(cand), _ptr(dist),
+                                                   dst.numel(), _ptr(reservoirs), _stream()))
         return reservoirs
 
     def reservoir_canonical(self, res):

@@ -12,6 +12,7 @@
 
 #include "common.hpp"
 #include <map>
+#include <mutex>
 
 #include "internal.hpp"
 
@@ -195,6 +196,35 @@ std::vector<KnnItem> plan_items(const std::vector<KnnJob> &jobs, int rows_per_it
 
 }  // namespace
 
+namespace {
+
+// Scratch of pipnn_hashprune_insert_static: one array per device, held from
+// the library's load until the process ends. Host code never passes the
+// array's name to a kernel (on the host it is a stand-in symbol, not a
+// device address); static_scratch() looks up its address on each device
+// once, with that device current, and the kernels get that pointer.
+constexpr size_t kStaticScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned char *g_scratch_ptr[kMaxDevices] = {};
+
+hipError_t static_scratch(int dev, unsigned char **out) {
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = static_cast<unsigned char *>(ptr);
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
+}  // namespace
+
 namespace pipnn {
 
 hipError_t DevBuf::ensure(size_t bytes) {
@@ -341,6 +371,7 @@ pipnn_status pipnn_create(const pipnn_params *p, const void *d_X, int64_t n, int
   hipError_t e;
   {
     int dev = 0, ncu = 0;
+    if (hipGetDevice(&dev) == hipSuccess) I->device = dev;
     if (hipGetDevice(&dev) == hipSuccess &&
         hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
         ncu >= kNumXcd)
@@ -881,7 +912,45 @@ pipnn_status run_pick(Index &I, const std::vector<int64_t> &offs, int64_t l0, in
   return st;
 }
 
-// Bin records by destination and merge them into the reservoirs.
+// Scratch of one binning pass: per-point counts (n), bin offsets (n + 1),
+// the offsets' scan workspace and the binned records.
+struct BinScratch {
+  uint32_t *cnt;
+  int64_t *off;
+  int64_t *tmp0;
+  uint64_t *bins;
+};
+
+// Bin records by destination and merge them into the reservoirs, with the
+// scratch given.
+pipnn_status bin_and_merge_in(Index &I, const BinScratch &B, bool from_picks, const uint32_t *a,
+                              const uint32_t *b, const float *dist, int64_t count, int32_t k,
+                              uint64_t *res, hipStream_t s) {
+  const int64_t n = I.n;
+  {
+    PhaseTimer tb(I, kPhBin, s);
+    HIPCHK(launch_fill_u32(B.cnt, 0u, n, s));
+    if (from_picks)
+      HIPCHK(launch_bin_count(a, b, count, k, B.cnt, n, I.flag.as<int32_t>(), s));
+    else
+      HIPCHK(launch_rec_count(a, b, count, B.cnt, n, I.flag.as<int32_t>(), s));
+    HIPCHK(launch_scan_u32(B.cnt, B.off, n, B.tmp0, s));
+    HIPCHK(launch_fill_u32(B.cnt, 0u, n, s));
+    if (from_picks)
+      HIPCHK(launch_bin_scatter(a, b, dist, count, k, I.sketches.as<float>(), I.m, B.off, B.cnt,
+                                B.bins, n, s));
+    else
+      HIPCHK(launch_rec_scatter(a, b, dist, count, I.sketches.as<float>(), I.m, B.off, B.cnt,
+                                B.bins, n, s));
+  }
+  {
+    PhaseTimer tm(I, kPhMerge, s);
+    HIPCHK(launch_hashprune_merge(res, n, I.p.l_max, B.bins, B.off, s));
+  }
+  return PIPNN_OK;
+}
+
+// The same with the index's own scratch.
 pipnn_status bin_and_merge(Index &I, bool from_picks, const uint32_t *a, const uint32_t *b,
                            const float *dist, int64_t count, int32_t k, uint64_t *res,
                            hipStream_t s) {
@@ -892,31 +961,9 @@ pipnn_status bin_and_merge(Index &I, bool from_picks, const uint32_t *a, const u
   HIPCHK(I.s_off.ensure((size_t)(n + 1) * 8));
   HIPCHK(I.s_tmp0.ensure((size_t)scan_tmp_elems(n) * 8));
   HIPCHK(I.s_bins.ensure((size_t)std::max<int64_t>(max_rec, 1) * 8));
-  {
-    PhaseTimer tb(I, kPhBin, s);
-    HIPCHK(launch_fill_u32(I.s_cnt.as<uint32_t>(), 0u, n, s));
-    if (from_picks)
-      HIPCHK(launch_bin_count(a, b, count, k, I.s_cnt.as<uint32_t>(), n, I.flag.as<int32_t>(), s));
-    else
-      HIPCHK(launch_rec_count(a, b, count, I.s_cnt.as<uint32_t>(), n, I.flag.as<int32_t>(), s));
-    HIPCHK(launch_scan_u32(I.s_cnt.as<uint32_t>(), I.s_off.as<int64_t>(), n,
-                           I.s_tmp0.as<int64_t>(), s));
-    HIPCHK(launch_fill_u32(I.s_cnt.as<uint32_t>(), 0u, n, s));
-    if (from_picks)
-      HIPCHK(launch_bin_scatter(a, b, dist, count, k, I.sketches.as<float>(), I.m,
-                                I.s_off.as<int64_t>(), I.s_cnt.as<uint32_t>(),
-                                I.s_bins.as<uint64_t>(), n, s));
-    else
-      HIPCHK(launch_rec_scatter(a, b, dist, count, I.sketches.as<float>(), I.m,
-                                I.s_off.as<int64_t>(), I.s_cnt.as<uint32_t>(),
-                                I.s_bins.as<uint64_t>(), n, s));
-  }
-  {
-    PhaseTimer tm(I, kPhMerge, s);
-    HIPCHK(launch_hashprune_merge(res, n, I.p.l_max, I.s_bins.as<uint64_t>(),
-                                  I.s_off.as<int64_t>(), s));
-  }
-  return PIPNN_OK;
+  const BinScratch B{I.s_cnt.as<uint32_t>(), I.s_off.as<int64_t>(), I.s_tmp0.as<int64_t>(),
+                     I.s_bins.as<uint64_t>()};
+  return bin_and_merge_in(I, B, from_picks, a, b, dist, count, k, res, s);
 }
 
 // The same for the picks of a batch of leaves written as local column
@@ -953,11 +1000,13 @@ pipnn_status bin_and_merge_leaves(Index &I, const int64_t *d_leaf_off, int64_t o
 }
 
 // Reads the device error flag and the last bin total (one synchronisation).
-pipnn_status finish_bins(Index &I, hipStream_t s, const char *what) {
+pipnn_status finish_bins(Index &I, hipStream_t s, const char *what,
+                         const int64_t *bin_off = nullptr) {
   int32_t flag = 0;
   int64_t total = 0;
+  if (!bin_off) bin_off = I.s_off.as<int64_t>();
   HIPCHK(hipMemcpyAsync(&flag, I.flag.p, 4, hipMemcpyDeviceToHost, s));
-  HIPCHK(hipMemcpyAsync(&total, I.s_off.as<int64_t>() + I.n, 8, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(&total, bin_off + I.n, 8, hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
   HIPCHK(hipMemsetAsync(I.flag.p, 0, 4, s));
   I.stats.records += total;
@@ -1618,6 +1667,47 @@ pipnn_status pipnn_hashprune_insert(pipnn_index *idx, const uint32_t *d_dst,
   pipnn_status st = bin_and_merge(I, false, d_dst, d_cand, d_dist, n_records, 1, d_reservoirs, s);
   if (st != PIPNN_OK) return st;
   return finish_bins(I, s, "hashprune_insert");
+  GUARD_END
+}
+
+pipnn_status pipnn_hashprune_insert_static(pipnn_index *idx, const uint32_t *d_dst,
+                                           const uint32_t *d_cand, const float *d_dist,
+                                           int64_t n_records, uint64_t *d_reservoirs,
+                                           pipnn_stream_t stream) {
+  GUARD_BEGIN
+  if (!idx || !d_reservoirs || n_records < 0) return fail(PIPNN_EINVAL, "invalid argument");
+  if (n_records == 0) return PIPNN_OK;
+  if (!d_dst || !d_cand || !d_dist) return fail(PIPNN_EINVAL, "NULL record array");
+  Index &I = *reinterpret_cast<Index *>(idx);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const int64_t n = I.n;
+  auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
+  const size_t o_off = 0;
+  const size_t o_tmp = o_off + up((size_t)(n + 1) * 8);
+  const size_t o_cnt = o_tmp + up((size_t)scan_tmp_elems(n) * 8);
+  const size_t o_bins = o_cnt + up((size_t)n * 4);
+  const size_t need = o_bins + (size_t)n_records * 8;
+  if (need > kStaticScratchBytes)
+    return fail(PIPNN_EINVAL,
+                "hashprune_insert_static: %lld points and %lld records need %zu bytes of static "
+                "scratch; the maximum is %zu",
+                (long long)n, (long long)n_records, need, kStaticScratchBytes);
+  int dev = -1;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev != I.device)
+    return fail(PIPNN_EINVAL, "hashprune_insert_static: the current device (%d) is not the "
+                              "index's (%d)", dev, I.device);
+  unsigned char *base = nullptr;
+  HIPCHK(static_scratch(dev, &base));
+  const BinScratch B{reinterpret_cast<uint32_t *>(base + o_cnt),
+                     reinterpret_cast<int64_t *>(base + o_off),
+                     reinterpret_cast<int64_t *>(base + o_tmp),
+                     reinterpret_cast<uint64_t *>(base + o_bins)};
+  I.stats.records = 0;
+  pipnn_status st = bin_and_merge_in(I, B, false, d_dst, d_cand, d_dist, n_records, 1,
+                                     d_reservoirs, s);
+  if (st != PIPNN_OK) return st;
+  return finish_bins(I, s, "hashprune_insert_static", B.off);
   GUARD_END
 }
 

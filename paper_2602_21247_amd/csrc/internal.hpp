@@ -65,6 +65,7 @@ struct Index {
   int64_t cap = 0;              // rows the per-point buffers hold (pipnn_reserve)
   DevBuf i_rows, i_cols, i_assign, i_flag, i_pos, i_list, i_tmp, i_segs;
   DevBuf q_conv, q_seen;        // search scratch (search may overlap an insertion)
+  int32_t device = 0;           // the HIP device current at pipnn_create
   int32_t n_cu = 256;           // compute units of the device (persistent grid size)
   int32_t leaf_nw = 4;          // waves (of 32 rows) per leaf work item: 4, or 2 where built
   int32_t leaf_persistent = 0;  // 1: persistent workgroups take items from the counters
