@@ -110,8 +110,10 @@ def ground_truth(torch, Xd, Qd, metric=0, k=10):
 
 
 # Settings of the frontier: the paper's knobs around the workload's own
-# (fanout {2,1,1,1}, leaf k 16, l_max 64): the leaf k, the reservoir bound
-# and single- or multi-level fanout.
+# (fanout {2,1,1,1}, leaf k 16, l_max 64, m 12 hash bits): the leaf k, the
+# reservoir bound, single- or multi-level fanout, and the number of
+# hyperplanes m of HashPrune's hash (the workload's hyperplanes are drawn for
+# 16 and the first m are used).
 FRONTIER = [
     {"fanout": (2, 1, 1, 1), "k": 16, "l_max": 64},
     {"fanout": (2, 1, 1, 1), "k": 8, "l_max": 64},
@@ -122,14 +124,17 @@ FRONTIER = [
     {"fanout": (3, 1, 1, 1), "k": 16, "l_max": 64},
     {"fanout": (2, 2, 1, 1), "k": 16, "l_max": 64},
     {"fanout": (3, 2, 1, 1), "k": 12, "l_max": 64},
+    {"fanout": (2, 1, 1, 1), "k": 16, "l_max": 64, "m": 8},
+    {"fanout": (2, 1, 1, 1), "k": 16, "l_max": 64, "m": 10},
+    {"fanout": (2, 1, 1, 1), "k": 16, "l_max": 64, "m": 14},
+    {"fanout": (2, 1, 1, 1), "k": 16, "l_max": 64, "m": 16},
 ]
 
 
 def knn_graph_stage(torch, np, idx, g, Xd, w, Ls, sample=10000):
-    """Approximate 10-NN graph of the points: every point searched on the
-    built graph (11 results, its own id dropped, else the 11th), in batches
-    whose visited bitmaps (n bits per query) stay within 1 GiB; recall@10 on
-    a sample against exact ground truth (the 11th nearest including itself is
+    """Approximate 10-NN graph of the points (pipnn_knn_graph: every point
+    searched on the built graph, its own id dropped), timed; recall@10 on a
+    sample against exact ground truth (the 11th nearest including itself is
     the 10th nearest other point)."""
     n = Xd.shape[0]
     start = idx.start_node()
@@ -137,29 +142,18 @@ def knn_graph_stage(torch, np, idx, g, Xd, w, Ls, sample=10000):
     samp = np.sort(rng.choice(n, size=min(sample, n), replace=False)).astype(np.int64)
     sd = torch.from_numpy(samp).cuda()
     kth = ground_truth(torch, Xd, Xd[sd], w.metric, k=11)
-    chunk = max(1, min(8192, (1 << 30) // (((n + 31) // 32) * 4)))
     out = []
     for L in Ls:
-        ids_all = torch.empty((n, 11), dtype=torch.int32, device="cuda")
-        dist_all = torch.empty((n, 11), dtype=torch.float32, device="cuda")
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for q0 in range(0, n, chunk):
-            q1 = min(n, q0 + chunk)
-            ids, dist, _ = idx.search(g, Xd[q0:q1], 11, max(11, L), start, want_cmps=False)
-            ids_all[q0:q1] = ids
-            dist_all[q0:q1] = dist
+        ids, dist = idx.knn_graph(g, 10, max(11, L), start)
         torch.cuda.synchronize()
         t = time.perf_counter() - t0
-        si, sdist = ids_all[sd], dist_all[sd]
-        own = si == sd[:, None].to(torch.int32)
-        keep = ~own
-        keep[:, 10] &= own.any(1)  # no own id among the 11: the 11th is dropped
-        hits = ((sdist.double() <= kth[:, None]) & keep).sum().item()
+        hits = (dist[sd].double() <= kth[:, None]).sum().item()
         r = hits / (10.0 * len(samp))
         log(f"[bench] knn graph: L={L} {t:.2f} s ({n / t:.0f} points/s), recall@10 {r:.4f}")
         out.append({"L": L, "seconds": t, "points_per_s": n / t, "recall_at_10_sampled": r,
-                    "sample": len(samp), "batch": chunk})
+                    "sample": len(samp)})
     return out
 
 
@@ -405,6 +399,14 @@ def main():
     H = pi.workload_hyperplanes(cfg)
     Xd = torch.from_numpy(X).cuda()
     Hd = torch.from_numpy(H).cuda()
+    # hyperplanes for other hash widths m (frontier): the first m rows of a
+    # 16-row draw with the workload's generator
+    Hm = {}
+    if args.frontier:
+        H16 = pi.workload_hyperplanes(cfg, m=16)
+        for o in FRONTIER:
+            if "m" in o:
+                Hm[o["m"]] = torch.from_numpy(np.ascontiguousarray(H16[:o["m"]])).cuda()
     Qd = kth = None
     if not args.no_recall:
         nq = args.queries or w.n_queries
@@ -427,12 +429,13 @@ def main():
         the workload's fanout, k or l_max."""
         over = over or {}
         fk, fl, ff = over.get("k", w.k), over.get("l_max", w.l_max), over.get("fanout", w.fanout)
+        fm = over.get("m", w.hash_bits)
         p = pp.default_params(metric=w.metric, c_max=w.c_max, c_min=w.c_min, k=fk,
-                              l_max=fl, R=w.R, alpha=w.alpha, hash_bits=w.hash_bits,
+                              l_max=fl, R=w.R, alpha=w.alpha, hash_bits=fm,
                               leader_div=w.leader_div, leader_cap=w.leader_cap, fanout=ff,
                               seed=pi.workload_seed(cfg), gemm_prec=PREC_CODES[prec],
                               rescore_mult=mult)
-        idx = pp.Index(Xd, Hd, p)
+        idx = pp.Index(Xd, Hm.get(fm, Hd), p)
         res = torch.empty((n, fl), dtype=torch.int64, device="cuda")
         tune = None
 
@@ -532,7 +535,7 @@ def main():
                 "L_at_recall_0.95": l_at, "search_qps_at_L": qps, "recall_curve": curve,
                 "phase_ms": phases, "stats": st, "autotune": tune}
         if over:
-            form["params"] = {"fanout": list(ff), "k": fk, "l_max": fl}
+            form["params"] = {"fanout": list(ff), "k": fk, "l_max": fl, "m": fm}
         if keep:
             form["_out"] = (idx, res, off, mem, g, deg)
         else:

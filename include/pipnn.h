@@ -253,7 +253,11 @@ pipnn_status pipnn_reserve(pipnn_index *idx, int64_t n_cap, pipnn_stream_t strea
  * (HashPrune does not depend on the order of its records). The leaves
  * themselves do not grow. ESTATE before any build or under capture;
  * EOVERFLOW past the reserved capacity; EINVAL if a leaf would exceed 65535
- * columns. On a failure the index is left in an unspecified state. */
+ * columns. A failed call leaves the point count (and the exactness checks
+ * of X) as they were, and the old points' reservoirs and graph rows
+ * untouched when it fails before step 4 (every argument and size check
+ * does), so the caller may retry with other points in the same rows; the
+ * new rows' buffers are rewritten by the next insertion. */
 pipnn_status pipnn_insert(pipnn_index *idx, int64_t n_new, const int32_t *d_group,
                           uint64_t *d_reservoirs, uint32_t *d_graph, uint32_t *d_degree,
                           pipnn_stream_t stream);
@@ -361,6 +365,18 @@ pipnn_status pipnn_search(pipnn_index *idx, const uint32_t *d_graph, const void 
                           int32_t q_dtype, int32_t k, int32_t L, uint32_t start,
                           uint32_t *d_out_ids, float *d_out_dist, uint32_t *d_out_cmps,
                           pipnn_stream_t stream);
+
+/* Approximate k-nearest-neighbour graph of the indexed points (Sec. 5, k-NN
+ * graph construction: build the index, then search every point): for each
+ * point p, BeamSearch (Alg. 1, as pipnn_search) for X[p] with beam width L
+ * from `start` returns its k + 1 nearest, and p itself is dropped (or, when
+ * p is not among them, the (k + 1)-th). Writes d_out_ids (n x k, ids in
+ * (distance, id) order) and d_out_dist (n x k FP32 distances; may be NULL).
+ * Points are searched in chunks of up to 65,536. EINVAL unless
+ * 1 <= k < L <= 1024 and start < n. */
+pipnn_status pipnn_knn_graph(pipnn_index *idx, const uint32_t *d_graph, int32_t k, int32_t L,
+                             uint32_t start, uint32_t *d_out_ids, float *d_out_dist,
+                             pipnn_stream_t stream);
 
 /* Recompute the per-point squared norms and sketches from X (call after the
  * caller changed X in place; pipnn_create already does this once), with the

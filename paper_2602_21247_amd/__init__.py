@@ -31,6 +31,7 @@ EXPORTS = [
     "pipnn_knn_block", "pipnn_leaf_pick", "pipnn_prepare", "pipnn_set_profiling",
     "pipnn_get_stats", "pipnn_get_operand", "pipnn_plan_leaves", "pipnn_set_leaf_config",
     "pipnn_autotune", "pipnn_reserve", "pipnn_insert", "pipnn_hashprune_insert_static",
+    "pipnn_knn_graph",
 ]
 
 
@@ -94,6 +95,7 @@ def lib():
         L.pipnn_start_node.argtypes = [P, C.POINTER(u32), P]
         L.pipnn_search.argtypes = [P, P, P, i64, i32, i32, i32, u32, P, P, P, P]
         L.pipnn_get_sketches.argtypes = [P, P, P]
+        L.pipnn_knn_graph.argtypes = [P, P, i32, i32, u32, P, P, P]
         L.pipnn_knn_block.argtypes = [P, P, i64, P, i64, i32, i32, P, P, P, P]
         L.pipnn_leaf_pick.argtypes = [P, P, P, i64, P, P, P]
         L.pipnn_prepare.argtypes = [P, P]
@@ -304,6 +306,16 @@ class Index:
         _check(lib().pipnn_search(self._h, _ptr(graph), _ptr(Q), nq, _dtype_code(Q), k, L, start,
                                   _ptr(ids), _ptr(dist), _ptr(cmps), _stream()))
         return ids, dist, cmps
+
+    def knn_graph(self, graph, k: int, L: int, start: int, want_dist=True):
+        """k nearest other points of every indexed point, by searching each
+        one on the graph (see pipnn_knn_graph): ids (n x k), dist (n x k)."""
+        torch = _torch()
+        ids = torch.empty((self.n, k), dtype=torch.int32, device="cuda")
+        dist = torch.empty((self.n, k), dtype=torch.float32, device="cuda") if want_dist else None
+        _check(lib().pipnn_knn_graph(self._h, _ptr(graph), k, L, start, _ptr(ids), _ptr(dist),
+                                     _stream()))
+        return ids, dist
 
     # ---- inspection
     def get_sketches(self):

@@ -435,7 +435,7 @@ void pipnn_destroy(pipnn_index *idx) {
   Index *I = reinterpret_cast<Index *>(idx);
   (void)hipDeviceSynchronize();
   for (DevBuf *b : {&I->rp_order, &I->o_first, &I->o_flag, &I->o_pos, &I->o_pos2, &I->o_tmp,
-                    &I->xf32, &I->xpad, &I->xlow, &I->op_flag, &I->int_chk, &I->xscale, &I->lnorms, &I->s_counter, &I->q_conv, &I->q_seen,
+                    &I->xf32, &I->xpad, &I->xlow, &I->op_flag, &I->int_chk, &I->xscale, &I->lnorms, &I->s_counter, &I->q_conv, &I->q_seen, &I->g_ids, &I->g_dist,
                     &I->lt_off, &I->lt_mem, &I->lt_rep, &I->i_rows, &I->i_cols, &I->i_assign,
                     &I->i_flag, &I->i_pos, &I->i_list, &I->i_tmp, &I->i_segs, &I->sketches, &I->norms, &I->flag, &I->s_jobs,
                     &I->s_items, &I->s_picks_c, &I->s_picks_d, &I->s_cnt, &I->s_off, &I->s_bins,
@@ -1306,9 +1306,29 @@ pipnn_status pipnn_insert(pipnn_index *idx, int64_t n_new, const int32_t *d_grou
   const int64_t n0 = I.n, n1 = n0 + n_new, d = I.d;
   const int k = P.k;
   const int ksel = P.rescore_mult ? P.rescore_mult * k : k;
+  const int64_t NL = I.lt_n_leaves;
+  if (NL > 65535) return fail(PIPNN_EINVAL, "insert routes over at most 65535 leaves");
+  if (n_new > 0x7FFFFFFF) return fail(PIPNN_EINVAL, "insert batch too large");
 
   // 1. the new rows' float32 copy, norms, sketches and GEMM operand (the
-  //    count is published atomically for a search running on another thread)
+  //    count is published atomically for a search running on another thread).
+  //    Until the insertion has succeeded, any return restores the count and
+  //    the exactness flags that the new rows' checks update, so that a failed
+  //    call leaves the index as it was for the next one (the new rows'
+  //    buffers and reservoirs are rewritten by it).
+  struct Rollback {
+    Index &I;
+    int64_t n0, int_lo, int_hi;
+    bool int_exact, op_exact, done = false;
+    ~Rollback() {
+      if (done) return;
+      __atomic_store_n(&I.n, n0, __ATOMIC_RELEASE);
+      I.int_exact = int_exact;
+      I.int_lo = int_lo;
+      I.int_hi = int_hi;
+      I.op_exact = op_exact;
+    }
+  } rollback{I, n0, I.int_lo, I.int_hi, I.int_exact, I.op_exact};
   __atomic_store_n(&I.n, n1, __ATOMIC_RELEASE);
   I.rp_order_valid = false;  // the leaf order covers the old points only
   if (I.x_dtype != PIPNN_DTYPE_F32) {
@@ -1328,8 +1348,6 @@ pipnn_status pipnn_insert(pipnn_index *idx, int64_t n_new, const int32_t *d_grou
   HIPCHK(launch_fill_u64(d_reservoirs + n0 * P.l_max, empty_slot(), n_new * P.l_max, s));
 
   // 2. route every new point to its f nearest leaves (by the leaf representatives)
-  const int64_t NL = I.lt_n_leaves;
-  if (NL > 65535) return fail(PIPNN_EINVAL, "insert routes over at most 65535 leaves");
   HIPCHK(I.lt_rep.ensure((size_t)NL * 4));
   if (!I.lt_reps_valid) {
     HIPCHK(launch_leaf_reps(I.xf(), I.d, I.lt_off.as<int64_t>(), I.lt_mem.as<uint32_t>(), NL,
@@ -1344,7 +1362,6 @@ pipnn_status pipnn_insert(pipnn_index *idx, int64_t n_new, const int32_t *d_grou
     jobs[0].n_rows = (int32_t)n_new;
     jobs[0].n_cols = (int32_t)NL;
     jobs[0].k_sel = f;
-    if (n_new > 0x7FFFFFFF) return fail(PIPNN_EINVAL, "insert batch too large");
     std::vector<KnnItem> items = plan_items(jobs, 128);
     HIPCHK(upload(I.s_jobs, jobs, s));
     HIPCHK(upload(I.s_items, items, s));
@@ -1476,7 +1493,9 @@ pipnn_status pipnn_insert(pipnn_index *idx, int64_t n_new, const int32_t *d_grou
   HIPCHK(hipStreamSynchronize(s));
   HIPCHK(launch_robustprune(I, d_reservoirs, d_graph, d_degree, I.i_list.as<uint32_t>(), touched,
                             s));
-  return finish_bins(I, s, "insert");
+  st = finish_bins(I, s, "insert");
+  rollback.done = st == PIPNN_OK;
+  return st;
   GUARD_END
 }
 
@@ -1792,6 +1811,37 @@ pipnn_status pipnn_search(pipnn_index *idx, const uint32_t *d_graph, const void 
                          d_out_dist ? d_out_dist + q0 * k : nullptr,
                          d_out_cmps ? d_out_cmps + q0 : nullptr, I.q_seen.as<uint32_t>(), words,
                          s));
+  }
+  return PIPNN_OK;
+  GUARD_END
+}
+
+pipnn_status pipnn_knn_graph(pipnn_index *idx, const uint32_t *d_graph, int32_t k, int32_t L,
+                             uint32_t start, uint32_t *d_out_ids, float *d_out_dist,
+                             pipnn_stream_t stream) {
+  GUARD_BEGIN
+  if (!idx || !d_graph || !d_out_ids) return fail(PIPNN_EINVAL, "NULL argument");
+  Index &I = *reinterpret_cast<Index *>(idx);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  if (k < 1 || k + 1 > L || L > 1024) return fail(PIPNN_EINVAL, "need 1 <= k < L <= 1024");
+  const int64_t n = I.n;
+  if ((int64_t)start >= n) return fail(PIPNN_EINVAL, "start >= n");
+  const int64_t words = (n + 31) / 32;
+  const int64_t budget_words = (int64_t)1 << 26;  // 256 MiB of seen bitmaps
+  const int64_t chunk =
+      std::max<int64_t>(1, std::min<int64_t>({n, budget_words / words, (int64_t)1 << 16}));
+  const int32_t k1 = k + 1;
+  HIPCHK(I.q_seen.ensure((size_t)chunk * words * 4));
+  HIPCHK(I.g_ids.ensure((size_t)chunk * k1 * 4));
+  HIPCHK(I.g_dist.ensure((size_t)chunk * k1 * 4));
+  for (int64_t q0 = 0; q0 < n; q0 += chunk) {
+    const int64_t nb = std::min(chunk, n - q0);
+    HIPCHK(hipMemsetAsync(I.q_seen.p, 0, (size_t)nb * words * 4, s));
+    HIPCHK(launch_search(I, n, d_graph, I.xf() + q0 * I.d, nb, k1, L, start,
+                         I.g_ids.as<uint32_t>(), I.g_dist.as<float>(), nullptr,
+                         I.q_seen.as<uint32_t>(), words, s));
+    HIPCHK(launch_drop_self(I.g_ids.as<uint32_t>(), I.g_dist.as<float>(), nb, k1, q0, d_out_ids,
+                            d_out_dist, s));
   }
   return PIPNN_OK;
   GUARD_END

@@ -987,4 +987,40 @@ hipError_t launch_search(const Index &I, int64_t n, const uint32_t *graph, const
   return hipGetLastError();
 }
 
+// Rows of k + 1 search results of the points q0 .. q0 + nq - 1 searched as
+// queries: each row's own id is dropped (its first occurrence), or, when it
+// is not among the k + 1, the last entry; k entries per point remain.
+__global__ void drop_self_kernel(const uint32_t *__restrict__ ids, const float *__restrict__ dist,
+                                 int64_t nq, int k1, int64_t q0, uint32_t *__restrict__ out_ids,
+                                 float *__restrict__ out_dist) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nq) return;
+  const uint32_t self = (uint32_t)(q0 + r);
+  const int k = k1 - 1;
+  const uint32_t *in = ids + r * k1;
+  const float *din = dist + r * k1;
+  uint32_t *o = out_ids + (q0 + r) * k;
+  float *od = out_dist ? out_dist + (q0 + r) * k : nullptr;
+  bool dropped = false;
+  int j = 0;
+  for (int i = 0; i < k1 && j < k; ++i) {
+    const uint32_t id = in[i];
+    if (!dropped && id == self) {
+      dropped = true;
+      continue;
+    }
+    o[j] = id;
+    if (od) od[j] = din[i];
+    ++j;
+  }
+}
+
+hipError_t launch_drop_self(const uint32_t *ids, const float *dist, int64_t nq, int32_t k1,
+                            int64_t q0, uint32_t *out_ids, float *out_dist, hipStream_t s) {
+  if (nq == 0) return hipSuccess;
+  hipLaunchKernelGGL(drop_self_kernel, dim3((unsigned)((nq + 255) / 256)), dim3(256), 0, s, ids,
+                     dist, nq, k1, q0, out_ids, out_dist);
+  return hipGetLastError();
+}
+
 }  // namespace pipnn

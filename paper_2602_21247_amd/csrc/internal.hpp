@@ -65,6 +65,7 @@ struct Index {
   int64_t cap = 0;              // rows the per-point buffers hold (pipnn_reserve)
   DevBuf i_rows, i_cols, i_assign, i_flag, i_pos, i_list, i_tmp, i_segs;
   DevBuf q_conv, q_seen;        // search scratch (search may overlap an insertion)
+  DevBuf g_ids, g_dist;         // k-NN graph: k + 1 results per point of a chunk
   int32_t device = 0;           // the HIP device current at pipnn_create
   int32_t n_cu = 256;           // compute units of the device (persistent grid size)
   int32_t leaf_nw = 4;          // waves (of 32 rows) per leaf work item: 4, or 2 where built
@@ -281,5 +282,9 @@ hipError_t launch_search(const Index &I, int64_t n, const uint32_t *graph, const
                          int64_t nq, int32_t k, int32_t L, uint32_t start, uint32_t *out_ids,
                          float *out_dist, uint32_t *out_cmps, uint32_t *visited_bits,
                          int64_t words_per_query, hipStream_t s);
+
+// k + 1 results per point searched as a query -> k without the point itself
+hipError_t launch_drop_self(const uint32_t *ids, const float *dist, int64_t nq, int32_t k1,
+                            int64_t q0, uint32_t *out_ids, float *out_dist, hipStream_t s);
 
 }  // namespace pipnn

@@ -305,9 +305,12 @@ def workload_queries(cfg: int, nq: int | None = None) -> np.ndarray:
     raise ValueError(cfg)
 
 
-def workload_hyperplanes(cfg: int) -> np.ndarray:
+def workload_hyperplanes(cfg: int, m: int | None = None) -> np.ndarray:
+    """Hyperplanes of workload ``cfg`` (its hash_bits rows, or ``m``): rows
+    are drawn in order from one seeded stream, so the first rows of a larger
+    draw equal a smaller draw."""
     w = WORKLOADS[cfg]
-    return hyperplanes(w.hash_bits, w.d, seed=2000 + cfg, integer=(cfg == 2))
+    return hyperplanes(m or w.hash_bits, w.d, seed=2000 + cfg, integer=(cfg == 2))
 
 
 def workload_seed(cfg: int) -> int:

@@ -240,7 +240,7 @@ def test_wide_build_recall_against_oracle_graph(wide):
     X16, H, off, mem = wide
     X = X16.astype(np.float32)
     p = wide_params()
-    Q = pi.workload_queries(4, 200).astype(np.float32)
+    Q = pi.workload_queries(4, 1000).astype(np.float32)
     idx = pp.Index(dev(X16), dev(H), p)
     res = pp.reservoir_init(X.shape[0], p.l_max)
     idx.build_leaves(dev(off), dev(mem), res)
@@ -254,13 +254,16 @@ def test_wide_build_recall_against_oracle_graph(wide):
     og, _ = oracle.robustprune(X, ores, p.alpha, p.R, metric=1)
     start, _ = oracle.start_node(X)
     _, gd = oracle.bruteforce_knn(X, Q, 10, metric=1)
-    for L in (32, 64):
-        a, _, _ = oracle.beam_search(X, u32(g), Q, 10, L, start, metric=1)
+    G = u32(g)
+    same = np.mean(np.all(G == og, axis=1))
+    for L in (32, 64, 128):
+        a, _, _ = oracle.beam_search(X, G, Q, 10, L, start, metric=1)
         b, _, _ = oracle.beam_search(X, og, Q, 10, L, start, metric=1)
         ra = oracle.recall_at_k(a, X, Q, gd, metric=1)
         rb = oracle.recall_at_k(b, X, Q, gd, metric=1)
-        print(f"L={L} gpu-graph recall {ra:.4f} oracle-graph recall {rb:.4f}")
-        assert abs(ra - rb) <= 0.01
+        print(f"identical graph rows {same:.4f}; L={L} gpu-graph recall {ra:.4f} "
+              f"oracle-graph recall {rb:.4f}")
+        assert abs(ra - rb) <= 0.003
     idx.close()
 
 

@@ -361,6 +361,47 @@ def test_full_build_bit_exact(exact_build):
     idx.close()
 
 
+def _drop_own(ids, dist, k):
+    """Rows of k + 1 results of point i searched as a query: i's own id
+    dropped (its first occurrence), else the last entry."""
+    out_i = np.zeros((ids.shape[0], k), dtype=np.uint32)
+    out_d = np.zeros((ids.shape[0], k), dtype=np.float64)
+    for i in range(ids.shape[0]):
+        row = list(zip(ids[i].tolist(), dist[i].tolist()))
+        j = next((t for t, (v, _) in enumerate(row) if v == i), None)
+        keep = row[:j] + row[j + 1:] if j is not None else row[:k]
+        out_i[i] = [v for v, _ in keep]
+        out_d[i] = [dd for _, dd in keep]
+    return out_i, out_d
+
+
+def test_knn_graph_bit_exact(exact_build):
+    """Approximate 10-NN graph (Sec. 5, k-NN graph construction: every point
+    searched on the built graph): equal to the oracle's BeamSearch of every
+    point with its own id dropped, ids and distances bit for bit, and its
+    recall against the exact 10 nearest other points reported."""
+    X, H, p, ref = exact_build
+    idx = pp.Index(dev(X), dev(H), p)
+    g = dev(ref["graph"])
+    start, _ = oracle.start_node(X)
+    k = 10
+    for L in (16, 48):
+        ids, dist = idx.knn_graph(g, k, L, start)
+        torch.cuda.synchronize()
+        oi, od, _ = oracle.beam_search(X, ref["graph"], X, k + 1, L, start)
+        wi, wd = _drop_own(oi, od, k)
+        assert np.array_equal(u32(ids), wi), L
+        assert np.array_equal(dist.cpu().numpy().astype(np.float64), wd), L
+        # recall on a sample: exact 11 nearest including the point itself
+        samp = np.arange(0, X.shape[0], 97)
+        _, gd = oracle.bruteforce_knn(X, X[samp], k + 1)
+        hits = sum(int((wd[i] <= gd[t, k]).sum()) for t, i in enumerate(samp))
+        print(f"k-NN graph L={L}: recall@10 {hits / (k * len(samp)):.4f}")
+    with pytest.raises(pp.PipnnError):
+        idx.knn_graph(g, 10, 10, start)  # needs L > k
+    idx.close()
+
+
 def test_build_order_independence(exact_build):
     X, H, p, ref = exact_build
     idx = pp.Index(dev(X), dev(H), p)

@@ -95,6 +95,48 @@ def test_insert_bit_exact_against_oracle(base):
     idx.close()
 
 
+def test_failed_insert_leaves_index_usable(base):
+    """An insertion that fails after its rows were routed (a leaf would grow
+    past 65,535 columns) leaves the point count as it was: the next
+    insertion, of other points in the same rows, still equals the oracle's
+    insertion bit for bit."""
+    X, H, p = base
+    m_bad = 65_000
+    cap = N0 + m_bad
+    Xc = torch.zeros((cap, D), dtype=torch.float32, device="cuda")
+    Xc[:N0] = torch.from_numpy(X[:N0]).cuda()
+    Hd = torch.from_numpy(H).cuda()
+    idx = pp.Index(Xc[:N0], Hd, p)
+    off, mem = idx.partition()
+    res = torch.empty((cap, p.l_max), dtype=torch.int64, device="cuda")
+    pp.reservoir_init(N0, p.l_max, out=res[:N0])
+    idx.build_leaves(off, mem, res[:N0])
+    g = torch.full((cap, p.R), -1, dtype=torch.int32, device="cuda")
+    deg = torch.zeros(cap, dtype=torch.int32, device="cuda")
+    idx.robustprune(res[:N0], g[:N0], deg[:N0])
+    idx.reserve(cap)
+    torch.cuda.synchronize()
+    res0 = canon(idx, res, N0).copy()
+    # 65,000 copies of one point in one request: its two leaves would grow
+    # past 65,535 columns
+    Xc[N0:] = Xc[0]
+    with pytest.raises(pp.PipnnError, match="65535"):
+        idx.insert(m_bad, res, g, deg)
+    torch.cuda.synchronize()
+    assert idx.n == N0
+    assert np.array_equal(canon(idx, res, N0), res0)
+    m = 1200
+    Xc[N0:N0 + m] = torch.from_numpy(X[N0:N0 + m]).cuda()
+    groups = np.repeat(np.arange(2, dtype=np.int32), m // 2)
+    idx.insert(m, res, g, deg, torch.from_numpy(groups).cuda())
+    torch.cuda.synchronize()
+    ores, touched, orows = oracle.insert(X[:N0 + m], N0, groups, off.cpu().numpy(), u32(mem),
+                                         res0, H, p.k, p.alpha, p.R, fanout0=p.fanout[0])
+    assert np.array_equal(canon(idx, res, N0 + m), oracle.reservoir_canonical(ores))
+    assert np.array_equal(u32(g[:N0 + m])[touched], orows)
+    idx.close()
+
+
 def test_insert_alone_equals_together(base):
     X, H, p = base
     m = 900
