@@ -96,7 +96,12 @@ typedef int32_t pipnn_status;
  *               distances and RobustPrune's rows are read from the copy
  *               too (half the bytes; the same values); otherwise the
  *               partition uses the float32 vectors for d <= 256 and the
- *               copy above.
+ *               copy above. A float32 index of at most 128 dimensions
+ *               keeps an fp16 copy while X passes the integer check (see
+ *               pipnn_stats.data_int_exact); where that copy holds X
+ *               exactly, the partition and RobustPrune read it the same
+ *               way (every distance form is then the same integer in
+ *               either format) and the leaf GEMM stays FP32.
  *  rescore_mult 0, or r >= 2: select the r*k nearest by the GEMM distance
  *               and keep the k nearest by an FP32 direct-difference rescore.
  *  seed         root key of the leader sampling (Alg. 5, SampleLeaders).
@@ -397,7 +402,9 @@ typedef struct {
   int32_t leaf_knn_launches;     /* leaf kernel launches since profiling on */
   int64_t leaf_pairs;            /* sum of s^2 over the leaves of the last build */
   int64_t records;               /* candidate records binned by the last build */
-  int32_t operand_exact;         /* 1: the reduced-precision copy holds X exactly */
+  int32_t operand_exact;         /* 1: the 16-bit or reduced-precision copy of X (the GEMM
+                                    operand, or a float32 index's fp16 copy) holds X exactly
+                                    and is used where the gemm_prec notes say */
   int32_t data_int_exact;        /* 1: X is integral with a range that makes every squared-L2
                                     form exact in float32, so the leaf picks skip the winners'
                                     FP32 recompute (no rescoring) */

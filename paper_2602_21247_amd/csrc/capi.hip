@@ -295,6 +295,39 @@ static void flush_events(Index &I) {
 
 }  // namespace pipnn
 
+namespace {
+
+// The fp16 copy of a float32 index of at most 128 dimensions, kept while X
+// is integral (int_exact): made or refreshed by create and prepare; outside
+// stream capture it also reads back whether the copy holds X exactly. Where
+// it does, the partition's leader distances and RobustPrune's rows come from
+// it (half the bytes, the same values; every distance form is the same
+// integer in either format).
+hipError_t refresh_fp32_copy(Index &I, hipStream_t s) {
+  if (I.p.gemm_prec != PIPNN_PREC_FP32 || I.d > 128) return hipSuccess;
+  const bool capturing = stream_capturing(s);
+  if (!I.int_exact) {
+    if (!capturing) I.op_exact = false;
+    return hipSuccess;
+  }
+  hipError_t e;
+  if (!I.xlow.p) {
+    if (capturing) return hipSuccess;  // no copy yet: op_exact stays false
+    I.copy_prec = PIPNN_PREC_FP16;
+    I.ldo = lowp_padded_dim(I.d);
+    const size_t c = (size_t)I.cap;
+    if ((e = I.xlow.ensure(c * I.ldo * 2)) != hipSuccess ||
+        (e = I.xscale.ensure(c * 4)) != hipSuccess || (e = I.lnorms.ensure(c * 4)) != hipSuccess ||
+        (e = I.op_flag.ensure(64)) != hipSuccess)
+      return e;
+  }
+  if ((e = clear_op_flag(I, s)) != hipSuccess || (e = launch_quantize(I, s)) != hipSuccess)
+    return e;
+  return capturing ? hipSuccess : read_op_flag(I, true, s);
+}
+
+}  // namespace
+
 extern "C" {
 
 const char *pipnn_version(void) { return "pipnn-gfx950 0.1.0"; }
@@ -335,7 +368,7 @@ size_t pipnn_workspace_bytes(const pipnn_params *p, int64_t n, int32_t d,
   b += (size_t)picks * 8;                                     // picks (id + dist)
   b += (size_t)rec * 8;                                       // binned slots
   b += (size_t)(n + 1) * 8 + (size_t)n * 4;                   // bin offsets + counts
-  if (p->gemm_prec != PIPNN_PREC_FP32)                        // operand copy, scales, norms
+  if (p->gemm_prec != PIPNN_PREC_FP32 || d <= 128)         // operand / fp16 copy, scales, norms
     b += (size_t)n * lowp_padded_dim(d) * (p->gemm_prec == PIPNN_PREC_FP8 ? 1 : 2) +
          (size_t)n * 8;
   return b;
@@ -409,7 +442,11 @@ pipnn_status pipnn_create(const pipnn_params *p, const void *d_X, int64_t n, int
     if ((e = launch_pad_range(*I, 0, n, s)) != hipSuccess)
       return cleanup(fail(PIPNN_EDEVICE, "pad launch failed: %s", hipGetErrorString(e)));
   }
+  if ((e = refresh_fp32_copy(*I, s)) != hipSuccess)
+    return cleanup(fail(e == hipErrorOutOfMemory ? PIPNN_ENOMEM : PIPNN_EDEVICE,
+                        "fp16 copy failed: %s", hipGetErrorString(e)));
   if (p->gemm_prec != PIPNN_PREC_FP32) {
+    I->copy_prec = p->gemm_prec;
     I->ldo = lowp_padded_dim(d);
     if (I->ldo == 0)
       return cleanup(fail(PIPNN_EINVAL, "a reduced-precision leaf GEMM needs d <= 768"));
@@ -479,9 +516,11 @@ pipnn_status pipnn_partition_replica(pipnn_index *idx, int32_t replica, int64_t 
   // point-to-leader distances on the index's reduced-precision operand when
   // it holds X exactly or the float32 kernel is not built (d > 256), else
   // in float32
-  const int32_t part_prec =
-      (P.gemm_prec != PIPNN_PREC_FP32 && (I.op_exact || !knn_operand_dim(I.d, PIPNN_PREC_FP32)))
-          ? P.gemm_prec : PIPNN_PREC_FP32;
+  int32_t part_prec = PIPNN_PREC_FP32;
+  if (P.gemm_prec == PIPNN_PREC_FP32)
+    part_prec = I.copy16_exact() ? I.copy_prec : PIPNN_PREC_FP32;
+  else if (I.op_exact || !knn_operand_dim(I.d, PIPNN_PREC_FP32))
+    part_prec = P.gemm_prec;
   if (knn_operand_dim(I.d, part_prec) == 0)
     return fail(PIPNN_EINVAL, "partition of d = %d needs a reduced gemm_prec (float32 partition "
                               "distances are built for d <= 256)", I.d);
@@ -1277,8 +1316,8 @@ pipnn_status pipnn_reserve(pipnn_index *idx, int64_t n_cap, pipnn_stream_t strea
   HIPCHK(grow_keep(I.sketches, c * I.m * 4, n * I.m * 4, s));
   if (I.x_dtype != PIPNN_DTYPE_F32) HIPCHK(grow_keep(I.xf32, c * d * 4, n * d * 4, s));
   if (I.xpad.p) HIPCHK(grow_keep(I.xpad, c * I.ldf * 4, n * I.ldf * 4, s));
-  if (I.p.gemm_prec != PIPNN_PREC_FP32) {
-    const size_t eb = I.p.gemm_prec == PIPNN_PREC_FP8 ? 1 : 2;
+  if (I.xlow.p) {
+    const size_t eb = I.copy_prec == PIPNN_PREC_FP8 ? 1 : 2;
     HIPCHK(grow_keep(I.xlow, c * I.ldo * eb, n * I.ldo * eb, s));
     HIPCHK(grow_keep(I.xscale, c * 4, n * 4, s));
     HIPCHK(grow_keep(I.lnorms, c * 4, n * 4, s));
@@ -1340,7 +1379,7 @@ pipnn_status pipnn_insert(pipnn_index *idx, int64_t n_new, const int32_t *d_grou
   HIPCHK(launch_norms_sketches_range(I, n0, n_new, s));
   HIPCHK(read_int_check(I, false, s));
   HIPCHK(launch_pad_range(I, n0, n_new, s));
-  if (P.gemm_prec != PIPNN_PREC_FP32) {
+  if (I.xlow.p) {
     HIPCHK(clear_op_flag(I, s));
     HIPCHK(launch_quantize_range(I, n0, n_new, s));
     HIPCHK(read_op_flag(I, false, s));
@@ -1867,6 +1906,8 @@ pipnn_status pipnn_prepare(pipnn_index *idx, pipnn_stream_t stream) {
     // outside capture the operand's exactness is taken again; a captured
     // prepare keeps the one found by the last uncaptured encode
     if (!stream_capturing(s)) HIPCHK(read_op_flag(I, true, s));
+  } else {
+    HIPCHK(refresh_fp32_copy(I, s));
   }
   return PIPNN_OK;
   GUARD_END

@@ -714,8 +714,7 @@ hipError_t launch_robustprune(const Index &I, const uint64_t *res, uint32_t *gra
       subset ? subset : (I.rp_order_valid ? I.rp_order.as<uint32_t>() : nullptr);
   const int64_t n_items = subset ? n_subset : I.n;
   if (n_items <= 0) return hipSuccess;
-  const bool op16 = (I.p.gemm_prec == PIPNN_PREC_BF16 || I.p.gemm_prec == PIPNN_PREC_FP16) &&
-                    I.op_exact && I.xlow.p;
+  const bool op16 = I.copy16_exact();
   if (I.p.l_max <= 64 && op16 && (I.ldo == 64 || I.ldo == 96 || I.ldo == 128)) {
     const int64_t blocks = xcd_grid((n_items + kRpWaves - 1) / kRpWaves);
     auto go = [&](auto kern) {
@@ -723,7 +722,7 @@ hipError_t launch_robustprune(const Index &I, const uint64_t *res, uint32_t *gra
                          I.xlow.as<uint8_t>(), I.norms.as<float>(), I.n, I.p.metric, res,
                          I.p.l_max, I.p.alpha, I.p.R, order, n_items, graph, degree);
     };
-    const bool b = I.p.gemm_prec == PIPNN_PREC_BF16;
+    const bool b = I.copy_prec == PIPNN_PREC_BF16;
     if (I.ldo == 64) b ? go(robustprune_mfma16_kernel<PIPNN_PREC_BF16, 64>)
                        : go(robustprune_mfma16_kernel<PIPNN_PREC_FP16, 64>);
     else if (I.ldo == 96) b ? go(robustprune_mfma16_kernel<PIPNN_PREC_BF16, 96>)

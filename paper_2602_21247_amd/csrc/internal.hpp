@@ -32,7 +32,10 @@ struct Index {
   hipStream_t stream = nullptr;
 
   DevBuf xf32;      // float32 copy of X when X is not float32
-  DevBuf xlow;      // low-precision copy for the leaf GEMM (bf16 / fp16 / fp8)
+  DevBuf xlow;      // low-precision copy of X (copy_prec): the leaf GEMM operand of a reduced
+                    // gemm_prec; for a float32 index of at most 128 dimensions an fp16 copy
+                    // kept while X is integral (int_exact), used where it holds X exactly
+  int32_t copy_prec = PIPNN_PREC_FP32;  // the format of xlow (FP32: none)
   DevBuf xscale;    // per-point fp8 decode scale (value = code * scale)
   DevBuf lnorms;    // n float32, squared norms of the decoded low-precision operand
   DevBuf op_flag;   // int32: set by the encoder when a value does not survive encoding
@@ -104,6 +107,15 @@ struct Index {
   double phase_ms[8] = {0};
   int leaf_launches = 0;
 
+  // The exact 16-bit copy serves the partition's leader distances and
+  // RobustPrune's rows: for a bf16 / fp16 index when it holds X exactly; for
+  // a float32 index when it holds X exactly and X passed the integer check
+  // (then every distance form is the same integer in either format).
+  bool copy16_exact() const {
+    if (!xlow.p || !op_exact) return false;
+    if (copy_prec != PIPNN_PREC_BF16 && copy_prec != PIPNN_PREC_FP16) return false;
+    return p.gemm_prec != PIPNN_PREC_FP32 || int_exact;
+  }
   const float *xf() const;
   const float *xop32() const;  // the float32 GEMM operand: xpad if allocated, else xf()
 };

@@ -74,7 +74,7 @@ hipError_t launch_knn(const KnnLaunch &L, hipStream_t s) {
   }
   const int nw = L.nw, n_cu = I.n_cu;
   if (lowp) {
-    if (!a.Xop || a.ldo != lowp_padded_dim(I.d) || L.prec != I.p.gemm_prec)
+    if (!a.Xop || a.ldo != lowp_padded_dim(I.d) || L.prec != I.copy_prec)
       return hipErrorInvalidValue;
     if (L.prec == PIPNN_PREC_BF16) return launch_knn_bf16(a, L.ksel, L.n_items, nw, quad, n_cu, s);
     if (L.prec == PIPNN_PREC_FP16) return launch_knn_fp16(a, L.ksel, L.n_items, nw, quad, n_cu, s);

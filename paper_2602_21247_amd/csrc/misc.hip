@@ -274,9 +274,10 @@ hipError_t launch_quantize(const Index &I, hipStream_t s) {
 hipError_t launch_quantize_range(const Index &I, int64_t p0, int64_t cnt, hipStream_t s) {
   if (cnt <= 0) return hipSuccess;
   const int64_t blocks = (cnt + 3) / 4;
-  const size_t eb = I.p.gemm_prec == PIPNN_PREC_FP8 ? 1 : 2;
+  if (!I.xlow.p || I.copy_prec == PIPNN_PREC_FP32) return hipErrorInvalidValue;
+  const size_t eb = I.copy_prec == PIPNN_PREC_FP8 ? 1 : 2;
   hipLaunchKernelGGL(quantize_kernel, dim3((unsigned)blocks), dim3(256), 0, s, I.xf() + p0 * I.d,
-                     cnt, I.d, I.ldo, I.p.gemm_prec,
+                     cnt, I.d, I.ldo, I.copy_prec,
                      reinterpret_cast<void *>(I.xlow.as<uint8_t>() + p0 * I.ldo * eb),
                      I.xscale.as<float>() + p0, I.lnorms.as<float>() + p0, I.op_flag.as<int>());
   return hipGetLastError();

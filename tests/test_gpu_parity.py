@@ -424,15 +424,17 @@ def test_build_order_independence(exact_build):
     idx.close()
 
 
-@pytest.mark.parametrize("prec", ["bf16", "fp16"])
+@pytest.mark.parametrize("prec", ["bf16", "fp16", "fp32"])
 def test_exact_16bit_operand_build(exact_build, prec):
     """Integer features of at most 8 significant bits survive bf16 / fp16
     encoding, so the 16-bit copy holds X exactly: the partition reads the
-    copy, the leaf GEMM multiplies it, RobustPrune loads its rows from it,
-    and the whole build is still the oracle's bit for bit. A copy that does
-    not hold X (the same data plus 1/3) keeps the float32 paths."""
+    copy, the leaf GEMM multiplies it (a float32 index keeps its float32
+    leaf GEMM and an fp16 copy for the partition and RobustPrune while X is
+    integral), RobustPrune loads its rows from it, and the whole build is
+    still the oracle's bit for bit. A copy that does not hold X (the same
+    data plus 1/3) keeps the float32 paths."""
     X, H, p, ref = exact_build
-    code = {"bf16": pp.PREC_BF16, "fp16": pp.PREC_FP16}[prec]
+    code = {"bf16": pp.PREC_BF16, "fp16": pp.PREC_FP16, "fp32": pp.PREC_FP32}[prec]
     kw = {f: getattr(p, f) for f in ("c_max", "c_min", "k", "l_max", "R", "seed")}
     p16 = gpu_params(gemm_prec=code, **kw)
     idx, off, mem, res, g, deg = pp.build(dev(X), dev(H), p16)
