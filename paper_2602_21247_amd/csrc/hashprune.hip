@@ -127,9 +127,18 @@ __global__ void __launch_bounds__(256) bin_scatter_kernel(const uint32_t *row_id
 // hashes compare LDS copies instead of gathering two sketches from memory;
 // larger leaves read the sketches from memory. The compares are the same.
 constexpr int kLeafBinLds = kLeafBinMaxRows * 20;  // bytes: int64 base + 3 uint32 counters per row
+// The scatter of leaves whose counters and sketches need more than
+// kLeafBinLds runs in a second launch with one workgroup per CU and this
+// much LDS (leaves of up to ~2,100 rows at m = 12), so that their hashes
+// also compare LDS copies.
+constexpr int kLeafBinLdsBig = 144 * 1024;
 constexpr int kLeafBinThreads = 1024;  // 16 waves: the LDS admits two workgroups per CU
 
-template <bool SCATTER>
+// LDSB: LDS bytes of the scatter. A leaf is scattered by the instance that
+// stages its sketches with the least LDS: the small one unless only the big
+// one fits them; leaves that fit neither read the sketches from memory in
+// the small instance.
+template <bool SCATTER, int LDSB = kLeafBinLds>
 __global__ void __launch_bounds__(kLeafBinThreads) leaf_bin_kernel(
     const int64_t *__restrict__ leaf_off, int64_t off0, const uint32_t *__restrict__ members,
     const uint32_t *__restrict__ picks, const float *__restrict__ dist, int k,
@@ -137,10 +146,15 @@ __global__ void __launch_bounds__(kLeafBinThreads) leaf_bin_kernel(
     uint32_t *__restrict__ cnt, uint64_t *__restrict__ bins) {
   // per row: sB (the row's first bin position), sF / sR (forward / reverse
   // records: count, then cursor), sRn (reverse total); then the sketches
-  __shared__ __attribute__((aligned(16))) uint8_t sMem[SCATTER ? kLeafBinLds : kLeafBinMaxRows * 8];
+  __shared__ __attribute__((aligned(16))) uint8_t sMem[SCATTER ? LDSB : kLeafBinMaxRows * 8];
   const int64_t r0 = leaf_off[blockIdx.x] - off0;
   const int mm = (int)(leaf_off[blockIdx.x + 1] - off0 - r0);
-  const bool lds_sk = SCATTER && (int64_t)mm * (20 + 4 * m) <= kLeafBinLds;
+  const int64_t need = (int64_t)mm * (20 + 4 * m);
+  if (SCATTER) {
+    const bool big_only = need > kLeafBinLds && need <= kLeafBinLdsBig;
+    if (big_only != (LDSB == kLeafBinLdsBig)) return;
+  }
+  const bool lds_sk = SCATTER && need <= LDSB;
   const int cap = lds_sk ? mm : kLeafBinMaxRows;
   int64_t *sB = reinterpret_cast<int64_t *>(sMem);
   uint32_t *sF = reinterpret_cast<uint32_t *>(sMem + (SCATTER ? (size_t)cap * 8 : 0));
@@ -218,10 +232,13 @@ hipError_t launch_leaf_bin(bool scatter, const int64_t *leaf_off, int64_t off0, 
                            int32_t k, const float *sketch, int32_t m, const int64_t *bin_off,
                            uint32_t *cnt, uint64_t *bins, hipStream_t s) {
   if (n_leaves <= 0) return hipSuccess;
-  if (scatter)
+  if (scatter) {
     hipLaunchKernelGGL(leaf_bin_kernel<true>, dim3((unsigned)n_leaves), dim3(kLeafBinThreads), 0, s, leaf_off,
                        off0, members, picks, dist, k, sketch, m, bin_off, cnt, bins);
-  else
+    hipLaunchKernelGGL((leaf_bin_kernel<true, kLeafBinLdsBig>), dim3((unsigned)n_leaves),
+                       dim3(kLeafBinThreads), 0, s, leaf_off, off0, members, picks, dist, k, sketch,
+                       m, bin_off, cnt, bins);
+  } else
     hipLaunchKernelGGL(leaf_bin_kernel<false>, dim3((unsigned)n_leaves), dim3(kLeafBinThreads), 0, s, leaf_off,
                        off0, members, picks, dist, k, sketch, m, bin_off, cnt, bins);
   return hipGetLastError();
@@ -429,12 +446,189 @@ __global__ void __launch_bounds__(64 * kMergeWaves) hashprune_merge_kernel(
   for (int i = lane; i < l_max; i += 64) r[i] = i < nres ? slot_of_key2(B[i]) : empty_slot();
 }
 
+// ---------------------------------------------------------------------
+// Register merge (l_max <= 128): a wave holds the point's reservoir and up
+// to 64 * E - l_max of its records as 64-bit keys, E per lane (element
+// i = e * 64 + lane). A bitonic sort by key1 = (hash, rank, id) puts every
+// bucket's minimum first in its run, so an element is a bucket minimum iff
+// its hash differs from the previous element's; a second sort of the minima
+// by key2 = (rank, id, hash) gives the reservoir order, whose first l_max
+// entries are the new reservoir. Larger bins are taken in chunks (the kept
+// minima stay in the first elements). No LDS is used.
+// x of lane ^ J, by VALU lane moves: DPP quad permutations (J = 1, 2), a
+// half-row mirror then a quad reversal (J = 4: 7 - (i ^ 3) = i ^ 4 within 8
+// lanes), a row rotation by 8 (J = 8), and the gfx950 row / half-wave swaps
+// (J = 16, 32).
+template <int J>
+__device__ __forceinline__ uint32_t xor_lane_u32(uint32_t x) {
+  if constexpr (J == 1) {
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0xB1, 0xF, 0xF, false);  // [1,0,3,2]
+  } else if constexpr (J == 2) {
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x4E, 0xF, 0xF, false);  // [2,3,0,1]
+  } else if constexpr (J == 4) {
+    const int m = __builtin_amdgcn_mov_dpp((int)x, 0x141, 0xF, 0xF, false);   // row_half_mirror
+    return (uint32_t)__builtin_amdgcn_mov_dpp(m, 0x1B, 0xF, 0xF, false);      // [3,2,1,0]
+  } else if constexpr (J == 8) {
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x128, 0xF, 0xF, false);  // row_ror:8
+  } else if constexpr (J == 16) {
+    const auto r = __builtin_amdgcn_permlane16_swap(x, x, false, false);
+    return (__lane_id() & 16) ? r[0] : r[1];
+  } else {
+    static_assert(J == 32, "lane xor of 1..32");
+    const auto r = __builtin_amdgcn_permlane32_swap(x, x, false, false);
+    return (__lane_id() & 32) ? r[0] : r[1];
+  }
+}
+template <int J>
+__device__ __forceinline__ uint64_t xor_lane_u64(uint64_t v) {
+  const uint32_t lo = xor_lane_u32<J>((uint32_t)v);
+  const uint32_t hi = xor_lane_u32<J>((uint32_t)(v >> 32));
+  return ((uint64_t)hi << 32) | lo;
+}
+__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int j) {
+  switch (j) {
+    case 1: return xor_lane_u64<1>(v);
+    case 2: return xor_lane_u64<2>(v);
+    case 4: return xor_lane_u64<4>(v);
+    case 8: return xor_lane_u64<8>(v);
+    case 16: return xor_lane_u64<16>(v);
+    default: return xor_lane_u64<32>(v);
+  }
+}
+__device__ __forceinline__ uint64_t shfl_up1_u64(uint64_t v) {
+  const uint32_t lo = (uint32_t)__shfl_up((int)(uint32_t)v, 1, 64);
+  const uint32_t hi = (uint32_t)__shfl_up((int)(uint32_t)(v >> 32), 1, 64);
+  return ((uint64_t)hi << 32) | lo;
+}
+__device__ __forceinline__ uint64_t readlane63_u64(uint64_t v) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, 63);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), 63);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// Ascending bitonic sort of the 64 * E keys of the wave.
+template <int E>
+__device__ __forceinline__ void reg_bitonic_sort(uint64_t (&v)[E], int lane) {
+  constexpr int N = 64 * E;
+#pragma unroll
+  for (int k = 2; k <= N; k <<= 1) {
+#pragma unroll
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      if (j >= 64) {
+        const int je = j >> 6;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+          if ((e & je) == 0) {
+            const bool asc = ((e * 64 + lane) & k) == 0;
+            const uint64_t x = v[e], y = v[e | je];
+            const bool sw = (x > y) == asc;
+            v[e] = sw ? y : x;
+            v[e | je] = sw ? x : y;
+          }
+        }
+      } else {
+        const bool lower = (lane & j) == 0;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+          // the lower lane of a pair keeps the minimum in an ascending block,
+          // the upper lane in a descending one: one compare and one select
+          const bool keep_min = lower == (((e * 64 + lane) & k) == 0);
+          const uint64_t y = shfl_xor_u64(v[e], j);
+          v[e] = ((v[e] < y) == keep_min) ? v[e] : y;
+        }
+      }
+    }
+  }
+}
+
+// Merge of one point with E keys per lane, writing its reservoir r. s0/s1:
+// the reservoir's slots lane and 64 + lane (as loaded); `used`: the elements
+// the reservoir occupies (its valid prefix, or all l_max slots when the
+// valid slots are not a prefix), so records start at element `used`.
+template <int E>
+__device__ void merge_point_reg(uint64_t *__restrict__ r, int l_max, uint64_t s0, uint64_t s1,
+                                int used, const uint64_t *__restrict__ bins, int64_t b0,
+                                int64_t b1, int lane) {
+  constexpr int N = 64 * E;
+  uint64_t v[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const uint64_t sl = e == 0 ? s0 : e == 1 ? s1 : empty_slot();
+    v[e] = slot_id(sl) != kEmptyId ? key1_of_slot(sl) : kNone;
+  }
+  int nres = 0;
+  int64_t c0 = b0;
+  for (;;) {
+    const int nc = (int)min((int64_t)(N - used), b1 - c0);
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int i = e * 64 + lane;
+      if (i >= used && i < used + nc) v[e] = key1_of_slot(bins[c0 + (i - used)]);
+    }
+    c0 += nc;
+    reg_bitonic_sort<E>(v, lane);
+    // bucket minima: the first element of every run of equal hash
+    uint64_t last = kNone;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const uint64_t up = shfl_up1_u64(v[e]);
+      const uint64_t prev = lane == 0 ? last : up;
+      const bool first = (e == 0 && lane == 0) || (prev >> 48) != (v[e] >> 48);
+      last = readlane63_u64(v[e]);
+      v[e] = (v[e] != kNone && first) ? key2_of_key1(v[e]) : kNone;
+    }
+    int nk = 0;
+#pragma unroll
+    for (int e = 0; e < E; ++e) nk += __popcll(__ballot(v[e] != kNone));
+    reg_bitonic_sort<E>(v, lane);
+    nres = nk < l_max ? nk : l_max;
+    if (c0 >= b1) break;
+    // keep the first nres minima (as key1) for the next chunk
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int i = e * 64 + lane;
+      v[e] = i < nres ? key1_of_key2(v[e]) : kNone;
+    }
+    used = nres;
+  }
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int i = e * 64 + lane;
+    if (i < l_max) r[i] = i < nres ? slot_of_key2(v[e]) : empty_slot();
+  }
+  for (int i = N + lane; i < l_max; i += 64) r[i] = empty_slot();
+}
+
+__global__ void __launch_bounds__(64 * kMergeWaves) hashprune_merge_reg_kernel(
+    uint64_t *__restrict__ res, int64_t n, int l_max, const uint64_t *__restrict__ bins,
+    const int64_t *__restrict__ off) {
+  const int lane = threadIdx.x & 63;
+  const int64_t p = (int64_t)blockIdx.x * kMergeWaves + (threadIdx.x >> 6);
+  if (p >= n) return;
+  const int64_t b0 = off[p], b1 = off[p + 1];
+  if (b1 == b0) return;
+  uint64_t *r = res + p * l_max;
+  // the reservoir (l_max <= 128: two slots per lane)
+  const uint64_t s0 = lane < l_max ? r[lane] : empty_slot();
+  const uint64_t s1 = 64 + lane < l_max ? r[64 + lane] : empty_slot();
+  const uint64_t m0 = __ballot(slot_id(s0) != kEmptyId);
+  const uint64_t m1 = __ballot(slot_id(s1) != kEmptyId);
+  const int nres = __popcll(m0) + __popcll(m1);
+  // reservoirs this library writes keep their valid slots first
+  const bool prefix = m1 == 0 ? (m0 & (m0 + 1)) == 0 : (m0 == ~0ull && (m1 & (m1 + 1)) == 0);
+  const int used = prefix ? nres : l_max;
+  const int64_t tot = (int64_t)used + (b1 - b0);
+  if (tot <= 64) merge_point_reg<1>(r, l_max, s0, s1, used, bins, b0, b1, lane);
+  else if (tot <= 128) merge_point_reg<2>(r, l_max, s0, s1, used, bins, b0, b1, lane);
+  else merge_point_reg<4>(r, l_max, s0, s1, used, bins, b0, b1, lane);
+}
+
 hipError_t launch_hashprune_merge(uint64_t *res, int64_t n, int32_t l_max, const uint64_t *bins,
                                   const int64_t *off, hipStream_t s) {
   if (l_max > 256) return hipErrorInvalidValue;
   const int64_t blocks = (n + kMergeWaves - 1) / kMergeWaves;
   if (l_max <= 128)
-    hipLaunchKernelGGL(hashprune_merge_kernel<256>, dim3((unsigned)blocks), dim3(64 * kMergeWaves),
+    hipLaunchKernelGGL(hashprune_merge_reg_kernel, dim3((unsigned)blocks), dim3(64 * kMergeWaves),
                        0, s, res, n, l_max, bins, off);
   else
     hipLaunchKernelGGL(hashprune_merge_kernel<512>, dim3((unsigned)blocks), dim3(64 * kMergeWaves),
