@@ -60,8 +60,14 @@ def parse():
     ap.add_argument("--no-recall", action="store_true")
     ap.add_argument("--no-serving", action="store_true",
                     help="skip the insert/query serving stage")
-    ap.add_argument("--serve-requests", type=int, default=200,
-                    help="requests of the serving stage (80%% queries, 20%% insertions)")
+    ap.add_argument("--serve-requests", type=int, default=1000,
+                    help="requests of the serving stage per load (80%% queries, 20%% insertions)")
+    ap.add_argument("--serve-rates", default="0.25,0.5,0.75,1.0",
+                    help="offered loads of the serving stage, as fractions of its closed-loop "
+                         "capacity")
+    ap.add_argument("--serve-recall-queries", type=int, default=1000,
+                    help="queries per load whose recall@10 is checked against exact ground "
+                         "truth at their epoch")
     ap.add_argument("--cpu-budget", type=float, default=4.0,
                     help="target seconds of oracle work per sampled phase")
     ap.add_argument("--prec", default=None, choices=sorted(PREC_CODES),
@@ -273,23 +279,27 @@ def serving_stage(args, torch, np, pp, pi, w, cfg, X, H, p_kw, L_serve):
     stream (80% k=10 query batches of floor(exp(U(0, ln 4097))) queries, 20%
     insertion batches of floor(exp(U(0, ln 50001))) fresh points of the same
     mixture) first arrives all at once (closed loop: the capacity in
-    requests/s), then as a Poisson process at half that capacity on a fresh
-    copy of the index; latencies of the second run are reported."""
+    requests/s), then as a Poisson process at each of --serve-rates times
+    that capacity, each on a fresh copy of the index that starts with room
+    for one largest insertion and grows its capacity as insertions need it
+    (admitted by free HBM). Per rate: p50/p99 latency per request class,
+    inserts/s, QPS, capacity growths, and recall@10 of sampled queries
+    against exact ground truth over the points committed at their epoch."""
     from paper_2602_21247_amd import serving
     rng = np.random.default_rng(5)
     n = X.shape[0]
-    kinds = rng.random(args.serve_requests) < 0.8
-    sizes_q = np.floor(np.exp(rng.uniform(0, np.log(4097), args.serve_requests))).astype(int)
-    sizes_i = np.floor(np.exp(rng.uniform(0, np.log(50001), args.serve_requests))).astype(int)
+    nreq = args.serve_requests
+    kinds = rng.random(nreq) < 0.8
+    sizes_q = np.floor(np.exp(rng.uniform(0, np.log(4097), nreq))).astype(int)
+    sizes_i = np.floor(np.exp(rng.uniform(0, np.log(50001), nreq))).astype(int)
     n_ins = int(sizes_i[~kinds].sum())
-    cap = n + n_ins
     newpts = pi.integer_mixture(n_ins, w.d, 1000, pi.INT_MIXTURE_SIGMA, seed=5005,
-                                center_seed=2) if cfg == 2 else pi.workload_points(cfg, cap)[n:]
+                                center_seed=2) if cfg == 2 else pi.workload_points(cfg, n + n_ins)[n:]
     nq = int(sizes_q[kinds].sum())
     Qall = pi.workload_queries(cfg, nq)
     reqs_proto = []
     qo = io = 0
-    for rid in range(args.serve_requests):
+    for rid in range(nreq):
         if kinds[rid]:
             m = int(sizes_q[rid])
             reqs_proto.append(("query", Qall[qo:qo + m]))
@@ -298,20 +308,21 @@ def serving_stage(args, torch, np, pp, pi, w, cfg, X, H, p_kw, L_serve):
             m = int(sizes_i[rid])
             reqs_proto.append(("insert", newpts[io:io + m]))
             io += m
+    cap0 = n + 50_000   # room for one largest insertion; the server grows the rest
 
     def fresh():
-        Xc = torch.empty((cap, w.d), dtype=torch.float32, device="cuda")
+        Xc = torch.empty((cap0, w.d), dtype=torch.float32, device="cuda")
         Xc[:n].copy_(torch.from_numpy(X))
         params = pp.default_params(**p_kw)
         idx = pp.Index(Xc[:n], torch.from_numpy(H).cuda(), params)
         off, mem = idx.partition()
-        res = torch.empty((cap, w.l_max), dtype=torch.int64, device="cuda")
+        res = torch.empty((cap0, w.l_max), dtype=torch.int64, device="cuda")
         pp.reservoir_init(n, w.l_max, out=res[:n])
         idx.build_leaves(off, mem, res[:n])
-        g = torch.full((cap, w.R), -1, dtype=torch.int32, device="cuda")
-        deg = torch.zeros(cap, dtype=torch.int32, device="cuda")
+        g = torch.full((cap0, w.R), -1, dtype=torch.int32, device="cuda")
+        deg = torch.zeros(cap0, dtype=torch.int32, device="cuda")
         idx.robustprune(res[:n], g[:n], deg[:n])
-        idx.reserve(cap)
+        idx.reserve(cap0)
         start = idx.start_node()
         torch.cuda.synchronize()
         return idx, Xc, res, g, deg, start
@@ -324,51 +335,80 @@ def serving_stage(args, torch, np, pp, pi, w, cfg, X, H, p_kw, L_serve):
         t0 = time.perf_counter()
         out = srv.run(reqs)
         wall = time.perf_counter() - t0
-        return out, wall, idx, Xc, srv
+        return out, wall, idx, srv
 
-    out, wall, idx, Xc, srv = run(np.zeros(args.serve_requests))
-    capacity = args.serve_requests / wall
+    def recall_by_epoch(out, srv, budget):
+        """recall@10 of up to `budget` queries spread over the run's epochs,
+        each against the points committed when it ran; overall and the
+        lowest of the run's epoch quartiles."""
+        commit_n = {0: n}
+        for r in sorted((r for r in out.values() if r.kind == "insert" and r.status == "ok"),
+                        key=lambda r: r.first_id):
+            commit_n[r.batch + 1] = r.first_id + len(reqs_proto[r.rid][1])
+        qreqs = sorted((r for r in out.values() if r.kind == "query"), key=lambda r: r.epoch)
+        if not qreqs:
+            return None, None, 0
+        step = max(1, len(qreqs) * 40 // max(1, budget))
+        picked = qreqs[::step]
+        hits = tot = 0
+        per_q = []
+        for r in picked:
+            if tot >= budget * 10:
+                break
+            ne = max(v for b, v in commit_n.items() if b <= r.epoch)
+            Q = reqs_proto[r.rid][1][:64]
+            kth = ground_truth(torch, srv.X[:ne], torch.from_numpy(Q).cuda(), w.metric)
+            hq = int((torch.from_numpy(r.dist[:64]).cuda().double() <= kth[:, None]).sum().item())
+            hits += hq
+            tot += Q.shape[0] * 10
+            per_q.append((r.epoch, hq / (Q.shape[0] * 10.0)))
+        quart = np.array_split(np.array([v for _, v in per_q]), 4)
+        low = min(float(np.mean(qv)) for qv in quart if len(qv))
+        return hits / max(1, tot), low, tot // 10
+
+    out, wall, idx, srv = run(np.zeros(nreq))
+    capacity = nreq / wall
     idx.close()
-    del Xc, srv
-    log(f"[bench] serving: closed loop {args.serve_requests} requests in {wall:.2f} s "
+    del srv
+    log(f"[bench] serving: closed loop {nreq} requests in {wall:.2f} s "
         f"({capacity:.1f} requests/s)")
-    rate = 0.5 * capacity
-    arr = np.cumsum(np.random.default_rng(55).exponential(1.0 / rate, args.serve_requests))
-    out, wall, idx, Xc, srv = run(arr)
-    summ = serving.summarize(out, wall)
     ins_pts = sum(len(d) for kd, d in reqs_proto if kd == "insert")
     qs = sum(len(d) for kd, d in reqs_proto if kd == "query")
-    # recall@10 of a sample of queries against the points committed at their epoch
-    epochs = {}
-    for r in out.values():
-        if r.kind == "query":
-            epochs.setdefault(r.epoch, []).append(r)
-    commit_n = {0: n}
-    for r in sorted((r for r in out.values() if r.kind == "insert"), key=lambda r: r.first_id):
-        commit_n[r.batch + 1] = r.first_id + len(reqs_proto[r.rid][1])
-    hits = tot = 0
-    budget = 2000
-    for e, rs in sorted(epochs.items()):
-        if tot >= budget:
-            break
-        ne = max(v for b, v in commit_n.items() if b <= e)
-        for r in rs:
-            if tot >= budget:
-                break
-            Qd = torch.from_numpy(reqs_proto[r.rid][1]).cuda()
-            kth = ground_truth(torch, Xc[:ne], Qd, w.metric)
-            hits += int((torch.from_numpy(r.dist).cuda().double() <= kth[:, None]).sum().item())
-            tot += r.ids.shape[0] * 10
-    recall = hits / max(1, tot)
-    idx.close()
-    res = {"requests": args.serve_requests, "closed_loop_requests_per_s": capacity,
-           "offered_requests_per_s": rate, "wall_s": wall, "L": L_serve,
-           "inserted_points": ins_pts, "queries": qs,
-           "inserts_per_s": ins_pts / wall, "qps": qs / wall,
-           "recall_at_10_sampled": recall, "recall_sample_queries": tot // 10}
-    res.update(summ)
-    log(f"[bench] serving at {rate:.1f} requests/s: {summ}; recall@10 {recall:.4f}")
-    return res
+    rates = []
+    for frac in [float(v) for v in args.serve_rates.split(",") if v.strip()]:
+        rate = frac * capacity
+        arr = np.cumsum(np.random.default_rng(55).exponential(1.0 / rate, nreq))
+        out, wall, idx, srv = run(arr)
+        summ = serving.summarize(out, wall)
+        recall, low, sampled = recall_by_epoch(out, srv, args.serve_recall_queries)
+        ent = {"load": frac, "offered_requests_per_s": rate, "wall_s": wall,
+               "inserts_per_s": ins_pts / wall, "qps": qs / wall,
+               "capacity_growths": len(srv.growths),
+               "growth_ms": [round(t * 1e3, 1) for _, t in srv.growths],
+               "final_capacity": srv.cap, "rejected": srv.rejected,
+               "recall_at_10_sampled": recall, "recall_lowest_epoch_quartile": low,
+               "recall_sample_queries": sampled}
+        ent.update(summ)
+        log(f"[bench] serving at {frac:.2f} x capacity ({rate:.1f} requests/s): {summ}; "
+            f"recall@10 {recall:.4f}, growths {len(srv.growths)}")
+        idx.close()
+        del srv
+        rates.append(ent)
+    return {"requests_per_rate": nreq, "closed_loop_requests_per_s": capacity, "L": L_serve,
+            "inserted_points": ins_pts, "queries": qs, "initial_capacity": cap0,
+            "rates": rates}
+
+
+def insert_p99(serve):
+    """Insertion p99 of the serving stage at half its capacity (the load the
+    headline latency is quoted at), else at the lowest load measured."""
+    if not serve or not serve.get("rates"):
+        return None
+    rates = [r for r in serve["rates"] if "insert" in r]
+    if not rates:
+        return None
+    half = [r for r in rates if abs(r["load"] - 0.5) < 1e-9]
+    return (half or sorted(rates, key=lambda r: r["load"]))[0]["insert"]["p99_ms"]
 
 
 def main():
@@ -622,7 +662,7 @@ def main():
         "L_at_recall_0.95": main_form["L_at_recall_0.95"],
         "recall_curve": main_form["recall_curve"],
         "leaf_gemm_tflops": achieved,
-        "insert_p99_ms": serve["insert"]["p99_ms"] if serve and "insert" in serve else None,
+        "insert_p99_ms": insert_p99(serve),
         "serving": serve,
         "phase_ms": main_form["phase_ms"],
         "build_stats": {k: st[k] for k in ("n_leaves", "n_members", "leader_dists", "levels",

@@ -233,11 +233,21 @@ pipnn_status pipnn_autotune(pipnn_index *idx, const int64_t *d_leaf_offsets,
 /* ---- serving: growing an index in place ---- */
 
 /* (sync) Make room for n_cap points: grows the index's per-point buffers
- * (norms, sketches, float32 copy, GEMM operand), keeping their contents.
- * The caller's X (bound at pipnn_create) must have n_cap rows, and the
- * caller sizes its reservoirs (n_cap x l_max), graph (n_cap x R) and degree
- * (n_cap) buffers the same way. EINVAL if n_cap >= 2^32 - 1. */
-pipnn_status pipnn_reserve(pipnn_index *idx, int64_t n_cap, pipnn_stream_t stream);
+ * (norms, sketches, float32 copy, GEMM operand) keeping their contents, and
+ * sizes the point-indexed scratch of insertion for n_cap, so that
+ * insertions up to the capacity reallocate none of it. d_X (may be NULL:
+ * keep the current one) rebinds the index to a new X of the same dtype and
+ * dimension whose first n rows hold the current points -- the way to grow
+ * past the rows of the X bound at pipnn_create: the caller allocates a
+ * larger X, copies the rows, calls this, and then frees the old X (this
+ * call synchronises the stream before rebinding; work on other streams that
+ * reads the old X must have finished). The bound X must have n_cap rows,
+ * and the caller sizes its reservoirs (n_cap x l_max), graph (n_cap x R)
+ * and degree (n_cap) buffers the same way. EINVAL if n_cap >= 2^32 - 1, or
+ * if a new float32 X that the leaf kernel reads directly is not 16-byte
+ * aligned. */
+pipnn_status pipnn_reserve(pipnn_index *idx, int64_t n_cap, const void *d_X,
+                           pipnn_stream_t stream);
 
 /* (sync) Insert the n_new points the caller has written to rows
  * [n, n + n_new) of X (n = the current point count), which becomes

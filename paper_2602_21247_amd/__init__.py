@@ -104,7 +104,7 @@ def lib():
         L.pipnn_get_operand.argtypes = [P, P, P, P, P]
         L.pipnn_plan_leaves.argtypes = [P, P, P, i64, P]
         L.pipnn_set_leaf_config.argtypes = [P, i32, i32, i32]
-        L.pipnn_reserve.argtypes = [P, i64, P]
+        L.pipnn_reserve.argtypes = [P, i64, P, P]
         L.pipnn_insert.argtypes = [P, i64, P, P, P, P, P]
         L.pipnn_autotune.argtypes = [P, P, P, i64, C.POINTER(TuneResult), i32, C.POINTER(i32), P]
         for name in EXPORTS:
@@ -232,9 +232,20 @@ class Index:
         return [(out[i].rows_per_item, bool(out[i].persistent), out[i].layout, out[i].ms)
                 for i in range(cnt.value)]
 
-    def reserve(self, n_cap: int):
-        """Room for n_cap points (X must have n_cap rows)."""
-        _check(lib().pipnn_reserve(self._h, n_cap, _stream()))
+    def workspace_bytes(self, n: int, max_batch_records: int = 0) -> int:
+        """pipnn_workspace_bytes for this index's parameters at n points."""
+        return workspace_bytes(self.params, n, self.d, max_batch_records)
+
+    def reserve(self, n_cap: int, X=None):
+        """Room for n_cap points (the bound X must have n_cap rows). X: a new
+        device tensor (same dtype and width, the current points in its first
+        n rows) to bind instead of the current one."""
+        if X is not None:
+            assert X.is_cuda and X.is_contiguous() and X.dim() == 2 and X.shape[1] == self.d
+            assert X.dtype == self.X.dtype and X.shape[0] >= n_cap
+        _check(lib().pipnn_reserve(self._h, n_cap, None if X is None else _ptr(X), _stream()))
+        if X is not None:
+            self.X = X
 
     def insert(self, n_new: int, reservoirs, graph, degree, groups=None):
         """Insert rows [n, n + n_new) of X (already written by the caller)."""

@@ -229,8 +229,11 @@ namespace pipnn {
 
 hipError_t DevBuf::ensure(size_t bytes) {
   if (bytes <= cap && p) return hipSuccess;
+  // a buffer that has to grow again takes half as much once more, so that
+  // calls of slowly rising size (insertions) reallocate rarely
+  const size_t grown = p ? cap + cap / 2 : 0;
   release();
-  const size_t want = std::max<size_t>(bytes, 256);
+  const size_t want = std::max<size_t>({bytes, grown, (size_t)256});
   hipError_t e = hipMalloc(&p, want);
   if (e != hipSuccess) {
     p = nullptr;
@@ -1303,15 +1306,35 @@ static hipError_t grow_keep(DevBuf &b, size_t bytes, size_t keep, hipStream_t s)
   return hipSuccess;
 }
 
-pipnn_status pipnn_reserve(pipnn_index *idx, int64_t n_cap, pipnn_stream_t stream) {
+pipnn_status pipnn_reserve(pipnn_index *idx, int64_t n_cap, const void *d_X,
+                           pipnn_stream_t stream) {
   GUARD_BEGIN
   if (!idx) return fail(PIPNN_EINVAL, "NULL index");
   Index &I = *reinterpret_cast<Index *>(idx);
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   if (stream_capturing(s)) return fail(PIPNN_ESTATE, "reserve cannot run under capture");
   if (n_cap >= (int64_t)0xFFFFFFFFll) return fail(PIPNN_EINVAL, "capacity must be < 2^32 - 1");
+  if (d_X) {
+    // the float32 GEMM operand is X itself unless a padded copy exists, and
+    // then it must be 16-byte aligned like the X it replaces
+    if (I.x_dtype == PIPNN_DTYPE_F32 && !I.xpad.p && I.ldf != 0 &&
+        (reinterpret_cast<uintptr_t>(d_X) & 15u) != 0)
+      return fail(PIPNN_EINVAL, "the new X must be 16-byte aligned");
+    // the old X may still be read by work on the stream
+    HIPCHK(hipStreamSynchronize(s));
+    I.X = d_X;
+  }
   if (n_cap <= I.cap) return PIPNN_OK;
   const size_t n = (size_t)I.n, c = (size_t)n_cap, d = (size_t)I.d;
+  // scratch indexed by point id, sized for the capacity once so that
+  // insertions up to it allocate none of it
+  HIPCHK(I.s_cnt.ensure(c * 4));
+  HIPCHK(I.s_off.ensure((c + 1) * 8));
+  HIPCHK(I.s_tmp0.ensure((size_t)scan_tmp_elems(n_cap) * 8));
+  HIPCHK(I.i_flag.ensure(c * 4));
+  HIPCHK(I.i_pos.ensure((c + 1) * 8));
+  HIPCHK(I.i_list.ensure(c * 4));
+  HIPCHK(I.o_tmp.ensure((size_t)scan_tmp_elems(n_cap) * 8));
   HIPCHK(grow_keep(I.norms, c * 4, n * 4, s));
   HIPCHK(grow_keep(I.sketches, c * I.m * 4, n * I.m * 4, s));
   if (I.x_dtype != PIPNN_DTYPE_F32) HIPCHK(grow_keep(I.xf32, c * d * 4, n * d * 4, s));

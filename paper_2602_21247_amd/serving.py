@@ -15,6 +15,14 @@ streams, so query batches and insert batches overlap on the device:
   links only to the index and to its own points), and publishes the updated
   graph into the spare of two graph copies that queries read.
 
+Admission by memory: a query batch is limited by the free HBM its visited
+bitmaps need; an insertion that does not fit the reserved capacity grows it
+(new X, reservoirs, graph copies and the index's per-point buffers, by
+pipnn_reserve with the new X) when the free HBM (hipMemGetInfo, plus what
+torch holds cached) covers the growth, with query batches paused while the
+buffers are swapped; otherwise the insertion is deferred and retried as
+memory frees, and rejected after a timeout.
+
 A request arriving while a batch is on the GPU is admitted by the next batch
 of its kind as soon as the thread is free: continuous batching, not a
 queue drained between batches. Each query's result depends only on its
@@ -56,6 +64,7 @@ class Result:
     ids: np.ndarray | None = None
     dist: np.ndarray | None = None
     first_id: int = -1   # first point id given to an insertion
+    status: str = "ok"   # "ok", or "rejected" (no memory for the growth it needed)
 
     @property
     def latency(self) -> float:
@@ -67,7 +76,17 @@ class ServerConfig:
     L: int = 64                    # beam width of the queries
     max_query_batch: int = 4096    # queries per search launch
     max_insert_batch: int = 65536  # points per insert launch
-    query_scratch_bytes: int = 1 << 30  # visited bitmaps of one query batch
+    query_scratch_bytes: int = 1 << 30  # at most this much of visited bitmaps per batch
+    hbm_keep_bytes: int = 2 << 30  # free HBM that admission leaves untouched
+    grow_factor: float = 1.25      # capacity after a growth: at least this times the old
+    defer_timeout_s: float = 5.0   # an insertion waiting this long for memory is rejected
+
+
+def free_hbm_bytes(torch) -> int:
+    """Free device memory: what the driver reports (hipMemGetInfo) plus what
+    torch's caching allocator holds unused."""
+    free, _ = torch.cuda.mem_get_info()
+    return int(free) + int(torch.cuda.memory_reserved() - torch.cuda.memory_allocated())
 
 
 class Server:
@@ -91,6 +110,9 @@ class Server:
         self.pub_n = self.n
         self.epoch = 0
         self.readers = [0, 0]             # query batches in flight on each copy
+        self.growing = False              # buffers are being swapped: no query starts
+        self.growths = []                 # (new capacity, seconds) of each growth
+        self.rejected = 0
         self.s_q = torch.cuda.Stream()
         self.s_i = torch.cuda.Stream()
         self.lock = threading.Condition()
@@ -98,10 +120,12 @@ class Server:
 
     # ---- admission
     def _query_batch(self, pending, now):
-        """Arrived queries in arrival order while the batch and scratch
-        budgets allow (the visited bitmap of one query holds n bits)."""
+        """Arrived queries in arrival order while the batch limit and the
+        memory for their visited bitmaps (n bits per query) allow."""
         per_q = ((self.pub_n + 31) // 32) * 4
-        limit = min(self.cfg.max_query_batch, max(1, self.cfg.query_scratch_bytes // per_q))
+        budget = min(self.cfg.query_scratch_bytes,
+                     max(0, free_hbm_bytes(self.torch) - self.cfg.hbm_keep_bytes))
+        limit = min(self.cfg.max_query_batch, max(1, budget // per_q))
         out, tot = [], 0
         while pending and pending[0].arrival <= now and tot + len(pending[0].data) <= limit:
             r = pending.pop(0)
@@ -121,6 +145,50 @@ class Server:
             tot += m
         return out
 
+    def _growth_bytes(self, new_cap: int) -> int:
+        """Device memory a growth to new_cap takes while the old buffers still
+        exist: X, reservoirs, the graph and its two published copies, degrees,
+        and the index's own per-point buffers (pipnn_workspace_bytes' bound)."""
+        row = (self.X.shape[1] * self.X.element_size() + self.res.shape[1] * 8
+               + 3 * self.g.shape[1] * 4 + 4)
+        idx_b = self.idx.workspace_bytes(new_cap)
+        return new_cap * row + idx_b
+
+    def _grow(self, need: int) -> bool:
+        """Grow the capacity to hold `need` points if the free HBM allows;
+        query batches are paused while the buffers are swapped."""
+        torch = self.torch
+        new_cap = max(need, int(self.cap * self.cfg.grow_factor))
+        if self._growth_bytes(new_cap) + self.cfg.hbm_keep_bytes > free_hbm_bytes(torch):
+            return False
+        t0 = time.perf_counter()
+        with self.lock:
+            self.growing = True
+            while self.readers[0] or self.readers[1]:
+                self.lock.wait()
+        try:
+            torch.cuda.synchronize()
+            n = self.n
+            X = torch.empty((new_cap, self.X.shape[1]), dtype=self.X.dtype, device="cuda")
+            X[:n].copy_(self.X[:n])
+            res = torch.empty((new_cap, self.res.shape[1]), dtype=self.res.dtype, device="cuda")
+            res[:n].copy_(self.res[:n])
+            g = torch.full((new_cap, self.g.shape[1]), -1, dtype=self.g.dtype, device="cuda")
+            g[:n].copy_(self.g[:n])
+            deg = torch.zeros(new_cap, dtype=self.deg.dtype, device="cuda")
+            deg[:n].copy_(self.deg[:n])
+            self.idx.reserve(new_cap, X=X)
+            self.X, self.res, self.g, self.deg = X, res, g, deg
+            self.pub = [g.clone(), g.clone()]
+            self.cap = new_cap
+            torch.cuda.synchronize()
+        finally:
+            with self.lock:
+                self.growing = False
+                self.lock.notify_all()
+        self.growths.append((new_cap, time.perf_counter() - t0))
+        return True
+
     # ---- the two workers
     def _run_queries(self, pending, results, t0, seq):
         torch = self.torch
@@ -129,9 +197,14 @@ class Server:
             if pending[0].arrival > now:
                 time.sleep(min(1e-4, pending[0].arrival - now))
                 continue
+            with self.lock:
+                while self.growing:
+                    self.lock.wait()
             batch = self._query_batch(pending, now)
             adm = time.perf_counter() - t0
             with self.lock:
+                while self.growing:
+                    self.lock.wait()
                 cur, epoch = self.cur, self.epoch
                 self.readers[cur] += 1
             Q = np.concatenate([r.data for r in batch]).astype(np.float32, copy=False)
@@ -166,7 +239,18 @@ class Server:
                 continue
             batch = self._insert_batch(pending, now)
             if not batch:
-                raise RuntimeError("insert request does not fit in the reserved capacity")
+                # the first arrived request does not fit: grow, or defer it
+                # until memory frees, or reject it after the timeout
+                r = pending[0]
+                if not self._grow(self.n + len(r.data)):
+                    if now - r.arrival > self.cfg.defer_timeout_s:
+                        pending.pop(0)
+                        self.rejected += 1
+                        results[r.rid] = Result(r.rid, "insert", r.arrival, now, now,
+                                                status="rejected")
+                    else:
+                        time.sleep(1e-3)
+                continue
             adm = time.perf_counter() - t0
             P = np.concatenate([r.data for r in batch])
             groups = np.concatenate([np.full(len(r.data), i, dtype=np.int32)
@@ -227,7 +311,8 @@ def summarize(results: dict[int, Result], wall_s: float) -> dict:
     """p50/p99 latency per request class, inserts/s and QPS."""
     out = {}
     for kind in ("query", "insert"):
-        lat = np.array([r.latency for r in results.values() if r.kind == kind])
+        lat = np.array([r.latency for r in results.values()
+                        if r.kind == kind and r.status == "ok"])
         if len(lat):
             out[kind] = {"count": int(len(lat)), "p50_ms": float(np.percentile(lat, 50) * 1e3),
                          "p99_ms": float(np.percentile(lat, 99) * 1e3),

@@ -49,19 +49,19 @@ def base():
     return X, H, p
 
 
-def built(X, H, p):
-    """A GPU build on the first N0 points with buffers of capacity CAP."""
-    Xc = torch.from_numpy(X).cuda()
+def built(X, H, p, cap=CAP):
+    """A GPU build on the first N0 points with buffers of capacity cap."""
+    Xc = torch.from_numpy(X[:cap]).cuda()
     Hd = torch.from_numpy(H).cuda()
     idx = pp.Index(Xc[:N0], Hd, p)
     off, mem = idx.partition()
-    res = torch.empty((CAP, p.l_max), dtype=torch.int64, device="cuda")
+    res = torch.empty((cap, p.l_max), dtype=torch.int64, device="cuda")
     pp.reservoir_init(N0, p.l_max, out=res[:N0])
     idx.build_leaves(off, mem, res[:N0])
-    g = torch.full((CAP, p.R), -1, dtype=torch.int32, device="cuda")
-    deg = torch.zeros(CAP, dtype=torch.int32, device="cuda")
+    g = torch.full((cap, p.R), -1, dtype=torch.int32, device="cuda")
+    deg = torch.zeros(cap, dtype=torch.int32, device="cuda")
     idx.robustprune(res[:N0], g[:N0], deg[:N0])
-    idx.reserve(CAP)
+    idx.reserve(cap)
     torch.cuda.synchronize()
     return idx, Xc, off, mem, res, g, deg
 
@@ -137,6 +137,23 @@ def test_failed_insert_leaves_index_usable(base):
     idx.close()
 
 
+def test_inserts_after_reserve_take_no_memory(base):
+    """After pipnn_reserve, insertions up to the capacity reallocate none of
+    the library's point-indexed scratch: free HBM is the same after every
+    insertion of a series (the first one sizes the per-call buffers)."""
+    X, H, p = base
+    idx, Xc, off, mem, res, g, deg = built(X, H, p)
+    sizes = [400, 300, 200, 150, 100]
+    frees = []
+    for m in sizes:
+        idx.insert(m, res, g, deg)
+        torch.cuda.synchronize()
+        frees.append(torch.cuda.mem_get_info()[0])
+    print("free HBM after each insertion:", frees)
+    assert len(set(frees[1:])) == 1
+    idx.close()
+
+
 def test_insert_alone_equals_together(base):
     X, H, p = base
     m = 900
@@ -173,20 +190,31 @@ def _requests(X, seed, n_req=40):
     return reqs
 
 
-def test_server_same_alone_and_in_mix(base):
+@pytest.mark.parametrize("grow", [False, True])
+def test_server_same_alone_and_in_mix(base, grow):
+    """Every request's result is the same alone and in the continuous-batching
+    mix; with grow, the server starts with room for 64 more points only and
+    grows the capacity (new X, reservoirs and graphs, pipnn_reserve with the
+    new X) several times mid-stream, admitted by free HBM."""
     X, H, p = base
     reqs = _requests(X, seed=7)
     # the mix: continuous batching on two streams
-    idx, Xc, off, mem, res, g, deg = built(X, H, p)
+    idx, Xc, off, mem, res, g, deg = built(X, H, p, cap=N0 + 64 if grow else CAP)
     start = idx.start_node()
-    srv = serving.Server(idx, Xc, res, g, deg, start, serving.ServerConfig(L=48))
+    srv = serving.Server(idx, Xc, res, g, deg, start,
+                         serving.ServerConfig(L=48, grow_factor=1.0))
     out = srv.run(reqs)
     n_mix = srv.n
+    res, g = srv.res, srv.g
     g_mix = u32(g[:n_mix]).copy()
     res_mix = canon(idx, res, n_mix)
     summ = serving.summarize(out, 1.0)
     print("mix:", summ, "insert batches", len({r.batch for r in out.values() if r.kind == "insert"}),
-          "query batches", len({r.batch for r in out.values() if r.kind == "query"}))
+          "query batches", len({r.batch for r in out.values() if r.kind == "query"}),
+          "growths", srv.growths)
+    assert srv.rejected == 0
+    if grow:
+        assert len(srv.growths) >= 2 and srv.cap >= n_mix
     idx.close()
     # alone: every insertion by itself, in the mix's commit order; each query
     # alone against the graph that held the same insertions
