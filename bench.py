@@ -18,12 +18,19 @@ with FP32 rescoring of the top-2k, fp8 with rescoring, and FP32 with two
 replicas of the partition) built, timed and searched the same way on the
 same points after the main measurement.
 
-Printed: one JSON line. `roofline` is for the fused leaf distance +
-selection kernel (the dominant kernel): its average launch time comes from
-HIP events recorded around it on its own stream during the timed steps.
-`cpu_baseline` is the FP64 oracle timed on a bounded sample of the same
-build (each phase on a sample of its units, scaled by the unit counts of the
-GPU build).
+Printed: one JSON line. `rooflines` holds every main kernel of the build
+(leaf pick, partition, binning, merge, RobustPrune) against the roofline
+that bounds it, each from its algorithmic work and its time per build from
+HIP events recorded around it on its own stream during the timed steps;
+`roofline` is the entry of the kernel that takes the most time (the fused
+leaf distance + selection kernel on the default workload). `precision` is
+the 1M x 96 vMF workload built with the float32, bf16 + rescore and fp8 +
+rescore leaf GEMMs, with each form's error against the FP64 oracle on
+sampled leaves. `cpu_baseline` is the FP64 oracle timed on a bounded sample
+of the same build (each phase on a sample of its units, scaled by the unit
+counts of the GPU build; phase times from the oracle's own steady clock),
+plus the oracle's whole pipeline on the 10,000-point workload on one thread
+and on all threads, and the host's CPU model.
 """
 from __future__ import annotations
 
@@ -86,6 +93,13 @@ def parse():
                     help="beam widths (comma separated): search every point of the main build's "
                          "graph for its 10 nearest other points (an approximate 10-NN graph), "
                          "timed, with recall@10 on a sample of 10,000 points")
+    ap.add_argument("--no-precision", action="store_true",
+                    help="skip the precision workload (1M x 96 vMF: FP32 vs bf16 and fp8 with "
+                         "rescoring, error against FP64)")
+    ap.add_argument("--precision-steps", type=int, default=3)
+    ap.add_argument("--precision-queries", type=int, default=10000)
+    ap.add_argument("--precision-leaves", type=int, default=40,
+                    help="leaves of the precision workload whose picks are checked against FP64")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="after the timed steps, copy this many MiB once (a plain copy of known "
                          "size, used to scale hardware byte counters)")
@@ -184,11 +198,69 @@ def traffic_from_profiles(workload):
         return None
 
 
+def cpu_model() -> str:
+    """The host CPU's model name (lscpu, else /proc/cpuinfo)."""
+    import subprocess
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.lower().startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except Exception:
+        pass
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except Exception:
+        pass
+    return "unknown"
+
+
+def oracle_full_build(np, pi, cfg, threads_list):
+    """The whole oracle pipeline (Alg. 4: partition, leaf pick, HashPrune,
+    RobustPrune, with the sketches) on workload `cfg` at its full size, once
+    per thread count; per-phase wall times from the oracle's own steady clock,
+    and recall@10 of its graph at a few beam widths."""
+    import oracle
+    w = pi.WORKLOADS[cfg]
+    X = pi.workload_points(cfg)
+    H = pi.workload_hyperplanes(cfg)
+    op = oracle.make_params(metric=w.metric, c_max=w.c_max, c_min=w.c_min,
+                            leader_div=w.leader_div, leader_cap=w.leader_cap,
+                            fanout=tuple(w.fanout), k=w.k, hash_bits=w.hash_bits, l_max=w.l_max,
+                            R=w.R, alpha=w.alpha, seed=pi.workload_seed(cfg))
+    runs = {}
+    ref = None
+    for th in threads_list:
+        oracle.set_threads(th)
+        oracle.phase_seconds(reset=True)
+        ref = oracle.build_index(X, H, op)
+        ph = oracle.phase_seconds(reset=True)
+        wall = sum(ph[k] for k in ("sketches", "partition", "leaf_pick", "hashprune",
+                                   "robustprune"))
+        runs[str(oracle.get_threads())] = {"build_s": wall, "points_per_s": X.shape[0] / wall,
+                                           "phase_s": {k: v for k, v in ph.items() if v > 0}}
+    Q = pi.workload_queries(cfg)
+    start, _ = oracle.start_node(X)
+    _, gd = oracle.bruteforce_knn(X, Q, 10, metric=w.metric)
+    curve = {}
+    for L in (16, 32, 64, 128):
+        ids, _, _ = oracle.beam_search(X, ref["graph"], Q, 10, L, start, metric=w.metric)
+        curve[L] = round(oracle.recall_at_k(ids, X, Q, gd, metric=w.metric), 5)
+    return {"workload": w.name, "n": int(X.shape[0]), "runs_by_threads": runs,
+            "recall_at_10_by_L": curve}
+
+
 def cpu_baseline(X, H, off, mem, res_np, stats, w, budget):
-    """The FP64 oracle on a bounded sample of this build, phase by phase."""
+    """The FP64 oracle on a bounded sample of this build, phase by phase
+    (each phase's wall time read from the oracle's own steady clock, scaled
+    by the GPU build's unit counts), plus the whole oracle pipeline of the
+    10,000-point correctness workload on one thread and on all threads."""
     import numpy as np
 
     import oracle
+    import pipnn_inputs as pi
     oracle.lib()
     threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or (os.cpu_count() or 1)
     oracle.set_threads(threads)
@@ -198,6 +270,11 @@ def cpu_baseline(X, H, off, mem, res_np, stats, w, budget):
     notes = []
     total = 0.0
 
+    def timed(phase, fn, *a, **kw):
+        oracle.phase_seconds(reset=True)
+        out = fn(*a, **kw)
+        return out, oracle.phase_seconds(reset=True)[phase]
+
     # partition: point-to-leader distances with top-f selection (none when
     # the leaves are given)
     t_part = 0.0
@@ -205,43 +282,48 @@ def cpu_baseline(X, H, off, mem, res_np, stats, w, budget):
         ell = min(w.leader_cap, max(2, -(-n // w.leader_div)), n)
         leaders = X[rng.choice(n, ell, replace=False)]
         m = 2000
-        t = time.perf_counter()
-        oracle.bruteforce_knn(leaders, X[rng.choice(n, m, replace=False)], 2, metric=w.metric)
-        dt = time.perf_counter() - t
+        _, dt = timed("bruteforce_knn", oracle.bruteforce_knn, leaders,
+                      X[rng.choice(n, m, replace=False)], 2, metric=w.metric)
         m2 = int(min(n, max(m, m * budget / max(dt, 1e-3))))
-        t = time.perf_counter()
-        oracle.bruteforce_knn(leaders, X[rng.choice(n, m2, replace=False)], 2, metric=w.metric)
-        dt = time.perf_counter() - t
+        _, dt = timed("bruteforce_knn", oracle.bruteforce_knn, leaders,
+                      X[rng.choice(n, m2, replace=False)], 2, metric=w.metric)
         t_part = dt * stats["leader_dists"] / float(m2 * ell)
         total += t_part
         notes.append(f"partition: {m2} points x {ell} leaders "
                      f"(x{stats['leader_dists'] / (m2 * ell):.0f})")
 
-    # leaf pick: a random sample of the GPU build's leaves
+    # leaf pick: a random sample of the GPU build's leaves, grown after a
+    # first timing so that it takes about `budget` seconds
     nl = len(off) - 1
     order = rng.permutation(nl)
     sizes = np.diff(off)
     pairs_tot = float((sizes.astype(np.float64) ** 2).sum())
-    pick, acc = [], 0.0
-    for i in order:
-        pick.append(i)
-        acc += float(sizes[i]) ** 2
-        if acc >= pairs_tot * 0.004 and len(pick) >= 4:
-            break
-    s_off = np.concatenate([[0], np.cumsum(sizes[pick])]).astype(np.int64)
-    s_mem = np.concatenate([mem[off[i]:off[i + 1]] for i in pick]).astype(np.uint32)
-    t = time.perf_counter()
-    cand, dist = oracle.leaf_knn(X, s_off, s_mem, w.k, metric=w.metric)
-    dt = time.perf_counter() - t
+
+    def leaf_sample(frac):
+        pick, acc = [], 0.0
+        for i in order:
+            if acc >= pairs_tot * frac and len(pick) >= 4:
+                break
+            pick.append(i)
+            acc += float(sizes[i]) ** 2
+        s_off = np.concatenate([[0], np.cumsum(sizes[pick])]).astype(np.int64)
+        s_mem = np.concatenate([mem[off[i]:off[i + 1]] for i in pick]).astype(np.uint32)
+        return pick, acc, s_off, s_mem
+
+    pick, acc, s_off, s_mem = leaf_sample(0.001)
+    (cand, dist), dt = timed("leaf_pick", oracle.leaf_knn, X, s_off, s_mem, w.k, metric=w.metric)
+    if dt < budget / 2 and acc < pairs_tot:
+        pick, acc, s_off, s_mem = leaf_sample(min(1.0, acc / pairs_tot * budget / max(dt, 1e-3)))
+        (cand, dist), dt = timed("leaf_pick", oracle.leaf_knn, X, s_off, s_mem, w.k,
+                                 metric=w.metric)
     t_leaf = dt * pairs_tot / acc
     total += t_leaf
     notes.append(f"leaf pick: {len(pick)} leaves, {acc / pairs_tot * 100:.2f}% of pairs")
 
     # sketches of every point
-    t = time.perf_counter()
     ns_sk = min(n, 100000)
-    oracle.sketches(X[:ns_sk], H)
-    t_sk = (time.perf_counter() - t) * n / ns_sk
+    _, dt = timed("sketches", oracle.sketches, X[:ns_sk], H)
+    t_sk = dt * n / ns_sk
     total += t_sk
     notes.append(f"sketches: {ns_sk} points")
 
@@ -251,27 +333,179 @@ def cpu_baseline(X, H, off, mem, res_np, stats, w, budget):
     dst_c = inv[:len(dst)].astype(np.uint32)
     cnd_c = inv[len(dst):].astype(np.uint32)
     S = oracle.sketches(X[uniq], H)
-    t = time.perf_counter()
-    oracle.hashprune(oracle.reservoir_init(len(uniq), w.l_max), S, dst_c, cnd_c, dv)
-    dt = time.perf_counter() - t
+    _, dt = timed("hashprune", oracle.hashprune, oracle.reservoir_init(len(uniq), w.l_max), S,
+                  dst_c, cnd_c, dv)
     t_hp = dt * stats["records"] / max(1, len(dst))
     total += t_hp
     notes.append(f"HashPrune: {len(dst)} records ({len(dst) / max(1, stats['records']) * 100:.2f}%)")
 
-    # RobustPrune: the reservoirs of the first points
-    ns = 20000
-    t = time.perf_counter()
-    oracle.robustprune(X, res_np[:ns], w.alpha, w.R, metric=w.metric)
-    dt = time.perf_counter() - t
+    # RobustPrune: the reservoirs of the first points (grown like the leaf sample)
+    ns = min(n, 20000)
+    _, dt = timed("robustprune", oracle.robustprune, X, res_np[:ns], w.alpha, w.R,
+                  metric=w.metric)
+    if dt < budget / 2 and ns < n:
+        ns = int(min(n, ns * budget / max(dt, 1e-3)))
+        _, dt = timed("robustprune", oracle.robustprune, X, res_np[:ns], w.alpha, w.R,
+                      metric=w.metric)
     t_rp = dt * n / ns
     total += t_rp
     notes.append(f"RobustPrune: {ns} points")
+    full = oracle_full_build(np, pi, 1, [1, threads])
+    oracle.set_threads(threads)
     return {
         "value": n / total, "unit": "points/s", "cores": threads, "kind": "oracle",
         "sample": "; ".join(notes) + "; each phase scaled by the GPU build's unit counts",
+        "cpu_model": cpu_model(),
         "phase_s": {"sketches": t_sk, "partition": t_part, "leaf_pick": t_leaf,
                     "hashprune": t_hp, "robustprune": t_rp},
+        "full_pipeline_small_workload": full,
     }
+
+
+def precision_stage(args, torch, np, pp, pi):
+    """The precision workload (1,000,000 unit vectors of 96 dimensions from a
+    vMF mixture, L2): the float32 leaf GEMM, bf16 and OCP e4m3 with FP32
+    rescoring of the top 2k, each built and timed the same way on the same
+    points (the partition is float32 for all three: the 16-bit copies do not
+    hold this data exactly), searched at the same beam widths, and the
+    error of each form's leaf picks against the FP64 oracle's on a random
+    sample of the leaves: the share of FP64 picks found, and the largest
+    error of an emitted distance (against the FP64 distance of the same
+    pair)."""
+    import oracle
+    cfg = 3
+    w = pi.WORKLOADS[cfg]
+    log(f"[bench] precision workload {w.name}: generating")
+    X = pi.workload_points(cfg)
+    H = pi.workload_hyperplanes(cfg)
+    n = X.shape[0]
+    Xd, Hd = torch.from_numpy(X).cuda(), torch.from_numpy(H).cuda()
+    Qd = torch.from_numpy(pi.workload_queries(cfg, args.precision_queries)).cuda()
+    kth = ground_truth(torch, Xd, Qd, w.metric)
+    nq = Qd.shape[0]
+    forms = []
+    sample = None
+    for prec, mult in (("fp32", 0), ("bf16", 2), ("fp8", 2)):
+        p = pp.default_params(metric=w.metric, c_max=w.c_max, c_min=w.c_min, k=w.k,
+                              l_max=w.l_max, R=w.R, alpha=w.alpha, hash_bits=w.hash_bits,
+                              leader_div=w.leader_div, leader_cap=w.leader_cap, fanout=w.fanout,
+                              seed=pi.workload_seed(cfg), gemm_prec=PREC_CODES[prec],
+                              rescore_mult=mult)
+        idx = pp.Index(Xd, Hd, p)
+        res = torch.empty((n, w.l_max), dtype=torch.int64, device="cuda")
+
+        def step():
+            idx.prepare()
+            pp.reservoir_init(n, w.l_max, out=res)
+            off, mem = idx.partition()
+            idx.build_leaves(off, mem, res)
+            g, deg = idx.robustprune(res)
+            return off, mem, g
+
+        step()
+        torch.cuda.synchronize()
+        idx.set_profiling(True)
+        t0 = time.perf_counter()
+        for _ in range(args.precision_steps):
+            off, mem, g = step()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1000.0 / args.precision_steps
+        st = idx.stats()
+        idx.set_profiling(False)
+        start = idx.start_node()
+        curve = {}
+        for L in (64, 128, 256, 512):
+            ids, dist, _ = idx.search(g, Qd, 10, L, start, want_cmps=False)
+            curve[L] = round((dist.double() <= kth[:, None]).sum().item() / (nq * 10.0), 5)
+        # picks of every leaf row, compared on a sample of leaves with FP64
+        cand, dd = idx.leaf_pick(off, mem)
+        torch.cuda.synchronize()
+        off_h, mem_h = off.cpu().numpy(), mem.cpu().numpy().view(np.uint32)
+        if sample is None:
+            rng = np.random.default_rng(303)
+            nl = len(off_h) - 1
+            sample = np.sort(rng.choice(nl, min(nl, args.precision_leaves), replace=False))
+        s_sizes = np.diff(off_h)[sample]
+        s_off = np.concatenate([[0], np.cumsum(s_sizes)]).astype(np.int64)
+        s_mem = np.concatenate([mem_h[off_h[i]:off_h[i + 1]] for i in sample])
+        rows = np.concatenate([np.arange(off_h[i], off_h[i + 1]) for i in sample])
+        ocand, odist = oracle.leaf_knn(X, s_off, s_mem, w.k, metric=w.metric)
+        gc = cand.cpu().numpy().view(np.uint32)[rows]
+        gd = dd.cpu().numpy()[rows].astype(np.float64)
+        agree = float(np.mean([len(set(a[a != 0xFFFFFFFF]) & set(b[b != 0xFFFFFFFF]))
+                               / max(1, (b != 0xFFFFFFFF).sum()) for a, b in zip(gc, ocand)]))
+        # FP64 distance of each emitted pair, from the emitting row's point
+        valid = gc != 0xFFFFFFFF
+        Xs = X.astype(np.float64)
+        src = np.repeat(s_mem.astype(np.int64), w.k).reshape(gc.shape)[valid]
+        dst = gc[valid].astype(np.int64)
+        d64 = ((Xs[src] - Xs[dst]) ** 2).sum(1)
+        err = np.abs(gd[valid] - d64)
+        rel = err / np.maximum(np.abs(d64), 1e-30)
+        within = float(np.mean(err <= np.maximum(1e-5 * np.abs(d64), 1e-6)))
+        f = {"prec": prec, "rescore_mult": mult, "ms_per_step": ms, "points_per_s": n / (ms / 1e3),
+             "recall_at_10_by_L": curve,
+             "leaf_gemm_tflops": 2.0 * st["leaf_pairs"] * w.d * args.precision_steps
+             / max(1, st["leaf_knn_launches"]) / (st["ms_leaf_knn"] / max(1, st["leaf_knn_launches"])
+                                                  / 1e3) / 1e12,
+             "phase_ms": {k: st[k] / args.precision_steps for k in
+                          ("ms_prepare", "ms_partition", "ms_leaf_knn", "ms_bin", "ms_merge",
+                           "ms_robustprune")},
+             "vs_fp64": {"leaves": int(len(sample)), "rows": int(len(rows)),
+                         "pick_agreement": agree, "max_abs_dist_err": float(err.max()),
+                         "max_rel_dist_err": float(rel.max()),
+                         "share_within_1e-5_rel": within}}
+        log(f"[bench] precision {prec} x{mult}: {ms:.2f} ms/build, recall {curve}, "
+            f"picks vs FP64 {agree:.5f}, max rel err {rel.max():.2e}")
+        forms.append(f)
+        idx.close()
+        del res
+    return {"workload": w.name, "n": n, "d": w.d, "queries": nq, "forms": forms}
+
+
+def kernel_rooflines(st, w, n, steps, res_valid, rp_elem, prec):
+    """Achieved rate of each main kernel of one build against the roofline
+    that bounds it, from the HIP-event phase times (ms per build) and the
+    algorithmic work of the build:
+      leaf pick: 2 d sum(s^2) flops (every pair of every leaf; MFMA peak of
+        the operand's precision);
+      partition: 2 d flops per point-to-leader distance (float32 MFMA);
+      binning: 12 B per record (4 B of the pick and distance that yield it,
+        8 B of slot written) + m 4 B of sketch per leaf member (HBM);
+      merge: 8 B per binned record read + 2 l_max 8 B per point (reservoir
+        read and written; HBM);
+      RobustPrune: the candidates' rows (valid reservoir slots x d x the
+        element size read) + l_max 8 B of reservoir and R 4 B of graph per
+        point (HBM)."""
+    d = w.d
+    per = lambda k: st[k] / steps    # phase times are summed over the timed builds
+    rec = st["records"]              # counts are those of the last build
+    pairs = st["leaf_pairs"]
+    hbm = 8000.0
+    out = {}
+
+    def put(name, ms, amount, unit, peak, bound):
+        if ms <= 0:
+            return
+        a = amount / (ms / 1e3) / (1e12 if unit == "TFLOP/s" else 1e9)
+        out[name] = {"bound": bound, "ms": ms, "achieved": a, "peak": peak, "unit": unit,
+                     "frac": a / peak, "work": amount}
+
+    put("leaf_knn", per("ms_leaf_knn"), 2.0 * d * pairs, "TFLOP/s", PEAK_MFMA_TFLOPS[prec], "mfma")
+    if "leaf_knn" in out:
+        out["leaf_knn"]["precision"] = prec
+    # the partition multiplies the exact 16-bit copy where there is one
+    part_prec = "fp32" if not st["operand_exact"] or d > 256 else (
+        prec if prec in ("bf16", "fp16") else "fp16")
+    put("partition", per("ms_partition"), 2.0 * d * st["leader_dists"], "TFLOP/s",
+        PEAK_MFMA_TFLOPS[part_prec], "mfma")
+    if "partition" in out:
+        out["partition"]["precision"] = part_prec
+    put("bin", per("ms_bin"), 12.0 * rec + st["n_members"] * w.hash_bits * 4.0, "GB/s", hbm, "hbm")
+    put("merge", per("ms_merge"), 8.0 * rec + 16.0 * w.l_max * n, "GB/s", hbm, "hbm")
+    put("robustprune", per("ms_robustprune"),
+        res_valid * d * rp_elem + n * (8.0 * w.l_max + 4.0 * w.R), "GB/s", hbm, "hbm")
+    return out
 
 
 def serving_stage(args, torch, np, pp, pi, w, cfg, X, H, p_kw, L_serve):
@@ -542,7 +776,8 @@ def main():
         log(f"[bench] {prec} x{mult} r{replicas}: {steps} steps, {ms:.2f} ms/step")
         # leaf kernel roofline: dense flops 2 s^2 d per leaf, per launch
         launches = max(1, st["leaf_knn_launches"])
-        flops_per_launch = 2.0 * st["leaf_pairs"] * w.d * steps / launches
+        # leaf_pairs counts the last build_leaves call: one replica's leaves
+        flops_per_launch = 2.0 * st["leaf_pairs"] * replicas * w.d * steps / launches
         avg_launch_s = st["ms_leaf_knn"] / launches / 1000.0
         achieved = flops_per_launch / avg_launch_s / 1e12
         phases = {k: st[k] / steps for k in ("ms_prepare", "ms_partition", "ms_leaf_knn",
@@ -637,8 +872,19 @@ def main():
         L_serve = main_form["L_at_recall_0.95"] or 128
         serve = serving_stage(args, torch, np, pp, pi, w, cfg, X, H, p_kw, L_serve)
 
+    precision = None
+    if cfg == 2 and not args.no_precision:
+        precision = precision_stage(args, torch, np, pp, pi)
+
     traffic = traffic_from_profiles(w.name) if args.prec == "fp32" else None
     peak = PEAK_MFMA_TFLOPS[args.prec]
+    res_valid = int(((res & 0xFFFFFFFF) != 0xFFFFFFFF).sum().item())
+    rp_elem = 2 if (st["operand_exact"] and args.prec in ("fp32", "bf16", "fp16")) else 4
+    roofs = kernel_rooflines(st, w, n, args.steps, res_valid, rp_elem, args.prec)
+    dominant = max(roofs, key=lambda k: roofs[k]["ms"])
+    main_roof = dict(roofs[dominant])
+    main_roof["kernel"] = dominant
+    main_roof["traffic"] = traffic if dominant == "leaf_knn" else None
     gemm = f"{args.prec}-mfma" + (f", fp32 rescore of top-{args.rescore_mult}k"
                                   if args.rescore_mult else "")
     line = {
@@ -667,11 +913,14 @@ def main():
         "phase_ms": main_form["phase_ms"],
         "build_stats": {k: st[k] for k in ("n_leaves", "n_members", "leader_dists", "levels",
                                            "leaf_pairs", "records")},
-        "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak,
-                     "unit": "TFLOP/s", "frac": achieved / peak, "traffic": traffic},
+        "roofline": {k: main_roof[k] for k in ("bound", "achieved", "peak", "unit", "frac",
+                                               "traffic", "kernel", "ms")},
+        "rooflines": roofs,
         "cpu_baseline": cpu,
         "variants": variants,
     }
+    if precision is not None:
+        line["precision"] = precision
     if frontier is not None:
         line["frontier"] = frontier
     if knn_graph is not None:

@@ -112,6 +112,8 @@ def lib():
         L.orc_leaf_reps.argtypes = [P, i32, P, P, i64, P]
         L.orc_robustprune_points.argtypes = [P, i32, i32, P, P, i64, i32, C.c_float, i32, P, P]
         L.orc_get_threads.restype = i32
+        L.orc_phase_seconds.restype = i32
+        L.orc_phase_seconds.argtypes = [P, i32]
         _lib = L
     return _lib
 
@@ -130,6 +132,19 @@ def set_threads(n: int) -> None:
 
 def get_threads() -> int:
     return int(lib().orc_get_threads())
+
+
+PHASES = ("sketches", "partition", "leaf_pick", "hashprune", "robustprune", "beam_search",
+          "bruteforce_knn")
+
+
+def phase_seconds(reset: bool = True) -> dict:
+    """Wall seconds spent in each phase function of the C oracle since the
+    last reset (a steady clock read inside the C code)."""
+    out = np.zeros(len(PHASES), dtype=np.float64)
+    cnt = lib().orc_phase_seconds(_p(out), 1 if reset else 0)
+    assert cnt == len(PHASES)
+    return {k: float(v) for k, v in zip(PHASES, out)}
 
 
 def dist(a, b, metric=0) -> float:

@@ -32,6 +32,7 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#include <time.h>
 #ifdef _OPENMP
 #include <omp.h>
 #endif
@@ -70,6 +71,39 @@ int orc_get_threads(void) {
 /* ------------------------------------------------------------------ */
 /* Dissimilarity (Preliminaries): squared L2 by direct difference with the
  * coordinate index ascending, or the negated inner product. */
+/* Wall time of each phase, summed over the calls since the last reset:
+ * CLOCK_MONOTONIC (a steady clock) read at the entry and exit of every
+ * exported phase function. Timing only; it never changes a result. */
+enum {
+  ORC_PH_SKETCH = 0,
+  ORC_PH_PARTITION,
+  ORC_PH_LEAF,
+  ORC_PH_HASHPRUNE,
+  ORC_PH_ROBUSTPRUNE,
+  ORC_PH_SEARCH,
+  ORC_PH_BRUTEFORCE,
+  ORC_PH_COUNT
+};
+static double orc_phase_s[ORC_PH_COUNT];
+
+static double orc_now(void) {
+  struct timespec ts;
+  clock_gettime(CLOCK_MONOTONIC, &ts);
+  return (double)ts.tv_sec + 1e-9 * (double)ts.tv_nsec;
+}
+static void orc_phase_add(int ph, double t0) { orc_phase_s[ph] += orc_now() - t0; }
+
+/* out[ORC_PH_COUNT] receives the summed seconds of sketches, partition, leaf
+ * pick, HashPrune, RobustPrune, BeamSearch and brute-force k-NN; returns the
+ * count. reset != 0 clears the sums afterwards. */
+int orc_phase_seconds(double *out, int reset) {
+  for (int i = 0; i < ORC_PH_COUNT; ++i) {
+    if (out) out[i] = orc_phase_s[i];
+    if (reset) orc_phase_s[i] = 0.0;
+  }
+  return ORC_PH_COUNT;
+}
+
 double orc_dist(const float *a, const float *b, int d, int metric) {
   double s = 0.0;
   if (metric == 0) {
@@ -113,7 +147,7 @@ static uint64_t draw_below(uint64_t r, uint64_t m) {
 /* ------------------------------------------------------------------ */
 /* Sketches (Sec. 3, Implementation): Sketch(v)_b = H_b . v, in FP64 with
  * the coordinate index ascending. */
-void orc_sketches(const float *X, int64_t n, int d, const float *H, int m, double *S) {
+static void orc_sketches_impl(const float *X, int64_t n, int d, const float *H, int m, double *S) {
 #pragma omp parallel for schedule(static)
   for (int64_t p = 0; p < n; p++) {
     for (int b = 0; b < m; b++) {
@@ -234,7 +268,7 @@ static int check_ids(const uint32_t *dst, const uint32_t *cand, int64_t cnt, int
  *   - else: let z be the largest key in M; if key(c) < key(z), evict z and
  *     insert c.
  * Records with dst == cand are ignored. Returns -1 on an id >= n. */
-int orc_hashprune_stream(uint64_t *res, int64_t n, int l_max, const double *S, int m,
+static int orc_hashprune_stream_impl(uint64_t *res, int64_t n, int l_max, const double *S, int m,
                          const uint32_t *dst, const uint32_t *cand, const double *dist,
                          int64_t cnt) {
   if (check_ids(dst, cand, cnt, n)) return -1;
@@ -304,7 +338,7 @@ static int cmp_entry_key(const void *a, const void *b) {
  * reservoir of p ends up holding the l_max smallest keys among the
  * minimum-key entry of every hash bucket, taken over the existing
  * reservoir and all records addressed to p. */
-int orc_hashprune_closed(uint64_t *res, int64_t n, int l_max, const double *S, int m,
+static int orc_hashprune_closed_impl(uint64_t *res, int64_t n, int l_max, const double *S, int m,
                          const uint32_t *dst, const uint32_t *cand, const double *dist,
                          int64_t cnt) {
   if (check_ids(dst, cand, cnt, n)) return -1;
@@ -516,7 +550,7 @@ static void rbc(const float *X, int d, const orc_params *prm, const uint32_t *P,
 /* Partition all n points. Leaves are written as CSR (offsets[n_leaves+1],
  * members). Returns 0, or -1 if a capacity was too small (the needed sizes
  * are still written to *n_leaves_out and *n_members_out). */
-int orc_partition(const float *X, int64_t n, int d, const orc_params *prm, int64_t *offsets,
+static int orc_partition_impl(const float *X, int64_t n, int d, const orc_params *prm, int64_t *offsets,
                   int64_t cap_leaves, uint32_t *members, int64_t cap_members,
                   int64_t *n_leaves_out, int64_t *n_members_out, int64_t *leader_dists_out) {
   leafbuf lb;
@@ -716,7 +750,7 @@ static double dist64(const double *a, const double *b, int d, int metric) {
  * k kept. mult = 0 keeps the k nearest by the operand distance without
  * re-ranking. Emitted distances are always those of the original vectors.
  * Output layout as orc_leaf_knn. */
-void orc_leaf_knn_lowp(const float *X, const double *xq, int d, int metric,
+static void orc_leaf_knn_lowp_impl(const float *X, const double *xq, int d, int metric,
                        const int64_t *offsets, const uint32_t *members, int64_t n_leaves, int k,
                        int mult, uint32_t *out_cand, double *out_dist) {
   int k1 = mult > 0 ? mult * k : k;
@@ -782,7 +816,7 @@ void orc_leaf_knn_lowp(const float *X, const double *xq, int d, int metric,
  * member order: row r = offsets[leaf] + i holds k slots; unused slots have
  * cand = 0xFFFFFFFF. The bi-directed records are (dst=i, cand=j, d) and
  * (dst=j, cand=i, d). */
-void orc_leaf_knn(const float *X, int d, int metric, const int64_t *offsets,
+static void orc_leaf_knn_impl(const float *X, int d, int metric, const int64_t *offsets,
                   const uint32_t *members, int64_t n_leaves, int k, uint32_t *out_cand,
                   double *out_dist) {
 #pragma omp parallel
@@ -876,7 +910,7 @@ static int cmp_dcand(const void *a, const void *b) {
   return (x->id > y->id) - (x->id < y->id);
 }
 
-void orc_robustprune(const float *X, int d, int metric, const uint64_t *res, int64_t n,
+static void orc_robustprune_impl(const float *X, int d, int metric, const uint64_t *res, int64_t n,
                      int l_max, float alpha_f, int R, int lazy, uint32_t *graph,
                      uint32_t *degree) {
   double alpha = (double)alpha_f;
@@ -948,7 +982,7 @@ void orc_robustprune(const float *X, int d, int metric, const uint64_t *res, int
  * d(q, .), the start included. */
 /* Lazy RobustPrune (as in orc_robustprune) of the listed points only:
  * point xs[i] uses reservoir row res[i] and writes graph row i. */
-void orc_robustprune_points(const float *X, int d, int metric, const uint64_t *res,
+static void orc_robustprune_points_impl(const float *X, int d, int metric, const uint64_t *res,
                             const uint32_t *xs, int64_t nx, int l_max, float alpha_f, int R,
                             uint32_t *graph, uint32_t *degree) {
   double alpha = (double)alpha_f;
@@ -987,7 +1021,7 @@ void orc_robustprune_points(const float *X, int d, int metric, const uint64_t *r
   }
 }
 
-void orc_beam_search(const float *X, int64_t n, int d, int metric, const uint32_t *graph, int R,
+static void orc_beam_search_impl(const float *X, int64_t n, int d, int metric, const uint32_t *graph, int R,
                      const float *Q, int64_t nq, int k, int L, uint32_t start, uint32_t *out_ids,
                      double *out_dist, uint32_t *out_cmps) {
 #pragma omp parallel
@@ -1046,7 +1080,7 @@ void orc_beam_search(const float *X, int64_t n, int d, int metric, const uint32_
 }
 
 /* Exact k nearest neighbours (Definition of k-NN search), ties by id. */
-void orc_bruteforce_knn(const float *X, int64_t n, int d, int metric, const float *Q, int64_t nq,
+static void orc_bruteforce_knn_impl(const float *X, int64_t n, int d, int metric, const float *Q, int64_t nq,
                         int k, uint32_t *out_ids, double *out_dist) {
 #pragma omp parallel
   {
@@ -1139,4 +1173,69 @@ void orc_leaf_reps(const float *X, int d, const int64_t *offsets, const uint32_t
     }
     free(S);
   }
+}
+
+/* Exported phase functions: the definitions above, timed. */
+
+void orc_sketches(const float *X, int64_t n, int d, const float *H, int m, double *S) {
+  const double t0 = orc_now();
+  orc_sketches_impl(X, n, d, H, m, S);
+  orc_phase_add(ORC_PH_SKETCH, t0);
+}
+
+int orc_hashprune_stream(uint64_t *res, int64_t n, int l_max, const double *S, int m, const uint32_t *dst, const uint32_t *cand, const double *dist, int64_t cnt) {
+  const double t0 = orc_now();
+  const int r = orc_hashprune_stream_impl(res, n, l_max, S, m, dst, cand, dist, cnt);
+  orc_phase_add(ORC_PH_HASHPRUNE, t0);
+  return r;
+}
+
+int orc_hashprune_closed(uint64_t *res, int64_t n, int l_max, const double *S, int m, const uint32_t *dst, const uint32_t *cand, const double *dist, int64_t cnt) {
+  const double t0 = orc_now();
+  const int r = orc_hashprune_closed_impl(res, n, l_max, S, m, dst, cand, dist, cnt);
+  orc_phase_add(ORC_PH_HASHPRUNE, t0);
+  return r;
+}
+
+int orc_partition(const float *X, int64_t n, int d, const orc_params *prm, int64_t *offsets, int64_t cap_leaves, uint32_t *members, int64_t cap_members, int64_t *n_leaves_out, int64_t *n_members_out, int64_t *leader_dists_out) {
+  const double t0 = orc_now();
+  const int r = orc_partition_impl(X, n, d, prm, offsets, cap_leaves, members, cap_members, n_leaves_out, n_members_out, leader_dists_out);
+  orc_phase_add(ORC_PH_PARTITION, t0);
+  return r;
+}
+
+void orc_leaf_knn_lowp(const float *X, const double *xq, int d, int metric, const int64_t *offsets, const uint32_t *members, int64_t n_leaves, int k, int mult, uint32_t *out_cand, double *out_dist) {
+  const double t0 = orc_now();
+  orc_leaf_knn_lowp_impl(X, xq, d, metric, offsets, members, n_leaves, k, mult, out_cand, out_dist);
+  orc_phase_add(ORC_PH_LEAF, t0);
+}
+
+void orc_leaf_knn(const float *X, int d, int metric, const int64_t *offsets, const uint32_t *members, int64_t n_leaves, int k, uint32_t *out_cand, double *out_dist) {
+  const double t0 = orc_now();
+  orc_leaf_knn_impl(X, d, metric, offsets, members, n_leaves, k, out_cand, out_dist);
+  orc_phase_add(ORC_PH_LEAF, t0);
+}
+
+void orc_robustprune(const float *X, int d, int metric, const uint64_t *res, int64_t n, int l_max, float alpha_f, int R, int lazy, uint32_t *graph, uint32_t *degree) {
+  const double t0 = orc_now();
+  orc_robustprune_impl(X, d, metric, res, n, l_max, alpha_f, R, lazy, graph, degree);
+  orc_phase_add(ORC_PH_ROBUSTPRUNE, t0);
+}
+
+void orc_robustprune_points(const float *X, int d, int metric, const uint64_t *res, const uint32_t *xs, int64_t nx, int l_max, float alpha_f, int R, uint32_t *graph, uint32_t *degree) {
+  const double t0 = orc_now();
+  orc_robustprune_points_impl(X, d, metric, res, xs, nx, l_max, alpha_f, R, graph, degree);
+  orc_phase_add(ORC_PH_ROBUSTPRUNE, t0);
+}
+
+void orc_beam_search(const float *X, int64_t n, int d, int metric, const uint32_t *graph, int R, const float *Q, int64_t nq, int k, int L, uint32_t start, uint32_t *out_ids, double *out_dist, uint32_t *out_cmps) {
+  const double t0 = orc_now();
+  orc_beam_search_impl(X, n, d, metric, graph, R, Q, nq, k, L, start, out_ids, out_dist, out_cmps);
+  orc_phase_add(ORC_PH_SEARCH, t0);
+}
+
+void orc_bruteforce_knn(const float *X, int64_t n, int d, int metric, const float *Q, int64_t nq, int k, uint32_t *out_ids, double *out_dist) {
+  const double t0 = orc_now();
+  orc_bruteforce_knn_impl(X, n, d, metric, Q, nq, k, out_ids, out_dist);
+  orc_phase_add(ORC_PH_BRUTEFORCE, t0);
 }
