@@ -112,6 +112,7 @@ def lib():
         L.orc_leaf_reps.argtypes = [P, i32, P, P, i64, P]
         L.orc_robustprune_points.argtypes = [P, i32, i32, P, P, i64, i32, C.c_float, i32, P, P]
         L.orc_get_threads.restype = i32
+        L.orc_leaf_all_to_all.argtypes = [P, i32, i32, P, P, i64, i32, C.c_float, P, P]
         L.orc_phase_seconds.restype = i32
         L.orc_phase_seconds.argtypes = [P, i32]
         _lib = L
@@ -292,6 +293,21 @@ def quantize(X, prec: int):
     xq = np.zeros((n, d), dtype=np.float64)
     lib().orc_quantize(_p(X), n, d, prec, _p(codes), _p(inv), _p(xq))
     return codes, inv, xq
+
+
+def leaf_all_to_all(X, offsets, members, R_leaf: int, alpha: float, metric: int = 0):
+    """All-to-All Prune leaf picker: per leaf member, lazy RobustPrune over
+    the other members of its leaf (up to R_leaf admitted, in admission
+    order); returns (cand, dist), (total members) x R_leaf like leaf_knn."""
+    X = _f32(X)
+    offsets = np.ascontiguousarray(offsets, dtype=np.int64)
+    members = np.ascontiguousarray(members, dtype=np.uint32)
+    tot = int(offsets[-1])
+    cand = np.zeros((tot, R_leaf), dtype=np.uint32)
+    dd = np.zeros((tot, R_leaf), dtype=np.float64)
+    lib().orc_leaf_all_to_all(_p(X), X.shape[1], metric, _p(offsets), _p(members),
+                              len(offsets) - 1, R_leaf, alpha, _p(cand), _p(dd))
+    return cand, dd
 
 
 def leaf_knn_lowp(X, xq, offsets, members, k: int, mult: int, metric: int = 0):

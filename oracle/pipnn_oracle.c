@@ -16,7 +16,8 @@
  *     history-independence lemma (Supplement, proof of determinism);
  *   - Randomized Ball Carving with fanout (Alg. 5, Sec. 4.1);
  *   - the bi-directed k-NN leaf pick (Sec. 4.2, Supplement "k-NN leaf
- *     design space");
+ *     design space") and the All-to-All Prune leaf picker (Supplement,
+ *     "Picking within Leaves");
  *   - RobustPrune, standard (Alg. 2) and lazy (Supplement "Optimizing
  *     RobustPrune");
  *   - BeamSearch (Alg. 1) and brute-force k-NN (Definition of k-NN search).
@@ -1175,6 +1176,66 @@ void orc_leaf_reps(const float *X, int d, const int64_t *offsets, const uint32_t
   }
 }
 
+/* ------------------------------------------------------------------ */
+/* All-to-All Prune leaf picker (Supplement, "Picking within Leaves",
+ * All-to-All Prune): for every member x of a leaf, RobustPrune (Alg. 2, in
+ * the lazy form of the Supplement's "Optimizing RobustPrune") with every
+ * other member of the leaf as the candidate set N: the candidates are taken
+ * in (d(x, c), id) order; c is skipped if an already admitted y has
+ * alpha * d(y, c) < d(x, c), else appended; the scan stops once R_leaf are
+ * admitted. All distances in FP64. Row i of the CSR (offsets, members)
+ * writes out_cand[i * R_leaf ..] (ids in admission order, EMPTY padding)
+ * and out_dist (d(x, c) of each, +inf padding). */
+static void orc_leaf_all_to_all_impl(const float *X, int d, int metric, const int64_t *offsets,
+                                     const uint32_t *members, int64_t n_leaves, int R_leaf,
+                                     float alpha_f, uint32_t *out_cand, double *out_dist) {
+  const double alpha = (double)alpha_f;
+  int64_t max_sz = 0;
+  for (int64_t l = 0; l < n_leaves; l++)
+    if (offsets[l + 1] - offsets[l] > max_sz) max_sz = offsets[l + 1] - offsets[l];
+#pragma omp parallel
+  {
+    dcand *N = (dcand *)malloc(sizeof(dcand) * (size_t)(max_sz > 0 ? max_sz : 1));
+    uint32_t *E = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)(R_leaf > 0 ? R_leaf : 1));
+    double *ED = (double *)malloc(sizeof(double) * (size_t)(R_leaf > 0 ? R_leaf : 1));
+#pragma omp for schedule(dynamic, 1)
+    for (int64_t l = 0; l < n_leaves; l++) {
+      const int64_t o = offsets[l], sz = offsets[l + 1] - offsets[l];
+      for (int64_t i = 0; i < sz; i++) {
+        const uint32_t x = members[o + i];
+        const float *xv = X + (int64_t)x * d;
+        int64_t nn = 0;
+        for (int64_t j = 0; j < sz; j++) {
+          if (j == i) continue;
+          N[nn].id = members[o + j];
+          N[nn].d = orc_dist(xv, X + (int64_t)N[nn].id * d, d, metric);
+          nn++;
+        }
+        qsort(N, (size_t)nn, sizeof(dcand), cmp_dcand);
+        int ne = 0;
+        for (int64_t t = 0; t < nn && ne < R_leaf; t++) {
+          const float *cv = X + (int64_t)N[t].id * d;
+          int pruned = 0;
+          for (int e = 0; e < ne && !pruned; e++)
+            if (alpha * orc_dist(X + (int64_t)E[e] * d, cv, d, metric) < N[t].d) pruned = 1;
+          if (!pruned) {
+            E[ne] = N[t].id;
+            ED[ne] = N[t].d;
+            ne++;
+          }
+        }
+        for (int e = 0; e < R_leaf; e++) {
+          out_cand[(o + i) * R_leaf + e] = e < ne ? E[e] : ORC_EMPTY_ID;
+          out_dist[(o + i) * R_leaf + e] = e < ne ? ED[e] : INFINITY;
+        }
+      }
+    }
+    free(N);
+    free(E);
+    free(ED);
+  }
+}
+
 /* Exported phase functions: the definitions above, timed. */
 
 void orc_sketches(const float *X, int64_t n, int d, const float *H, int m, double *S) {
@@ -1238,4 +1299,13 @@ void orc_bruteforce_knn(const float *X, int64_t n, int d, int metric, const floa
   const double t0 = orc_now();
   orc_bruteforce_knn_impl(X, n, d, metric, Q, nq, k, out_ids, out_dist);
   orc_phase_add(ORC_PH_BRUTEFORCE, t0);
+}
+
+void orc_leaf_all_to_all(const float *X, int d, int metric, const int64_t *offsets,
+                         const uint32_t *members, int64_t n_leaves, int R_leaf, float alpha_f,
+                         uint32_t *out_cand, double *out_dist) {
+  const double t0 = orc_now();
+  orc_leaf_all_to_all_impl(X, d, metric, offsets, members, n_leaves, R_leaf, alpha_f, out_cand,
+                           out_dist);
+  orc_phase_add(ORC_PH_LEAF, t0);
 }
