@@ -82,9 +82,10 @@ def parse():
                          "fp32, or fp16 for the 768-d workload)")
     ap.add_argument("--rescore-mult", type=int, default=0,
                     help="select rescore_mult*k by the GEMM distance, keep k by FP32 rescoring")
-    ap.add_argument("--variants", default="bf16:0,bf16:2,fp8:2,fp32:0:2",
-                    help="other forms (prec:rescore_mult[:replicas], comma separated) built and "
-                         "timed after the main one on the same workload; '' for none")
+    ap.add_argument("--variants", default="bf16:0,bf16:2,fp8:2,fp32:0:2,fp32:0:1:a2a",
+                    help="other forms (prec:rescore_mult[:replicas[:a2a]], comma separated) built "
+                         "and timed after the main one on the same workload (a2a: the All-to-All "
+                         "Prune leaf picker); '' for none")
     ap.add_argument("--frontier", action="store_true",
                     help="also build (float32) with other fanouts, leaf k and l_max, and report "
                          "each one's build rate, the beam width reaching recall@10 >= 0.95 and "
@@ -693,7 +694,7 @@ def main():
         leaves = (torch.from_numpy(lo).cuda(), torch.from_numpy(lm.view(np.int32)).cuda())
         log(f"[bench] explicit leaves: {len(lo) - 1}, sizes {np.diff(lo).min()}..{np.diff(lo).max()}")
 
-    def run_form(prec, mult, steps, warmup, keep=False, replicas=1, over=None):
+    def run_form(prec, mult, steps, warmup, keep=False, replicas=1, over=None, picker=0):
         """Build the whole index `warmup + steps` times with one leaf-GEMM
         form (and `replicas` independent partitions feeding the reservoirs);
         time the last `steps`; search the last graph for recall@10.
@@ -708,7 +709,7 @@ def main():
                               l_max=fl, R=w.R, alpha=w.alpha, hash_bits=fm,
                               leader_div=w.leader_div, leader_cap=w.leader_cap, fanout=ff,
                               seed=pi.workload_seed(cfg), gemm_prec=PREC_CODES[prec],
-                              rescore_mult=mult)
+                              rescore_mult=mult, leaf_picker=picker)
         idx = pp.Index(Xd, Hm.get(fm, Hd), p)
         res = torch.empty((n, fl), dtype=torch.int64, device="cuda")
         tune = None
@@ -773,7 +774,7 @@ def main():
             torch.cuda.synchronize()
             t1 = time.perf_counter()
         ms = (t1 - t0) * 1000.0 / steps
-        log(f"[bench] {prec} x{mult} r{replicas}: {steps} steps, {ms:.2f} ms/step")
+        log(f"[bench] {prec} x{mult} r{replicas}{' a2a' if picker else ''}: {steps} steps, {ms:.2f} ms/step")
         # leaf kernel roofline: dense flops 2 s^2 d per leaf, per launch
         launches = max(1, st["leaf_knn_launches"])
         # leaf_pairs counts the last build_leaves call: one replica's leaves
@@ -803,7 +804,9 @@ def main():
             idx.search(g, Qd, 10, l_at or RECALL_LS[-1], start, want_cmps=False)
             torch.cuda.synchronize()
             qps = nq / (time.perf_counter() - tq)
-        form = {"prec": prec, "rescore_mult": mult, "replicas": replicas, "ms_per_step": ms,
+        form = {"prec": prec, "rescore_mult": mult, "replicas": replicas,
+                "leaf_picker": "all-to-all-prune" if picker else "bi-directed-knn",
+                "ms_per_step": ms,
                 "value": n / (ms / 1000.0),
                 "leaf_gemm_tflops": achieved, "peak": PEAK_MFMA_TFLOPS[prec],
                 "frac": achieved / PEAK_MFMA_TFLOPS[prec], "recall_at_10": recall,
@@ -841,11 +844,13 @@ def main():
         parts = spec.split(":")
         vp, vm = parts[0], int(parts[1])
         vr = int(parts[2]) if len(parts) > 2 else 1
-        if (vp, vm, vr) == (args.prec, args.rescore_mult, 1):
+        va = 1 if len(parts) > 3 and parts[3] == "a2a" else 0
+        if (vp, vm, vr, va) == (args.prec, args.rescore_mult, 1, 0):
             continue
-        if leaves is not None and vr > 1:
-            continue  # explicit leaves: no partition to replicate
-        f = run_form(vp, vm, args.steps, 1, replicas=vr)
+        if leaves is not None and (vr > 1 or va):
+            continue  # explicit leaves: no partition to replicate; leaves above 2,048
+        f = run_form(vp, vm, min(args.steps, 5) if va else args.steps, 1, replicas=vr,
+                     picker=va)
         f.pop("stats")
         variants.append(f)
 

@@ -69,6 +69,9 @@ typedef int32_t pipnn_status;
 #define PIPNN_PREC_FP8 2     /* OCP e4m3 MFMA with per-point scales, FP32 accumulation */
 #define PIPNN_PREC_FP16 3    /* FP16 MFMA, FP32 accumulation */
 
+#define PIPNN_PICKER_KNN 0        /* bi-directed k nearest co-members (Sec. 4.2) */
+#define PIPNN_PICKER_ALL_TO_ALL 1 /* RobustPrune over the whole leaf (Supplement) */
+
 #define PIPNN_EMPTY_ID 0xFFFFFFFFu
 
 /* Hyper-parameter bundle BP of Alg. 4.
@@ -104,6 +107,14 @@ typedef int32_t pipnn_status;
  *               either format) and the leaf GEMM stays FP32.
  *  rescore_mult 0, or r >= 2: select the r*k nearest by the GEMM distance
  *               and keep the k nearest by an FP32 direct-difference rescore.
+ *  leaf_picker  PIPNN_PICKER_*: how a leaf member picks its candidates
+ *               (Sec. 4.2 and the Supplement, "Picking within Leaves"):
+ *               KNN, its k nearest co-members, bi-directed (both records
+ *               of each pick go to HashPrune); ALL_TO_ALL, RobustPrune
+ *               (Alg. 2, lazy form) of the member over every other member
+ *               of its leaf with this alpha, up to k admitted, each giving
+ *               the member one record (leaves of at most 2,048 members;
+ *               rescore_mult 0; no planned / captured builds, no insertion).
  *  seed         root key of the leader sampling (Alg. 5, SampleLeaders).
  */
 typedef struct {
@@ -114,7 +125,7 @@ typedef struct {
   float alpha;
   int32_t gemm_prec;
   int32_t rescore_mult;
-  int32_t reserved;
+  int32_t leaf_picker;
   uint64_t seed;
 } pipnn_params;
 
@@ -286,7 +297,11 @@ pipnn_status pipnn_insert(pipnn_index *idx, int64_t n_new, const int32_t *d_grou
  * norm-expansion cancellation to repair; for squared L2 without rescoring
  * on data the integer check found exact -- see pipnn_stats.data_int_exact --
  * the GEMM distance, which then is the same integer), and both directed records of each
- * picked edge inserted into HashPrune.
+ * picked edge inserted into HashPrune. With leaf_picker ALL_TO_ALL each member
+ * instead keeps the candidates that RobustPrune over its whole leaf admits
+ * (distances from the leaf's GEMM distance matrix, emitted as FP32 direct
+ * differences unless the two forms agree), each giving one record
+ * (member, candidate); EINVAL on a leaf of more than 2,048 members.
  * d_leaf_offsets/d_leaf_members is any CSR of leaves with ascending member
  * ids (RBC output or explicit leaves); leaves of size 1 contribute nothing.
  * d_reservoirs holds n x l_max uint64 slots (see pipnn_reservoir_init);
@@ -450,7 +465,8 @@ pipnn_status pipnn_knn_block(pipnn_index *idx, const uint32_t *d_row_ids, int64_
 /* The pick step alone: like pipnn_build_leaves but, instead of inserting
  * into HashPrune, writes each leaf row's picks as point ids d_out_cand and
  * FP32 direct-difference distances d_out_dist, both (offsets[L] x k) in CSR
- * member order, unused slots 0xFFFFFFFF / +inf. */
+ * member order, unused slots 0xFFFFFFFF / +inf. With leaf_picker ALL_TO_ALL
+ * the picks are the admitted candidates in admission order. */
 pipnn_status pipnn_leaf_pick(pipnn_index *idx, const int64_t *d_leaf_offsets,
                              const uint32_t *d_leaf_members, int64_t n_leaves, uint32_t *d_out_cand,
                              float *d_out_dist, pipnn_stream_t stream);

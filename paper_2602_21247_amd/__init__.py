@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(HERE, "libpipnn.so")
 METRIC_L2, METRIC_IP = 0, 1
 DTYPE_F32, DTYPE_F16, DTYPE_BF16 = 0, 1, 2
 PREC_FP32, PREC_BF16, PREC_FP8, PREC_FP16 = 0, 1, 2, 3
+PICKER_KNN, PICKER_ALL_TO_ALL = 0, 1
 LAYOUT_PAIR, LAYOUT_QUAD = 0, 1
 EMPTY_ID = 0xFFFFFFFF
 EMPTY_SLOT = 0x7F80 << 48 | 0xFFFFFFFF
@@ -47,7 +48,7 @@ class Params(C.Structure):
                 ("fanout", C.c_int32 * 4), ("k", C.c_int32), ("hash_bits", C.c_int32),
                 ("l_max", C.c_int32), ("R", C.c_int32), ("alpha", C.c_float),
                 ("gemm_prec", C.c_int32), ("rescore_mult", C.c_int32),
-                ("reserved", C.c_int32), ("seed", C.c_uint64)]
+                ("leaf_picker", C.c_int32), ("seed", C.c_uint64)]
 
 
 class Stats(C.Structure):

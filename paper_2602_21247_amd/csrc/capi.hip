@@ -138,6 +138,10 @@ bool valid_params(const pipnn_params *p, std::string &why) {
   }
   if (p->rescore_mult != 0 && (p->rescore_mult < 2 || p->rescore_mult * p->k > 32))
     return bad("rescore_mult must be 0, or >= 2 with rescore_mult * k <= 32");
+  if (p->leaf_picker != PIPNN_PICKER_KNN && p->leaf_picker != PIPNN_PICKER_ALL_TO_ALL)
+    return bad("unknown leaf_picker");
+  if (p->leaf_picker == PIPNN_PICKER_ALL_TO_ALL && p->rescore_mult != 0)
+    return bad("the all-to-all leaf picker takes no rescoring (rescore_mult 0)");
   return true;
 }
 
@@ -967,20 +971,20 @@ struct BinScratch {
 // scratch given.
 pipnn_status bin_and_merge_in(Index &I, const BinScratch &B, bool from_picks, const uint32_t *a,
                               const uint32_t *b, const float *dist, int64_t count, int32_t k,
-                              uint64_t *res, hipStream_t s) {
+                              uint64_t *res, hipStream_t s, bool bidir = true) {
   const int64_t n = I.n;
   {
     PhaseTimer tb(I, kPhBin, s);
     HIPCHK(launch_fill_u32(B.cnt, 0u, n, s));
     if (from_picks)
-      HIPCHK(launch_bin_count(a, b, count, k, B.cnt, n, I.flag.as<int32_t>(), s));
+      HIPCHK(launch_bin_count(a, b, count, k, B.cnt, n, I.flag.as<int32_t>(), s, bidir));
     else
       HIPCHK(launch_rec_count(a, b, count, B.cnt, n, I.flag.as<int32_t>(), s));
     HIPCHK(launch_scan_u32(B.cnt, B.off, n, B.tmp0, s));
     HIPCHK(launch_fill_u32(B.cnt, 0u, n, s));
     if (from_picks)
       HIPCHK(launch_bin_scatter(a, b, dist, count, k, I.sketches.as<float>(), I.m, B.off, B.cnt,
-                                B.bins, n, s));
+                                B.bins, n, s, bidir));
     else
       HIPCHK(launch_rec_scatter(a, b, dist, count, I.sketches.as<float>(), I.m, B.off, B.cnt,
                                 B.bins, n, s));
@@ -995,17 +999,109 @@ pipnn_status bin_and_merge_in(Index &I, const BinScratch &B, bool from_picks, co
 // The same with the index's own scratch.
 pipnn_status bin_and_merge(Index &I, bool from_picks, const uint32_t *a, const uint32_t *b,
                            const float *dist, int64_t count, int32_t k, uint64_t *res,
-                           hipStream_t s) {
+                           hipStream_t s, bool bidir = true) {
   const int64_t n = I.n;
-  // every pick yields two records, every explicit record one
-  const int64_t max_rec = from_picks ? 2 * count * k : count;
+  // every pick yields two records (one when not bidir), every explicit record one
+  const int64_t max_rec = from_picks ? (bidir ? 2 : 1) * count * k : count;
   HIPCHK(I.s_cnt.ensure((size_t)n * 4));
   HIPCHK(I.s_off.ensure((size_t)(n + 1) * 8));
   HIPCHK(I.s_tmp0.ensure((size_t)scan_tmp_elems(n) * 8));
   HIPCHK(I.s_bins.ensure((size_t)std::max<int64_t>(max_rec, 1) * 8));
   const BinScratch B{I.s_cnt.as<uint32_t>(), I.s_off.as<int64_t>(), I.s_tmp0.as<int64_t>(),
                      I.s_bins.as<uint64_t>()};
-  return bin_and_merge_in(I, B, from_picks, a, b, dist, count, k, res, s);
+  return bin_and_merge_in(I, B, from_picks, a, b, dist, count, k, res, s, bidir);
+}
+
+// All-to-All Prune leaf picker: batches of leaves whose distance matrices
+// (rows x largest leaf x 4 B) fit 1 GiB.
+std::vector<std::pair<int64_t, int64_t>> a2a_batches(const std::vector<int64_t> &offs,
+                                                     int64_t l0, int64_t l1) {
+  const int64_t budget = (int64_t)1 << 28;  // floats
+  std::vector<std::pair<int64_t, int64_t>> out;
+  int64_t b0 = l0, rows = 0, wide = 1;
+  for (int64_t l = l0; l < l1; ++l) {
+    const int64_t sz = offs[(size_t)l + 1] - offs[(size_t)l];
+    const int64_t w2 = std::max(wide, sz);
+    if (l > b0 && (rows + sz) * w2 > budget) {
+      out.push_back({b0, l});
+      b0 = l;
+      rows = 0;
+      wide = 1;
+    }
+    rows += sz;
+    wide = std::max(wide, sz);
+  }
+  if (b0 < l1) out.push_back({b0, l1});
+  return out;
+}
+
+// All-to-All Prune picks of leaves [l0, l1): the leaf kernel writes each
+// leaf's GEMM distance matrix, then one wave per row runs the lazy
+// RobustPrune over it. out_ids / out_dist: the batch's rows x k, point ids.
+pipnn_status a2a_pick(Index &I, const std::vector<int64_t> &offs, int64_t l0, int64_t l1,
+                      const int64_t *d_leaf_off, const uint32_t *d_members, uint32_t *out_ids,
+                      float *out_dist, hipStream_t s) {
+  const pipnn_params &P = I.p;
+  const int64_t rows = offs[(size_t)l1] - offs[(size_t)l0];
+  if (rows == 0) return PIPNN_OK;
+  int64_t wide = 1;
+  for (int64_t l = l0; l < l1; ++l)
+    wide = std::max<int64_t>(wide, offs[(size_t)l + 1] - offs[(size_t)l]);
+  if (wide > kA2aMaxLeaf)
+    return fail(PIPNN_EINVAL, "the all-to-all leaf picker takes leaves of at most %d members",
+                kA2aMaxLeaf);
+  HIPCHK(I.a2a_mat.ensure((size_t)rows * wide * 4));
+  HIPCHK(I.a2a_tmp.ensure((size_t)rows * 8));
+  int32_t n_items = 0, max_cols = 0;
+  int64_t pairs = 0;
+  pipnn_status st = plan_pick(I, offs, l0, l1, I.s_jobs, I.s_items, n_items, max_cols, pairs, s);
+  if (st != PIPNN_OK) return st;
+  I.stats.leaf_pairs += pairs;
+  if (n_items > 0) {
+    KnnLaunch L{};
+    L.idx = &I;
+    L.row_base = d_members;
+    L.col_base = d_members;
+    L.jobs = I.s_jobs.as<KnnJob>();
+    L.items = I.s_items.as<KnnItem>();
+    L.n_items = n_items;
+    L.max_cols = max_cols;
+    L.ksel = 4;  // only the distance matrix is used: the smallest selection
+    L.k_out = 1;
+    L.out_ids = 0;
+    L.recompute = 0;
+    L.rescore_k = 0;
+    L.prec = P.gemm_prec;
+    L.nw = I.leaf_nw;
+    L.persistent = I.leaf_persistent;
+    L.quad = I.leaf_quad;
+    L.out_col = I.a2a_tmp.as<uint32_t>();
+    L.out_dist = reinterpret_cast<float *>(I.a2a_tmp.as<uint32_t>() + rows);
+    L.out_matrix = I.a2a_mat.as<float>();
+    L.matrix_ld = wide;
+    PhaseTimer t(I, kPhLeafKnn, s);
+    HIPCHK(launch_knn(L, s));
+    ++I.leaf_launches;
+  }
+  PhaseTimer t(I, kPhLeafKnn, s);
+  HIPCHK(launch_a2a_prune(I.a2a_mat.as<float>(), wide, d_leaf_off + l0, l1 - l0, offs[(size_t)l0],
+                          rows, d_members, I.xf(), I.d, P.metric, gemm_is_direct(I) ? 0 : 1, P.k,
+                          P.alpha, out_ids, out_dist, s));
+  return PIPNN_OK;
+}
+
+// Every leaf's All-to-All Prune picks into out_ids / out_dist (indexed from
+// offs[l0]).
+pipnn_status a2a_pick_all(Index &I, const std::vector<int64_t> &offs, int64_t l0, int64_t l1,
+                          const int64_t *d_leaf_off, const uint32_t *d_members, uint32_t *out_ids,
+                          float *out_dist, hipStream_t s) {
+  for (auto &b : a2a_batches(offs, l0, l1)) {
+    const int64_t o = (offs[(size_t)b.first] - offs[(size_t)l0]) * I.p.k;
+    pipnn_status st = a2a_pick(I, offs, b.first, b.second, d_leaf_off, d_members, out_ids + o,
+                               out_dist + o, s);
+    if (st != PIPNN_OK) return st;
+  }
+  return PIPNN_OK;
 }
 
 // The same for the picks of a batch of leaves written as local column
@@ -1158,6 +1254,8 @@ pipnn_status pipnn_plan_leaves(pipnn_index *idx, const int64_t *d_leaf_offsets,
                                const uint32_t *d_leaf_members, int64_t n_leaves,
                                pipnn_stream_t stream) {
   GUARD_BEGIN
+  if (idx && reinterpret_cast<Index *>(idx)->p.leaf_picker == PIPNN_PICKER_ALL_TO_ALL)
+    return fail(PIPNN_ESTATE, "the all-to-all leaf picker has no planned build");
   if (!idx || !d_leaf_offsets || !d_leaf_members || n_leaves < 1)
     return fail(PIPNN_EINVAL, "invalid argument");
   Index &I = *reinterpret_cast<Index *>(idx);
@@ -1204,6 +1302,34 @@ pipnn_status pipnn_build_leaves(pipnn_index *idx, const int64_t *d_leaf_offsets,
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   const int k = I.p.k;
   const bool capturing = stream_capturing(s);
+  if (I.p.leaf_picker == PIPNN_PICKER_ALL_TO_ALL) {
+    // All-to-All Prune picks of every leaf, then their records (one per
+    // admitted candidate) into HashPrune
+    if (capturing)
+      return fail(PIPNN_ESTATE, "the all-to-all leaf picker has no captured build");
+    std::vector<int64_t> offs;
+    pipnn_status st = read_offsets(d_leaf_offsets, n_leaves, s, offs);
+    if (st != PIPNN_OK) return st;
+    I.stats.leaf_pairs = 0;
+    I.stats.records = 0;
+    const int64_t rows = offs[(size_t)n_leaves] - offs[0];
+    st = check_ids(I, d_leaf_members + offs[0], rows, s, "build_leaves");
+    if (st != PIPNN_OK) return st;
+    const std::vector<std::pair<int64_t, int64_t>> all{{0, n_leaves}};
+    st = reserve_build(I, offs, all, n_leaves);
+    if (st != PIPNN_OK) return st;
+    st = a2a_pick_all(I, offs, 0, n_leaves, d_leaf_offsets, d_leaf_members,
+                      I.s_picks_c.as<uint32_t>(), I.s_picks_d.as<float>(), s);
+    if (st != PIPNN_OK) return st;
+    st = bin_and_merge(I, true, d_leaf_members + offs[0], I.s_picks_c.as<uint32_t>(),
+                       I.s_picks_d.as<float>(), rows, k, d_reservoirs, s, false);
+    if (st != PIPNN_OK) return st;
+    st = leaf_order(I, d_leaf_members + offs[0], rows, s);
+    if (st != PIPNN_OK) return st;
+    st = keep_leaf_table(I, d_leaf_offsets, d_leaf_members, offs, n_leaves, s);
+    if (st != PIPNN_OK) return st;
+    return finish_bins(I, s, "build_leaves");
+  }
   const bool planned = plan_matches(I, d_leaf_offsets, d_leaf_members, n_leaves);
   if (capturing && !planned)
     return fail(PIPNN_ESTATE, "build_leaves under stream capture needs pipnn_plan_leaves on the "
@@ -1361,6 +1487,8 @@ pipnn_status pipnn_insert(pipnn_index *idx, int64_t n_new, const int32_t *d_grou
   if (n_new == 0) return PIPNN_OK;
   if (stream_capturing(s)) return fail(PIPNN_ESTATE, "insert cannot run under capture");
   if (I.lt_n_leaves < 1) return fail(PIPNN_ESTATE, "insert needs the leaves of a build first");
+  if (I.p.leaf_picker != PIPNN_PICKER_KNN)
+    return fail(PIPNN_ESTATE, "insertion picks by the k-NN leaf picker only");
   if (I.n + n_new > I.cap)
     return fail(PIPNN_EOVERFLOW, "insert of %lld points exceeds the reserved capacity %lld",
                 (long long)n_new, (long long)I.cap);
@@ -1675,6 +1803,9 @@ pipnn_status pipnn_leaf_pick(pipnn_index *idx, const int64_t *d_leaf_offsets,
   if (offs[0] != 0) return fail(PIPNN_EINVAL, "offsets[0] must be 0");
   st = check_ids(I, d_leaf_members, offs[(size_t)n_leaves], s, "leaf_pick");
   if (st != PIPNN_OK) return st;
+  if (I.p.leaf_picker == PIPNN_PICKER_ALL_TO_ALL)
+    return a2a_pick_all(I, offs, 0, n_leaves, d_leaf_offsets, d_leaf_members, d_out_cand,
+                        d_out_dist, s);
   return run_pick(I, offs, 0, n_leaves, d_leaf_members, d_out_cand, d_out_dist, s);
   GUARD_END
 }

@@ -18,6 +18,7 @@
 // inside a bin, never reservoir contents, so the result is deterministic.
 #include "common.hpp"
 #include "internal.hpp"
+#include "wave_sort.hpp"
 
 namespace pipnn {
 
@@ -51,7 +52,7 @@ __device__ __forceinline__ void hash_pair(const float *__restrict__ S, int m, ui
 // One thread per pick, so the k picks of a row are k consecutive lanes; when
 // k is a power of two that group is aligned inside a wave and the row's
 // forward records are counted and placed with one atomic (AGG).
-template <bool AGG>
+template <bool AGG, bool BIDIR = true>
 __global__ void __launch_bounds__(256) bin_count_kernel(const uint32_t *row_ids,
                                                         const uint32_t *picks, int64_t n_rows,
                                                         int k, uint32_t *cnt, int64_t n,
@@ -71,10 +72,10 @@ __global__ void __launch_bounds__(256) bin_count_kernel(const uint32_t *row_ids,
   } else if (ok) {
     atomicAdd(&cnt[i], 1u);
   }
-  if (ok) atomicAdd(&cnt[j], 1u);
+  if (BIDIR && ok) atomicAdd(&cnt[j], 1u);
 }
 
-template <bool AGG>
+template <bool AGG, bool BIDIR = true>
 __global__ void __launch_bounds__(256) bin_scatter_kernel(const uint32_t *row_ids,
                                                           const uint32_t *picks, const float *dist,
                                                           int64_t n_rows, int k, const float *S,
@@ -107,8 +108,10 @@ __global__ void __launch_bounds__(256) bin_scatter_kernel(const uint32_t *row_id
   }
   if (!ok) return;
   bins[pi] = slot_pack(j, hij, bf);
-  const int64_t pj = off[j] + atomicAdd(&cursor[j], 1u);
-  bins[pj] = slot_pack(i, hji, bf);
+  if (BIDIR) {
+    const int64_t pj = off[j] + atomicAdd(&cursor[j], 1u);
+    bins[pj] = slot_pack(i, hji, bf);
+  }
 }
 
 // Leaf-local binning. Every record of a leaf pick joins two members of the
@@ -245,32 +248,43 @@ hipError_t launch_leaf_bin(bool scatter, const int64_t *leaf_off, int64_t off0, 
 }
 
 hipError_t launch_bin_count(const uint32_t *row_ids, const uint32_t *picks, int64_t n_rows,
-                            int32_t k, uint32_t *cnt, int64_t n, int32_t *flag, hipStream_t s) {
+                            int32_t k, uint32_t *cnt, int64_t n, int32_t *flag, hipStream_t s,
+                            bool bidir) {
   const int64_t tot = n_rows * k;
   if (tot == 0) return hipSuccess;
   const bool agg = k <= 64 && (k & (k - 1)) == 0;
-  if (agg)
-    hipLaunchKernelGGL(bin_count_kernel<true>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0,
-                       s, row_ids, picks, n_rows, k, cnt, n, flag);
+  const dim3 g((unsigned)((tot + 255) / 256)), b(256);
+  if (agg && bidir)
+    hipLaunchKernelGGL((bin_count_kernel<true, true>), g, b, 0, s, row_ids, picks, n_rows, k, cnt, n, flag);
+  else if (agg)
+    hipLaunchKernelGGL((bin_count_kernel<true, false>), g, b, 0, s, row_ids, picks, n_rows, k, cnt, n, flag);
+  else if (bidir)
+    hipLaunchKernelGGL((bin_count_kernel<false, true>), g, b, 0, s, row_ids, picks, n_rows, k, cnt, n, flag);
   else
-    hipLaunchKernelGGL(bin_count_kernel<false>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0,
-                       s, row_ids, picks, n_rows, k, cnt, n, flag);
+    hipLaunchKernelGGL((bin_count_kernel<false, false>), g, b, 0, s, row_ids, picks, n_rows, k, cnt, n, flag);
   return hipGetLastError();
 }
 
 hipError_t launch_bin_scatter(const uint32_t *row_ids, const uint32_t *picks, const float *dist,
                               int64_t n_rows, int32_t k, const float *sketch, int32_t m,
                               const int64_t *off, uint32_t *cursor, uint64_t *bins, int64_t n,
-                              hipStream_t s) {
+                              hipStream_t s, bool bidir) {
   const int64_t tot = n_rows * k;
   if (tot == 0) return hipSuccess;
   const bool agg = k <= 64 && (k & (k - 1)) == 0;
-  if (agg)
-    hipLaunchKernelGGL(bin_scatter_kernel<true>, dim3((unsigned)((tot + 255) / 256)), dim3(256),
-                       0, s, row_ids, picks, dist, n_rows, k, sketch, m, off, cursor, bins, n);
+  const dim3 g((unsigned)((tot + 255) / 256)), b(256);
+  if (agg && bidir)
+    hipLaunchKernelGGL((bin_scatter_kernel<true, true>), g, b, 0, s, row_ids, picks, dist, n_rows,
+                       k, sketch, m, off, cursor, bins, n);
+  else if (agg)
+    hipLaunchKernelGGL((bin_scatter_kernel<true, false>), g, b, 0, s, row_ids, picks, dist, n_rows,
+                       k, sketch, m, off, cursor, bins, n);
+  else if (bidir)
+    hipLaunchKernelGGL((bin_scatter_kernel<false, true>), g, b, 0, s, row_ids, picks, dist,
+                       n_rows, k, sketch, m, off, cursor, bins, n);
   else
-    hipLaunchKernelGGL(bin_scatter_kernel<false>, dim3((unsigned)((tot + 255) / 256)), dim3(256),
-                       0, s, row_ids, picks, dist, n_rows, k, sketch, m, off, cursor, bins, n);
+    hipLaunchKernelGGL((bin_scatter_kernel<false, false>), g, b, 0, s, row_ids, picks, dist,
+                       n_rows, k, sketch, m, off, cursor, bins, n);
   return hipGetLastError();
 }
 
@@ -455,46 +469,6 @@ __global__ void __launch_bounds__(64 * kMergeWaves) hashprune_merge_kernel(
 // by key2 = (rank, id, hash) gives the reservoir order, whose first l_max
 // entries are the new reservoir. Larger bins are taken in chunks (the kept
 // minima stay in the first elements). No LDS is used.
-// x of lane ^ J, by VALU lane moves: DPP quad permutations (J = 1, 2), a
-// half-row mirror then a quad reversal (J = 4: 7 - (i ^ 3) = i ^ 4 within 8
-// lanes), a row rotation by 8 (J = 8), and the gfx950 row / half-wave swaps
-// (J = 16, 32).
-template <int J>
-__device__ __forceinline__ uint32_t xor_lane_u32(uint32_t x) {
-  if constexpr (J == 1) {
-    return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0xB1, 0xF, 0xF, false);  // [1,0,3,2]
-  } else if constexpr (J == 2) {
-    return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x4E, 0xF, 0xF, false);  // [2,3,0,1]
-  } else if constexpr (J == 4) {
-    const int m = __builtin_amdgcn_mov_dpp((int)x, 0x141, 0xF, 0xF, false);   // row_half_mirror
-    return (uint32_t)__builtin_amdgcn_mov_dpp(m, 0x1B, 0xF, 0xF, false);      // [3,2,1,0]
-  } else if constexpr (J == 8) {
-    return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x128, 0xF, 0xF, false);  // row_ror:8
-  } else if constexpr (J == 16) {
-    const auto r = __builtin_amdgcn_permlane16_swap(x, x, false, false);
-    return (__lane_id() & 16) ? r[0] : r[1];
-  } else {
-    static_assert(J == 32, "lane xor of 1..32");
-    const auto r = __builtin_amdgcn_permlane32_swap(x, x, false, false);
-    return (__lane_id() & 32) ? r[0] : r[1];
-  }
-}
-template <int J>
-__device__ __forceinline__ uint64_t xor_lane_u64(uint64_t v) {
-  const uint32_t lo = xor_lane_u32<J>((uint32_t)v);
-  const uint32_t hi = xor_lane_u32<J>((uint32_t)(v >> 32));
-  return ((uint64_t)hi << 32) | lo;
-}
-__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int j) {
-  switch (j) {
-    case 1: return xor_lane_u64<1>(v);
-    case 2: return xor_lane_u64<2>(v);
-    case 4: return xor_lane_u64<4>(v);
-    case 8: return xor_lane_u64<8>(v);
-    case 16: return xor_lane_u64<16>(v);
-    default: return xor_lane_u64<32>(v);
-  }
-}
 __device__ __forceinline__ uint64_t shfl_up1_u64(uint64_t v) {
   const uint32_t lo = (uint32_t)__shfl_up((int)(uint32_t)v, 1, 64);
   const uint32_t hi = (uint32_t)__shfl_up((int)(uint32_t)(v >> 32), 1, 64);
@@ -504,41 +478,6 @@ __device__ __forceinline__ uint64_t readlane63_u64(uint64_t v) {
   const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, 63);
   const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), 63);
   return ((uint64_t)hi << 32) | lo;
-}
-
-// Ascending bitonic sort of the 64 * E keys of the wave.
-template <int E>
-__device__ __forceinline__ void reg_bitonic_sort(uint64_t (&v)[E], int lane) {
-  constexpr int N = 64 * E;
-#pragma unroll
-  for (int k = 2; k <= N; k <<= 1) {
-#pragma unroll
-    for (int j = k >> 1; j > 0; j >>= 1) {
-      if (j >= 64) {
-        const int je = j >> 6;
-#pragma unroll
-        for (int e = 0; e < E; ++e) {
-          if ((e & je) == 0) {
-            const bool asc = ((e * 64 + lane) & k) == 0;
-            const uint64_t x = v[e], y = v[e | je];
-            const bool sw = (x > y) == asc;
-            v[e] = sw ? y : x;
-            v[e | je] = sw ? x : y;
-          }
-        }
-      } else {
-        const bool lower = (lane & j) == 0;
-#pragma unroll
-        for (int e = 0; e < E; ++e) {
-          // the lower lane of a pair keeps the minimum in an ascending block,
-          // the upper lane in a descending one: one compare and one select
-          const bool keep_min = lower == (((e * 64 + lane) & k) == 0);
-          const uint64_t y = shfl_xor_u64(v[e], j);
-          v[e] = ((v[e] < y) == keep_min) ? v[e] : y;
-        }
-      }
-    }
-  }
 }
 
 // Merge of one point with E keys per lane, writing its reservoir r. s0/s1:

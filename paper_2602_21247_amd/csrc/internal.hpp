@@ -69,6 +69,7 @@ struct Index {
   DevBuf i_rows, i_cols, i_assign, i_flag, i_pos, i_list, i_tmp, i_segs;
   DevBuf q_conv, q_seen;        // search scratch (search may overlap an insertion)
   DevBuf g_ids, g_dist;         // k-NN graph: k + 1 results per point of a chunk
+  DevBuf a2a_mat, a2a_tmp;      // all-to-all picker: leaf distance matrices of a batch
   int32_t device = 0;           // the HIP device current at pipnn_create
   int32_t n_cu = 256;           // compute units of the device (persistent grid size)
   int32_t leaf_nw = 4;          // waves (of 32 rows) per leaf work item: 4, or 2 where built
@@ -264,12 +265,15 @@ hipError_t launch_leaf_bin(bool scatter, const int64_t *leaf_off, int64_t off0, 
                            const uint32_t *members, const uint32_t *picks, const float *dist,
                            int32_t k, const float *sketch, int32_t m, const int64_t *bin_off,
                            uint32_t *cnt, uint64_t *bins, hipStream_t s);
+// bidir: every pick (i -> j) yields the records (i, j) and (j, i); else
+// only (i, j)
 hipError_t launch_bin_count(const uint32_t *row_ids, const uint32_t *picks, int64_t n_rows,
-                            int32_t k, uint32_t *cnt, int64_t n, int32_t *flag, hipStream_t s);
+                            int32_t k, uint32_t *cnt, int64_t n, int32_t *flag, hipStream_t s,
+                            bool bidir = true);
 hipError_t launch_bin_scatter(const uint32_t *row_ids, const uint32_t *picks, const float *dist,
                               int64_t n_rows, int32_t k, const float *sketch, int32_t m,
                               const int64_t *off, uint32_t *cursor, uint64_t *bins, int64_t n,
-                              hipStream_t s);
+                              hipStream_t s, bool bidir = true);
 hipError_t launch_rec_count(const uint32_t *dst, const uint32_t *cand, int64_t cnt_rec,
                             uint32_t *cnt, int64_t n, int32_t *flag, hipStream_t s);
 hipError_t launch_rec_scatter(const uint32_t *dst, const uint32_t *cand, const float *dist,
@@ -294,6 +298,16 @@ hipError_t launch_search(const Index &I, int64_t n, const uint32_t *graph, const
                          int64_t nq, int32_t k, int32_t L, uint32_t start, uint32_t *out_ids,
                          float *out_dist, uint32_t *out_cmps, uint32_t *visited_bits,
                          int64_t words_per_query, hipStream_t s);
+
+// All-to-All Prune picks of the rows [off0, off0 + rows) of a batch of
+// leaves (leaf_off: absolute offsets of the batch's n_leaves leaves) from
+// their GEMM distance matrices D (row r at D + r * ld, column = position in
+// the leaf): out_id / out_dist rows x R (point ids in admission order).
+hipError_t launch_a2a_prune(const float *D, int64_t ld, const int64_t *leaf_off, int64_t n_leaves,
+                            int64_t off0, int64_t rows, const uint32_t *members, const float *X,
+                            int32_t d, int32_t metric, int32_t recompute, int32_t R, float alpha,
+                            uint32_t *out_id, float *out_dist, hipStream_t s);
+constexpr int kA2aMaxLeaf = 2048;
 
 // k + 1 results per point searched as a query -> k without the point itself
 hipError_t launch_drop_self(const uint32_t *ids, const float *dist, int64_t nq, int32_t k1,

@@ -17,7 +17,7 @@ OUT = os.path.join(HERE, "libpipnn.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 SOURCES = ["knn.hip", "knn_fp32q.hip", "knn_bf16.hip", "knn_fp16.hip", "knn_fp8.hip", "capi.hip",
            "misc.hip",
-           "hashprune.hip", "graph.hip"]
+           "hashprune.hip", "graph.hip", "a2a.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
