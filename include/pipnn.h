@@ -24,10 +24,15 @@
  *  - Pointers: arguments named d_* are device pointers; h_* are host
  *    pointers. All of them are owned by the caller and must stay valid until
  *    the enqueued work has finished. X (and H) must outlive the index.
- *  - Memory: the index allocates its own device scratch (sketches, norms,
- *    low-precision copies, partition levels, candidate bins) with hipMalloc
- *    and frees it in pipnn_destroy. pipnn_workspace_bytes reports an upper
- *    bound of that scratch so that a caller can admit work by free memory.
+ *  - Memory: an index created over a caller's workspace (pipnn_create's
+ *    d_workspace, of at least pipnn_workspace_bytes) allocates no device
+ *    memory: every device buffer it uses (sketches, norms, copies of X,
+ *    partition levels, picks, candidate bins, search scratch) is a fixed
+ *    slice of that workspace, and a call whose data would exceed its slice
+ *    fails with PIPNN_ENOMEM. With no workspace the index allocates its
+ *    buffers itself (hipMalloc, grown on demand, freed by pipnn_destroy);
+ *    only such an index can grow its capacity (pipnn_reserve) for
+ *    pipnn_insert. pipnn_hashprune_insert_static uses neither (see there).
  *  - Ids are uint32 point indices 0..n-1; 0xFFFFFFFF marks an empty slot.
  *  - Distances are squared L2 (metric 0) or the negated inner product
  *    (metric 1), so that smaller is always nearer (Preliminaries).
@@ -140,11 +145,19 @@ const char *pipnn_last_error(void);
  * FP32 GEMM, no rescore, seed 0. */
 void pipnn_default_params(pipnn_params *p);
 
-/* Upper bound, in bytes, of the device scratch an index over n points of
- * dimension d holds at its peak (partition levels, candidate bins for
- * up to max_batch_records records, sketches, norms, low-precision copies).
- * Returns 0 if the parameters are invalid. */
-size_t pipnn_workspace_bytes(const pipnn_params *p, int64_t n, int32_t d,
+/* Bytes of the workspace an index over n points of dimension d with X of
+ * x_dtype needs when a build bins at most max_batch_records candidate
+ * records at a time (a leaf pick gives two records per pick: the batch is
+ * max_batch_records / (2k) leaf rows, at least 65535 -- the largest leaf --
+ * and at most a whole build; 0 = a whole build in one batch). The value is
+ * the sum of the index's fixed buffer slices, each sized for the worst case
+ * the parameters allow: a partition of the n points (Alg. 5, at most n times
+ * fanout[0] * fanout[1] * fanout[2] leaf members), one batch of picks and
+ * records, RobustPrune's order, search and k-NN-graph batches. pipnn_create
+ * succeeds with exactly this many bytes and fails with PIPNN_ENOMEM with
+ * fewer than the value for the smallest batch. Returns 0 for invalid
+ * parameters, n, d or dtype. */
+size_t pipnn_workspace_bytes(const pipnn_params *p, int64_t n, int32_t d, int32_t x_dtype,
                              int64_t max_batch_records);
 
 /* Create an index over d_X (n x d, row-major, x_dtype) with hyperplanes
@@ -155,14 +168,28 @@ size_t pipnn_workspace_bytes(const pipnn_params *p, int64_t n, int32_t d,
  * EINVAL if n < 2, d < 1, hash_bits not in 1..16, k < 1, l_max not in
  * 1..256, R not in 1..256, alpha < 1, c_max < 2, c_min > c_max, leader_div
  * < 1, leader_cap < 2, a fanout < 1, fanout[3] != 1, an unknown dtype or
- * precision, n >= 2^32 - 1, d > 256 with gemm_prec FP32, or d > 768. ENOMEM
- * if scratch cannot be allocated. With a reduced gemm_prec it also encodes
- * the GEMM operand (see pipnn_get_operand). */
+ * precision, n >= 2^32 - 1, d > 256 with gemm_prec FP32, or d > 768. With a
+ * reduced gemm_prec it also encodes the GEMM operand (see
+ * pipnn_get_operand).
+ * d_workspace / ws_bytes: a device buffer owned by the caller (256-byte
+ * aligned; it must outlive the index) from which every device buffer of the
+ * index is carved; the index then allocates nothing. Build batches take the
+ * most leaf rows whose layout fits ws_bytes (see pipnn_workspace_bytes;
+ * pipnn_get_stats reports the layout and batch). On a workspace a float32 X
+ * must be 16-byte aligned (EINVAL otherwise), the point count is fixed at n,
+ * and a call whose data exceed the layout (leaves with more members than
+ * the bound, a knn_block of more rows than a batch) fails with ENOMEM.
+ * ENOMEM if ws_bytes is below pipnn_workspace_bytes for the smallest batch
+ * (this check takes no device call). NULL / 0: the index allocates its own
+ * buffers (ENOMEM if that fails). */
 pipnn_status pipnn_create(const pipnn_params *p, const void *d_X, int64_t n, int32_t d,
-                          int32_t x_dtype, const float *d_H, pipnn_stream_t stream,
-                          pipnn_index **out);
+                          int32_t x_dtype, const float *d_H, void *d_workspace, size_t ws_bytes,
+                          pipnn_stream_t stream, pipnn_index **out);
 
-/* Release the index and its device scratch (synchronises its stream). */
+/* Release the index and the device buffers it allocated (none on a
+ * workspace, which the caller frees afterwards). The caller must have
+ * finished the work that uses the index on every stream; no device-wide
+ * synchronisation is made. */
 void pipnn_destroy(pipnn_index *idx);
 
 /* (sync) Randomized ball carving (Alg. 5) of all n points into leaves of at
@@ -256,7 +283,8 @@ pipnn_status pipnn_autotune(pipnn_index *idx, const int64_t *d_leaf_offsets,
  * and the caller sizes its reservoirs (n_cap x l_max), graph (n_cap x R)
  * and degree (n_cap) buffers the same way. EINVAL if n_cap >= 2^32 - 1, or
  * if a new float32 X that the leaf kernel reads directly is not 16-byte
- * aligned. */
+ * aligned; ESTATE if the index was created over a workspace and n_cap
+ * exceeds its point count (such an index has a fixed capacity). */
 pipnn_status pipnn_reserve(pipnn_index *idx, int64_t n_cap, const void *d_X,
                            pipnn_stream_t stream);
 
@@ -283,10 +311,15 @@ pipnn_status pipnn_reserve(pipnn_index *idx, int64_t n_cap, const void *d_X,
  * of X) as they were, and the old points' reservoirs and graph rows
  * untouched when it fails before step 4 (every argument and size check
  * does), so the caller may retry with other points in the same rows; the
- * new rows' buffers are rewritten by the next insertion. */
+ * new rows' buffers are rewritten by the next insertion.
+ * epoch: the caller's label of the snapshot this insertion publishes; it
+ * must exceed the label of the last committed insertion (the index starts
+ * at 0), EINVAL otherwise, so that insertions commit in the caller's order.
+ * On success (n_new = 0 included) it becomes the index's epoch, reported
+ * with the point count by pipnn_get_stats; a failed call keeps the old one. */
 pipnn_status pipnn_insert(pipnn_index *idx, int64_t n_new, const int32_t *d_group,
                           uint64_t *d_reservoirs, uint32_t *d_graph, uint32_t *d_degree,
-                          pipnn_stream_t stream);
+                          uint64_t epoch, pipnn_stream_t stream);
 
 /* Pick + Prune_And_Add_Edges for every leaf (Alg. 4, the parallel loop over
  * leaves; Sec. 4.2): per leaf, the distance matrix on MFMA, each member's
@@ -434,6 +467,10 @@ typedef struct {
                                     form exact in float32, so the leaf picks skip the winners'
                                     FP32 recompute (no rescoring) */
   double ms_prepare, ms_partition, ms_leaf_knn, ms_bin, ms_merge, ms_robustprune;
+  uint64_t epoch;                /* epoch of the last committed pipnn_insert (0: none) */
+  int64_t n_points;              /* current point count */
+  int64_t workspace_bytes;       /* the workspace layout in use (0: the index allocates) */
+  int64_t batch_rows;            /* leaf rows per pick + binning batch of a build */
 } pipnn_stats;
 
 /* Switch phase timing on (1; also clears the sums) or off (0). */

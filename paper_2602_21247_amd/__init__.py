@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(HERE, "libpipnn.so")
 METRIC_L2, METRIC_IP = 0, 1
 DTYPE_F32, DTYPE_F16, DTYPE_BF16 = 0, 1, 2
 PREC_FP32, PREC_BF16, PREC_FP8, PREC_FP16 = 0, 1, 2, 3
+OK, EINVAL, ENOMEM, EOVERFLOW, EDEVICE, ESTATE = 0, -1, -2, -3, -4, -5
 PICKER_KNN, PICKER_ALL_TO_ALL = 0, 1
 LAYOUT_PAIR, LAYOUT_QUAD = 0, 1
 EMPTY_ID = 0xFFFFFFFF
@@ -58,7 +59,8 @@ class Stats(C.Structure):
                 ("operand_exact", C.c_int32), ("data_int_exact", C.c_int32),
                 ("ms_prepare", C.c_double), ("ms_partition", C.c_double),
                 ("ms_leaf_knn", C.c_double), ("ms_bin", C.c_double), ("ms_merge", C.c_double),
-                ("ms_robustprune", C.c_double)]
+                ("ms_robustprune", C.c_double), ("epoch", C.c_uint64), ("n_points", C.c_int64),
+                ("workspace_bytes", C.c_int64), ("batch_rows", C.c_int64)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -80,8 +82,9 @@ def lib():
         L.pipnn_last_error.restype = C.c_char_p
         L.pipnn_default_params.argtypes = [C.POINTER(Params)]
         L.pipnn_workspace_bytes.restype = C.c_size_t
-        L.pipnn_workspace_bytes.argtypes = [C.POINTER(Params), i64, i32, i64]
-        L.pipnn_create.argtypes = [C.POINTER(Params), P, i64, i32, i32, P, P, C.POINTER(P)]
+        L.pipnn_workspace_bytes.argtypes = [C.POINTER(Params), i64, i32, i32, i64]
+        L.pipnn_create.argtypes = [C.POINTER(Params), P, i64, i32, i32, P, P, C.c_size_t, P,
+                                   C.POINTER(P)]
         L.pipnn_destroy.argtypes = [P]
         L.pipnn_destroy.restype = None
         L.pipnn_partition.argtypes = [P, P, i64, P, i64, C.POINTER(i64), C.POINTER(i64), P]
@@ -106,7 +109,7 @@ def lib():
         L.pipnn_plan_leaves.argtypes = [P, P, P, i64, P]
         L.pipnn_set_leaf_config.argtypes = [P, i32, i32, i32]
         L.pipnn_reserve.argtypes = [P, i64, P, P]
-        L.pipnn_insert.argtypes = [P, i64, P, P, P, P, P]
+        L.pipnn_insert.argtypes = [P, i64, P, P, P, P, C.c_uint64, P]
         L.pipnn_autotune.argtypes = [P, P, P, i64, C.POINTER(TuneResult), i32, C.POINTER(i32), P]
         for name in EXPORTS:
             if name not in ("pipnn_version", "pipnn_last_error", "pipnn_default_params",
@@ -138,8 +141,12 @@ def default_params(**kw) -> Params:
     return p
 
 
-def workspace_bytes(params: Params, n: int, d: int, max_batch_records: int = 0) -> int:
-    return int(lib().pipnn_workspace_bytes(C.byref(params), n, d, max_batch_records))
+def workspace_bytes(params: Params, n: int, d: int, max_batch_records: int = 0,
+                    x_dtype: int = 0) -> int:
+    """pipnn_workspace_bytes: the workspace an index over n x d points (X of
+    x_dtype) needs with build batches of max_batch_records records (0: a
+    whole build in one batch)."""
+    return int(lib().pipnn_workspace_bytes(C.byref(params), n, d, x_dtype, max_batch_records))
 
 
 def _torch():
@@ -178,16 +185,26 @@ class TuneResult(C.Structure):
 class Index:
     """An index over device-resident points X (n x d) with hyperplanes H."""
 
-    def __init__(self, X, H, params: Params):
+    def __init__(self, X, H, params: Params, workspace=None):
+        """workspace: a device tensor (contiguous, 256-byte aligned) whose
+        bytes hold every device buffer of the index (see workspace_bytes);
+        None: the index allocates its own."""
         torch = _torch()
         assert X.is_cuda and X.is_contiguous() and X.dim() == 2
         self.X = X
         self.H = H.to(device=X.device, dtype=torch.float32).contiguous()
         self.params = params
         self.n, self.d = X.shape
+        self.epoch = 0
+        self.workspace = workspace
+        ws_bytes = 0
+        if workspace is not None:
+            assert workspace.is_cuda and workspace.is_contiguous()
+            ws_bytes = workspace.numel() * workspace.element_size()
         h = C.c_void_p()
         _check(lib().pipnn_create(C.byref(params), _ptr(X), self.n, self.d, _dtype_code(X),
-                                  _ptr(self.H), _stream(), C.byref(h)))
+                                  _ptr(self.H), _ptr(workspace), ws_bytes, _stream(),
+                                  C.byref(h)))
         self._h = h
 
     def close(self):
@@ -234,8 +251,9 @@ class Index:
                 for i in range(cnt.value)]
 
     def workspace_bytes(self, n: int, max_batch_records: int = 0) -> int:
-        """pipnn_workspace_bytes for this index's parameters at n points."""
-        return workspace_bytes(self.params, n, self.d, max_batch_records)
+        """pipnn_workspace_bytes for this index's parameters and X dtype at
+        n points."""
+        return workspace_bytes(self.params, n, self.d, max_batch_records, _dtype_code(self.X))
 
     def reserve(self, n_cap: int, X=None):
         """Room for n_cap points (the bound X must have n_cap rows). X: a new
@@ -248,11 +266,14 @@ class Index:
         if X is not None:
             self.X = X
 
-    def insert(self, n_new: int, reservoirs, graph, degree, groups=None):
-        """Insert rows [n, n + n_new) of X (already written by the caller)."""
+    def insert(self, n_new: int, reservoirs, graph, degree, groups=None, epoch=None):
+        """Insert rows [n, n + n_new) of X (already written by the caller)
+        as snapshot `epoch` (default: the last one + 1)."""
+        ep = self.epoch + 1 if epoch is None else int(epoch)
         _check(lib().pipnn_insert(self._h, n_new, None if groups is None else _ptr(groups),
-                                  _ptr(reservoirs), _ptr(graph), _ptr(degree), _stream()))
+                                  _ptr(reservoirs), _ptr(graph), _ptr(degree), ep, _stream()))
         self.n += n_new
+        self.epoch = ep
 
     def partition(self, replica: int = 0):
         """Ball carving (Alg. 5); replica r > 0 is an independent carving
@@ -267,7 +288,7 @@ class Index:
                                                cap_m, C.byref(nl), C.byref(nm), _stream())
             if st == 0:
                 return off[: nl.value + 1], mem[: nm.value]
-            if st != -3:
+            if st != EOVERFLOW:
                 _check(st)
             cap_l, cap_m = nl.value, nm.value
         _check(st)

@@ -233,6 +233,13 @@ namespace pipnn {
 
 hipError_t DevBuf::ensure(size_t bytes) {
   if (bytes <= cap && p) return hipSuccess;
+  if (fixed) {
+    // a slice of the caller's workspace: handed out whole on first use
+    if (bytes > lim || !ws_p) return hipErrorOutOfMemory;
+    p = ws_p;
+    cap = lim;
+    return hipSuccess;
+  }
   // a buffer that has to grow again takes half as much once more, so that
   // calls of slowly rising size (insertions) reallocate rarely
   const size_t grown = p ? cap + cap / 2 : 0;
@@ -249,7 +256,7 @@ hipError_t DevBuf::ensure(size_t bytes) {
 }
 
 void DevBuf::release() {
-  if (p) (void)hipFree(p);
+  if (p && !fixed) (void)hipFree(p);
   p = nullptr;
   cap = 0;
 }
@@ -333,6 +340,153 @@ hipError_t refresh_fp32_copy(Index &I, hipStream_t s) {
   return capturing ? hipSuccess : read_op_flag(I, true, s);
 }
 
+// ---------------------------------------------------------------------
+// Workspace layout. Every device buffer of an index has a worst-case size
+// that follows from the parameters, n, d, the dtype of X and the leaf rows
+// of one pick + binning batch. On a caller's workspace each buffer is a
+// fixed slice of that size (256-byte aligned, in the order of all_bufs), so
+// pipnn_workspace_bytes is the sum of the slices and nothing is allocated.
+//
+// The partition bounds follow from Alg. 5 with fanout: a point is assigned
+// to at most fanout[l] leaders at level l, so the subproblems of any level
+// hold at most F = n * fanout[0] * fanout[1] * fanout[2] members (fanout[3]
+// is 1), their assignments at most F, and the leaves of one partition at
+// most F members in total; every subproblem below the root has more than
+// C_max members, and a subproblem of c members has at most
+// min(leader_cap, c / leader_div + 3) leaders (buckets).
+
+constexpr int64_t kMaxLeafRows = 65535;       // the largest leaf a build takes
+constexpr int64_t kMaxBatchRows = (int64_t)1 << 25;
+constexpr int64_t kSeenBudgetWords = (int64_t)1 << 26;  // 256 MiB of search seen-bitmaps
+constexpr int64_t kMaxQueryBatch = (int64_t)1 << 16;
+constexpr int64_t kGraphMaxK1 = 65;           // k + 1 of a full k-NN graph chunk
+constexpr int64_t kA2aBudgetFloats = (int64_t)1 << 28;  // all-to-all distance matrices of a batch
+
+int64_t members_bound(const pipnn_params &p, int64_t n) {
+  return n * p.fanout[0] * p.fanout[1] * p.fanout[2];
+}
+
+// Leaf rows of one batch for max_batch_records records (a pick gives two):
+// at least the largest leaf, at most a whole build. 0: a whole build.
+int64_t batch_rows_for(const pipnn_params &p, int64_t n, int64_t max_batch_records) {
+  const int64_t whole =
+      std::min<int64_t>(kMaxBatchRows, std::max<int64_t>(kMaxLeafRows, members_bound(p, n)));
+  if (max_batch_records <= 0) return whole;
+  return std::max<int64_t>(kMaxLeafRows,
+                           std::min<int64_t>(whole, max_batch_records / (2 * (int64_t)p.k)));
+}
+
+// Queries per search launch (their seen bitmaps take n bits each).
+int64_t query_batch(int64_t n) {
+  const int64_t words = (n + 31) / 32;
+  return std::max<int64_t>(1, std::min<int64_t>(kMaxQueryBatch, kSeenBudgetWords / words));
+}
+
+// The shape-dependent fields of an index (also set on a host-only index by
+// pipnn_workspace_bytes).
+void init_shape(Index &I, const pipnn_params &p, int64_t n, int32_t d, int32_t x_dtype) {
+  I.p = p;
+  I.n = n;
+  I.cap = n;
+  I.d = d;
+  I.x_dtype = x_dtype;
+  I.m = p.hash_bits;
+  I.ldf = knn_operand_dim(d, PIPNN_PREC_FP32);
+}
+
+std::vector<DevBuf *> all_bufs(Index &I) {
+  return {&I.flag, &I.int_chk, &I.op_flag, &I.s_counter, &I.sketches, &I.norms, &I.xf32,
+          &I.xpad, &I.xlow, &I.xscale, &I.lnorms, &I.rp_order, &I.lt_off, &I.lt_mem, &I.lt_rep,
+          &I.s_jobs, &I.s_items, &I.s_picks_c, &I.s_picks_d, &I.s_cnt, &I.s_off, &I.s_bins,
+          &I.s_tmp0, &I.s_tmp1, &I.p_mem[0], &I.p_mem[1], &I.p_asg, &I.p_G, &I.p_gout,
+          &I.p_gsize, &I.p_leaders, &I.p_cm, &I.p_bstart, &I.p_groups, &I.p_seg, &I.p_seglen,
+          &I.p_segfirst, &I.p_segoff, &I.p_rsrc, &I.p_roff, &I.p_rlen, &I.p_esrc, &I.p_eoff,
+          &I.p_elen, &I.o_first, &I.o_flag, &I.o_pos, &I.o_pos2, &I.o_tmp, &I.plan.jobs,
+          &I.plan.items, &I.i_rows, &I.i_cols, &I.i_assign, &I.i_flag, &I.i_pos, &I.i_list,
+          &I.i_tmp, &I.i_segs, &I.q_conv, &I.q_seen, &I.g_ids, &I.g_dist, &I.a2a_mat,
+          &I.a2a_tmp};
+}
+
+size_t slice_bytes(size_t b) { return (std::max<size_t>(b, 256) + 255) & ~(size_t)255; }
+
+// Sets every buffer's lim for the index's shape and batch_rows. Buffers
+// only insertion uses get none (an index on a workspace holds a fixed set of
+// points).
+void set_limits(Index &I) {
+  const pipnn_params &P = I.p;
+  const int64_t n = I.n, d = I.d, k = P.k, B = I.batch_rows;
+  const int64_t F = std::max<int64_t>(n, members_bound(P, n));
+  const int64_t S = std::max<int64_t>(1, F / ((int64_t)P.c_max + 1));      // subproblems per level
+  const int64_t ell_max = std::min<int64_t>(P.leader_cap, F / P.leader_div + 3);
+  // (each bound adds one per subproblem and one more for integer division)
+  const int64_t NB = F / P.leader_div + 3 * S + 1;                          // buckets per level
+  const int64_t tiles = F / kGroupTile + S + 1;                             // group-by tiles
+  const int64_t CM = ell_max * tiles;                                       // group-by counters
+  const int64_t LV = 2 * NB + F / P.c_max + S + 1;                          // leaves per level
+  const int64_t mx = std::max(F, n);
+  const size_t nb_start = (size_t)((n + 255) / 256);
+  for (DevBuf *b : all_bufs(I)) b->lim = 0;
+  I.flag.lim = I.int_chk.lim = I.op_flag.lim = I.s_counter.lim = 64;
+  I.sketches.lim = (size_t)n * I.m * 4;
+  I.norms.lim = (size_t)n * 4;
+  if (I.x_dtype != PIPNN_DTYPE_F32) I.xf32.lim = (size_t)n * d * 4;
+  if (I.ldf != 0 && I.ldf != d) I.xpad.lim = (size_t)n * I.ldf * 4;
+  if (P.gemm_prec != PIPNN_PREC_FP32 || d <= 128) {
+    const size_t eb = P.gemm_prec == PIPNN_PREC_FP8 ? 1 : 2;
+    I.xlow.lim = (size_t)n * lowp_padded_dim((int)d) * eb;
+    I.xscale.lim = I.lnorms.lim = (size_t)n * 4;
+  }
+  I.rp_order.lim = (size_t)n * 4;
+  I.lt_off.lim = (size_t)(F + 1) * 8;
+  I.lt_mem.lim = (size_t)F * 4;
+  // work lists: a partition level (its subproblems, row blocks of 128), or
+  // a batch of leaves (a job per leaf of two or more rows, row blocks of at
+  // least 32), or one block
+  const int64_t jobs = std::max<int64_t>(S, B / 2 + 1);
+  const int64_t items = std::max<int64_t>(F / 128 + S + 1, B / 32 + B / 2 + 2);
+  I.s_jobs.lim = (size_t)jobs * sizeof(KnnJob);
+  I.s_items.lim = (size_t)items * sizeof(KnnItem);
+  I.s_picks_c.lim = I.s_picks_d.lim = (size_t)B * k * 4;
+  I.s_bins.lim = (size_t)2 * B * k * 8;
+  I.s_cnt.lim = (size_t)n * 4;
+  I.s_off.lim = std::max<size_t>((size_t)(n + 1) * 8, (size_t)scan_tmp_elems(CM) * 8);
+  I.s_tmp0.lim = std::max<size_t>((size_t)scan_tmp_elems(n) * 8, (size_t)S * sizeof(GroupSub));
+  I.s_tmp1.lim = std::max<size_t>((size_t)NB * 8, ((size_t)d + 2 * nb_start + 1) * 8 + 8);
+  I.p_mem[0].lim = I.p_mem[1].lim = I.p_asg.lim = I.p_G.lim = I.p_gout.lim = (size_t)F * 4;
+  I.p_gsize.lim = I.p_leaders.lim = I.p_seglen.lim = I.p_rlen.lim = (size_t)NB * 4;
+  I.p_segfirst.lim = (size_t)(NB + 1) * 4;
+  I.p_seg.lim = I.p_segoff.lim = I.p_rsrc.lim = I.p_roff.lim = (size_t)NB * 8;
+  I.p_bstart.lim = (size_t)(NB + 1) * 8;
+  I.p_cm.lim = (size_t)(CM + 1) * 8;
+  I.p_groups.lim = (size_t)tiles * sizeof(GroupTile);
+  I.p_esrc.lim = I.p_eoff.lim = (size_t)LV * 8;
+  I.p_elen.lim = (size_t)LV * 4;
+  I.o_first.lim = (size_t)n * 4;
+  I.o_flag.lim = (size_t)mx * 4;
+  I.o_pos.lim = (size_t)(mx + 1) * 8;
+  I.o_pos2.lim = (size_t)(n + 1) * 8;
+  I.o_tmp.lim = (size_t)scan_tmp_elems(mx) * 8;
+  // a planned build: every batch's jobs and row blocks
+  I.plan.jobs.lim = (size_t)(F / 2 + F / B + 2) * sizeof(KnnJob);
+  I.plan.items.lim = (size_t)(F / 32 + F / 2 + F / B + 2) * sizeof(KnnItem);
+  const int64_t QB = query_batch(n);
+  I.q_conv.lim = (size_t)QB * d * 4;
+  I.q_seen.lim = (size_t)QB * ((n + 31) / 32) * 4;
+  I.g_ids.lim = I.g_dist.lim = (size_t)std::min<int64_t>(n, QB) * kGraphMaxK1 * 4;
+  if (P.leaf_picker == PIPNN_PICKER_ALL_TO_ALL) {
+    I.a2a_mat.lim = (size_t)kA2aBudgetFloats * 4;
+    I.a2a_tmp.lim = (size_t)B * 8;
+  }
+}
+
+// Sum of the slices of the layout.
+size_t layout_bytes(Index &I) {
+  size_t t = 0;
+  for (DevBuf *b : all_bufs(I))
+    if (b->lim) t += slice_bytes(b->lim);
+  return t;
+}
+
 }  // namespace
 
 extern "C" {
@@ -361,29 +515,27 @@ void pipnn_default_params(pipnn_params *p) {
   p->seed = 0;
 }
 
-size_t pipnn_workspace_bytes(const pipnn_params *p, int64_t n, int32_t d,
+size_t pipnn_workspace_bytes(const pipnn_params *p, int64_t n, int32_t d, int32_t x_dtype,
                              int64_t max_batch_records) {
-  std::string why;
-  if (!valid_params(p, why) || n < 2 || d < 1) return 0;
-  const int64_t inst = n * p->fanout[0] * p->fanout[1] * p->fanout[2];
-  const int64_t picks = inst * p->k;
-  const int64_t rec = std::max<int64_t>(2 * picks, max_batch_records);
-  size_t b = 0;
-  b += (size_t)n * (size_t)(p->hash_bits + 1) * 4;          // sketches + norms
-  b += (size_t)inst * 4 * 6;                                  // partition levels
-  b += (size_t)inst * p->fanout[0] * 4 * 2;                   // assignments
-  b += (size_t)picks * 8;                                     // picks (id + dist)
-  b += (size_t)rec * 8;                                       // binned slots
-  b += (size_t)(n + 1) * 8 + (size_t)n * 4;                   // bin offsets + counts
-  if (p->gemm_prec != PIPNN_PREC_FP32 || d <= 128)         // operand / fp16 copy, scales, norms
-    b += (size_t)n * lowp_padded_dim(d) * (p->gemm_prec == PIPNN_PREC_FP8 ? 1 : 2) +
-         (size_t)n * 8;
-  return b;
+  try {
+    std::string why;
+    if (!valid_params(p, why) || n < 2 || n >= (int64_t)0xFFFFFFFFll || d < 1 || d > 1024)
+      return 0;
+    if (x_dtype != PIPNN_DTYPE_F32 && x_dtype != PIPNN_DTYPE_F16 && x_dtype != PIPNN_DTYPE_BF16)
+      return 0;
+    Index I;
+    init_shape(I, *p, n, d, x_dtype);
+    I.batch_rows = batch_rows_for(*p, n, max_batch_records);
+    set_limits(I);
+    return layout_bytes(I);
+  } catch (...) {
+    return 0;
+  }
 }
 
 pipnn_status pipnn_create(const pipnn_params *p, const void *d_X, int64_t n, int32_t d,
-                          int32_t x_dtype, const float *d_H, pipnn_stream_t stream,
-                          pipnn_index **out) {
+                          int32_t x_dtype, const float *d_H, void *d_workspace, size_t ws_bytes,
+                          pipnn_stream_t stream, pipnn_index **out) {
   GUARD_BEGIN
   std::string why;
   if (!out) return fail(PIPNN_EINVAL, "out is NULL");
@@ -394,20 +546,55 @@ pipnn_status pipnn_create(const pipnn_params *p, const void *d_X, int64_t n, int
   if (d < 1 || d > 1024) return fail(PIPNN_EINVAL, "d must be in 1..1024");
   if (x_dtype != PIPNN_DTYPE_F32 && x_dtype != PIPNN_DTYPE_F16 && x_dtype != PIPNN_DTYPE_BF16)
     return fail(PIPNN_EINVAL, "unknown x_dtype %d", x_dtype);
+  const bool ws = d_workspace != nullptr || ws_bytes != 0;
+  if (ws) {
+    if (!d_workspace) return fail(PIPNN_EINVAL, "workspace is NULL but ws_bytes is not 0");
+    if (reinterpret_cast<uintptr_t>(d_workspace) & 255u)
+      return fail(PIPNN_EINVAL, "the workspace must be 256-byte aligned");
+    if (x_dtype == PIPNN_DTYPE_F32 && (reinterpret_cast<uintptr_t>(d_X) & 15u))
+      return fail(PIPNN_EINVAL, "an index on a workspace needs a 16-byte aligned float32 X");
+  }
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   Index *I = new Index();
-  I->p = *p;
+  init_shape(*I, *p, n, d, x_dtype);
   I->X = d_X;
-  I->n = n;
-  I->d = d;
-  I->x_dtype = x_dtype;
   I->H = d_H;
-  I->m = p->hash_bits;
   I->stream = s;
   auto cleanup = [&](pipnn_status st) {
     pipnn_destroy(reinterpret_cast<pipnn_index *>(I));
     return st;
   };
+  if (ws) {
+    // the largest batch of leaf rows whose layout fits the workspace
+    auto bytes_at = [&](int64_t rows) {
+      I->batch_rows = rows;
+      set_limits(*I);
+      return layout_bytes(*I);
+    };
+    int64_t lo = kMaxLeafRows, hi = batch_rows_for(*p, n, 0);
+    const size_t need_min = bytes_at(lo);
+    if (need_min > ws_bytes)
+      return cleanup(fail(PIPNN_ENOMEM, "the workspace has %zu bytes; this index needs at least "
+                          "%zu (pipnn_workspace_bytes)", ws_bytes, need_min));
+    if (bytes_at(hi) > ws_bytes) {
+      while (lo < hi) {  // bytes_at(lo) fits, bytes_at(hi) does not
+        const int64_t mid = lo + (hi - lo + 1) / 2;
+        if (bytes_at(mid) <= ws_bytes) lo = mid; else hi = mid - 1;
+      }
+    } else {
+      lo = hi;
+    }
+    I->ws_bytes = bytes_at(lo);
+    unsigned char *base = static_cast<unsigned char *>(d_workspace);
+    size_t off = 0;
+    for (DevBuf *b : all_bufs(*I)) {
+      b->fixed = true;
+      if (!b->lim) continue;
+      b->ws_p = base + off;
+      off += slice_bytes(b->lim);
+    }
+    I->ws_mode = true;
+  }
   hipError_t e;
   {
     int dev = 0, ncu = 0;
@@ -477,21 +664,10 @@ pipnn_status pipnn_create(const pipnn_params *p, const void *d_X, int64_t n, int
 void pipnn_destroy(pipnn_index *idx) {
   if (!idx) return;
   Index *I = reinterpret_cast<Index *>(idx);
-  (void)hipDeviceSynchronize();
-  for (DevBuf *b : {&I->rp_order, &I->o_first, &I->o_flag, &I->o_pos, &I->o_pos2, &I->o_tmp,
-                    &I->xf32, &I->xpad, &I->xlow, &I->op_flag, &I->int_chk, &I->xscale, &I->lnorms, &I->s_counter, &I->q_conv, &I->q_seen, &I->g_ids, &I->g_dist,
-                    &I->lt_off, &I->lt_mem, &I->lt_rep, &I->i_rows, &I->i_cols, &I->i_assign,
-                    &I->i_flag, &I->i_pos, &I->i_list, &I->i_tmp, &I->i_segs, &I->sketches, &I->norms, &I->flag, &I->s_jobs,
-                    &I->s_items, &I->s_picks_c, &I->s_picks_d, &I->s_cnt, &I->s_off, &I->s_bins,
-                    &I->s_tmp0, &I->s_tmp1, &I->p_asg, &I->p_leaders, &I->p_cm, &I->p_bstart,
-                    &I->p_groups, &I->p_gout, &I->p_gsize, &I->p_copy})
-    b->release();
-  for (DevBuf &b : I->levels) b.release();
-  for (auto &b : I->plan.batches) {
-    b.jobs.release();
-    b.items.release();
-  }
-  for (DevBuf &b : I->ppool) b.release();
+  // the caller has finished the work that uses the index (no device-wide
+  // synchronisation: other streams keep running); hipFree waits for the
+  // device where it must
+  for (DevBuf *b : all_bufs(*I)) b->release();
   for (auto &e : I->events) {
     (void)hipEventDestroy(e.a);
     (void)hipEventDestroy(e.b);
@@ -537,40 +713,61 @@ pipnn_status pipnn_partition_replica(pipnn_index *idx, int32_t replica, int64_t 
     uint64_t key;
     int depth;
   };
+  // Leaves are written to the output level by level, in the order they are
+  // found, so that one level's buffers serve the next: the members of the
+  // level's subproblems (ping-pong between p_mem[0] and p_mem[1]), their
+  // leader assignments (p_asg), the assignments grouped by bucket (p_G) and
+  // the merged small buckets (p_gout).
   struct Leaf {
     const uint32_t *src;
-    int64_t len;        // -1: size read from a merge-size array
-    int32_t *size_dev;  // merge output sizes (device) when len < 0
-    int size_idx;
+    int64_t len;  // -1: the size of merged group `grp`, read back
+    int32_t grp;
   };
-  std::vector<Leaf> leaves;
-  // every level allocates its own buffers; they are kept until the end
-  // per-call buffers come from a pool kept by the index (stable addresses,
-  // reused by the next call, so repeated partitions allocate nothing)
-  I.ppool_used = 0;
-  auto fresh = [&](size_t bytes, DevBuf *&out) -> hipError_t {
-    if (I.ppool_used == I.ppool.size()) I.ppool.emplace_back();
-    out = &I.ppool[I.ppool_used++];
-    return out->ensure(bytes);
-  };
+  std::vector<int64_t> offs(1, 0);  // output CSR offsets (host)
+  bool writing = d_leaf_offsets && d_leaf_members;
   PhaseTimer timer(I, kPhPartition, s);
   int64_t leader_dists = 0;
   int levels = 0;
+  // appends a level's leaves; members are copied while everything so far
+  // fits the output's capacities
+  auto emit = [&](const std::vector<Leaf> &lv, const std::vector<int32_t> &grp_size) -> pipnn_status {
+    if (lv.empty()) return PIPNN_OK;
+    const int64_t base = offs.back();
+    std::vector<const uint32_t *> src;
+    std::vector<int64_t> doff;
+    std::vector<int32_t> lens;
+    for (const Leaf &lf : lv) {
+      const int64_t len = lf.len >= 0 ? lf.len : grp_size[(size_t)lf.grp];
+      src.push_back(lf.src);
+      doff.push_back(offs.back() - base);
+      lens.push_back((int32_t)len);
+      offs.push_back(offs.back() + len);
+    }
+    if ((int64_t)offs.size() - 1 > cap_leaves || offs.back() > cap_members) writing = false;
+    if (!writing) return PIPNN_OK;
+    HIPCHK(upload(I.p_esrc, src, s));
+    HIPCHK(upload(I.p_eoff, doff, s));
+    HIPCHK(upload(I.p_elen, lens, s));
+    HIPCHK(launch_copy_segments(I.p_esrc.as<const uint32_t *>(), I.p_eoff.as<int64_t>(),
+                                I.p_elen.as<int32_t>(), (int32_t)src.size(),
+                                d_leaf_members + base, s));
+    HIPCHK(hipStreamSynchronize(s));  // the host tables may be released now
+    return PIPNN_OK;
+  };
 
-  DevBuf *A0;
-  HIPCHK(fresh((size_t)n * 4, A0));
-  HIPCHK(launch_iota(A0->as<uint32_t>(), n, s));
+  int cur = 0;
+  HIPCHK(I.p_mem[0].ensure((size_t)n * 4));
+  HIPCHK(launch_iota(I.p_mem[0].as<uint32_t>(), n, s));
   std::vector<Sub> subs;
   if (n <= P.c_max) {
-    leaves.push_back({A0->as<uint32_t>(), n, nullptr, 0});
+    pipnn_status st = emit({{I.p_mem[0].as<uint32_t>(), n, 0}}, {});
+    if (st != PIPNN_OK) return st;
   } else {
     subs.push_back({0, n, replica_key(P.seed, replica), 0});
   }
-  DevBuf *A = A0;
-  std::vector<int32_t> gsize_host;
-  std::vector<std::pair<int32_t *, int>> gsize_arrays;  // (device array, count)
 
   while (!subs.empty()) {
+    const uint32_t *A = I.p_mem[cur].as<uint32_t>();
     // --- leaders and assignment jobs
     std::vector<KnnJob> jobs;
     std::vector<KnnItem> items;
@@ -607,7 +804,7 @@ pipnn_status pipnn_partition_replica(pipnn_index *idx, int32_t replica, int64_t 
     ++levels;
     HIPCHK(upload(I.s_tmp1, lead_idx, s));
     HIPCHK(I.p_leaders.ensure(lead_idx.size() * 4));
-    HIPCHK(launch_gather_u32(A->as<uint32_t>(), I.s_tmp1.as<int64_t>(), I.p_leaders.as<uint32_t>(),
+    HIPCHK(launch_gather_u32(A, I.s_tmp1.as<int64_t>(), I.p_leaders.as<uint32_t>(),
                              (int64_t)lead_idx.size(), s));
     items = plan_items(jobs, 128);
     HIPCHK(upload(I.s_jobs, jobs, s));
@@ -615,7 +812,7 @@ pipnn_status pipnn_partition_replica(pipnn_index *idx, int32_t replica, int64_t 
     HIPCHK(I.p_asg.ensure((size_t)inst * fmax * 4));
     KnnLaunch L{};
     L.idx = &I;
-    L.row_base = A->as<uint32_t>();
+    L.row_base = A;
     L.col_base = I.p_leaders.as<uint32_t>();
     L.jobs = I.s_jobs.as<KnnJob>();
     L.items = I.s_items.as<KnnItem>();
@@ -661,13 +858,12 @@ pipnn_status pipnn_partition_replica(pipnn_index *idx, int32_t replica, int64_t 
     HIPCHK(upload(I.p_bstart, bucket_cm, s));
     HIPCHK(I.p_cm.ensure((size_t)(cm_len + 1) * 8));
     HIPCHK(I.s_off.ensure((size_t)scan_tmp_elems(cm_len) * 8));
-    DevBuf *G;
-    HIPCHK(fresh((size_t)inst * fmax * 4, G));
+    HIPCHK(I.p_G.ensure((size_t)inst * fmax * 4));
     int32_t fm = fmax;
-    HIPCHK(launch_groupby(I.p_asg.as<uint32_t>(), A->as<uint32_t>(), &fm, I.s_tmp0.as<GroupSub>(),
+    HIPCHK(launch_groupby(I.p_asg.as<uint32_t>(), A, &fm, I.s_tmp0.as<GroupSub>(),
                           I.p_groups.as<GroupTile>(), (int32_t)tiles.size(), kGroupTile,
                           I.p_cm.as<int64_t>(), cm_len, I.s_off.as<int64_t>(),
-                          G->as<uint32_t>(), I.p_bstart.as<int64_t>(), nbuck + 1, s));
+                          I.p_G.as<uint32_t>(), I.p_bstart.as<int64_t>(), nbuck + 1, s));
     std::vector<int64_t> bstart((size_t)nbuck + 1);
     HIPCHK(hipMemcpyAsync(bstart.data(), I.p_bstart.p, bstart.size() * 8, hipMemcpyDeviceToHost,
                           s));
@@ -675,6 +871,7 @@ pipnn_status pipnn_partition_replica(pipnn_index *idx, int32_t replica, int64_t 
 
     // --- plan: merge small buckets, emit leaves, recurse
     std::vector<Sub> next;
+    std::vector<Leaf> lv;  // this level's leaves, in output order
     std::vector<const uint32_t *> seg_ptr;
     std::vector<int32_t> seg_len, grp_first;
     std::vector<int64_t> grp_off;
@@ -682,7 +879,7 @@ pipnn_status pipnn_partition_replica(pipnn_index *idx, int32_t replica, int64_t 
     int32_t max_sum = 0;
     std::vector<std::pair<const uint32_t *, int64_t>> recurse_src;
     int64_t next_off = 0;
-    uint32_t *Gp = G->as<uint32_t>();
+    const uint32_t *Gp = I.p_G.as<uint32_t>();
     for (size_t si = 0; si < subs.size(); ++si) {
       const Sub &sb = subs[si];
       const int64_t b0 = gsubs[si].bucket_off;
@@ -713,14 +910,14 @@ pipnn_status pipnn_partition_replica(pipnn_index *idx, int32_t replica, int64_t 
         const int64_t sz = bstart[(size_t)(b0 + t + 1)] - st;
         if (sz == 0 || sz < P.c_min) continue;
         if (sz <= P.c_max) {
-          leaves.push_back({Gp + st, sz, nullptr, 0});
+          lv.push_back({Gp + st, sz, 0});
         } else if (sz == sb.cnt) {
           const int64_t q = (sz + P.c_max - 1) / P.c_max;
           const int64_t base = sz / q, extra = sz % q;
           int64_t pos = 0;
           for (int64_t c = 0; c < q; ++c) {
             const int64_t len = base + (c < extra ? 1 : 0);
-            leaves.push_back({Gp + st + pos, len, nullptr, 0});
+            lv.push_back({Gp + st + pos, len, 0});
             pos += len;
           }
         } else {
@@ -731,34 +928,32 @@ pipnn_status pipnn_partition_replica(pipnn_index *idx, int32_t replica, int64_t 
       }
     }
     const int n_groups = (int)grp_off.size();
+    std::vector<int32_t> grp_size((size_t)n_groups);
     if (n_groups > 0) {
       grp_first.push_back((int32_t)seg_ptr.size());
-      DevBuf *gout, *gptr, *glen, *gfirst, *goff, *gsz;
-      HIPCHK(fresh((size_t)gout_total * 4, gout));
-      HIPCHK(fresh(seg_ptr.size() * sizeof(void *), gptr));
-      HIPCHK(fresh(seg_len.size() * 4, glen));
-      HIPCHK(fresh(grp_first.size() * 4, gfirst));
-      HIPCHK(fresh(grp_off.size() * 8, goff));
-      HIPCHK(fresh((size_t)n_groups * 4, gsz));
-      HIPCHK(hipMemcpyAsync(gptr->p, seg_ptr.data(), seg_ptr.size() * sizeof(void *),
-                            hipMemcpyHostToDevice, s));
-      HIPCHK(hipMemcpyAsync(glen->p, seg_len.data(), seg_len.size() * 4, hipMemcpyHostToDevice, s));
-      HIPCHK(hipMemcpyAsync(gfirst->p, grp_first.data(), grp_first.size() * 4,
-                            hipMemcpyHostToDevice, s));
-      HIPCHK(hipMemcpyAsync(goff->p, grp_off.data(), grp_off.size() * 8, hipMemcpyHostToDevice, s));
-      HIPCHK(launch_merge_dedup(gptr->as<const uint32_t *>(), glen->as<int32_t>(),
-                                gfirst->as<int32_t>(), n_groups, max_sum, gout->as<uint32_t>(),
-                                goff->as<int64_t>(), gsz->as<int32_t>(), s));
+      HIPCHK(I.p_gout.ensure((size_t)gout_total * 4));
+      HIPCHK(upload(I.p_seg, seg_ptr, s));
+      HIPCHK(upload(I.p_seglen, seg_len, s));
+      HIPCHK(upload(I.p_segfirst, grp_first, s));
+      HIPCHK(upload(I.p_segoff, grp_off, s));
+      HIPCHK(I.p_gsize.ensure((size_t)n_groups * 4));
+      HIPCHK(launch_merge_dedup(I.p_seg.as<const uint32_t *>(), I.p_seglen.as<int32_t>(),
+                                I.p_segfirst.as<int32_t>(), n_groups, max_sum,
+                                I.p_gout.as<uint32_t>(), I.p_segoff.as<int64_t>(),
+                                I.p_gsize.as<int32_t>(), s));
       for (int g = 0; g < n_groups; ++g)
-        leaves.push_back({gout->as<uint32_t>() + grp_off[(size_t)g], -1, gsz->as<int32_t>(), g});
-      gsize_arrays.push_back({gsz->as<int32_t>(), n_groups});
-      // host-side copies of the segment tables must live until the copies finish
+        lv.push_back({I.p_gout.as<uint32_t>() + grp_off[(size_t)g], -1, g});
+      // the merged sizes (and the host tables' copies have finished)
+      HIPCHK(hipMemcpyAsync(grp_size.data(), I.p_gsize.p, (size_t)n_groups * 4,
+                            hipMemcpyDeviceToHost, s));
       HIPCHK(hipStreamSynchronize(s));
     }
+    pipnn_status st = emit(lv, grp_size);
+    if (st != PIPNN_OK) return st;
     // --- next level: recursing buckets, contiguous
     if (!next.empty()) {
-      DevBuf *An, *sp, *so, *sl;
-      HIPCHK(fresh((size_t)next_off * 4, An));
+      DevBuf &An = I.p_mem[cur ^ 1];
+      HIPCHK(An.ensure((size_t)next_off * 4));
       std::vector<const uint32_t *> src;
       std::vector<int64_t> doff;
       std::vector<int32_t> lens;
@@ -769,60 +964,29 @@ pipnn_status pipnn_partition_replica(pipnn_index *idx, int32_t replica, int64_t 
         lens.push_back((int32_t)rs.second);
         o += rs.second;
       }
-      HIPCHK(fresh(src.size() * sizeof(void *), sp));
-      HIPCHK(fresh(doff.size() * 8, so));
-      HIPCHK(fresh(lens.size() * 4, sl));
-      HIPCHK(hipMemcpyAsync(sp->p, src.data(), src.size() * sizeof(void *), hipMemcpyHostToDevice,
-                            s));
-      HIPCHK(hipMemcpyAsync(so->p, doff.data(), doff.size() * 8, hipMemcpyHostToDevice, s));
-      HIPCHK(hipMemcpyAsync(sl->p, lens.data(), lens.size() * 4, hipMemcpyHostToDevice, s));
-      HIPCHK(launch_copy_segments(sp->as<const uint32_t *>(), so->as<int64_t>(), sl->as<int32_t>(),
-                                  (int32_t)src.size(), An->as<uint32_t>(), s));
+      HIPCHK(upload(I.p_rsrc, src, s));
+      HIPCHK(upload(I.p_roff, doff, s));
+      HIPCHK(upload(I.p_rlen, lens, s));
+      HIPCHK(launch_copy_segments(I.p_rsrc.as<const uint32_t *>(), I.p_roff.as<int64_t>(),
+                                  I.p_rlen.as<int32_t>(), (int32_t)src.size(),
+                                  An.as<uint32_t>(), s));
       HIPCHK(hipStreamSynchronize(s));
-      A = An;
+      cur ^= 1;
     }
     subs.swap(next);
   }
 
-  // --- sizes of merged leaves, then the final CSR
-  std::unordered_map<const int32_t *, std::vector<int32_t>> gsz_host;
-  for (auto &ga : gsize_arrays) {
-    std::vector<int32_t> v((size_t)ga.second);
-    HIPCHK(hipMemcpyAsync(v.data(), ga.first, v.size() * 4, hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    gsz_host[ga.first] = std::move(v);
-  }
-  std::vector<int64_t> offs(leaves.size() + 1, 0);
-  std::vector<const uint32_t *> srcs;
-  std::vector<int32_t> lens;
-  for (size_t i = 0; i < leaves.size(); ++i) {
-    int64_t len = leaves[i].len;
-    if (len < 0) len = gsz_host[leaves[i].size_dev][(size_t)leaves[i].size_idx];
-    offs[i + 1] = offs[i] + len;
-    srcs.push_back(leaves[i].src);
-    lens.push_back((int32_t)len);
-  }
-  *h_n_leaves = (int64_t)leaves.size();
+  // --- the CSR offsets
+  const int64_t n_leaves = (int64_t)offs.size() - 1;
+  *h_n_leaves = n_leaves;
   *h_n_members = offs.back();
-  if ((int64_t)leaves.size() > cap_leaves || offs.back() > cap_members)
+  if (n_leaves > cap_leaves || offs.back() > cap_members)
     return fail(PIPNN_EOVERFLOW, "partition needs %lld leaves and %lld members",
-                (long long)leaves.size(), (long long)offs.back());
+                (long long)n_leaves, (long long)offs.back());
   if (!d_leaf_offsets || !d_leaf_members) return fail(PIPNN_EINVAL, "NULL output");
-  {
-    DevBuf *sp, *so, *sl;
-    HIPCHK(fresh(srcs.size() * sizeof(void *), sp));
-    HIPCHK(fresh(offs.size() * 8, so));
-    HIPCHK(fresh(lens.size() * 4, sl));
-    HIPCHK(hipMemcpyAsync(sp->p, srcs.data(), srcs.size() * sizeof(void *), hipMemcpyHostToDevice,
-                          s));
-    HIPCHK(hipMemcpyAsync(so->p, offs.data(), offs.size() * 8, hipMemcpyHostToDevice, s));
-    HIPCHK(hipMemcpyAsync(sl->p, lens.data(), lens.size() * 4, hipMemcpyHostToDevice, s));
-    HIPCHK(launch_copy_segments(sp->as<const uint32_t *>(), so->as<int64_t>(), sl->as<int32_t>(),
-                                (int32_t)srcs.size(), d_leaf_members, s));
-    HIPCHK(hipMemcpyAsync(d_leaf_offsets, offs.data(), offs.size() * 8, hipMemcpyHostToDevice, s));
-    HIPCHK(hipStreamSynchronize(s));
-  }
-  I.stats.n_leaves = (int64_t)leaves.size();
+  HIPCHK(hipMemcpyAsync(d_leaf_offsets, offs.data(), offs.size() * 8, hipMemcpyHostToDevice, s));
+  HIPCHK(hipStreamSynchronize(s));
+  I.stats.n_leaves = n_leaves;
   I.stats.n_members = offs.back();
   I.stats.leader_dists = leader_dists;
   I.stats.levels = levels;
@@ -870,14 +1034,14 @@ static bool gemm_is_direct(const Index &I) {
          (I.p.gemm_prec == PIPNN_PREC_BF16 && I.x_dtype == PIPNN_DTYPE_BF16);
 }
 
-// Work list of the pick on leaves [l0, l1) (rows indexed from offs[l0]),
-// uploaded into jobs_buf / items_buf.
-pipnn_status plan_pick(Index &I, const std::vector<int64_t> &offs, int64_t l0, int64_t l1,
-                       DevBuf &jobs_buf, DevBuf &items_buf, int32_t &n_items, int32_t &max_cols,
-                       int64_t &pairs, hipStream_t s) {
+// Work list of the pick on leaves [l0, l1) (rows indexed from offs[l0]).
+void pick_lists(const Index &I, const std::vector<int64_t> &offs, int64_t l0, int64_t l1,
+                std::vector<KnnJob> &jobs, std::vector<KnnItem> &items, int32_t &max_cols,
+                int64_t &pairs) {
   const pipnn_params &P = I.p;
   const int ksel = P.rescore_mult ? P.rescore_mult * P.k : P.k;
-  std::vector<KnnJob> jobs;
+  jobs.clear();
+  items.clear();
   max_cols = 0;
   pairs = 0;
   const int64_t base = offs[(size_t)l0];
@@ -896,12 +1060,20 @@ pipnn_status plan_pick(Index &I, const std::vector<int64_t> &offs, int64_t l0, i
     max_cols = std::max<int32_t>(max_cols, (int32_t)sz);
     pairs += sz * sz;
   }
-  n_items = 0;
+  if (!jobs.empty()) items = plan_items(jobs, 32 * I.leaf_nw);
+}
+
+// The same, uploaded into jobs_buf / items_buf.
+pipnn_status plan_pick(Index &I, const std::vector<int64_t> &offs, int64_t l0, int64_t l1,
+                       DevBuf &jobs_buf, DevBuf &items_buf, int32_t &n_items, int32_t &max_cols,
+                       int64_t &pairs, hipStream_t s) {
+  std::vector<KnnJob> jobs;
+  std::vector<KnnItem> items;
+  pick_lists(I, offs, l0, l1, jobs, items, max_cols, pairs);
+  n_items = (int32_t)items.size();
   if (jobs.empty()) return PIPNN_OK;
-  std::vector<KnnItem> items = plan_items(jobs, 32 * I.leaf_nw);
   HIPCHK(upload(jobs_buf, jobs, s));
   HIPCHK(upload(items_buf, items, s));
-  n_items = (int32_t)items.size();
   return PIPNN_OK;
 }
 
@@ -1016,7 +1188,7 @@ pipnn_status bin_and_merge(Index &I, bool from_picks, const uint32_t *a, const u
 // (rows x largest leaf x 4 B) fit 1 GiB.
 std::vector<std::pair<int64_t, int64_t>> a2a_batches(const std::vector<int64_t> &offs,
                                                      int64_t l0, int64_t l1) {
-  const int64_t budget = (int64_t)1 << 28;  // floats
+  const int64_t budget = kA2aBudgetFloats;
   std::vector<std::pair<int64_t, int64_t>> out;
   int64_t b0 = l0, rows = 0, wide = 1;
   for (int64_t l = l0; l < l1; ++l) {
@@ -1175,10 +1347,12 @@ pipnn_status check_ids(Index &I, const uint32_t *ids, int64_t cnt, hipStream_t s
 
 }  // namespace
 
-// Batches of leaves bounded in picks, so that scratch stays bounded.
-static std::vector<std::pair<int64_t, int64_t>> leaf_batches(const std::vector<int64_t> &offs,
+// Batches of leaves of at most I.batch_rows rows (a larger leaf is a batch
+// of its own), so that the picks and records of a batch fit their scratch.
+static std::vector<std::pair<int64_t, int64_t>> leaf_batches(const Index &I,
+                                                             const std::vector<int64_t> &offs,
                                                              int64_t n_leaves) {
-  const int64_t max_rows = (int64_t)1 << 25;
+  const int64_t max_rows = I.batch_rows;
   std::vector<std::pair<int64_t, int64_t>> out;
   int64_t l0 = 0;
   while (l0 < n_leaves) {
@@ -1196,6 +1370,15 @@ static pipnn_status reserve_build(Index &I, const std::vector<int64_t> &offs,
                                   const std::vector<std::pair<int64_t, int64_t>> &batches,
                                   int64_t n_leaves) {
   const int k = I.p.k;
+  if (I.ws_mode) {
+    // the layout holds the leaves of one partition of the index's points
+    const int64_t F = std::max<int64_t>(I.n, members_bound(I.p, I.n));
+    const int64_t cnt = offs[(size_t)n_leaves] - offs[0];
+    if (cnt > F || n_leaves > F)
+      return fail(PIPNN_ENOMEM, "an index on a workspace takes leaves of at most %lld members "
+                  "(n times the product of the fanouts); these have %lld in %lld leaves",
+                  (long long)F, (long long)cnt, (long long)n_leaves);
+  }
   int64_t max_rows = 1;
   for (auto &b : batches)
     max_rows = std::max<int64_t>(max_rows, offs[(size_t)b.second] - offs[(size_t)b.first]);
@@ -1268,20 +1451,28 @@ pipnn_status pipnn_plan_leaves(pipnn_index *idx, const int64_t *d_leaf_offsets,
   st = check_ids(I, d_leaf_members + P.offs[0], P.offs[(size_t)n_leaves] - P.offs[0], s,
                  "plan_leaves");
   if (st != PIPNN_OK) return st;
-  auto batches = leaf_batches(P.offs, n_leaves);
+  auto batches = leaf_batches(I, P.offs, n_leaves);
   st = reserve_build(I, P.offs, batches, n_leaves);
   if (st != PIPNN_OK) return st;
-  while (P.batches.size() < batches.size()) P.batches.emplace_back();
+  // every batch's work lists, one after another
+  P.batches.assign(batches.size(), Index::PlanBatch{});
+  std::vector<KnnJob> all_jobs, jobs;
+  std::vector<KnnItem> all_items, items;
   for (size_t i = 0; i < batches.size(); ++i) {
     Index::PlanBatch &B = P.batches[i];
     B.l0 = batches[i].first;
     B.l1 = batches[i].second;
     B.rows = P.offs[(size_t)B.l1] - P.offs[(size_t)B.l0];
-    st = plan_pick(I, P.offs, B.l0, B.l1, B.jobs, B.items, B.n_items, B.max_cols, B.pairs, s);
-    if (st != PIPNN_OK) return st;
+    pick_lists(I, P.offs, B.l0, B.l1, jobs, items, B.max_cols, B.pairs);
+    B.job_off = (int64_t)all_jobs.size();
+    B.item_off = (int64_t)all_items.size();
+    B.n_items = (int32_t)items.size();
+    all_jobs.insert(all_jobs.end(), jobs.begin(), jobs.end());
+    all_items.insert(all_items.end(), items.begin(), items.end());
   }
+  HIPCHK(upload(P.jobs, all_jobs, s));
+  HIPCHK(upload(P.items, all_items, s));
   HIPCHK(hipStreamSynchronize(s));  // the host work lists may be released now
-  P.batches.resize(batches.size());
   P.d_off = d_leaf_offsets;
   P.d_mem = d_leaf_members;
   P.n_leaves = n_leaves;
@@ -1315,15 +1506,23 @@ pipnn_status pipnn_build_leaves(pipnn_index *idx, const int64_t *d_leaf_offsets,
     const int64_t rows = offs[(size_t)n_leaves] - offs[0];
     st = check_ids(I, d_leaf_members + offs[0], rows, s, "build_leaves");
     if (st != PIPNN_OK) return st;
-    const std::vector<std::pair<int64_t, int64_t>> all{{0, n_leaves}};
-    st = reserve_build(I, offs, all, n_leaves);
+    const auto batches = leaf_batches(I, offs, n_leaves);
+    st = reserve_build(I, offs, batches, n_leaves);
     if (st != PIPNN_OK) return st;
-    st = a2a_pick_all(I, offs, 0, n_leaves, d_leaf_offsets, d_leaf_members,
-                      I.s_picks_c.as<uint32_t>(), I.s_picks_d.as<float>(), s);
-    if (st != PIPNN_OK) return st;
-    st = bin_and_merge(I, true, d_leaf_members + offs[0], I.s_picks_c.as<uint32_t>(),
-                       I.s_picks_d.as<float>(), rows, k, d_reservoirs, s, false);
-    if (st != PIPNN_OK) return st;
+    for (size_t i = 0; i < batches.size(); ++i) {
+      const int64_t l0 = batches[i].first, l1 = batches[i].second;
+      st = a2a_pick_all(I, offs, l0, l1, d_leaf_offsets, d_leaf_members,
+                        I.s_picks_c.as<uint32_t>(), I.s_picks_d.as<float>(), s);
+      if (st != PIPNN_OK) return st;
+      st = bin_and_merge(I, true, d_leaf_members + offs[(size_t)l0], I.s_picks_c.as<uint32_t>(),
+                         I.s_picks_d.as<float>(), offs[(size_t)l1] - offs[(size_t)l0], k,
+                         d_reservoirs, s, false);
+      if (st != PIPNN_OK) return st;
+      if (i + 1 < batches.size()) {
+        st = finish_bins(I, s, "build_leaves");
+        if (st != PIPNN_OK) return st;
+      }
+    }
     st = leaf_order(I, d_leaf_members + offs[0], rows, s);
     if (st != PIPNN_OK) return st;
     st = keep_leaf_table(I, d_leaf_offsets, d_leaf_members, offs, n_leaves, s);
@@ -1345,8 +1544,8 @@ pipnn_status pipnn_build_leaves(pipnn_index *idx, const int64_t *d_leaf_offsets,
     for (size_t i = 0; i < P.batches.size(); ++i) {
       const Index::PlanBatch &B = P.batches[i];
       const bool local = B.max_cols <= kLeafBinMaxRows;
-      st = launch_pick(I, B.jobs.as<KnnJob>(), B.items.as<KnnItem>(), B.n_items, B.max_cols,
-                       B.rows, d_leaf_members, I.s_picks_c.as<uint32_t>(),
+      st = launch_pick(I, P.jobs.as<KnnJob>() + B.job_off, P.items.as<KnnItem>() + B.item_off,
+                       B.n_items, B.max_cols, B.rows, d_leaf_members, I.s_picks_c.as<uint32_t>(),
                        I.s_picks_d.as<float>(), s, local);
       if (st != PIPNN_OK) return st;
       if (!capturing) I.stats.leaf_pairs += B.pairs;
@@ -1378,7 +1577,7 @@ pipnn_status pipnn_build_leaves(pipnn_index *idx, const int64_t *d_leaf_offsets,
   I.stats.records = 0;
   st = check_ids(I, d_leaf_members + offs[0], offs[(size_t)n_leaves] - offs[0], s, "build_leaves");
   if (st != PIPNN_OK) return st;
-  auto batches = leaf_batches(offs, n_leaves);
+  auto batches = leaf_batches(I, offs, n_leaves);
   st = reserve_build(I, offs, batches, n_leaves);
   if (st != PIPNN_OK) return st;
   for (size_t i = 0; i < batches.size(); ++i) {
@@ -1415,20 +1614,19 @@ pipnn_status pipnn_build_leaves(pipnn_index *idx, const int64_t *d_leaf_offsets,
 // Grow a buffer to `bytes`, keeping its first `keep` bytes.
 static hipError_t grow_keep(DevBuf &b, size_t bytes, size_t keep, hipStream_t s) {
   if (b.p && b.cap >= bytes) return hipSuccess;
-  void *np = nullptr;
-  hipError_t e = hipMalloc(&np, std::max<size_t>(bytes, 256));
+  DevBuf nb;
+  hipError_t e = nb.ensure(bytes);
   if (e != hipSuccess) return e;
   if (b.p && keep) {
-    if ((e = hipMemcpyAsync(np, b.p, std::min(keep, b.cap), hipMemcpyDeviceToDevice, s)) !=
+    if ((e = hipMemcpyAsync(nb.p, b.p, std::min(keep, b.cap), hipMemcpyDeviceToDevice, s)) !=
             hipSuccess ||
         (e = hipStreamSynchronize(s)) != hipSuccess) {
-      (void)hipFree(np);
+      nb.release();
       return e;
     }
   }
   b.release();
-  b.p = np;
-  b.cap = std::max<size_t>(bytes, 256);
+  b = nb;
   return hipSuccess;
 }
 
@@ -1451,6 +1649,9 @@ pipnn_status pipnn_reserve(pipnn_index *idx, int64_t n_cap, const void *d_X,
     I.X = d_X;
   }
   if (n_cap <= I.cap) return PIPNN_OK;
+  if (I.ws_mode)
+    return fail(PIPNN_ESTATE, "an index on a caller's workspace holds the %lld points it was "
+                "created with", (long long)I.cap);
   const size_t n = (size_t)I.n, c = (size_t)n_cap, d = (size_t)I.d;
   // scratch indexed by point id, sized for the capacity once so that
   // insertions up to it allocate none of it
@@ -1478,13 +1679,20 @@ pipnn_status pipnn_reserve(pipnn_index *idx, int64_t n_cap, const void *d_X,
 
 pipnn_status pipnn_insert(pipnn_index *idx, int64_t n_new, const int32_t *d_group,
                           uint64_t *d_reservoirs, uint32_t *d_graph, uint32_t *d_degree,
-                          pipnn_stream_t stream) {
+                          uint64_t epoch, pipnn_stream_t stream) {
   GUARD_BEGIN
   if (!idx || !d_reservoirs || !d_graph || !d_degree || n_new < 0)
     return fail(PIPNN_EINVAL, "invalid argument");
   Index &I = *reinterpret_cast<Index *>(idx);
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  if (n_new == 0) return PIPNN_OK;
+  const uint64_t epoch0 = __atomic_load_n(&I.epoch, __ATOMIC_ACQUIRE);
+  if (epoch <= epoch0)
+    return fail(PIPNN_EINVAL, "epoch %llu does not follow the index's epoch %llu",
+                (unsigned long long)epoch, (unsigned long long)epoch0);
+  if (n_new == 0) {
+    __atomic_store_n(&I.epoch, epoch, __ATOMIC_RELEASE);
+    return PIPNN_OK;
+  }
   if (stream_capturing(s)) return fail(PIPNN_ESTATE, "insert cannot run under capture");
   if (I.lt_n_leaves < 1) return fail(PIPNN_ESTATE, "insert needs the leaves of a build first");
   if (I.p.leaf_picker != PIPNN_PICKER_KNN)
@@ -1685,6 +1893,7 @@ pipnn_status pipnn_insert(pipnn_index *idx, int64_t n_new, const int32_t *d_grou
                             s));
   st = finish_bins(I, s, "insert");
   rollback.done = st == PIPNN_OK;
+  if (rollback.done) __atomic_store_n(&I.epoch, epoch, __ATOMIC_RELEASE);
   return st;
   GUARD_END
 }
@@ -1731,7 +1940,7 @@ pipnn_status pipnn_autotune(pipnn_index *idx, const int64_t *d_leaf_offsets,
   st = check_ids(I, d_leaf_members + offs[0], offs[(size_t)n_leaves] - offs[0], s, "autotune");
   if (st != PIPNN_OK) return st;
   // the first batch of leaves is the sample
-  auto batches = leaf_batches(offs, n_leaves);
+  auto batches = leaf_batches(I, offs, n_leaves);
   const int64_t l0 = batches[0].first, l1 = batches[0].second;
   const int64_t rows = offs[(size_t)l1] - offs[(size_t)l0];
   HIPCHK(I.s_picks_c.ensure((size_t)std::max<int64_t>(rows, 1) * I.p.k * 4));
@@ -1803,10 +2012,16 @@ pipnn_status pipnn_leaf_pick(pipnn_index *idx, const int64_t *d_leaf_offsets,
   if (offs[0] != 0) return fail(PIPNN_EINVAL, "offsets[0] must be 0");
   st = check_ids(I, d_leaf_members, offs[(size_t)n_leaves], s, "leaf_pick");
   if (st != PIPNN_OK) return st;
-  if (I.p.leaf_picker == PIPNN_PICKER_ALL_TO_ALL)
-    return a2a_pick_all(I, offs, 0, n_leaves, d_leaf_offsets, d_leaf_members, d_out_cand,
-                        d_out_dist, s);
-  return run_pick(I, offs, 0, n_leaves, d_leaf_members, d_out_cand, d_out_dist, s);
+  for (auto &b : leaf_batches(I, offs, n_leaves)) {
+    const int64_t o = offs[(size_t)b.first] * I.p.k;
+    st = I.p.leaf_picker == PIPNN_PICKER_ALL_TO_ALL
+             ? a2a_pick_all(I, offs, b.first, b.second, d_leaf_offsets, d_leaf_members,
+                            d_out_cand + o, d_out_dist + o, s)
+             : run_pick(I, offs, b.first, b.second, d_leaf_members, d_out_cand + o,
+                        d_out_dist + o, s);
+    if (st != PIPNN_OK) return st;
+  }
+  return PIPNN_OK;
   GUARD_END
 }
 
@@ -1876,9 +2091,18 @@ pipnn_status pipnn_hashprune_insert(pipnn_index *idx, const uint32_t *d_dst,
   Index &I = *reinterpret_cast<Index *>(idx);
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   I.stats.records = 0;
-  pipnn_status st = bin_and_merge(I, false, d_dst, d_cand, d_dist, n_records, 1, d_reservoirs, s);
-  if (st != PIPNN_OK) return st;
-  return finish_bins(I, s, "hashprune_insert");
+  // on a workspace, in chunks that fit the binned-record slice (HashPrune's
+  // result does not depend on the order or grouping of its records)
+  const int64_t chunk = I.ws_mode ? std::max<int64_t>(1, (int64_t)(I.s_bins.lim / 8)) : n_records;
+  for (int64_t r0 = 0; r0 < n_records; r0 += chunk) {
+    const int64_t cnt = std::min(chunk, n_records - r0);
+    pipnn_status st = bin_and_merge(I, false, d_dst + r0, d_cand + r0, d_dist + r0, cnt, 1,
+                                    d_reservoirs, s);
+    if (st != PIPNN_OK) return st;
+    st = finish_bins(I, s, "hashprune_insert");
+    if (st != PIPNN_OK) return st;
+  }
+  return PIPNN_OK;
   GUARD_END
 }
 
@@ -1987,20 +2211,23 @@ pipnn_status pipnn_search(pipnn_index *idx, const uint32_t *d_graph, const void 
   if (q_dtype != PIPNN_DTYPE_F32 && q_dtype != PIPNN_DTYPE_F16 && q_dtype != PIPNN_DTYPE_BF16)
     return fail(PIPNN_EINVAL, "unknown q_dtype");
   if (nq == 0) return PIPNN_OK;
-  const float *Q = reinterpret_cast<const float *>(d_Q);
-  if (q_dtype != PIPNN_DTYPE_F32) {
-    HIPCHK(I.q_conv.ensure((size_t)nq * I.d * 4));
-    HIPCHK(launch_to_f32(d_Q, q_dtype, I.q_conv.as<float>(), nq * (int64_t)I.d, s));
-    Q = I.q_conv.as<float>();
-  }
+  // batches of queries whose seen bitmaps (n bits each) fit the budget; a
+  // 16-bit batch is widened to float32 first
   const int64_t words = (n + 31) / 32;
-  const int64_t budget_words = (int64_t)1 << 26;  // 256 MiB of seen bitmaps
-  const int64_t batch = std::max<int64_t>(1, std::min<int64_t>(nq, budget_words / words));
+  const int64_t batch = std::min<int64_t>(nq, query_batch(n));
   HIPCHK(I.q_seen.ensure((size_t)batch * words * 4));
+  if (q_dtype != PIPNN_DTYPE_F32) HIPCHK(I.q_conv.ensure((size_t)batch * I.d * 4));
+  const size_t qrow = (size_t)I.d * (q_dtype == PIPNN_DTYPE_F32 ? 4 : 2);
   for (int64_t q0 = 0; q0 < nq; q0 += batch) {
     const int64_t nb = std::min(batch, nq - q0);
+    const void *qb = static_cast<const char *>(d_Q) + (size_t)q0 * qrow;
+    const float *Q = reinterpret_cast<const float *>(qb);
+    if (q_dtype != PIPNN_DTYPE_F32) {
+      HIPCHK(launch_to_f32(qb, q_dtype, I.q_conv.as<float>(), nb * (int64_t)I.d, s));
+      Q = I.q_conv.as<float>();
+    }
     HIPCHK(hipMemsetAsync(I.q_seen.p, 0, (size_t)nb * words * 4, s));
-    HIPCHK(launch_search(I, n, d_graph, Q + q0 * I.d, nb, k, L, start, d_out_ids + q0 * k,
+    HIPCHK(launch_search(I, n, d_graph, Q, nb, k, L, start, d_out_ids + q0 * k,
                          d_out_dist ? d_out_dist + q0 * k : nullptr,
                          d_out_cmps ? d_out_cmps + q0 : nullptr, I.q_seen.as<uint32_t>(), words,
                          s));
@@ -2020,10 +2247,10 @@ pipnn_status pipnn_knn_graph(pipnn_index *idx, const uint32_t *d_graph, int32_t 
   const int64_t n = I.n;
   if ((int64_t)start >= n) return fail(PIPNN_EINVAL, "start >= n");
   const int64_t words = (n + 31) / 32;
-  const int64_t budget_words = (int64_t)1 << 26;  // 256 MiB of seen bitmaps
-  const int64_t chunk =
-      std::max<int64_t>(1, std::min<int64_t>({n, budget_words / words, (int64_t)1 << 16}));
   const int32_t k1 = k + 1;
+  int64_t chunk = std::min<int64_t>(n, query_batch(n));
+  // on a workspace the result slices hold a chunk of k + 1 <= 65 results
+  if (I.ws_mode) chunk = std::max<int64_t>(1, std::min<int64_t>(chunk, I.g_ids.lim / (k1 * 4)));
   HIPCHK(I.q_seen.ensure((size_t)chunk * words * 4));
   HIPCHK(I.g_ids.ensure((size_t)chunk * k1 * 4));
   HIPCHK(I.g_dist.ensure((size_t)chunk * k1 * 4));
@@ -2094,6 +2321,10 @@ pipnn_status pipnn_get_stats(pipnn_index *idx, pipnn_stats *h_out) {
   st.ms_bin = I.phase_ms[kPhBin];
   st.ms_merge = I.phase_ms[kPhMerge];
   st.ms_robustprune = I.phase_ms[kPhRobustPrune];
+  st.epoch = __atomic_load_n(&I.epoch, __ATOMIC_ACQUIRE);
+  st.n_points = __atomic_load_n(&I.n, __ATOMIC_ACQUIRE);
+  st.workspace_bytes = (int64_t)I.ws_bytes;
+  st.batch_rows = I.batch_rows;
   *h_out = st;
   return PIPNN_OK;
   GUARD_END

@@ -13,9 +13,16 @@
 namespace pipnn {
 
 // A device buffer owned by the index; grows on demand, never shrinks.
+// On an index created over a caller's workspace the buffer is `fixed`: its
+// slice of the workspace (ws_p, lim bytes) is set at creation, ensure()
+// hands it out on first use and fails with hipErrorOutOfMemory for a
+// request above lim; nothing is ever allocated.
 struct DevBuf {
   void *p = nullptr;
   size_t cap = 0;
+  void *ws_p = nullptr;  // the fixed slice (fixed buffers)
+  size_t lim = 0;        // its size in bytes
+  bool fixed = false;
   hipError_t ensure(size_t bytes);
   void release();
   template <class T> T *as() const { return reinterpret_cast<T *>(p); }
@@ -23,6 +30,10 @@ struct DevBuf {
 
 struct Index {
   pipnn_params p;
+  bool ws_mode = false;      // every DevBuf is a fixed slice of the caller's workspace
+  size_t ws_bytes = 0;       // the layout's total (ws_mode)
+  int64_t batch_rows = (int64_t)1 << 25;  // leaf rows per pick + binning batch
+  uint64_t epoch = 0;        // the caller's label of the last committed insertion
   const void *X = nullptr;  // n x d, caller-owned
   int64_t n = 0;
   int32_t d = 0;
@@ -55,8 +66,13 @@ struct Index {
 
   // scratch reused across calls
   DevBuf s_jobs, s_items, s_picks_c, s_picks_d, s_cnt, s_off, s_bins, s_tmp0, s_tmp1;
-  std::vector<DevBuf> levels;   // partition level member arrays
-  DevBuf p_asg, p_leaders, p_cm, p_bstart, p_groups, p_gout, p_gsize, p_copy;
+  // partition (one level at a time): the members of the level's
+  // subproblems (ping-pong), their leader assignments, the assignments
+  // grouped by bucket, the merged small buckets and their sizes, and the
+  // host-built tables of the merge, recursion and leaf-output copies
+  DevBuf p_mem[2], p_asg, p_G, p_gout, p_gsize;
+  DevBuf p_leaders, p_cm, p_bstart, p_groups;
+  DevBuf p_seg, p_seglen, p_segfirst, p_segoff, p_rsrc, p_roff, p_rlen, p_esrc, p_eoff, p_elen;
   DevBuf rp_order;              // RobustPrune processing order (from the last leaves)
   DevBuf s_counter;             // per-XCD work counters of the persistent leaf schedule
   // the leaves of the last build, kept for insertion: CSR rebased to 0 (a
@@ -80,8 +96,8 @@ struct Index {
   // captured in a graph.
   struct PlanBatch {
     int64_t l0 = 0, l1 = 0, rows = 0, pairs = 0;
+    int64_t job_off = 0, item_off = 0;  // the batch's work lists in jobs / items
     int32_t n_items = 0, max_cols = 0;
-    DevBuf jobs, items;
   };
   struct LeafPlan {
     const int64_t *d_off = nullptr;
@@ -89,12 +105,11 @@ struct Index {
     int64_t n_leaves = -1;
     int32_t nw = 0;
     std::vector<int64_t> offs;
-    std::deque<PlanBatch> batches;
+    std::vector<PlanBatch> batches;
+    DevBuf jobs, items;  // every batch's work lists, one after another
   } plan;
   DevBuf o_first, o_flag, o_pos, o_pos2, o_tmp;
   bool rp_order_valid = false;
-  std::deque<DevBuf> ppool;     // per-call partition buffers, reused across calls
-  size_t ppool_used = 0;
 
   // statistics and phase events
   pipnn_stats stats{};

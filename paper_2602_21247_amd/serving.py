@@ -259,7 +259,8 @@ class Server:
             with torch.cuda.stream(self.s_i):
                 self.X[n0:n0 + m].copy_(torch.from_numpy(P).to(self.X.dtype))
                 gd = torch.from_numpy(groups).cuda()
-                self.idx.insert(m, self.res, self.g, self.deg, gd)
+                # the snapshot this batch publishes is the next epoch
+                self.idx.insert(m, self.res, self.g, self.deg, gd, epoch=self.epoch + 1)
                 self.n = n0 + m
                 # publish into the spare copy once no query batch reads it
                 with self.lock:

@@ -51,6 +51,67 @@ def test_workspace_bytes(L):
     assert b1 > 0 and b2 > b1
     bad = pp.default_params(l_max=0)
     assert pp.workspace_bytes(bad, 100, 8) == 0
+    assert pp.workspace_bytes(p, 100, 8, x_dtype=7) == 0
+    assert pp.workspace_bytes(p, 1, 8) == 0
+
+
+def test_workspace_bytes_follow_the_batch_and_the_dtype(L):
+    """Slices are 256-byte multiples; smaller record batches need less, down
+    to the smallest batch (one leaf of 65535 rows); a 16-bit X adds its
+    float32 copy (n * d * 4 bytes); the all-to-all picker adds its matrices."""
+    p = pp.default_params()
+    n, d, k = 1_000_000, 128, p.k
+    whole = pp.workspace_bytes(p, n, d)
+    half = pp.workspace_bytes(p, n, d, max_batch_records=2 * k * 500_000)
+    smallest = pp.workspace_bytes(p, n, d, max_batch_records=1)
+    assert whole % 256 == 0 and half % 256 == 0 and smallest % 256 == 0
+    assert whole > half > smallest > 0
+    assert smallest == pp.workspace_bytes(p, n, d, max_batch_records=2 * k * 65535)
+    # a batch above a whole build is a whole build
+    assert whole == pp.workspace_bytes(p, n, d, max_batch_records=1 << 40)
+    # records scale the picks (2 x 4 B per pick) and the bins (2 x 8 B per pick)
+    rows = 500_000 - 65535
+    assert half - smallest >= rows * k * (8 + 16)
+    bf = pp.workspace_bytes(p, n, d, x_dtype=pp.DTYPE_BF16)
+    assert bf - whole == n * d * 4
+    a2a = pp.workspace_bytes(pp.default_params(leaf_picker=pp.PICKER_ALL_TO_ALL), n, d)
+    assert a2a - whole >= (1 << 28) * 4
+
+
+def _create(L, p, n, d, ws, ws_bytes, x=0x100000):
+    h = C.c_void_p()
+    st = L.pipnn_create(C.byref(p), C.c_void_p(x), n, d, 0, C.c_void_p(0x200000),
+                        C.c_void_p(ws), ws_bytes, None, C.byref(h))
+    return st, h
+
+
+@pytest.mark.parametrize("mbr", [1, 0])
+def test_create_refuses_a_workspace_one_page_short(L, mbr):
+    """The size check precedes any device call: a workspace one page (4 KiB)
+    below pipnn_workspace_bytes for the smallest batch gets ENOMEM; with a
+    whole-build size, one page less still fits a smaller batch (the check
+    then passes and creation goes on to the device, which is not made
+    here)."""
+    p = pp.default_params()
+    n, d = 1_000_000, 128
+    need = pp.workspace_bytes(p, n, d, max_batch_records=mbr)
+    if mbr == 1:
+        st, h = _create(L, p, n, d, 0x10000000, need - 4096)
+        assert st == -2 and not h.value
+        assert b"needs at least" in L.pipnn_last_error()
+    st, h = _create(L, p, n, d, 0x10000000, 255)
+    assert st == -2 and not h.value
+
+
+def test_create_checks_the_workspace_arguments(L):
+    p = pp.default_params()
+    need = pp.workspace_bytes(p, 1000, 128)
+    st, _ = _create(L, p, 1000, 128, 0, need)            # NULL with a size
+    assert st == -1
+    st, _ = _create(L, p, 1000, 128, 0x10000080, need)   # not 256-byte aligned
+    assert st == -1 and b"256-byte" in L.pipnn_last_error()
+    st, _ = _create(L, p, 1000, 128, 0x10000000, need, x=0x100004)  # float32 X not 16-B aligned
+    assert st == -1 and b"16-byte" in L.pipnn_last_error()
 
 
 @pytest.mark.parametrize("field,value", [("c_max", 1), ("k", 0), ("hash_bits", 17), ("l_max", 300),
@@ -59,7 +120,8 @@ def test_workspace_bytes(L):
 def test_create_rejects_bad_params(L, field, value):
     p = pp.default_params(**{field: value})
     h = C.c_void_p()
-    st = L.pipnn_create(C.byref(p), C.c_void_p(16), 100, 8, 0, C.c_void_p(16), None, C.byref(h))
+    st = L.pipnn_create(C.byref(p), C.c_void_p(16), 100, 8, 0, C.c_void_p(16), None, 0, None,
+                        C.byref(h))
     assert st == -1
     assert len(L.pipnn_last_error()) > 0
     assert not h.value
@@ -68,12 +130,13 @@ def test_create_rejects_bad_params(L, field, value):
 def test_create_rejects_bad_shapes(L):
     p = pp.default_params()
     h = C.c_void_p()
-    assert L.pipnn_create(C.byref(p), C.c_void_p(16), 1, 8, 0, C.c_void_p(16), None,
+    assert L.pipnn_create(C.byref(p), C.c_void_p(16), 1, 8, 0, C.c_void_p(16), None, 0, None,
                           C.byref(h)) == -1
-    assert L.pipnn_create(C.byref(p), C.c_void_p(16), 100, 0, 0, C.c_void_p(16), None,
+    assert L.pipnn_create(C.byref(p), C.c_void_p(16), 100, 0, 0, C.c_void_p(16), None, 0, None,
                           C.byref(h)) == -1
-    assert L.pipnn_create(C.byref(p), None, 100, 8, 0, C.c_void_p(16), None, C.byref(h)) == -1
-    assert L.pipnn_create(C.byref(p), C.c_void_p(16), 100, 8, 7, C.c_void_p(16), None,
+    assert L.pipnn_create(C.byref(p), None, 100, 8, 0, C.c_void_p(16), None, 0, None,
+                          C.byref(h)) == -1
+    assert L.pipnn_create(C.byref(p), C.c_void_p(16), 100, 8, 7, C.c_void_p(16), None, 0, None,
                           C.byref(h)) == -1
 
 
