@@ -834,10 +834,36 @@ hipError_t launch_leaf_order(const uint32_t *mem, int64_t cnt, int64_t n, uint32
 // caller). Each step visits the first unvisited entry, evaluates its
 // neighbours that were never seen, sorts them, and merges them into the
 // beam, which keeps its first L entries (Alg. 1).
+//
+// LDS is sized per launch for the beam width L, the degree bound R and the
+// dimension d (beam and merge buffer: 2 x 8 L bytes, visited flags 2 L,
+// sorted new keys 8 x pow2(R), the query 4 d), so that narrow beams keep
+// many queries resident per compute unit. A lane evaluates one neighbour:
+// with VEC its row is read as 16-byte vectors (d a multiple of 4, rows 16-byte
+// aligned); the products are summed in index order either way.
 constexpr int kMaxL = 1024;
 constexpr int kMaxR = 256;
 constexpr int kMaxQD = 1024;
 
+struct SearchLds {
+  int beam, tmp, vis, tvis, nw, qv, bytes;
+};
+static SearchLds search_lds(int L, int R, int d) {
+  int P = 2;
+  while (P < R) P <<= 1;
+  auto up = [](int b) { return (b + 15) & ~15; };
+  SearchLds o;
+  o.beam = 0;
+  o.tmp = o.beam + up(8 * L);
+  o.nw = o.tmp + up(8 * L);
+  o.qv = o.nw + up(8 * P);
+  o.vis = o.qv + up(4 * d);
+  o.tvis = o.vis + up(L);
+  o.bytes = o.tvis + up(L);
+  return o;
+}
+
+template <bool VEC>
 __global__ void __launch_bounds__(64) search_kernel(const float *__restrict__ X, int64_t n, int d,
                                                     int metric, const uint32_t *__restrict__ graph,
                                                     int R, const float *__restrict__ Q, int k,
@@ -846,13 +872,14 @@ __global__ void __launch_bounds__(64) search_kernel(const float *__restrict__ X,
                                                     float *__restrict__ out_dist,
                                                     uint32_t *__restrict__ out_cmps,
                                                     uint32_t *__restrict__ seen_bits,
-                                                    int64_t words_per_query) {
-  __shared__ uint64_t beam[kMaxL];
-  __shared__ uint64_t tmp[kMaxL];
-  __shared__ uint8_t vis[kMaxL];
-  __shared__ uint8_t tvis[kMaxL];
-  __shared__ uint64_t nw[kMaxR];
-  __shared__ float qv[kMaxQD];
+                                                    int64_t words_per_query, SearchLds lo) {
+  extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
+  uint64_t *beam = reinterpret_cast<uint64_t *>(smem + lo.beam);
+  uint64_t *tmp = reinterpret_cast<uint64_t *>(smem + lo.tmp);
+  uint8_t *vis = smem + lo.vis;
+  uint8_t *tvis = smem + lo.tvis;
+  uint64_t *nw = reinterpret_cast<uint64_t *>(smem + lo.nw);
+  float *qv = reinterpret_cast<float *>(smem + lo.qv);
   const int lane = threadIdx.x;
   const int64_t qi = blockIdx.x;
   const bool l2 = metric == PIPNN_METRIC_L2;
@@ -865,12 +892,30 @@ __global__ void __launch_bounds__(64) search_kernel(const float *__restrict__ X,
   auto qdist = [&](uint32_t u) {
     const float *xu = X + (int64_t)u * d;
     float s = 0.f;
-    for (int i = 0; i < d; ++i) {
-      if (l2) {
-        const float t = qv[i] - xu[i];
-        s = fmaf(t, t, s);
-      } else {
-        s = fmaf(qv[i], xu[i], s);
+    if constexpr (VEC) {
+      const float4 *xv = reinterpret_cast<const float4 *>(xu);
+      const float4 *qq = reinterpret_cast<const float4 *>(qv);
+#pragma unroll 4
+      for (int i = 0; i < d / 4; ++i) {
+        const float4 x = xv[i], c = qq[i];
+        if (l2) {
+          float t = c.x - x.x; s = fmaf(t, t, s);
+          t = c.y - x.y; s = fmaf(t, t, s);
+          t = c.z - x.z; s = fmaf(t, t, s);
+          t = c.w - x.w; s = fmaf(t, t, s);
+        } else {
+          s = fmaf(c.x, x.x, s); s = fmaf(c.y, x.y, s);
+          s = fmaf(c.z, x.z, s); s = fmaf(c.w, x.w, s);
+        }
+      }
+    } else {
+      for (int i = 0; i < d; ++i) {
+        if (l2) {
+          const float t = qv[i] - xu[i];
+          s = fmaf(t, t, s);
+        } else {
+          s = fmaf(qv[i], xu[i], s);
+        }
       }
     }
     return l2 ? s : -s;
@@ -933,12 +978,12 @@ __global__ void __launch_bounds__(64) search_kernel(const float *__restrict__ X,
     const int total = nb + nn < L ? nb + nn : L;
     for (int i = lane; i < nb; i += 64) {
       const uint64_t key = beam[i];
-      int lo = 0, hi = nn;
-      while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (nw[mid] < key) lo = mid + 1; else hi = mid;
+      int lo2 = 0, hi = nn;
+      while (lo2 < hi) {
+        const int mid = (lo2 + hi) >> 1;
+        if (nw[mid] < key) lo2 = mid + 1; else hi = mid;
       }
-      const int pos = i + lo;
+      const int pos = i + lo2;
       if (pos < total) {
         tmp[pos] = key;
         tvis[pos] = vis[i];
@@ -946,12 +991,12 @@ __global__ void __launch_bounds__(64) search_kernel(const float *__restrict__ X,
     }
     for (int j = lane; j < nn; j += 64) {
       const uint64_t key = nw[j];
-      int lo = 0, hi = nb;
-      while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (beam[mid] < key) lo = mid + 1; else hi = mid;
+      int lo2 = 0, hi = nb;
+      while (lo2 < hi) {
+        const int mid = (lo2 + hi) >> 1;
+        if (beam[mid] < key) lo2 = mid + 1; else hi = mid;
       }
-      const int pos = j + lo;
+      const int pos = j + lo2;
       if (pos < total) {
         tmp[pos] = key;
         tvis[pos] = 0;
@@ -978,11 +1023,19 @@ hipError_t launch_search(const Index &I, int64_t n, const uint32_t *graph, const
                          float *out_dist, uint32_t *out_cmps, uint32_t *visited_bits,
                          int64_t words_per_query, hipStream_t s) {
   if (nq == 0) return hipSuccess;
-  if (L > kMaxL || I.p.R > kMaxR || I.d > kMaxQD || words_per_query * 32 < n)
+  if (L < 1 || L > kMaxL || I.p.R > kMaxR || I.d > kMaxQD || words_per_query * 32 < n)
     return hipErrorInvalidValue;
-  hipLaunchKernelGGL(search_kernel, dim3((unsigned)nq), dim3(64), 0, s, I.xf(), n, I.d,
-                     I.p.metric, graph, I.p.R, Q, k, L, start, out_ids, out_dist, out_cmps,
-                     visited_bits, words_per_query);
+  const SearchLds lo = search_lds(L, I.p.R, I.d);
+  const float *X = I.xf();
+  const bool vec = I.d % 4 == 0 && (reinterpret_cast<uintptr_t>(X) & 15u) == 0;
+  if (vec)
+    hipLaunchKernelGGL(search_kernel<true>, dim3((unsigned)nq), dim3(64), (size_t)lo.bytes, s, X, n,
+                       I.d, I.p.metric, graph, I.p.R, Q, k, L, start, out_ids, out_dist, out_cmps,
+                       visited_bits, words_per_query, lo);
+  else
+    hipLaunchKernelGGL(search_kernel<false>, dim3((unsigned)nq), dim3(64), (size_t)lo.bytes, s, X,
+                       n, I.d, I.p.metric, graph, I.p.R, Q, k, L, start, out_ids, out_dist,
+                       out_cmps, visited_bits, words_per_query, lo);
   return hipGetLastError();
 }
 

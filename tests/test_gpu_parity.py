@@ -362,6 +362,28 @@ def test_full_build_bit_exact(exact_build):
     idx.close()
 
 
+@pytest.mark.parametrize("d", [37, 128])
+def test_search_any_width_bit_exact(d):
+    """BeamSearch (Alg. 1) on a built graph equals the oracle's on the same
+    graph bit for bit -- ids, distances and comparison counts -- with rows
+    read as 16-byte vectors (d = 128) or one value at a time (d = 37), at
+    beam widths whose LDS layouts differ."""
+    X = int_points(3000, d, seed=d)
+    H = pi.hyperplanes(12, d, seed=5, integer=True)
+    idx, off, mem, res, g, deg = pp.build(dev(X), dev(H), gpu_params())
+    Q = int_points(200, d, seed=d + 1)
+    start, _ = oracle.start_node(X)
+    G = u32(g)
+    for L in (10, 33, 100, 257):
+        ids, dist, cmps = idx.search(g, dev(Q), 10, L, start)
+        torch.cuda.synchronize()
+        oi, odd, oc = oracle.beam_search(X, G, Q, 10, L, start)
+        assert np.array_equal(u32(ids), oi), L
+        assert np.array_equal(u32(cmps), oc), L
+        assert np.array_equal(dist.cpu().numpy().astype(np.float64), odd), L
+    idx.close()
+
+
 def _drop_own(ids, dist, k):
     """Rows of k + 1 results of point i searched as a query: i's own id
     dropped (its first occurrence), else the last entry."""
