@@ -911,6 +911,7 @@ def main():
                    "alpha": w.alpha, "hash_bits": w.hash_bits, "gemm": gemm},
         "recall_at_10": main_form["recall_at_10"],
         "L_at_recall_0.95": main_form["L_at_recall_0.95"],
+        "search_qps_at_L": main_form["search_qps_at_L"],
         "recall_curve": main_form["recall_curve"],
         "leaf_gemm_tflops": achieved,
         "insert_p99_ms": insert_p99(serve),
