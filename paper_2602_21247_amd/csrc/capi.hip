@@ -145,6 +145,12 @@ bool valid_params(const pipnn_params *p, std::string &why) {
   return true;
 }
 
+// The same through the index's pinned staging (asynchronous; see HostStage).
+template <class T>
+hipError_t staged(Index &I, DevBuf &b, const std::vector<T> &v, hipStream_t s) {
+  return I.stage.put(b, v.data(), v.size() * sizeof(T), s);
+}
+
 template <class T>
 hipError_t upload(DevBuf &b, const std::vector<T> &v, hipStream_t s) {
   hipError_t e = b.ensure(std::max<size_t>(1, v.size()) * sizeof(T));
@@ -253,6 +259,36 @@ hipError_t DevBuf::ensure(size_t bytes) {
   }
   cap = want;
   return hipSuccess;
+}
+
+hipError_t HostStage::put(DevBuf &dst, const void *src, size_t bytes, hipStream_t s) {
+  hipError_t e = dst.ensure(std::max<size_t>(bytes, 1));
+  if (e != hipSuccess || bytes == 0) return e;
+  const size_t need = (bytes + 255) & ~(size_t)255;
+  if (used + need > cap) {
+    // the pending copies read the buffer: wait for them, then start over
+    if (used > 0 && (e = hipStreamSynchronize(s)) != hipSuccess) return e;
+    used = 0;
+    if (need > cap) {
+      release();
+      const size_t want = std::max<size_t>(need, (size_t)1 << 20);
+      if ((e = hipHostMalloc(reinterpret_cast<void **>(&p), want)) != hipSuccess) {
+        p = nullptr;
+        return e;
+      }
+      cap = want;
+    }
+  }
+  memcpy(p + used, src, bytes);
+  e = hipMemcpyAsync(dst.p, p + used, bytes, hipMemcpyHostToDevice, s);
+  used += need;
+  return e;
+}
+
+void HostStage::release() {
+  if (p) (void)hipHostFree(p);
+  p = nullptr;
+  cap = used = 0;
 }
 
 void DevBuf::release() {
@@ -668,6 +704,7 @@ void pipnn_destroy(pipnn_index *idx) {
   // synchronisation: other streams keep running); hipFree waits for the
   // device where it must
   for (DevBuf *b : all_bufs(*I)) b->release();
+  I->stage.release();
   for (auto &e : I->events) {
     (void)hipEventDestroy(e.a);
     (void)hipEventDestroy(e.b);
@@ -745,13 +782,12 @@ pipnn_status pipnn_partition_replica(pipnn_index *idx, int32_t replica, int64_t 
     }
     if ((int64_t)offs.size() - 1 > cap_leaves || offs.back() > cap_members) writing = false;
     if (!writing) return PIPNN_OK;
-    HIPCHK(upload(I.p_esrc, src, s));
-    HIPCHK(upload(I.p_eoff, doff, s));
-    HIPCHK(upload(I.p_elen, lens, s));
+    HIPCHK(staged(I, I.p_esrc, src, s));
+    HIPCHK(staged(I, I.p_eoff, doff, s));
+    HIPCHK(staged(I, I.p_elen, lens, s));
     HIPCHK(launch_copy_segments(I.p_esrc.as<const uint32_t *>(), I.p_eoff.as<int64_t>(),
                                 I.p_elen.as<int32_t>(), (int32_t)src.size(),
                                 d_leaf_members + base, s));
-    HIPCHK(hipStreamSynchronize(s));  // the host tables may be released now
     return PIPNN_OK;
   };
 
@@ -802,13 +838,13 @@ pipnn_status pipnn_partition_replica(pipnn_index *idx, int32_t replica, int64_t 
       leader_dists += sb.cnt * ell;
     }
     ++levels;
-    HIPCHK(upload(I.s_tmp1, lead_idx, s));
+    HIPCHK(staged(I, I.s_tmp1, lead_idx, s));
     HIPCHK(I.p_leaders.ensure(lead_idx.size() * 4));
     HIPCHK(launch_gather_u32(A, I.s_tmp1.as<int64_t>(), I.p_leaders.as<uint32_t>(),
                              (int64_t)lead_idx.size(), s));
     items = plan_items(jobs, 128);
-    HIPCHK(upload(I.s_jobs, jobs, s));
-    HIPCHK(upload(I.s_items, items, s));
+    HIPCHK(staged(I, I.s_jobs, jobs, s));
+    HIPCHK(staged(I, I.s_items, items, s));
     HIPCHK(I.p_asg.ensure((size_t)inst * fmax * 4));
     KnnLaunch L{};
     L.idx = &I;
@@ -853,9 +889,9 @@ pipnn_status pipnn_partition_replica(pipnn_index *idx, int32_t replica, int64_t 
       gsubs.push_back(g);
     }
     bucket_cm.push_back(cm_len);  // end of the last bucket = total
-    HIPCHK(upload(I.s_tmp0, gsubs, s));
-    HIPCHK(upload(I.p_groups, tiles, s));
-    HIPCHK(upload(I.p_bstart, bucket_cm, s));
+    HIPCHK(staged(I, I.s_tmp0, gsubs, s));
+    HIPCHK(staged(I, I.p_groups, tiles, s));
+    HIPCHK(staged(I, I.p_bstart, bucket_cm, s));
     HIPCHK(I.p_cm.ensure((size_t)(cm_len + 1) * 8));
     HIPCHK(I.s_off.ensure((size_t)scan_tmp_elems(cm_len) * 8));
     HIPCHK(I.p_G.ensure((size_t)inst * fmax * 4));
@@ -868,6 +904,7 @@ pipnn_status pipnn_partition_replica(pipnn_index *idx, int32_t replica, int64_t 
     HIPCHK(hipMemcpyAsync(bstart.data(), I.p_bstart.p, bstart.size() * 8, hipMemcpyDeviceToHost,
                           s));
     HIPCHK(hipStreamSynchronize(s));
+    I.stage.reset();
 
     // --- plan: merge small buckets, emit leaves, recurse
     std::vector<Sub> next;
@@ -932,10 +969,10 @@ pipnn_status pipnn_partition_replica(pipnn_index *idx, int32_t replica, int64_t 
     if (n_groups > 0) {
       grp_first.push_back((int32_t)seg_ptr.size());
       HIPCHK(I.p_gout.ensure((size_t)gout_total * 4));
-      HIPCHK(upload(I.p_seg, seg_ptr, s));
-      HIPCHK(upload(I.p_seglen, seg_len, s));
-      HIPCHK(upload(I.p_segfirst, grp_first, s));
-      HIPCHK(upload(I.p_segoff, grp_off, s));
+      HIPCHK(staged(I, I.p_seg, seg_ptr, s));
+      HIPCHK(staged(I, I.p_seglen, seg_len, s));
+      HIPCHK(staged(I, I.p_segfirst, grp_first, s));
+      HIPCHK(staged(I, I.p_segoff, grp_off, s));
       HIPCHK(I.p_gsize.ensure((size_t)n_groups * 4));
       HIPCHK(launch_merge_dedup(I.p_seg.as<const uint32_t *>(), I.p_seglen.as<int32_t>(),
                                 I.p_segfirst.as<int32_t>(), n_groups, max_sum,
@@ -943,10 +980,11 @@ pipnn_status pipnn_partition_replica(pipnn_index *idx, int32_t replica, int64_t 
                                 I.p_gsize.as<int32_t>(), s));
       for (int g = 0; g < n_groups; ++g)
         lv.push_back({I.p_gout.as<uint32_t>() + grp_off[(size_t)g], -1, g});
-      // the merged sizes (and the host tables' copies have finished)
+      // the merged sizes
       HIPCHK(hipMemcpyAsync(grp_size.data(), I.p_gsize.p, (size_t)n_groups * 4,
                             hipMemcpyDeviceToHost, s));
       HIPCHK(hipStreamSynchronize(s));
+      I.stage.reset();
     }
     pipnn_status st = emit(lv, grp_size);
     if (st != PIPNN_OK) return st;
@@ -964,13 +1002,12 @@ pipnn_status pipnn_partition_replica(pipnn_index *idx, int32_t replica, int64_t 
         lens.push_back((int32_t)rs.second);
         o += rs.second;
       }
-      HIPCHK(upload(I.p_rsrc, src, s));
-      HIPCHK(upload(I.p_roff, doff, s));
-      HIPCHK(upload(I.p_rlen, lens, s));
+      HIPCHK(staged(I, I.p_rsrc, src, s));
+      HIPCHK(staged(I, I.p_roff, doff, s));
+      HIPCHK(staged(I, I.p_rlen, lens, s));
       HIPCHK(launch_copy_segments(I.p_rsrc.as<const uint32_t *>(), I.p_roff.as<int64_t>(),
                                   I.p_rlen.as<int32_t>(), (int32_t)src.size(),
                                   An.as<uint32_t>(), s));
-      HIPCHK(hipStreamSynchronize(s));
       cur ^= 1;
     }
     subs.swap(next);
@@ -986,6 +1023,7 @@ pipnn_status pipnn_partition_replica(pipnn_index *idx, int32_t replica, int64_t 
   if (!d_leaf_offsets || !d_leaf_members) return fail(PIPNN_EINVAL, "NULL output");
   HIPCHK(hipMemcpyAsync(d_leaf_offsets, offs.data(), offs.size() * 8, hipMemcpyHostToDevice, s));
   HIPCHK(hipStreamSynchronize(s));
+  I.stage.reset();
   I.stats.n_leaves = n_leaves;
   I.stats.n_members = offs.back();
   I.stats.leader_dists = leader_dists;

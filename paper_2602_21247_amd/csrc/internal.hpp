@@ -28,8 +28,23 @@ struct DevBuf {
   template <class T> T *as() const { return reinterpret_cast<T *>(p); }
 };
 
+// Pinned host staging for the small tables a call uploads (work lists,
+// segment tables): each table is appended to one pinned buffer and copied
+// to its device buffer asynchronously, so the host need not wait for the
+// copy; the buffer is reused from the start only after the stream has been
+// synchronised (reset), and a table that does not fit synchronises first.
+// Host memory only (an index on a workspace allocates no device memory).
+struct HostStage {
+  uint8_t *p = nullptr;
+  size_t cap = 0, used = 0;
+  hipError_t put(DevBuf &dst, const void *src, size_t bytes, hipStream_t s);
+  void reset() { used = 0; }
+  void release();
+};
+
 struct Index {
   pipnn_params p;
+  HostStage stage;           // pinned staging of uploaded tables
   bool ws_mode = false;      // every DevBuf is a fixed slice of the caller's workspace
   size_t ws_bytes = 0;       // the layout's total (ws_mode)
   int64_t batch_rows = (int64_t)1 << 25;  // leaf rows per pick + binning batch
