@@ -14,9 +14,10 @@ queries from the same mixture for recall@10 against exact brute force
 
 `--prec` / `--rescore-mult` choose the leaf-GEMM form of the measured build
 (default FP32). `variants` lists other forms (by default bf16 exact, bf16
-with FP32 rescoring of the top-2k, fp8 with rescoring, and FP32 with two
-replicas of the partition) built, timed and searched the same way on the
-same points after the main measurement.
+with FP32 rescoring of the top-2k, fp8 with rescoring, FP32 with two
+replicas of the partition, and FP32 with the All-to-All Prune leaf picker)
+built, timed and searched the same way on the same points after the main
+measurement.
 
 Printed: one JSON line. `rooflines` holds every main kernel of the build
 (leaf pick, partition, binning, merge, RobustPrune) against the roofline
