@@ -254,6 +254,14 @@ __device__ __forceinline__ void knn_quad_item(const KnnArgs &a, const int item) 
   // columns [diag0, diag0 + RW)
   const int diag0 = excl ? J.self_off + wrow : -(1 << 30);
 
+  // B-fragment addresses without per-read arithmetic: when the row and the
+  // per-lane vector count are powers of two, column l16's chunk qn + s sits
+  // at (buffer + l16 CB + ((qn ^ swz) << 4)) ^ (s << 4) (the terms occupy
+  // disjoint bits), and both column groups share the swizzle (the second
+  // group adds 16 CB, a constant offset).
+  constexpr bool PRE = (CB & (CB - 1)) == 0 && (NQ & (NQ - 1)) == 0 && TB % CB == 0;
+  const int bbase = l16 * CB + (((q * NQ) ^ chunk_swz<CPC>(l16)) << 4);
+
   for (int t = 0, c0 = 0; c0 < n_cols; ++t, c0 += BN) {
     const int buf = t & 1;
     const bool more = c0 + BN < n_cols;
@@ -285,12 +293,25 @@ __device__ __forceinline__ void knn_quad_item(const KnnArgs &a, const int item) 
       asm volatile("" : "+v"(rb), "+v"(qn), "+v"(sw0), "+v"(sw1), "+v"(tb));
       // accumulator entry j of group g: row wrow + 4q + j, column c0 + 16g + l16
       f32x4 acc0 = f32x4{0.f, 0.f, 0.f, 0.f}, acc1 = f32x4{0.f, 0.f, 0.f, 0.f};
+      if constexpr (PRE) {
+        int tbase = buf * TB + bbase;
+        asm volatile("" : "+v"(tbase));
 #pragma unroll
-      for (int s = 0; s < NQ; ++s) {
-        const uint4 b0 = *reinterpret_cast<const uint4 *>(sT + tb + (((qn + s) ^ sw0) << 4));
-        const uint4 b1 = *reinterpret_cast<const uint4 *>(sT + tb + 16 * CB + (((qn + s) ^ sw1) << 4));
-        acc0 = mfma16x16<PREC>(aw[s], b0, acc0);
-        acc1 = mfma16x16<PREC>(aw[s], b1, acc1);
+        for (int s = 0; s < NQ; ++s) {
+          const uint8_t *a = sT + (tbase ^ (s << 4));
+          const uint4 b0 = *reinterpret_cast<const uint4 *>(a);
+          const uint4 b1 = *reinterpret_cast<const uint4 *>(a + 16 * CB);
+          acc0 = mfma16x16<PREC>(aw[s], b0, acc0);
+          acc1 = mfma16x16<PREC>(aw[s], b1, acc1);
+        }
+      } else {
+#pragma unroll
+        for (int s = 0; s < NQ; ++s) {
+          const uint4 b0 = *reinterpret_cast<const uint4 *>(sT + tb + (((qn + s) ^ sw0) << 4));
+          const uint4 b1 = *reinterpret_cast<const uint4 *>(sT + tb + 16 * CB + (((qn + s) ^ sw1) << 4));
+          acc0 = mfma16x16<PREC>(aw[s], b0, acc0);
+          acc1 = mfma16x16<PREC>(aw[s], b1, acc1);
+        }
       }
       // survivors as wave masks: bit l of mk[g][j] is lane l's entry j of
       // group g (no branch per entry; the masks are the append's ranks)
