@@ -525,6 +525,29 @@ size_t layout_bytes(Index &I) {
 
 }  // namespace
 
+// All-to-All Prune leaf picker: batches of leaves whose distance matrices
+// (rows x largest leaf x 4 B) fit 1 GiB.
+std::vector<std::pair<int64_t, int64_t>> a2a_batches(const std::vector<int64_t> &offs,
+                                                     int64_t l0, int64_t l1) {
+  const int64_t budget = kA2aBudgetFloats;
+  std::vector<std::pair<int64_t, int64_t>> out;
+  int64_t b0 = l0, rows = 0, wide = 1;
+  for (int64_t l = l0; l < l1; ++l) {
+    const int64_t sz = offs[(size_t)l + 1] - offs[(size_t)l];
+    const int64_t w2 = std::max(wide, sz);
+    if (l > b0 && (rows + sz) * w2 > budget) {
+      out.push_back({b0, l});
+      b0 = l;
+      rows = 0;
+      wide = 1;
+    }
+    rows += sz;
+    wide = std::max(wide, sz);
+  }
+  if (b0 < l1) out.push_back({b0, l1});
+  return out;
+}
+
 extern "C" {
 
 const char *pipnn_version(void) { return "pipnn-gfx950 0.1.0"; }
@@ -1222,28 +1245,6 @@ pipnn_status bin_and_merge(Index &I, bool from_picks, const uint32_t *a, const u
   return bin_and_merge_in(I, B, from_picks, a, b, dist, count, k, res, s, bidir);
 }
 
-// All-to-All Prune leaf picker: batches of leaves whose distance matrices
-// (rows x largest leaf x 4 B) fit 1 GiB.
-std::vector<std::pair<int64_t, int64_t>> a2a_batches(const std::vector<int64_t> &offs,
-                                                     int64_t l0, int64_t l1) {
-  const int64_t budget = kA2aBudgetFloats;
-  std::vector<std::pair<int64_t, int64_t>> out;
-  int64_t b0 = l0, rows = 0, wide = 1;
-  for (int64_t l = l0; l < l1; ++l) {
-    const int64_t sz = offs[(size_t)l + 1] - offs[(size_t)l];
-    const int64_t w2 = std::max(wide, sz);
-    if (l > b0 && (rows + sz) * w2 > budget) {
-      out.push_back({b0, l});
-      b0 = l;
-      rows = 0;
-      wide = 1;
-    }
-    rows += sz;
-    wide = std::max(wide, sz);
-  }
-  if (b0 < l1) out.push_back({b0, l1});
-  return out;
-}
 
 // All-to-All Prune picks of leaves [l0, l1): the leaf kernel writes each
 // leaf's GEMM distance matrix, then one wave per row runs the lazy

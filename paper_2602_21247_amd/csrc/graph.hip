@@ -149,110 +149,97 @@ __device__ __forceinline__ int acc_row32(int v, int h) { return (v & 3) + 8 * (v
 // RobustPrune with the candidate Gram on MFMA (up to 64 candidates,
 // d <= DP <= 128). One wave per point x:
 //  1. the valid reservoir candidates, compacted in slot order;
-//  2. their rows loaded once into MFMA operand fragments (lane l: candidate
-//     l%32 of a 32-block, the dims of its half); d(x,c) by FP32 direct
-//     difference from those registers (each half summed in index order, the
-//     lower half's sum plus the upper half's); G = C C^T on
-//     v_mfma_f32_32x32x2_f32;
-//  3. d(y,z) = |y|^2 + |z|^2 - 2 G[y][z] (or -G for inner product), and bit y
-//     of z's 64-bit mask is set when alpha*d(y,z) < d(x,z) (sign of a fused
-//     multiply-add);
-//  4. the candidates ranked by (d(x,c), id) by counting, and the lazy scan in
+//  2. their rows loaded into MFMA operand fragments (lane l: candidate l%32
+//     of a 32-block, the dims of its half); d(x,c) by direct difference
+//     from those registers (each half summed in index order, the lower
+//     half's sum plus the upper half's); the 64 x 64 Gram G = C C^T as four
+//     32 x 32 blocks on MFMA;
+//  3. d(y,z) = |y|^2 + |z|^2 - 2 G[y][z] (or -G for inner product), and y
+//     prunes z when alpha*d(y,z) < d(x,z): the sign of one fused
+//     multiply-add. A lane holds one column z of a block; the signs of its
+//     16 rows are shifted into a word (v_alignbit), so z's set of pruners is
+//     built with one instruction per pair, and the two halves of a column
+//     meet in one cross-half lane swap;
+//  4. for each candidate, the set of candidates ranked before it by
+//     (d(x,c), id), by comparison with every key; then the lazy scan in
 //     that order -- z is admitted iff no admitted candidate ranked before it
 //     prunes it, the first R admitted kept -- run as rounds over the whole
-//     wave on the masks restricted to earlier candidates. This admits exactly
-//     the candidates of Alg. 2.
-// Steps 3 and 4 of the MFMA RobustPrune described above, shared by its operand forms:
-// from the Gram blocks and the per-slot d(x,c), norms and ranking keys in
-// LDS to the admitted neighbours of x.
-__device__ __forceinline__ void rp_finish(const f32x16 &g00, const f32x16 &g01, const f32x16 &g11,
-                                          int nv, bool l2, float alpha, int R, uint32_t x,
-                                          const float *sDw, const float *sNw, const uint64_t *sKw,
-                                          const uint32_t *sIw, uint32_t *sSw,
+//     wave on the pruner sets restricted to earlier candidates. This admits
+//     exactly the candidates of Alg. 2.
+
+// Column z of Gram block g (rows row0 + acc_row32(v, h), v = 0..15): bit
+// 8*(v>>2) + (v&3) is set when row y prunes z. The lanes of the upper half
+// hold rows 4 further on, so their word is the same pattern shifted by 4.
+// ndx is 0 - d(x,z), never -0, so the fused multiply-add is never -0 and
+// its sign bit is exactly (alpha*d(y,z) - d(x,z) < 0) for non-NaN inputs.
+template <bool L2>
+__device__ __forceinline__ uint32_t rp_sign_bits(const f32x16 &g, const float *sNw, int row0,
+                                                 float nz, float ndx, float alpha) {
+  const int h = (threadIdx.x >> 5) & 1;
+  uint32_t b = 0u;
+#pragma unroll
+  for (int grp = 3; grp >= 0; --grp) {
+    float ny[4] = {0.f, 0.f, 0.f, 0.f};
+    if constexpr (L2) {
+      const float4 q = *reinterpret_cast<const float4 *>(sNw + row0 + 8 * grp + 4 * h);
+      ny[0] = q.x; ny[1] = q.y; ny[2] = q.z; ny[3] = q.w;
+    }
+#pragma unroll
+    for (int j = 3; j >= 0; --j) {
+      const float gv = g[4 * grp + j];
+      const float dyz = L2 ? ny[j] + fmaf(-2.f, gv, nz) : -gv;
+      b = __builtin_amdgcn_alignbit(b, __float_as_uint(fmaf(alpha, dyz, ndx)), 31);
+    }
+    if (grp) b <<= 4;
+  }
+  return b;
+}
+
+// Joins the half-column words of two blocks that share their rows: lane j
+// (< 32) gets column j of block A whole, lane 32 + j column j of block B.
+__device__ __forceinline__ uint32_t rp_join(uint32_t a, uint32_t b) {
+  const auto s = __builtin_amdgcn_permlane32_swap(a, b, false, false);
+  return s[0] | (s[1] << 4);
+}
+
+// Step 4: from the pruner sets by slot (lane j holds slot j's: bit y of
+// mlo / mhi for slot y / 32 + y) and the ranking keys in LDS, the admitted
+// neighbours of x in rank order.
+__device__ __forceinline__ void rp_select(uint32_t mlo, uint32_t mhi, int nv, int R, uint32_t x,
+                                          const uint64_t *sKw, const uint32_t *sIw,
                                           uint32_t *__restrict__ graph,
                                           uint32_t *__restrict__ degree) {
   const int lane = threadIdx.x & 63;
-  const int h = lane >> 5, l32 = lane & 31;
-  // 3. prune masks. Column of this lane: z = l32 (block 00), 32 + l32 (01, 11);
-  //    rows y of block 01 are slots 0..31 (they may prune z in 32..63), and
-  //    block 00 / 11 cover the pairs within each half. Pairs (y in 32..63,
-  //    z in 0..31) are the transposes of block 01.
-  uint32_t b00 = 0, b01 = 0, b11 = 0, b10 = 0;
+  const uint64_t valid = nv >= 64 ? ~0ull : ((1ull << nv) - 1ull);
+  // slots ranked before this lane's: keys are distinct (distinct ids), so
+  // this is a strict order; keys past nv are stale and masked off
+  uint64_t before = 0ull;
   {
-    const int zA = l32, zB = 32 + l32;
-    const float dxA = sDw[zA], dxB = sDw[zB];
-    const float nA = sNw[zA], nB = sNw[zB];
-#pragma unroll
-    for (int v = 0; v < 16; ++v) {
-      const int y = acc_row32(v, h);
-      const float ny = sNw[y], ny1 = sNw[32 + y];
-      const float dy0 = sDw[y], dy1 = sDw[32 + y];
-      const float d00 = l2 ? ny + fmaf(-2.f, g00[v], nA) : -g00[v];
-      if (y != zA && zA < nv && y < nv && fmaf(alpha, d00, -dxA) < 0.f) b00 |= 1u << y;
-      if (nv > 32) {
-        const float d01 = l2 ? ny + fmaf(-2.f, g01[v], nB) : -g01[v];
-        const float d11 = l2 ? ny1 + fmaf(-2.f, g11[v], nB) : -g11[v];
-        // slot y (0..31) prunes slot zB; and slot zB, as a row, prunes slot y
-        if (zB < nv && y < nv && fmaf(alpha, d01, -dxB) < 0.f) b01 |= 1u << y;
-        if (zB < nv && y < nv && fmaf(alpha, d01, -dy0) < 0.f) b10 |= 1u << y;
-        if (32 + y != zB && zB < nv && 32 + y < nv && fmaf(alpha, d11, -dxB) < 0.f)
-          b11 |= 1u << y;
-        (void)dy1;
-      }
-    }
-    b00 |= __shfl_xor(b00, 32, 64);
-    b01 |= __shfl_xor(b01, 32, 64);
-    b11 |= __shfl_xor(b11, 32, 64);
-    b10 |= __shfl_xor(b10, 32, 64);
-  }
-  // masks by slot: lane j < 32 holds slot j's pruners among slots 0..31 (b00)
-  // and 32..63 (transposed from b10); lane 32 + j holds slot 32 + j's from
-  // b01 (0..31) and b11 (32..63). b10 of lane zB has bit y set when zB prunes
-  // y: it is gathered per y below.
-  uint32_t mlo = h == 0 ? b00 : b01;
-  uint32_t mhi = h == 0 ? 0u : b11;
-  if (nv > 32) {
-    // slot y < 32, bit (zB - 32): zB prunes y. Lane zB holds b10 with bit y.
-    uint32_t t = 0;
-    for (int j = 0; j < 32; ++j) {
-      const uint32_t bj = (uint32_t)__builtin_amdgcn_readlane((int)b10, 32 + j);
-      t |= ((bj >> l32) & 1u) << j;
-    }
-    if (h == 0) mhi = t;
-  }
-
-  // 4. ranks by (d(x,c), id) by counting
-  int my_rank = 64;
-  if (lane < nv) {
     const uint64_t kt = sKw[lane];
-    int rank = 0;
-    for (int u = 0; u < nv; ++u) rank += sKw[u] < kt ? 1 : 0;
-    sSw[rank] = (uint32_t)lane;
-    my_rank = rank;
+    // four keys per step, the highest slot first: slot u lands on bit u
+    auto bits = [&](int u0) -> uint32_t {
+      uint32_t b = 0u;
+#pragma unroll 2
+      for (int u = u0 + 28; u >= u0; u -= 4) {
+        const ulonglong2 p = *reinterpret_cast<const ulonglong2 *>(sKw + u);
+        const ulonglong2 q = *reinterpret_cast<const ulonglong2 *>(sKw + u + 2);
+        b = b + b + (q.y < kt ? 1u : 0u);
+        b = b + b + (q.x < kt ? 1u : 0u);
+        b = b + b + (p.y < kt ? 1u : 0u);
+        b = b + b + (p.x < kt ? 1u : 0u);
+      }
+      return b;
+    };
+    const uint32_t hi = nv > 32 ? bits(32) : 0u;
+    const uint32_t lo = bits(0);
+    if (lane < nv) before = ((((uint64_t)hi) << 32) | lo) & valid;
   }
-  wave_sync();
-  auto shfl64 = [](uint64_t v, int src) -> uint64_t {
-    const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)v, src, 64);
-    const uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(v >> 32), src, 64);
-    return ((uint64_t)hi << 32) | lo;
-  };
-  // slots ranked before each slot: a prefix OR over the sorted positions
-  // (position q contributes its slot's bit), read back at the slot's rank
-  uint64_t pre = lane < nv ? (1ull << sSw[lane]) : 0ull;
-#pragma unroll
-  for (int off = 1; off < 64; off <<= 1) {
-    const uint64_t o = shfl64(pre, lane >= off ? lane - off : lane);
-    if (lane >= off) pre |= o;
-  }
-  uint64_t excl = shfl64(pre, lane > 0 ? lane - 1 : 0);
-  if (lane == 0) excl = 0ull;
-  const uint64_t before = lane < nv ? shfl64(excl, my_rank < 64 ? my_rank : 0) : 0ull;
   // the lazy scan of Alg. 2 in rounds: a candidate is admitted once none of
   // its earlier pruners is admitted or undecided, rejected once one of them
   // is admitted; each round decides at least the earliest undecided one, and
   // the outcome is the sequential scan's
-  const uint64_t pr = (((uint64_t)mhi << 32) | mlo) & before;
-  uint64_t adm = 0ull, und = nv >= 64 ? ~0ull : ((1ull << nv) - 1ull);
+  const uint64_t pr = ((((uint64_t)mhi) << 32) | mlo) & before;
+  uint64_t adm = 0ull, und = valid;
   while (und != 0ull) {
     const bool u = (und >> lane) & 1ull;
     const bool rej = u && (pr & adm) != 0ull;
@@ -273,37 +260,61 @@ __device__ __forceinline__ void rp_finish(const f32x16 &g00, const f32x16 &g01, 
   if (lane == 0) degree[x] = (uint32_t)ne;
 }
 
-template <int DP>
+// Steps 1 and the per-slot records shared by the MFMA forms: the valid
+// candidates compacted into sIw in slot order; returns their count.
+__device__ __forceinline__ int rp_compact(const uint64_t *__restrict__ res, int l_max, uint32_t x,
+                                          int64_t n, uint32_t *sIw) {
+  const int lane = threadIdx.x & 63;
+  uint32_t c = kEmptyId;
+  if (lane < l_max) c = slot_id(res[(int64_t)x * l_max + lane]);
+  const bool ok = lane < l_max && c != kEmptyId && c != x && c < n;
+  const uint64_t m = __ballot(ok);
+  const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  if (ok) sIw[__popcll(m & below)] = c;
+  return __popcll(m);
+}
+
+// d(x, slot) of this lane's two slots (lanes j and 32 + j hold the lower and
+// upper half sums of slots j and 32 + j) into the per-slot records.
+template <bool L2>
+__device__ __forceinline__ void rp_records(float s0, float s1, int nv,
+                                           const float *__restrict__ norms, float *sDw,
+                                           float *sNw, uint64_t *sKw, const uint32_t *sIw) {
+  const int lane = threadIdx.x & 63;
+  const int h = lane >> 5;
+  // lower half's sum plus upper half's
+  const float o0 = __shfl_xor(s0, 32, 64), o1 = __shfl_xor(s1, 32, 64);
+  const float t0 = h == 0 ? s0 + o0 : o0 + s0, t1 = h == 0 ? s1 + o1 : o1 + s1;
+  // lane j < 32 records slot j, lane 32 + j records slot 32 + j
+  const float t = h == 0 ? t0 : t1;
+  const float dxm = L2 ? t : -t;
+  if (lane < nv) {
+    const uint32_t cid = sIw[lane];
+    sDw[lane] = dxm;
+    sNw[lane] = L2 ? norms[cid] : 0.f;
+    sKw[lane] = ((uint64_t)f32_rank(dxm) << 32) | cid;
+  }
+}
+
+template <int DP, bool L2, bool FULL>
 __global__ void __launch_bounds__(64 * kRpWaves, 4) robustprune_mfma_kernel(
-    const float *__restrict__ X, const float *__restrict__ norms, int64_t n, int d, int metric,
+    const float *__restrict__ X, const float *__restrict__ norms, int64_t n, int d,
     const uint64_t *__restrict__ res, int l_max, float alpha, int R,
     const uint32_t *__restrict__ order, int64_t n_items, uint32_t *__restrict__ graph,
     uint32_t *__restrict__ degree) {
   constexpr int HALF = DP / 2;
-  __shared__ uint64_t sK[kRpWaves][64];
-  __shared__ float sD[kRpWaves][64];
-  __shared__ float sN[kRpWaves][64];
+  __shared__ __align__(16) uint64_t sK[kRpWaves][64];
+  __shared__ __align__(16) float sD[kRpWaves][64];
+  __shared__ __align__(16) float sN[kRpWaves][64];
   __shared__ uint32_t sI[kRpWaves][64];
-  __shared__ uint32_t sS[kRpWaves][64];  // sorted position -> slot
+  __shared__ float sT[kRpWaves][32 * 33];  // block 01, transposed into block 10
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int h = lane >> 5, l32 = lane & 31;
   const int64_t item = (int64_t)xcd_item(blockIdx.x, gridDim.x) * kRpWaves + wave;
   if (item >= n_items) return;
   const uint32_t x = __builtin_amdgcn_readfirstlane(order ? order[item] : (uint32_t)item);
-  const bool l2 = metric == PIPNN_METRIC_L2;
-  const bool full_d = d == DP;
-
-  // 1. valid candidates in slot order
-  int nv;
-  {
-    uint32_t c = kEmptyId;
-    if (lane < l_max) c = slot_id(res[(int64_t)x * l_max + lane]);
-    const bool ok = lane < l_max && c != kEmptyId && c != x && c < n;
-    const uint64_t m = __ballot(ok);
-    nv = __popcll(m);
-    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    if (ok) sI[wave][__popcll(m & below)] = c;
-  }
+  // 1. valid candidates in slot order (FULL: d == DP)
+  const int nv = rp_compact(res, l_max, x, n, sI[wave]);
   wave_sync();
 
   // 2. fragments F0 (slots 0..31) and F1 (slots 32..63), taken CH
@@ -318,17 +329,19 @@ __global__ void __launch_bounds__(64 * kRpWaves, 4) robustprune_mfma_kernel(
 #pragma unroll
   for (int v = 0; v < 16; ++v) { g00[v] = 0.f; g01[v] = 0.f; g11[v] = 0.f; }
   float s0 = 0.f, s1 = 0.f;
+  const bool both = nv > 32;
   {
     const int kb = h * HALF;
+    // slots past nv read x's own row: finite values whose Gram rows and
+    // columns no decision reads (the rank sets hold valid slots only)
     const bool v0 = l32 < nv, v1 = 32 + l32 < nv;
     const uint32_t c0 = v0 ? sI[wave][l32] : x, c1 = v1 ? sI[wave][32 + l32] : x;
     const float *r0 = X + (int64_t)c0 * d + kb;
     const float *r1 = X + (int64_t)c1 * d + kb;
     const float *rx = X + (int64_t)x * d + kb;
-    const bool both = nv > 32;
     float n0[CH], n1[CH], nx[CH];
     auto load_chunk = [&](int k0) {
-      if (full_d) {
+      if constexpr (FULL) {
 #pragma unroll
         for (int j = 0; j < CH; j += 4) {
           const float4 q0 = *reinterpret_cast<const float4 *>(r0 + k0 + j);
@@ -361,7 +374,7 @@ __global__ void __launch_bounds__(64 * kRpWaves, 4) robustprune_mfma_kernel(
       if (k0 + CH < HALF) load_chunk(k0 + CH);
 #pragma unroll
       for (int j = 0; j < CH; ++j) {
-        if (l2) {
+        if constexpr (L2) {
           const float t0 = f0[j] - fx[j], t1 = f1[j] - fx[j];
           s0 = fmaf(t0, t0, s0);
           s1 = fmaf(t1, t1, s1);
@@ -369,11 +382,6 @@ __global__ void __launch_bounds__(64 * kRpWaves, 4) robustprune_mfma_kernel(
           s0 = fmaf(f0[j], fx[j], s0);
           s1 = fmaf(f1[j], fx[j], s1);
         }
-      }
-#pragma unroll
-      for (int j = 0; j < CH; ++j) {
-        f0[j] = v0 ? f0[j] : 0.f;
-        f1[j] = v1 ? f1[j] : 0.f;
       }
 #pragma unroll
       for (int j = 0; j < CH; ++j)
@@ -385,24 +393,44 @@ __global__ void __launch_bounds__(64 * kRpWaves, 4) robustprune_mfma_kernel(
           g11 = __builtin_amdgcn_mfma_f32_32x32x2f32(f1[j], f1[j], g11, 0, 0, 0);
         }
       }
-    }
-    // lower half's sum plus upper half's
-    const float o0 = __shfl_xor(s0, 32, 64), o1 = __shfl_xor(s1, 32, 64);
-    const float t0 = h == 0 ? s0 + o0 : o0 + s0, t1 = h == 0 ? s1 + o1 : o1 + s1;
-    const float dx0 = l2 ? t0 : -t0, dx1 = l2 ? t1 : -t1;
-    // lane j < 32 records slot j, lane 32 + j records slot 32 + j
-    const float dxm = h == 0 ? dx0 : dx1;
-    const int slot = lane;
-    if (slot < nv) {
-      const uint32_t cid = sI[wave][slot];
-      sD[wave][slot] = dxm;
-      sN[wave][slot] = l2 ? norms[cid] : 0.f;
-      sK[wave][slot] = ((uint64_t)f32_rank(dxm) << 32) | cid;
+      // the chunk's sums are taken here, with one chunk in flight ahead and
+      // no more: the compiler would otherwise defer the sums past the loop
+      // and keep every chunk's rows live
+      asm volatile("" : "+v"(s0), "+v"(s1));
+      __builtin_amdgcn_sched_barrier(0);
     }
   }
+  rp_records<L2>(s0, s1, nv, norms, sD[wave], sN[wave], sK[wave], sI[wave]);
+  // block 10 (rows 32..63, columns 0..31) is block 01 transposed: T[r][c] =
+  // G[r][32 + c] is written from block 01's layout and read back in block
+  // 10's, G[32 + r][c] = T[c][r] (rows padded to 33 words)
+  f32x16 g10;
+  float *T = sT[wave];
+  if (both) {
+#pragma unroll
+    for (int v = 0; v < 16; ++v) T[acc_row32(v, h) * 33 + l32] = g01[v];
+  }
   wave_sync();
-  rp_finish(g00, g01, g11, nv, l2, alpha, R, x, sD[wave], sN[wave], sK[wave], sI[wave], sS[wave],
-            graph, degree);
+  if (both) {
+#pragma unroll
+    for (int v = 0; v < 16; ++v) g10[v] = T[l32 * 33 + acc_row32(v, h)];
+  }
+  // 3. pruner sets by slot
+  const float *sNw = sN[wave];
+  const float nA = L2 ? sNw[l32] : 0.f, xA = 0.f - sD[wave][l32];
+  const uint32_t c00 = rp_sign_bits<L2>(g00, sNw, 0, nA, xA, alpha);
+  uint32_t mlo, mhi = 0u;
+  if (both) {
+    const float nB = L2 ? sNw[32 + l32] : 0.f, xB = 0.f - sD[wave][32 + l32];
+    const uint32_t c10 = rp_sign_bits<L2>(g10, sNw, 32, nA, xA, alpha);
+    const uint32_t c01 = rp_sign_bits<L2>(g01, sNw, 0, nB, xB, alpha);
+    const uint32_t c11 = rp_sign_bits<L2>(g11, sNw, 32, nB, xB, alpha);
+    mlo = rp_join(c00, c01);
+    mhi = rp_join(c10, c11);
+  } else {
+    mlo = c00 | ((uint32_t)__shfl_xor((int)c00, 32, 64) << 4);
+  }
+  rp_select(mlo, mhi, nv, R, x, sK[wave], sI[wave], graph, degree);
 }
 
 // The same RobustPrune reading a 16-bit operand (the index's bf16 / fp16
@@ -410,47 +438,46 @@ __global__ void __launch_bounds__(64 * kRpWaves, 4) robustprune_mfma_kernel(
 // half the bytes, d(x,c) is the same FP32 direct difference (of the same
 // values, in the same order), and the Gram runs on v_mfma_f32_32x32x16 with
 // FP32 accumulation of exact products, so where those sums are exact
-// (integer data) every decision is the float32 kernel's.
-template <int PREC, int DP>
+// (integer data) every decision is the float32 kernel's. IDIFF (fp16 copy
+// of integer data of range <= 2048, every distance form exact in float32):
+// the differences are taken two at a time in fp16 (exact integers) and
+// squared and summed by v_dot2_f32_f16, whose every partial sum is an
+// integer of at most 2^24, so d(x,c) is the float32 kernel's value with a
+// quarter of the instructions.
+template <int PREC, int DP, bool L2, bool IDIFF>
 __global__ void __launch_bounds__(64 * kRpWaves, 4) robustprune_mfma16_kernel(
-    const uint8_t *__restrict__ Xop, const float *__restrict__ norms, int64_t n, int metric,
+    const uint8_t *__restrict__ Xop, const float *__restrict__ norms, int64_t n,
     const uint64_t *__restrict__ res, int l_max, float alpha, int R,
     const uint32_t *__restrict__ order, int64_t n_items, uint32_t *__restrict__ graph,
     uint32_t *__restrict__ degree) {
+  static_assert(!IDIFF || PREC == PIPNN_PREC_FP16, "packed differences are fp16");
   constexpr int HALF = DP / 2;
   constexpr int NA = HALF / 8;        // 16-byte vectors (8 values) per lane
   constexpr int CB = DP * 2;          // bytes per operand row
-  __shared__ uint64_t sK[kRpWaves][64];
-  __shared__ float sD[kRpWaves][64];
-  __shared__ float sN[kRpWaves][64];
+  __shared__ __align__(16) uint64_t sK[kRpWaves][64];
+  __shared__ __align__(16) float sD[kRpWaves][64];
+  __shared__ __align__(16) float sN[kRpWaves][64];
   __shared__ uint32_t sI[kRpWaves][64];
-  __shared__ uint32_t sS[kRpWaves][64];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int h = lane >> 5, l32 = lane & 31;
   const int64_t item = (int64_t)xcd_item(blockIdx.x, gridDim.x) * kRpWaves + wave;
   if (item >= n_items) return;
   const uint32_t x = __builtin_amdgcn_readfirstlane(order ? order[item] : (uint32_t)item);
-  const bool l2 = metric == PIPNN_METRIC_L2;
 
-  int nv;
-  {
-    uint32_t c = kEmptyId;
-    if (lane < l_max) c = slot_id(res[(int64_t)x * l_max + lane]);
-    const bool ok = lane < l_max && c != kEmptyId && c != x && c < n;
-    const uint64_t m = __ballot(ok);
-    nv = __popcll(m);
-    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    if (ok) sI[wave][__popcll(m & below)] = c;
-  }
+  const int nv = rp_compact(res, l_max, x, n, sI[wave]);
   wave_sync();
 
   auto val = [](uint32_t code) -> float {
     if constexpr (PREC == PIPNN_PREC_BF16) return __uint_as_float(code << 16);
     else return (float)__builtin_bit_cast(_Float16, (uint16_t)code);
   };
+  typedef _Float16 h2_t __attribute__((ext_vector_type(2)));
   uint4 a0[NA], a1[NA];
   float s0 = 0.f, s1 = 0.f;
+  const bool both = nv > 32;
   {
+    // slots past nv read x's own row: finite values whose Gram rows and
+    // columns no decision reads (the rank sets hold valid slots only)
     const bool v0 = l32 < nv, v1 = 32 + l32 < nv;
     const uint32_t c0 = v0 ? sI[wave][l32] : x, c1 = v1 ? sI[wave][32 + l32] : x;
     const uint4 *r0 = reinterpret_cast<const uint4 *>(Xop + (int64_t)c0 * CB + h * HALF * 2);
@@ -458,46 +485,45 @@ __global__ void __launch_bounds__(64 * kRpWaves, 4) robustprune_mfma16_kernel(
     const uint4 *rx = reinterpret_cast<const uint4 *>(Xop + (int64_t)x * CB + h * HALF * 2);
 #pragma unroll
     for (int sv = 0; sv < NA; ++sv) {
-      const uint4 q0 = r0[sv], q1 = r1[sv], qx = rx[sv];
-      a0[sv] = q0;
-      a1[sv] = q1;
-      const uint32_t w0[4] = {q0.x, q0.y, q0.z, q0.w}, w1[4] = {q1.x, q1.y, q1.z, q1.w};
+      a0[sv] = r0[sv];
+      a1[sv] = r1[sv];
+      const uint4 qx = rx[sv];
+      const uint32_t w0[4] = {a0[sv].x, a0[sv].y, a0[sv].z, a0[sv].w};
+      const uint32_t w1[4] = {a1[sv].x, a1[sv].y, a1[sv].z, a1[sv].w};
       const uint32_t wx[4] = {qx.x, qx.y, qx.z, qx.w};
+      if constexpr (IDIFF) {
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const float c0v = val((w0[e >> 1] >> (16 * (e & 1))) & 0xFFFFu);
-        const float c1v = val((w1[e >> 1] >> (16 * (e & 1))) & 0xFFFFu);
-        const float xv = val((wx[e >> 1] >> (16 * (e & 1))) & 0xFFFFu);
-        if (l2) {
-          const float t0 = c0v - xv, t1 = c1v - xv;
-          s0 = fmaf(t0, t0, s0);
-          s1 = fmaf(t1, t1, s1);
-        } else {
-          s0 = fmaf(c0v, xv, s0);
-          s1 = fmaf(c1v, xv, s1);
+        for (int e = 0; e < 4; ++e) {
+          const h2_t c0v = __builtin_bit_cast(h2_t, w0[e]), c1v = __builtin_bit_cast(h2_t, w1[e]);
+          const h2_t xv = __builtin_bit_cast(h2_t, wx[e]);
+          if constexpr (L2) {
+            const h2_t t0 = c0v - xv, t1 = c1v - xv;
+            s0 = __builtin_amdgcn_fdot2(t0, t0, s0, false);
+            s1 = __builtin_amdgcn_fdot2(t1, t1, s1, false);
+          } else {
+            s0 = __builtin_amdgcn_fdot2(c0v, xv, s0, false);
+            s1 = __builtin_amdgcn_fdot2(c1v, xv, s1, false);
+          }
+        }
+      } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const float c0v = val((w0[e >> 1] >> (16 * (e & 1))) & 0xFFFFu);
+          const float c1v = val((w1[e >> 1] >> (16 * (e & 1))) & 0xFFFFu);
+          const float xv = val((wx[e >> 1] >> (16 * (e & 1))) & 0xFFFFu);
+          if constexpr (L2) {
+            const float t0 = c0v - xv, t1 = c1v - xv;
+            s0 = fmaf(t0, t0, s0);
+            s1 = fmaf(t1, t1, s1);
+          } else {
+            s0 = fmaf(c0v, xv, s0);
+            s1 = fmaf(c1v, xv, s1);
+          }
         }
       }
     }
-    if (!v0) {
-#pragma unroll
-      for (int sv = 0; sv < NA; ++sv) a0[sv] = make_uint4(0u, 0u, 0u, 0u);
-    }
-    if (!v1) {
-#pragma unroll
-      for (int sv = 0; sv < NA; ++sv) a1[sv] = make_uint4(0u, 0u, 0u, 0u);
-    }
-    const float o0 = __shfl_xor(s0, 32, 64), o1 = __shfl_xor(s1, 32, 64);
-    const float t0 = h == 0 ? s0 + o0 : o0 + s0, t1 = h == 0 ? s1 + o1 : o1 + s1;
-    const float dx0 = l2 ? t0 : -t0, dx1 = l2 ? t1 : -t1;
-    const float dxm = h == 0 ? dx0 : dx1;
-    const int slot = lane;
-    if (slot < nv) {
-      const uint32_t cid = sI[wave][slot];
-      sD[wave][slot] = dxm;
-      sN[wave][slot] = l2 ? norms[cid] : 0.f;
-      sK[wave][slot] = ((uint64_t)f32_rank(dxm) << 32) | cid;
-    }
   }
+  rp_records<L2>(s0, s1, nv, norms, sD[wave], sN[wave], sK[wave], sI[wave]);
   wave_sync();
   typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
   typedef _Float16 f16x8_t __attribute__((ext_vector_type(8)));
@@ -509,20 +535,41 @@ __global__ void __launch_bounds__(64 * kRpWaves, 4) robustprune_mfma16_kernel(
       return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8_t, p),
                                                      __builtin_bit_cast(f16x8_t, q), acc, 0, 0, 0);
   };
-  f32x16 g00, g01, g11;
+  auto gram = [&](const uint4 *p, const uint4 *q) -> f32x16 {
+    f32x16 g;
 #pragma unroll
-  for (int v = 0; v < 16; ++v) { g00[v] = 0.f; g01[v] = 0.f; g11[v] = 0.f; }
+    for (int v = 0; v < 16; ++v) g[v] = 0.f;
 #pragma unroll
-  for (int sv = 0; sv < NA; ++sv) g00 = mm(a0[sv], a0[sv], g00);
-  if (nv > 32) {
-#pragma unroll
-    for (int sv = 0; sv < NA; ++sv) {
-      g01 = mm(a0[sv], a1[sv], g01);
-      g11 = mm(a1[sv], a1[sv], g11);
-    }
+    for (int sv = 0; sv < NA; ++sv) g = mm(p[sv], q[sv], g);
+    return g;
+  };
+  // 3. the four blocks, in the order that frees F0 after the third
+  const float *sNw = sN[wave];
+  const float nA = L2 ? sNw[l32] : 0.f, xA = 0.f - sD[wave][l32];
+  uint32_t mlo, mhi = 0u;
+  if (both) {
+    const float nB = L2 ? sNw[32 + l32] : 0.f, xB = 0.f - sD[wave][32 + l32];
+    // (the scheduling barriers keep at most two fragments and three blocks
+    // live, so that the rows fit the registers of four waves per SIMD)
+    const f32x16 g00 = gram(a0, a0);
+    const f32x16 g01 = gram(a0, a1);
+    __builtin_amdgcn_sched_barrier(0);
+    const uint32_t c00 = rp_sign_bits<L2>(g00, sNw, 0, nA, xA, alpha);
+    const f32x16 g10 = gram(a1, a0);
+    __builtin_amdgcn_sched_barrier(0);
+    const uint32_t c01 = rp_sign_bits<L2>(g01, sNw, 0, nB, xB, alpha);
+    const f32x16 g11 = gram(a1, a1);
+    __builtin_amdgcn_sched_barrier(0);
+    const uint32_t c10 = rp_sign_bits<L2>(g10, sNw, 32, nA, xA, alpha);
+    const uint32_t c11 = rp_sign_bits<L2>(g11, sNw, 32, nB, xB, alpha);
+    mlo = rp_join(c00, c01);
+    mhi = rp_join(c10, c11);
+  } else {
+    const f32x16 g00 = gram(a0, a0);
+    const uint32_t c00 = rp_sign_bits<L2>(g00, sNw, 0, nA, xA, alpha);
+    mlo = c00 | ((uint32_t)__shfl_xor((int)c00, 32, 64) << 4);
   }
-  rp_finish(g00, g01, g11, nv, l2, alpha, R, x, sD[wave], sN[wave], sK[wave], sI[wave], sS[wave],
-            graph, degree);
+  rp_select(mlo, mhi, nv, R, x, sK[wave], sI[wave], graph, degree);
 }
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
@@ -715,33 +762,55 @@ hipError_t launch_robustprune(const Index &I, const uint64_t *res, uint32_t *gra
   const int64_t n_items = subset ? n_subset : I.n;
   if (n_items <= 0) return hipSuccess;
   const bool op16 = I.copy16_exact();
+  const bool l2 = I.p.metric == PIPNN_METRIC_L2;
   if (I.p.l_max <= 64 && op16 && (I.ldo == 64 || I.ldo == 96 || I.ldo == 128)) {
     const int64_t blocks = xcd_grid((n_items + kRpWaves - 1) / kRpWaves);
     auto go = [&](auto kern) {
       hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(64 * kRpWaves), 0, s,
-                         I.xlow.as<uint8_t>(), I.norms.as<float>(), I.n, I.p.metric, res,
-                         I.p.l_max, I.p.alpha, I.p.R, order, n_items, graph, degree);
+                         I.xlow.as<uint8_t>(), I.norms.as<float>(), I.n, res, I.p.l_max,
+                         I.p.alpha, I.p.R, order, n_items, graph, degree);
     };
-    const bool b = I.copy_prec == PIPNN_PREC_BF16;
-    if (I.ldo == 64) b ? go(robustprune_mfma16_kernel<PIPNN_PREC_BF16, 64>)
-                       : go(robustprune_mfma16_kernel<PIPNN_PREC_FP16, 64>);
-    else if (I.ldo == 96) b ? go(robustprune_mfma16_kernel<PIPNN_PREC_BF16, 96>)
-                            : go(robustprune_mfma16_kernel<PIPNN_PREC_FP16, 96>);
-    else b ? go(robustprune_mfma16_kernel<PIPNN_PREC_BF16, 128>)
-           : go(robustprune_mfma16_kernel<PIPNN_PREC_FP16, 128>);
+    // packed fp16 differences: integer data (every distance form exact in
+    // float32) whose differences are fp16 integers (range <= 2048)
+    const bool idiff = I.copy_prec == PIPNN_PREC_FP16 && I.int_exact &&
+                       (!l2 || I.int_hi - I.int_lo <= 2048);
+    auto pick = [&](auto dp) {
+      constexpr int DP = decltype(dp)::value;
+      if (I.copy_prec == PIPNN_PREC_BF16)
+        l2 ? go(robustprune_mfma16_kernel<PIPNN_PREC_BF16, DP, true, false>)
+           : go(robustprune_mfma16_kernel<PIPNN_PREC_BF16, DP, false, false>);
+      else if (idiff)
+        l2 ? go(robustprune_mfma16_kernel<PIPNN_PREC_FP16, DP, true, true>)
+           : go(robustprune_mfma16_kernel<PIPNN_PREC_FP16, DP, false, true>);
+      else
+        l2 ? go(robustprune_mfma16_kernel<PIPNN_PREC_FP16, DP, true, false>)
+           : go(robustprune_mfma16_kernel<PIPNN_PREC_FP16, DP, false, false>);
+    };
+    if (I.ldo == 64) pick(std::integral_constant<int, 64>());
+    else if (I.ldo == 96) pick(std::integral_constant<int, 96>());
+    else pick(std::integral_constant<int, 128>());
     return hipGetLastError();
   }
   if (I.p.l_max <= 64 && I.d <= 128) {
     const int64_t blocks = xcd_grid((n_items + kRpWaves - 1) / kRpWaves);
     auto args = [&](auto kern) {
       hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(64 * kRpWaves), 0, s, I.xf(),
-                         I.norms.as<float>(), I.n, I.d, I.p.metric, res, I.p.l_max, I.p.alpha,
-                         I.p.R, order, n_items, graph, degree);
+                         I.norms.as<float>(), I.n, I.d, res, I.p.l_max, I.p.alpha, I.p.R, order,
+                         n_items, graph, degree);
     };
-    if (I.d <= 32) args(robustprune_mfma_kernel<32>);
-    else if (I.d <= 64) args(robustprune_mfma_kernel<64>);
-    else if (I.d <= 96) args(robustprune_mfma_kernel<96>);
-    else args(robustprune_mfma_kernel<128>);
+    auto pick = [&](auto dp) {
+      constexpr int DP = decltype(dp)::value;
+      if (I.d == DP)
+        l2 ? args(robustprune_mfma_kernel<DP, true, true>)
+           : args(robustprune_mfma_kernel<DP, false, true>);
+      else
+        l2 ? args(robustprune_mfma_kernel<DP, true, false>)
+           : args(robustprune_mfma_kernel<DP, false, false>);
+    };
+    if (I.d <= 32) pick(std::integral_constant<int, 32>());
+    else if (I.d <= 64) pick(std::integral_constant<int, 64>());
+    else if (I.d <= 96) pick(std::integral_constant<int, 96>());
+    else pick(std::integral_constant<int, 128>());
     return hipGetLastError();
   }
   const int dp = I.ldo;
@@ -751,7 +820,6 @@ hipError_t launch_robustprune(const Index &I, const uint64_t *res, uint32_t *gra
     const int64_t blocks = xcd_grid((n_items + kRpWaves - 1) / kRpWaves);
     const uint8_t *xop = I.xlow.as<uint8_t>();
     const int64_t op_ld = (int64_t)dp * 2;
-    const bool l2 = I.p.metric == PIPNN_METRIC_L2;
     auto go = [&](auto kern) {
       hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(64 * kRpWaves), 0, s, xop, op_ld, I.n,
                          res, I.p.l_max, I.p.alpha, I.p.R, order, n_items, graph, degree);
