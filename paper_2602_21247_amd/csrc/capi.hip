@@ -7,7 +7,6 @@
 #include <deque>
 #include <new>
 #include <string>
-#include <unordered_map>
 #include <vector>
 
 #include "common.hpp"
@@ -88,13 +87,26 @@ uint64_t sub_key(uint64_t key, int64_t t) {
 // Positions (within the subproblem's ascending id list) of its `ell`
 // leaders: the first ell entries of a partial Fisher-Yates shuffle driven by
 // splitmix64 from `key`, drawing j = t + floor(r * (np - t) / 2^64) (Alg. 5,
-// SampleLeaders). Only swapped positions are stored.
+// SampleLeaders). Only swapped positions are stored, in an open-addressing
+// table (linear probing, at most half full).
 std::vector<int64_t> leader_positions(uint64_t key, int64_t np, int64_t ell) {
-  std::unordered_map<int64_t, int64_t> sw;
-  sw.reserve((size_t)ell * 2);
+  size_t cap = 16;
+  while (cap < (size_t)ell * 4) cap <<= 1;
+  const size_t mask = cap - 1;
+  std::vector<int64_t> keys(cap, -1), vals(cap);
+  auto slot = [&](int64_t i) {
+    size_t h = (size_t)(((uint64_t)i * 0x9E3779B97F4A7C15ull) >> 20) & mask;
+    while (keys[h] != -1 && keys[h] != i) h = (h + 1) & mask;
+    return h;
+  };
   auto at = [&](int64_t i) {
-    auto it = sw.find(i);
-    return it == sw.end() ? i : it->second;
+    const size_t h = slot(i);
+    return keys[h] == -1 ? i : vals[h];
+  };
+  auto put = [&](int64_t i, int64_t v) {
+    const size_t h = slot(i);
+    keys[h] = i;
+    vals[h] = v;
   };
   std::vector<int64_t> pos((size_t)ell);
   uint64_t st = key;
@@ -103,8 +115,8 @@ std::vector<int64_t> leader_positions(uint64_t key, int64_t np, int64_t ell) {
     const int64_t j =
         t + (int64_t)(((unsigned __int128)r * (unsigned __int128)(uint64_t)(np - t)) >> 64);
     const int64_t vt = at(t), vj = at(j);
-    sw[t] = vj;
-    sw[j] = vt;
+    put(t, vj);
+    put(j, vt);
     pos[(size_t)t] = vj;
   }
   return pos;
@@ -163,44 +175,80 @@ constexpr int kGroupTile = 1024;
 // Work items of a knn launch in launch order: block b runs on XCD b % 8 and
 // takes item b. Jobs are taken largest first (by rows x columns); a job of
 // at most 16 row blocks goes whole to the least-loaded XCD (its columns stay
-// in that XCD's L2), the row blocks of a larger job are dealt one by one to
-// the least-loaded XCD. Shorter XCD lists are padded with idle items.
+// in that XCD's L2), the row blocks of a larger job are dealt in turn to the
+// XCDs in rising order of load. Shorter XCD lists are padded with idle
+// items. The first pass fixes each job's XCDs and the list lengths, the
+// second writes the items in place. (Every row's result is the same for
+// any order of the items: the plan decides only the balance.)
 std::vector<KnnItem> plan_items(const std::vector<KnnJob> &jobs, int rows_per_item = 128) {
-  const int kKnnRows = rows_per_item;
   constexpr int X = kNumXcd;
-  std::vector<int> order(jobs.size());
-  for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
-  auto work = [&](int j) { return (double)jobs[(size_t)j].n_rows * jobs[(size_t)j].n_cols; };
-  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return work(a) > work(b); });
-  std::vector<std::vector<KnnItem>> per(X);
+  const int64_t rpi = rows_per_item;
+  const size_t nj = jobs.size();
+  std::vector<int> order(nj);
+  std::vector<double> work(nj);
+  for (size_t i = 0; i < nj; ++i) {
+    order[i] = (int)i;
+    work[i] = (double)jobs[i].n_rows * jobs[i].n_cols;
+  }
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int a, int b) { return work[(size_t)a] > work[(size_t)b]; });
+  // pass 1: a small job's XCD, or a large job's XCD order (3 bits each)
+  std::vector<uint32_t> where(nj);
   double load[X] = {0};
-  auto least = [&]() {
-    int b = 0;
-    for (int x = 1; x < X; ++x)
-      if (load[x] < load[b]) b = x;
-    return b;
-  };
+  int64_t cnt[X] = {0};
   for (int j : order) {
     const KnnJob &J = jobs[(size_t)j];
-    const int nrb = (J.n_rows + kKnnRows - 1) / kKnnRows;
-    const double w_item = (double)kKnnRows * J.n_cols;
+    const int64_t nrb = (J.n_rows + rpi - 1) / rpi;
+    const double w_item = (double)rpi * J.n_cols;
     if (nrb <= 16) {
-      const int x = least();
-      for (int rb = 0; rb < nrb; ++rb) per[x].push_back({j, rb});
-      load[x] += w_item * nrb;
+      int x = 0;
+      for (int y = 1; y < X; ++y)
+        if (load[y] < load[x]) x = y;
+      where[(size_t)j] = (uint32_t)x;
+      load[x] += w_item * (double)nrb;
+      cnt[x] += nrb;
+    } else {
+      int rank[X];
+      for (int q = 0; q < X; ++q) {  // XCDs by rising load (stable insertion)
+        int p = q;
+        while (p > 0 && load[rank[p - 1]] > load[q]) {
+          rank[p] = rank[p - 1];
+          --p;
+        }
+        rank[p] = q;
+      }
+      uint32_t code = 0;
+      for (int q = 0; q < X; ++q) {
+        const int64_t c = nrb / X + (q < nrb % X ? 1 : 0);
+        load[rank[q]] += w_item * (double)c;
+        cnt[rank[q]] += c;
+        code |= (uint32_t)rank[q] << (3 * q);
+      }
+      where[(size_t)j] = code;
+    }
+  }
+  int64_t mx = 0;
+  for (int x = 0; x < X; ++x) mx = std::max(mx, cnt[x]);
+  std::vector<KnnItem> items((size_t)(mx * X));
+  // pass 2: the items in place
+  int64_t cur[X] = {0};
+  for (int j : order) {
+    const KnnJob &J = jobs[(size_t)j];
+    const int nrb = (int)((J.n_rows + rpi - 1) / rpi);
+    const uint32_t w = where[(size_t)j];
+    if (nrb <= 16) {
+      const int x = (int)w;
+      for (int rb = 0; rb < nrb; ++rb) items[(size_t)((cur[x] + rb) * X + x)] = KnnItem{j, rb};
+      cur[x] += nrb;
     } else {
       for (int rb = 0; rb < nrb; ++rb) {
-        const int x = least();
-        per[x].push_back({j, rb});
-        load[x] += w_item;
+        const int x = (int)((w >> (3 * (rb % X))) & 7u);
+        items[(size_t)(cur[x]++ * X + x)] = KnnItem{j, rb};
       }
     }
   }
-  size_t mx = 0;
-  for (auto &v : per) mx = std::max(mx, v.size());
-  std::vector<KnnItem> items(mx * X, KnnItem{-1, 0});
   for (int x = 0; x < X; ++x)
-    for (size_t i = 0; i < per[x].size(); ++i) items[i * X + x] = per[x][i];
+    for (int64_t i = cur[x]; i < mx; ++i) items[(size_t)(i * X + x)] = KnnItem{-1, 0};
   return items;
 }
 

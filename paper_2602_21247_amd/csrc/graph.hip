@@ -260,13 +260,12 @@ __device__ __forceinline__ void rp_select(uint32_t mlo, uint32_t mhi, int nv, in
   if (lane == 0) degree[x] = (uint32_t)ne;
 }
 
-// Steps 1 and the per-slot records shared by the MFMA forms: the valid
-// candidates compacted into sIw in slot order; returns their count.
-__device__ __forceinline__ int rp_compact(const uint64_t *__restrict__ res, int l_max, uint32_t x,
-                                          int64_t n, uint32_t *sIw) {
+// Step 1, shared by the MFMA forms: the valid candidates (rv: this lane's
+// reservoir word) compacted into sIw in slot order; returns their count.
+__device__ __forceinline__ int rp_compact(uint64_t rv, int l_max, uint32_t x, int64_t n,
+                                          uint32_t *sIw) {
   const int lane = threadIdx.x & 63;
-  uint32_t c = kEmptyId;
-  if (lane < l_max) c = slot_id(res[(int64_t)x * l_max + lane]);
+  const uint32_t c = slot_id(rv);
   const bool ok = lane < l_max && c != kEmptyId && c != x && c < n;
   const uint64_t m = __ballot(ok);
   const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
@@ -277,8 +276,7 @@ __device__ __forceinline__ int rp_compact(const uint64_t *__restrict__ res, int 
 // d(x, slot) of this lane's two slots (lanes j and 32 + j hold the lower and
 // upper half sums of slots j and 32 + j) into the per-slot records.
 template <bool L2>
-__device__ __forceinline__ void rp_records(float s0, float s1, int nv,
-                                           const float *__restrict__ norms, float *sDw,
+__device__ __forceinline__ void rp_records(float s0, float s1, int nv, float nrm, float *sDw,
                                            float *sNw, uint64_t *sKw, const uint32_t *sIw) {
   const int lane = threadIdx.x & 63;
   const int h = lane >> 5;
@@ -291,7 +289,7 @@ __device__ __forceinline__ void rp_records(float s0, float s1, int nv,
   if (lane < nv) {
     const uint32_t cid = sIw[lane];
     sDw[lane] = dxm;
-    sNw[lane] = L2 ? norms[cid] : 0.f;
+    sNw[lane] = nrm;
     sKw[lane] = ((uint64_t)f32_rank(dxm) << 32) | cid;
   }
 }
@@ -313,8 +311,9 @@ __global__ void __launch_bounds__(64 * kRpWaves, 4) robustprune_mfma_kernel(
   const int64_t item = (int64_t)xcd_item(blockIdx.x, gridDim.x) * kRpWaves + wave;
   if (item >= n_items) return;
   const uint32_t x = __builtin_amdgcn_readfirstlane(order ? order[item] : (uint32_t)item);
+  const uint64_t rv = lane < l_max ? res[(int64_t)x * l_max + lane] : (uint64_t)kEmptyId;
   // 1. valid candidates in slot order (FULL: d == DP)
-  const int nv = rp_compact(res, l_max, x, n, sI[wave]);
+  const int nv = rp_compact(rv, l_max, x, n, sI[wave]);
   wave_sync();
 
   // 2. fragments F0 (slots 0..31) and F1 (slots 32..63), taken CH
@@ -328,7 +327,7 @@ __global__ void __launch_bounds__(64 * kRpWaves, 4) robustprune_mfma_kernel(
   f32x16 g00, g01, g11;
 #pragma unroll
   for (int v = 0; v < 16; ++v) { g00[v] = 0.f; g01[v] = 0.f; g11[v] = 0.f; }
-  float s0 = 0.f, s1 = 0.f;
+  float s0 = 0.f, s1 = 0.f, nrm = 0.f;
   const bool both = nv > 32;
   {
     const int kb = h * HALF;
@@ -336,6 +335,9 @@ __global__ void __launch_bounds__(64 * kRpWaves, 4) robustprune_mfma_kernel(
     // columns no decision reads (the rank sets hold valid slots only)
     const bool v0 = l32 < nv, v1 = 32 + l32 < nv;
     const uint32_t c0 = v0 ? sI[wave][l32] : x, c1 = v1 ? sI[wave][32 + l32] : x;
+    // the norm of this lane's record slot (lane j: slot j, lane 32 + j: slot
+    // 32 + j), loaded with the rows
+    nrm = (L2 && lane < nv) ? norms[h == 0 ? c0 : c1] : 0.f;
     const float *r0 = X + (int64_t)c0 * d + kb;
     const float *r1 = X + (int64_t)c1 * d + kb;
     const float *rx = X + (int64_t)x * d + kb;
@@ -400,7 +402,7 @@ __global__ void __launch_bounds__(64 * kRpWaves, 4) robustprune_mfma_kernel(
       __builtin_amdgcn_sched_barrier(0);
     }
   }
-  rp_records<L2>(s0, s1, nv, norms, sD[wave], sN[wave], sK[wave], sI[wave]);
+  rp_records<L2>(s0, s1, nv, nrm, sD[wave], sN[wave], sK[wave], sI[wave]);
   // block 10 (rows 32..63, columns 0..31) is block 01 transposed: T[r][c] =
   // G[r][32 + c] is written from block 01's layout and read back in block
   // 10's, G[32 + r][c] = T[c][r] (rows padded to 33 words)
@@ -463,8 +465,9 @@ __global__ void __launch_bounds__(64 * kRpWaves, 4) robustprune_mfma16_kernel(
   const int64_t item = (int64_t)xcd_item(blockIdx.x, gridDim.x) * kRpWaves + wave;
   if (item >= n_items) return;
   const uint32_t x = __builtin_amdgcn_readfirstlane(order ? order[item] : (uint32_t)item);
+  const uint64_t rv = lane < l_max ? res[(int64_t)x * l_max + lane] : (uint64_t)kEmptyId;
 
-  const int nv = rp_compact(res, l_max, x, n, sI[wave]);
+  const int nv = rp_compact(rv, l_max, x, n, sI[wave]);
   wave_sync();
 
   auto val = [](uint32_t code) -> float {
@@ -473,13 +476,16 @@ __global__ void __launch_bounds__(64 * kRpWaves, 4) robustprune_mfma16_kernel(
   };
   typedef _Float16 h2_t __attribute__((ext_vector_type(2)));
   uint4 a0[NA], a1[NA];
-  float s0 = 0.f, s1 = 0.f;
+  float s0 = 0.f, s1 = 0.f, nrm = 0.f;
   const bool both = nv > 32;
   {
     // slots past nv read x's own row: finite values whose Gram rows and
     // columns no decision reads (the rank sets hold valid slots only)
     const bool v0 = l32 < nv, v1 = 32 + l32 < nv;
     const uint32_t c0 = v0 ? sI[wave][l32] : x, c1 = v1 ? sI[wave][32 + l32] : x;
+    // the norm of this lane's record slot (lane j: slot j, lane 32 + j: slot
+    // 32 + j), loaded with the rows
+    nrm = (L2 && lane < nv) ? norms[h == 0 ? c0 : c1] : 0.f;
     const uint4 *r0 = reinterpret_cast<const uint4 *>(Xop + (int64_t)c0 * CB + h * HALF * 2);
     const uint4 *r1 = reinterpret_cast<const uint4 *>(Xop + (int64_t)c1 * CB + h * HALF * 2);
     const uint4 *rx = reinterpret_cast<const uint4 *>(Xop + (int64_t)x * CB + h * HALF * 2);
@@ -523,7 +529,7 @@ __global__ void __launch_bounds__(64 * kRpWaves, 4) robustprune_mfma16_kernel(
       }
     }
   }
-  rp_records<L2>(s0, s1, nv, norms, sD[wave], sN[wave], sK[wave], sI[wave]);
+  rp_records<L2>(s0, s1, nv, nrm, sD[wave], sN[wave], sK[wave], sI[wave]);
   wave_sync();
   typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
   typedef _Float16 f16x8_t __attribute__((ext_vector_type(8)));
