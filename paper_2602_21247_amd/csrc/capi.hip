@@ -934,7 +934,7 @@ pipnn_status pipnn_partition_replica(pipnn_index *idx, int32_t replica, int64_t 
     L.persistent = 0;
     // float32 leader distances in the four-lane layout (where built), the
     // reduced-precision ones in the two-lane layout
-    L.quad = part_prec == PIPNN_PREC_FP32 && knn_quad_available(I.d, PIPNN_PREC_FP32) ? 1 : 0;
+    L.quad = knn_quad_available(I.d, part_prec) ? 1 : 0;
     L.out_col = I.p_asg.as<uint32_t>();
     L.out_dist = nullptr;
     L.out_matrix = nullptr;

@@ -607,7 +607,7 @@ static hipError_t launch_knn_quad(KnnArgs args, int n_items, int n_cu, hipStream
 template <int PREC, int DP>
 static hipError_t launch_knn_quad_k(const KnnArgs &a, int ksel, int n_items, int n_cu,
                                     hipStream_t s) {
-  if constexpr (PREC == PIPNN_PREC_FP32) {
+  if constexpr (PREC == PIPNN_PREC_FP32 || DP <= 256) {
     if (ksel <= 4) return launch_knn_quad<PREC, DP, 4>(a, n_items, n_cu, s);
   }
   if (ksel <= 16) return launch_knn_quad<PREC, DP, 16>(a, n_items, n_cu, s);

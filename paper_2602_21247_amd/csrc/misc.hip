@@ -13,8 +13,10 @@ namespace pipnn {
 // takes the integer check: chk[0] is set when a coordinate is not an
 // integer of magnitude <= 2^20, chk[1] / chk[2] collect the smallest and
 // largest coordinate (one atomic per wave, only when it would change them).
+// A coordinate is flagged here when it is not an integer (NaN included);
+// infinities and magnitudes above 2^20 show in the wave's lo / hi.
 __device__ __forceinline__ void coord_check(float v, bool &bad, float &lo, float &hi) {
-  bad |= !(fabsf(v) <= 1048576.f) || v != rintf(v);
+  bad |= v != rintf(v);
   lo = fminf(lo, v);
   hi = fmaxf(hi, v);
 }
@@ -27,40 +29,78 @@ __global__ void __launch_bounds__(256) norms_sketches_kernel(const float *__rest
   // The block's 256 rows pass through LDS 16 dimensions at a time: the slab
   // is loaded with consecutive lanes on consecutive 16-byte pieces of the
   // rows (coalesced), then each thread continues its own row's sums in
-  // dimension order from LDS.
+  // dimension order from LDS. The next slab's pieces are loaded into
+  // registers while the current one is summed.
   constexpr int KD = 16;
   __shared__ float sX[256][KD + 1];             // the slab (+1: conflict-free row reads)
   __shared__ float sHk[16][KD];                 // the slab's columns of the hyperplanes (m <= 16)
   const int64_t p0 = (int64_t)blockIdx.x * 256;
   const int64_t p = p0 + threadIdx.x;
   const int rows = (int)min<int64_t>(256, n - p0);
+  const bool vec = (d & 3) == 0;
   bool bad = false;
   float lo = INFINITY, hi = -INFINITY;
   float nn = 0.f;
   float sk[16];
 #pragma unroll
   for (int b = 0; b < 16; ++b) sk[b] = 0.f;
-  for (int k0 = 0; k0 < d; k0 += KD) {
+  // this thread's pieces of slab k0: float4 pieces t = threadIdx.x + 256 i
+  // (row t / 4, columns 4 (t % 4) ...) when d is a multiple of 4, else
+  // single values t = threadIdx.x + 256 i (row t / kw, column t % kw)
+  float pf[KD];
+  auto load = [&](int k0) {
     const int kw = min(KD, d - k0);
-    __syncthreads();  // the previous slab is consumed
+    if (vec) {
+      const int pr = kw >> 2;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int t = threadIdx.x + 256 * i;
+        const int r = t / pr, c = (t - r * pr) * 4;
+        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (t < rows * pr) v = *reinterpret_cast<const float4 *>(X + (p0 + r) * d + k0 + c);
+        pf[4 * i] = v.x; pf[4 * i + 1] = v.y; pf[4 * i + 2] = v.z; pf[4 * i + 3] = v.w;
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < KD; ++i) {
+        const int t = threadIdx.x + 256 * i;
+        const int r = t / kw, c = t - r * kw;
+        pf[i] = t < rows * kw ? X[(p0 + r) * d + k0 + c] : 0.f;
+      }
+    }
+  };
+  auto stage = [&](int k0) {
+    const int kw = min(KD, d - k0);
     for (int t = threadIdx.x; t < m * kw; t += 256) {
       const int b = t / kw, c = t - b * kw;
       sHk[b][c] = H[b * d + k0 + c];
     }
-    if ((d & 3) == 0) {
-      // kw is a multiple of 4: 4-float pieces, kw / 4 per row
+    if (vec) {
       const int pr = kw >> 2;
-      for (int t = threadIdx.x; t < rows * pr; t += 256) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int t = threadIdx.x + 256 * i;
         const int r = t / pr, c = (t - r * pr) * 4;
-        const float4 v = *reinterpret_cast<const float4 *>(X + (p0 + r) * d + k0 + c);
-        sX[r][c] = v.x; sX[r][c + 1] = v.y; sX[r][c + 2] = v.z; sX[r][c + 3] = v.w;
+        if (t < rows * pr) {
+          sX[r][c] = pf[4 * i]; sX[r][c + 1] = pf[4 * i + 1];
+          sX[r][c + 2] = pf[4 * i + 2]; sX[r][c + 3] = pf[4 * i + 3];
+        }
       }
     } else {
-      for (int t = threadIdx.x; t < rows * kw; t += 256) {
+#pragma unroll
+      for (int i = 0; i < KD; ++i) {
+        const int t = threadIdx.x + 256 * i;
         const int r = t / kw, c = t - r * kw;
-        sX[r][c] = X[(p0 + r) * d + k0 + c];
+        if (t < rows * kw) sX[r][c] = pf[i];
       }
     }
+  };
+  load(0);
+  for (int k0 = 0; k0 < d; k0 += KD) {
+    const int kw = min(KD, d - k0);
+    __syncthreads();  // the previous slab is consumed
+    stage(k0);
+    if (k0 + KD < d) load(k0 + KD);
     __syncthreads();
     if (p < n) {
       for (int j = 0; j < kw; ++j) {
@@ -80,13 +120,14 @@ __global__ void __launch_bounds__(256) norms_sketches_kernel(const float *__rest
       if (b < m) S[p * m + b] = sk[b];
   }
   // the wave's check (lanes past n hold the neutral +inf / -inf)
-  const bool wbad = __ballot(bad) != 0ull;
+  bool wbad = __ballot(bad) != 0ull;
   if (!wbad) {
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) {
       lo = fminf(lo, __shfl_xor(lo, off, 64));
       hi = fmaxf(hi, __shfl_xor(hi, off, 64));
     }
+    wbad = lo <= hi && (lo < -1048576.f || hi > 1048576.f);
   }
   if ((threadIdx.x & 63) == 0 && chk) {
     if (wbad) {
@@ -240,6 +281,57 @@ __global__ void __launch_bounds__(256) quantize_kernel(const float *__restrict__
   if (__ballot(lossy) != 0ull && lane == 0 && *(volatile int *)inexact == 0) *inexact = 1;
 }
 
+// The two-byte codes (bf16, fp16) of rows whose padded width ldo is 64, 128,
+// 256 or 512 and whose width d is a multiple of 4: one lane per 8 values
+// (two 16-byte loads, one 16-byte store), the G = ldo / 8 lanes of a point
+// consecutive in the wave; the squared norm of the decoded values is summed
+// per lane in index order, then over the point's lanes.
+template <int PREC>
+__global__ void __launch_bounds__(256) quantize16_kernel(const float *__restrict__ X, int64_t n,
+                                                         int d, int lg, uint4 *__restrict__ out,
+                                                         float *__restrict__ norms,
+                                                         int *__restrict__ inexact) {
+  const int G = 1 << lg;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t p = t >> lg;
+  const int c = (int)(t & (G - 1));
+  float nn = 0.f;
+  bool lossy = false;
+  if (p < n) {
+    const float *x = X + p * d + 8 * c;
+    float v[8];
+#pragma unroll
+    for (int hh = 0; hh < 2; ++hh) {
+      float4 q = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (8 * c + 4 * hh < d) q = *reinterpret_cast<const float4 *>(x + 4 * hh);
+      v[4 * hh] = q.x; v[4 * hh + 1] = q.y; v[4 * hh + 2] = q.z; v[4 * hh + 3] = q.w;
+    }
+    uint32_t w[4];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      uint32_t code;
+      float q;
+      if constexpr (PREC == PIPNN_PREC_BF16) {
+        code = enc_bf16(v[j]);
+        q = __uint_as_float(code << 16);
+      } else {
+        const _Float16 hv = (_Float16)v[j];
+        code = __builtin_bit_cast(uint16_t, hv);
+        q = (float)hv;
+      }
+      if (j & 1) w[j >> 1] |= code << 16;
+      else w[j >> 1] = code;
+      nn = fmaf(q, q, nn);
+      lossy |= q != v[j];
+    }
+    out[t] = make_uint4(w[0], w[1], w[2], w[3]);
+  }
+  for (int off = G >> 1; off >= 1; off >>= 1) nn += __shfl_xor(nn, off, 64);
+  if (p < n && c == 0) norms[p] = nn;
+  if (__ballot(lossy) != 0ull && (threadIdx.x & 63) == 0 && *(volatile int *)inexact == 0)
+    *inexact = 1;
+}
+
 // One thread per 16-byte chunk of the padded rows: float32 values, zeros
 // past d.
 __global__ void __launch_bounds__(256) pad_kernel(const float *__restrict__ X, int64_t n, int d,
@@ -276,6 +368,19 @@ hipError_t launch_quantize_range(const Index &I, int64_t p0, int64_t cnt, hipStr
   const int64_t blocks = (cnt + 3) / 4;
   if (!I.xlow.p || I.copy_prec == PIPNN_PREC_FP32) return hipErrorInvalidValue;
   const size_t eb = I.copy_prec == PIPNN_PREC_FP8 ? 1 : 2;
+  const int lg = I.ldo == 64 ? 3 : I.ldo == 128 ? 4 : I.ldo == 256 ? 5 : I.ldo == 512 ? 6 : 0;
+  if (eb == 2 && lg && I.d % 4 == 0 && (reinterpret_cast<uintptr_t>(I.xf()) & 15u) == 0) {
+    const int64_t threads = cnt << lg;
+    auto go = [&](auto kern) {
+      hipLaunchKernelGGL(kern, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s,
+                         I.xf() + p0 * I.d, cnt, I.d, lg,
+                         reinterpret_cast<uint4 *>(I.xlow.as<uint8_t>() + p0 * I.ldo * eb),
+                         I.lnorms.as<float>() + p0, I.op_flag.as<int>());
+    };
+    if (I.copy_prec == PIPNN_PREC_BF16) go(quantize16_kernel<PIPNN_PREC_BF16>);
+    else go(quantize16_kernel<PIPNN_PREC_FP16>);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(quantize_kernel, dim3((unsigned)blocks), dim3(256), 0, s, I.xf() + p0 * I.d,
                      cnt, I.d, I.ldo, I.copy_prec,
                      reinterpret_cast<void *>(I.xlow.as<uint8_t>() + p0 * I.ldo * eb),
