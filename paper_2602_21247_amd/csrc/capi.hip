@@ -970,7 +970,8 @@ pipnn_status pipnn_partition_replica(pipnn_index *idx, int32_t replica, int64_t 
     HIPCHK(launch_groupby(I.p_asg.as<uint32_t>(), A, &fm, I.s_tmp0.as<GroupSub>(),
                           I.p_groups.as<GroupTile>(), (int32_t)tiles.size(), kGroupTile,
                           I.p_cm.as<int64_t>(), cm_len, I.s_off.as<int64_t>(),
-                          I.p_G.as<uint32_t>(), I.p_bstart.as<int64_t>(), nbuck + 1, s));
+                          I.p_G.as<uint32_t>(), I.p_bstart.as<int64_t>(), nbuck + 1,
+                          *std::max_element(ells.begin(), ells.end()), s));
     std::vector<int64_t> bstart((size_t)nbuck + 1);
     HIPCHK(hipMemcpyAsync(bstart.data(), I.p_bstart.p, bstart.size() * 8, hipMemcpyDeviceToHost,
                           s));

@@ -274,7 +274,7 @@ hipError_t launch_groupby(const uint32_t *asg_col, const uint32_t *src_ids, int3
                           const GroupSub *subs, const GroupTile *tiles, int32_t n_tiles,
                           int32_t tile_elems, int64_t *cm, int64_t cm_len, int64_t *tmp,
                           uint32_t *out, int64_t *bucket_start, int64_t n_buckets_total,
-                          hipStream_t s);
+                          int32_t max_buckets, hipStream_t s);
 struct MergeGroup {
   int64_t src_off[1];
 };

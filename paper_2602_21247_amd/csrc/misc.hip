@@ -29,78 +29,40 @@ __global__ void __launch_bounds__(256) norms_sketches_kernel(const float *__rest
   // The block's 256 rows pass through LDS 16 dimensions at a time: the slab
   // is loaded with consecutive lanes on consecutive 16-byte pieces of the
   // rows (coalesced), then each thread continues its own row's sums in
-  // dimension order from LDS. The next slab's pieces are loaded into
-  // registers while the current one is summed.
+  // dimension order from LDS.
   constexpr int KD = 16;
   __shared__ float sX[256][KD + 1];             // the slab (+1: conflict-free row reads)
   __shared__ float sHk[16][KD];                 // the slab's columns of the hyperplanes (m <= 16)
   const int64_t p0 = (int64_t)blockIdx.x * 256;
   const int64_t p = p0 + threadIdx.x;
   const int rows = (int)min<int64_t>(256, n - p0);
-  const bool vec = (d & 3) == 0;
   bool bad = false;
   float lo = INFINITY, hi = -INFINITY;
   float nn = 0.f;
   float sk[16];
 #pragma unroll
   for (int b = 0; b < 16; ++b) sk[b] = 0.f;
-  // this thread's pieces of slab k0: float4 pieces t = threadIdx.x + 256 i
-  // (row t / 4, columns 4 (t % 4) ...) when d is a multiple of 4, else
-  // single values t = threadIdx.x + 256 i (row t / kw, column t % kw)
-  float pf[KD];
-  auto load = [&](int k0) {
+  for (int k0 = 0; k0 < d; k0 += KD) {
     const int kw = min(KD, d - k0);
-    if (vec) {
-      const int pr = kw >> 2;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int t = threadIdx.x + 256 * i;
-        const int r = t / pr, c = (t - r * pr) * 4;
-        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (t < rows * pr) v = *reinterpret_cast<const float4 *>(X + (p0 + r) * d + k0 + c);
-        pf[4 * i] = v.x; pf[4 * i + 1] = v.y; pf[4 * i + 2] = v.z; pf[4 * i + 3] = v.w;
-      }
-    } else {
-#pragma unroll
-      for (int i = 0; i < KD; ++i) {
-        const int t = threadIdx.x + 256 * i;
-        const int r = t / kw, c = t - r * kw;
-        pf[i] = t < rows * kw ? X[(p0 + r) * d + k0 + c] : 0.f;
-      }
-    }
-  };
-  auto stage = [&](int k0) {
-    const int kw = min(KD, d - k0);
+    __syncthreads();  // the previous slab is consumed
     for (int t = threadIdx.x; t < m * kw; t += 256) {
       const int b = t / kw, c = t - b * kw;
       sHk[b][c] = H[b * d + k0 + c];
     }
-    if (vec) {
+    if ((d & 3) == 0) {
+      // kw is a multiple of 4: 4-float pieces, kw / 4 per row
       const int pr = kw >> 2;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int t = threadIdx.x + 256 * i;
+      for (int t = threadIdx.x; t < rows * pr; t += 256) {
         const int r = t / pr, c = (t - r * pr) * 4;
-        if (t < rows * pr) {
-          sX[r][c] = pf[4 * i]; sX[r][c + 1] = pf[4 * i + 1];
-          sX[r][c + 2] = pf[4 * i + 2]; sX[r][c + 3] = pf[4 * i + 3];
-        }
+        const float4 v = *reinterpret_cast<const float4 *>(X + (p0 + r) * d + k0 + c);
+        sX[r][c] = v.x; sX[r][c + 1] = v.y; sX[r][c + 2] = v.z; sX[r][c + 3] = v.w;
       }
     } else {
-#pragma unroll
-      for (int i = 0; i < KD; ++i) {
-        const int t = threadIdx.x + 256 * i;
+      for (int t = threadIdx.x; t < rows * kw; t += 256) {
         const int r = t / kw, c = t - r * kw;
-        if (t < rows * kw) sX[r][c] = pf[i];
+        sX[r][c] = X[(p0 + r) * d + k0 + c];
       }
     }
-  };
-  load(0);
-  for (int k0 = 0; k0 < d; k0 += KD) {
-    const int kw = min(KD, d - k0);
-    __syncthreads();  // the previous slab is consumed
-    stage(k0);
-    if (k0 + KD < d) load(k0 + KD);
     __syncthreads();
     if (p < n) {
       for (int j = 0; j < kw; ++j) {
@@ -756,37 +718,52 @@ __global__ void __launch_bounds__(64) group_hist_kernel(const uint32_t *asg, con
     cm[sb.cm_off + (int64_t)t * sb.n_tiles + tl.tile] = hist[t];
 }
 
+// The scatter of a tile, 64 elements at a time: each element ORs its lane
+// bit into its bucket's LDS mask; an element's rank among the chunk's
+// elements of its bucket is the count of lower lanes in that mask, so the
+// elements keep their order, and the bucket's first element advances the
+// bucket's position by the count and clears the mask. LDS: the buckets'
+// positions, then their masks (max_buckets of each).
 __global__ void __launch_bounds__(64) group_scatter_kernel(const uint32_t *asg,
                                                            const uint32_t *src_ids, int32_t fmax,
                                                            const GroupSub *subs,
                                                            const GroupTile *tiles,
-                                                           const int64_t *cm, uint32_t *out) {
-  __shared__ int64_t pos[kMaxLeaders];
+                                                           const int64_t *cm, uint32_t *out,
+                                                           int32_t max_buckets) {
+  extern __shared__ int64_t gs_lds[];
+  int64_t *pos = gs_lds;
+  unsigned long long *mask = reinterpret_cast<unsigned long long *>(gs_lds + max_buckets);
   const GroupTile tl = tiles[blockIdx.x];
   const GroupSub sb = subs[tl.sub];
   const int lane = threadIdx.x;
-  for (int t = lane; t < sb.n_buckets; t += 64)
+  for (int t = lane; t < sb.n_buckets; t += 64) {
     pos[t] = cm[sb.cm_off + (int64_t)t * sb.n_tiles + tl.tile];
+    mask[t] = 0ull;
+  }
   wave_sync();
   const int64_t e0 = sb.elem_off + (int64_t)tl.tile * kGroupTile;
   const int64_t e1 = min(e0 + kGroupTile, sb.elem_off + sb.n_elems);
-  const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   for (int64_t c = e0; c < e1; c += 64) {
     const int64_t e = c + lane;
-    const bool valid = e < e1;
-    const uint32_t t = valid ? asg[e] : kEmptyId;
-    uint64_t todo = __ballot(valid && t != kEmptyId);
+    const uint32_t t = e < e1 ? asg[e] : kEmptyId;
+    const bool live = t != kEmptyId;
+    if (live) atomicOr(&mask[t], 1ull << lane);
+    wave_sync();
     int64_t mypos = -1;
-    while (todo) {
-      const int leader = __ffsll((long long)todo) - 1;
-      const uint32_t bt = __shfl(t, leader, 64);
-      const uint64_t same = __ballot(t == bt) & todo;
-      if (t == bt && ((todo >> lane) & 1ull)) mypos = pos[bt] + __popcll(same & below);
-      wave_sync();
-      if (lane == leader) pos[bt] += __popcll(same);
-      wave_sync();
-      todo &= ~same;
+    int cnt = 0;
+    if (live) {
+      const unsigned long long m = mask[t];
+      const int rank = __popcll(m & below);
+      mypos = pos[t] + rank;
+      cnt = rank == 0 ? __popcll(m) : 0;
     }
+    wave_sync();
+    if (cnt > 0) {
+      pos[t] += cnt;
+      mask[t] = 0ull;
+    }
+    wave_sync();
     if (mypos >= 0) out[mypos] = src_ids[e / fmax];
   }
 }
@@ -801,15 +778,16 @@ hipError_t launch_groupby(const uint32_t *asg_col, const uint32_t *src_ids, int3
                           const GroupSub *subs, const GroupTile *tiles, int32_t n_tiles,
                           int32_t tile_elems, int64_t *cm, int64_t cm_len, int64_t *tmp,
                           uint32_t *out, int64_t *bucket_start, int64_t n_buckets_total,
-                          hipStream_t s) {
+                          int32_t max_buckets, hipStream_t s) {
   (void)tile_elems;
   const int32_t fmax = *fan;
   if (n_tiles == 0) return hipSuccess;
+  if (max_buckets < 1 || max_buckets > kMaxLeaders) return hipErrorInvalidValue;
   hipLaunchKernelGGL(group_hist_kernel, dim3(n_tiles), dim3(64), 0, s, asg_col, subs, tiles, cm);
   hipError_t e = launch_scan_i64_inplace(cm, cm_len, tmp, s);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(group_scatter_kernel, dim3(n_tiles), dim3(64), 0, s, asg_col, src_ids, fmax,
-                     subs, tiles, cm, out);
+  hipLaunchKernelGGL(group_scatter_kernel, dim3(n_tiles), dim3(64), (size_t)max_buckets * 16, s,
+                     asg_col, src_ids, fmax, subs, tiles, cm, out, max_buckets);
   // bucket_start holds, on entry, the cm index of every bucket's first tile
   hipLaunchKernelGGL(bucket_start_kernel, dim3((unsigned)((n_buckets_total + 255) / 256)),
                      dim3(256), 0, s, cm, bucket_start, n_buckets_total, bucket_start);
