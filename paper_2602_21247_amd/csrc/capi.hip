@@ -172,6 +172,24 @@ hipError_t upload(DevBuf &b, const std::vector<T> &v, hipStream_t s) {
 
 constexpr int kGroupTile = 1024;
 
+// Indices 0..n-1 by falling w, equal values by rising index: a stable LSD
+// radix sort (8-bit digits) of max(w) - w.
+std::vector<int> order_by_falling(const std::vector<uint64_t> &w) {
+  const size_t n = w.size();
+  uint64_t mx = 0;
+  for (uint64_t v : w) mx = std::max(mx, v);
+  std::vector<int> a(n), b(n);
+  for (size_t i = 0; i < n; ++i) a[i] = (int)i;
+  for (int shift = 0; shift < 64 && (mx >> shift) != 0; shift += 8) {
+    size_t cnt[257] = {0};
+    for (size_t i = 0; i < n; ++i) ++cnt[(((mx - w[(size_t)a[i]]) >> shift) & 255u) + 1];
+    for (int k = 0; k < 256; ++k) cnt[k + 1] += cnt[k];
+    for (size_t i = 0; i < n; ++i) b[cnt[((mx - w[(size_t)a[i]]) >> shift) & 255u]++] = a[i];
+    a.swap(b);
+  }
+  return a;
+}
+
 // Work items of a knn launch in launch order: block b runs on XCD b % 8 and
 // takes item b. Jobs are taken largest first (by rows x columns); a job of
 // at most 16 row blocks goes whole to the least-loaded XCD (its columns stay
@@ -184,28 +202,23 @@ std::vector<KnnItem> plan_items(const std::vector<KnnJob> &jobs, int rows_per_it
   constexpr int X = kNumXcd;
   const int64_t rpi = rows_per_item;
   const size_t nj = jobs.size();
-  std::vector<int> order(nj);
-  std::vector<double> work(nj);
-  for (size_t i = 0; i < nj; ++i) {
-    order[i] = (int)i;
-    work[i] = (double)jobs[i].n_rows * jobs[i].n_cols;
-  }
-  std::stable_sort(order.begin(), order.end(),
-                   [&](int a, int b) { return work[(size_t)a] > work[(size_t)b]; });
+  std::vector<uint64_t> work(nj);
+  for (size_t i = 0; i < nj; ++i) work[i] = (uint64_t)jobs[i].n_rows * (uint64_t)jobs[i].n_cols;
+  const std::vector<int> order = order_by_falling(work);
   // pass 1: a small job's XCD, or a large job's XCD order (3 bits each)
   std::vector<uint32_t> where(nj);
-  double load[X] = {0};
+  int64_t load[X] = {0};
   int64_t cnt[X] = {0};
   for (int j : order) {
     const KnnJob &J = jobs[(size_t)j];
     const int64_t nrb = (J.n_rows + rpi - 1) / rpi;
-    const double w_item = (double)rpi * J.n_cols;
+    const int64_t w_item = rpi * (int64_t)J.n_cols;
     if (nrb <= 16) {
       int x = 0;
       for (int y = 1; y < X; ++y)
         if (load[y] < load[x]) x = y;
       where[(size_t)j] = (uint32_t)x;
-      load[x] += w_item * (double)nrb;
+      load[x] += w_item * nrb;
       cnt[x] += nrb;
     } else {
       int rank[X];
@@ -220,7 +233,7 @@ std::vector<KnnItem> plan_items(const std::vector<KnnJob> &jobs, int rows_per_it
       uint32_t code = 0;
       for (int q = 0; q < X; ++q) {
         const int64_t c = nrb / X + (q < nrb % X ? 1 : 0);
-        load[rank[q]] += w_item * (double)c;
+        load[rank[q]] += w_item * c;
         cnt[rank[q]] += c;
         code |= (uint32_t)rank[q] << (3 * q);
       }
