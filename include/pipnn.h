@@ -471,6 +471,10 @@ typedef struct {
   int64_t n_points;              /* current point count */
   int64_t workspace_bytes;       /* the workspace layout in use (0: the index allocates) */
   int64_t batch_rows;            /* leaf rows per pick + binning batch of a build */
+  int32_t rp_row_bits;           /* element width of the rows pipnn_robustprune reads: 8 (the
+                                    int8 rows of an integral float32 X spanning <= 256 values,
+                                    L2), 16 (the exact 16-bit copy) or 32 (float32) */
+  int32_t reserved_;
 } pipnn_stats;
 
 /* Switch phase timing on (1; also clears the sums) or off (0). */

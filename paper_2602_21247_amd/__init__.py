@@ -60,7 +60,8 @@ class Stats(C.Structure):
                 ("ms_prepare", C.c_double), ("ms_partition", C.c_double),
                 ("ms_leaf_knn", C.c_double), ("ms_bin", C.c_double), ("ms_merge", C.c_double),
                 ("ms_robustprune", C.c_double), ("epoch", C.c_uint64), ("n_points", C.c_int64),
-                ("workspace_bytes", C.c_int64), ("batch_rows", C.c_int64)]
+                ("workspace_bytes", C.c_int64), ("batch_rows", C.c_int64),
+                ("rp_row_bits", C.c_int32), ("reserved_", C.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

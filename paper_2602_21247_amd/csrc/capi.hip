@@ -419,6 +419,7 @@ hipError_t refresh_fp32_copy(Index &I, hipStream_t s) {
   const bool capturing = stream_capturing(s);
   if (!I.int_exact) {
     if (!capturing) I.op_exact = false;
+    I.i8_ok = false;
     return hipSuccess;
   }
   hipError_t e;
@@ -432,8 +433,21 @@ hipError_t refresh_fp32_copy(Index &I, hipStream_t s) {
         (e = I.op_flag.ensure(64)) != hipSuccess)
       return e;
   }
-  if ((e = clear_op_flag(I, s)) != hipSuccess || (e = launch_quantize(I, s)) != hipSuccess)
+  // the int8 rows (L2): coordinates of range <= 255 fit int8 after the shift
+  I.i8_ok = false;
+  const bool with8 =
+      I.p.metric == PIPNN_METRIC_L2 && I.int_hi - I.int_lo <= 255 && (I.x8.p || !capturing);
+  if (with8) {
+    I.ld8 = rows8_width(I.d);
+    const size_t c = (size_t)I.cap;
+    if ((e = I.x8.ensure(c * I.ld8)) != hipSuccess || (e = I.n8.ensure(c * 4)) != hipSuccess)
+      return e;
+    I.lo8 = I.int_lo;
+  }
+  if ((e = clear_op_flag(I, s)) != hipSuccess ||
+      (e = launch_quantize_range(I, 0, I.n, s, with8)) != hipSuccess)
     return e;
+  I.i8_ok = with8;
   return capturing ? hipSuccess : read_op_flag(I, true, s);
 }
 
@@ -501,7 +515,7 @@ std::vector<DevBuf *> all_bufs(Index &I) {
           &I.p_elen, &I.o_first, &I.o_flag, &I.o_pos, &I.o_pos2, &I.o_tmp, &I.plan.jobs,
           &I.plan.items, &I.i_rows, &I.i_cols, &I.i_assign, &I.i_flag, &I.i_pos, &I.i_list,
           &I.i_tmp, &I.i_segs, &I.q_conv, &I.q_seen, &I.g_ids, &I.g_dist, &I.a2a_mat,
-          &I.a2a_tmp};
+          &I.a2a_tmp, &I.x8, &I.n8};
 }
 
 size_t slice_bytes(size_t b) { return (std::max<size_t>(b, 256) + 255) & ~(size_t)255; }
@@ -532,6 +546,10 @@ void set_limits(Index &I) {
     const size_t eb = P.gemm_prec == PIPNN_PREC_FP8 ? 1 : 2;
     I.xlow.lim = (size_t)n * lowp_padded_dim((int)d) * eb;
     I.xscale.lim = I.lnorms.lim = (size_t)n * 4;
+  }
+  if (P.gemm_prec == PIPNN_PREC_FP32 && d <= 128 && P.metric == PIPNN_METRIC_L2) {
+    I.x8.lim = (size_t)n * rows8_width((int)d);
+    I.n8.lim = (size_t)n * 4;
   }
   I.rp_order.lim = (size_t)n * 4;
   I.lt_off.lim = (size_t)(F + 1) * 8;
@@ -1773,6 +1791,10 @@ pipnn_status pipnn_reserve(pipnn_index *idx, int64_t n_cap, const void *d_X,
     HIPCHK(grow_keep(I.xscale, c * 4, n * 4, s));
     HIPCHK(grow_keep(I.lnorms, c * 4, n * 4, s));
   }
+  if (I.x8.p) {
+    HIPCHK(grow_keep(I.x8, c * I.ld8, n * I.ld8, s));
+    HIPCHK(grow_keep(I.n8, c * 4, n * 4, s));
+  }
   I.cap = n_cap;
   return PIPNN_OK;
   GUARD_END
@@ -1818,7 +1840,7 @@ pipnn_status pipnn_insert(pipnn_index *idx, int64_t n_new, const int32_t *d_grou
   struct Rollback {
     Index &I;
     int64_t n0, int_lo, int_hi;
-    bool int_exact, op_exact, done = false;
+    bool int_exact, op_exact, i8_ok, done = false;
     ~Rollback() {
       if (done) return;
       __atomic_store_n(&I.n, n0, __ATOMIC_RELEASE);
@@ -1826,8 +1848,9 @@ pipnn_status pipnn_insert(pipnn_index *idx, int64_t n_new, const int32_t *d_grou
       I.int_lo = int_lo;
       I.int_hi = int_hi;
       I.op_exact = op_exact;
+      I.i8_ok = i8_ok;
     }
-  } rollback{I, n0, I.int_lo, I.int_hi, I.int_exact, I.op_exact};
+  } rollback{I, n0, I.int_lo, I.int_hi, I.int_exact, I.op_exact, I.i8_ok};
   __atomic_store_n(&I.n, n1, __ATOMIC_RELEASE);
   I.rp_order_valid = false;  // the leaf order covers the old points only
   if (I.x_dtype != PIPNN_DTYPE_F32) {
@@ -1839,10 +1862,15 @@ pipnn_status pipnn_insert(pipnn_index *idx, int64_t n_new, const int32_t *d_grou
   HIPCHK(launch_norms_sketches_range(I, n0, n_new, s));
   HIPCHK(read_int_check(I, false, s));
   HIPCHK(launch_pad_range(I, n0, n_new, s));
+  // the new rows' int8 rows keep the shift while they stay within its range
+  if (I.i8_ok && !(I.int_exact && I.int_lo >= I.lo8 && I.int_hi <= I.lo8 + 255))
+    I.i8_ok = false;
   if (I.xlow.p) {
     HIPCHK(clear_op_flag(I, s));
-    HIPCHK(launch_quantize_range(I, n0, n_new, s));
+    HIPCHK(launch_quantize_range(I, n0, n_new, s, I.i8_ok));
     HIPCHK(read_op_flag(I, false, s));
+  } else if (I.i8_ok) {
+    HIPCHK(launch_quantize8_range(I, n0, n_new, s));
   }
   HIPCHK(launch_fill_u64(d_reservoirs + n0 * P.l_max, empty_slot(), n_new * P.l_max, s));
 
@@ -2416,6 +2444,7 @@ pipnn_status pipnn_get_stats(pipnn_index *idx, pipnn_stats *h_out) {
   st.leaf_knn_launches = I.leaf_launches;
   st.operand_exact = I.op_exact ? 1 : 0;
   st.data_int_exact = I.int_exact ? 1 : 0;
+  st.rp_row_bits = rp_row_bits(I);
   st.ms_prepare = I.phase_ms[kPhPrepare];
   st.ms_partition = I.phase_ms[kPhPartition];
   st.ms_leaf_knn = I.phase_ms[kPhLeafKnn];

@@ -578,6 +578,114 @@ __global__ void __launch_bounds__(64 * kRpWaves, 4) robustprune_mfma16_kernel(
   rp_select(mlo, mhi, nv, R, x, sK[wave], sI[wave], graph, degree);
 }
 
+typedef int i32x4_t __attribute__((ext_vector_type(4)));
+typedef int i32x16_t __attribute__((ext_vector_type(16)));
+
+// The same RobustPrune (L2) on the index's int8 rows (x - lo8 - 128 of an
+// integral X whose coordinates span at most 256 values, DB bytes per row):
+// the rows are a quarter of the float32 bytes and half the fp16 ones. Every
+// distance is an integer below 2^24 and L2 is translation invariant, so
+// d(x,c) = |x'|^2 + |c'|^2 - 2 x'.c' (x'.c' by v_dot4_i32_i8, each half
+// wave's partial sum plus the other's) and the Gram (v_mfma_i32_32x32x32_i8)
+// are exact: d(x,c) is the float32 direct difference's value, and every
+// decision the float32 kernel's.
+template <int DB>
+__global__ void __launch_bounds__(64 * kRpWaves, 4) robustprune_i8_kernel(
+    const uint8_t *__restrict__ X8, const float *__restrict__ n8, int64_t n,
+    const uint64_t *__restrict__ res, int l_max, float alpha, int R,
+    const uint32_t *__restrict__ order, int64_t n_items, uint32_t *__restrict__ graph,
+    uint32_t *__restrict__ degree) {
+  constexpr int HB = DB / 2;   // bytes of a row per half wave
+  constexpr int NA = HB / 16;  // 16-byte vectors per lane
+  __shared__ __align__(16) uint64_t sK[kRpWaves][64];
+  __shared__ __align__(16) float sD[kRpWaves][64];
+  __shared__ __align__(16) float sN[kRpWaves][64];
+  __shared__ uint32_t sI[kRpWaves][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int h = lane >> 5, l32 = lane & 31;
+  const int64_t item = (int64_t)xcd_item(blockIdx.x, gridDim.x) * kRpWaves + wave;
+  if (item >= n_items) return;
+  const uint32_t x = __builtin_amdgcn_readfirstlane(order ? order[item] : (uint32_t)item);
+  const uint64_t rv = lane < l_max ? res[(int64_t)x * l_max + lane] : (uint64_t)kEmptyId;
+
+  const int nv = rp_compact(rv, l_max, x, n, sI[wave]);
+  wave_sync();
+
+  uint4 a0[NA], a1[NA];
+  const bool both = nv > 32;
+  {
+    // slots past nv read x's own row: finite values whose Gram rows and
+    // columns no decision reads (the rank sets hold valid slots only)
+    const bool v0 = l32 < nv, v1 = 32 + l32 < nv;
+    const uint32_t c0 = v0 ? sI[wave][l32] : x, c1 = v1 ? sI[wave][32 + l32] : x;
+    const float nrm = lane < nv ? n8[h == 0 ? c0 : c1] : 0.f;
+    const float nx = n8[x];
+    const uint4 *r0 = reinterpret_cast<const uint4 *>(X8 + (int64_t)c0 * DB + h * HB);
+    const uint4 *r1 = reinterpret_cast<const uint4 *>(X8 + (int64_t)c1 * DB + h * HB);
+    const uint4 *rx = reinterpret_cast<const uint4 *>(X8 + (int64_t)x * DB + h * HB);
+    int p0 = 0, p1 = 0;
+#pragma unroll
+    for (int sv = 0; sv < NA; ++sv) {
+      a0[sv] = r0[sv];
+      a1[sv] = r1[sv];
+      const uint4 qx = rx[sv];
+      p0 = __builtin_amdgcn_sdot4((int)a0[sv].x, (int)qx.x, p0, false);
+      p0 = __builtin_amdgcn_sdot4((int)a0[sv].y, (int)qx.y, p0, false);
+      p0 = __builtin_amdgcn_sdot4((int)a0[sv].z, (int)qx.z, p0, false);
+      p0 = __builtin_amdgcn_sdot4((int)a0[sv].w, (int)qx.w, p0, false);
+      p1 = __builtin_amdgcn_sdot4((int)a1[sv].x, (int)qx.x, p1, false);
+      p1 = __builtin_amdgcn_sdot4((int)a1[sv].y, (int)qx.y, p1, false);
+      p1 = __builtin_amdgcn_sdot4((int)a1[sv].z, (int)qx.z, p1, false);
+      p1 = __builtin_amdgcn_sdot4((int)a1[sv].w, (int)qx.w, p1, false);
+    }
+    // lane j < 32 records slot j, lane 32 + j records slot 32 + j
+    const int o0 = __shfl_xor(p0, 32, 64), o1 = __shfl_xor(p1, 32, 64);
+    const int xc = h == 0 ? p0 + o0 : p1 + o1;
+    const float dxm = (float)((int)nx + (int)nrm - 2 * xc);
+    if (lane < nv) {
+      const uint32_t cid = sI[wave][lane];
+      sD[wave][lane] = dxm;
+      sN[wave][lane] = nrm;
+      sK[wave][lane] = ((uint64_t)f32_rank(dxm) << 32) | cid;
+    }
+  }
+  wave_sync();
+  auto gram = [&](const uint4 *p, const uint4 *q) -> f32x16 {
+    i32x16_t g;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) g[v] = 0;
+#pragma unroll
+    for (int sv = 0; sv < NA; ++sv)
+      g = __builtin_amdgcn_mfma_i32_32x32x32_i8(__builtin_bit_cast(i32x4_t, p[sv]),
+                                                __builtin_bit_cast(i32x4_t, q[sv]), g, 0, 0, 0);
+    f32x16 f;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) f[v] = (float)g[v];  // exact: |G| < 2^24
+    return f;
+  };
+  const float *sNw = sN[wave];
+  const float nA = sNw[l32], xA = 0.f - sD[wave][l32];
+  uint32_t mlo, mhi = 0u;
+  if (both) {
+    const float nB = sNw[32 + l32], xB = 0.f - sD[wave][32 + l32];
+    const f32x16 g00 = gram(a0, a0);
+    const f32x16 g01 = gram(a0, a1);
+    const uint32_t c00 = rp_sign_bits<true>(g00, sNw, 0, nA, xA, alpha);
+    const f32x16 g10 = gram(a1, a0);
+    const uint32_t c01 = rp_sign_bits<true>(g01, sNw, 0, nB, xB, alpha);
+    const f32x16 g11 = gram(a1, a1);
+    const uint32_t c10 = rp_sign_bits<true>(g10, sNw, 32, nA, xA, alpha);
+    const uint32_t c11 = rp_sign_bits<true>(g11, sNw, 32, nB, xB, alpha);
+    mlo = rp_join(c00, c01);
+    mhi = rp_join(c10, c11);
+  } else {
+    const f32x16 g00 = gram(a0, a0);
+    const uint32_t c00 = rp_sign_bits<true>(g00, sNw, 0, nA, xA, alpha);
+    mlo = c00 | ((uint32_t)__shfl_xor((int)c00, 32, 64) << 4);
+  }
+  rp_select(mlo, mhi, nv, R, x, sK[wave], sI[wave], graph, degree);
+}
+
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
@@ -760,6 +868,19 @@ __global__ void __launch_bounds__(256, 1) robustprune_wide_kernel(
   if (lane == 0) degree[x] = (uint32_t)ne;
 }
 
+int rp_row_bits(const Index &I) {
+  if (I.p.l_max > 64) return I.p.l_max <= kRpwRows - 1 && I.p.R <= 64 && I.xlow.p &&
+                             (I.p.gemm_prec == PIPNN_PREC_FP16 || I.p.gemm_prec == PIPNN_PREC_BF16) &&
+                             (I.ldo == 512 || I.ldo == 768) ? 16 : 32;
+  if (I.p.metric == PIPNN_METRIC_L2 && I.i8_ok && I.x8.p && (I.ld8 == 64 || I.ld8 == 128))
+    return 8;
+  if (I.copy16_exact() && (I.ldo == 64 || I.ldo == 96 || I.ldo == 128)) return 16;
+  if (I.d <= 128) return 32;
+  const bool wide_op = (I.p.gemm_prec == PIPNN_PREC_FP16 || I.p.gemm_prec == PIPNN_PREC_BF16) &&
+                       (I.ldo == 512 || I.ldo == 768) && I.xlow.p;
+  return wide_op && I.p.R <= 64 ? 16 : 32;
+}
+
 hipError_t launch_robustprune(const Index &I, const uint64_t *res, uint32_t *graph, uint32_t *degree,
                               const uint32_t *subset, int64_t n_subset, hipStream_t s) {
   if (I.p.l_max > 256 || I.p.R > 256) return hipErrorInvalidValue;
@@ -769,6 +890,16 @@ hipError_t launch_robustprune(const Index &I, const uint64_t *res, uint32_t *gra
   if (n_items <= 0) return hipSuccess;
   const bool op16 = I.copy16_exact();
   const bool l2 = I.p.metric == PIPNN_METRIC_L2;
+  if (rp_row_bits(I) == 8) {
+    const int64_t blocks = xcd_grid((n_items + kRpWaves - 1) / kRpWaves);
+    auto go = [&](auto kern) {
+      hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(64 * kRpWaves), 0, s,
+                         I.x8.as<uint8_t>(), I.n8.as<float>(), I.n, res, I.p.l_max, I.p.alpha,
+                         I.p.R, order, n_items, graph, degree);
+    };
+    I.ld8 == 64 ? go(robustprune_i8_kernel<64>) : go(robustprune_i8_kernel<128>);
+    return hipGetLastError();
+  }
   if (I.p.l_max <= 64 && op16 && (I.ldo == 64 || I.ldo == 96 || I.ldo == 128)) {
     const int64_t blocks = xcd_grid((n_items + kRpWaves - 1) / kRpWaves);
     auto go = [&](auto kern) {

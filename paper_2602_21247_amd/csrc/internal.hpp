@@ -73,6 +73,15 @@ struct Index {
   bool int_exact = false;
   int64_t int_lo = 0, int_hi = 0;
   int32_t ldo = 0;  // row stride (elements) of xlow: d padded by lowp_padded_dim
+  // int8 rows for RobustPrune (L2, float32 index of at most 128 dimensions):
+  // while X is integral and every coordinate lies in [lo8, lo8 + 255], row
+  // p holds x_p - lo8 - 128 (zero padded to ld8 bytes) and n8 its squared
+  // norm; distances are translation invariant, so every L2 distance form
+  // is the same integer on these rows
+  DevBuf x8, n8;
+  int32_t ld8 = 0;
+  int64_t lo8 = 0;
+  bool i8_ok = false;
   DevBuf xpad;      // float32 GEMM operand zero padded to ldf, when X itself cannot serve
   int32_t ldf = 0;  // row stride (floats) of the float32 GEMM operand; 0: d > 256
   DevBuf sketches;  // n x m float32
@@ -216,6 +225,10 @@ inline int lowp_padded_dim(int d) {
        : d <= 768 ? 768 : 0;
 }
 
+// Bytes per int8 row (d <= 128): 64 or 128, so that a row is whole MFMA
+// k-steps of 32 split over the two half-waves.
+inline int rows8_width(int d) { return d <= 64 ? 64 : 128; }
+
 // ---- misc kernels ----------------------------------------------------
 hipError_t launch_norms_sketches(const Index &I, hipStream_t s);
 // The index's reduced-precision operand (I.p.gemm_prec): codes into I.xlow
@@ -224,7 +237,11 @@ hipError_t launch_norms_sketches(const Index &I, hipStream_t s);
 hipError_t launch_quantize(const Index &I, hipStream_t s);
 // the same for points [p0, p0 + cnt) only
 hipError_t launch_norms_sketches_range(const Index &I, int64_t p0, int64_t cnt, hipStream_t s);
-hipError_t launch_quantize_range(const Index &I, int64_t p0, int64_t cnt, hipStream_t s);
+hipError_t launch_quantize_range(const Index &I, int64_t p0, int64_t cnt, hipStream_t s,
+                                 bool with8 = false);
+// The int8 rows and their norms (I.x8, I.n8) of points [p0, p0 + cnt)
+// (launch_quantize_range with with8 writes them in its own pass where it can).
+hipError_t launch_quantize8_range(const Index &I, int64_t p0, int64_t cnt, hipStream_t s);
 // Clear the encoder's inexact flag (a fill kernel, so it may be captured),
 // and, outside capture, read it back into I.op_exact (synchronizes s):
 // `reset` clears op_exact first for a full re-encode.
@@ -317,6 +334,8 @@ hipError_t launch_reservoir_canonical(const uint64_t *in, uint64_t *out, int64_t
 // ---- RobustPrune / search ---------------------------------------------
 // RobustPrune of every point (subset NULL; in leaf order when known) or of
 // the n_subset points listed in subset.
+// Element width (8, 16 or 32 bits) of the rows launch_robustprune reads.
+int rp_row_bits(const Index &I);
 hipError_t launch_robustprune(const Index &I, const uint64_t *res, uint32_t *graph, uint32_t *degree,
                               const uint32_t *subset, int64_t n_subset, hipStream_t s);
 hipError_t launch_leaf_order(const uint32_t *mem, int64_t cnt, int64_t n, uint32_t *first,

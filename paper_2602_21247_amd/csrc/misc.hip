@@ -248,16 +248,21 @@ __global__ void __launch_bounds__(256) quantize_kernel(const float *__restrict__
 // (two 16-byte loads, one 16-byte store), the G = ldo / 8 lanes of a point
 // consecutive in the wave; the squared norm of the decoded values is summed
 // per lane in index order, then over the point's lanes.
-template <int PREC>
+// With I8 the same pass also writes the int8 rows (x - base, base = lo8 +
+// 128; 8 bytes per lane) and their exact squared norms.
+template <int PREC, bool I8>
 __global__ void __launch_bounds__(256) quantize16_kernel(const float *__restrict__ X, int64_t n,
                                                          int d, int lg, uint4 *__restrict__ out,
                                                          float *__restrict__ norms,
-                                                         int *__restrict__ inexact) {
+                                                         int *__restrict__ inexact, float base,
+                                                         uint2 *__restrict__ out8,
+                                                         float *__restrict__ norms8) {
   const int G = 1 << lg;
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t p = t >> lg;
   const int c = (int)(t & (G - 1));
   float nn = 0.f;
+  int n8 = 0;
   bool lossy = false;
   if (p < n) {
     const float *x = X + p * d + 8 * c;
@@ -267,6 +272,16 @@ __global__ void __launch_bounds__(256) quantize16_kernel(const float *__restrict
       float4 q = make_float4(0.f, 0.f, 0.f, 0.f);
       if (8 * c + 4 * hh < d) q = *reinterpret_cast<const float4 *>(x + 4 * hh);
       v[4 * hh] = q.x; v[4 * hh + 1] = q.y; v[4 * hh + 2] = q.z; v[4 * hh + 3] = q.w;
+    }
+    if constexpr (I8) {
+      uint32_t b[2] = {0u, 0u};
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int q = 8 * c + j < d ? (int)(v[j] - base) : 0;  // padding gives 0
+        n8 += q * q;
+        b[j >> 2] |= ((uint32_t)q & 0xFFu) << (8 * (j & 3));
+      }
+      out8[t] = make_uint2(b[0], b[1]);
     }
     uint32_t w[4];
 #pragma unroll
@@ -290,8 +305,66 @@ __global__ void __launch_bounds__(256) quantize16_kernel(const float *__restrict
   }
   for (int off = G >> 1; off >= 1; off >>= 1) nn += __shfl_xor(nn, off, 64);
   if (p < n && c == 0) norms[p] = nn;
+  if constexpr (I8) {
+    for (int off = G >> 1; off >= 1; off >>= 1) n8 += __shfl_xor(n8, off, 64);
+    if (p < n && c == 0) norms8[p] = (float)n8;
+  }
   if (__ballot(lossy) != 0ull && (threadIdx.x & 63) == 0 && *(volatile int *)inexact == 0)
     *inexact = 1;
+}
+
+// The int8 rows of an integral float32 X whose coordinates lie in
+// [lo8, lo8 + 255]: value x - lo8 - 128 (exact), zero past d (a zero
+// coordinate adds nothing to any dot product or norm), one lane per 16
+// values (one 16-byte store), the G = ld8 / 16 lanes of a point consecutive
+// in the wave; the squared norm is an exact integer sum.
+__global__ void __launch_bounds__(256) quantize8_kernel(const float *__restrict__ X, int64_t n,
+                                                        int d, int lg, float base, bool vec,
+                                                        uint4 *__restrict__ out,
+                                                        float *__restrict__ norms) {
+  const int G = 1 << lg;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t p = t >> lg;
+  const int c = (int)(t & (G - 1));
+  int nn = 0;
+  if (p < n) {
+    const float *x = X + p * d + 16 * c;
+    float v[16];
+    if (vec) {
+#pragma unroll
+      for (int j4 = 0; j4 < 4; ++j4) {
+        float4 q = make_float4(base, base, base, base);
+        if (16 * c + 4 * j4 < d) q = *reinterpret_cast<const float4 *>(x + 4 * j4);
+        v[4 * j4] = q.x; v[4 * j4 + 1] = q.y; v[4 * j4 + 2] = q.z; v[4 * j4 + 3] = q.w;
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < 16; ++j) v[j] = 16 * c + j < d ? x[j] : base;
+    }
+    uint32_t w[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const int q = (int)(v[j] - base);  // base = lo8 + 128; padding gives 0
+      nn += q * q;
+      w[j >> 2] |= ((uint32_t)q & 0xFFu) << (8 * (j & 3));
+    }
+    out[t] = make_uint4(w[0], w[1], w[2], w[3]);
+  }
+  for (int off = G >> 1; off >= 1; off >>= 1) nn += __shfl_xor(nn, off, 64);
+  if (p < n && c == 0) norms[p] = (float)nn;
+}
+
+hipError_t launch_quantize8_range(const Index &I, int64_t p0, int64_t cnt, hipStream_t s) {
+  if (cnt <= 0) return hipSuccess;
+  if (!I.x8.p || !I.n8.p || (I.ld8 != 64 && I.ld8 != 128)) return hipErrorInvalidValue;
+  const int lg = I.ld8 == 64 ? 2 : 3;
+  const int64_t threads = cnt << lg;
+  const bool vec = I.d % 4 == 0 && (reinterpret_cast<uintptr_t>(I.xf()) & 15u) == 0;
+  hipLaunchKernelGGL(quantize8_kernel, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s,
+                     I.xf() + p0 * I.d, cnt, I.d, lg, (float)(I.lo8 + 128), vec,
+                     reinterpret_cast<uint4 *>(I.x8.as<uint8_t>() + p0 * I.ld8),
+                     I.n8.as<float>() + p0);
+  return hipGetLastError();
 }
 
 // One thread per 16-byte chunk of the padded rows: float32 values, zeros
@@ -322,26 +395,42 @@ hipError_t launch_pad_range(const Index &I, int64_t p0, int64_t cnt, hipStream_t
 }
 
 hipError_t launch_quantize(const Index &I, hipStream_t s) {
-  return launch_quantize_range(I, 0, I.n, s);
+  return launch_quantize_range(I, 0, I.n, s, false);
 }
 
-hipError_t launch_quantize_range(const Index &I, int64_t p0, int64_t cnt, hipStream_t s) {
+hipError_t launch_quantize_range(const Index &I, int64_t p0, int64_t cnt, hipStream_t s,
+                                 bool with8) {
   if (cnt <= 0) return hipSuccess;
   const int64_t blocks = (cnt + 3) / 4;
   if (!I.xlow.p || I.copy_prec == PIPNN_PREC_FP32) return hipErrorInvalidValue;
   const size_t eb = I.copy_prec == PIPNN_PREC_FP8 ? 1 : 2;
   const int lg = I.ldo == 64 ? 3 : I.ldo == 128 ? 4 : I.ldo == 256 ? 5 : I.ldo == 512 ? 6 : 0;
   if (eb == 2 && lg && I.d % 4 == 0 && (reinterpret_cast<uintptr_t>(I.xf()) & 15u) == 0) {
+    // the int8 rows in the same pass where their width is the copy's
+    const bool fuse8 = with8 && I.copy_prec == PIPNN_PREC_FP16 && I.x8.p && I.ld8 == I.ldo;
     const int64_t threads = cnt << lg;
     auto go = [&](auto kern) {
       hipLaunchKernelGGL(kern, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s,
                          I.xf() + p0 * I.d, cnt, I.d, lg,
                          reinterpret_cast<uint4 *>(I.xlow.as<uint8_t>() + p0 * I.ldo * eb),
-                         I.lnorms.as<float>() + p0, I.op_flag.as<int>());
+                         I.lnorms.as<float>() + p0, I.op_flag.as<int>(), (float)(I.lo8 + 128),
+                         fuse8 ? reinterpret_cast<uint2 *>(I.x8.as<uint8_t>() + p0 * I.ld8)
+                               : nullptr,
+                         fuse8 ? I.n8.as<float>() + p0 : nullptr);
     };
-    if (I.copy_prec == PIPNN_PREC_BF16) go(quantize16_kernel<PIPNN_PREC_BF16>);
-    else go(quantize16_kernel<PIPNN_PREC_FP16>);
+    if (I.copy_prec == PIPNN_PREC_BF16) go(quantize16_kernel<PIPNN_PREC_BF16, false>);
+    else if (fuse8) go(quantize16_kernel<PIPNN_PREC_FP16, true>);
+    else go(quantize16_kernel<PIPNN_PREC_FP16, false>);
+    if (with8 && !fuse8) {
+      hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+      return launch_quantize8_range(I, p0, cnt, s);
+    }
     return hipGetLastError();
+  }
+  if (with8) {
+    hipError_t e = launch_quantize8_range(I, p0, cnt, s);
+    if (e != hipSuccess) return e;
   }
   hipLaunchKernelGGL(quantize_kernel, dim3((unsigned)blocks), dim3(256), 0, s, I.xf() + p0 * I.d,
                      cnt, I.d, I.ldo, I.copy_prec,
