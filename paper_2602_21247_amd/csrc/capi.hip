@@ -451,6 +451,26 @@ hipError_t refresh_fp32_copy(Index &I, hipStream_t s) {
   return capturing ? hipSuccess : read_op_flag(I, true, s);
 }
 
+// The int8 rows of an index whose GEMM operand is a reduced-precision copy
+// (the float32 index makes them with its fp16 copy, above): kept while X is
+// integral and spans at most 256 values (L2, d <= 128).
+hipError_t refresh_rows8(Index &I, hipStream_t s) {
+  const bool capturing = stream_capturing(s);
+  const bool want = I.p.metric == PIPNN_METRIC_L2 && I.d <= 128 && I.int_exact &&
+                    I.int_hi - I.int_lo <= 255 && (I.x8.p || !capturing);
+  I.i8_ok = false;
+  if (!want) return hipSuccess;
+  I.ld8 = rows8_width(I.d);
+  const size_t c = (size_t)I.cap;
+  hipError_t e;
+  if ((e = I.x8.ensure(c * I.ld8)) != hipSuccess || (e = I.n8.ensure(c * 4)) != hipSuccess)
+    return e;
+  I.lo8 = I.int_lo;
+  if ((e = launch_quantize8_range(I, 0, I.n, s)) != hipSuccess) return e;
+  I.i8_ok = true;
+  return hipSuccess;
+}
+
 // ---------------------------------------------------------------------
 // Workspace layout. Every device buffer of an index has a worst-case size
 // that follows from the parameters, n, d, the dtype of X and the leaf rows
@@ -547,7 +567,7 @@ void set_limits(Index &I) {
     I.xlow.lim = (size_t)n * lowp_padded_dim((int)d) * eb;
     I.xscale.lim = I.lnorms.lim = (size_t)n * 4;
   }
-  if (P.gemm_prec == PIPNN_PREC_FP32 && d <= 128 && P.metric == PIPNN_METRIC_L2) {
+  if (d <= 128 && P.metric == PIPNN_METRIC_L2) {
     I.x8.lim = (size_t)n * rows8_width((int)d);
     I.n8.lim = (size_t)n * 4;
   }
@@ -791,6 +811,9 @@ pipnn_status pipnn_create(const pipnn_params *p, const void *d_X, int64_t n, int
     if ((e = clear_op_flag(*I, s)) != hipSuccess || (e = launch_quantize(*I, s)) != hipSuccess ||
         (e = read_op_flag(*I, true, s)) != hipSuccess)
       return cleanup(fail(PIPNN_EDEVICE, "quantize launch failed: %s", hipGetErrorString(e)));
+    if ((e = refresh_rows8(*I, s)) != hipSuccess)
+      return cleanup(fail(e == hipErrorOutOfMemory ? PIPNN_ENOMEM : PIPNN_EDEVICE,
+                          "int8 rows failed: %s", hipGetErrorString(e)));
   }
   if ((e = hipMemsetAsync(I->flag.p, 0, 64, s)) != hipSuccess)
     return cleanup(fail(PIPNN_EDEVICE, "memset failed: %s", hipGetErrorString(e)));
@@ -2416,6 +2439,7 @@ pipnn_status pipnn_prepare(pipnn_index *idx, pipnn_stream_t stream) {
     // outside capture the operand's exactness is taken again; a captured
     // prepare keeps the one found by the last uncaptured encode
     if (!stream_capturing(s)) HIPCHK(read_op_flag(I, true, s));
+    HIPCHK(refresh_rows8(I, s));
   } else {
     HIPCHK(refresh_fp32_copy(I, s));
   }
