@@ -1,4 +1,6 @@
 // Final RobustPrune (Alg. 2, Sec. 4.3) and BeamSearch (Alg. 1) on gfx950.
+#include <cmath>
+
 #include "common.hpp"
 #include "internal.hpp"
 
@@ -586,20 +588,25 @@ typedef int i32x16_t __attribute__((ext_vector_type(16)));
 // the rows are a quarter of the float32 bytes and half the fp16 ones. Every
 // distance is an integer below 2^24 and L2 is translation invariant, so
 // d(x,c) = |x'|^2 + |c'|^2 - 2 x'.c' (x'.c' by v_dot4_i32_i8, each half
-// wave's partial sum plus the other's) and the Gram (v_mfma_i32_32x32x32_i8)
-// are exact: d(x,c) is the float32 direct difference's value, and every
-// decision the float32 kernel's.
+// wave's partial sum plus the other's) is the float32 direct difference's
+// value, and the prune test becomes integer arithmetic: with alpha = am *
+// 2^-ash exactly, fma(alpha, d(y,z), -d(x,z)) < 0 (one rounding of an exact
+// multiple of 2^-ash, so its sign is exact) holds iff d(y,z) < t_z, t_z the
+// least integer with am * t_z >= d(x,z) * 2^ash. So the Gram MFMA
+// (v_mfma_i32_32x32x32_i8) starts from t_z - 1 - |z'|^2 - |y'|^2 and takes
+// each k-step twice: entry (y,z) ends as t_z - 1 - d(y,z), >= 0 exactly when
+// y prunes z, and its sign bit is the complement of the pruner bit.
 template <int DB>
 __global__ void __launch_bounds__(64 * kRpWaves, 4) robustprune_i8_kernel(
     const uint8_t *__restrict__ X8, const float *__restrict__ n8, int64_t n,
-    const uint64_t *__restrict__ res, int l_max, float alpha, int R,
+    const uint64_t *__restrict__ res, int l_max, float alpha, uint32_t am, int ash, int R,
     const uint32_t *__restrict__ order, int64_t n_items, uint32_t *__restrict__ graph,
     uint32_t *__restrict__ degree) {
   constexpr int HB = DB / 2;   // bytes of a row per half wave
   constexpr int NA = HB / 16;  // 16-byte vectors per lane
   __shared__ __align__(16) uint64_t sK[kRpWaves][64];
   __shared__ __align__(16) float sD[kRpWaves][64];
-  __shared__ __align__(16) float sN[kRpWaves][64];
+  __shared__ __align__(16) int sN[kRpWaves][64];  // |c'|^2
   __shared__ uint32_t sI[kRpWaves][64];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int h = lane >> 5, l32 = lane & 31;
@@ -618,8 +625,8 @@ __global__ void __launch_bounds__(64 * kRpWaves, 4) robustprune_i8_kernel(
     // columns no decision reads (the rank sets hold valid slots only)
     const bool v0 = l32 < nv, v1 = 32 + l32 < nv;
     const uint32_t c0 = v0 ? sI[wave][l32] : x, c1 = v1 ? sI[wave][32 + l32] : x;
-    const float nrm = lane < nv ? n8[h == 0 ? c0 : c1] : 0.f;
-    const float nx = n8[x];
+    const int nrm = lane < nv ? (int)n8[h == 0 ? c0 : c1] : 0;
+    const int nx = (int)n8[x];
     const uint4 *r0 = reinterpret_cast<const uint4 *>(X8 + (int64_t)c0 * DB + h * HB);
     const uint4 *r1 = reinterpret_cast<const uint4 *>(X8 + (int64_t)c1 * DB + h * HB);
     const uint4 *rx = reinterpret_cast<const uint4 *>(X8 + (int64_t)x * DB + h * HB);
@@ -641,7 +648,7 @@ __global__ void __launch_bounds__(64 * kRpWaves, 4) robustprune_i8_kernel(
     // lane j < 32 records slot j, lane 32 + j records slot 32 + j
     const int o0 = __shfl_xor(p0, 32, 64), o1 = __shfl_xor(p1, 32, 64);
     const int xc = h == 0 ? p0 + o0 : p1 + o1;
-    const float dxm = (float)((int)nx + (int)nrm - 2 * xc);
+    const float dxm = (float)(nx + nrm - 2 * xc);
     if (lane < nv) {
       const uint32_t cid = sI[wave][lane];
       sD[wave][lane] = dxm;
@@ -650,37 +657,54 @@ __global__ void __launch_bounds__(64 * kRpWaves, 4) robustprune_i8_kernel(
     }
   }
   wave_sync();
-  auto gram = [&](const uint4 *p, const uint4 *q) -> f32x16 {
+  // t_z - 1 - |z'|^2 for column slot z (d(x,z) < 2^24: the float estimate
+  // of t_z is off by at most one; two exact 48-bit tests settle it)
+  auto col_term = [&](int z) -> int {
+    const float dx = sD[wave][z];
+    const uint64_t num = (uint64_t)(uint32_t)(int)dx << ash;
+    int t = (int)ceilf(dx / alpha);
+    t = t < 1 ? 1 : t;
+    if ((uint64_t)(uint32_t)(t - 1) * am >= num) --t;
+    if ((uint64_t)(uint32_t)t * am < num) ++t;
+    return t - 1 - sN[wave][z];
+  };
+  // pruner bits of column z of block (rows row0 + acc_row32(v, h)), laid out
+  // as rp_sign_bits lays them out
+  auto pruners = [&](const uint4 *p, const uint4 *q, int row0, int cz) -> uint32_t {
     i32x16_t g;
 #pragma unroll
-    for (int v = 0; v < 16; ++v) g[v] = 0;
+    for (int grp = 0; grp < 4; ++grp) {
+      const int4 ny = *reinterpret_cast<const int4 *>(&sN[wave][row0 + 8 * grp + 4 * h]);
+      g[4 * grp] = cz - ny.x; g[4 * grp + 1] = cz - ny.y;
+      g[4 * grp + 2] = cz - ny.z; g[4 * grp + 3] = cz - ny.w;
+    }
 #pragma unroll
-    for (int sv = 0; sv < NA; ++sv)
-      g = __builtin_amdgcn_mfma_i32_32x32x32_i8(__builtin_bit_cast(i32x4_t, p[sv]),
-                                                __builtin_bit_cast(i32x4_t, q[sv]), g, 0, 0, 0);
-    f32x16 f;
+    for (int sv = 0; sv < NA; ++sv) {
+      const i32x4_t pa = __builtin_bit_cast(i32x4_t, p[sv]), qb = __builtin_bit_cast(i32x4_t, q[sv]);
+      g = __builtin_amdgcn_mfma_i32_32x32x32_i8(pa, qb, g, 0, 0, 0);
+      g = __builtin_amdgcn_mfma_i32_32x32x32_i8(pa, qb, g, 0, 0, 0);
+    }
+    uint32_t b = 0u;
 #pragma unroll
-    for (int v = 0; v < 16; ++v) f[v] = (float)g[v];  // exact: |G| < 2^24
-    return f;
+    for (int grp = 3; grp >= 0; --grp) {
+#pragma unroll
+      for (int j = 3; j >= 0; --j) b = __builtin_amdgcn_alignbit(b, (uint32_t)g[4 * grp + j], 31);
+      if (grp) b <<= 4;
+    }
+    return ~b & 0x0F0F0F0Fu;
   };
-  const float *sNw = sN[wave];
-  const float nA = sNw[l32], xA = 0.f - sD[wave][l32];
+  const int czA = col_term(l32);
   uint32_t mlo, mhi = 0u;
   if (both) {
-    const float nB = sNw[32 + l32], xB = 0.f - sD[wave][32 + l32];
-    const f32x16 g00 = gram(a0, a0);
-    const f32x16 g01 = gram(a0, a1);
-    const uint32_t c00 = rp_sign_bits<true>(g00, sNw, 0, nA, xA, alpha);
-    const f32x16 g10 = gram(a1, a0);
-    const uint32_t c01 = rp_sign_bits<true>(g01, sNw, 0, nB, xB, alpha);
-    const f32x16 g11 = gram(a1, a1);
-    const uint32_t c10 = rp_sign_bits<true>(g10, sNw, 32, nA, xA, alpha);
-    const uint32_t c11 = rp_sign_bits<true>(g11, sNw, 32, nB, xB, alpha);
+    const int czB = col_term(32 + l32);
+    const uint32_t c00 = pruners(a0, a0, 0, czA);
+    const uint32_t c01 = pruners(a0, a1, 0, czB);
+    const uint32_t c10 = pruners(a1, a0, 32, czA);
+    const uint32_t c11 = pruners(a1, a1, 32, czB);
     mlo = rp_join(c00, c01);
     mhi = rp_join(c10, c11);
   } else {
-    const f32x16 g00 = gram(a0, a0);
-    const uint32_t c00 = rp_sign_bits<true>(g00, sNw, 0, nA, xA, alpha);
+    const uint32_t c00 = pruners(a0, a0, 0, czA);
     mlo = c00 | ((uint32_t)__shfl_xor((int)c00, 32, 64) << 4);
   }
   rp_select(mlo, mhi, nv, R, x, sK[wave], sI[wave], graph, degree);
@@ -872,7 +896,8 @@ int rp_row_bits(const Index &I) {
   if (I.p.l_max > 64) return I.p.l_max <= kRpwRows - 1 && I.p.R <= 64 && I.xlow.p &&
                              (I.p.gemm_prec == PIPNN_PREC_FP16 || I.p.gemm_prec == PIPNN_PREC_BF16) &&
                              (I.ldo == 512 || I.ldo == 768) ? 16 : 32;
-  if (I.p.metric == PIPNN_METRIC_L2 && I.i8_ok && I.x8.p && (I.ld8 == 64 || I.ld8 == 128))
+  if (I.p.metric == PIPNN_METRIC_L2 && I.i8_ok && I.x8.p && (I.ld8 == 64 || I.ld8 == 128) &&
+      I.p.alpha < 8388608.f)
     return 8;
   if (I.copy16_exact() && (I.ldo == 64 || I.ldo == 96 || I.ldo == 128)) return 16;
   if (I.d <= 128) return 32;
@@ -892,10 +917,15 @@ hipError_t launch_robustprune(const Index &I, const uint64_t *res, uint32_t *gra
   const bool l2 = I.p.metric == PIPNN_METRIC_L2;
   if (rp_row_bits(I) == 8) {
     const int64_t blocks = xcd_grid((n_items + kRpWaves - 1) / kRpWaves);
+    // alpha = am * 2^-ash exactly (1 <= alpha < 2^23: ash in 1..23)
+    int ex = 0;
+    const float fr = std::frexp(I.p.alpha, &ex);
+    const uint32_t am = (uint32_t)std::ldexp(fr, 24);
+    const int ash = 24 - ex;
     auto go = [&](auto kern) {
       hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(64 * kRpWaves), 0, s,
-                         I.x8.as<uint8_t>(), I.n8.as<float>(), I.n, res, I.p.l_max, I.p.alpha,
-                         I.p.R, order, n_items, graph, degree);
+                         I.x8.as<uint8_t>(), I.n8.as<float>(), I.n, res, I.p.l_max, I.p.alpha, am,
+                         ash, I.p.R, order, n_items, graph, degree);
     };
     I.ld8 == 64 ? go(robustprune_i8_kernel<64>) : go(robustprune_i8_kernel<128>);
     return hipGetLastError();
