@@ -477,8 +477,9 @@ def kernel_rooflines(st, w, n, steps, res_valid, rp_elem, prec):
       merge: 8 B per binned record read + 2 l_max 8 B per point (reservoir
         read and written; HBM);
       RobustPrune: the candidates' rows (valid reservoir slots x d x the
-        element size read) + l_max 8 B of reservoir and R 4 B of graph per
-        point (HBM)."""
+        element size of the rows it reads: 1 B int8, 2 B of a 16-bit copy
+        or 4 B float32) + l_max 8 B of reservoir and R 4 B of graph per point
+        (HBM)."""
     d = w.d
     per = lambda k: st[k] / steps    # phase times are summed over the timed builds
     rec = st["records"]              # counts are those of the last build
@@ -885,7 +886,7 @@ def main():
     traffic = traffic_from_profiles(w.name) if args.prec == "fp32" else None
     peak = PEAK_MFMA_TFLOPS[args.prec]
     res_valid = int(((res & 0xFFFFFFFF) != 0xFFFFFFFF).sum().item())
-    rp_elem = 2 if (st["operand_exact"] and args.prec in ("fp32", "bf16", "fp16")) else 4
+    rp_elem = st["rp_row_bits"] / 8.0   # the rows RobustPrune reads: int8, 16-bit or float32
     roofs = kernel_rooflines(st, w, n, args.steps, res_valid, rp_elem, args.prec)
     dominant = max(roofs, key=lambda k: roofs[k]["ms"])
     main_roof = dict(roofs[dominant])

@@ -556,18 +556,21 @@ def test_robustprune_exact_on_oracle_reservoirs(exact_build):
     idx.close()
 
 
-@pytest.mark.parametrize("shift,span,d,bits", [(0, 256, 128, 8), (100, 256, 64, 8),
-                                               (-128, 256, 96, 8), (0, 300, 32, 16)])
-def test_robustprune_row_forms(shift, span, d, bits):
+@pytest.mark.parametrize("shift,span,d,bits,alpha", [(0, 256, 128, 8, 1.2), (100, 256, 64, 8, 1.0),
+                                                     (-128, 256, 96, 8, 3.75),
+                                                     (0, 256, 128, 8, 1.3),
+                                                     (0, 300, 32, 16, 1.2)])
+def test_robustprune_row_forms(shift, span, d, bits, alpha):
     """RobustPrune reads int8 rows (the coordinates minus the smallest one
-    minus 128) for integral data spanning at most 256 values, the exact
+    minus 128; the prune test in integer arithmetic with alpha's exact
+    binary value) for integral data spanning at most 256 values, the exact
     fp16 copy for a wider integral span; every distance is the same integer
     in each form, so on the build's own reservoirs each gives the oracle's
-    graph."""
+    graph (whose test alpha * d(y,z) < d(x,z) is exact in FP64)."""
     rng = np.random.default_rng(span + d + shift + 1000)
     X = (rng.integers(0, span, size=(2500, d)) + shift).astype(np.float32)
     H = pi.hyperplanes(12, d, seed=d, integer=True)
-    p = gpu_params(c_max=512, c_min=48, k=16, l_max=64, R=32, seed=9)
+    p = gpu_params(c_max=512, c_min=48, k=16, l_max=64, R=32, seed=9, alpha=alpha)
     idx, off, mem, res, g, deg = pp.build(dev(X), dev(H), p)
     torch.cuda.synchronize()
     assert idx.stats()["rp_row_bits"] == bits
