@@ -109,7 +109,12 @@ typedef int32_t pipnn_status;
  *               pipnn_stats.data_int_exact); where that copy holds X
  *               exactly, the partition and RobustPrune read it the same
  *               way (every distance form is then the same integer in
- *               either format) and the leaf GEMM stays FP32.
+ *               either format) and the leaf GEMM stays FP32. An L2 index of
+ *               at most 128 dimensions whose values are integers spanning at
+ *               most 256 consecutive values (any precision) also keeps int8
+ *               rows x - lo - 128; RobustPrune then reads those (a quarter of
+ *               the float32 bytes; exact integer distances, see
+ *               pipnn_stats.rp_row_bits).
  *  rescore_mult 0, or r >= 2: select the r*k nearest by the GEMM distance
  *               and keep the k nearest by an FP32 direct-difference rescore.
  *  leaf_picker  PIPNN_PICKER_*: how a leaf member picks its candidates
@@ -406,11 +411,16 @@ pipnn_status pipnn_reservoir_canonical(const pipnn_index *idx, const uint64_t *d
  * |y|^2 + |c|^2 - 2 y.c (or -y.c) from a Gram on MFMA (up to 64 candidates
  * and 128 dimensions; the 16-bit copy of X when it holds X exactly, see
  * gemm_prec), for 512 / 768-dimension bf16 / fp16 operands both come from
- * the operand's Gram, and otherwise both are direct differences.
+ * the operand's Gram, and otherwise both are direct differences. With the
+ * int8 rows (L2, integral X spanning at most 256 values, d <= 128,
+ * l_max <= 64, alpha < 2^23) every distance is an exact integer (dot4
+ * products and an int8 Gram on MFMA), and the test alpha*d(y,c) < d(x,c)
+ * is taken exactly in integers; pipnn_stats.rp_row_bits names the row
+ * width read (8, 16 or 32).
  * Candidates are taken in (d(x,c), id) order and c is admitted unless an
  * admitted y has alpha*d(y,c) < d(x,c) (evaluated as the sign of one fused
- * multiply-add). Writes d_graph (n x R, admission order, 0xFFFFFFFF
- * padding) and d_degree (n). */
+ * multiply-add, or exactly in integers on the int8 rows). Writes d_graph
+ * (n x R, admission order, 0xFFFFFFFF padding) and d_degree (n). */
 pipnn_status pipnn_robustprune(pipnn_index *idx, const uint64_t *d_reservoirs, uint32_t *d_graph,
                                uint32_t *d_degree, pipnn_stream_t stream);
 
