@@ -83,10 +83,14 @@ def parse():
                          "fp32, or fp16 for the 768-d workload)")
     ap.add_argument("--rescore-mult", type=int, default=0,
                     help="select rescore_mult*k by the GEMM distance, keep k by FP32 rescoring")
-    ap.add_argument("--variants", default="bf16:0,bf16:2,fp8:2,fp32:0:2,fp32:0:1:a2a",
-                    help="other forms (prec:rescore_mult[:replicas[:a2a]], comma separated) built "
-                         "and timed after the main one on the same workload (a2a: the All-to-All "
-                         "Prune leaf picker); '' for none")
+    ap.add_argument("--rescore-extra", type=int, default=0,
+                    help="select k + rescore_extra by the GEMM distance, keep k by FP32 "
+                         "rescoring (instead of --rescore-mult)")
+    ap.add_argument("--variants", default="bf16:0,bf16:2,bf16:+4,fp8:2,fp32:0:2,fp32:0:1:a2a",
+                    help="other forms (prec:rescore[:replicas[:a2a]], comma separated; rescore "
+                         "is rescore_mult, or +e for rescore_extra e) built and timed after the "
+                         "main one on the same workload (a2a: the All-to-All Prune leaf picker); "
+                         "'' for none")
     ap.add_argument("--frontier", action="store_true",
                     help="also build (float32) with other fanouts, leaf k and l_max, and report "
                          "each one's build rate, the beam width reaching recall@10 >= 0.95 and "
@@ -364,6 +368,20 @@ def cpu_baseline(X, H, off, mem, res_np, stats, w, budget):
     }
 
 
+def rescore_kw(spec):
+    """A form's rescoring from its spec: '0' none, 'r' rescore_mult r, '+e'
+    rescore_extra e."""
+    t = str(spec)
+    if t.startswith("+"):
+        return {"rescore_mult": 0, "rescore_extra": int(t[1:])}
+    return {"rescore_mult": int(t), "rescore_extra": 0}
+
+
+def rescore_label(spec):
+    kw = rescore_kw(spec)
+    return f"+{kw['rescore_extra']}" if kw["rescore_extra"] else f"x{kw['rescore_mult']}"
+
+
 def precision_stage(args, torch, np, pp, pi):
     """The precision workload (1,000,000 unit vectors of 96 dimensions from a
     vMF mixture, L2): the float32 leaf GEMM, bf16 and OCP e4m3 with FP32
@@ -387,12 +405,12 @@ def precision_stage(args, torch, np, pp, pi):
     nq = Qd.shape[0]
     forms = []
     sample = None
-    for prec, mult in (("fp32", 0), ("bf16", 2), ("fp8", 2)):
+    for prec, mult in (("fp32", 0), ("bf16", 2), ("bf16", "+4"), ("fp8", 2)):
         p = pp.default_params(metric=w.metric, c_max=w.c_max, c_min=w.c_min, k=w.k,
                               l_max=w.l_max, R=w.R, alpha=w.alpha, hash_bits=w.hash_bits,
                               leader_div=w.leader_div, leader_cap=w.leader_cap, fanout=w.fanout,
                               seed=pi.workload_seed(cfg), gemm_prec=PREC_CODES[prec],
-                              rescore_mult=mult)
+                              **rescore_kw(mult))
         idx = pp.Index(Xd, Hd, p)
         res = torch.empty((n, w.l_max), dtype=torch.int64, device="cuda")
 
@@ -445,7 +463,7 @@ def precision_stage(args, torch, np, pp, pi):
         err = np.abs(gd[valid] - d64)
         rel = err / np.maximum(np.abs(d64), 1e-30)
         within = float(np.mean(err <= np.maximum(1e-5 * np.abs(d64), 1e-6)))
-        f = {"prec": prec, "rescore_mult": mult, "ms_per_step": ms, "points_per_s": n / (ms / 1e3),
+        f = {"prec": prec, **rescore_kw(mult), "ms_per_step": ms, "points_per_s": n / (ms / 1e3),
              "recall_at_10_by_L": curve,
              "leaf_gemm_tflops": 2.0 * st["leaf_pairs"] * w.d * args.precision_steps
              / max(1, st["leaf_knn_launches"]) / (st["ms_leaf_knn"] / max(1, st["leaf_knn_launches"])
@@ -457,7 +475,7 @@ def precision_stage(args, torch, np, pp, pi):
                          "pick_agreement": agree, "max_abs_dist_err": float(err.max()),
                          "max_rel_dist_err": float(rel.max()),
                          "share_within_1e-5_rel": within}}
-        log(f"[bench] precision {prec} x{mult}: {ms:.2f} ms/build, recall {curve}, "
+        log(f"[bench] precision {prec} {rescore_label(mult)}: {ms:.2f} ms/build, recall {curve}, "
             f"picks vs FP64 {agree:.5f}, max rel err {rel.max():.2e}")
         forms.append(f)
         idx.close()
@@ -711,7 +729,7 @@ def main():
                               l_max=fl, R=w.R, alpha=w.alpha, hash_bits=fm,
                               leader_div=w.leader_div, leader_cap=w.leader_cap, fanout=ff,
                               seed=pi.workload_seed(cfg), gemm_prec=PREC_CODES[prec],
-                              rescore_mult=mult, leaf_picker=picker)
+                              leaf_picker=picker, **rescore_kw(mult))
         idx = pp.Index(Xd, Hm.get(fm, Hd), p)
         res = torch.empty((n, fl), dtype=torch.int64, device="cuda")
         tune = None
@@ -729,7 +747,7 @@ def main():
             for i in range(warmup):
                 step()
                 torch.cuda.synchronize()
-                log(f"[bench] {prec} x{mult} r{replicas}: warmup {i + 1}/{warmup} done")
+                log(f"[bench] {prec} {rescore_label(mult)} r{replicas}: warmup {i + 1}/{warmup} done")
             torch.cuda.synchronize()
             idx.set_profiling(True)
             t0 = time.perf_counter()
@@ -743,7 +761,7 @@ def main():
         else:
             off, mem = leaves
             tune = idx.autotune(off, mem)
-            log(f"[bench] {prec} x{mult} r{replicas}: autotune {tune}")
+            log(f"[bench] {prec} {rescore_label(mult)} r{replicas}: autotune {tune}")
             g = torch.empty((n, w.R), dtype=torch.int32, device="cuda")
             deg = torch.empty(n, dtype=torch.int32, device="cuda")
 
@@ -769,14 +787,14 @@ def main():
             for i in range(warmup):
                 graph.replay()
                 torch.cuda.synchronize()
-                log(f"[bench] {prec} x{mult} r{replicas}: warmup replay {i + 1}/{warmup} done")
+                log(f"[bench] {prec} {rescore_label(mult)} r{replicas}: warmup replay {i + 1}/{warmup} done")
             t0 = time.perf_counter()
             for i in range(steps):
                 graph.replay()
             torch.cuda.synchronize()
             t1 = time.perf_counter()
         ms = (t1 - t0) * 1000.0 / steps
-        log(f"[bench] {prec} x{mult} r{replicas}{' a2a' if picker else ''}: {steps} steps, {ms:.2f} ms/step")
+        log(f"[bench] {prec} {rescore_label(mult)} r{replicas}{' a2a' if picker else ''}: {steps} steps, {ms:.2f} ms/step")
         # leaf kernel roofline: dense flops 2 s^2 d per leaf, per launch
         launches = max(1, st["leaf_knn_launches"])
         # leaf_pairs counts the last build_leaves call: one replica's leaves
@@ -794,7 +812,7 @@ def main():
                 hits = (dist.double() <= kth[:, None]).sum().item()
                 r = hits / (nq * 10.0)
                 curve[L] = {"recall": round(r, 5), "cmps": round(cmps.double().mean().item(), 1)}
-                log(f"[bench] {prec} x{mult} r{replicas}: L={L} recall@10={r:.4f} cmps={curve[L]['cmps']}")
+                log(f"[bench] {prec} {rescore_label(mult)} r{replicas}: L={L} recall@10={r:.4f} cmps={curve[L]['cmps']}")
                 if r >= 0.95:
                     l_at, recall = L, r
                     break
@@ -806,7 +824,7 @@ def main():
             idx.search(g, Qd, 10, l_at or RECALL_LS[-1], start, want_cmps=False)
             torch.cuda.synchronize()
             qps = nq / (time.perf_counter() - tq)
-        form = {"prec": prec, "rescore_mult": mult, "replicas": replicas,
+        form = {"prec": prec, **rescore_kw(mult), "replicas": replicas,
                 "leaf_picker": "all-to-all-prune" if picker else "bi-directed-knn",
                 "ms_per_step": ms,
                 "value": n / (ms / 1000.0),
@@ -822,7 +840,8 @@ def main():
             idx.close()
         return form
 
-    main_form = run_form(args.prec, args.rescore_mult, args.steps, args.warmup, keep=True)
+    main_resc = f"+{args.rescore_extra}" if args.rescore_extra else str(args.rescore_mult)
+    main_form = run_form(args.prec, main_resc, args.steps, args.warmup, keep=True)
     idx, res, off, mem, g, deg = main_form.pop("_out")
     st = main_form.pop("stats")
     ms = main_form["ms_per_step"]
@@ -844,10 +863,10 @@ def main():
     variants = []
     for spec in [v for v in args.variants.split(",") if v.strip()]:
         parts = spec.split(":")
-        vp, vm = parts[0], int(parts[1])
+        vp, vm = parts[0], parts[1]
         vr = int(parts[2]) if len(parts) > 2 else 1
         va = 1 if len(parts) > 3 and parts[3] == "a2a" else 0
-        if (vp, vm, vr, va) == (args.prec, args.rescore_mult, 1, 0):
+        if (vp, rescore_kw(vm), vr, va) == (args.prec, rescore_kw(main_resc), 1, 0):
             continue
         if leaves is not None and (vr > 1 or va):
             continue  # explicit leaves: no partition to replicate; leaves above 2,048
@@ -875,7 +894,7 @@ def main():
         p_kw = dict(metric=w.metric, c_max=w.c_max, c_min=w.c_min, k=w.k, l_max=w.l_max, R=w.R,
                     alpha=w.alpha, hash_bits=w.hash_bits, leader_div=w.leader_div,
                     leader_cap=w.leader_cap, fanout=w.fanout, seed=pi.workload_seed(cfg),
-                    gemm_prec=PREC_CODES[args.prec], rescore_mult=args.rescore_mult)
+                    gemm_prec=PREC_CODES[args.prec], **rescore_kw(main_resc))
         L_serve = main_form["L_at_recall_0.95"] or 128
         serve = serving_stage(args, torch, np, pp, pi, w, cfg, X, H, p_kw, L_serve)
 
@@ -893,7 +912,9 @@ def main():
     main_roof["kernel"] = dominant
     main_roof["traffic"] = traffic if dominant == "leaf_knn" else None
     gemm = f"{args.prec}-mfma" + (f", fp32 rescore of top-{args.rescore_mult}k"
-                                  if args.rescore_mult else "")
+                                  if args.rescore_mult else
+                                  f", fp32 rescore of top-(k+{args.rescore_extra})"
+                                  if args.rescore_extra else "")
     line = {
         "metric": "build points/sec at recall@10>=0.95",
         "value": n / (ms / 1000.0),

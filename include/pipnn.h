@@ -117,6 +117,13 @@ typedef int32_t pipnn_status;
  *               pipnn_stats.rp_row_bits).
  *  rescore_mult 0, or r >= 2: select the r*k nearest by the GEMM distance
  *               and keep the k nearest by an FP32 direct-difference rescore.
+ *  rescore_extra 0, or e >= 1 (k + e <= 32; rescore_mult then 0): select
+ *               the k + e nearest by the GEMM distance, i.e. the k winners and
+ *               the e just past the boundary, and keep the k nearest of them
+ *               by the same rescore. A smaller margin than r*k: the selection
+ *               keeps shorter lists (its cost grows with their length) and
+ *               recovers a true neighbour only if the GEMM error moved it at
+ *               most e places.
  *  leaf_picker  PIPNN_PICKER_*: how a leaf member picks its candidates
  *               (Sec. 4.2 and the Supplement, "Picking within Leaves"):
  *               KNN, its k nearest co-members, bi-directed (both records
@@ -124,7 +131,7 @@ typedef int32_t pipnn_status;
  *               (Alg. 2, lazy form) of the member over every other member
  *               of its leaf with this alpha, up to k admitted, each giving
  *               the member one record (leaves of at most 2,048 members;
- *               rescore_mult 0; no planned / captured builds, no insertion).
+ *               no rescoring; no planned / captured builds, no insertion).
  *  seed         root key of the leader sampling (Alg. 5, SampleLeaders).
  */
 typedef struct {
@@ -136,6 +143,7 @@ typedef struct {
   int32_t gemm_prec;
   int32_t rescore_mult;
   int32_t leaf_picker;
+  int32_t rescore_extra;
   uint64_t seed;
 } pipnn_params;
 
@@ -252,9 +260,10 @@ pipnn_status pipnn_plan_leaves(pipnn_index *idx, const int64_t *d_leaf_offsets,
  * orders, so where that arithmetic rounds (non-integer data) GEMM distances
  * can differ in the last bits between them, and with them the choice among
  * near-tied candidates; the FP32 recomputed distances of a pair do not
- * depend on the layout. The index starts with QUAD, 128 rows, static for a
- * float32 GEMM operand and PAIR, 128 rows, static otherwise (QUAD where PAIR
- * is not built). EINVAL for other values or a shape that is not built. */
+ * depend on the layout. The index starts with QUAD, 128 rows, static for
+ * float32, bf16 and fp16 GEMM operands and PAIR, 128 rows, static for e4m3
+ * (QUAD where the other is not built). EINVAL for other values or a shape
+ * that is not built. */
 pipnn_status pipnn_set_leaf_config(pipnn_index *idx, int32_t rows_per_item, int32_t persistent,
                                    int32_t layout);
 
@@ -328,8 +337,8 @@ pipnn_status pipnn_insert(pipnn_index *idx, int64_t n_new, const int32_t *d_grou
 
 /* Pick + Prune_And_Add_Edges for every leaf (Alg. 4, the parallel loop over
  * leaves; Sec. 4.2): per leaf, the distance matrix on MFMA, each member's
- * k nearest co-members by (GEMM distance, id) (or the rescore_mult*k
- * nearest, rescored), the FP32 direct-difference distance of each winner
+ * k nearest co-members by (GEMM distance, id) (or the rescore_mult*k or
+ * k + rescore_extra nearest, rescored), the FP32 direct-difference distance of each winner
  * (for the inner product on an operand equal to the data -- FP32, or fp16 /
  * bf16 data with the same gemm_prec -- the GEMM's own FP32 sum, which has no
  * norm-expansion cancellation to repair; for squared L2 without rescoring
@@ -507,7 +516,8 @@ pipnn_status pipnn_get_sketches(const pipnn_index *idx, float *d_out, pipnn_stre
  * distances d_out_dist (n_rows x k, may be NULL) and, when d_out_matrix is
  * not NULL, the GEMM distances of every pair (n_rows x n_cols). The same
  * code as pipnn_build_leaves runs, with the index's gemm_prec and
- * rescore_mult. EINVAL if k < 1, k > 32, n_cols > 65535. */
+ * rescoring. EINVAL if k < 1, the selected count (k, rescore_mult * k or
+ * k + rescore_extra) > 32, n_cols > 65535. */
 pipnn_status pipnn_knn_block(pipnn_index *idx, const uint32_t *d_row_ids, int64_t n_rows,
                              const uint32_t *d_col_ids, int64_t n_cols, int32_t k,
                              int32_t exclude_diag, uint32_t *d_out_col, float *d_out_dist,

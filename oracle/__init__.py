@@ -108,7 +108,7 @@ def lib():
         L.orc_e4m3_value.restype = C.c_double
         L.orc_e4m3_value.argtypes = [C.c_uint8]
         L.orc_quantize.argtypes = [P, i64, i32, i32, P, P, P]
-        L.orc_leaf_knn_lowp.argtypes = [P, P, i32, i32, P, P, i64, i32, i32, P, P]
+        L.orc_leaf_knn_lowp.argtypes = [P, P, i32, i32, P, P, i64, i32, i32, i32, P, P]
         L.orc_leaf_reps.argtypes = [P, i32, P, P, i64, P]
         L.orc_robustprune_points.argtypes = [P, i32, i32, P, P, i64, i32, C.c_float, i32, P, P]
         L.orc_get_threads.restype = i32
@@ -310,9 +310,10 @@ def leaf_all_to_all(X, offsets, members, R_leaf: int, alpha: float, metric: int 
     return cand, dd
 
 
-def leaf_knn_lowp(X, xq, offsets, members, k: int, mult: int, metric: int = 0):
-    """Leaf pick on the decoded operand xq with FP64 rescoring of the
-    mult*k nearest (mult 0: no re-ranking); returns (cand, dist) like leaf_knn."""
+def leaf_knn_lowp(X, xq, offsets, members, k: int, mult: int, metric: int = 0, extra: int = 0):
+    """Leaf pick on the decoded operand xq with FP64 rescoring of the mult*k
+    nearest, or with mult 0 of the k + extra nearest (both 0: no re-ranking);
+    returns (cand, dist) like leaf_knn."""
     X = _f32(X)
     xq = np.ascontiguousarray(xq, dtype=np.float64)
     offsets = np.ascontiguousarray(offsets, dtype=np.int64)
@@ -321,7 +322,7 @@ def leaf_knn_lowp(X, xq, offsets, members, k: int, mult: int, metric: int = 0):
     cand = np.zeros((tot, k), dtype=np.uint32)
     dd = np.zeros((tot, k), dtype=np.float64)
     lib().orc_leaf_knn_lowp(_p(X), _p(xq), X.shape[1], metric, _p(offsets), _p(members),
-                            len(offsets) - 1, k, mult, _p(cand), _p(dd))
+                            len(offsets) - 1, k, mult, extra, _p(cand), _p(dd))
     return cand, dd
 
 

@@ -744,17 +744,18 @@ static double dist64(const double *a, const double *b, int d, int metric) {
 }
 
 /* Leaf pick with a reduced-precision GEMM distance and rescoring, in the
- * independent (FP64) mode. For every member i of a leaf: the k1 = mult * k
- * nearest co-members j != i by (distance between the decoded operands xq_i,
- * xq_j, id_j) -- the value a low-precision GEMM approximates -- then those
- * k1 re-ranked by (distance between the original vectors, id) and the first
- * k kept. mult = 0 keeps the k nearest by the operand distance without
- * re-ranking. Emitted distances are always those of the original vectors.
- * Output layout as orc_leaf_knn. */
+ * independent (FP64) mode. For every member i of a leaf: the k1 nearest
+ * co-members j != i by (distance between the decoded operands xq_i, xq_j,
+ * id_j) -- the value a low-precision GEMM approximates -- then those k1
+ * re-ranked by (distance between the original vectors, id) and the first k
+ * kept. k1 = mult * k, or k + extra when mult = 0; with both 0 the k nearest
+ * by the operand distance are kept without re-ranking. Emitted distances
+ * are always those of the original vectors. Output layout as orc_leaf_knn. */
 static void orc_leaf_knn_lowp_impl(const float *X, const double *xq, int d, int metric,
                        const int64_t *offsets, const uint32_t *members, int64_t n_leaves, int k,
-                       int mult, uint32_t *out_cand, double *out_dist) {
-  int k1 = mult > 0 ? mult * k : k;
+                       int mult, int extra, uint32_t *out_cand, double *out_dist) {
+  const int k1 = mult > 0 ? mult * k : k + extra;
+  const int rerank = mult > 0 || extra > 0;
 #pragma omp parallel
   {
     double *bd = (double *)malloc(sizeof(double) * (size_t)k1);
@@ -784,7 +785,7 @@ static void orc_leaf_knn_lowp_impl(const float *X, const double *xq, int d, int 
         /* distances of the original vectors; re-rank when rescoring */
         for (int r = 0; r < cnt; r++)
           rd[r] = orc_dist(X + (int64_t)pi * d, X + (int64_t)bi[r] * d, d, metric);
-        if (mult > 0) {
+        if (rerank) {
           for (int a = 1; a < cnt; a++) {
             double dv = rd[a];
             uint32_t iv = bi[a];
@@ -1265,9 +1266,9 @@ int orc_partition(const float *X, int64_t n, int d, const orc_params *prm, int64
   return r;
 }
 
-void orc_leaf_knn_lowp(const float *X, const double *xq, int d, int metric, const int64_t *offsets, const uint32_t *members, int64_t n_leaves, int k, int mult, uint32_t *out_cand, double *out_dist) {
+void orc_leaf_knn_lowp(const float *X, const double *xq, int d, int metric, const int64_t *offsets, const uint32_t *members, int64_t n_leaves, int k, int mult, int extra, uint32_t *out_cand, double *out_dist) {
   const double t0 = orc_now();
-  orc_leaf_knn_lowp_impl(X, xq, d, metric, offsets, members, n_leaves, k, mult, out_cand, out_dist);
+  orc_leaf_knn_lowp_impl(X, xq, d, metric, offsets, members, n_leaves, k, mult, extra, out_cand, out_dist);
   orc_phase_add(ORC_PH_LEAF, t0);
 }
 

@@ -49,7 +49,8 @@ class Params(C.Structure):
                 ("fanout", C.c_int32 * 4), ("k", C.c_int32), ("hash_bits", C.c_int32),
                 ("l_max", C.c_int32), ("R", C.c_int32), ("alpha", C.c_float),
                 ("gemm_prec", C.c_int32), ("rescore_mult", C.c_int32),
-                ("leaf_picker", C.c_int32), ("seed", C.c_uint64)]
+                ("leaf_picker", C.c_int32), ("rescore_extra", C.c_int32),
+                ("seed", C.c_uint64)]
 
 
 class Stats(C.Structure):

@@ -122,6 +122,14 @@ std::vector<int64_t> leader_positions(uint64_t key, int64_t np, int64_t ell) {
   return pos;
 }
 
+// Whether the leaf pick re-ranks its GEMM winners by the FP32 direct
+// difference, and how many it selects by the GEMM distance for k kept:
+// rescore_mult * k, or k + rescore_extra (k itself without rescoring).
+static bool rescoring(const pipnn_params &P) { return P.rescore_mult != 0 || P.rescore_extra != 0; }
+static int sel_count(const pipnn_params &P, int k) {
+  return P.rescore_mult ? P.rescore_mult * k : k + P.rescore_extra;
+}
+
 bool valid_params(const pipnn_params *p, std::string &why) {
   char b[160];
   auto bad = [&](const char *m) {
@@ -150,10 +158,14 @@ bool valid_params(const pipnn_params *p, std::string &why) {
   }
   if (p->rescore_mult != 0 && (p->rescore_mult < 2 || p->rescore_mult * p->k > 32))
     return bad("rescore_mult must be 0, or >= 2 with rescore_mult * k <= 32");
+  if (p->rescore_extra < 0 || p->k + p->rescore_extra > 32)
+    return bad("rescore_extra must be >= 0 with k + rescore_extra <= 32");
+  if (p->rescore_mult != 0 && p->rescore_extra != 0)
+    return bad("rescore_mult and rescore_extra are alternatives: set at most one");
   if (p->leaf_picker != PIPNN_PICKER_KNN && p->leaf_picker != PIPNN_PICKER_ALL_TO_ALL)
     return bad("unknown leaf_picker");
-  if (p->leaf_picker == PIPNN_PICKER_ALL_TO_ALL && p->rescore_mult != 0)
-    return bad("the all-to-all leaf picker takes no rescoring (rescore_mult 0)");
+  if (p->leaf_picker == PIPNN_PICKER_ALL_TO_ALL && rescoring(*p))
+    return bad("the all-to-all leaf picker takes no rescoring (rescore_mult and rescore_extra 0)");
   return true;
 }
 
@@ -670,6 +682,7 @@ void pipnn_default_params(pipnn_params *p) {
   p->alpha = 1.2f;
   p->gemm_prec = PIPNN_PREC_FP32;
   p->rescore_mult = 0;
+  p->rescore_extra = 0;
   p->seed = 0;
 }
 
@@ -763,10 +776,13 @@ pipnn_status pipnn_create(const pipnn_params *p, const void *d_X, int64_t n, int
       I->n_cu = ncu;
   }
   I->cap = n;
-  // leaf-kernel default: four lanes per row for the float32 operand (its MFMA
-  // work dominates and the smaller A fragment leaves room for more waves),
-  // two lanes for the reduced-precision operands; pipnn_autotune may change it
-  I->leaf_quad = (p->gemm_prec == PIPNN_PREC_FP32 && knn_quad_available(d, PIPNN_PREC_FP32)) ? 1 : 0;
+  // leaf-kernel default: four lanes per row where that layout is built for
+  // the operand, except fp8 (two lanes); pipnn_autotune may change it. Four
+  // lanes hold a row's kept list in a quarter of the registers each, so an
+  // insertion compares fewer keys per lane: on 1M points of 128 (96) dims
+  // the bf16 pick took 2.55 ms against 2.68 ms (two lanes) for k = 16 and
+  // 6.9 (7.1) ms against 7.5 (8.9) ms with 32 selected for rescoring.
+  I->leaf_quad = (p->gemm_prec != PIPNN_PREC_FP8 && knn_quad_available(d, p->gemm_prec)) ? 1 : 0;
   if (p->gemm_prec == PIPNN_PREC_FP32 && knn_operand_dim(d, PIPNN_PREC_FP32) == 0)
     return cleanup(fail(PIPNN_EINVAL, "a float32 leaf GEMM needs d <= 256 (use a reduced "
                                       "gemm_prec for wider vectors)"));
@@ -1190,7 +1206,7 @@ pipnn_status read_offsets(const int64_t *d_off, int64_t n_leaves, hipStream_t s,
 //   direct difference are then the same integer.
 static bool gemm_is_direct(const Index &I) {
   if (I.p.metric != PIPNN_METRIC_IP)
-    return I.p.metric == PIPNN_METRIC_L2 && I.p.rescore_mult == 0 && I.int_exact &&
+    return I.p.metric == PIPNN_METRIC_L2 && !rescoring(I.p) && I.int_exact &&
            (I.p.gemm_prec == PIPNN_PREC_FP32 ||
             (I.op_exact && (I.p.gemm_prec == PIPNN_PREC_BF16 || I.p.gemm_prec == PIPNN_PREC_FP16)));
   return I.p.gemm_prec == PIPNN_PREC_FP32 ||
@@ -1203,7 +1219,7 @@ void pick_lists(const Index &I, const std::vector<int64_t> &offs, int64_t l0, in
                 std::vector<KnnJob> &jobs, std::vector<KnnItem> &items, int32_t &max_cols,
                 int64_t &pairs) {
   const pipnn_params &P = I.p;
-  const int ksel = P.rescore_mult ? P.rescore_mult * P.k : P.k;
+  const int ksel = sel_count(P, P.k);
   jobs.clear();
   items.clear();
   max_cols = 0;
@@ -1247,7 +1263,7 @@ pipnn_status launch_pick(Index &I, const KnnJob *d_jobs, const KnnItem *d_items,
                          int32_t max_cols, int64_t rows, const uint32_t *d_members,
                          uint32_t *pick_c, float *pick_d, hipStream_t s, bool local = false) {
   const pipnn_params &P = I.p;
-  const int ksel = P.rescore_mult ? P.rescore_mult * P.k : P.k;
+  const int ksel = sel_count(P, P.k);
   HIPCHK(launch_fill_u32(pick_c, kEmptyId, rows * P.k, s));
   HIPCHK(launch_fill_u32(reinterpret_cast<uint32_t *>(pick_d), 0x7F800000u, rows * P.k, s));
   if (n_items == 0) return PIPNN_OK;
@@ -1263,7 +1279,7 @@ pipnn_status launch_pick(Index &I, const KnnJob *d_jobs, const KnnItem *d_items,
   L.k_out = P.k;
   L.out_ids = local ? 0 : 1;
   L.recompute = gemm_is_direct(I) ? 0 : 1;
-  L.rescore_k = P.rescore_mult ? P.k : 0;
+  L.rescore_k = rescoring(P) ? P.k : 0;
   L.prec = P.gemm_prec;
   L.nw = I.leaf_nw;
   L.persistent = I.leaf_persistent;
@@ -1849,7 +1865,7 @@ pipnn_status pipnn_insert(pipnn_index *idx, int64_t n_new, const int32_t *d_grou
   const pipnn_params &P = I.p;
   const int64_t n0 = I.n, n1 = n0 + n_new, d = I.d;
   const int k = P.k;
-  const int ksel = P.rescore_mult ? P.rescore_mult * k : k;
+  const int ksel = sel_count(P, k);
   const int64_t NL = I.lt_n_leaves;
   if (NL > 65535) return fail(PIPNN_EINVAL, "insert routes over at most 65535 leaves");
   if (n_new > 0x7FFFFFFF) return fail(PIPNN_EINVAL, "insert batch too large");
@@ -2012,7 +2028,7 @@ pipnn_status pipnn_insert(pipnn_index *idx, int64_t n_new, const int32_t *d_grou
     L.k_out = k;
     L.out_ids = 1;
     L.recompute = gemm_is_direct(I) ? 0 : 1;
-    L.rescore_k = P.rescore_mult ? k : 0;
+    L.rescore_k = rescoring(P) ? k : 0;
     L.prec = P.gemm_prec;
     L.nw = I.leaf_nw;
     L.persistent = 0;
@@ -2185,7 +2201,7 @@ pipnn_status pipnn_knn_block(pipnn_index *idx, const uint32_t *d_row_ids, int64_
   if (!idx || !d_row_ids || !d_col_ids || !d_out_col) return fail(PIPNN_EINVAL, "NULL argument");
   Index &I = *reinterpret_cast<Index *>(idx);
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  const int ksel = I.p.rescore_mult ? I.p.rescore_mult * k : k;
+  const int ksel = sel_count(I.p, k);
   if (k < 1 || ksel > 32) return fail(PIPNN_EINVAL, "k out of range");
   if (n_rows < 1 || n_cols < 1 || n_cols > 65535 || n_rows > 0x7FFFFFFF)
     return fail(PIPNN_EINVAL, "bad block size");
@@ -2217,7 +2233,7 @@ pipnn_status pipnn_knn_block(pipnn_index *idx, const uint32_t *d_row_ids, int64_
   L.k_out = k;
   L.out_ids = 0;
   L.recompute = gemm_is_direct(I) ? 0 : 1;
-  L.rescore_k = I.p.rescore_mult ? k : 0;
+  L.rescore_k = rescoring(I.p) ? k : 0;
   L.prec = I.p.gemm_prec;
   L.nw = I.leaf_nw;
   L.persistent = I.leaf_persistent;

@@ -601,9 +601,10 @@ static hipError_t launch_knn_quad(KnnArgs args, int n_items, int n_cu, hipStream
   return hipGetLastError();
 }
 
-// Selection sizes built: 4 (the partition's nearest leaders; two-lane
-// layout for the reduced-precision operands, both layouts for float32), 16
-// and 32.
+// Selection sizes built: 4 (the partition's nearest leaders), 16, 20 and 24
+// (rows of up to 256 dimensions) and 32. A selection costs about its list
+// length times its survivor count (k (1 + ln(s / k)) over a random column
+// order), so a size between 16 and 32 pays only for what it keeps.
 template <int PREC, int DP>
 static hipError_t launch_knn_quad_k(const KnnArgs &a, int ksel, int n_items, int n_cu,
                                     hipStream_t s) {
@@ -611,6 +612,10 @@ static hipError_t launch_knn_quad_k(const KnnArgs &a, int ksel, int n_items, int
     if (ksel <= 4) return launch_knn_quad<PREC, DP, 4>(a, n_items, n_cu, s);
   }
   if (ksel <= 16) return launch_knn_quad<PREC, DP, 16>(a, n_items, n_cu, s);
+  if constexpr (PREC == PIPNN_PREC_FP32 || DP <= 256) {
+    if (ksel <= 20) return launch_knn_quad<PREC, DP, 20>(a, n_items, n_cu, s);
+    if (ksel <= 24) return launch_knn_quad<PREC, DP, 24>(a, n_items, n_cu, s);
+  }
   return launch_knn_quad<PREC, DP, 32>(a, n_items, n_cu, s);
 }
 

@@ -116,7 +116,8 @@ def test_create_checks_the_workspace_arguments(L):
 
 @pytest.mark.parametrize("field,value", [("c_max", 1), ("k", 0), ("hash_bits", 17), ("l_max", 300),
                                          ("R", 0), ("alpha", 0.5), ("c_min", 5000),
-                                         ("gemm_prec", 9)])
+                                         ("gemm_prec", 9), ("rescore_extra", -1),
+                                         ("rescore_extra", 17), ("rescore_mult", 3)])
 def test_create_rejects_bad_params(L, field, value):
     p = pp.default_params(**{field: value})
     h = C.c_void_p()
@@ -125,6 +126,22 @@ def test_create_rejects_bad_params(L, field, value):
     assert st == -1
     assert len(L.pipnn_last_error()) > 0
     assert not h.value
+
+
+@pytest.mark.parametrize("kw", [dict(rescore_mult=2, rescore_extra=4),
+                                dict(rescore_extra=4, leaf_picker=1),
+                                dict(k=30, rescore_extra=3)])
+def test_create_rejects_bad_rescoring(L, kw):
+    """rescore_mult and rescore_extra are alternatives, the all-to-all picker
+    takes neither, and at most 32 are selected."""
+    p = pp.default_params(**kw)
+    h = C.c_void_p()
+    st = L.pipnn_create(C.byref(p), C.c_void_p(16), 100, 8, 0, C.c_void_p(16), None, 0, None,
+                        C.byref(h))
+    assert st == -1 and b"rescor" in L.pipnn_last_error()
+    assert not h.value
+    ok = pp.default_params(k=16, rescore_extra=16, gemm_prec=pp.PREC_BF16)
+    assert pp.workspace_bytes(ok, 1000, 128) > 0
 
 
 def test_create_rejects_bad_shapes(L):

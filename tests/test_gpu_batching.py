@@ -110,7 +110,7 @@ def test_wide_leaf_pick_against_fp64(wide):
     idx.close()
 
 
-@pytest.mark.parametrize("case", ["int128-fp32", "vmf96-bf16", "wide768-fp16"])
+@pytest.mark.parametrize("case", ["int128-fp32", "vmf96-bf16", "vmf96-bf16-extra", "wide768-fp16"])
 def test_leaf_configs_give_identical_picks(case, wide):
     """Work-item size and schedule never change a pick. The two register
     layouts sum the GEMM products in different orders: on integer data
@@ -125,10 +125,12 @@ def test_leaf_configs_give_identical_picks(case, wide):
         ref_idx.close()
         off, mem = off.cpu().numpy(), u32(mem)
         Xs = X
-    elif case == "vmf96-bf16":
+    elif case.startswith("vmf96-bf16"):
         Xs = pi.workload_points(3, 12000)
         H = pi.workload_hyperplanes(3)
-        p = pp.default_params(c_max=1024, k=16, seed=7, gemm_prec=pp.PREC_BF16, rescore_mult=2)
+        # 32 selected for rescoring, or 20 (four lanes: a list of 20; two: 32)
+        resc = dict(rescore_extra=4) if case.endswith("extra") else dict(rescore_mult=2)
+        p = pp.default_params(c_max=1024, k=16, seed=7, gemm_prec=pp.PREC_BF16, **resc)
         o = oracle.partition(Xs, oracle.make_params(c_max=1024, k=16, seed=7))
         off, mem = o[0], o[1]
     else:

@@ -123,7 +123,8 @@ def test_bf16_equals_fp32_on_integer_data(d, mult):
     idx.close()
 
 
-def _check_rescored_block(X, xq, ids, oc, od, M, k, mult, d, prec, codes=None, scales=None):
+def _check_rescored_block(X, xq, ids, oc, od, M, k, mult, d, prec, codes=None, scales=None,
+                          extra=0):
     n = len(ids)
     self_col = np.arange(n)
     Xd = X[ids].astype(np.float64)
@@ -180,18 +181,19 @@ def _check_rescored_block(X, xq, ids, oc, od, M, k, mult, d, prec, codes=None, s
     # typical errors are far below the worst case
     assert np.median(ratio) < 0.1
     # 2. the first selection, replayed on the GPU's own GEMM values
-    k1 = mult * k if mult else k
+    k1 = mult * k if mult else k + extra
+    rescored = bool(mult or extra)
     sel, _ = oracle.topk_rows(M, k1, self_col=self_col)
     got = u32(oc)
     D64 = ((Xd[:, None, :] - Xd[None]) ** 2).sum(-1)
-    if not mult:
+    if not rescored:
         assert np.array_equal(got, sel)
     gd = od.cpu().numpy()
     ref = np.take_along_axis(D64, got.astype(np.int64), 1)
     tol = np.maximum(REL * np.abs(ref), ABS)
     # 3. emitted distances: FP32 direct differences of the original vectors
     assert np.all(np.abs(gd - ref) <= tol)
-    if mult:
+    if rescored:
         for r in range(n):
             s = set(sel[r].tolist())
             g = got[r].tolist()
@@ -246,19 +248,20 @@ def test_fp8_matrix_core_accumulation():
 
 
 @pytest.mark.parametrize("prec", LOWP)
-@pytest.mark.parametrize("mult", [0, 2])
-def test_lowp_knn_block_replay(prec, mult):
+@pytest.mark.parametrize("mult,extra", [(0, 0), (2, 0), (0, 4), (0, 8)])
+def test_lowp_knn_block_replay(prec, mult, extra):
     d, n, k = 96, 900, 16
     X = pi.workload_points(3, 6000)
     H = pi.workload_hyperplanes(3)
-    idx = pp.Index(dev(X), dev(H), pp.default_params(k=k, gemm_prec=prec, rescore_mult=mult))
-    ids = np.sort(np.random.default_rng(prec * 10 + mult).choice(6000, n, replace=False)).astype(
-        np.uint32)
+    idx = pp.Index(dev(X), dev(H), pp.default_params(k=k, gemm_prec=prec, rescore_mult=mult,
+                                                      rescore_extra=extra))
+    ids = np.sort(np.random.default_rng(prec * 10 + mult + extra).choice(
+        6000, n, replace=False)).astype(np.uint32)
     oc, od, om = idx.knn_block(dev(ids), dev(ids), k, True, want_matrix=True)
     torch.cuda.synchronize()
     codes, scales, xq = oracle.quantize(X, prec)
     _check_rescored_block(X, xq, ids, oc, od, om.cpu().numpy(), k, mult, d, prec,
-                          codes=codes[ids], scales=scales[ids])
+                          codes=codes[ids], scales=scales[ids], extra=extra)
     idx.close()
 
 
@@ -267,16 +270,19 @@ def test_lowp_ragged_blocks(prec):
     """Blocks that are not whole tiles, rectangular, and smaller than k1."""
     X = pi.workload_points(3, 3000)
     H = pi.workload_hyperplanes(3)
-    for nr, nc, k, mult, diag in [(37, 37, 16, 2, True), (300, 1001, 8, 2, False),
-                                  (5, 5, 16, 2, True), (129, 129, 4, 4, True)]:
-        idx = pp.Index(dev(X), dev(H), pp.default_params(k=k, gemm_prec=prec, rescore_mult=mult))
+    for nr, nc, k, mult, extra, diag in [(37, 37, 16, 2, 0, True), (300, 1001, 8, 2, 0, False),
+                                         (5, 5, 16, 2, 0, True), (129, 129, 4, 4, 0, True),
+                                         (37, 37, 16, 0, 4, True), (300, 1001, 16, 0, 8, False)]:
+        idx = pp.Index(dev(X), dev(H), pp.default_params(k=k, gemm_prec=prec, rescore_mult=mult,
+                                                          rescore_extra=extra))
         rng = np.random.default_rng(nr + nc)
         cols = np.sort(rng.choice(3000, nc, replace=False)).astype(np.uint32)
         rows = cols if diag else np.sort(rng.choice(3000, nr, replace=False)).astype(np.uint32)
         oc, od, om = idx.knn_block(dev(rows), dev(cols), k, diag, want_matrix=True)
         torch.cuda.synchronize()
         M = om.cpu().numpy()
-        sel, _ = oracle.topk_rows(M, mult * k, self_col=np.arange(nr) if diag else None)
+        sel, _ = oracle.topk_rows(M, mult * k if mult else k + extra,
+                                  self_col=np.arange(nr) if diag else None)
         got = u32(oc)
         Xr, Xc = X[rows].astype(np.float64), X[cols].astype(np.float64)
         D64 = ((Xr[:, None, :] - Xc[None]) ** 2).sum(-1)
@@ -305,10 +311,10 @@ def test_lowp_leaf_pick_against_fp64():
     X, H, p, off, mem = _vmf_partition(12000)
     exact, _ = oracle.leaf_knn(X, off, mem, p.k)
     for prec in [pp.PREC_FP32] + LOWP:
-        for mult in (0, 2):
-            if prec == pp.PREC_FP32 and mult:
+        for mult, extra in ((0, 0), (2, 0), (0, 4)):
+            if prec == pp.PREC_FP32 and (mult or extra):
                 continue
-            p.gemm_prec, p.rescore_mult = prec, mult
+            p.gemm_prec, p.rescore_mult, p.rescore_extra = prec, mult, extra
             idx = pp.Index(dev(X), dev(H), p)
             oc, od = idx.leaf_pick(dev(off), dev(mem))
             torch.cuda.synchronize()
@@ -317,20 +323,23 @@ def test_lowp_leaf_pick_against_fp64():
             # the oracle's independent run of the same form
             if prec != pp.PREC_FP32:
                 _, _, xq = oracle.quantize(X, prec)
-                oref, _ = oracle.leaf_knn_lowp(X, xq, off, mem, p.k, mult)
+                oref, _ = oracle.leaf_knn_lowp(X, xq, off, mem, p.k, mult, extra=extra)
                 same = np.mean([len(set(a) & set(b)) / len(b) for a, b in zip(got, oref)])
             else:
                 same = agree
-            print(f"{NAMES.get(prec, 'fp32')} rescore x{mult}: pick agreement with FP64 "
+            form = f"rescore x{mult}" if mult else f"rescore +{extra}"
+            print(f"{NAMES.get(prec, 'fp32')} {form}: pick agreement with FP64 "
                   f"{agree:.5f}, with the oracle's {NAMES.get(prec, 'fp32')} form {same:.5f}")
             floor = {pp.PREC_FP32: 0.999, pp.PREC_BF16: 0.97, pp.PREC_FP16: 0.995,
                      pp.PREC_FP8: 0.80}[prec]
             if mult:
                 floor = max(floor, 0.995 if prec != pp.PREC_FP8 else 0.97)
+            elif extra:
+                floor = max(floor, 0.99 if prec != pp.PREC_FP8 else 0.90)
             assert agree >= floor
             assert same >= 0.99
             idx.close()
-    p.gemm_prec, p.rescore_mult = pp.PREC_FP32, 0
+    p.gemm_prec, p.rescore_mult, p.rescore_extra = pp.PREC_FP32, 0, 0
 
 
 def test_lowp_build_recall():
@@ -343,19 +352,22 @@ def test_lowp_build_recall():
     start, _ = oracle.start_node(X)
     _, gd = oracle.bruteforce_knn(X, Q, 10)
     rec = {}
-    for prec, mult in [(pp.PREC_FP32, 0), (pp.PREC_BF16, 2), (pp.PREC_FP16, 2),
-                       (pp.PREC_FP8, 2)]:
-        p.gemm_prec, p.rescore_mult = prec, mult
+    for prec, mult, extra in [(pp.PREC_FP32, 0, 0), (pp.PREC_BF16, 2, 0), (pp.PREC_BF16, 0, 4),
+                              (pp.PREC_FP16, 2, 0), (pp.PREC_FP8, 2, 0)]:
+        p.gemm_prec, p.rescore_mult, p.rescore_extra = prec, mult, extra
         idx, off, mem, res, g, deg = pp.build(dev(X), dev(H), p)
         ids, _, _ = idx.search(g, dev(Q), 10, 64, start)
         torch.cuda.synchronize()
-        rec[prec] = oracle.recall_at_k(u32(ids), X, Q, gd)
-        print(f"{NAMES.get(prec, 'fp32')} rescore x{mult}: recall@10 at L=64 {rec[prec]:.4f}")
+        rec[(prec, extra)] = oracle.recall_at_k(u32(ids), X, Q, gd)
+        form = f"rescore x{mult}" if mult else f"rescore +{extra}"
+        print(f"{NAMES.get(prec, 'fp32')} {form}: recall@10 at L=64 {rec[(prec, extra)]:.4f}")
         idx.close()
-    assert abs(rec[pp.PREC_BF16] - rec[pp.PREC_FP32]) <= 0.01
-    assert abs(rec[pp.PREC_FP16] - rec[pp.PREC_FP32]) <= 0.01
-    assert abs(rec[pp.PREC_FP8] - rec[pp.PREC_FP32]) <= 0.02
-    p.gemm_prec, p.rescore_mult = pp.PREC_FP32, 0
+    base = rec[(pp.PREC_FP32, 0)]
+    assert abs(rec[(pp.PREC_BF16, 0)] - base) <= 0.01
+    assert abs(rec[(pp.PREC_BF16, 4)] - base) <= 0.01
+    assert abs(rec[(pp.PREC_FP16, 0)] - base) <= 0.01
+    assert abs(rec[(pp.PREC_FP8, 0)] - base) <= 0.02
+    p.gemm_prec, p.rescore_mult, p.rescore_extra = pp.PREC_FP32, 0, 0
 
 
 @pytest.fixture(scope="module")
@@ -379,27 +391,29 @@ def vmf_oracle_graph():
     return dict(X=X, H=H, p=p, off=off, mem=mem, graph=og, Q=Q, start=start, gd=gd, recall=orec)
 
 
-@pytest.mark.parametrize("prec,mult", [(pp.PREC_FP32, 0), (pp.PREC_BF16, 2), (pp.PREC_FP8, 2)])
-def test_vmf_graph_recall_against_oracle_graph(vmf_oracle_graph, prec, mult):
+@pytest.mark.parametrize("prec,mult,extra", [(pp.PREC_FP32, 0, 0), (pp.PREC_BF16, 2, 0),
+                                             (pp.PREC_BF16, 0, 4), (pp.PREC_FP8, 2, 0)])
+def test_vmf_graph_recall_against_oracle_graph(vmf_oracle_graph, prec, mult, extra):
     """End graph of each form on the vMF workload (real-valued unit vectors)
     against the FP64 oracle's graph on the same leaves: recall@10 at
     L = 64 / 128 / 256 within 0.3 points, both graphs searched by the
     oracle's BeamSearch from the same start."""
     V = vmf_oracle_graph
     X, p = V["X"], V["p"]
-    p.gemm_prec, p.rescore_mult = prec, mult
+    p.gemm_prec, p.rescore_mult, p.rescore_extra = prec, mult, extra
     idx = pp.Index(dev(X), dev(V["H"]), p)
     res = pp.reservoir_init(X.shape[0], p.l_max)
     idx.build_leaves(dev(V["off"]), dev(V["mem"]), res)
     g, _ = idx.robustprune(res)
     torch.cuda.synchronize()
     G = u32(g)
-    p.gemm_prec, p.rescore_mult = pp.PREC_FP32, 0
+    p.gemm_prec, p.rescore_mult, p.rescore_extra = pp.PREC_FP32, 0, 0
     same = np.mean(np.all(G == V["graph"], axis=1))
     for L in (64, 128, 256):
         ids, _, _ = oracle.beam_search(X, G, V["Q"], 10, L, V["start"])
         r = oracle.recall_at_k(ids, X, V["Q"], V["gd"])
-        print(f"{NAMES.get(prec, 'fp32')} rescore x{mult}: identical graph rows {same:.4f}; "
+        form = f"rescore x{mult}" if mult else f"rescore +{extra}"
+        print(f"{NAMES.get(prec, 'fp32')} {form}: identical graph rows {same:.4f}; "
               f"L={L} recall@10 gpu graph {r:.4f} oracle graph {V['recall'][L]:.4f}")
         assert abs(r - V["recall"][L]) <= 0.003
     idx.close()

@@ -128,16 +128,18 @@ def _bf_knn(A, B, k, self_skip=True):
     return out
 
 
-def test_leaf_knn_lowp_equals_bruteforce_rescore():
+@pytest.mark.parametrize("mult,extra", [(2, 0), (0, 1), (0, 3)])
+def test_leaf_knn_lowp_equals_bruteforce_rescore(mult, extra):
     rng = np.random.default_rng(10)
-    s, d, k, mult = 40, 24, 4, 2
+    s, d, k = 40, 24, 4
     X = rng.standard_normal((s, d)).astype(np.float32)
     offsets = np.array([0, s], dtype=np.int64)
     members = np.arange(s, dtype=np.uint32)
+    k1 = mult * k if mult else k + extra
     for prec in (BF16, FP8, FP16):
         _, _, xq = oracle.quantize(X, prec)
-        cand, dist = oracle.leaf_knn_lowp(X, xq, offsets, members, k, mult)
-        first = _bf_knn(xq, xq, mult * k)
+        cand, dist = oracle.leaf_knn_lowp(X, xq, offsets, members, k, mult, extra=extra)
+        first = _bf_knn(xq, xq, k1)
         X64 = X.astype(np.float64)
         for i in range(s):
             rescored = sorted((((X64[i] - X64[j]) ** 2).sum(), j) for j in first[i])[:k]
