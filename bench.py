@@ -12,12 +12,12 @@ After the timed steps the graph of the last build is searched with 10,000
 queries from the same mixture for recall@10 against exact brute force
 (FP64), and the smallest beam width reaching 0.95 is reported.
 
-`--prec` / `--rescore-mult` choose the leaf-GEMM form of the measured build
-(default FP32). `variants` lists other forms (by default bf16 exact, bf16
-with FP32 rescoring of the top-2k, fp8 with rescoring, FP32 with two
-replicas of the partition, and FP32 with the All-to-All Prune leaf picker)
-built, timed and searched the same way on the same points after the main
-measurement.
+`--prec` / `--rescore-mult` / `--rescore-extra` choose the leaf-GEMM form of
+the measured build (default FP32). `variants` lists other forms (by default
+bf16 exact, bf16 with FP32 rescoring of the top-2k and of the top k + 4, fp8
+with rescoring of the top-2k, FP32 with two replicas of the partition, and
+FP32 with the All-to-All Prune leaf picker) built, timed and searched the
+same way on the same points after the main measurement.
 
 Printed: one JSON line. `rooflines` holds every main kernel of the build
 (leaf pick, partition, binning, merge, RobustPrune) against the roofline
@@ -25,9 +25,9 @@ that bounds it, each from its algorithmic work and its time per build from
 HIP events recorded around it on its own stream during the timed steps;
 `roofline` is the entry of the kernel that takes the most time (the fused
 leaf distance + selection kernel on the default workload). `precision` is
-the 1M x 96 vMF workload built with the float32, bf16 + rescore and fp8 +
-rescore leaf GEMMs, with each form's error against the FP64 oracle on
-sampled leaves. `cpu_baseline` is the FP64 oracle timed on a bounded sample
+the 1M x 96 vMF workload built with the float32, bf16 + rescore (top-2k
+and top k + 4) and fp8 + rescore leaf GEMMs, with each form's error against
+the FP64 oracle on sampled leaves. `cpu_baseline` is the FP64 oracle timed on a bounded sample
 of the same build (each phase on a sample of its units, scaled by the unit
 counts of the GPU build; phase times from the oracle's own steady clock),
 plus the oracle's whole pipeline on the 10,000-point workload on one thread
