@@ -102,15 +102,15 @@ def test_operand_encoding_bit_exact(prec, d):
 
 
 @pytest.mark.parametrize("d", [128, 96, 40])
-@pytest.mark.parametrize("mult", [0, 2])
-def test_bf16_equals_fp32_on_integer_data(d, mult):
+@pytest.mark.parametrize("mult,extra", [(0, 0), (2, 0), (0, 4)])
+def test_bf16_equals_fp32_on_integer_data(d, mult, extra):
     """Integers 0..255 are exact in bf16 and every product and sum stays
     below 2^24: the bf16 GEMM is the exact distance, as the FP32 one is."""
     X = pi.integer_mixture(1200, d, 40, 30.0, seed=11 + d)
     H = pi.hyperplanes(12, d, seed=5, integer=True)
-    k = 16 if mult == 0 else 8
+    k = 8 if mult else 16
     idx = pp.Index(dev(X), dev(H), pp.default_params(k=k, gemm_prec=pp.PREC_BF16,
-                                                      rescore_mult=mult))
+                                                      rescore_mult=mult, rescore_extra=extra))
     ids = np.sort(np.random.default_rng(d).choice(1200, 500, replace=False)).astype(np.uint32)
     oc, od, om = idx.knn_block(dev(ids), dev(ids), k, True, want_matrix=True)
     torch.cuda.synchronize()
