@@ -327,7 +327,7 @@ def test_lowp_leaf_pick_against_fp64():
                 same = np.mean([len(set(a) & set(b)) / len(b) for a, b in zip(got, oref)])
             else:
                 same = agree
-            form = f"rescore x{mult}" if mult else f"rescore +{extra}"
+            form = f"rescore x{mult}" if mult else f"rescore +{extra}" if extra else "no rescore"
             print(f"{NAMES.get(prec, 'fp32')} {form}: pick agreement with FP64 "
                   f"{agree:.5f}, with the oracle's {NAMES.get(prec, 'fp32')} form {same:.5f}")
             floor = {pp.PREC_FP32: 0.999, pp.PREC_BF16: 0.97, pp.PREC_FP16: 0.995,
@@ -359,7 +359,7 @@ def test_lowp_build_recall():
         ids, _, _ = idx.search(g, dev(Q), 10, 64, start)
         torch.cuda.synchronize()
         rec[(prec, extra)] = oracle.recall_at_k(u32(ids), X, Q, gd)
-        form = f"rescore x{mult}" if mult else f"rescore +{extra}"
+        form = f"rescore x{mult}" if mult else f"rescore +{extra}" if extra else "no rescore"
         print(f"{NAMES.get(prec, 'fp32')} {form}: recall@10 at L=64 {rec[(prec, extra)]:.4f}")
         idx.close()
     base = rec[(pp.PREC_FP32, 0)]
@@ -412,7 +412,7 @@ def test_vmf_graph_recall_against_oracle_graph(vmf_oracle_graph, prec, mult, ext
     for L in (64, 128, 256):
         ids, _, _ = oracle.beam_search(X, G, V["Q"], 10, L, V["start"])
         r = oracle.recall_at_k(ids, X, V["Q"], V["gd"])
-        form = f"rescore x{mult}" if mult else f"rescore +{extra}"
+        form = f"rescore x{mult}" if mult else f"rescore +{extra}" if extra else "no rescore"
         print(f"{NAMES.get(prec, 'fp32')} {form}: identical graph rows {same:.4f}; "
               f"L={L} recall@10 gpu graph {r:.4f} oracle graph {V['recall'][L]:.4f}")
         assert abs(r - V["recall"][L]) <= 0.003
