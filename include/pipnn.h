@@ -338,13 +338,14 @@ pipnn_status pipnn_insert(pipnn_index *idx, int64_t n_new, const int32_t *d_grou
 /* Pick + Prune_And_Add_Edges for every leaf (Alg. 4, the parallel loop over
  * leaves; Sec. 4.2): per leaf, the distance matrix on MFMA, each member's
  * k nearest co-members by (GEMM distance, id) (or the rescore_mult*k or
- * k + rescore_extra nearest, rescored), the FP32 direct-difference distance of each winner
- * (for the inner product on an operand equal to the data -- FP32, or fp16 /
- * bf16 data with the same gemm_prec -- the GEMM's own FP32 sum, which has no
- * norm-expansion cancellation to repair; for squared L2 without rescoring
- * on data the integer check found exact -- see pipnn_stats.data_int_exact --
- * the GEMM distance, which then is the same integer), and both directed records of each
- * picked edge inserted into HashPrune. With leaf_picker ALL_TO_ALL each member
+ * k + rescore_extra nearest, rescored), the FP32 direct-difference
+ * distance of each winner (for the inner product on an operand equal to the
+ * data -- FP32, or fp16 / bf16 data with the same gemm_prec -- the GEMM's
+ * own FP32 sum, which has no norm-expansion cancellation to repair; for
+ * squared L2 without rescoring on data the integer check found exact -- see
+ * pipnn_stats.data_int_exact -- the GEMM distance, which then is the same
+ * integer), and both directed records of each picked edge inserted into
+ * HashPrune. With leaf_picker ALL_TO_ALL each member
  * instead keeps the candidates that RobustPrune over its whole leaf admits
  * (distances from the leaf's GEMM distance matrix, emitted as FP32 direct
  * differences unless the two forms agree), each giving one record
