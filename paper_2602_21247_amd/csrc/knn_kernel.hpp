@@ -317,6 +317,12 @@ __device__ __forceinline__ void knn_item(const KnnArgs &a, const int item) {
   uint64_t ks[KH];
 #pragma unroll
   for (int i = 0; i < KH; ++i) ks[i] = kEmptyKey;
+  // The filter's threshold is the job's k_sel-th smallest kept key (a key
+  // above it can no longer reach the output, even where the list keeps
+  // more): position KSEL - k_sel of the descending list, entry tidx of
+  // half thalf.
+  const int tpos = KSEL - (J.k_sel < KSEL ? J.k_sel : KSEL);
+  const int thalf = tpos / KH, tidx = tpos - thalf * KH;
 
   // Drain: a key x enters by b[i] = max(a[i+1], min(a[i], x)): the largest
   // entry drops out when x is smaller, and nothing changes otherwise. Every
@@ -343,9 +349,12 @@ __device__ __forceinline__ void knn_item(const KnnArgs &a, const int item) {
           ks[i] = kmax(nxt, kmin(ks[i], x));
         }
       }
-      if (h == 0) {
-        sBufN[orow] = 0;
-        sTau[orow] = ks[0] == kEmptyKey ? INFINITY : key_dist(ks[0]);
+      if (h == 0) sBufN[orow] = 0;
+      if (h == thalf) {
+        uint64_t kt = ks[0];
+#pragma unroll
+        for (int i = 1; i < KH; ++i) kt = i == tidx ? ks[i] : kt;
+        sTau[orow] = kt == kEmptyKey ? INFINITY : key_dist(kt);
       }
     }
   };

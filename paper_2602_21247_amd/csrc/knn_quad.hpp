@@ -200,6 +200,12 @@ __device__ __forceinline__ void knn_quad_item(const KnnArgs &a, const int item) 
   uint64_t ks[KQ];
 #pragma unroll
   for (int i = 0; i < KQ; ++i) ks[i] = kEmptyKey;
+  // The filter's threshold is the job's k_sel-th smallest kept key: a key
+  // above it can no longer reach the output, even where the list keeps more
+  // (k_sel < KSEL: the partition's top-f, a smaller k). In the descending
+  // list that is position KSEL - k_sel, entry tidx of part tpart.
+  const int tpos = KSEL - (J.k_sel < KSEL ? J.k_sel : KSEL);
+  const int tpart = tpos / KQ, tidx = tpos - tpart * KQ;
   auto drain = [&]() {
     const int nb = (wrow + dr < n_rows) ? sBufN[drow] : 0;
     if (nb > 0) {
@@ -224,9 +230,12 @@ __device__ __forceinline__ void knn_quad_item(const KnnArgs &a, const int item) 
           ks[i] = gt[i + 1] ? nxt : (gt[i] ? x : ks[i]);
         }
       }
-      if (part == 0) {
-        sBufN[drow] = 0;
-        sTau[drow] = ks[0] == kEmptyKey ? INFINITY : key_dist(ks[0]);
+      if (part == 0) sBufN[drow] = 0;
+      if (part == tpart) {
+        uint64_t kt = ks[0];
+#pragma unroll
+        for (int i = 1; i < KQ; ++i) kt = i == tidx ? ks[i] : kt;
+        sTau[drow] = kt == kEmptyKey ? INFINITY : key_dist(kt);
       }
     }
   };

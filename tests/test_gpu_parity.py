@@ -105,7 +105,8 @@ def leaf_sets(off, mem):
 @pytest.mark.parametrize("nr,nc,k,diag", [(300, 300, 16, True), (257, 1000, 4, False),
                                           (70, 70, 32, True), (5, 3, 16, True),
                                           (129, 700, 16, False), (300, 300, 20, True),
-                                          (257, 1000, 24, False)])
+                                          (257, 1000, 24, False), (300, 300, 12, True),
+                                          (257, 1000, 2, False), (129, 700, 18, False)])
 def test_knn_block_exact(d, nr, nc, k, diag):
     if diag:
         nc = nr
