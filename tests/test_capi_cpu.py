@@ -6,6 +6,7 @@ sizing, argument validation) are made.
 import ctypes as C
 import os
 import re
+import subprocess
 
 import pytest
 
@@ -171,3 +172,29 @@ def test_compile_step_does_not_shadow_the_index_build():
     import types
     from paper_2602_21247_amd import hipbuild  # noqa: F401
     assert callable(pp.build) and not isinstance(pp.build, types.ModuleType)
+
+
+def _c_layout(tmp_path, struct, fields):
+    """sizeof and offsetof of a header struct, from a C program compiled
+    against include/pipnn.h."""
+    src = tmp_path / "layout.c"
+    body = "".join(f'  printf("{f} %zu\\n", offsetof({struct}, {f}));\n' for f in fields)
+    src.write_text('#include <stddef.h>\n#include <stdio.h>\n#include "pipnn.h"\n'
+                   "int main(void) {\n"
+                   f'  printf("sizeof %zu\\n", sizeof({struct}));\n{body}  return 0;\n}}\n')
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o",
+                    str(exe)], check=True, capture_output=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout
+    return {k: int(v) for k, v in (line.split() for line in out.splitlines())}
+
+
+@pytest.mark.parametrize("cls,struct", [(pp.Params, "pipnn_params"), (pp.Stats, "pipnn_stats"),
+                                        (pp.TuneResult, "pipnn_tune_result")])
+def test_binding_structs_match_the_header(tmp_path, cls, struct):
+    """The ctypes mirrors have the C structs' size and field offsets."""
+    names = [f[0] for f in cls._fields_]
+    lay = _c_layout(tmp_path, struct, names)
+    assert lay["sizeof"] == C.sizeof(cls)
+    for n in names:
+        assert lay[n] == getattr(cls, n).offset, n
