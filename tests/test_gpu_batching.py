@@ -310,3 +310,41 @@ def test_wide_robustprune_against_oracle(wide):
           f"mean degree gpu {u32(deg).mean():.2f} oracle {odeg.mean():.2f}")
     assert same_rows >= 0.98 and jac >= 0.995
     idx.close()
+
+
+def test_graph_replay_equals_eager_rescored():
+    """A captured build whose leaf pick rescores the top k + 4 of a bf16 GEMM
+    (the FP32 recompute in the graph): every replay equals the eager build."""
+    X = pi.workload_points(3, 12000)
+    H = pi.workload_hyperplanes(3)
+    p = pp.default_params(c_max=1024, k=16, seed=7, gemm_prec=pp.PREC_BF16, rescore_extra=4)
+    o = oracle.partition(X, oracle.make_params(c_max=1024, k=16, seed=7))
+    off, mem = o[0], o[1]
+    idx = pp.Index(dev(X), dev(H), p)
+    doff, dmem = dev(off), dev(mem)
+    n = X.shape[0]
+    res_e = pp.reservoir_init(n, p.l_max)
+    idx.build_leaves(doff, dmem, res_e)
+    g_e, _ = idx.robustprune(res_e)
+    torch.cuda.synchronize()
+    ref_res, ref_g = u64(res_e).copy(), u32(g_e).copy()
+    idx.plan_leaves(doff, dmem)
+    res = torch.empty((n, p.l_max), dtype=torch.int64, device="cuda")
+    g = torch.empty((n, p.R), dtype=torch.int32, device="cuda")
+    deg = torch.empty(n, dtype=torch.int32, device="cuda")
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        pp.reservoir_init(n, p.l_max, out=res)
+        idx.build_leaves(doff, dmem, res)
+        idx.robustprune(res, g, deg)
+    for rep in range(3):
+        res.fill_(0)
+        g.fill_(0)
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(u64(res), ref_res), f"replay {rep}: reservoirs differ"
+        assert np.array_equal(u32(g), ref_g), f"replay {rep}: graph differs"
+        oc, od = idx.leaf_pick(doff, dmem)
+        torch.cuda.synchronize()
+    idx.close()
